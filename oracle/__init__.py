@@ -1,0 +1,272 @@
+"""Plain FP64 CPU oracle for the particle-inference hot path.
+
+TEST INFRASTRUCTURE ONLY: the test suite, the package smoke check and the
+benchmark's CPU-baseline leg are the only callers.  The product path (the HIP
+library and its Python binding) never imports this package, and this package
+imports nothing from the product path.
+
+The C part (``ppl_oracle.c``) computes the sampling, scoring, importance
+sampling, log-sum-exp/ESS, resampling and SMC definitions in double precision;
+``closed_forms`` holds the exact answers (conjugate Gaussian posteriors,
+enumeration over the polynomial degree, the Kalman filter) that pin it.
+"""
+import ctypes
+import os
+import subprocess
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SRC = os.path.join(_HERE, "ppl_oracle.c")
+_LIB = os.path.join(_HERE, "liboracle.so")
+
+MODEL_POLY, MODEL_BLR, MODEL_LGSSM, MODEL_GMM = 1, 2, 3, 4
+TAG_PRIOR, TAG_PROPOSAL, TAG_RESAMPLE = 0, 1, 2
+
+
+def build(force=False):
+    """Compile the oracle with gcc (FP64, no FP contraction, OpenMP over particles)."""
+    if not force and os.path.exists(_LIB) and os.path.getmtime(_LIB) >= os.path.getmtime(_SRC):
+        return _LIB
+    cmd = ["gcc", "-O2", "-std=c11", "-fPIC", "-shared", "-fopenmp", "-ffp-contract=off",
+           "-fno-fast-math", "-Wall", "-o", _LIB + ".tmp", _SRC, "-lm"]
+    subprocess.check_call(cmd)
+    os.replace(_LIB + ".tmp", _LIB)
+    return _LIB
+
+
+_lib = None
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        build()
+        L = ctypes.CDLL(_LIB)
+        P = ctypes.c_void_p
+        i32, i64, u32, u64, f64 = ctypes.c_int32, ctypes.c_int64, ctypes.c_uint32, ctypes.c_uint64, ctypes.c_double
+        L.or_philox.argtypes = [u32, u32, u32, u32, u64, P]
+        L.or_philox_batch.argtypes = [i64, P, P, P]
+        L.or_u01_single.argtypes = [u32]; L.or_u01_single.restype = f64
+        L.or_u01_double.argtypes = [u32, u32]; L.or_u01_double.restype = f64
+        L.or_box_muller.argtypes = [f64, f64, P, P]
+        L.or_uniform_discrete.argtypes = [u32, i64, i64]; L.or_uniform_discrete.restype = i64
+        L.or_lse_ess.argtypes = [P, i64, P]
+        L.or_poly_draw.argtypes = [u64, i64, u32, P, P, P]
+        L.or_poly_loglik.argtypes = [i32, P, P, P, i64]; L.or_poly_loglik.restype = f64
+        L.or_blr_draw_std.argtypes = [u64, i64, u32, i32, P]
+        L.or_blr_loglik.argtypes = [P, i32, P, P, i64, f64]; L.or_blr_loglik.restype = f64
+        L.or_importance.argtypes = [i32, P, P, i64, i32, P, i64, u64, i32, P, P, P, P, P]
+        L.or_importance.restype = ctypes.c_int
+        L.or_particle_logweights.argtypes = [i32, P, P, i64, i32, P, u64, i32, P, i64, P, P, P]
+        L.or_quant_bits.argtypes = [i64]; L.or_quant_bits.restype = i32
+        L.or_resample.argtypes = [P, i64, u64, u32, u32, P, f64, P]; L.or_resample.restype = ctypes.c_int
+        L.or_resample_textbook.argtypes = [P, i64, u64, u32, u32, P]; L.or_resample_textbook.restype = ctypes.c_int
+        L.or_gmm_logfactor.argtypes = [i32, P, P, f64, f64]; L.or_gmm_logfactor.restype = f64
+        L.or_gmm_init.argtypes = [u64, u32, i32, P, i64, P]
+        L.or_smc.argtypes = [i32, P, i64, i32, P, i64, u64, u32, f64, f64, f64, i64,
+                             P, P, P, P, P, P, P, P]
+        L.or_smc.restype = ctypes.c_int
+        L.or_num_threads.restype = ctypes.c_int
+        _lib = L
+    return _lib
+
+
+def _p(a):
+    return None if a is None else a.ctypes.data_as(ctypes.c_void_p)
+
+
+def _f64(a):
+    return np.ascontiguousarray(a, dtype=np.float64)
+
+
+def num_threads():
+    return lib().or_num_threads()
+
+
+# ------------------------------------------------------------------ streams --
+def philox(ctr, seeds):
+    """Philox4x32-10 blocks for rows of counters ``ctr`` [n,4] under keys ``seeds`` [n]."""
+    ctr = np.ascontiguousarray(ctr, dtype=np.uint32).reshape(-1, 4)
+    seeds = np.ascontiguousarray(np.broadcast_to(np.asarray(seeds, dtype=np.uint64), (ctr.shape[0],)))
+    out = np.empty_like(ctr)
+    lib().or_philox_batch(ctr.shape[0], _p(ctr), _p(seeds), _p(out))
+    return out
+
+
+def u01_single(w):
+    return lib().or_u01_single(int(w))
+
+
+def u01_double(lo, hi):
+    return lib().or_u01_double(int(lo), int(hi))
+
+
+def box_muller(u1, u2):
+    z0, z1 = ctypes.c_double(), ctypes.c_double()
+    lib().or_box_muller(float(u1), float(u2), ctypes.byref(z0), ctypes.byref(z1))
+    return z0.value, z1.value
+
+
+def uniform_discrete(w, lo, hi):
+    return lib().or_uniform_discrete(int(w), int(lo), int(hi))
+
+
+# --------------------------------------------------------------- reductions --
+def lse_ess(lw):
+    """{max, s1, s2, LSE, ESS} of a log-weight vector, FP64, compensated sums."""
+    lw = _f64(lw)
+    out = np.empty(5)
+    lib().or_lse_ess(_p(lw), lw.size, _p(out))
+    return dict(max=out[0], s1=out[1], s2=out[2], lse=out[3], ess=out[4])
+
+
+def quant_bits(n):
+    return lib().or_quant_bits(int(n))
+
+
+def resample(lw, seed, step=0, inst=0, band=0.0):
+    """Integer-rule systematic resampling; returns (ancestors, tie flags)."""
+    lw = _f64(lw)
+    anc = np.empty(lw.size, dtype=np.int32)
+    tie = np.zeros(lw.size, dtype=np.uint8)
+    rc = lib().or_resample(_p(lw), lw.size, seed, step, inst, _p(anc), band, _p(tie))
+    if rc:
+        raise ValueError(f"or_resample failed ({rc})")
+    return anc, tie.astype(bool)
+
+
+def resample_textbook(lw, seed, step=0, inst=0):
+    lw = _f64(lw)
+    anc = np.empty(lw.size, dtype=np.int32)
+    rc = lib().or_resample_textbook(_p(lw), lw.size, seed, step, inst, _p(anc))
+    if rc:
+        raise ValueError(f"or_resample_textbook failed ({rc})")
+    return anc
+
+
+# ------------------------------------------------------------------- models --
+POLY_HYPER = (10.0, 2.0, 5.0)
+BLR_HYPER = (1.0, 0.5)
+LGSSM_HYPER = (0.9, 1.0, 0.5, 0.0, 0.0)
+GMM_HYPER = (5.0, 1.0)
+
+
+def poly_draw(seed, i, hyper=POLY_HYPER, tag=TAG_PRIOR):
+    h = _f64(hyper)
+    n = ctypes.c_int32()
+    c = np.empty(6)
+    lib().or_poly_draw(seed, i, tag, _p(h), ctypes.byref(n), _p(c))
+    return n.value, c
+
+
+def poly_loglik(n, c, x, y):
+    c, x, y = _f64(c), _f64(x), _f64(y)
+    return lib().or_poly_loglik(int(n), _p(c), _p(x), _p(y), x.size)
+
+
+def blr_draw_std(seed, i, dim=16, tag=TAG_PRIOR):
+    z = np.empty(16)
+    lib().or_blr_draw_std(seed, i, tag, dim, _p(z))
+    return z[:dim]
+
+
+def blr_loglik(w, X, y, noise_sd=0.5):
+    w, X, y = _f64(w), _f64(X), _f64(y)
+    return lib().or_blr_loglik(_p(w), w.size, _p(X), _p(y), y.size, noise_sd)
+
+
+def gmm_logfactor(lpi, mu, sd, y):
+    lpi, mu = _f64(lpi), _f64(mu)
+    return lib().or_gmm_logfactor(lpi.size, _p(lpi), _p(mu), sd, y)
+
+
+def gmm_init(seed, inst, K, N, hyper=GMM_HYPER):
+    h = _f64(hyper)
+    st = np.empty((2 * K, N))
+    lib().or_gmm_init(seed, inst, K, _p(h), N, _p(st))
+    return st
+
+
+def _q_args(q):
+    if q is None:
+        return 0, None
+    mean, chol = q
+    return 1, _f64(np.concatenate([np.ravel(mean), np.ravel(chol)]))
+
+
+def importance(model, x, y, n, seed, hyper=None, dim=0, q=None, want_lw=False, want_latents=False):
+    """Importance sampling (likelihood weighting, or the Gaussian proposal ``q`` =
+    (mean, lower Cholesky factor) for BLR).  Returns a dict with log_z, ess and
+    model summaries (see ``ppl_oracle.c`` for the layout)."""
+    if hyper is None:
+        hyper = POLY_HYPER if model == MODEL_POLY else BLR_HYPER
+    x = _f64(x) if x is not None else np.zeros(1)
+    y = _f64(y)
+    h = _f64(hyper)
+    qk, qp = _q_args(q)
+    D = y.size
+    n_sum = 29 if model == MODEL_POLY else dim
+    summ = np.empty(max(n_sum, 1))
+    scal = np.empty(5)
+    lw = np.empty(n) if want_lw else None
+    n_lat = 6 if model == MODEL_POLY else dim
+    lat = np.empty((n_lat, n)) if want_latents else None
+    rc = lib().or_importance(model, _p(x), _p(y), D, dim, _p(h), n, seed, qk, _p(qp),
+                             _p(lw), _p(lat), _p(summ), _p(scal))
+    if rc:
+        raise ValueError(f"or_importance failed ({rc})")
+    out = dict(log_z=scal[0], ess=scal[1], max_lw=scal[2], s1=scal[3], s2=scal[4], summaries=summ[:n_sum])
+    if want_lw:
+        out["lw"] = lw
+    if want_latents:
+        out["latents"] = lat
+    return out
+
+
+def particle_logweights(model, x, y, idx, seed, hyper=None, dim=0, q=None):
+    """Log-weights (and latents) of the listed particle indices, one by one."""
+    if hyper is None:
+        hyper = POLY_HYPER if model == MODEL_POLY else BLR_HYPER
+    x = _f64(x) if x is not None else np.zeros(1)
+    y = _f64(y)
+    h = _f64(hyper)
+    idx = np.ascontiguousarray(idx, dtype=np.int64)
+    qk, qp = _q_args(q)
+    lw = np.empty(idx.size)
+    n_lat = 6 if model == MODEL_POLY else dim
+    lat = np.empty((idx.size, n_lat))
+    lib().or_particle_logweights(model, _p(x), _p(y), y.size, dim, _p(h), seed, qk, _p(qp),
+                                 idx.size, _p(idx), _p(lw), _p(lat))
+    return lw, lat
+
+
+def smc(model, y, n, seed, ess_frac=0.5, hyper=None, K=0, inst=0, ess_band=0.0,
+        anc_band=0.0, max_events=0, want_state=False):
+    """Sequential Monte Carlo over the factors y[0..T-1] (LGSSM or GMM)."""
+    if hyper is None:
+        hyper = LGSSM_HYPER if model == MODEL_LGSSM else GMM_HYPER
+    y = _f64(y)
+    T = y.size
+    h = _f64(hyper)
+    nf = 1 if model == MODEL_LGSSM else 2 * K
+    scal = np.empty(4)
+    ess_tr = np.empty(max(T, 1))
+    res_tr = np.zeros(max(T, 1), dtype=np.uint8)
+    ess_tie = np.zeros(max(T, 1), dtype=np.uint8)
+    anc = np.empty((max_events, n), dtype=np.int32) if max_events else None
+    tie = np.zeros((max_events, n), dtype=np.uint8) if max_events else None
+    st = np.empty((nf, n)) if want_state else None
+    lw = np.empty(n) if want_state else None
+    rc = lib().or_smc(model, _p(y), T, K, _p(h), n, seed, inst, ess_frac, ess_band, anc_band,
+                      max_events, _p(scal), _p(ess_tr), _p(res_tr), _p(ess_tie), _p(anc), _p(tie),
+                      _p(st), _p(lw))
+    out = dict(log_z=scal[0], ess=scal[1], n_resample=int(scal[2]), status=int(scal[3]), rc=rc,
+               ess_trace=ess_tr[:T], resampled=res_tr[:T].astype(bool), ess_tie=ess_tie[:T].astype(bool))
+    if max_events:
+        out["ancestors"] = anc
+        out["anc_tie"] = tie.astype(bool)
+    if want_state:
+        out["state"] = st
+        out["lw"] = lw
+    return out

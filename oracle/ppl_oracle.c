@@ -1,0 +1,612 @@
+/*
+ * ppl_oracle.c -- plain, slow, obviously-correct FP64 CPU oracle.
+ *
+ * TEST INFRASTRUCTURE ONLY.  Nothing on the product path may load, link or
+ * call this library: only the test suite, the package smoke check and the
+ * benchmark's CPU-baseline leg use it.  It shares no code, header, table or
+ * constant with the HIP library; the only contract the two sides share is the
+ * written random-stream specification (Philox4x32-10 counter layout, uniform
+ * and Box-Muller conversions), which each side implements on its own.
+ *
+ * What it computes, and where the paper defines it:
+ *   - sample / factor / observe semantics: a particle draws its latents at the
+ *     model's sample sites and adds log-factors to its log-weight
+ *     (paper Sec. 3.4, figure "sample-factor-observe-impl").
+ *   - importance sampling: run the model N times, each run's sample/factor
+ *     calls give it a log-probability, normalise those over the runs
+ *     (paper Sec. 3.6.2).
+ *   - the polynomial model of the paper's running example (Sec. 1.1, figure
+ *     "ppl-example2"): degree from a uniform-discrete prior, Gaussian
+ *     coefficients, factor(-distance).
+ *   - particle-based inference (SMC), named as future work in Sec. 6: bootstrap
+ *     propagation, log-sum-exp normaliser, ESS trigger, systematic resampling.
+ *   - fixed-size distribution/state values (Sec. 4.2.2, 4.2.4): every model here
+ *     has a static maximum latent size.
+ * All arithmetic is IEEE double, built with -ffp-contract=off, in the order the
+ * definitions state.  Particle loops are independent and may run on several
+ * host threads (OpenMP); every reduction runs sequentially in particle order
+ * with Neumaier-compensated sums.
+ *
+ * Philox4x32-10 follows Salmon, Moraes, Dror, Shaw, "Parallel Random Numbers:
+ * As Easy as 1, 2, 3" (SC'11): ten rounds of the Philox S-box on a 4x32-bit
+ * counter with a 2x32-bit key bumped by the golden-ratio / sqrt(3)-1 Weyl
+ * constants between rounds.
+ */
+#include <stdint.h>
+#include <stdlib.h>
+#include <string.h>
+#include <math.h>
+
+#ifdef _OPENMP
+#include <omp.h>
+#endif
+
+#ifndef M_PI
+#define M_PI 3.14159265358979323846
+#endif
+
+/* ---------------------------------------------------------------- Philox -- */
+/* Round multipliers and Weyl key increments of Philox4x32 (SC'11, Table 2 / Sec. 4). */
+#define PHX_MUL_A 0xD2511F53u
+#define PHX_MUL_B 0xCD9E8D57u
+#define PHX_WEYL_A 0x9E3779B9u
+#define PHX_WEYL_B 0xBB67AE85u
+
+/* One Philox4x32-10 block: counter (c0,c1,c2,c3), key = (lo32(seed), hi32(seed)). */
+void or_philox(uint32_t c0, uint32_t c1, uint32_t c2, uint32_t c3,
+               uint64_t seed, uint32_t out[4])
+{
+    uint32_t x0 = c0, x1 = c1, x2 = c2, x3 = c3;
+    uint32_t k0 = (uint32_t)seed, k1 = (uint32_t)(seed >> 32);
+    for (int round = 0; round < 10; ++round) {
+        if (round > 0) { k0 += PHX_WEYL_A; k1 += PHX_WEYL_B; }
+        uint64_t pa = (uint64_t)PHX_MUL_A * x0;
+        uint64_t pb = (uint64_t)PHX_MUL_B * x2;
+        uint32_t y0 = (uint32_t)(pb >> 32) ^ x1 ^ k0;
+        uint32_t y1 = (uint32_t)pb;
+        uint32_t y2 = (uint32_t)(pa >> 32) ^ x3 ^ k1;
+        uint32_t y3 = (uint32_t)pa;
+        x0 = y0; x1 = y1; x2 = y2; x3 = y3;
+    }
+    out[0] = x0; out[1] = x1; out[2] = x2; out[3] = x3;
+}
+
+/* Batch form for tests: ctr is [n][4], seeds is [n] (one key per row). */
+void or_philox_batch(int64_t n, const uint32_t *ctr, const uint64_t *seeds, uint32_t *out)
+{
+    for (int64_t i = 0; i < n; ++i)
+        or_philox(ctr[4 * i], ctr[4 * i + 1], ctr[4 * i + 2], ctr[4 * i + 3], seeds[i], out + 4 * i);
+}
+
+/* Stream tags carried in the low byte of counter word 3 (instance id above it). */
+enum { TAG_PRIOR = 0, TAG_PROPOSAL = 1, TAG_RESAMPLE = 2, TAG_TRAIN_SIM = 4,
+       TAG_INIT_WEIGHTS = 5 };
+
+static inline void draw4(uint64_t seed, uint32_t c0, uint32_t c1, uint32_t c2,
+                         uint32_t inst, uint32_t tag, uint32_t w[4])
+{
+    or_philox(c0, c1, c2, (inst << 8) | tag, seed, w);
+}
+
+/* ------------------------------------------------------------- uniforms -- */
+/* Single-precision stream uniform: 23 high bits plus one half, exact in FP32. */
+double or_u01_single(uint32_t w) { return ((double)(w >> 9) + 0.5) * 0x1p-23; }
+
+/* Double-precision stream uniform from two words (lo first): 52 bits plus a half. */
+double or_u01_double(uint32_t lo, uint32_t hi)
+{
+    uint64_t v = ((uint64_t)hi << 32) | lo;
+    return ((double)(v >> 12) + 0.5) * 0x1p-52;
+}
+
+/* Box-Muller: radius sqrt(-2 ln u1), angle 2*pi*u2. */
+void or_box_muller(double u1, double u2, double *z0, double *z1)
+{
+    double r = sqrt(-2.0 * log(u1));
+    double th = 2.0 * M_PI * u2;
+    *z0 = r * cos(th);
+    *z1 = r * sin(th);
+}
+
+/* Uniform-discrete on {lo..hi} from one word: lo + floor(w * (hi-lo+1) / 2^32). */
+int64_t or_uniform_discrete(uint32_t w, int64_t lo, int64_t hi)
+{
+    uint64_t range = (uint64_t)(hi - lo + 1);
+    return lo + (int64_t)(((uint64_t)w * range) >> 32);
+}
+
+/* Four single-precision-stream normals from one Philox block (two Box-Muller pairs). */
+static void normals4_single(const uint32_t w[4], double z[4])
+{
+    or_box_muller(or_u01_single(w[0]), or_u01_single(w[1]), &z[0], &z[1]);
+    or_box_muller(or_u01_single(w[2]), or_u01_single(w[3]), &z[2], &z[3]);
+}
+
+/* ---------------------------------------------------- compensated sums -- */
+typedef struct { double s, c; } nsum;
+static inline void nadd(nsum *a, double v)
+{
+    double t = a->s + v;
+    if (fabs(a->s) >= fabs(v)) a->c += (a->s - t) + v;
+    else                       a->c += (v - t) + a->s;
+    a->s = t;
+}
+static inline double nval(nsum a) { return a.s + a.c; }
+
+/* ------------------------------------------------- log-sum-exp and ESS -- */
+/* out = {max, s1 = sum exp(l-m), s2 = sum exp(2(l-m)), LSE = m + log s1, ESS = s1^2/s2}.
+ * -inf entries contribute zero.  All entries -inf: LSE = -inf, ESS = 0. */
+void or_lse_ess(const double *lw, int64_t n, double out[5])
+{
+    double m = -INFINITY;
+    for (int64_t i = 0; i < n; ++i) if (lw[i] > m) m = lw[i];
+    if (!(m > -INFINITY)) {
+        out[0] = m; out[1] = 0.0; out[2] = 0.0; out[3] = -INFINITY; out[4] = 0.0;
+        return;
+    }
+    nsum s1 = {0, 0}, s2 = {0, 0};
+    for (int64_t i = 0; i < n; ++i) {
+        double e = exp(lw[i] - m);
+        nadd(&s1, e);
+        nadd(&s2, e * e);
+    }
+    double a = nval(s1), b = nval(s2);
+    out[0] = m; out[1] = a; out[2] = b; out[3] = m + log(a); out[4] = a * a / b;
+}
+
+/* ------------------------------------------------------------- models -- */
+enum { MODEL_POLY = 1, MODEL_BLR = 2, MODEL_LGSSM = 3, MODEL_GMM = 4 };
+
+/* POLY (paper Sec. 1.1): n ~ UniformDiscrete{2..5}; c_j ~ Normal(0, sd), j < n;
+ * factor(-sum_d (y_d - poly_c(x_d))^2 / 2).  Word allocation per particle i:
+ * block 0 word 0 -> n; blocks 1..3 -> one double-precision Box-Muller pair each,
+ * giving c_0..c_5 (always all drawn; only c_0..c_{n-1} are used).
+ * hyper = {sd, n_lo, n_hi}. */
+void or_poly_draw(uint64_t seed, int64_t i, uint32_t tag, const double *hyper,
+                  int32_t *n_out, double c[6])
+{
+    uint32_t w[4];
+    draw4(seed, (uint32_t)i, 0, 0, 0, tag, w);
+    *n_out = (int32_t)or_uniform_discrete(w[0], (int64_t)hyper[1], (int64_t)hyper[2]);
+    for (uint32_t b = 1; b <= 3; ++b) {
+        draw4(seed, (uint32_t)i, b, 0, 0, tag, w);
+        double z0, z1;
+        or_box_muller(or_u01_double(w[0], w[1]), or_u01_double(w[2], w[3]), &z0, &z1);
+        c[2 * (b - 1)] = hyper[0] * z0;
+        c[2 * (b - 1) + 1] = hyper[0] * z1;
+    }
+}
+
+/* Horner over c_{n-1}..c_0, then -1/2 * sum of squared residuals. */
+double or_poly_loglik(int32_t n, const double *c, const double *x, const double *y, int64_t D)
+{
+    double acc = 0.0;
+    for (int64_t d = 0; d < D; ++d) {
+        double p = 0.0;
+        for (int32_t j = n - 1; j >= 0; --j) p = p * x[d] + c[j];
+        double r = y[d] - p;
+        acc += r * r;
+    }
+    return -0.5 * acc;
+}
+
+/* BLR: w_k ~ Normal(0, prior_sd), k < d (d <= 16, multiple of 4);
+ * observe(Normal(x_d . w, noise_sd), y_d) for every row d.
+ * Word allocation: block b gives w_{4b..4b+3} (two single-precision Box-Muller pairs).
+ * hyper = {prior_sd, noise_sd}. */
+void or_blr_draw_std(uint64_t seed, int64_t i, uint32_t tag, int32_t dim, double z[16])
+{
+    uint32_t w[4];
+    for (int32_t b = 0; b < dim / 4; ++b) {
+        draw4(seed, (uint32_t)i, (uint32_t)b, 0, 0, tag, w);
+        normals4_single(w, z + 4 * b);
+    }
+}
+
+double or_blr_loglik(const double *wv, int32_t dim, const double *X, const double *y,
+                     int64_t D, double noise_sd)
+{
+    double var = noise_sd * noise_sd;
+    double c = -0.5 * log(2.0 * M_PI * var);
+    double acc = 0.0;
+    for (int64_t d = 0; d < D; ++d) {
+        double mu = 0.0;
+        for (int32_t k = 0; k < dim; ++k) mu += X[d * dim + k] * wv[k];
+        double r = y[d] - mu;
+        acc += c - r * r / (2.0 * var);
+    }
+    return acc;
+}
+
+/* Gaussian proposal q = N(mean, L L^T) for BLR (L lower-triangular, row-major).
+ * w = mean + L z with z standard normal from the PROPOSAL stream; returns
+ * log p(w) - log q(w) where p is the N(0, prior_sd^2 I) prior. */
+static double blr_proposal_draw(uint64_t seed, int64_t i, int32_t dim, const double *qp,
+                                double prior_sd, double wv[16])
+{
+    double z[16];
+    or_blr_draw_std(seed, i, TAG_PROPOSAL, dim, z);
+    const double *mean = qp, *L = qp + dim;
+    double logdet = 0.0, zz = 0.0, ww = 0.0;
+    for (int32_t r = 0; r < dim; ++r) {
+        double v = mean[r];
+        for (int32_t k = 0; k <= r; ++k) v += L[r * dim + k] * z[k];
+        wv[r] = v;
+        logdet += log(L[r * dim + r]);
+        zz += z[r] * z[r];
+        ww += v * v;
+    }
+    double log_q = -0.5 * zz - logdet - 0.5 * dim * log(2.0 * M_PI);
+    double log_p = -0.5 * ww / (prior_sd * prior_sd) - dim * log(prior_sd) - 0.5 * dim * log(2.0 * M_PI);
+    return log_p - log_q;
+}
+
+/* ------------------------------------------------- importance sampling -- */
+/* Summary layout.
+ *   POLY: [0..3]  P(n = 2..5 | y)
+ *         [4..23] E[c_j | n, y] for n = 2..5 (5 slots each, zero beyond n; zero if mass 0)
+ *         [24..28] E[c_j 1{j < n} | y] (zero-padded marginal)          -> 29 values
+ *   BLR:  [0..d-1] E[w | y]                                             -> d values
+ * scalars = {log Z-hat, ESS, max lw, s1, s2}. */
+int or_importance(int32_t model, const double *x, const double *y, int64_t D, int32_t dim,
+                  const double *hyper, int64_t N, uint64_t seed,
+                  int32_t q_kind, const double *q_params,
+                  double *lw_out, double *lat_out, double *summaries, double *scalars)
+{
+    if (N <= 0) return -1;
+    if (model != MODEL_POLY && model != MODEL_BLR) return -2;
+    if (model == MODEL_BLR && (dim <= 0 || dim > 16 || dim % 4)) return -1;
+    int n_lat = model == MODEL_POLY ? 6 : dim;       /* POLY: n plus c_0..c_4 */
+    double *lw = (double *)malloc(sizeof(double) * N);
+    double *lat = (double *)malloc(sizeof(double) * N * n_lat);
+    if (!lw || !lat) { free(lw); free(lat); return -3; }
+
+#pragma omp parallel for schedule(static)
+    for (int64_t i = 0; i < N; ++i) {
+        if (model == MODEL_POLY) {
+            int32_t n; double c[6];
+            or_poly_draw(seed, i, TAG_PRIOR, hyper, &n, c);
+            lw[i] = or_poly_loglik(n, c, x, y, D);
+            lat[0 * N + i] = n;
+            for (int j = 0; j < 5; ++j) lat[(1 + j) * N + i] = c[j];
+        } else {
+            double wv[16], extra = 0.0;
+            if (q_kind == 1) {
+                extra = blr_proposal_draw(seed, i, dim, q_params, hyper[0], wv);
+            } else {
+                double z[16];
+                or_blr_draw_std(seed, i, TAG_PRIOR, dim, z);
+                for (int k = 0; k < dim; ++k) wv[k] = hyper[0] * z[k];
+            }
+            lw[i] = or_blr_loglik(wv, dim, x, y, D, hyper[1]) + extra;
+            for (int k = 0; k < dim; ++k) lat[k * N + i] = wv[k];
+        }
+    }
+
+    double st[5];
+    or_lse_ess(lw, N, st);
+    scalars[0] = st[3] - log((double)N);
+    scalars[1] = st[4];
+    scalars[2] = st[0];
+    scalars[3] = st[1];
+    scalars[4] = st[2];
+
+    if (summaries) {
+        double m = st[0];
+        if (model == MODEL_POLY) {
+            nsum mass[4] = {{0}}, cm[4][5] = {{{0}}}, marg[5] = {{0}};
+            for (int64_t i = 0; i < N; ++i) {
+                double e = exp(lw[i] - m);
+                int n = (int)lat[i];
+                nadd(&mass[n - 2], e);
+                for (int j = 0; j < n; ++j) {
+                    double c = lat[(1 + j) * N + i];
+                    nadd(&cm[n - 2][j], e * c);
+                    nadd(&marg[j], e * c);
+                }
+            }
+            for (int k = 0; k < 4; ++k) {
+                double mk = nval(mass[k]);
+                summaries[k] = mk / st[1];
+                for (int j = 0; j < 5; ++j)
+                    summaries[4 + 5 * k + j] = mk > 0 ? nval(cm[k][j]) / mk : 0.0;
+            }
+            for (int j = 0; j < 5; ++j) summaries[24 + j] = nval(marg[j]) / st[1];
+        } else {
+            for (int k = 0; k < dim; ++k) {
+                nsum a = {0, 0};
+                for (int64_t i = 0; i < N; ++i) nadd(&a, exp(lw[i] - m) * lat[k * N + i]);
+                summaries[k] = nval(a) / st[1];
+            }
+        }
+    }
+    if (lw_out) memcpy(lw_out, lw, sizeof(double) * N);
+    if (lat_out) memcpy(lat_out, lat, sizeof(double) * N * n_lat);
+    free(lw); free(lat);
+    return 0;
+}
+
+/* Per-particle log-weights for an arbitrary list of particle indices (used to
+ * check sampled outputs of a full-size run one particle at a time). */
+int or_particle_logweights(int32_t model, const double *x, const double *y, int64_t D,
+                           int32_t dim, const double *hyper, uint64_t seed,
+                           int32_t q_kind, const double *q_params,
+                           int64_t m, const int64_t *idx, double *lw, double *lat /* [m][6 or dim] */)
+{
+#pragma omp parallel for schedule(dynamic, 1)
+    for (int64_t r = 0; r < m; ++r) {
+        int64_t i = idx[r];
+        if (model == MODEL_POLY) {
+            int32_t n; double c[6];
+            or_poly_draw(seed, i, TAG_PRIOR, hyper, &n, c);
+            lw[r] = or_poly_loglik(n, c, x, y, D);
+            if (lat) { lat[r * 6] = n; for (int j = 0; j < 5; ++j) lat[r * 6 + 1 + j] = c[j]; }
+        } else {
+            double wv[16], extra = 0.0;
+            if (q_kind == 1) extra = blr_proposal_draw(seed, i, dim, q_params, hyper[0], wv);
+            else {
+                double z[16];
+                or_blr_draw_std(seed, i, TAG_PRIOR, dim, z);
+                for (int k = 0; k < dim; ++k) wv[k] = hyper[0] * z[k];
+            }
+            lw[r] = or_blr_loglik(wv, dim, x, y, D, hyper[1]) + extra;
+            if (lat) for (int k = 0; k < dim; ++k) lat[r * dim + k] = wv[k];
+        }
+    }
+    return 0;
+}
+
+/* ------------------------------------------------------------ resampling -- */
+/* Quantisation exponent: q_i = floor(exp(lw_i - max) * 2^k), k = 62 - ceil(log2 N),
+ * so that the total S = sum q_i fits in 62 bits. */
+int32_t or_quant_bits(int64_t N)
+{
+    int c = 0;
+    while (((int64_t)1 << c) < N) ++c;
+    return 62 - c;
+}
+
+/* Systematic resampling with integer-quantised weights (association-free).
+ *   Q = inclusive prefix sum of q, S = Q_{N-1};
+ *   R = one 64-bit word (words 0,1 of block (0, 0, step, inst<<8 | RESAMPLE));
+ *   U = floor(R * S / 2^64);  ancestor a(j) = min{a : N * Q_a > j * S + U}.
+ * tie (optional): slot j is flagged when the slot point j*S+U lies within
+ * band * N * S of either neighbouring boundary N*Q_{a-1}, N*Q_a.
+ * Returns 0, or -1 when no weight is positive (every entry -inf or NaN). */
+int or_resample(const double *lw, int64_t N, uint64_t seed, uint32_t step, uint32_t inst,
+                int32_t *anc, double band, uint8_t *tie)
+{
+    double m = -INFINITY;
+    for (int64_t i = 0; i < N; ++i) if (lw[i] > m) m = lw[i];
+    if (!(m > -INFINITY)) return -1;
+    int32_t k = or_quant_bits(N);
+    uint64_t *Q = (uint64_t *)malloc(sizeof(uint64_t) * N);
+    if (!Q) return -3;
+    uint64_t acc = 0;
+    for (int64_t i = 0; i < N; ++i) {
+        double e = exp(lw[i] - m);
+        uint64_t q = (uint64_t)floor(ldexp(e, k));
+        acc += q;
+        Q[i] = acc;
+    }
+    uint64_t S = acc;
+    uint32_t w[4];
+    draw4(seed, 0, 0, step, inst, TAG_RESAMPLE, w);
+    uint64_t R = ((uint64_t)w[1] << 32) | w[0];
+    uint64_t U = (uint64_t)(((unsigned __int128)R * S) >> 64);
+    long double tot = (long double)N * (long double)S;
+    int64_t a = 0;
+    for (int64_t j = 0; j < N; ++j) {
+        unsigned __int128 t = (unsigned __int128)j * S + U;
+        while ((unsigned __int128)N * Q[a] <= t) ++a;
+        anc[j] = (int32_t)a;
+        if (tie) {
+            unsigned __int128 hi = (unsigned __int128)N * Q[a];
+            unsigned __int128 lo = a > 0 ? (unsigned __int128)N * Q[a - 1] : 0;
+            long double d1 = (long double)(hi - t), d2 = (long double)(t - lo);
+            long double dm = d1 < d2 ? d1 : d2;
+            tie[j] = (uint8_t)(dm <= (long double)band * tot);
+        }
+    }
+    free(Q);
+    return 0;
+}
+
+/* Textbook FP64 systematic resampling with the same uniform u = R / 2^64:
+ * a(j) = min{a : C_a > (j + u) / N}, C = cumulative normalised weights. */
+int or_resample_textbook(const double *lw, int64_t N, uint64_t seed, uint32_t step,
+                         uint32_t inst, int32_t *anc)
+{
+    double m = -INFINITY;
+    for (int64_t i = 0; i < N; ++i) if (lw[i] > m) m = lw[i];
+    if (!(m > -INFINITY)) return -1;
+    double *C = (double *)malloc(sizeof(double) * N);
+    if (!C) return -3;
+    nsum s = {0, 0};
+    for (int64_t i = 0; i < N; ++i) { nadd(&s, exp(lw[i] - m)); C[i] = nval(s); }
+    double tot = C[N - 1];
+    uint32_t w[4];
+    draw4(seed, 0, 0, step, inst, TAG_RESAMPLE, w);
+    double u = (double)(((uint64_t)w[1] << 32) | w[0]) * 0x1p-64;
+    int64_t a = 0;
+    for (int64_t j = 0; j < N; ++j) {
+        double p = (j + u) / (double)N;
+        while (a < N - 1 && C[a] / tot <= p) ++a;
+        anc[j] = (int32_t)a;
+    }
+    free(C);
+    return 0;
+}
+
+/* ------------------------------------------------------------------ SMC -- */
+/* LGSSM (bootstrap filter):  x_0 = m0 + p0_sd * z;  x_s = a x_{s-1} + q_sd eps_s;
+ * observe(Normal(x_s, r_sd), y_s).  hyper = {a, q_sd, r_sd, m0, p0_sd}.
+ * Noise word allocation for slot i: eps_s = the (s mod 4)-th normal of block
+ * (i, 0, s div 4, PRIOR) (two single-precision Box-Muller pairs); the initial
+ * normal is normal 0 of block (i, 1, 0, PRIOR).
+ *
+ * GMM (mixture with known K, unit-sd components by default): pi ~ Dirichlet(1_K)
+ * as normalised Exp(1) draws E_k = -ln u (words 0..7 of blocks 0,1), mu_k ~
+ * Normal(0, mu_sd) (normals 0..7 of blocks 2,3); one factor per datum,
+ * log sum_k pi_k Normal(y_s; mu_k, comp_sd).  hyper = {mu_sd, comp_sd}.
+ * State layout [field][N]: GMM fields 0..K-1 = log pi_k, K..2K-1 = mu_k. */
+static inline void lgssm_eps4(uint64_t seed, int64_t i, uint32_t grp, uint32_t inst, double z[4])
+{
+    uint32_t w[4];
+    draw4(seed, (uint32_t)i, 0, grp, inst, TAG_PRIOR, w);
+    normals4_single(w, z);
+}
+
+static void gmm_init_particle(uint64_t seed, int64_t i, uint32_t inst, int32_t K,
+                              const double *hyper, double *lpi, double *mu)
+{
+    uint32_t w[8];
+    draw4(seed, (uint32_t)i, 0, 0, inst, TAG_PRIOR, w);
+    draw4(seed, (uint32_t)i, 1, 0, inst, TAG_PRIOR, w + 4);
+    double E[8], tot = 0.0;
+    for (int k = 0; k < K; ++k) { E[k] = -log(or_u01_single(w[k])); tot += E[k]; }
+    for (int k = 0; k < K; ++k) lpi[k] = log(E[k] / tot);
+    double z[8];
+    uint32_t v[4];
+    draw4(seed, (uint32_t)i, 2, 0, inst, TAG_PRIOR, v);
+    normals4_single(v, z);
+    draw4(seed, (uint32_t)i, 3, 0, inst, TAG_PRIOR, v);
+    normals4_single(v, z + 4);
+    for (int k = 0; k < K; ++k) mu[k] = hyper[0] * z[k];
+}
+
+/* log sum_k pi_k Normal(y; mu_k, sd), evaluated with the max shift. */
+double or_gmm_logfactor(int32_t K, const double *lpi, const double *mu, double sd, double y)
+{
+    double t[8], mx = -INFINITY;
+    double c = -0.5 * log(2.0 * M_PI) - log(sd);
+    for (int k = 0; k < K; ++k) {
+        double r = (y - mu[k]) / sd;
+        t[k] = lpi[k] + c - 0.5 * r * r;
+        if (t[k] > mx) mx = t[k];
+    }
+    if (!(mx > -INFINITY)) return -INFINITY;
+    double s = 0.0;
+    for (int k = 0; k < K; ++k) s += exp(t[k] - mx);
+    return mx + log(s);
+}
+
+/* Generic SMC driver.
+ *   y[T] observations; N particles; ess_frac threshold (resample when ESS < ess_frac*N,
+ *   never after the last factor).  log Z-hat = sum over epochs of (LSE(lw) - log N).
+ * Outputs (any may be NULL):
+ *   scal[4]      = {log Z-hat, final ESS, number of resamplings, status}
+ *   ess_tr[T]    = ESS after factor s (before any resampling)
+ *   res_tr[T]    = 1 if resampled after factor s
+ *   ess_tie[T]   = 1 if |ESS/N - ess_frac| <= ess_band (decision sensitive to rounding)
+ *   anc_hist[max_events][N], tie_hist[max_events][N]: ancestors / tie flags per event
+ *   state_out[n_fields][N], lw_out[N]: final particles and log-weights */
+int or_smc(int32_t model, const double *y, int64_t T, int32_t K, const double *hyper,
+           int64_t N, uint64_t seed, uint32_t inst, double ess_frac,
+           double ess_band, double anc_band, int64_t max_events,
+           double *scal, double *ess_tr, uint8_t *res_tr, uint8_t *ess_tie,
+           int32_t *anc_hist, uint8_t *tie_hist, double *state_out, double *lw_out)
+{
+    if (N <= 0 || T < 0) return -1;
+    if (model != MODEL_LGSSM && model != MODEL_GMM) return -2;
+    if (model == MODEL_GMM && (K < 1 || K > 8)) return -1;
+    int nf = model == MODEL_LGSSM ? 1 : 2 * K;
+    double *st = (double *)malloc(sizeof(double) * N * nf);
+    double *st2 = (double *)malloc(sizeof(double) * N * nf);
+    double *lw = (double *)calloc(N, sizeof(double));
+    int32_t *anc = (int32_t *)malloc(sizeof(int32_t) * N);
+    uint8_t *tie = (uint8_t *)malloc(N);
+    if (!st || !st2 || !lw || !anc || !tie) { free(st); free(st2); free(lw); free(anc); free(tie); return -3; }
+
+    if (model == MODEL_LGSSM) {
+        for (int64_t i = 0; i < N; ++i) {
+            double z0 = 0.0;
+            if (hyper[4] != 0.0) {
+                uint32_t w[4]; double z[4];
+                draw4(seed, (uint32_t)i, 1, 0, inst, TAG_PRIOR, w);
+                normals4_single(w, z);
+                z0 = z[0];
+            }
+            st[i] = hyper[3] + hyper[4] * z0;
+        }
+    } else {
+        for (int64_t i = 0; i < N; ++i) {
+            double lpi[8], mu[8];
+            gmm_init_particle(seed, i, inst, K, hyper, lpi, mu);
+            for (int k = 0; k < K; ++k) { st[k * N + i] = lpi[k]; st[(K + k) * N + i] = mu[k]; }
+        }
+    }
+
+    nsum logz = {0, 0};
+    int64_t nres = 0, ev = 0;
+    double ess = (double)N, stat[5];
+    int status = 0;
+    for (int64_t s = 0; s < T; ++s) {
+#pragma omp parallel for schedule(static)
+        for (int64_t i = 0; i < N; ++i) {
+            if (model == MODEL_LGSSM) {
+                double z[4];
+                lgssm_eps4(seed, i, (uint32_t)(s >> 2), inst, z);
+                double xv = hyper[0] * st[i] + hyper[1] * z[s & 3];
+                st[i] = xv;
+                double r = (y[s] - xv) / hyper[2];
+                lw[i] += -0.5 * log(2.0 * M_PI) - log(hyper[2]) - 0.5 * r * r;
+            } else {
+                double lpi[8], mu[8];
+                for (int k = 0; k < K; ++k) { lpi[k] = st[k * N + i]; mu[k] = st[(K + k) * N + i]; }
+                lw[i] += or_gmm_logfactor(K, lpi, mu, hyper[1], y[s]);
+            }
+        }
+        or_lse_ess(lw, N, stat);
+        if (!(stat[0] > -INFINITY) || isnan(stat[3])) { status = -7; ess = 0.0; break; }
+        ess = stat[4];
+        if (ess_tr) ess_tr[s] = ess;
+        if (ess_tie) ess_tie[s] = (uint8_t)(fabs(ess / (double)N - ess_frac) <= ess_band);
+        int resample = (s < T - 1) && (ess < ess_frac * (double)N);
+        if (res_tr) res_tr[s] = (uint8_t)resample;
+        if (resample) {
+            nadd(&logz, stat[3] - log((double)N));
+            int rc = or_resample(lw, N, seed, (uint32_t)s, inst, anc, anc_band, tie);
+            if (rc) { status = rc; break; }
+            if (anc_hist && ev < max_events) memcpy(anc_hist + ev * N, anc, sizeof(int32_t) * N);
+            if (tie_hist && ev < max_events) memcpy(tie_hist + ev * N, tie, N);
+            for (int f = 0; f < nf; ++f)
+                for (int64_t j = 0; j < N; ++j) st2[f * N + j] = st[f * N + anc[j]];
+            double *tmp = st; st = st2; st2 = tmp;
+            for (int64_t j = 0; j < N; ++j) lw[j] = 0.0;
+            ++nres; ++ev;
+        }
+    }
+    if (status == 0) {
+        if (T > 0) { or_lse_ess(lw, N, stat); nadd(&logz, stat[3] - log((double)N)); ess = stat[4]; }
+        else ess = (double)N;
+    }
+    if (scal) {
+        scal[0] = status == 0 ? nval(logz) : -INFINITY;
+        scal[1] = ess; scal[2] = (double)nres; scal[3] = status;
+    }
+    if (state_out) memcpy(state_out, st, sizeof(double) * N * nf);
+    if (lw_out) memcpy(lw_out, lw, sizeof(double) * N);
+    free(st); free(st2); free(lw); free(anc); free(tie);
+    return status;
+}
+
+/* Per-particle GMM initial state (tests of the Dirichlet / Normal prior draws). */
+void or_gmm_init(uint64_t seed, uint32_t inst, int32_t K, const double *hyper,
+                 int64_t N, double *state /* [2K][N] */)
+{
+    for (int64_t i = 0; i < N; ++i) {
+        double lpi[8], mu[8];
+        gmm_init_particle(seed, i, inst, K, hyper, lpi, mu);
+        for (int k = 0; k < K; ++k) { state[k * N + i] = lpi[k]; state[(K + k) * N + i] = mu[k]; }
+    }
+}
+
+int or_num_threads(void)
+{
+#ifdef _OPENMP
+    return omp_get_max_threads();
+#else
+    return 1;
+#endif
+}
