@@ -1,0 +1,164 @@
+"""Benchmark of the particle-inference hot path on one MI355X.
+
+Workload (one step = one ppl_importance call = the whole path): conjugate
+Bayesian linear regression, d = 16 weights, D = 10^4 rows, N = 2^20 particles,
+prior proposal, FP32 likelihood with FP64 log-sum-exp / ESS / posterior mean.
+Inputs are synthetic (seeded, see synthetic/) and resident in HBM before the
+timed region.  The metric is particle-likelihood evaluations per second
+(N * D per step).
+
+Printed as one JSON line, with
+  roofline     -- the dominant kernel (blr_is_kernel) timed with HIP events on
+                  its launch stream during the timed steps, against the FP32
+                  VALU ceiling of this build (packed FP32 is disabled):
+                  algorithmic work 34 FLOP per evaluation (16 FMA residual +
+                  1 FMA square-accumulate);
+  cpu_baseline -- the CPU oracle on a bounded sample of the same workload.
+
+Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu] [--config blr|poly|poly-paper]
+"""
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+# Published MI355X figures used as denominators.
+CU, CLOCK_HZ, SIMD_PER_CU, LANES_PER_SIMD = 256, 2.4e9, 4, 16
+FP32_VALU_UNPACKED_TFLOPS = CU * SIMD_PER_CU * LANES_PER_SIMD * 2 * CLOCK_HZ / 1e12   # 78.6
+FP32_VALU_PUBLISHED_TFLOPS = 157.3        # needs packed FP32, which this build disables
+FP64_VALU_TFLOPS = 78.6
+
+FLOP_PER_EVAL_BLR = 34                    # 17 FMA per (particle, row) at d = 16
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--config", default="blr", choices=["blr", "poly", "poly-paper"])
+    ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
+    ap.add_argument("--cpu-sample", type=int, default=1 << 19, help="particles in the oracle sample")
+    return ap.parse_args()
+
+
+def cpu_baseline_blr(X, y, n_sample, seed):
+    import oracle
+    oracle.build()
+    t0 = time.perf_counter()
+    oracle.importance(oracle.MODEL_BLR, X, y, n_sample, seed, dim=X.shape[1])
+    dt = time.perf_counter() - t0
+    return {"value": n_sample * y.size / dt, "unit": "particle-likelihood evals/s",
+            "cores": oracle.num_threads(), "kind": "oracle",
+            "sample": f"{n_sample} of the 2^20 particles over all {y.size} rows (FP64 oracle, {dt:.1f} s)"}
+
+
+def cpu_baseline_poly(x, y, n, seed):
+    import oracle
+    oracle.build()
+    t0 = time.perf_counter()
+    oracle.importance(oracle.MODEL_POLY, x, y, n, seed)
+    dt = time.perf_counter() - t0
+    return {"value": n * y.size / dt, "unit": "particle-likelihood evals/s", "cores": oracle.num_threads(),
+            "kind": "oracle", "sample": f"{n} particles over all {y.size} points ({dt:.1f} s)"}
+
+
+def main():
+    args = parse()
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
+        print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1"}))
+        sys.exit(2)
+    import numpy as np
+    import torch
+
+    import synthetic
+    import paper_2010_08454_amd as ppl
+
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+    stream = torch.cuda.current_stream()
+
+    if args.config == "blr":
+        d, D, N, seed = 16, 10_000, 1 << 20, 1
+        X, y, _ = synthetic.blr_data(D=D, d=d)
+        dX, dy = torch.from_numpy(X).to(dev), torch.from_numpy(y).to(dev)
+        data = ppl.make_data(dX, dy, dim=d)
+        model, kname = ppl.PPL_MODEL_BLR, "blr_is_kernel"
+        nsum = d
+        workload = {"workload": "blr-importance-sampling", "model": "conjugate Bayesian linear regression",
+                    "d": d, "rows": D, "particles": N, "proposal": "prior",
+                    "precision": "fp32 likelihood, fp64 normaliser"}
+        flop_per_launch = FLOP_PER_EVAL_BLR * N * D
+        peak, bound, unit, dtype = FP32_VALU_UNPACKED_TFLOPS, "alu", "TFLOP/s", "f32"
+    else:
+        D = 100
+        N = 10_000 if args.config == "poly" else 2_000_000
+        seed = 1
+        x, y = synthetic.poly_data(D=D)
+        dx, dy = torch.from_numpy(x).to(dev), torch.from_numpy(y).to(dev)
+        data = ppl.make_data(dx, dy)
+        model, kname = ppl.PPL_MODEL_POLY, "poly_is_kernel"
+        nsum = 29
+        workload = {"workload": "poly-importance-sampling", "model": "polynomial fit (degree ~ U{2..5})",
+                    "points": D, "particles": N, "precision": "fp64"}
+        flop_per_launch = 10 * N * D      # 4 FMA Horner + sub + FMA square, zero-padded: 10 FLOP
+        peak, bound, unit, dtype = FP64_VALU_TFLOPS, "alu", "TFLOP/s", "f64"
+
+    ws = ppl.workspace(ppl.ppl_workspace_size(model, data, N, ppl.PPL_ALGO_IS), dev)
+    scal = torch.empty(8, dtype=torch.float64, device=dev)
+    summ = torch.empty(nsum, dtype=torch.float64, device=dev)
+
+    def step():
+        ppl.ppl_importance(model, data, N, seed, ws=ws, stream=stream, scalars=scal, summaries=summ)
+
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    ppl.ppl_timing_enable(True)
+    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    ev0.record(stream)
+    for _ in range(args.steps):
+        step()
+    ev1.record(stream)
+    torch.cuda.synchronize()
+    total_ms = ev0.elapsed_time(ev1)
+    k_ms, k_n = ppl.ppl_timing_query(kname)
+    ppl.ppl_timing_enable(False)
+    ms_per_step = total_ms / args.steps
+    evals = N * D
+    value = evals / (ms_per_step / 1e3)
+    k_avg_ms = k_ms / max(k_n, 1)
+    achieved = flop_per_launch / (k_avg_ms / 1e3) / 1e12
+    s = scal.cpu().numpy()
+    assert s[3] == 0 and math.isfinite(s[0]), f"device status {s[3]}"
+
+    roofline = {"bound": bound, "achieved": round(achieved, 3), "peak": round(peak, 2), "unit": unit,
+                "frac": round(achieved / peak, 4), "traffic": None,
+                "kernel": kname, "kernel_ms": round(k_avg_ms, 4), "kernel_launches": k_n,
+                "flop_per_launch": flop_per_launch}
+    if args.config == "blr":
+        roofline["peak_note"] = ("fp32 FMA VALU ceiling without packed-FP32 (disabled in this build): "
+                                 "256 CU x 64 lanes x 2 FLOP x 2.4 GHz; the published 157.3 assumes packed FP32")
+        roofline["frac_vs_published_157_3"] = round(achieved / FP32_VALU_PUBLISHED_TFLOPS, 4)
+
+    out = {"metric": "particle-likelihood evals/s", "value": value, "unit": "evals/s", "n_gpus": 1,
+           "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(ms_per_step, 4),
+           "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": dtype,
+           "data": "synthetic (seeded generators, inputs resident in HBM)", "config": workload,
+           "log_evidence": float(s[0]), "ess": float(s[1]), "roofline": roofline}
+    if not args.no_cpu:
+        if args.config == "blr":
+            out["cpu_baseline"] = cpu_baseline_blr(X, y, args.cpu_sample, seed)
+        else:
+            out["cpu_baseline"] = cpu_baseline_poly(x, y, min(N, 1 << 20), seed)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

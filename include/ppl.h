@@ -1,0 +1,208 @@
+/*
+ * ppl.h -- C ABI of the MI355X (gfx950) particle-inference library libppl.so.
+ *
+ * The library runs the data-parallel hot path of particle-based inference over
+ * hand-written generative models: many independent executions (particles)
+ * draw latents at the model's `sample` sites and add to a log-weight at its
+ * `factor` sites (paper Sec. 3.4, figure "sample-factor-observe-impl");
+ * importance sampling normalises the log-weights over the executions (Sec.
+ * 3.6.2); sequential Monte Carlo -- the particle-based method the paper names
+ * as future work (Sec. 6) -- suspends every particle at each `factor`,
+ * computes a log-sum-exp normaliser and the effective sample size (ESS), and
+ * resamples systematically before resuming.  A suspended particle is a resume
+ * point (the index of the next factor) plus fixed-size state in device memory,
+ * in place of the paper's delimited continuations (Sec. 1.2, 4.3); every model
+ * has a static maximum state size (Sec. 4.2.4).
+ *
+ * Conventions for every entry point:
+ *   - Pointers named d_* are DEVICE pointers; everything else is host memory.
+ *     The caller owns every buffer (inputs, outputs and the workspace); the
+ *     library never allocates, frees or retains caller memory.
+ *   - Work is enqueued on `stream` (a hipStream_t; NULL is the null stream)
+ *     and is asynchronous unless a result struct asks for host scalars.
+ *   - Return value: PPL_OK (0) or a negative PPL_E_* code.  Host-detectable
+ *     errors (arguments, model id, workspace size, no gfx950 device) are
+ *     reported before anything is launched.  Nothing throws across the ABI.
+ *     ppl_last_error() gives a text for the last failing call on the thread.
+ *   - Layouts are structure-of-arrays: a per-particle field f of particle i
+ *     lives at [f * n_particles + i].
+ *   - Random numbers: Philox4x32-10 (Salmon et al., SC'11) keyed by `seed`;
+ *     counter = (particle or slot index, block index, step, instance << 8 | tag)
+ *     with tags 0 = prior, 1 = proposal, 2 = resampling.  Results depend only
+ *     on (seed, inputs), never on the launch configuration.
+ */
+#ifndef PPL_H
+#define PPL_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* ------------------------------------------------------------- status -- */
+enum {
+    PPL_OK = 0,
+    PPL_E_ARG = -1,          /* invalid argument (null pointer, bad size, bad hyper-parameter) */
+    PPL_E_MODEL = -2,        /* unknown model id, or model not supported by this entry point   */
+    PPL_E_DEVICE = -3,       /* no HIP device, or the current device is not gfx950            */
+    PPL_E_HIP = -4,          /* a HIP runtime call failed (text in ppl_last_error)            */
+    PPL_E_WORKSPACE = -5,    /* workspace missing or smaller than ppl_workspace_size()        */
+    PPL_E_NONFINITE = -6,    /* a log-weight was NaN (device-detected)                        */
+    PPL_E_ZERO_WEIGHT = -7,  /* every weight was zero: log Z-hat = -inf (device-detected)      */
+    PPL_E_UNSUPPORTED = -8   /* valid request outside what this build implements              */
+};
+
+/* Short description of a status code (static storage). */
+const char *ppl_status_string(int status);
+/* Detail text of the last failing call on the calling thread ("" if none). */
+const char *ppl_last_error(void);
+/* Library ABI version (major * 100 + minor). */
+int ppl_version(void);
+
+/* ------------------------------------------------------------- models -- */
+enum {
+    /* Polynomial fit, the paper's running example (Sec. 1.1, figure "ppl-example2"):
+     * n ~ UniformDiscrete{n_lo..n_hi}; c_j ~ Normal(0, sd) for j < n;
+     * factor(-sum_d (y_d - sum_j c_j x_d^j)^2 / 2).  FP64 throughout.
+     * data: x[D], y[D] float64; hyper = {sd, n_lo, n_hi} (default {10, 2, 5}, n_hi <= 5).
+     * latents [6][N] float64: n, c_0..c_4 (c_j for j >= n are drawn but unused). */
+    PPL_MODEL_POLY = 1,
+    /* Bayesian linear regression: w_k ~ Normal(0, prior_sd), k < d;
+     * observe(Normal(x_d . w, noise_sd), y_d) for every row (Sec. 3.4: observe
+     * is factor of the log-density).  Likelihood in FP32, normaliser in FP64.
+     * data: x = X row-major [D][d] float32, y[D] float32, dim = d in {4, 8, 12, 16};
+     * hyper = {prior_sd, noise_sd} (default {1, 0.5}).  latents [d][N] float32. */
+    PPL_MODEL_BLR = 2,
+    /* Linear-Gaussian state space: x_0 = m0 + p0_sd z, x_t = a x_{t-1} + q_sd eps_t;
+     * observe(Normal(x_t, r_sd), y_t), one factor per step.  FP32 state.
+     * data: y[T] float32, x = NULL; hyper = {a, q_sd, r_sd, m0, p0_sd}
+     * (default {0.9, 1, 0.5, 0, 0}).  latents [1][N] float32 (final x). */
+    PPL_MODEL_LGSSM = 3,
+    /* Gaussian mixture with K known components (1 <= K <= 8):
+     * pi ~ Dirichlet(1_K), mu_k ~ Normal(0, mu_sd); one factor per datum,
+     * log sum_k pi_k Normal(y_d; mu_k, comp_sd).  FP32 state.
+     * data: y[D] float32, dim = K; hyper = {mu_sd, comp_sd} (default {5, 1}).
+     * latents [2K][N] float32: log pi_0..log pi_{K-1}, mu_0..mu_{K-1}. */
+    PPL_MODEL_GMM = 4
+};
+
+enum { PPL_F32 = 1, PPL_F64 = 2 };
+
+/* Observed data of one model instance.  x / y are DEVICE pointers (read-only,
+ * caller-owned); hyper is a HOST array (NULL or n_hyper == 0: model defaults). */
+typedef struct ppl_data {
+    const void *x;
+    const void *y;
+    int64_t n_data;          /* D (rows / points) or T (steps) */
+    int32_t dim;             /* BLR: d; GMM: K; otherwise 0 */
+    int32_t dtype;           /* PPL_F64 for POLY, PPL_F32 otherwise */
+    const double *hyper;
+    int32_t n_hyper;
+} ppl_data;
+
+/* Outputs.  Every pointer may be NULL (not produced).
+ * d_scalars (DEVICE, 8 doubles, written asynchronously):
+ *   [0] log Z-hat   [1] ESS (FP64)   [2] number of resamplings   [3] status (0 or PPL_E_*)
+ *   [4] max log-weight   [5] s1 = sum exp(lw - max)   [6] s2 = sum exp(2(lw - max))   [7] N
+ * Host scalars log_evidence / ess / n_resample / status are filled only when
+ * sync_host != 0 (the call then blocks on the stream and also returns
+ * PPL_E_NONFINITE / PPL_E_ZERO_WEIGHT when the device flagged them). */
+typedef struct ppl_result {
+    double log_evidence;
+    double ess;
+    int64_t n_resample;
+    int32_t status;
+    int32_t sync_host;
+    double *d_scalars;        /* [8] */
+    void *d_latents;          /* SoA [n_latent][N], model dtype (see the model list) */
+    void *d_log_weights;      /* [N] final unnormalised log-weights: float64 for importance
+                               * sampling (the FP64 sum the normaliser uses), float32 for SMC */
+    double *d_summaries;      /* model posterior summaries (see ppl_importance) */
+    /* SMC traces (ppl_smc only): */
+    double *d_ess_trace;      /* [T]: ESS after factor t, before resampling */
+    uint8_t *d_resampled;     /* [T]: 1 if resampled after factor t */
+    int32_t *d_ancestors;     /* [max_events][N]: ancestor vector of each resampling event */
+    int64_t max_events;       /* rows available in d_ancestors */
+} ppl_result;
+
+/* Proposal for importance sampling (NULL or kind PPL_Q_PRIOR: the prior,
+ * i.e. likelihood weighting).
+ * PPL_Q_GAUSS_FULL (BLR): d_params = float32 [d] mean followed by [d][d]
+ *   row-major lower-triangular Cholesky factor L (positive diagonal);
+ *   w = mean + L z with z ~ N(0, I) from the proposal stream, and each
+ *   log-weight gains log p(w) - log q(w). */
+enum { PPL_Q_PRIOR = 0, PPL_Q_GAUSS_FULL = 1 };
+typedef struct ppl_proposal {
+    int32_t kind;
+    int32_t dim;
+    const void *d_params;
+} ppl_proposal;
+
+enum { PPL_ALGO_IS = 0, PPL_ALGO_SMC = 1, PPL_ALGO_LSE = 2, PPL_ALGO_RESAMPLE = 3 };
+
+/* Bytes of device workspace an entry point needs for (model, data, N).
+ * The workspace is a caller-owned device buffer, at least 256-byte aligned,
+ * whose contents need not be initialised and may be reused between calls on
+ * one stream. */
+int ppl_workspace_size(int model, const ppl_data *data, int64_t n_particles, int algo,
+                       size_t *bytes);
+
+/* Importance sampling (paper Sec. 3.6.2): run the model n_particles times,
+ * each execution's sample/factor calls give it a log-weight; the FP64
+ * log-sum-exp normaliser gives log Z-hat = LSE(lw) - log N and
+ * ESS = (sum w)^2 / sum w^2.
+ * model: PPL_MODEL_POLY or PPL_MODEL_BLR.  n_particles in [1, 2^31).
+ * d_summaries (FP64):
+ *   POLY: [0..3] P(n = 2..5 | y); [4 + 5(n-2) + j] E[c_j | n, y] (0 where that
+ *         degree has no mass); [24 + j] E[c_j 1{j < n} | y]        -> 29 values
+ *   BLR:  [0..d-1] E[w | y]                                          -> d values */
+int ppl_importance(int model, const ppl_data *data, int64_t n_particles, uint64_t seed,
+                   const ppl_proposal *q, void *d_ws, size_t ws_bytes, void *stream,
+                   ppl_result *out);
+
+/* FP64 normaliser of a device log-weight vector d_lw[n] (dtype PPL_F32 or
+ * PPL_F64): d_out[5] = {max, s1, s2, LSE = max + log s1, ESS = s1^2 / s2}.
+ * -inf entries carry zero weight; all -inf gives LSE = -inf and ESS = 0;
+ * a NaN entry makes every output NaN. */
+int ppl_lse_ess(const void *d_lw, int dtype, int64_t n, double *d_out, void *d_ws,
+                size_t ws_bytes, void *stream);
+
+/* Systematic resampling with integer-quantised weights (association-free, so
+ * the result does not depend on the reduction order):
+ *   q_i = floor(exp(lw_i - max) * 2^k), k = 62 - ceil(log2 n);  Q = inclusive
+ *   prefix sum, S = Q_{n-1};  R = 64-bit word from Philox block
+ *   (0, 0, step, inst << 8 | 2);  U = floor(R S / 2^64);
+ *   d_anc[j] = min{a : n Q_a > j S + U}, j < n.
+ * NaN entries carry zero weight; if every weight is zero, every d_anc[j] = -1. */
+int ppl_resample(const void *d_lw, int dtype, int64_t n, uint64_t seed, uint32_t step,
+                 uint32_t inst, int32_t *d_anc, void *d_ws, size_t ws_bytes, void *stream);
+
+/* Raw stream: d_out[4 i + r] = word r of Philox4x32-10 block
+ * (i, c1, c2, c3) under key seed, for i < n. */
+int ppl_philox(uint64_t seed, uint32_t c1, uint32_t c2, uint32_t c3, int64_t n,
+               uint32_t *d_out, void *stream);
+
+/* Sequential Monte Carlo over the model's factors (paper Sec. 6 future work;
+ * sample/factor semantics of Sec. 3.4).  Bootstrap proposal; after factor t
+ * (t < T - 1) the particles are resampled with ppl_resample's rule when
+ * ESS < ess_frac * N, and the epoch's normaliser LSE(lw) - log N is added to
+ * log Z-hat in FP64; the final epoch's normaliser is added after the last
+ * factor.  model: PPL_MODEL_LGSSM or PPL_MODEL_GMM.  ess_frac in [0, 1]. */
+int ppl_smc(int model, const ppl_data *data, int64_t n_particles, uint64_t seed,
+            double ess_frac, void *d_ws, size_t ws_bytes, void *stream, ppl_result *out);
+
+/* Kernel timing (a measurement aid).  ppl_timing_enable(1) clears the
+ * accumulators and makes the launchers bracket their dominant kernels
+ * (blr_is_kernel, poly_is_kernel, smc kernels) with HIP events recorded on
+ * the launch stream; ppl_timing_enable(0) stops recording.
+ * ppl_timing_query waits for the recorded events of `kernel` and returns the
+ * summed elapsed milliseconds and the number of timed launches. */
+int ppl_timing_enable(int on);
+int ppl_timing_query(const char *kernel, double *total_ms, int64_t *launches);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* PPL_H */

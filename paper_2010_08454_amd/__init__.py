@@ -1,0 +1,200 @@
+"""Python binding of libppl (the MI355X particle-inference library).
+
+Argument marshalling only: every step of inference runs in the library's HIP
+kernels.  PyTorch provides device memory (tensors) and streams.  The functions
+keep the C names (``ppl_importance``, ``ppl_smc``, ...); outputs and the
+workspace may be passed in pre-allocated (as a benchmark does) or are
+allocated here with ``torch.empty`` when omitted.
+
+The library must be built first (``__graft_entry__.build()`` or
+``python -m paper_2010_08454_amd.build``); importing this module without it
+raises, there is no fallback path.
+"""
+import ctypes
+import os
+
+import torch  # loads the HIP runtime torch ships with before libppl binds to it
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libppl.so")
+
+PPL_OK, PPL_E_ARG, PPL_E_MODEL, PPL_E_DEVICE, PPL_E_HIP = 0, -1, -2, -3, -4
+PPL_E_WORKSPACE, PPL_E_NONFINITE, PPL_E_ZERO_WEIGHT, PPL_E_UNSUPPORTED = -5, -6, -7, -8
+PPL_MODEL_POLY, PPL_MODEL_BLR, PPL_MODEL_LGSSM, PPL_MODEL_GMM = 1, 2, 3, 4
+PPL_F32, PPL_F64 = 1, 2
+PPL_Q_PRIOR, PPL_Q_GAUSS_FULL = 0, 1
+PPL_ALGO_IS, PPL_ALGO_SMC, PPL_ALGO_LSE, PPL_ALGO_RESAMPLE = 0, 1, 2, 3
+
+# Exported C symbols (kept in step with include/ppl.h).
+EXPORTS = ("ppl_status_string", "ppl_last_error", "ppl_version", "ppl_workspace_size",
+           "ppl_importance", "ppl_lse_ess", "ppl_resample", "ppl_philox", "ppl_smc",
+           "ppl_timing_enable", "ppl_timing_query")
+
+P = ctypes.c_void_p
+
+
+class PplData(ctypes.Structure):
+    _fields_ = [("x", P), ("y", P), ("n_data", ctypes.c_int64), ("dim", ctypes.c_int32),
+                ("dtype", ctypes.c_int32), ("hyper", ctypes.POINTER(ctypes.c_double)),
+                ("n_hyper", ctypes.c_int32)]
+
+
+class PplResult(ctypes.Structure):
+    _fields_ = [("log_evidence", ctypes.c_double), ("ess", ctypes.c_double),
+                ("n_resample", ctypes.c_int64), ("status", ctypes.c_int32), ("sync_host", ctypes.c_int32),
+                ("d_scalars", P), ("d_latents", P), ("d_log_weights", P), ("d_summaries", P),
+                ("d_ess_trace", P), ("d_resampled", P), ("d_ancestors", P), ("max_events", ctypes.c_int64)]
+
+
+class PplProposal(ctypes.Structure):
+    _fields_ = [("kind", ctypes.c_int32), ("dim", ctypes.c_int32), ("d_params", P)]
+
+
+class PplError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__(f"libppl error {code}: {msg}")
+        self.code = code
+
+
+def _load():
+    if not os.path.exists(LIB_PATH):
+        raise ImportError(f"{LIB_PATH} is not built; run __graft_entry__.build() first")
+    L = ctypes.CDLL(LIB_PATH)
+    i32, i64, u32, u64, f64 = ctypes.c_int32, ctypes.c_int64, ctypes.c_uint32, ctypes.c_uint64, ctypes.c_double
+    L.ppl_status_string.argtypes = [ctypes.c_int]
+    L.ppl_status_string.restype = ctypes.c_char_p
+    L.ppl_last_error.restype = ctypes.c_char_p
+    L.ppl_version.restype = ctypes.c_int
+    L.ppl_workspace_size.argtypes = [ctypes.c_int, ctypes.POINTER(PplData), i64, ctypes.c_int, ctypes.POINTER(ctypes.c_size_t)]
+    L.ppl_importance.argtypes = [ctypes.c_int, ctypes.POINTER(PplData), i64, u64, ctypes.POINTER(PplProposal),
+                                 P, ctypes.c_size_t, P, ctypes.POINTER(PplResult)]
+    L.ppl_lse_ess.argtypes = [P, ctypes.c_int, i64, P, P, ctypes.c_size_t, P]
+    L.ppl_resample.argtypes = [P, ctypes.c_int, i64, u64, u32, u32, P, P, ctypes.c_size_t, P]
+    L.ppl_philox.argtypes = [u64, u32, u32, u32, i64, P, P]
+    L.ppl_smc.argtypes = [ctypes.c_int, ctypes.POINTER(PplData), i64, u64, f64, P, ctypes.c_size_t, P,
+                          ctypes.POINTER(PplResult)]
+    L.ppl_timing_enable.argtypes = [ctypes.c_int]
+    L.ppl_timing_query.argtypes = [ctypes.c_char_p, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_int64)]
+    for name in EXPORTS:
+        if name not in ("ppl_status_string", "ppl_last_error"):
+            getattr(L, name).restype = ctypes.c_int
+    return L
+
+
+lib = _load()
+
+
+def _check(rc):
+    if rc != PPL_OK:
+        raise PplError(rc, lib.ppl_last_error().decode())
+    return rc
+
+
+def _ptr(t):
+    return None if t is None else ctypes.c_void_p(t.data_ptr())
+
+
+def _stream(stream):
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    return ctypes.c_void_p(stream.cuda_stream)
+
+
+def make_data(x, y, n_data=None, dim=0, hyper=None, dtype=None):
+    """Build a ppl_data block from device tensors (keeps the hyper array alive)."""
+    if dtype is None:
+        dtype = PPL_F64 if y.dtype == torch.float64 else PPL_F32
+    h = None
+    if hyper is not None:
+        h = (ctypes.c_double * len(hyper))(*[float(v) for v in hyper])
+    d = PplData(x=None if x is None else x.data_ptr(), y=None if y is None else y.data_ptr(),
+                n_data=int(y.numel() if n_data is None else n_data), dim=int(dim), dtype=dtype,
+                hyper=ctypes.cast(h, ctypes.POINTER(ctypes.c_double)) if h is not None else None,
+                n_hyper=0 if hyper is None else len(hyper))
+    d._keep = h
+    return d
+
+
+def ppl_workspace_size(model, data, n, algo):
+    b = ctypes.c_size_t()
+    _check(lib.ppl_workspace_size(model, ctypes.byref(data) if data is not None else None, int(n), algo, ctypes.byref(b)))
+    return b.value
+
+
+def workspace(nbytes, device=None):
+    """Caller-owned device workspace (256-byte aligned: the allocator aligns to 512)."""
+    return torch.empty(max(int(nbytes), 1), dtype=torch.uint8, device=device or "cuda")
+
+
+def ppl_importance(model, data, n, seed, q=None, ws=None, stream=None, log_weights=None, latents=None,
+                   summaries=None, scalars=None, sync=False):
+    """Importance sampling; returns the ppl_result struct (host scalars when sync)."""
+    if ws is None:
+        ws = workspace(ppl_workspace_size(model, data, n, PPL_ALGO_IS))
+    res = PplResult(sync_host=1 if sync else 0, d_scalars=_ptr(scalars), d_latents=_ptr(latents),
+                    d_log_weights=_ptr(log_weights), d_summaries=_ptr(summaries))
+    prop = None
+    if q is not None:
+        prop = PplProposal(kind=PPL_Q_GAUSS_FULL, dim=data.dim, d_params=q.data_ptr())
+    _check(lib.ppl_importance(model, ctypes.byref(data), int(n), int(seed) & (2 ** 64 - 1),
+                              ctypes.byref(prop) if prop is not None else None, _ptr(ws), ws.numel(),
+                              _stream(stream), ctypes.byref(res)))
+    return res
+
+
+def ppl_lse_ess(lw, out=None, ws=None, stream=None):
+    """FP64 {max, s1, s2, LSE, ESS} of a device log-weight vector (returns the device tensor)."""
+    n = lw.numel()
+    if out is None:
+        out = torch.empty(5, dtype=torch.float64, device=lw.device)
+    if ws is None:
+        ws = workspace(ppl_workspace_size(0, None, n, PPL_ALGO_LSE), lw.device)
+    dt = PPL_F64 if lw.dtype == torch.float64 else PPL_F32
+    _check(lib.ppl_lse_ess(_ptr(lw), dt, n, _ptr(out), _ptr(ws), ws.numel(), _stream(stream)))
+    return out
+
+
+def ppl_resample(lw, seed, step=0, inst=0, anc=None, ws=None, stream=None):
+    """Integer-rule systematic resampling; returns the int32 ancestor tensor."""
+    n = lw.numel()
+    if anc is None:
+        anc = torch.empty(n, dtype=torch.int32, device=lw.device)
+    if ws is None:
+        ws = workspace(ppl_workspace_size(0, None, n, PPL_ALGO_RESAMPLE), lw.device)
+    dt = PPL_F64 if lw.dtype == torch.float64 else PPL_F32
+    _check(lib.ppl_resample(_ptr(lw), dt, n, int(seed) & (2 ** 64 - 1), step, inst, _ptr(anc), _ptr(ws),
+                            ws.numel(), _stream(stream)))
+    return anc
+
+
+def ppl_philox(seed, c1, c2, c3, n, out=None, stream=None):
+    """Philox4x32-10 words of blocks (i, c1, c2, c3), i < n, as an int32 tensor [n, 4]."""
+    if out is None:
+        out = torch.empty((n, 4), dtype=torch.int32, device="cuda")
+    _check(lib.ppl_philox(int(seed) & (2 ** 64 - 1), c1, c2, c3, n, _ptr(out), _stream(stream)))
+    return out
+
+
+def ppl_smc(model, data, n, seed, ess_frac=0.5, ws=None, stream=None, log_weights=None, latents=None,
+            scalars=None, ess_trace=None, resampled=None, ancestors=None, sync=False):
+    """Sequential Monte Carlo; returns the ppl_result struct (host scalars when sync)."""
+    if ws is None:
+        ws = workspace(ppl_workspace_size(model, data, n, PPL_ALGO_SMC))
+    res = PplResult(sync_host=1 if sync else 0, d_scalars=_ptr(scalars), d_latents=_ptr(latents),
+                    d_log_weights=_ptr(log_weights), d_ess_trace=_ptr(ess_trace), d_resampled=_ptr(resampled),
+                    d_ancestors=_ptr(ancestors), max_events=0 if ancestors is None else ancestors.shape[0])
+    _check(lib.ppl_smc(model, ctypes.byref(data), int(n), int(seed) & (2 ** 64 - 1), float(ess_frac), _ptr(ws),
+                       ws.numel(), _stream(stream), ctypes.byref(res)))
+    return res
+
+
+def ppl_timing_enable(on):
+    """Start (clearing the accumulators) or stop event timing of the library's dominant kernels."""
+    _check(lib.ppl_timing_enable(1 if on else 0))
+
+
+def ppl_timing_query(kernel):
+    """(total milliseconds, launches) recorded for ``kernel`` since timing was enabled."""
+    ms, n = ctypes.c_double(), ctypes.c_int64()
+    _check(lib.ppl_timing_query(kernel.encode(), ctypes.byref(ms), ctypes.byref(n)))
+    return ms.value, n.value

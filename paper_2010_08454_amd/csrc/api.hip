@@ -1,0 +1,287 @@
+// api.hip -- the extern "C" boundary of libppl: argument validation, workspace
+// planning, device check and dispatch to the kernel launchers.  Every error a
+// host can detect is returned before anything is enqueued.
+#include <math.h>
+#include <stdarg.h>
+#include <stdio.h>
+#include <string.h>
+
+#include <atomic>
+
+#include "host.h"
+#include "kernels.h"
+#include "smc.h"
+
+namespace ppl {
+
+static thread_local char g_last_error[512];
+
+int fail(int code, const char *fmt, ...) {
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(g_last_error, sizeof(g_last_error), fmt, ap);
+    va_end(ap);
+    return code;
+}
+
+void clear_error() { g_last_error[0] = 0; }
+
+int check_device() {
+    static std::atomic<int> verdict[64];   // 0 unknown, 1 ok, 2 not gfx950
+    int dev = -1;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess || dev < 0) {
+        (void)hipGetLastError();
+        return fail(PPL_E_DEVICE, "no HIP device available (%s)", hipGetErrorString(e));
+    }
+    if (dev < 64) {
+        const int v = verdict[dev].load(std::memory_order_relaxed);
+        if (v == 1) return PPL_OK;
+        if (v == 2) return fail(PPL_E_DEVICE, "device %d is not a gfx950 GPU", dev);
+    }
+    hipDeviceProp_t prop;
+    e = hipGetDeviceProperties(&prop, dev);
+    if (e != hipSuccess) return fail(PPL_E_DEVICE, "hipGetDeviceProperties: %s", hipGetErrorString(e));
+    const bool ok = strncmp(prop.gcnArchName, "gfx950", 6) == 0;
+    if (dev < 64) verdict[dev].store(ok ? 1 : 2, std::memory_order_relaxed);
+    if (!ok) return fail(PPL_E_DEVICE, "device %d is %s, this library is built for gfx950", dev, prop.gcnArchName);
+    return PPL_OK;
+}
+
+int check_grid(const char *kernel, int64_t blocks, int threads) {
+    if (blocks < 1 || blocks > 0x7fffffffLL || threads < 1 || threads > 1024)
+        return fail(PPL_E_ARG, "%s: launch shape %lld x %d out of range", kernel, (long long)blocks, threads);
+    return PPL_OK;
+}
+
+static bool finite_pos(double v) { return isfinite(v) && v > 0.0; }
+
+static bool is_int(double v) { return isfinite(v) && v == floor(v); }
+
+static int check_ws(void *ws, size_t ws_bytes, size_t need) {
+    if (need == 0) return PPL_OK;
+    if (!ws) return fail(PPL_E_WORKSPACE, "workspace is NULL (%zu bytes needed)", need);
+    if (((uintptr_t)ws & 255) != 0) return fail(PPL_E_WORKSPACE, "workspace must be 256-byte aligned");
+    if (ws_bytes < need) return fail(PPL_E_WORKSPACE, "workspace has %zu bytes, %zu needed", ws_bytes, need);
+    return PPL_OK;
+}
+
+// Validates a model's data block and fills the hyper-parameters with defaults.
+static int check_model_data(int model, const ppl_data *d, double hyper[8]) {
+    if (!d) return fail(PPL_E_ARG, "data is NULL");
+    if (d->n_data < 0 || d->n_data > 0x7fffffffLL) return fail(PPL_E_ARG, "n_data %lld out of range", (long long)d->n_data);
+    if (d->n_hyper < 0 || (d->n_hyper > 0 && !d->hyper)) return fail(PPL_E_ARG, "hyper is NULL with n_hyper > 0");
+    for (int i = 0; i < 8; ++i) hyper[i] = 0.0;
+    switch (model) {
+        case PPL_MODEL_POLY:
+            if (d->dtype != PPL_F64) return fail(PPL_E_ARG, "POLY data must be PPL_F64");
+            if (d->n_data > 0 && (!d->x || !d->y)) return fail(PPL_E_ARG, "POLY needs x and y");
+            hyper[0] = hyper_or(d, 0, 10.0);
+            hyper[1] = hyper_or(d, 1, 2.0);
+            hyper[2] = hyper_or(d, 2, 5.0);
+            if (!finite_pos(hyper[0])) return fail(PPL_E_ARG, "POLY prior sd must be positive");
+            if (!is_int(hyper[1]) || !is_int(hyper[2]) || hyper[1] < 1 || hyper[2] > 5 || hyper[1] > hyper[2])
+                return fail(PPL_E_ARG, "POLY degree range must satisfy 1 <= n_lo <= n_hi <= 5");
+            return PPL_OK;
+        case PPL_MODEL_BLR:
+            if (d->dtype != PPL_F32) return fail(PPL_E_ARG, "BLR data must be PPL_F32");
+            if (d->dim != 4 && d->dim != 8 && d->dim != 12 && d->dim != 16)
+                return fail(PPL_E_ARG, "BLR dim must be 4, 8, 12 or 16 (got %d)", d->dim);
+            if (d->n_data > 0 && (!d->x || !d->y)) return fail(PPL_E_ARG, "BLR needs x and y");
+            hyper[0] = hyper_or(d, 0, 1.0);
+            hyper[1] = hyper_or(d, 1, 0.5);
+            if (!finite_pos(hyper[0]) || !finite_pos(hyper[1])) return fail(PPL_E_ARG, "BLR sds must be positive");
+            return PPL_OK;
+        case PPL_MODEL_LGSSM:
+            if (d->dtype != PPL_F32) return fail(PPL_E_ARG, "LGSSM data must be PPL_F32");
+            if (d->n_data > 0 && !d->y) return fail(PPL_E_ARG, "LGSSM needs y");
+            hyper[0] = hyper_or(d, 0, 0.9);
+            hyper[1] = hyper_or(d, 1, 1.0);
+            hyper[2] = hyper_or(d, 2, 0.5);
+            hyper[3] = hyper_or(d, 3, 0.0);
+            hyper[4] = hyper_or(d, 4, 0.0);
+            if (!isfinite(hyper[0]) || !finite_pos(hyper[1]) || !finite_pos(hyper[2]) || !isfinite(hyper[3]) ||
+                !isfinite(hyper[4]) || hyper[4] < 0)
+                return fail(PPL_E_ARG, "LGSSM hyper-parameters must be finite with positive sds");
+            return PPL_OK;
+        case PPL_MODEL_GMM:
+            if (d->dtype != PPL_F32) return fail(PPL_E_ARG, "GMM data must be PPL_F32");
+            if (d->dim < 1 || d->dim > 8) return fail(PPL_E_ARG, "GMM K must be in 1..8 (got %d)", d->dim);
+            if (d->n_data > 0 && !d->y) return fail(PPL_E_ARG, "GMM needs y");
+            hyper[0] = hyper_or(d, 0, 5.0);
+            hyper[1] = hyper_or(d, 1, 1.0);
+            if (!finite_pos(hyper[0]) || !finite_pos(hyper[1])) return fail(PPL_E_ARG, "GMM sds must be positive");
+            return PPL_OK;
+    }
+    return fail(PPL_E_MODEL, "unknown model id %d", model);
+}
+
+static int check_n(int64_t n) {
+    if (n < 1 || n > 0x7fffffffLL) return fail(PPL_E_ARG, "particle count %lld out of range [1, 2^31)", (long long)n);
+    return PPL_OK;
+}
+
+static size_t is_ws_bytes(int model, int dim, int64_t n) { return 256 + align_up(is_partial_bytes(model, dim, n), 256); }
+
+// Blocks on the stream and copies the device scalars into the host fields.
+static int sync_scalars(ppl_result *out, const double *d_scal, hipStream_t st) {
+    double h[8];
+    PPL_HIP(hipMemcpyAsync(h, d_scal, sizeof(h), hipMemcpyDeviceToHost, st));
+    PPL_HIP(hipStreamSynchronize(st));
+    out->log_evidence = h[0];
+    out->ess = h[1];
+    out->n_resample = (int64_t)h[2];
+    out->status = (int32_t)h[3];
+    if (out->status) return fail(out->status, "device reported status %d (%s)", out->status, ppl_status_string(out->status));
+    return PPL_OK;
+}
+
+}  // namespace ppl
+
+using namespace ppl;
+
+extern "C" {
+
+const char *ppl_status_string(int status) {
+    switch (status) {
+        case PPL_OK: return "ok";
+        case PPL_E_ARG: return "invalid argument";
+        case PPL_E_MODEL: return "unknown or unsupported model";
+        case PPL_E_DEVICE: return "no gfx950 device";
+        case PPL_E_HIP: return "HIP runtime error";
+        case PPL_E_WORKSPACE: return "workspace missing or too small";
+        case PPL_E_NONFINITE: return "non-finite log-weight";
+        case PPL_E_ZERO_WEIGHT: return "every weight is zero";
+        case PPL_E_UNSUPPORTED: return "unsupported request";
+    }
+    return "unknown status";
+}
+
+const char *ppl_last_error(void) { return g_last_error; }
+
+int ppl_version(void) { return 100; }
+
+int ppl_workspace_size(int model, const ppl_data *data, int64_t n, int algo, size_t *bytes) {
+    clear_error();
+    if (!bytes) return fail(PPL_E_ARG, "bytes is NULL");
+    if (int rc = check_n(n)) return rc;
+    switch (algo) {
+        case PPL_ALGO_LSE: *bytes = align_up(lse_ws_bytes(n), 256); return PPL_OK;
+        case PPL_ALGO_RESAMPLE: *bytes = align_up(resample_ws_bytes(n), 256); return PPL_OK;
+        case PPL_ALGO_IS: {
+            double h[8];
+            if (model != PPL_MODEL_POLY && model != PPL_MODEL_BLR)
+                return fail(PPL_E_MODEL, "importance sampling supports POLY and BLR (got %d)", model);
+            if (int rc = check_model_data(model, data, h)) return rc;
+            *bytes = is_ws_bytes(model, data->dim, n);
+            return PPL_OK;
+        }
+        case PPL_ALGO_SMC: {
+            double h[8];
+            if (model != PPL_MODEL_LGSSM && model != PPL_MODEL_GMM)
+                return fail(PPL_E_MODEL, "SMC supports LGSSM and GMM (got %d)", model);
+            if (int rc = check_model_data(model, data, h)) return rc;
+            *bytes = smc_ws_bytes(model, data->dim, n);
+            return PPL_OK;
+        }
+    }
+    return fail(PPL_E_ARG, "unknown algo %d", algo);
+}
+
+int ppl_importance(int model, const ppl_data *data, int64_t n, uint64_t seed, const ppl_proposal *q, void *ws,
+                   size_t ws_bytes, void *stream, ppl_result *out) {
+    clear_error();
+    if (!out) return fail(PPL_E_ARG, "out is NULL");
+    if (model != PPL_MODEL_POLY && model != PPL_MODEL_BLR)
+        return fail(model >= 1 && model <= 4 ? PPL_E_MODEL : PPL_E_MODEL,
+                    "importance sampling supports POLY and BLR (got %d)", model);
+    if (int rc = check_n(n)) return rc;
+    IsArgs a{};
+    if (int rc = check_model_data(model, data, a.hyper)) return rc;
+    if (q && q->kind != PPL_Q_PRIOR) {
+        if (q->kind != PPL_Q_GAUSS_FULL || model != PPL_MODEL_BLR)
+            return fail(PPL_E_UNSUPPORTED, "proposal kind %d is not available for model %d", q->kind, model);
+        if (!q->d_params || q->dim != data->dim) return fail(PPL_E_ARG, "Gaussian proposal needs params of dim %d", data->dim);
+        a.q_params = q->d_params;
+    }
+    if (int rc = check_ws(ws, ws_bytes, is_ws_bytes(model, data->dim, n))) return rc;
+    if (int rc = check_device()) return rc;
+    a.model = model;
+    a.x = data->x;
+    a.y = data->y;
+    a.D = data->n_data;
+    a.dim = data->dim;
+    a.N = n;
+    a.seed = seed;
+    a.lw_out = out->d_log_weights;
+    a.lat_out = out->d_latents;
+    a.summaries = out->d_summaries;
+    a.scalars = out->d_scalars ? out->d_scalars : (double *)ws;
+    a.part = (double *)((char *)ws + 256);
+    hipStream_t st = (hipStream_t)stream;
+    if (int rc = run_importance(a, st)) return rc;
+    if (out->sync_host) return sync_scalars(out, a.scalars, st);
+    return PPL_OK;
+}
+
+int ppl_lse_ess(const void *lw, int dtype, int64_t n, double *out, void *ws, size_t ws_bytes, void *stream) {
+    clear_error();
+    if (!lw || !out) return fail(PPL_E_ARG, "d_lw and d_out must be non-NULL");
+    if (dtype != PPL_F32 && dtype != PPL_F64) return fail(PPL_E_ARG, "dtype must be PPL_F32 or PPL_F64");
+    if (int rc = check_n(n)) return rc;
+    if (int rc = check_ws(ws, ws_bytes, lse_ws_bytes(n))) return rc;
+    if (int rc = check_device()) return rc;
+    return run_lse(lw, dtype == PPL_F64, n, out, ws, (hipStream_t)stream);
+}
+
+int ppl_resample(const void *lw, int dtype, int64_t n, uint64_t seed, uint32_t step, uint32_t inst, int32_t *anc,
+                 void *ws, size_t ws_bytes, void *stream) {
+    clear_error();
+    if (!lw || !anc) return fail(PPL_E_ARG, "d_lw and d_anc must be non-NULL");
+    if (dtype != PPL_F32 && dtype != PPL_F64) return fail(PPL_E_ARG, "dtype must be PPL_F32 or PPL_F64");
+    if (int rc = check_n(n)) return rc;
+    if (inst >= (1u << 24)) return fail(PPL_E_ARG, "instance id must be < 2^24");
+    if (int rc = check_ws(ws, ws_bytes, resample_ws_bytes(n))) return rc;
+    if (int rc = check_device()) return rc;
+    return run_resample(lw, dtype == PPL_F64, n, seed, step, inst, anc, ws, (hipStream_t)stream);
+}
+
+int ppl_philox(uint64_t seed, uint32_t c1, uint32_t c2, uint32_t c3, int64_t n, uint32_t *out, void *stream) {
+    clear_error();
+    if (!out) return fail(PPL_E_ARG, "d_out is NULL");
+    if (n < 1 || n > (1LL << 32)) return fail(PPL_E_ARG, "n %lld out of range [1, 2^32]", (long long)n);
+    if (int rc = check_device()) return rc;
+    return run_philox(seed, c1, c2, c3, n, out, (hipStream_t)stream);
+}
+
+int ppl_smc(int model, const ppl_data *data, int64_t n, uint64_t seed, double ess_frac, void *ws, size_t ws_bytes,
+            void *stream, ppl_result *out) {
+    clear_error();
+    if (!out) return fail(PPL_E_ARG, "out is NULL");
+    if (model != PPL_MODEL_LGSSM && model != PPL_MODEL_GMM)
+        return fail(PPL_E_MODEL, "SMC supports LGSSM and GMM (got %d)", model);
+    if (int rc = check_n(n)) return rc;
+    SmcArgs a{};
+    if (int rc = check_model_data(model, data, a.hyper)) return rc;
+    if (!(ess_frac >= 0.0 && ess_frac <= 1.0)) return fail(PPL_E_ARG, "ess_frac must be in [0, 1]");
+    if (out->max_events < 0 || (out->max_events > 0 && !out->d_ancestors))
+        return fail(PPL_E_ARG, "d_ancestors is NULL with max_events > 0");
+    if (int rc = check_ws(ws, ws_bytes, smc_ws_bytes(model, data->dim, n))) return rc;
+    if (int rc = check_device()) return rc;
+    a.model = model;
+    a.y = (const float *)data->y;
+    a.T = data->n_data;
+    a.K = data->dim;
+    a.N = n;
+    a.seed = seed;
+    a.inst = 0;
+    a.ess_frac = ess_frac;
+    a.out = *out;
+    a.ws = ws;
+    hipStream_t st = (hipStream_t)stream;
+    if (int rc = run_smc(a, st)) return rc;
+    if (out->sync_host) return sync_scalars(out, smc_scalars_ptr(a), st);
+    return PPL_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,327 @@
+// importance.hip -- importance-sampling kernels (paper Sec. 3.6.2).
+//
+// Each thread owns P particles.  A particle draws its latents at the model's
+// sample sites, accumulates its factors over the data, and its log-weight is
+// folded into a per-block FP64 partial {max, sum e, sum e^2, sum e f}; a
+// one-wave finalize kernel merges the block partials in a fixed order and
+// writes log Z-hat = LSE - log N, the ESS and the posterior summaries.
+//
+// Data rows are the same for every lane of a wave (all lanes process the same
+// datum for different particles), so they are read with scalar loads into
+// SGPRs and used directly as the scalar operand of v_fma_f32; per-particle
+// state stays in VGPRs for the whole data loop.
+#include "device.h"
+#include "host.h"
+#include "kernels.h"
+#include "timing.h"
+
+namespace ppl {
+
+constexpr int kIsThreads = 256;
+constexpr int kIsWaves = kIsThreads / 64;
+constexpr int kPolyNF = 29;     // summary fields of the polynomial model
+
+// ------------------------------------------------------------------ BLR --
+// Likelihood of one particle set: FP32 residuals r = y_d - x_d . w and squared
+// sums in FP32 within consecutive 32-row blocks; block sums accumulate in FP64.
+template <int P, int DIM, bool PROP>
+__global__ __launch_bounds__(kIsThreads) void blr_is_kernel(
+    const float *__restrict__ X, const float *__restrict__ Y, int D, int64_t N, Key key,
+    float prior_sd, double noise_sd, const float *__restrict__ qp, double *__restrict__ lw_out,
+    float *__restrict__ lat_out, double *__restrict__ part) {
+    const int tid = threadIdx.x;
+    const int64_t base = (int64_t)blockIdx.x * (kIsThreads * P);
+
+    float w[P][DIM];
+    double extra[P];
+#pragma unroll
+    for (int p = 0; p < P; ++p) {
+        const uint32_t i = (uint32_t)(base + p * kIsThreads + tid);
+        float z[DIM];
+#pragma unroll
+        for (int b = 0; b < DIM / 4; ++b) normals4(philox(i, b, 0, PROP ? kTagProposal : kTagPrior, key), z + 4 * b);
+        if constexpr (PROP) {
+            // w = mean + L z; extra = log p(w) - log q(w) (normalising constants cancel).
+            double zz = 0.0, ww = 0.0, logdet = 0.0;
+#pragma unroll
+            for (int r = 0; r < DIM; ++r) {
+                float v = qp[r];
+#pragma unroll
+                for (int k = 0; k <= r; ++k) v = fmaf(qp[DIM + r * DIM + k], z[k], v);
+                w[p][r] = v;
+                zz += (double)z[r] * z[r];
+                ww += (double)v * v;
+                logdet += log((double)qp[DIM + r * DIM + r]);
+            }
+            const double s = prior_sd;
+            extra[p] = (-0.5 * ww / (s * s) - DIM * log(s)) - (-0.5 * zz - logdet);
+        } else {
+#pragma unroll
+            for (int k = 0; k < DIM; ++k) w[p][k] = prior_sd * z[k];
+            extra[p] = 0.0;
+        }
+    }
+
+    double acc[P];
+#pragma unroll
+    for (int p = 0; p < P; ++p) acc[p] = 0.0;
+    int d = 0;
+    for (; d + 32 <= D; d += 32) {
+        float s[P];
+#pragma unroll
+        for (int p = 0; p < P; ++p) s[p] = 0.0f;
+#pragma unroll 8
+        for (int dd = 0; dd < 32; ++dd) {
+            const float *row = X + (size_t)(d + dd) * DIM;
+            const float yv = Y[d + dd];
+#pragma unroll
+            for (int p = 0; p < P; ++p) {
+                float r = yv;
+#pragma unroll
+                for (int k = 0; k < DIM; ++k) r = fmaf(-row[k], w[p][k], r);
+                s[p] = fmaf(r, r, s[p]);
+            }
+        }
+#pragma unroll
+        for (int p = 0; p < P; ++p) acc[p] += (double)s[p];
+    }
+    if (d < D) {
+        float s[P];
+#pragma unroll
+        for (int p = 0; p < P; ++p) s[p] = 0.0f;
+        for (; d < D; ++d) {
+            const float *row = X + (size_t)d * DIM;
+            const float yv = Y[d];
+#pragma unroll
+            for (int p = 0; p < P; ++p) {
+                float r = yv;
+#pragma unroll
+                for (int k = 0; k < DIM; ++k) r = fmaf(-row[k], w[p][k], r);
+                s[p] = fmaf(r, r, s[p]);
+            }
+        }
+#pragma unroll
+        for (int p = 0; p < P; ++p) acc[p] += (double)s[p];
+    }
+
+    const double var = noise_sd * noise_sd;
+    const double cterm = (double)D * (-0.5 * log(2.0 * M_PI * var));
+    double lw[P];
+    Partial<DIM> part_p = partial_empty<DIM>();
+    double mloc = -INFINITY;
+#pragma unroll
+    for (int p = 0; p < P; ++p) {
+        const int64_t i = base + p * kIsThreads + tid;
+        lw[p] = (i < N) ? cterm - acc[p] / (2.0 * var) + extra[p] : -INFINITY;
+        if (i < N && isnan(lw[p])) part_p.nan += 1.0;
+        if (lw[p] > mloc) mloc = lw[p];
+        if (i < N) {
+            if (lw_out) lw_out[i] = lw[p];
+            if (lat_out) {
+#pragma unroll
+                for (int k = 0; k < DIM; ++k) lat_out[(size_t)k * N + i] = w[p][k];
+            }
+        }
+    }
+    part_p.m = mloc;
+    if (mloc > -INFINITY) {
+#pragma unroll
+        for (int p = 0; p < P; ++p) {
+            const double e = exp(lw[p] - mloc);
+            part_p.s1 += e;
+            part_p.s2 += e * e;
+#pragma unroll
+            for (int k = 0; k < DIM; ++k) part_p.f[k] += e * (double)w[p][k];
+        }
+    }
+    partial_block_reduce_store<DIM, kIsWaves>(part_p, part + (size_t)blockIdx.x * (4 + DIM));
+}
+
+// ----------------------------------------------------------------- POLY --
+// FP64 polynomial model.  Horner over the five coefficient slots with slots
+// j >= n set to zero: 0 * x + 0 = 0 exactly, so this equals n-term Horner and
+// no lane branches on the sampled degree.
+template <int P>
+__global__ __launch_bounds__(kIsThreads) void poly_is_kernel(
+    const double *__restrict__ X, const double *__restrict__ Y, int D, int64_t N, Key key, double sd,
+    int n_lo, int n_hi, double *__restrict__ lw_out, double *__restrict__ lat_out, double *__restrict__ part) {
+    const int tid = threadIdx.x;
+    const int64_t base = (int64_t)blockIdx.x * (kIsThreads * P);
+    double c[P][5];
+    int nn[P];
+#pragma unroll
+    for (int p = 0; p < P; ++p) {
+        const uint32_t i = (uint32_t)(base + p * kIsThreads + tid);
+        const uint4 w0 = philox(i, 0, 0, kTagPrior, key);
+        nn[p] = uniform_discrete(w0.x, n_lo, (uint32_t)(n_hi - n_lo + 1));
+        double z[6];
+#pragma unroll
+        for (int b = 1; b <= 3; ++b) {
+            const uint4 w = philox(i, b, 0, kTagPrior, key);
+            box_muller(unit_f64(w.x, w.y), unit_f64(w.z, w.w), z[2 * (b - 1)], z[2 * (b - 1) + 1]);
+        }
+#pragma unroll
+        for (int j = 0; j < 5; ++j) c[p][j] = sd * z[j];
+    }
+    double pc[P][5];
+#pragma unroll
+    for (int p = 0; p < P; ++p)
+#pragma unroll
+        for (int j = 0; j < 5; ++j) pc[p][j] = j < nn[p] ? c[p][j] : 0.0;
+
+    double acc[P];
+#pragma unroll
+    for (int p = 0; p < P; ++p) acc[p] = 0.0;
+    for (int d = 0; d < D; ++d) {
+        const double xv = X[d], yv = Y[d];
+#pragma unroll
+        for (int p = 0; p < P; ++p) {
+            double v = pc[p][4];
+            v = fma(v, xv, pc[p][3]);
+            v = fma(v, xv, pc[p][2]);
+            v = fma(v, xv, pc[p][1]);
+            v = fma(v, xv, pc[p][0]);
+            const double r = yv - v;
+            acc[p] = fma(r, r, acc[p]);
+        }
+    }
+
+    double lw[P];
+    Partial<kPolyNF> pp = partial_empty<kPolyNF>();
+    double mloc = -INFINITY;
+#pragma unroll
+    for (int p = 0; p < P; ++p) {
+        const int64_t i = base + p * kIsThreads + tid;
+        lw[p] = (i < N) ? -0.5 * acc[p] : -INFINITY;
+        if (i < N && isnan(lw[p])) pp.nan += 1.0;
+        if (lw[p] > mloc) mloc = lw[p];
+        if (i < N) {
+            if (lw_out) lw_out[i] = lw[p];
+            if (lat_out) {
+                lat_out[i] = (double)nn[p];
+#pragma unroll
+                for (int j = 0; j < 5; ++j) lat_out[(size_t)(1 + j) * N + i] = c[p][j];
+            }
+        }
+    }
+    pp.m = mloc;
+    if (mloc > -INFINITY) {
+#pragma unroll
+        for (int p = 0; p < P; ++p) {
+            const double e = exp(lw[p] - mloc);
+            pp.s1 += e;
+            pp.s2 += e * e;
+            const int k = nn[p] - 2;  // degree slot (n in 2..5)
+#pragma unroll
+            for (int s = 0; s < 4; ++s) {
+                const double sel = (s == k) ? e : 0.0;
+                pp.f[s] += sel;
+#pragma unroll
+                for (int j = 0; j < 5; ++j) pp.f[4 + 5 * s + j] += sel * pc[p][j];
+            }
+#pragma unroll
+            for (int j = 0; j < 5; ++j) pp.f[24 + j] += e * pc[p][j];
+        }
+    }
+    partial_block_reduce_store<kPolyNF, kIsWaves>(pp, part + (size_t)blockIdx.x * (4 + kPolyNF));
+}
+
+// ------------------------------------------------------------- finalize --
+// One wave merges the block partials (lane-strided, then a butterfly) and
+// writes scalars[8] and the model summaries.
+template <int NF, int MODEL>
+__global__ __launch_bounds__(64) void is_finalize_kernel(const double *__restrict__ part, int nblocks,
+                                                         int64_t N, double *__restrict__ scalars,
+                                                         double *__restrict__ summaries) {
+    const int lane = threadIdx.x;
+    Partial<NF> a = partial_empty<NF>();
+    for (int b = lane; b < nblocks; b += 64) {
+        Partial<NF> q = partial_load<NF>(part + (size_t)b * (4 + NF));
+        partial_merge(a, q);
+    }
+    partial_wave_reduce(a);
+    if (lane != 0) return;
+    int status = 0;
+    if (a.nan > 0) status = PPL_E_NONFINITE;
+    else if (!(a.m > -INFINITY)) status = PPL_E_ZERO_WEIGHT;
+    const double logz = status ? (a.nan > 0 ? NAN : -INFINITY) : a.m + log(a.s1) - log((double)N);
+    scalars[0] = logz;
+    scalars[1] = status ? 0.0 : a.s1 * a.s1 / a.s2;
+    scalars[2] = 0.0;
+    scalars[3] = (double)status;
+    scalars[4] = a.m;
+    scalars[5] = a.s1;
+    scalars[6] = a.s2;
+    scalars[7] = (double)N;
+    if (!summaries) return;
+    if (MODEL == PPL_MODEL_POLY) {
+        for (int s = 0; s < 4; ++s) {
+            const double mass = a.f[s];
+            summaries[s] = status ? 0.0 : mass / a.s1;
+            for (int j = 0; j < 5; ++j) summaries[4 + 5 * s + j] = (!status && mass > 0) ? a.f[4 + 5 * s + j] / mass : 0.0;
+        }
+        for (int j = 0; j < 5; ++j) summaries[24 + j] = status ? 0.0 : a.f[24 + j] / a.s1;
+    } else {
+        for (int k = 0; k < NF; ++k) summaries[k] = status ? 0.0 : a.f[k] / a.s1;
+    }
+}
+
+// ---------------------------------------------------------------- host --
+size_t is_partial_bytes(int model, int dim, int64_t N) {
+    const int P = model == PPL_MODEL_POLY ? 1 : 4;
+    const int64_t blocks = (N + (int64_t)kIsThreads * P - 1) / ((int64_t)kIsThreads * P);
+    const int nf = model == PPL_MODEL_POLY ? kPolyNF : dim;
+    return (size_t)blocks * (4 + nf) * sizeof(double);
+}
+
+template <int DIM>
+static int launch_blr(const IsArgs &a, double *part, int64_t blocks, hipStream_t st) {
+    constexpr int P = 4;
+    KernelTimer timer("blr_is_kernel", st);
+    if (a.q_params)
+        hipLaunchKernelGGL((blr_is_kernel<P, DIM, true>), dim3((unsigned)blocks), dim3(kIsThreads), 0, st,
+                           (const float *)a.x, (const float *)a.y, (int)a.D, a.N, make_key(a.seed),
+                           (float)a.hyper[0], a.hyper[1], (const float *)a.q_params, (double *)a.lw_out,
+                           (float *)a.lat_out, part);
+    else
+        hipLaunchKernelGGL((blr_is_kernel<P, DIM, false>), dim3((unsigned)blocks), dim3(kIsThreads), 0, st,
+                           (const float *)a.x, (const float *)a.y, (int)a.D, a.N, make_key(a.seed),
+                           (float)a.hyper[0], a.hyper[1], nullptr, (double *)a.lw_out, (float *)a.lat_out, part);
+    timer.stop();
+    PPL_LAUNCH_CHECK("blr_is_kernel");
+    hipLaunchKernelGGL((is_finalize_kernel<DIM, PPL_MODEL_BLR>), dim3(1), dim3(64), 0, st, part, (int)blocks,
+                       a.N, a.scalars, a.summaries);
+    PPL_LAUNCH_CHECK("is_finalize_kernel");
+    return PPL_OK;
+}
+
+int run_importance(const IsArgs &a, hipStream_t st) {
+    if (a.model == PPL_MODEL_POLY) {
+        constexpr int P = 1;
+        const int64_t blocks = (a.N + kIsThreads * P - 1) / (kIsThreads * P);
+        if (int rc = check_grid("poly_is_kernel", blocks, kIsThreads)) return rc;
+        KernelTimer timer("poly_is_kernel", st);
+        hipLaunchKernelGGL((poly_is_kernel<P>), dim3((unsigned)blocks), dim3(kIsThreads), 0, st,
+                           (const double *)a.x, (const double *)a.y, (int)a.D, a.N, make_key(a.seed),
+                           a.hyper[0], (int)a.hyper[1], (int)a.hyper[2], (double *)a.lw_out,
+                           (double *)a.lat_out, a.part);
+        timer.stop();
+        PPL_LAUNCH_CHECK("poly_is_kernel");
+        hipLaunchKernelGGL((is_finalize_kernel<kPolyNF, PPL_MODEL_POLY>), dim3(1), dim3(64), 0, st, a.part,
+                           (int)blocks, a.N, a.scalars, a.summaries);
+        PPL_LAUNCH_CHECK("is_finalize_kernel");
+        return PPL_OK;
+    }
+    constexpr int P = 4;
+    const int64_t blocks = (a.N + kIsThreads * P - 1) / (kIsThreads * P);
+    if (int rc = check_grid("blr_is_kernel", blocks, kIsThreads)) return rc;
+    switch (a.dim) {
+        case 4: return launch_blr<4>(a, a.part, blocks, st);
+        case 8: return launch_blr<8>(a, a.part, blocks, st);
+        case 12: return launch_blr<12>(a, a.part, blocks, st);
+        case 16: return launch_blr<16>(a, a.part, blocks, st);
+    }
+    return fail(PPL_E_ARG, "BLR dim must be 4, 8, 12 or 16 (got %d)", a.dim);
+}
+
+}  // namespace ppl

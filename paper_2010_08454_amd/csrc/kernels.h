@@ -1,0 +1,38 @@
+// kernels.h -- launch entry points shared between the C ABI layer and the kernel files.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace ppl {
+
+struct IsArgs {
+    int model;
+    const void *x, *y;
+    int64_t D;
+    int dim;
+    double hyper[8];
+    int64_t N;
+    uint64_t seed;
+    const void *q_params;   // BLR Gaussian proposal (float32 mean + Cholesky) or null
+    void *lw_out, *lat_out;
+    double *scalars;        // [8], device
+    double *summaries;      // device or null
+    double *part;           // workspace: per-block partial records
+};
+
+size_t is_partial_bytes(int model, int dim, int64_t N);
+int run_importance(const IsArgs &a, hipStream_t st);
+
+// Normaliser of a device log-weight vector (see ppl_lse_ess).
+size_t lse_ws_bytes(int64_t n);
+int run_lse(const void *lw, bool f64, int64_t n, double *out5, void *ws, hipStream_t st);
+
+// Integer-rule systematic resampling (see ppl_resample).
+size_t resample_ws_bytes(int64_t n);
+int run_resample(const void *lw, bool f64, int64_t n, uint64_t seed, uint32_t step, uint32_t inst,
+                 int32_t *anc, void *ws, hipStream_t st);
+
+int run_philox(uint64_t seed, uint32_t c1, uint32_t c2, uint32_t c3, int64_t n, uint32_t *out, hipStream_t st);
+
+}  // namespace ppl

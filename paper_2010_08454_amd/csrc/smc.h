@@ -1,0 +1,30 @@
+// smc.h -- sequential Monte Carlo launch interface (LGSSM and mixture models).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "ppl.h"
+
+namespace ppl {
+
+struct SmcArgs {
+    int model;
+    const float *y;      // observations [T]
+    int64_t T;
+    int K;               // mixture components (GMM)
+    int64_t N;
+    uint64_t seed;
+    uint32_t inst;       // instance id carried in Philox counter word 3
+    double ess_frac;
+    double hyper[8];
+    ppl_result out;      // caller's output pointers
+    void *ws;
+};
+
+size_t smc_ws_bytes(int model, int K, int64_t N);
+int run_smc(const SmcArgs &a, hipStream_t st);
+// Device scalars the run writes (the caller's d_scalars, or the workspace slot).
+double *smc_scalars_ptr(const SmcArgs &a);
+
+}  // namespace ppl
