@@ -34,6 +34,8 @@ FP32_VALU_PUBLISHED_TFLOPS = 157.3        # needs packed FP32, which this build 
 FP64_VALU_TFLOPS = 78.6
 
 FLOP_PER_EVAL_BLR = 34                    # 17 FMA per (particle, row) at d = 16
+# sources whose hash keys the committed PMC byte counts of the importance kernels
+KERNEL_SOURCES = ("paper_2010_08454_amd/csrc/importance.hip", "paper_2010_08454_amd/csrc/device.h")
 
 
 def parse():
@@ -41,21 +43,86 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--config", default="blr", choices=["blr", "poly", "poly-paper"])
+    ap.add_argument("--config", default="blr", choices=["blr", "poly", "poly-paper", "lgssm"])
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
-    ap.add_argument("--cpu-sample", type=int, default=1 << 19, help="particles in the oracle sample")
+    ap.add_argument("--cpu-seconds", type=float, default=15.0, help="target length of the oracle sample")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="only run a plain 256 MiB device copy (reference for HBM byte counters)")
     return ap.parse_args()
 
 
-def cpu_baseline_blr(X, y, n_sample, seed):
+def copy_calibration():
+    """A plain device-to-device copy of known size: 256 MiB read + 256 MiB written
+    per launch, the reference that scales the FETCH_SIZE / WRITE_SIZE counters."""
+    import torch
+    n = 64 << 20                                   # floats: 256 MiB
+    a = torch.ones(n, dtype=torch.float32, device="cuda")
+    b = torch.empty_like(a)
+    for _ in range(3):
+        b.copy_(a)
+    torch.cuda.synchronize()
+    print(json.dumps({"copy_calibration_bytes_read": 4 * n, "copy_calibration_bytes_written": 4 * n}), flush=True)
+
+
+def cpu_baseline_blr(X, y, n_full, seed, target_s=15.0):
+    """The oracle on a bounded sample: a short calibration run sets the particle
+    count for about `target_s` seconds (capped at the full 2^20); when even the
+    full workload is shorter than that, it is repeated."""
     import oracle
     oracle.build()
     t0 = time.perf_counter()
-    oracle.importance(oracle.MODEL_BLR, X, y, n_sample, seed, dim=X.shape[1])
-    dt = time.perf_counter() - t0
-    return {"value": n_sample * y.size / dt, "unit": "particle-likelihood evals/s",
+    oracle.importance(oracle.MODEL_BLR, X, y, 1 << 12, seed, dim=X.shape[1])
+    rate = (1 << 12) / (time.perf_counter() - t0)              # particles per second
+    n_sample = int(min(n_full, max(1 << 12, 2 ** round(math.log2(rate * target_s)))))
+    reps, dt = 0, 0.0
+    while reps == 0 or (n_sample == n_full and dt < target_s * 0.6 and reps < 4):
+        t0 = time.perf_counter()
+        oracle.importance(oracle.MODEL_BLR, X, y, n_sample, seed, dim=X.shape[1])
+        dt += time.perf_counter() - t0
+        reps += 1
+    what = "the full workload" if n_sample == n_full else f"{n_sample} of the {n_full} particles"
+    return {"value": reps * n_sample * y.size / dt, "unit": "particle-likelihood evals/s",
             "cores": oracle.num_threads(), "kind": "oracle",
-            "sample": f"{n_sample} of the 2^20 particles over all {y.size} rows (FP64 oracle, {dt:.1f} s)"}
+            "sample": f"{what} over all {y.size} rows, {reps} run(s), FP64 oracle, {dt:.1f} s"}
+
+
+def cpu_baseline_lgssm(y, seed, target_s=15.0):
+    """The oracle's SMC on a particle sample sized for about `target_s` seconds."""
+    import oracle
+    oracle.build()
+    y64 = y.astype("float64")
+    t0 = time.perf_counter()
+    oracle.smc(oracle.MODEL_LGSSM, y64, 1 << 12, seed)
+    rate = (1 << 12) / (time.perf_counter() - t0)
+    n = int(min(1 << 20, max(1 << 12, 2 ** round(math.log2(rate * target_s)))))
+    t0 = time.perf_counter()
+    oracle.smc(oracle.MODEL_LGSSM, y64, n, seed)
+    dt = time.perf_counter() - t0
+    return {"value": n * y.size / dt, "unit": "particle-step evals/s", "cores": oracle.num_threads(),
+            "kind": "oracle", "sample": f"{n} of the 2^20 particles over all {y.size} steps, FP64 oracle, {dt:.1f} s"}
+
+
+def measured_traffic(kernel, sources):
+    """HBM bytes per launch from the committed rocprofv3 PMC summary of `kernel`,
+    or None when the kernel's sources changed since the counters were taken."""
+    import hashlib
+    path = os.path.join(ROOT, "profiles", f"{kernel}_traffic.txt")
+    if not os.path.exists(path):
+        return None
+    kv = {}
+    for ln in open(path):
+        if ":" in ln and not ln.startswith("#"):
+            k, v = ln.split(":", 1)
+            kv[k.strip()] = v.strip()
+    h = hashlib.sha256()
+    for s in sources:
+        h.update(open(os.path.join(ROOT, s), "rb").read())
+    if kv.get("source_sha256") != h.hexdigest():
+        return None
+    try:
+        return int(float(kv["fetch_bytes_per_launch"]) + float(kv["write_bytes_per_launch"]))
+    except (KeyError, ValueError):
+        return None
 
 
 def cpu_baseline_poly(x, y, n, seed):
@@ -73,7 +140,9 @@ def main():
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1"}))
         sys.exit(2)
-    import numpy as np
+    if args.copy_calibration:
+        copy_calibration()
+        return
     import torch
 
     import synthetic
@@ -95,6 +164,20 @@ def main():
                     "precision": "fp32 likelihood, fp64 normaliser"}
         flop_per_launch = FLOP_PER_EVAL_BLR * N * D
         peak, bound, unit, dtype = FP32_VALU_UNPACKED_TFLOPS, "alu", "TFLOP/s", "f32"
+    elif args.config == "lgssm":
+        T, N, seed = 1000, 1 << 20, 1
+        y = synthetic.lgssm_data(T=T)
+        dy = torch.from_numpy(y).to(dev)
+        data = ppl.make_data(None, dy, dtype=ppl.PPL_F32)
+        model, kname = ppl.PPL_MODEL_LGSSM, "smc_persistent_kernel"
+        D = T
+        workload = {"workload": "lgssm-smc", "model": "1-D linear-Gaussian state space, bootstrap SMC",
+                    "steps": T, "particles": N, "ess_threshold": 0.5,
+                    "precision": "fp32 state, fp64 normaliser"}
+        # VALU work per particle-step: 1/4 Philox block (~10 rounds of 2 mul_hi + 2 mul_lo + 4 xor/add = 20),
+        # 1/2 Box-Muller pair (~12), dynamics + observation density (~6), trigger exp + sums (~4): ~42 ops
+        flop_per_launch = 42 * N * T
+        peak, bound, unit, dtype = FP32_VALU_UNPACKED_TFLOPS / 2, "alu", "TOP/s", "f32"
     else:
         D = 100
         N = 10_000 if args.config == "poly" else 2_000_000
@@ -109,12 +192,18 @@ def main():
         flop_per_launch = 10 * N * D      # 4 FMA Horner + sub + FMA square, zero-padded: 10 FLOP
         peak, bound, unit, dtype = FP64_VALU_TFLOPS, "alu", "TFLOP/s", "f64"
 
-    ws = ppl.workspace(ppl.ppl_workspace_size(model, data, N, ppl.PPL_ALGO_IS), dev)
     scal = torch.empty(8, dtype=torch.float64, device=dev)
-    summ = torch.empty(nsum, dtype=torch.float64, device=dev)
+    if args.config == "lgssm":
+        ws = ppl.workspace(ppl.ppl_workspace_size(model, data, N, ppl.PPL_ALGO_SMC), dev)
 
-    def step():
-        ppl.ppl_importance(model, data, N, seed, ws=ws, stream=stream, scalars=scal, summaries=summ)
+        def step():
+            ppl.ppl_smc(model, data, N, seed, 0.5, ws=ws, stream=stream, scalars=scal)
+    else:
+        ws = ppl.workspace(ppl.ppl_workspace_size(model, data, N, ppl.PPL_ALGO_IS), dev)
+        summ = torch.empty(nsum, dtype=torch.float64, device=dev)
+
+        def step():
+            ppl.ppl_importance(model, data, N, seed, ws=ws, stream=stream, scalars=scal, summaries=summ)
 
     for _ in range(args.warmup):
         step()
@@ -139,7 +228,7 @@ def main():
     assert s[3] == 0 and math.isfinite(s[0]), f"device status {s[3]}"
 
     roofline = {"bound": bound, "achieved": round(achieved, 3), "peak": round(peak, 2), "unit": unit,
-                "frac": round(achieved / peak, 4), "traffic": None,
+                "frac": round(achieved / peak, 4), "traffic": measured_traffic(kname, KERNEL_SOURCES),
                 "kernel": kname, "kernel_ms": round(k_avg_ms, 4), "kernel_launches": k_n,
                 "flop_per_launch": flop_per_launch}
     if args.config == "blr":
@@ -152,9 +241,14 @@ def main():
            "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": dtype,
            "data": "synthetic (seeded generators, inputs resident in HBM)", "config": workload,
            "log_evidence": float(s[0]), "ess": float(s[1]), "roofline": roofline}
+    if args.config == "lgssm":
+        out["n_resample"] = int(s[2])
+        out["metric"] = "particle-step evals/s"
     if not args.no_cpu:
         if args.config == "blr":
-            out["cpu_baseline"] = cpu_baseline_blr(X, y, args.cpu_sample, seed)
+            out["cpu_baseline"] = cpu_baseline_blr(X, y, N, seed, target_s=args.cpu_seconds)
+        elif args.config == "lgssm":
+            out["cpu_baseline"] = cpu_baseline_lgssm(y, seed, target_s=args.cpu_seconds)
         else:
             out["cpu_baseline"] = cpu_baseline_poly(x, y, min(N, 1 << 20), seed)
     print(json.dumps(out), flush=True)

@@ -7,7 +7,7 @@ workspace may be passed in pre-allocated (as a benchmark does) or are
 allocated here with ``torch.empty`` when omitted.
 
 The library must be built first (``__graft_entry__.build()`` or
-``python -m paper_2010_08454_amd.build``); importing this module without it
+``python paper_2010_08454_amd/build.py``); importing this module without it
 raises, there is no fallback path.
 """
 import ctypes

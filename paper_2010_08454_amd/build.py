@@ -1,7 +1,8 @@
 """Build step of libppl: compiles the HIP sources for gfx950 into libppl.so (in-tree).
 
-Run as ``python -m paper_2010_08454_amd.build``.  Packed-FP32 instructions are
-disabled (-packed-fp32-ops) for every HIP translation unit.
+Run as ``python paper_2010_08454_amd/build.py`` (by path: importing the package
+loads the library it builds).  Packed-FP32 instructions are disabled
+(-packed-fp32-ops) for every HIP translation unit.
 """
 import glob
 import os
