@@ -46,6 +46,8 @@ def parse():
     ap.add_argument("--config", default="blr", choices=["blr", "poly", "poly-paper", "lgssm"])
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--cpu-seconds", type=float, default=15.0, help="target length of the oracle sample")
+    ap.add_argument("--particles", type=int, default=0, help="lgssm: particle count (default 2^20)")
+    ap.add_argument("--ess-frac", type=float, default=0.5, help="lgssm: resampling threshold")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain 256 MiB device copy (reference for HBM byte counters)")
     return ap.parse_args()
@@ -165,14 +167,14 @@ def main():
         flop_per_launch = FLOP_PER_EVAL_BLR * N * D
         peak, bound, unit, dtype = FP32_VALU_UNPACKED_TFLOPS, "alu", "TFLOP/s", "f32"
     elif args.config == "lgssm":
-        T, N, seed = 1000, 1 << 20, 1
+        T, N, seed = 1000, args.particles or (1 << 20), 1
         y = synthetic.lgssm_data(T=T)
         dy = torch.from_numpy(y).to(dev)
         data = ppl.make_data(None, dy, dtype=ppl.PPL_F32)
         model, kname = ppl.PPL_MODEL_LGSSM, "smc_persistent_kernel"
         D = T
         workload = {"workload": "lgssm-smc", "model": "1-D linear-Gaussian state space, bootstrap SMC",
-                    "steps": T, "particles": N, "ess_threshold": 0.5,
+                    "steps": T, "particles": N, "ess_threshold": args.ess_frac,
                     "precision": "fp32 state, fp64 normaliser"}
         # VALU work per particle-step: 1/4 Philox block (~10 rounds of 2 mul_hi + 2 mul_lo + 4 xor/add = 20),
         # 1/2 Box-Muller pair (~12), dynamics + observation density (~6), trigger exp + sums (~4): ~42 ops
@@ -197,7 +199,7 @@ def main():
         ws = ppl.workspace(ppl.ppl_workspace_size(model, data, N, ppl.PPL_ALGO_SMC), dev)
 
         def step():
-            ppl.ppl_smc(model, data, N, seed, 0.5, ws=ws, stream=stream, scalars=scal)
+            ppl.ppl_smc(model, data, N, seed, args.ess_frac, ws=ws, stream=stream, scalars=scal)
     else:
         ws = ppl.workspace(ppl.ppl_workspace_size(model, data, N, ppl.PPL_ALGO_IS), dev)
         summ = torch.empty(nsum, dtype=torch.float64, device=dev)

@@ -4,25 +4,31 @@
 // (Sec. 3.4, 4.3) and names particle-based inference on the GPU as future work
 // (Sec. 6).  Here a suspended particle is its resume point (the factor index s,
 // shared by all particles) plus fixed-size state held in registers across the
-// whole run; only resampling moves state through HBM.
+// whole run; only resampling moves state through device memory.
 //
 // One workgroup of 1024 threads per CU, P particles per thread (slots
-// j = block * 1024 P + thread * P + p).  Per factor s:
+// j = block * 1024 P + thread * P + p; a block's slots form one "tile").
+// Per factor s:
 //   1. every particle advances to factor s and adds its log-factor (FP32);
-//   2. block partial {max lw, sum e, sum e^2}, e = exp(lw - max) -> HBM;
+//   2. block partial {max lw, sum e, sum e^2}, e = exp(lw - max) -> memory;
 //      grid barrier; every block merges the partials in the same order, so
-//      all blocks take the same ESS decision;
+//      every block takes the same ESS decision;
 //   3. if ESS < ess_frac N (and s is not the last factor): FP64 weights
 //      e = exp(lw - max) give the epoch normaliser and the quantised integer
-//      weights q; each block scans its q, publishes tile totals, its state
-//      and its local scan; grid barrier; each slot finds its ancestor
-//      (binary search over tile ends, then inside the tile) and gathers the
-//      ancestor's state; lw = 0.
-// The grid barrier is a monotone counter with a bounded spin: if a wait ever
-// exceeds the limit, the block raises the abort flag and every block leaves
-// its loop at its next barrier, so the grid always drains.
+//      weights q; each block scans its q and publishes its tile total, its
+//      tile-local prefix sums and its particles' state; grid barrier; each
+//      block finds the contiguous ancestor range of its slots, stages those
+//      prefix sums in LDS, and every slot binary-searches its ancestor there
+//      and gathers the ancestor's state; lw = 0.
+// The grid barrier is hierarchical (groups of 16 blocks count on their own
+// cache line; the last block of a group advances the global counter) and
+// spins a bounded number of times: if a wait exceeds the limit, the block
+// raises the abort flag and every block leaves its loop at its next barrier,
+// so the grid always drains.
 #include <math.h>
 #include <string.h>
+
+#include <algorithm>
 
 #include "device.h"
 #include "host.h"
@@ -33,7 +39,13 @@ namespace ppl {
 
 constexpr int kSmcThreads = 1024;
 constexpr int kSmcWaves = kSmcThreads / 64;
-constexpr uint32_t kSpinLimit = 1u << 24;     // ~1 s of s_sleep(2) per barrier wait
+constexpr int kSmcMaxBlocks = 1024;
+constexpr int kBarGroup = 16;                 // blocks per barrier group
+constexpr int kBarLine = 32;                  // unsigned per 128-byte line
+constexpr int kBarWords = kBarLine * (1 + kSmcMaxBlocks / kBarGroup);
+constexpr uint32_t kSpinLimit = 1u << 24;     // polls before a wait is declared hung (seconds)
+constexpr int kYChunk = 2048;                 // observations staged in LDS at a time
+constexpr int kStage = 8192;                  // most prefix sums staged in LDS for the ancestor search
 
 struct SmcDev {
     const float *y;
@@ -45,6 +57,7 @@ struct SmcDev {
     float hyp[5];            // model constants (FP32)
     double lconst;           // LGSSM: -1/2 log(2 pi r^2) ; GMM: -1/2 log(2 pi) - log(sd)
     int kbits;               // quantisation exponent
+    int stage_cap;           // prefix sums that fit in the LDS stage
     // outputs (may be null)
     double *scalars;
     float *lw_out, *lat_out;
@@ -53,33 +66,46 @@ struct SmcDev {
     int32_t *anc_out;
     int64_t max_events;
     // workspace
-    unsigned *bar;           // [0] barrier counter, [1] abort flag
+    unsigned *bar;           // [0] global counter, [1] abort flag, [32 (1 + g)] group g counter
     double *part;            // [2][nb][3]
     uint64_t *tot;           // [nb]
     double *esum;            // [nb]
     double *fin;             // [nb][2]
-    uint64_t *qloc;          // [N]
+    uint64_t *qloc;          // [N] tile-local inclusive prefix sums of q
     float *xbuf;             // [NF][N]
 };
 
 // ------------------------------------------------------------- barrier --
-// Returns false (uniformly in the block) once any block has aborted.
-__device__ __forceinline__ bool grid_barrier(unsigned *bar, unsigned target) {
+// Returns false (uniformly in the block) once any block has aborted.  Arrival
+// is acq_rel on the group counter (the block's writes are released; the last
+// arriver acquires the group's), then release on the global counter; the spin
+// uses relaxed device-scope loads and one acquire fence follows it.
+__device__ __forceinline__ bool grid_barrier(unsigned *bar, unsigned epoch, int nb) {
     __shared__ int s_ok;
     __syncthreads();
     if (threadIdx.x == 0) {
-        __hip_atomic_fetch_add(&bar[0], 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+        const int g = blockIdx.x / kBarGroup;
+        const int ngroups = (nb + kBarGroup - 1) / kBarGroup;
+        const unsigned gsize = (unsigned)min(kBarGroup, nb - g * kBarGroup);
+        const unsigned old = __hip_atomic_fetch_add(&bar[kBarLine * (1 + g)], 1u, __ATOMIC_ACQ_REL,
+                                                     __HIP_MEMORY_SCOPE_AGENT);
+        if (old + 1 == epoch * gsize)
+            __hip_atomic_fetch_add(&bar[0], 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+        const unsigned target = epoch * (unsigned)ngroups;
         uint32_t spins = 0;
         int ok = 1;
-        while (__hip_atomic_load(&bar[0], __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) < target) {
-            if (__hip_atomic_load(&bar[1], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) { ok = 0; break; }
-            __builtin_amdgcn_s_sleep(2);
-            if (++spins > kSpinLimit) {
-                __hip_atomic_store(&bar[1], 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-                ok = 0;
-                break;
+        while (__hip_atomic_load(&bar[0], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < target) {
+            __builtin_amdgcn_s_sleep(1);
+            if ((++spins & 63) == 0) {
+                if (__hip_atomic_load(&bar[1], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) { ok = 0; break; }
+                if (spins > kSpinLimit) {
+                    __hip_atomic_store(&bar[1], 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                    ok = 0;
+                    break;
+                }
             }
         }
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
         if (ok && __hip_atomic_load(&bar[1], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) ok = 0;
         s_ok = ok;
     }
@@ -148,6 +174,11 @@ struct Gmm {
     }
 };
 
+// FP64 log/exp kept out of line: inlined, their polynomial constants get hoisted
+// out of the factor loop and occupy registers for the whole run.
+__device__ __noinline__ double log_f64(double v) { return log(v); }
+__device__ __noinline__ double exp_f64(double v) { return exp(v); }
+
 // ------------------------------------------------------ block helpers --
 __device__ __forceinline__ float block_max_f32(float v, float *lds) {
     v = wave_max(v);
@@ -169,6 +200,26 @@ __device__ __forceinline__ double block_sum_f64(double v, double *lds) {
     for (int w = 0; w < kSmcWaves; ++w) s += lds[w];
     __syncthreads();
     return s;
+}
+
+// Two sums in one pass (lds holds 2 * kSmcWaves doubles).
+__device__ __forceinline__ void block_sum2_f64(double &u, double &v, double *lds) {
+    u = wave_sum(u);
+    v = wave_sum(v);
+    if ((threadIdx.x & 63) == 0) {
+        lds[threadIdx.x >> 6] = u;
+        lds[kSmcWaves + (threadIdx.x >> 6)] = v;
+    }
+    __syncthreads();
+    double a = 0.0, b = 0.0;
+#pragma unroll
+    for (int w = 0; w < kSmcWaves; ++w) {
+        a += lds[w];
+        b += lds[kSmcWaves + w];
+    }
+    __syncthreads();
+    u = a;
+    v = b;
 }
 
 // Exclusive scan of one u64 per thread across the block; returns the prefix,
@@ -199,54 +250,65 @@ __device__ __forceinline__ uint64_t block_exclusive_scan_u64(uint64_t v, uint64_
 // fixed order, FP32 rescale factors (this feeds the resampling trigger only).
 __device__ __forceinline__ void merge_partials(const double *part, int nb, float *ldsf, double *ldsd,
                                                float &M, double &S1, double &S2) {
-    float m = -INFINITY;
-    for (int b = threadIdx.x; b < nb; b += kSmcThreads) m = fmaxf(m, (float)part[3 * b]);
-    M = block_max_f32(m, ldsf);
+    float mb = -INFINITY;
+    double p1 = 0.0, p2 = 0.0;
+    if (threadIdx.x < nb) {          // nb <= kSmcThreads
+        mb = (float)part[3 * threadIdx.x];
+        p1 = part[3 * threadIdx.x + 1];
+        p2 = part[3 * threadIdx.x + 2];
+    }
+    M = block_max_f32(mb, ldsf);
     double s1 = 0.0, s2 = 0.0;
-    if (M > -INFINITY) {
-        for (int b = threadIdx.x; b < nb; b += kSmcThreads) {
-            const float mb = (float)part[3 * b];
-            const float c = expf(mb - M);
-            s1 += part[3 * b + 1] * (double)c;
-            s2 += part[3 * b + 2] * (double)(c * c);
-        }
+    if (M > -INFINITY && threadIdx.x < nb) {
+        const float c = expf(mb - M);
+        s1 = p1 * (double)c;
+        s2 = p2 * (double)(c * c);
     }
-    S1 = block_sum_f64(s1, ldsd);
-    S2 = block_sum_f64(s2, ldsd);
+    block_sum2_f64(s1, s2, ldsd);
+    S1 = s1;
+    S2 = s2;
 }
 
-// (ahi:alo) > (bhi:blo) for 128-bit values split in 64-bit halves.
-__device__ __forceinline__ bool gt128(uint64_t ahi, uint64_t alo, uint64_t bhi, uint64_t blo) {
-    return ahi > bhi || (ahi == bhi && alo > blo);
+// Slot thresholds.  For integers, N Q_a > j S + U  <=>  Q_a > floor((j S + U) / N),
+// and with S = N Sq + Sr (Sr < N < 2^31):
+//   tau_j = floor((j S + U) / N) = j Sq + floor((j Sr + U) / N),
+// where j Sr + U < 2^63, so tau_j needs only 64-bit arithmetic.  Consecutive
+// slots update the quotient and remainder incrementally.
+struct SlotThreshold {
+    uint64_t quo, rem;   // of (j Sr + U) / N
+};
+
+__device__ __forceinline__ SlotThreshold slot_threshold(uint32_t j, uint64_t Sr, uint64_t U, uint64_t N) {
+    const uint64_t num = (uint64_t)j * Sr + U;
+    return SlotThreshold{num / N, num % N};
 }
 
-// Ancestor of slot j: min{a : N Q_a > j S + U}, with Q_a = (tile_end[b] - tot[b]) + qloc[a]
-// for a in tile b.  `prev` (the previous slot's ancestor, or -1) bounds the search
-// from below, since ancestors are non-decreasing in j.
-__device__ __forceinline__ int find_ancestor(uint32_t j, uint64_t S, uint64_t U, uint64_t N, int nb, int tile,
-                                             const uint64_t *tile_end, const uint64_t *__restrict__ tot,
-                                             const uint64_t *__restrict__ qloc, int prev) {
-    const uint64_t tl0 = (uint64_t)j * S;
-    const uint64_t tlo = tl0 + U;
-    const uint64_t thi = __umul64hi((uint64_t)j, S) + (tlo < tl0 ? 1 : 0);
-    if (prev >= 0) {
-        const uint64_t q = tile_end[prev / tile] - tot[prev / tile] + qloc[prev];
-        if (gt128(__umul64hi(N, q), N * q, thi, tlo)) return prev;
+__device__ __forceinline__ void slot_threshold_next(SlotThreshold &t, uint64_t Sr, uint64_t N) {
+    t.rem += Sr;
+    if (t.rem >= N) {
+        t.rem -= N;
+        t.quo += 1;
     }
-    int lo = 0, hi = nb - 1;
+}
+
+// Ancestor of the slot with threshold tau over the whole population:
+// min{a : Q_a > tau}, with Q_a = tile_pre[b] + qloc[a] for a in tile b (tile
+// ends and exclusive tile prefixes are in LDS, qloc in device memory).
+__device__ __forceinline__ int find_ancestor_global(uint64_t tau, int64_t N, int nb, int tile, const uint64_t *tile_end,
+                                                    const uint64_t *tile_pre, const uint64_t *__restrict__ qloc,
+                                                    int lo_bound) {
+    int lo = lo_bound < 0 ? 0 : lo_bound / tile, hi = nb - 1;
     while (lo < hi) {
         const int mid = (lo + hi) >> 1;
-        const uint64_t q = tile_end[mid];
-        if (gt128(__umul64hi(N, q), N * q, thi, tlo)) hi = mid; else lo = mid + 1;
+        if (tile_end[mid] > tau) hi = mid; else lo = mid + 1;
     }
-    const uint64_t pre = tile_end[lo] - tot[lo];
+    const uint64_t pre = tile_pre[lo];
     int a0 = lo * tile, a1 = a0 + tile - 1;
     if (a1 > (int)N - 1) a1 = (int)N - 1;
-    if (prev >= a0) a0 = prev + 1;
+    if (lo_bound > a0) a0 = lo_bound;
     while (a0 < a1) {
         const int mid = (a0 + a1) >> 1;
-        const uint64_t q = pre + qloc[mid];
-        if (gt128(__umul64hi(N, q), N * q, thi, tlo)) a1 = mid; else a0 = mid + 1;
+        if (pre + qloc[mid] > tau) a1 = mid; else a0 = mid + 1;
     }
     return a0;
 }
@@ -255,13 +317,21 @@ __device__ __forceinline__ int find_ancestor(uint32_t j, uint64_t S, uint64_t U,
 template <class M, int P>
 __global__ __launch_bounds__(kSmcThreads) void smc_persistent_kernel(SmcDev a) {
     __shared__ float ldsf[kSmcWaves];
-    __shared__ double ldsd[kSmcWaves];
+    __shared__ double ldsd[2 * kSmcWaves];
     __shared__ uint64_t ldsu[kSmcWaves];
-    extern __shared__ uint64_t tile_end[];          // [nb] inclusive tile ends (resampling)
-
+    __shared__ float ybuf[kYChunk];
+    __shared__ int s_rng[2];
+    // dynamic LDS: tile_end[nb] | tile_pre[nb] | stage[stage_cap] (u64) | s_anc[1024 P] (i32)
+    extern __shared__ uint64_t dyn[];
     const int nb = gridDim.x;
+    uint64_t *tile_end = dyn;
+    uint64_t *tile_pre = dyn + nb;
+    uint64_t *stage = dyn + 2 * nb;
+    int32_t *s_anc = (int32_t *)(dyn + 2 * nb + a.stage_cap);
+
     const int64_t N = a.N;
-    const int64_t base = (int64_t)blockIdx.x * kSmcThreads * P + (int64_t)threadIdx.x * P;
+    constexpr int kTile = kSmcThreads * P;
+    const int64_t base = (int64_t)blockIdx.x * kTile + (int64_t)threadIdx.x * P;
 
     float st[P][M::NF];
     float lw[P];
@@ -280,13 +350,23 @@ __global__ __launch_bounds__(kSmcThreads) void smc_persistent_kernel(SmcDev a) {
     int status = 0;
     float Mlast = 0.0f;
     bool alive = true;
-    const double logN = log((double)N);
+    const double logN = log_f64((double)N);
 
     for (int64_t s = 0; s < a.T; ++s) {
-        const float ys = a.y[s];
+        if ((s % kYChunk) == 0) {          // stage the next chunk of observations
+            __syncthreads();
+            for (int i = threadIdx.x; i < kYChunk; i += kSmcThreads)
+                ybuf[i] = (s + i < a.T) ? a.y[s + i] : 0.0f;
+            __syncthreads();
+        }
+        const float ys = ybuf[s % kYChunk];
+        // The slot index is re-materialised every factor: otherwise the compiler
+        // hoists every per-slot address out of the factor loop and runs out of VGPRs.
+        int jb = (int)base;
+        asm volatile("" : "+v"(jb));
 #pragma unroll
         for (int p = 0; p < P; ++p) {
-            const float f = M::step(a, s, (uint32_t)(base + p), st[p], zc[p], ys);
+            const float f = M::step(a, s, (uint32_t)(jb + p), st[p], zc[p], ys);
             if (valid[p]) lw[p] += f;
         }
         // block partial for the ESS trigger
@@ -303,15 +383,15 @@ __global__ __launch_bounds__(kSmcThreads) void smc_persistent_kernel(SmcDev a) {
                 s2l = fmaf(e, e, s2l);
             }
         }
-        const double s1b = block_sum_f64((double)s1l, ldsd);
-        const double s2b = block_sum_f64((double)s2l, ldsd);
+        double s1b = s1l, s2b = s2l;
+        block_sum2_f64(s1b, s2b, ldsd);
         double *pp = a.part + (size_t)(s & 1) * nb * 3;
         if (threadIdx.x == 0) {
             pp[3 * blockIdx.x] = (double)mb;
             pp[3 * blockIdx.x + 1] = s1b;
             pp[3 * blockIdx.x + 2] = s2b;
         }
-        if (!grid_barrier(a.bar, ++epoch * (unsigned)nb)) { alive = false; status = PPL_E_HIP; break; }
+        if (!grid_barrier(a.bar, ++epoch, nb)) { alive = false; break; }
 
         float Mg;
         double S1, S2;
@@ -327,13 +407,13 @@ __global__ __launch_bounds__(kSmcThreads) void smc_persistent_kernel(SmcDev a) {
         }
         if (!res) continue;
 
-        // ---- resampling: FP64 weights, normaliser, integer quantisation, scan
+        // ---- resampling: FP64 weights, normaliser, integer quantisation, tile scan
         uint64_t q[P];
         uint64_t run = 0;
         double esl = 0.0;
 #pragma unroll
         for (int p = 0; p < P; ++p) {
-            const double e = valid[p] ? exp((double)lw[p] - (double)Mg) : 0.0;
+            const double e = valid[p] ? exp_f64((double)lw[p] - (double)Mg) : 0.0;
             esl += e;
             run += (uint64_t)floor(ldexp(e, a.kbits));
             q[p] = run;
@@ -344,51 +424,84 @@ __global__ __launch_bounds__(kSmcThreads) void smc_persistent_kernel(SmcDev a) {
 #pragma unroll
         for (int p = 0; p < P; ++p) {
             if (valid[p]) {
-                a.qloc[base + p] = off + q[p];
+                a.qloc[jb + p] = off + q[p];
 #pragma unroll
-                for (int f = 0; f < M::NF; ++f) a.xbuf[(size_t)f * N + base + p] = st[p][f];
+                for (int f = 0; f < M::NF; ++f) a.xbuf[(size_t)f * N + jb + p] = st[p][f];
             }
         }
         if (threadIdx.x == 0) {
             a.tot[blockIdx.x] = btot;
             a.esum[blockIdx.x] = eb;
         }
-        if (!grid_barrier(a.bar, ++epoch * (unsigned)nb)) { alive = false; status = PPL_E_HIP; break; }
+        if (!grid_barrier(a.bar, ++epoch, nb)) { alive = false; break; }
 
-        // tile ends (inclusive prefix of tile totals) and the normaliser sum, same order everywhere
-        uint64_t tv = 0;
-        double ev = 0.0;
-        for (int b0 = 0; b0 < nb; b0 += kSmcThreads) {
-            const int b = b0 + threadIdx.x;
-            const uint64_t v = b < nb ? a.tot[b] : 0;
-            uint64_t chunk;
-            const uint64_t ex = block_exclusive_scan_u64(v, ldsu, chunk);
-            if (b < nb) tile_end[b] = tv + ex + v;
-            tv += chunk;
-            ev += block_sum_f64(b < nb ? a.esum[b] : 0.0, ldsd);
-        }
-        __syncthreads();
-        const uint64_t S = tv;
-        const uint4 rw = philox(0, 0, (uint32_t)s, (a.inst << 8) | kTagResample, a.key);
-        const uint64_t U = __umul64hi(((uint64_t)rw.y << 32) | rw.x, S);
-        logz += (double)Mg + log(ev) - logN;
-        ++nres;
+        // tile prefixes (LDS) and the normaliser sum, in the same order in every block
+        {
+            const uint64_t v = threadIdx.x < nb ? a.tot[threadIdx.x] : 0;
+            const double ev0 = threadIdx.x < nb ? a.esum[threadIdx.x] : 0.0;
+            uint64_t S;
+            const uint64_t ex = block_exclusive_scan_u64(v, ldsu, S);
+            if (threadIdx.x < nb) {
+                tile_pre[threadIdx.x] = ex;
+                tile_end[threadIdx.x] = ex + v;
+            }
+            const double ev = block_sum_f64(ev0, ldsd);     // contains the barrier for tile_*
+            const uint4 rw = philox(0, 0, (uint32_t)s, (a.inst << 8) | kTagResample, a.key);
+            const uint64_t U = __umul64hi(((uint64_t)rw.y << 32) | rw.x, S);
+            logz += (double)Mg + log_f64(ev) - logN;
+            ++nres;
+            const uint64_t NN = (uint64_t)N;
+            const uint64_t Sq = S / NN, Sr = S - Sq * NN;
 
-        // phase A (one loop body, not unrolled): ancestors of this thread's slots -> LDS
-        int32_t *s_anc = (int32_t *)(tile_end + nb);
-        int32_t *anc_row = (a.anc_out && nres - 1 < a.max_events) ? a.anc_out + (size_t)(nres - 1) * N : nullptr;
-        int prev = -1;
+            // ancestor range of this block's slots (two searches, in different waves)
+            const int js0 = blockIdx.x * kTile;
+            const int js1 = (int)min((int64_t)js0 + kTile, N) - 1;
+            if (threadIdx.x == 0) {
+                const SlotThreshold t = slot_threshold((uint32_t)js0, Sr, U, NN);
+                s_rng[0] = find_ancestor_global((uint64_t)js0 * Sq + t.quo, N, nb, kTile, tile_end, tile_pre, a.qloc, -1);
+            }
+            if (threadIdx.x == 64) {
+                const SlotThreshold t = slot_threshold((uint32_t)js1, Sr, U, NN);
+                s_rng[1] = find_ancestor_global((uint64_t)js1 * Sq + t.quo, N, nb, kTile, tile_end, tile_pre, a.qloc, -1);
+            }
+            __syncthreads();
+            const int a_lo = s_rng[0], a_hi = s_rng[1];
+            const int span = a_hi - a_lo + 1;
+            const bool staged = span <= a.stage_cap;
+            if (staged) {
+                for (int i = threadIdx.x; i < span; i += kSmcThreads) {
+                    const int aa = a_lo + i;
+                    stage[i] = tile_pre[aa / kTile] + a.qloc[aa];
+                }
+            }
+            __syncthreads();
+
+            int32_t *anc_row = (a.anc_out && nres - 1 < a.max_events) ? a.anc_out + (size_t)(nres - 1) * N : nullptr;
+            int prev = a_lo;
+            SlotThreshold th = slot_threshold((uint32_t)jb, Sr, U, NN);
 #pragma unroll 1
-        for (int p = 0; p < P; ++p) {
-            const int j = (int)base + p;
-            if (j >= N) break;
-            const int anc = find_ancestor((uint32_t)j, S, U, (uint64_t)N, nb, kSmcThreads * P, tile_end, a.tot,
-                                          a.qloc, prev);
-            s_anc[threadIdx.x * P + p] = anc;
-            if (anc_row) anc_row[j] = anc;
-            prev = anc;
+            for (int p = 0; p < P; ++p) {
+                const int j = jb + p;
+                if (j >= N) break;
+                if (p) slot_threshold_next(th, Sr, NN);
+                const uint64_t tau = (uint64_t)j * Sq + th.quo;
+                int anc;
+                if (staged) {
+                    int lo = prev - a_lo, hi = span - 1;
+                    while (lo < hi) {
+                        const int mid = (lo + hi) >> 1;
+                        if (stage[mid] > tau) hi = mid; else lo = mid + 1;
+                    }
+                    anc = a_lo + lo;
+                } else {
+                    anc = find_ancestor_global(tau, N, nb, kTile, tile_end, tile_pre, a.qloc, prev);
+                }
+                s_anc[threadIdx.x * P + p] = anc;
+                if (anc_row) anc_row[j] = anc;
+                prev = anc;
+            }
         }
-        // phase B: gather the ancestors' state
+        // gather the ancestors' state
 #pragma unroll
         for (int p = 0; p < P; ++p) {
             if (!valid[p]) continue;
@@ -406,28 +519,23 @@ __global__ __launch_bounds__(kSmcThreads) void smc_persistent_kernel(SmcDev a) {
 #pragma unroll
         for (int p = 0; p < P; ++p) {
             if (valid[p]) {
-                const double e = exp((double)lw[p] - (double)Mlast);
+                const double e = exp_f64((double)lw[p] - (double)Mlast);
                 e1 += e;
                 e2 += e * e;
             }
         }
-        e1 = block_sum_f64(e1, ldsd);
-        e2 = block_sum_f64(e2, ldsd);
+        block_sum2_f64(e1, e2, ldsd);
         if (threadIdx.x == 0) {
             a.fin[2 * blockIdx.x] = e1;
             a.fin[2 * blockIdx.x + 1] = e2;
         }
-        if (!grid_barrier(a.bar, ++epoch * (unsigned)nb)) {
+        if (!grid_barrier(a.bar, ++epoch, nb)) {
             alive = false;
-            status = PPL_E_HIP;
         } else {
-            double t1 = 0.0, t2 = 0.0;
-            for (int b0 = 0; b0 < nb; b0 += kSmcThreads) {
-                const int b = b0 + threadIdx.x;
-                t1 += block_sum_f64(b < nb ? a.fin[2 * b] : 0.0, ldsd);
-                t2 += block_sum_f64(b < nb ? a.fin[2 * b + 1] : 0.0, ldsd);
-            }
-            logz += (double)Mlast + log(t1) - logN;
+            double t1 = threadIdx.x < nb ? a.fin[2 * threadIdx.x] : 0.0;
+            double t2 = threadIdx.x < nb ? a.fin[2 * threadIdx.x + 1] : 0.0;
+            block_sum2_f64(t1, t2, ldsd);
+            logz += (double)Mlast + log_f64(t1) - logN;
             ess_final = t1 * t1 / t2;
         }
     }
@@ -455,8 +563,10 @@ __global__ __launch_bounds__(kSmcThreads) void smc_persistent_kernel(SmcDev a) {
     }
 }
 
+// Clears the barrier counters and abort flag (a fill kernel, so the launch
+// sequence stays capturable).
 __global__ void smc_reset_kernel(unsigned *bar) {
-    if (threadIdx.x < 2) bar[threadIdx.x] = 0u;
+    for (int i = threadIdx.x; i < kBarWords; i += blockDim.x) bar[i] = 0u;
 }
 
 // ------------------------------------------------------------------ host --
@@ -485,7 +595,7 @@ static SmcLayout smc_layout(void *ws, int NF, int64_t N, int64_t nb) {
     size_t o = 0;
     auto take = [&](size_t n) { char *r = p + o; o += align_up(n, 256); return r; };
     L.scal = (double *)take(8 * sizeof(double));
-    L.bar = (unsigned *)take(2 * sizeof(unsigned));
+    L.bar = (unsigned *)take(kBarWords * sizeof(unsigned));
     L.part = (double *)take(2 * nb * 3 * sizeof(double));
     L.esum = (double *)take(nb * sizeof(double));
     L.fin = (double *)take(2 * nb * sizeof(double));
@@ -510,11 +620,17 @@ static int launch(SmcDev &d, int64_t nb, hipStream_t st) {
     int dev = 0, ncu = 0, occ = 0;
     PPL_HIP(hipGetDevice(&dev));
     PPL_HIP(hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev));
-    const size_t lds = (size_t)nb * sizeof(uint64_t) + (size_t)kSmcThreads * P * sizeof(int32_t);
+    // stage as many prefix sums as the per-block LDS limit leaves room for (<= kStage)
+    int max_lds = 0;
+    PPL_HIP(hipDeviceGetAttribute(&max_lds, hipDeviceAttributeMaxSharedMemoryPerBlock, dev));
+    const int64_t fixed = (int64_t)2 * nb * sizeof(uint64_t) + (int64_t)kSmcThreads * P * sizeof(int32_t) +
+                          (int64_t)kYChunk * sizeof(float) + 1024;      // + static LDS of the kernel
+    d.stage_cap = (int)std::max<int64_t>(0, std::min<int64_t>(kStage, (max_lds - fixed) / 8));
+    const size_t lds = (size_t)(2 * nb + d.stage_cap) * sizeof(uint64_t) + (size_t)kSmcThreads * P * sizeof(int32_t);
     PPL_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, kern, kSmcThreads, lds));
     if ((int64_t)occ * ncu < nb)
         return fail(PPL_E_UNSUPPORTED, "SMC needs %lld co-resident blocks, device holds %d", (long long)nb, occ * ncu);
-    hipLaunchKernelGGL(smc_reset_kernel, dim3(1), dim3(64), 0, st, d.bar);
+    hipLaunchKernelGGL(smc_reset_kernel, dim3(1), dim3(256), 0, st, d.bar);
     PPL_LAUNCH_CHECK("smc_reset_kernel");
     void *args[] = {&d};
     KernelTimer timer("smc_persistent_kernel", st);
@@ -538,9 +654,14 @@ int run_smc(const SmcArgs &a, hipStream_t st) {
     const int NF = a.model == PPL_MODEL_LGSSM ? 1 : 2 * a.K;
     const int P = pick_p(a.N);
     const int64_t nb = smc_blocks(a.N, P);
-    if (nb > 4096) return fail(PPL_E_UNSUPPORTED, "SMC supports at most %lld particles", (long long)4096 * kSmcThreads * 8);
+    if (nb > kSmcMaxBlocks)
+        return fail(PPL_E_UNSUPPORTED, "SMC supports at most %lld particles",
+                    (long long)kSmcMaxBlocks * kSmcThreads * 8);
     if (a.T > 0x7fffffffLL) return fail(PPL_E_ARG, "too many factors");
-    if ((a.T + 2) * 2 * nb >= 0xffffffffLL) return fail(PPL_E_UNSUPPORTED, "barrier counter would overflow");
+    // the global barrier counter reaches (2 T + 1) * groups
+    if ((2 * a.T + 2) * ((nb + kBarGroup - 1) / kBarGroup) >= 0xffffffffLL ||
+        (2 * a.T + 2) * kBarGroup >= 0xffffffffLL)
+        return fail(PPL_E_UNSUPPORTED, "barrier counter would overflow");
     SmcLayout L = smc_layout(a.ws, NF, a.N, nb);
     SmcDev d{};
     d.y = a.y;
