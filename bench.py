@@ -43,7 +43,7 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--config", default="blr", choices=["blr", "poly", "poly-paper", "lgssm"])
+    ap.add_argument("--config", default="blr", choices=["blr", "poly", "poly-paper", "lgssm", "gmm-batched"])
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--cpu-seconds", type=float, default=15.0, help="target length of the oracle sample")
     ap.add_argument("--particles", type=int, default=0, help="lgssm: particle count (default 2^20)")
@@ -180,7 +180,7 @@ def main():
         # 1/2 Box-Muller pair (~12), dynamics + observation density (~6), trigger exp + sums (~4): ~42 ops
         flop_per_launch = 42 * N * T
         peak, bound, unit, dtype = FP32_VALU_UNPACKED_TFLOPS / 2, "alu", "TOP/s", "f32"
-    else:
+    elif args.config in ("poly", "poly-paper"):
         D = 100
         N = 10_000 if args.config == "poly" else 2_000_000
         seed = 1
@@ -193,9 +193,32 @@ def main():
                     "points": D, "particles": N, "precision": "fp64"}
         flop_per_launch = 10 * N * D      # 4 FMA Horner + sub + FMA square, zero-padded: 10 FLOP
         peak, bound, unit, dtype = FP64_VALU_TFLOPS, "alu", "TFLOP/s", "f64"
+    elif args.config == "gmm-batched":
+        insts = synthetic.gmm_instances(256)
+        N, seed = 1 << 16, 1
+        ys = [torch.from_numpy(I["y"]).to(dev) for I in insts]
+        table = ppl.InstanceTable(ys, [I["K"] for I in insts], N)
+        D = sum(I["D"] for I in insts)
+        kD = sum(I["D"] * I["K"] for I in insts)
+        model, kname = ppl.PPL_MODEL_GMM, "smc_batched_kernel"
+        workload = {"workload": "gmm-batched-smc", "model": "Gaussian mixtures, K in 3..8, batched SMC",
+                    "instances": len(insts), "particles_per_instance": N, "total_data": D,
+                    "max_data": max(I["D"] for I in insts), "precision": "fp32 state, fp64 normaliser"}
+        # VALU work per particle-datum: K FMA-pairs (residual, square) + K max + K exp (quarter rate: 4) +
+        # 1 log (4) + trigger exp (4) + 3 sums: ~ 7K + 11 lane-ops
+        flop_per_launch = N * (7 * kD + 11 * D)
+        peak, bound, unit, dtype = FP32_VALU_UNPACKED_TFLOPS / 2, "alu", "TOP/s", "f32"
 
     scal = torch.empty(8, dtype=torch.float64, device=dev)
-    if args.config == "lgssm":
+    if args.config == "gmm-batched":
+        ws = ppl.workspace(ppl.ppl_smc_batched_workspace_size(model, table, None), dev)
+        outb = torch.empty((table.n, 4), dtype=torch.float64, device=dev)
+        tuned = ppl.ppl_smc_autotune(model, table, seed, 0.5, ws=ws, stream=stream, out=outb)
+        workload["tuned"] = {"particles_per_lane": tuned[0], "wgs_per_instance": tuned[1], "spec_block": tuned[2]}
+
+        def step():
+            ppl.ppl_smc_batched(model, table, seed, 0.5, tune=tuned + (0,), ws=ws, stream=stream, out=outb)
+    elif args.config == "lgssm":
         ws = ppl.workspace(ppl.ppl_workspace_size(model, data, N, ppl.PPL_ALGO_SMC), dev)
 
         def step():
@@ -226,8 +249,14 @@ def main():
     value = evals / (ms_per_step / 1e3)
     k_avg_ms = k_ms / max(k_n, 1)
     achieved = flop_per_launch / (k_avg_ms / 1e3) / 1e12
-    s = scal.cpu().numpy()
-    assert s[3] == 0 and math.isfinite(s[0]), f"device status {s[3]}"
+    if args.config == "gmm-batched":
+        ob = outb.cpu().numpy()
+        assert (ob[:, 3] == 0).all(), "device status"
+        s = [float(ob[:, 0].sum()), float(ob[:, 1].mean()), float(ob[:, 2].sum()), 0.0]
+        evals = N * D
+    else:
+        s = scal.cpu().numpy()
+        assert s[3] == 0 and math.isfinite(s[0]), f"device status {s[3]}"
 
     roofline = {"bound": bound, "achieved": round(achieved, 3), "peak": round(peak, 2), "unit": unit,
                 "frac": round(achieved / peak, 4), "traffic": measured_traffic(kname, KERNEL_SOURCES),

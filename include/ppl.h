@@ -193,6 +193,75 @@ int ppl_philox(uint64_t seed, uint32_t c1, uint32_t c2, uint32_t c3, int64_t n,
 int ppl_smc(int model, const ppl_data *data, int64_t n_particles, uint64_t seed,
             double ess_frac, void *d_ws, size_t ws_bytes, void *stream, ppl_result *out);
 
+/* ------------------------------------------------------ batched SMC -- */
+/* One model instance of a batched run.  The caller passes the same table
+ * twice: a HOST copy (validated and used for scheduling) and a DEVICE copy
+ * with identical bytes (read by the kernel).  Instance i uses Philox
+ * instance id i (counter word 3 = i << 8 | tag), so its result equals a
+ * ppl_smc-style run of that instance alone with instance id i. */
+typedef struct ppl_instance {
+    const float *y;           /* DEVICE observations [n_data] */
+    int64_t n_data;           /* D_i (factors) */
+    int64_t n_particles;      /* N_i */
+    int32_t dim;              /* GMM: K_i in 1..8 */
+    int32_t reserved;
+    double hyper[2];          /* GMM: {mu_sd, comp_sd}; 0 = default {5, 1} */
+} ppl_instance;
+
+/* Launch configuration of the batched engine (0 fields = default/derived).
+ * particles_per_lane P in {1,2,4,8}; wgs_per_instance W = 1024-thread
+ * workgroups that hold one instance (W * 1024 * P >= max N_i, W <= 64);
+ * spec_block = largest number of factors advanced between synchronisations
+ * (1..128).  Results are the SMC of each instance for any valid choice; the
+ * choice only changes the order of the FP64 sums behind the resampling
+ * trigger (so a decision within rounding of the threshold may differ). */
+typedef struct ppl_tune {
+    int32_t particles_per_lane;
+    int32_t wgs_per_instance;
+    int32_t spec_block;
+    int32_t reserved;
+} ppl_tune;
+
+/* Outputs of a batched run (any pointer may be NULL):
+ *   d_out [n_inst][4] FP64: log Z-hat, final ESS, resamplings, status;
+ *   d_log_weights [sum N_i] float32, instance i at offset P_i = sum_{k<i} N_k;
+ *   d_latents [16 * sum N_i] float32, instance i at 16 P_i as [2 K_i][N_i]
+ *             (log pi_k then mu_k);
+ *   d_ess_trace / d_resampled [sum D_i], instance i at offset sum_{k<i} D_k;
+ *   d_ancestors [max_events * sum N_i] int32, instance i at max_events * P_i as
+ *             [max_events][N_i]: the ancestor vectors of its first max_events
+ *             resampling events. */
+typedef struct ppl_batch_result {
+    double *d_out;
+    float *d_log_weights;
+    float *d_latents;
+    double *d_ess_trace;
+    uint8_t *d_resampled;
+    int32_t *d_ancestors;
+    int64_t max_events;
+} ppl_batch_result;
+
+/* Workspace bytes for a batched run with configuration `tune` (NULL: enough
+ * for every configuration the autotuner tries). */
+int ppl_smc_batched_workspace_size(int model, int32_t n_inst, const ppl_instance *h_inst, const ppl_tune *tune,
+                                   size_t *bytes);
+
+/* Batched SMC over n_inst independent mixture-model instances in one
+ * persistent cooperative launch (same per-instance algorithm and outputs as
+ * ppl_smc).  tune NULL: the autotuner's cached choice for this batch shape,
+ * else the defaults.  model: PPL_MODEL_GMM.  n_inst in 1..1024. */
+int ppl_smc_batched(int model, int32_t n_inst, const ppl_instance *h_inst, const ppl_instance *d_inst,
+                    uint64_t seed, double ess_frac, const ppl_tune *tune, void *d_ws, size_t ws_bytes,
+                    void *stream, ppl_batch_result *out);
+
+/* Autotuner: times each candidate configuration once on this batch (after a
+ * warm-up run, synchronising the stream), returns the fastest in *best and
+ * caches it for batches of the same shape (instance count, particle and data
+ * totals, largest instance).  Writes the outputs like ppl_smc_batched. */
+int ppl_smc_autotune(int model, int32_t n_inst, const ppl_instance *h_inst, const ppl_instance *d_inst,
+                     uint64_t seed, double ess_frac, void *d_ws, size_t ws_bytes, void *stream,
+                     ppl_batch_result *out, ppl_tune *best);
+
 /* Kernel timing (a measurement aid).  ppl_timing_enable(1) clears the
  * accumulators and makes the launchers bracket their dominant kernels
  * (blr_is_kernel, poly_is_kernel, smc kernels) with HIP events recorded on

@@ -198,3 +198,106 @@ def ppl_timing_query(kernel):
     ms, n = ctypes.c_double(), ctypes.c_int64()
     _check(lib.ppl_timing_query(kernel.encode(), ctypes.byref(ms), ctypes.byref(n)))
     return ms.value, n.value
+
+
+# ----------------------------------------------------------- batched SMC --
+class PplInstance(ctypes.Structure):
+    _fields_ = [("y", P), ("n_data", ctypes.c_int64), ("n_particles", ctypes.c_int64), ("dim", ctypes.c_int32),
+                ("reserved", ctypes.c_int32), ("hyper", ctypes.c_double * 2)]
+
+
+class PplTune(ctypes.Structure):
+    _fields_ = [("particles_per_lane", ctypes.c_int32), ("wgs_per_instance", ctypes.c_int32),
+                ("spec_block", ctypes.c_int32), ("reserved", ctypes.c_int32)]
+
+
+class PplBatchResult(ctypes.Structure):
+    _fields_ = [("d_out", P), ("d_log_weights", P), ("d_latents", P), ("d_ess_trace", P), ("d_resampled", P),
+                ("d_ancestors", P), ("max_events", ctypes.c_int64)]
+
+
+def _bind_batched():
+    L = lib
+    L.ppl_smc_batched_workspace_size.argtypes = [ctypes.c_int, ctypes.c_int32, ctypes.POINTER(PplInstance),
+                                                 ctypes.POINTER(PplTune), ctypes.POINTER(ctypes.c_size_t)]
+    L.ppl_smc_batched.argtypes = [ctypes.c_int, ctypes.c_int32, ctypes.POINTER(PplInstance), P, ctypes.c_uint64,
+                                  ctypes.c_double, ctypes.POINTER(PplTune), P, ctypes.c_size_t, P,
+                                  ctypes.POINTER(PplBatchResult)]
+    L.ppl_smc_autotune.argtypes = [ctypes.c_int, ctypes.c_int32, ctypes.POINTER(PplInstance), P, ctypes.c_uint64,
+                                   ctypes.c_double, P, ctypes.c_size_t, P, ctypes.POINTER(PplBatchResult),
+                                   ctypes.POINTER(PplTune)]
+    for n in ("ppl_smc_batched_workspace_size", "ppl_smc_batched", "ppl_smc_autotune"):
+        getattr(L, n).restype = ctypes.c_int
+
+
+_bind_batched()
+EXPORTS = EXPORTS + ("ppl_smc_batched_workspace_size", "ppl_smc_batched", "ppl_smc_autotune")
+
+
+class InstanceTable:
+    """Host and device copies of a ppl_instance table (the device copy holds the same bytes)."""
+
+    def __init__(self, ys, ks, n_particles, hypers=None, device="cuda"):
+        n = len(ys)
+        self.host = (PplInstance * n)()
+        self._ys = ys                                  # keep the device observation tensors alive
+        for i, (y, k) in enumerate(zip(ys, ks)):
+            h = hypers[i] if hypers is not None else (0.0, 0.0)
+            np_ = n_particles[i] if hasattr(n_particles, "__len__") else n_particles
+            self.host[i] = PplInstance(y=y.data_ptr() if y.numel() else None, n_data=y.numel(), n_particles=int(np_),
+                                       dim=int(k), reserved=0, hyper=(ctypes.c_double * 2)(*h))
+        raw = bytes(self.host)
+        self.device = torch.frombuffer(bytearray(raw), dtype=torch.uint8).to(device)
+        self.n = n
+
+    @property
+    def n_particles(self):
+        return [self.host[i].n_particles for i in range(self.n)]
+
+    @property
+    def n_data(self):
+        return [self.host[i].n_data for i in range(self.n)]
+
+
+def _tune_ptr(tune):
+    if tune is None:
+        return None, None
+    t = PplTune(*[int(v) for v in tune]) if not isinstance(tune, PplTune) else tune
+    return ctypes.byref(t), t
+
+
+def ppl_smc_batched_workspace_size(model, table, tune=None):
+    b = ctypes.c_size_t()
+    tp, _keep = _tune_ptr(tune)
+    _check(lib.ppl_smc_batched_workspace_size(model, table.n, table.host, tp, ctypes.byref(b)))
+    return b.value
+
+
+def ppl_smc_batched(model, table, seed, ess_frac=0.5, tune=None, ws=None, stream=None, out=None, log_weights=None,
+                    latents=None, ess_trace=None, resampled=None, ancestors=None, max_events=0):
+    """Batched SMC; returns the [n_inst, 4] FP64 device tensor (log Z, ESS, resamplings, status)."""
+    if ws is None:
+        ws = workspace(ppl_smc_batched_workspace_size(model, table, tune))
+    if out is None:
+        out = torch.empty((table.n, 4), dtype=torch.float64, device=ws.device)
+    res = PplBatchResult(d_out=_ptr(out), d_log_weights=_ptr(log_weights), d_latents=_ptr(latents),
+                         d_ess_trace=_ptr(ess_trace), d_resampled=_ptr(resampled), d_ancestors=_ptr(ancestors),
+                         max_events=int(max_events) if ancestors is not None else 0)
+    tp, _keep = _tune_ptr(tune)
+    _check(lib.ppl_smc_batched(model, table.n, table.host, _ptr(table.device), int(seed) & (2 ** 64 - 1),
+                               float(ess_frac), tp, _ptr(ws), ws.numel(), _stream(stream), ctypes.byref(res)))
+    return out
+
+
+def ppl_smc_autotune(model, table, seed, ess_frac=0.5, ws=None, stream=None, out=None):
+    """Times the candidate configurations on this batch; returns the chosen (P, W, spec_block)."""
+    if ws is None:
+        ws = workspace(ppl_smc_batched_workspace_size(model, table, None))
+    if out is None:
+        out = torch.empty((table.n, 4), dtype=torch.float64, device=ws.device)
+    res = PplBatchResult(d_out=_ptr(out))
+    best = PplTune()
+    _check(lib.ppl_smc_autotune(model, table.n, table.host, _ptr(table.device), int(seed) & (2 ** 64 - 1),
+                                float(ess_frac), _ptr(ws), ws.numel(), _stream(stream), ctypes.byref(res),
+                                ctypes.byref(best)))
+    return (best.particles_per_lane, best.wgs_per_instance, best.spec_block)

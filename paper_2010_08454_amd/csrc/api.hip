@@ -6,8 +6,13 @@
 #include <stdio.h>
 #include <string.h>
 
+#include <algorithm>
 #include <atomic>
+#include <map>
+#include <mutex>
+#include <tuple>
 
+#include "batched.h"
 #include "host.h"
 #include "kernels.h"
 #include "smc.h"
@@ -281,6 +286,127 @@ int ppl_smc(int model, const ppl_data *data, int64_t n, uint64_t seed, double es
     hipStream_t st = (hipStream_t)stream;
     if (int rc = run_smc(a, st)) return rc;
     if (out->sync_host) return sync_scalars(out, smc_scalars_ptr(a), st);
+    return PPL_OK;
+}
+
+// ------------------------------------------------------------ batched SMC --
+namespace {
+// Candidate configurations the autotuner times (the workspace covers them all).
+const ppl_tune kCandidates[] = {
+    {4, 0, 64, 0}, {4, 0, 128, 0}, {2, 0, 64, 0}, {2, 0, 128, 0}, {8, 0, 64, 0}, {1, 0, 64, 0}, {4, 0, 16, 0},
+};
+constexpr int kNumCandidates = sizeof(kCandidates) / sizeof(kCandidates[0]);
+
+struct BatchKey {
+    int n;
+    int64_t sum_n, sum_d, max_n;
+    bool operator<(const BatchKey &o) const {
+        return std::tie(n, sum_n, sum_d, max_n) < std::tie(o.n, o.sum_n, o.sum_d, o.max_n);
+    }
+};
+std::mutex g_tune_mu;
+std::map<BatchKey, ppl_tune> g_tune_cache;
+
+BatchKey batch_key(int n, const ppl_instance *h) {
+    BatchKey k{n, 0, 0, 0};
+    for (int i = 0; i < n; ++i) {
+        k.sum_n += h[i].n_particles;
+        k.sum_d += h[i].n_data * h[i].dim;
+        k.max_n = std::max<int64_t>(k.max_n, h[i].n_particles);
+    }
+    return k;
+}
+
+int check_batch_args(int model, int32_t n, const ppl_instance *h, const ppl_instance *d, double ess_frac) {
+    if (int rc = bt_check(model, n, h)) return rc;
+    if (!d) return fail(PPL_E_ARG, "device instance table is NULL");
+    if (!(ess_frac >= 0.0 && ess_frac <= 1.0)) return fail(PPL_E_ARG, "ess_frac must be in [0, 1]");
+    return PPL_OK;
+}
+}  // namespace
+
+int ppl_smc_batched_workspace_size(int model, int32_t n, const ppl_instance *h, const ppl_tune *tune, size_t *bytes) {
+    clear_error();
+    if (!bytes) return fail(PPL_E_ARG, "bytes is NULL");
+    if (int rc = bt_check(model, n, h)) return rc;
+    size_t need = 0;
+    if (tune) {
+        need = bt_ws_bytes_for(h, n, tune);
+        if (!need) return fail(PPL_E_ARG, "configuration does not fit these instances");
+    } else {
+        need = bt_ws_bytes_for(h, n, nullptr);
+        for (const ppl_tune &c : kCandidates) need = std::max(need, bt_ws_bytes_for(h, n, &c));
+        if (!need) return fail(PPL_E_UNSUPPORTED, "no configuration fits these instances");
+    }
+    *bytes = need;
+    return PPL_OK;
+}
+
+int ppl_smc_batched(int model, int32_t n, const ppl_instance *h, const ppl_instance *d, uint64_t seed,
+                    double ess_frac, const ppl_tune *tune, void *ws, size_t ws_bytes, void *stream,
+                    ppl_batch_result *out) {
+    clear_error();
+    if (!out) return fail(PPL_E_ARG, "out is NULL");
+    if (int rc = check_batch_args(model, n, h, d, ess_frac)) return rc;
+    ppl_tune cached{};
+    if (!tune) {
+        std::lock_guard<std::mutex> lk(g_tune_mu);
+        auto it = g_tune_cache.find(batch_key(n, h));
+        if (it != g_tune_cache.end()) {
+            cached = it->second;
+            tune = &cached;
+        }
+    }
+    const size_t need = bt_ws_bytes_for(h, n, tune);
+    if (!need) return fail(PPL_E_ARG, "configuration does not fit these instances");
+    if (int rc = check_ws(ws, ws_bytes, need)) return rc;
+    if (int rc = check_device()) return rc;
+    return run_smc_batched(n, h, d, seed, ess_frac, tune, ws, ws_bytes, (hipStream_t)stream, *out, nullptr);
+}
+
+int ppl_smc_autotune(int model, int32_t n, const ppl_instance *h, const ppl_instance *d, uint64_t seed,
+                     double ess_frac, void *ws, size_t ws_bytes, void *stream, ppl_batch_result *out,
+                     ppl_tune *best) {
+    clear_error();
+    if (!out || !best) return fail(PPL_E_ARG, "out and best must be non-NULL");
+    if (int rc = check_batch_args(model, n, h, d, ess_frac)) return rc;
+    if (int rc = check_ws(ws, ws_bytes, 256)) return rc;
+    if (int rc = check_device()) return rc;
+    hipStream_t st = (hipStream_t)stream;
+    hipEvent_t e0, e1;
+    PPL_HIP(hipEventCreate(&e0));
+    PPL_HIP(hipEventCreate(&e1));
+    float best_ms = -1.0f;
+    ppl_tune best_cfg{};
+    int rc = PPL_OK;
+    for (int c = 0; c < kNumCandidates && rc == PPL_OK; ++c) {
+        const size_t need = bt_ws_bytes_for(h, n, &kCandidates[c]);
+        if (!need || need > ws_bytes) continue;
+        ppl_tune used{};
+        rc = run_smc_batched(n, h, d, seed, ess_frac, &kCandidates[c], ws, ws_bytes, st, *out, &used);
+        if (rc == PPL_E_UNSUPPORTED) { rc = PPL_OK; continue; }     // does not fit the device
+        if (rc) break;
+        if (hipEventRecord(e0, st) != hipSuccess) { rc = fail(PPL_E_HIP, "hipEventRecord failed"); break; }
+        rc = run_smc_batched(n, h, d, seed, ess_frac, &kCandidates[c], ws, ws_bytes, st, *out, &used);
+        if (rc) break;
+        float ms = 0.0f;
+        if (hipEventRecord(e1, st) != hipSuccess || hipEventSynchronize(e1) != hipSuccess ||
+            hipEventElapsedTime(&ms, e0, e1) != hipSuccess) {
+            rc = fail(PPL_E_HIP, "autotune timing failed");
+            break;
+        }
+        if (best_ms < 0.0f || ms < best_ms) {
+            best_ms = ms;
+            best_cfg = used;
+        }
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    if (rc) return rc;
+    if (best_ms < 0.0f) return fail(PPL_E_UNSUPPORTED, "no candidate configuration fits the workspace and device");
+    *best = best_cfg;
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    g_tune_cache[batch_key(n, h)] = best_cfg;
     return PPL_OK;
 }
 

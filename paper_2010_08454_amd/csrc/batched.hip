@@ -1,0 +1,752 @@
+// batched.hip -- many SMC instances in one persistent cooperative launch.
+//
+// Each instance is a mixture model with its own data and particle count; the
+// per-instance algorithm is the SMC of smc.hip (the particle method the paper
+// names as future work, Sec. 6, over the sample/factor semantics of Sec. 3.4).
+//
+// Mapping.  The grid (one 1024-thread workgroup per CU) is split into teams of
+// W workgroups; a team holds one instance at a time (slots j = w * 1024 P +
+// thread * P + p, P particles per thread, state in registers) and walks a list
+// of instances assigned on the host by longest-processing-time-first, so the
+// makespan is balanced.  Teams never wait on each other.
+//
+// Speculative blocks.  A team advances its particles through up to B factors
+// before synchronising: after each factor every wave records {max, sum e,
+// sum e^2} of its particles in LDS; at the end of the block the workgroups
+// publish per-factor partials, meet at a team barrier, and every workgroup
+// merges them in the same order.  The first factor t* whose ESS falls below
+// ess_frac N decides: if there is none the block is committed (B doubles up to
+// the tuned maximum); otherwise the log-weights are rolled back to the block
+// start, the factors up to t* are recomputed (the same FP32 operations in the
+// same order, so the result is bit-identical to a factor-by-factor run), the
+// particles are resampled at t* with the integer rule of ppl_resample, and the
+// next block starts at t* + 1 with B = 1.
+#include <math.h>
+#include <string.h>
+
+#include <algorithm>
+#include <atomic>
+#include <map>
+#include <mutex>
+#include <vector>
+
+#include "device.h"
+#include "host.h"
+#include "timing.h"
+#include "batched.h"
+
+namespace ppl {
+
+constexpr int kBtThreads = 1024;
+constexpr int kBtWaves = kBtThreads / 64;
+constexpr int kBtMaxInst = 1024;
+constexpr int kBtMaxTeams = 256;
+constexpr int kBtMaxB = 128;                  // largest speculative block
+constexpr int kBtMaxW = 64;                   // largest team
+constexpr int kBtStage = 8192;                // prefix sums staged for the ancestor search
+constexpr int kBtNF = 16;                     // state floats per particle (2 K, K <= 8)
+constexpr uint32_t kBtSpinLimit = 1u << 24;
+constexpr int kBtBarLine = 32;
+
+struct BtDev {
+    const ppl_instance *inst;
+    int n_inst;
+    Key key;
+    float ess_frac;
+    int W;                   // workgroups per team
+    int Bmax;                // speculative block limit
+    int stage_cap;
+    int64_t cap;             // slots per team (W * 1024 * P)
+    double *out;             // [n_inst][4]
+    float *lw_out, *lat_out;
+    double *ess_tr;
+    uint8_t *res_tr;
+    int32_t *anc_out;        // [max_events * sum N], instance i at max_events * P_i as [max_events][N_i]
+    int64_t max_events;
+    unsigned *bar;          // [1 + teams] lines: line 0 word 1 = abort flag; line 1 + t = team t counter
+    double *part;            // [teams][W][Bmax][3]
+    uint64_t *tot;           // [teams][W]
+    double *esum;            // [teams][W]
+    double *fin;             // [teams][W][2]
+    uint64_t *qloc;          // [teams][cap]
+    float *xbuf;             // [teams][NF][cap]
+    uint16_t order[kBtMaxInst];           // instances in scheduling order
+    uint16_t team_off[kBtMaxTeams + 1];   // team t runs order[team_off[t] .. team_off[t+1])
+};
+
+// ------------------------------------------------------------ barrier ----
+__device__ __forceinline__ bool team_barrier(unsigned *bar, int team, unsigned target) {
+    __shared__ int s_ok;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        unsigned *ctr = &bar[kBtBarLine * (1 + team)];
+        __hip_atomic_fetch_add(ctr, 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+        uint32_t spins = 0;
+        int ok = 1;
+        while (__hip_atomic_load(ctr, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < target) {
+            __builtin_amdgcn_s_sleep(1);
+            if ((++spins & 63) == 0) {
+                if (__hip_atomic_load(&bar[1], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) { ok = 0; break; }
+                if (spins > kBtSpinLimit) {
+                    __hip_atomic_store(&bar[1], 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                    ok = 0;
+                    break;
+                }
+            }
+        }
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+        if (ok && __hip_atomic_load(&bar[1], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) ok = 0;
+        s_ok = ok;
+    }
+    __syncthreads();
+    return s_ok != 0;
+}
+
+__device__ __noinline__ double bt_log(double v) { return log(v); }
+__device__ __noinline__ double bt_exp(double v) { return exp(v); }
+
+// --------------------------------------------------------------- model ----
+// Mixture with K <= 8 known components, runtime K.  State: log pi_k (k < K),
+// mu_k at [8 + k].  Prior draws as in the single-instance SMC.
+struct BtGmm {
+    __device__ static void init(uint32_t j, uint32_t c3, Key key, int K, float mu_sd, float st[kBtNF]) {
+        const uint4 w0 = philox(j, 0, 0, c3, key), w1 = philox(j, 1, 0, c3, key);
+        const uint32_t w[8] = {w0.x, w0.y, w0.z, w0.w, w1.x, w1.y, w1.z, w1.w};
+        float E[8], tot = 0.0f;
+#pragma unroll
+        for (int k = 0; k < 8; ++k) {
+            E[k] = k < K ? -logf(unit_f32(w[k])) : 0.0f;
+            tot += E[k];
+        }
+        float z[8];
+        normals4(philox(j, 2, 0, c3, key), z);
+        normals4(philox(j, 3, 0, c3, key), z + 4);
+#pragma unroll
+        for (int k = 0; k < 8; ++k) {
+            st[k] = k < K ? logf(E[k] / tot) : -INFINITY;
+            st[8 + k] = mu_sd * z[k];
+        }
+    }
+    // log sum_k pi_k N(y; mu_k, sd), shifted by the largest term.
+    __device__ static float factor(const float st[kBtNF], int K, float inv_sd, float lconst, float ys) {
+        float t[8], mx = -INFINITY;
+#pragma unroll
+        for (int k = 0; k < 8; ++k) {
+            if (k < K) {
+                const float r = (ys - st[8 + k]) * inv_sd;
+                t[k] = fmaf(-0.5f * r, r, st[k]);
+                mx = fmaxf(mx, t[k]);
+            }
+        }
+        float s = 0.0f;
+#pragma unroll
+        for (int k = 0; k < 8; ++k)
+            if (k < K) s += expf(t[k] - mx);
+        return lconst + mx + logf(s);
+    }
+};
+
+// --------------------------------------------------------- LDS helpers ----
+__device__ __forceinline__ float bt_block_max(float v, float *lds) {
+    v = wave_max(v);
+    if ((threadIdx.x & 63) == 0) lds[threadIdx.x >> 6] = v;
+    __syncthreads();
+    float m = lds[0];
+#pragma unroll
+    for (int w = 1; w < kBtWaves; ++w) m = fmaxf(m, lds[w]);
+    __syncthreads();
+    return m;
+}
+
+__device__ __forceinline__ void bt_block_sum2(double &u, double &v, double *lds) {
+    u = wave_sum(u);
+    v = wave_sum(v);
+    if ((threadIdx.x & 63) == 0) {
+        lds[threadIdx.x >> 6] = u;
+        lds[kBtWaves + (threadIdx.x >> 6)] = v;
+    }
+    __syncthreads();
+    double a = 0.0, b = 0.0;
+#pragma unroll
+    for (int w = 0; w < kBtWaves; ++w) {
+        a += lds[w];
+        b += lds[kBtWaves + w];
+    }
+    __syncthreads();
+    u = a;
+    v = b;
+}
+
+__device__ __forceinline__ uint64_t bt_block_exscan(uint64_t v, uint64_t *lds, uint64_t &total) {
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    uint64_t incl = v;
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) {
+        const uint64_t t = __shfl_up(incl, o, 64);
+        if (lane >= o) incl += t;
+    }
+    if (lane == 63) lds[wv] = incl;
+    __syncthreads();
+    uint64_t off = 0, tot = 0;
+#pragma unroll
+    for (int w = 0; w < kBtWaves; ++w) {
+        const uint64_t x = lds[w];
+        if (w < wv) off += x;
+        tot += x;
+    }
+    __syncthreads();
+    total = tot;
+    return off + incl - v;
+}
+
+// ---------------------------------------------------------------- kernel --
+template <int P>
+__global__ __launch_bounds__(kBtThreads) void smc_batched_kernel(BtDev a) {
+    __shared__ float ldsf[kBtWaves];
+    __shared__ double ldsd[2 * kBtWaves];
+    __shared__ uint64_t ldsu[kBtWaves];
+    __shared__ float ybuf[kBtMaxB];
+    __shared__ float wpart[kBtMaxB][kBtWaves][3];     // per-factor wave partials {max, s1, s2}
+    __shared__ float sM[kBtMaxB];                      // merged max per factor
+    __shared__ unsigned char sBad[kBtMaxB];            // 1: all weights zero, 2: NaN
+    __shared__ int s_first;                            // first triggering factor in the block
+    __shared__ int s_rng[2];
+    __shared__ uint64_t tile_end[kBtMaxW], tile_pre[kBtMaxW];
+    extern __shared__ uint64_t dyn[];                  // stage[stage_cap] | s_anc[1024 P]
+    uint64_t *stage = dyn;
+    int32_t *s_anc = (int32_t *)(dyn + a.stage_cap);
+
+    const int W = a.W;
+    const int team = blockIdx.x / W, wg = blockIdx.x % W;
+    constexpr int kTile = kBtThreads * P;
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    unsigned epoch = 0;
+    bool alive = true;
+
+    double *tpart = a.part + (size_t)team * W * a.Bmax * 3;
+    uint64_t *ttot = a.tot + (size_t)team * W;
+    double *tesum = a.esum + (size_t)team * W;
+    double *tfin = a.fin + (size_t)team * W * 2;
+    uint64_t *tq = a.qloc + (size_t)team * a.cap;
+    float *tx = a.xbuf + (size_t)team * kBtNF * a.cap;
+
+    for (int idx = a.team_off[team]; idx < a.team_off[team + 1] && alive; ++idx) {
+        const int i = a.order[idx];
+        const ppl_instance I = a.inst[i];
+        const int64_t N = I.n_particles, D = I.n_data;
+        const int K = I.dim;
+        const float mu_sd = I.hyper[0] > 0 ? (float)I.hyper[0] : 5.0f;
+        const double comp_sd = I.hyper[1] > 0 ? I.hyper[1] : 1.0;
+        const float inv_sd = (float)(1.0 / comp_sd);
+        const float lconst = (float)(-0.5 * log(2.0 * M_PI) - log(comp_sd));
+        const uint32_t c3 = ((uint32_t)i << 8) | kTagPrior;
+        // particle and data offsets of this instance in the concatenated outputs
+        int64_t poff = 0, doff = 0;
+        for (int k = 0; k < i; ++k) {
+            poff += a.inst[k].n_particles;
+            doff += a.inst[k].n_data;
+        }
+        int c = 0;
+        while (((int64_t)1 << c) < N) ++c;
+        const int kbits = 62 - c;
+        const double logN = bt_log((double)N);
+
+        const int jb0 = wg * kTile + threadIdx.x * P;
+        float st[P][kBtNF];
+        float lw[P];
+        bool valid[P];
+#pragma unroll
+        for (int p = 0; p < P; ++p) {
+            valid[p] = jb0 + p < N;
+            BtGmm::init((uint32_t)(jb0 + p), c3, a.key, K, mu_sd, st[p]);
+            lw[p] = valid[p] ? 0.0f : -INFINITY;
+        }
+
+        double logz = 0.0;
+        int64_t nres = 0;
+        int status = 0;
+        float Mlast = 0.0f;
+        int64_t t0 = 0;
+        int B = 1;
+        while (t0 < D) {
+            const int tb = (int)std::min<int64_t>(B, D - t0);
+            __syncthreads();
+            for (int t = threadIdx.x; t < tb; t += kBtThreads) ybuf[t] = I.y[t0 + t];
+            __syncthreads();
+            // block-start log-weights, kept in LDS for a rollback (the ancestor
+            // area is free until resampling, which only starts after the rollback)
+            float *s_lw0 = (float *)s_anc;
+#pragma unroll
+            for (int p = 0; p < P; ++p) s_lw0[threadIdx.x * P + p] = lw[p];
+            for (int t = 0; t < tb; ++t) {
+                const float ys = ybuf[t];
+                float ml = -INFINITY;
+                int nan_seen = 0;
+#pragma unroll
+                for (int p = 0; p < P; ++p) {
+                    const float f = BtGmm::factor(st[p], K, inv_sd, lconst, ys);
+                    if (valid[p]) lw[p] += f;
+                    ml = fmaxf(ml, lw[p]);
+                    nan_seen |= isnan(lw[p]) ? 1 : 0;
+                }
+                const float mw = wave_max(ml);
+                float s1 = 0.0f, s2 = 0.0f;
+                if (mw > -INFINITY) {
+#pragma unroll
+                    for (int p = 0; p < P; ++p) {
+                        const float e = expf(lw[p] - mw);
+                        s1 += e;
+                        s2 = fmaf(e, e, s2);
+                    }
+                }
+#pragma unroll
+                for (int o = 32; o > 0; o >>= 1) {
+                    s1 += __shfl_xor(s1, o, 64);
+                    s2 += __shfl_xor(s2, o, 64);
+                }
+                if (wave_or(nan_seen)) s1 = NAN;      // a NaN log-weight poisons the factor's statistics
+                if (lane == 0) {
+                    wpart[t][wave][0] = mw;
+                    wpart[t][wave][1] = s1;
+                    wpart[t][wave][2] = s2;
+                }
+            }
+            __syncthreads();
+            // workgroup partial per factor: merge the waves in order
+            for (int t = threadIdx.x; t < tb; t += kBtThreads) {
+                float m = -INFINITY;
+                for (int w = 0; w < kBtWaves; ++w) m = fmaxf(m, wpart[t][w][0]);
+                double s1 = 0.0, s2 = 0.0;
+                if (m > -INFINITY) {
+                    for (int w = 0; w < kBtWaves; ++w) {
+                        const float cw = expf(wpart[t][w][0] - m);
+                        s1 += (double)wpart[t][w][1] * cw;
+                        s2 += (double)wpart[t][w][2] * (double)(cw * cw);
+                    }
+                }
+                double *dst = tpart + ((size_t)wg * a.Bmax + t) * 3;
+                dst[0] = (double)m;
+                dst[1] = s1;
+                dst[2] = s2;
+            }
+            if (!team_barrier(a.bar, team, ++epoch * (unsigned)W)) { alive = false; break; }
+            // team merge per factor (same order in every workgroup) and the trigger
+            if (threadIdx.x == 0) s_first = tb;
+            __syncthreads();
+            for (int t = threadIdx.x; t < tb; t += kBtThreads) {
+                float m = -INFINITY;
+                for (int w = 0; w < W; ++w) m = fmaxf(m, (float)tpart[((size_t)w * a.Bmax + t) * 3]);
+                double s1 = 0.0, s2 = 0.0;
+                if (m > -INFINITY) {
+                    for (int w = 0; w < W; ++w) {
+                        const double *src = tpart + ((size_t)w * a.Bmax + t) * 3;
+                        const float cw = expf((float)src[0] - m);
+                        s1 += src[1] * cw;
+                        s2 += src[2] * (double)(cw * cw);
+                    }
+                }
+                sM[t] = m;
+                const double ess = s1 * s1 / s2;
+                const bool bad = !(m > -INFINITY) || !(s1 > 0.0) || isnan(s1) || isnan(s2);
+                sBad[t] = bad ? (m > -INFINITY ? 2 : 1) : 0;
+                const bool trig = bad || ((t0 + t < D - 1) && ess < (double)a.ess_frac * (double)N);
+                if (wg == 0 && a.ess_tr) a.ess_tr[doff + t0 + t] = bad ? 0.0 : ess;
+                if (trig) atomicMin(&s_first, t);
+            }
+            __syncthreads();
+            const int tf = s_first;
+            if (tf == tb) {                    // no trigger: commit the block
+                if (wg == 0 && a.res_tr)
+                    for (int t = threadIdx.x; t < tb; t += kBtThreads) a.res_tr[doff + t0 + t] = 0;
+                Mlast = sM[tb - 1];
+                t0 += tb;
+                B = std::min(2 * B, a.Bmax);
+                continue;
+            }
+            const float Mg = sM[tf];
+            if (sBad[tf]) {                    // the same verdict in every workgroup of the team
+                status = sBad[tf] == 1 ? PPL_E_ZERO_WEIGHT : PPL_E_NONFINITE;
+                break;
+            }
+            if (wg == 0 && a.res_tr)
+                for (int t = threadIdx.x; t <= tf; t += kBtThreads) a.res_tr[doff + t0 + t] = t == tf ? 1 : 0;
+            // roll back to the block start and recompute up to factor tf
+            if (tf < tb - 1) {
+#pragma unroll
+                for (int p = 0; p < P; ++p) lw[p] = s_lw0[threadIdx.x * P + p];
+                for (int t = 0; t <= tf; ++t) {
+                    const float ys = ybuf[t];
+#pragma unroll
+                    for (int p = 0; p < P; ++p) {
+                        const float f = BtGmm::factor(st[p], K, inv_sd, lconst, ys);
+                        if (valid[p]) lw[p] += f;
+                    }
+                }
+            }
+            // ---- resampling at factor s = t0 + tf
+            const int64_t s = t0 + tf;
+            uint64_t q[P];
+            uint64_t run = 0;
+            double esl = 0.0;
+#pragma unroll
+            for (int p = 0; p < P; ++p) {
+                const double e = valid[p] ? bt_exp((double)lw[p] - (double)Mg) : 0.0;
+                esl += e;
+                if (e >= 0.0) run += (uint64_t)floor(ldexp(e, kbits));
+                q[p] = run;
+            }
+            uint64_t btot;
+            const uint64_t off = bt_block_exscan(run, ldsu, btot);
+            double eb = esl, unused = 0.0;
+            bt_block_sum2(eb, unused, ldsd);
+            int jb = jb0;
+            asm volatile("" : "+v"(jb));
+#pragma unroll
+            for (int p = 0; p < P; ++p) {
+                if (valid[p]) {
+                    tq[jb + p] = off + q[p];
+#pragma unroll
+                    for (int f = 0; f < kBtNF; ++f) tx[(size_t)f * a.cap + jb + p] = st[p][f];
+                }
+            }
+            if (threadIdx.x == 0) {
+                ttot[wg] = btot;
+                tesum[wg] = eb;
+            }
+            if (!team_barrier(a.bar, team, ++epoch * (unsigned)W)) { alive = false; break; }
+            {
+                const uint64_t v = threadIdx.x < W ? ttot[threadIdx.x] : 0;
+                double ev = threadIdx.x < W ? tesum[threadIdx.x] : 0.0, zero = 0.0;
+                uint64_t S;
+                const uint64_t ex = bt_block_exscan(v, ldsu, S);
+                if (threadIdx.x < W) {
+                    tile_pre[threadIdx.x] = ex;
+                    tile_end[threadIdx.x] = ex + v;
+                }
+                bt_block_sum2(ev, zero, ldsd);
+                const uint4 rw = philox(0, 0, (uint32_t)s, ((uint32_t)i << 8) | kTagResample, a.key);
+                const uint64_t U = __umul64hi(((uint64_t)rw.y << 32) | rw.x, S);
+                logz += (double)Mg + bt_log(ev) - logN;
+                ++nres;
+                const uint64_t NN = (uint64_t)N;
+                const uint64_t Sq = S / NN, Sr = S - Sq * NN;
+                // ancestors: min{a : Q_a > tau_j}, tau_j = j Sq + floor((j Sr + U) / N)
+                const int js0 = wg * kTile;
+                const int js1 = (int)std::min<int64_t>((int64_t)js0 + kTile, N) - 1;
+                if (js0 < N) {
+                    for (int e = 0; e < 2; ++e) {
+                        if (threadIdx.x == 64 * e) {
+                            const int jj = e ? js1 : js0;
+                            const uint64_t num = (uint64_t)jj * Sr + U;
+                            const uint64_t tau = (uint64_t)jj * Sq + num / NN;
+                            int lo = 0, hi = W - 1;
+                            while (lo < hi) {
+                                const int mid = (lo + hi) >> 1;
+                                if (tile_end[mid] > tau) hi = mid; else lo = mid + 1;
+                            }
+                            int a0 = lo * kTile, a1 = (int)std::min<int64_t>((int64_t)a0 + kTile, N) - 1;
+                            while (a0 < a1) {
+                                const int mid = (a0 + a1) >> 1;
+                                if (tile_pre[lo] + tq[mid] > tau) a1 = mid; else a0 = mid + 1;
+                            }
+                            s_rng[e] = a0;
+                        }
+                    }
+                }
+                __syncthreads();
+                if (js0 < N) {
+                    const int a_lo = s_rng[0], a_hi = s_rng[1];
+                    const int span = a_hi - a_lo + 1;
+                    const bool staged = span <= a.stage_cap;
+                    int32_t *anc_row = (a.anc_out && nres - 1 < a.max_events)
+                                           ? a.anc_out + (size_t)a.max_events * poff + (size_t)(nres - 1) * N
+                                           : nullptr;
+                    if (staged)
+                        for (int k = threadIdx.x; k < span; k += kBtThreads) {
+                            const int aa = a_lo + k;
+                            stage[k] = tile_pre[aa / kTile] + tq[aa];
+                        }
+                    __syncthreads();
+                    int prev = a_lo;
+                    uint64_t num = (uint64_t)jb * Sr + U;
+                    uint64_t quo = num / NN, rem = num - quo * NN;
+#pragma unroll 1
+                    for (int p = 0; p < P; ++p) {
+                        const int j = jb + p;
+                        if (j >= N) break;
+                        if (p) {
+                            rem += Sr;
+                            if (rem >= NN) { rem -= NN; ++quo; }
+                        }
+                        const uint64_t tau = (uint64_t)j * Sq + quo;
+                        int anc;
+                        if (staged) {
+                            int lo = prev - a_lo, hi = span - 1;
+                            while (lo < hi) {
+                                const int mid = (lo + hi) >> 1;
+                                if (stage[mid] > tau) hi = mid; else lo = mid + 1;
+                            }
+                            anc = a_lo + lo;
+                        } else {
+                            int lo = prev / kTile, hi = W - 1;
+                            while (lo < hi) {
+                                const int mid = (lo + hi) >> 1;
+                                if (tile_end[mid] > tau) hi = mid; else lo = mid + 1;
+                            }
+                            int a0 = std::max(lo * kTile, prev), a1 = (int)std::min<int64_t>((int64_t)lo * kTile + kTile, N) - 1;
+                            while (a0 < a1) {
+                                const int mid = (a0 + a1) >> 1;
+                                if (tile_pre[lo] + tq[mid] > tau) a1 = mid; else a0 = mid + 1;
+                            }
+                            anc = a0;
+                        }
+                        s_anc[threadIdx.x * P + p] = anc;
+                        if (anc_row) anc_row[j] = anc;
+                        prev = anc;
+                    }
+                } else {
+                    __syncthreads();
+                }
+            }
+#pragma unroll
+            for (int p = 0; p < P; ++p) {
+                if (!valid[p]) continue;
+                const int anc = s_anc[threadIdx.x * P + p];
+#pragma unroll
+                for (int f = 0; f < kBtNF; ++f) st[p][f] = tx[(size_t)f * a.cap + anc];
+                lw[p] = 0.0f;
+            }
+            t0 = s + 1;
+            B = 1;
+        }
+
+        // ---- final normaliser over the last epoch
+        double ess_final = (double)N;
+        if (alive && status == 0 && D > 0) {
+            double e1 = 0.0, e2 = 0.0;
+#pragma unroll
+            for (int p = 0; p < P; ++p) {
+                if (valid[p]) {
+                    const double e = bt_exp((double)lw[p] - (double)Mlast);
+                    e1 += e;
+                    e2 += e * e;
+                }
+            }
+            bt_block_sum2(e1, e2, ldsd);
+            if (threadIdx.x == 0) {
+                tfin[2 * wg] = e1;
+                tfin[2 * wg + 1] = e2;
+            }
+            if (!team_barrier(a.bar, team, ++epoch * (unsigned)W)) {
+                alive = false;
+            } else {
+                double t1 = threadIdx.x < W ? tfin[2 * threadIdx.x] : 0.0;
+                double t2 = threadIdx.x < W ? tfin[2 * threadIdx.x + 1] : 0.0;
+                bt_block_sum2(t1, t2, ldsd);
+                logz += (double)Mlast + bt_log(t1) - logN;
+                ess_final = t1 * t1 / t2;
+            }
+        }
+        if (!alive) status = PPL_E_HIP;
+        // outputs
+#pragma unroll
+        for (int p = 0; p < P; ++p) {
+            if (!valid[p]) continue;
+            const int64_t j = jb0 + p;
+            if (a.lw_out) a.lw_out[poff + j] = lw[p];
+            if (a.lat_out) {
+#pragma unroll
+                for (int k = 0; k < 8; ++k) {
+                    if (k < K) {
+                        a.lat_out[(size_t)kBtNF * poff + (size_t)k * N + j] = st[p][k];
+                        a.lat_out[(size_t)kBtNF * poff + (size_t)(K + k) * N + j] = st[p][8 + k];
+                    }
+                }
+            }
+        }
+        if (wg == 0 && threadIdx.x == 0) {
+            double *o = a.out + 4 * (size_t)i;
+            o[0] = status ? (status == PPL_E_ZERO_WEIGHT ? -INFINITY : NAN) : logz;
+            o[1] = status ? 0.0 : ess_final;
+            o[2] = (double)nres;
+            o[3] = (double)status;
+        }
+        // all workgroups of the team leave the instance together before its buffers are reused
+        if (alive && !team_barrier(a.bar, team, ++epoch * (unsigned)W)) alive = false;
+    }
+}
+
+__global__ void smc_batched_reset_kernel(unsigned *bar, int words) {
+    for (int i = threadIdx.x; i < words; i += blockDim.x) bar[i] = 0u;
+}
+
+// ------------------------------------------------------------------ host --
+struct BtLayout {
+    unsigned *bar;
+    double *part, *esum, *fin;
+    uint64_t *tot, *qloc;
+    float *xbuf;
+    size_t bytes;
+};
+
+static BtLayout bt_layout(void *ws, int teams, int W, int Bmax, int64_t cap) {
+    BtLayout L;
+    char *p = (char *)ws;
+    size_t o = 0;
+    auto take = [&](size_t n) { char *r = p + o; o += align_up(n, 256); return r; };
+    L.bar = (unsigned *)take((size_t)kBtBarLine * (1 + teams) * sizeof(unsigned));
+    L.part = (double *)take((size_t)teams * W * Bmax * 3 * sizeof(double));
+    L.esum = (double *)take((size_t)teams * W * sizeof(double));
+    L.fin = (double *)take((size_t)teams * W * 2 * sizeof(double));
+    L.tot = (uint64_t *)take((size_t)teams * W * sizeof(uint64_t));
+    L.qloc = (uint64_t *)take((size_t)teams * cap * sizeof(uint64_t));
+    L.xbuf = (float *)take((size_t)teams * kBtNF * cap * sizeof(float));
+    L.bytes = o;
+    return L;
+}
+
+static int device_cus(int &ncu) {
+    int dev = 0;
+    PPL_HIP(hipGetDevice(&dev));
+    PPL_HIP(hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev));
+    return PPL_OK;
+}
+
+// Resolved configuration: P and W chosen so that a team covers the largest instance.
+static int bt_resolve(const ppl_instance *h, int n, const ppl_tune *tune, int ncu, ppl_tune &cfg, int &teams,
+                      int64_t &cap) {
+    int64_t nmax = 1;
+    for (int i = 0; i < n; ++i) nmax = std::max<int64_t>(nmax, h[i].n_particles);
+    cfg.particles_per_lane = tune && tune->particles_per_lane ? tune->particles_per_lane : 4;
+    cfg.spec_block = tune && tune->spec_block ? tune->spec_block : 64;
+    const int P = cfg.particles_per_lane;
+    if (P != 1 && P != 2 && P != 4 && P != 8) return fail(PPL_E_ARG, "particles_per_lane must be 1, 2, 4 or 8");
+    if (cfg.spec_block < 1 || cfg.spec_block > kBtMaxB) return fail(PPL_E_ARG, "spec_block must be in 1..%d", kBtMaxB);
+    const int64_t need = (nmax + (int64_t)kBtThreads * P - 1) / ((int64_t)kBtThreads * P);
+    int W = tune && tune->wgs_per_instance ? tune->wgs_per_instance : (int)need;
+    if (W < need) return fail(PPL_E_ARG, "wgs_per_instance %d cannot hold %lld particles at %d per lane", W,
+                              (long long)nmax, P);
+    if (W > kBtMaxW || W > ncu) return fail(PPL_E_UNSUPPORTED, "an instance of %lld particles needs %d workgroups",
+                                            (long long)nmax, W);
+    cfg.wgs_per_instance = W;
+    teams = std::min(ncu / W, kBtMaxTeams);
+    teams = std::max(1, std::min(teams, n));
+    cap = (int64_t)W * kBtThreads * P;
+    return PPL_OK;
+}
+
+size_t bt_ws_bytes_for(const ppl_instance *h, int n, const ppl_tune *tune) {
+    int ncu = 256;
+    if (device_cus(ncu) != PPL_OK) ncu = 256;
+    ppl_tune cfg;
+    int teams;
+    int64_t cap;
+    if (bt_resolve(h, n, tune, ncu, cfg, teams, cap) != PPL_OK) return 0;
+    return bt_layout(nullptr, teams, cfg.wgs_per_instance, cfg.spec_block, cap).bytes;
+}
+
+int bt_check(int model, int n, const ppl_instance *h) {
+    if (model != PPL_MODEL_GMM) return fail(PPL_E_MODEL, "batched SMC supports the mixture model (got %d)", model);
+    if (n < 1 || n > kBtMaxInst) return fail(PPL_E_ARG, "n_inst must be in 1..%d", kBtMaxInst);
+    if (!h) return fail(PPL_E_ARG, "host instance table is NULL");
+    for (int i = 0; i < n; ++i) {
+        const ppl_instance &I = h[i];
+        if (I.n_particles < 1 || I.n_particles > (1LL << 30)) return fail(PPL_E_ARG, "instance %d: bad particle count", i);
+        if (I.n_data < 0 || I.n_data > 0x7fffffffLL) return fail(PPL_E_ARG, "instance %d: bad data length", i);
+        if (I.n_data > 0 && !I.y) return fail(PPL_E_ARG, "instance %d: y is NULL", i);
+        if (I.dim < 1 || I.dim > 8) return fail(PPL_E_ARG, "instance %d: K must be in 1..8", i);
+        if (!(I.hyper[0] >= 0) || !(I.hyper[1] >= 0) || !isfinite(I.hyper[0]) || !isfinite(I.hyper[1]))
+            return fail(PPL_E_ARG, "instance %d: hyper-parameters must be finite and non-negative (0 = default)", i);
+    }
+    return PPL_OK;
+}
+
+template <int P>
+static int bt_launch(BtDev &d, int nblocks, hipStream_t st) {
+    auto kern = smc_batched_kernel<P>;
+    int dev = 0, ncu = 0, occ = 0, max_lds = 0;
+    PPL_HIP(hipGetDevice(&dev));
+    PPL_HIP(hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev));
+    PPL_HIP(hipDeviceGetAttribute(&max_lds, hipDeviceAttributeMaxSharedMemoryPerBlock, dev));
+    hipFuncAttributes fa;
+    PPL_HIP(hipFuncGetAttributes(&fa, (const void *)kern));
+    const int64_t fixed = (int64_t)fa.sharedSizeBytes + (int64_t)kBtThreads * P * sizeof(int32_t);
+    d.stage_cap = (int)std::max<int64_t>(0, std::min<int64_t>(kBtStage, (max_lds - fixed) / 8));
+    const size_t lds = (size_t)d.stage_cap * sizeof(uint64_t) + (size_t)kBtThreads * P * sizeof(int32_t);
+    PPL_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, kern, kBtThreads, lds));
+    if ((int64_t)occ * ncu < nblocks)
+        return fail(PPL_E_UNSUPPORTED, "batched SMC needs %d co-resident workgroups, device holds %d", nblocks, occ * ncu);
+    void *args[] = {&d};
+    KernelTimer timer("smc_batched_kernel", st);
+    PPL_HIP(hipLaunchCooperativeKernel((const void *)kern, dim3((unsigned)nblocks), dim3(kBtThreads), args, lds, st));
+    timer.stop();
+    return PPL_OK;
+}
+
+int run_smc_batched(int n, const ppl_instance *h, const ppl_instance *d_inst, uint64_t seed, double ess_frac,
+                    const ppl_tune *tune, void *ws, size_t ws_bytes, hipStream_t st, const ppl_batch_result &out,
+                    ppl_tune *used) {
+    int ncu = 0;
+    if (int rc = device_cus(ncu)) return rc;
+    ppl_tune cfg;
+    int teams;
+    int64_t cap;
+    if (int rc = bt_resolve(h, n, tune, ncu, cfg, teams, cap)) return rc;
+    const int W = cfg.wgs_per_instance;
+    BtLayout L = bt_layout(ws, teams, W, cfg.spec_block, cap);
+    if (ws_bytes < L.bytes) return fail(PPL_E_WORKSPACE, "workspace has %zu bytes, %zu needed", ws_bytes, L.bytes);
+    // longest-processing-time-first assignment of instances to teams
+    std::vector<int> ord(n);
+    for (int i = 0; i < n; ++i) ord[i] = i;
+    auto work = [&](int i) { return (double)h[i].n_particles * (double)h[i].n_data * (h[i].dim + 2); };
+    std::stable_sort(ord.begin(), ord.end(), [&](int x, int y) { return work(x) > work(y); });
+    std::vector<std::vector<int>> lists(teams);
+    std::vector<double> load(teams, 0.0);
+    for (int i : ord) {
+        const int t = (int)(std::min_element(load.begin(), load.end()) - load.begin());
+        lists[t].push_back(i);
+        load[t] += work(i) + 1.0;
+    }
+    static_assert(sizeof(BtDev) <= 4096, "kernel argument block too large");
+    BtDev d{};
+    int pos = 0;
+    for (int t = 0; t < teams; ++t) {
+        d.team_off[t] = (uint16_t)pos;
+        for (int i : lists[t]) d.order[pos++] = (uint16_t)i;
+    }
+    d.team_off[teams] = (uint16_t)pos;
+    d.inst = d_inst;
+    d.n_inst = n;
+    d.key = make_key(seed);
+    d.ess_frac = (float)ess_frac;
+    d.W = W;
+    d.Bmax = cfg.spec_block;
+    d.cap = cap;
+    d.out = out.d_out;
+    d.lw_out = out.d_log_weights;
+    d.lat_out = out.d_latents;
+    d.ess_tr = out.d_ess_trace;
+    d.res_tr = out.d_resampled;
+    d.anc_out = out.d_ancestors;
+    d.max_events = out.d_ancestors ? out.max_events : 0;
+    d.bar = L.bar;
+    d.part = L.part;
+    d.tot = L.tot;
+    d.esum = L.esum;
+    d.fin = L.fin;
+    d.qloc = L.qloc;
+    d.xbuf = L.xbuf;
+    hipLaunchKernelGGL(smc_batched_reset_kernel, dim3(1), dim3(256), 0, st, L.bar, kBtBarLine * (1 + teams));
+    PPL_LAUNCH_CHECK("smc_batched_reset_kernel");
+    if (used) *used = cfg;
+    const int nblocks = teams * W;
+    switch (cfg.particles_per_lane) {
+        case 1: return bt_launch<1>(d, nblocks, st);
+        case 2: return bt_launch<2>(d, nblocks, st);
+        case 4: return bt_launch<4>(d, nblocks, st);
+        case 8: return bt_launch<8>(d, nblocks, st);
+    }
+    return fail(PPL_E_ARG, "particles_per_lane must be 1, 2, 4 or 8");
+}
+
+}  // namespace ppl
