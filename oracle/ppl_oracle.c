@@ -602,6 +602,334 @@ void or_gmm_init(uint64_t seed, uint32_t inst, int32_t K, const double *hyper,
     }
 }
 
+/* ------------------------------------------------ learned proposal: data -- */
+/* Training pairs are simulated from the model's own prior (Philox tag 4,
+ * counter (sample i, block, training step t, 4)):
+ *   POLY: block 0 word 0 -> n; blocks 1, 2 -> eight single-precision normals,
+ *         c_j = sd z_j; points come in pairs: block 8 + e gives x_{2e}, x_{2e+1}
+ *         = 2u - 1 from words 0, 1 and a Box-Muller pair from words 2, 3 for the
+ *         observation noise; y = sum_{j<n} c_j x^j + noise_sd * eps.
+ *   GMM:  blocks 0, 1 -> Exp(1) draws E_k, pi = E / sum E; blocks 2, 3 -> mu_k =
+ *         mu_sd z_k; block 8 + e gives the components of points 2e, 2e+1 from
+ *         words 0, 1 (categorical on pi) and their noise from words 2, 3. */
+enum { TAG_TRAIN = 4 };
+#define SUMM 64
+
+static int categorical(double u, const double *p, int K)
+{
+    double c = 0.0;
+    for (int k = 0; k < K; ++k) { c += p[k]; if (u < c) return k; }
+    return K - 1;
+}
+
+/* Cholesky solve of the n x n SPD system G beta = m (in place on copies). */
+static void chol_solve(int n, const double *G, const double *m, double *beta)
+{
+    double L[5][5] = {{0}};
+    for (int i = 0; i < n; ++i)
+        for (int j = 0; j <= i; ++j) {
+            double s = G[i * 5 + j];
+            for (int k = 0; k < j; ++k) s -= L[i][k] * L[j][k];
+            L[i][j] = (i == j) ? sqrt(s > 1e-300 ? s : 1e-300) : s / L[j][j];
+        }
+    double z[5];
+    for (int i = 0; i < n; ++i) { double s = m[i]; for (int k = 0; k < i; ++k) s -= L[i][k] * z[k]; z[i] = s / L[i][i]; }
+    for (int i = n - 1; i >= 0; --i) { double s = z[i]; for (int k = i + 1; k < n; ++k) s -= L[k][i] * beta[k]; beta[i] = s / L[i][i]; }
+}
+
+/* POLY summary statistics (64 slots, 42 used):
+ *   [0..7]   (1/D) sum x^j y / 10, j = 0..7
+ *   [8..21]  (1/D) sum x^k, k = 1..14
+ *   [22]     (1/D) sum y^2 / 100
+ *   [23..36] least-squares coefficients for n = 2, 3, 4, 5 (n values each) / 10
+ *   [37..40] log(RSS_n / D + 1e-3) / 10, RSS_n / D = (1/D) sum y^2 - beta_n . m_n
+ *   [41]     log(D) / 10 */
+void or_summary_poly(const double *x, const double *y, int64_t D, double *s)
+{
+    for (int k = 0; k < SUMM; ++k) s[k] = 0.0;
+    if (D <= 0) return;
+    double mxy[8] = {0}, gx[15] = {0}, syy = 0.0;
+    for (int64_t d = 0; d < D; ++d) {
+        double p = 1.0;
+        for (int k = 0; k <= 14; ++k) {
+            if (k < 8) mxy[k] += p * y[d];
+            gx[k] += p;
+            p *= x[d];
+        }
+        syy += y[d] * y[d];
+    }
+    for (int k = 0; k < 8; ++k) mxy[k] /= (double)D;
+    for (int k = 0; k <= 14; ++k) gx[k] /= (double)D;
+    syy /= (double)D;
+    for (int j = 0; j < 8; ++j) s[j] = mxy[j] / 10.0;
+    for (int k = 1; k <= 14; ++k) s[7 + k] = gx[k];
+    s[22] = syy / 100.0;
+    int o = 23;
+    for (int n = 2; n <= 5; ++n) {
+        double G[25], beta[5];
+        for (int i = 0; i < n; ++i) for (int j = 0; j < n; ++j) G[i * 5 + j] = gx[i + j];
+        chol_solve(n, G, mxy, beta);
+        double fit = 0.0;
+        for (int j = 0; j < n; ++j) { s[o + j] = beta[j] / 10.0; fit += beta[j] * mxy[j]; }
+        double rss = syy - fit;
+        if (rss < 0.0) rss = 0.0;
+        s[37 + n - 2] = log(rss + 1e-3) / 10.0;
+        o += n;
+    }
+    s[41] = log((double)D) / 10.0;
+}
+
+static int cmp_double(const void *a, const void *b)
+{
+    double x = *(const double *)a, y = *(const double *)b;
+    return (x > y) - (x < y);
+}
+
+/* GMM summary statistics (64 slots, 53 used):
+ *   [0..15]  order statistics y_(floor((q + 1/2) D / 16)) / 10, q = 0..15
+ *   [16..47] histogram of y on unit bins over [-16, 16) (ends clamped), / D
+ *   [48] mean / 10, [49] sd / 10, [50] skewness, [51] excess kurtosis / 10,
+ *   [52] log(D) / 10 */
+void or_summary_gmm(const double *y, int64_t D, double *s)
+{
+    for (int k = 0; k < SUMM; ++k) s[k] = 0.0;
+    if (D <= 0) return;
+    double *v = (double *)malloc(sizeof(double) * D);
+    memcpy(v, y, sizeof(double) * D);
+    qsort(v, D, sizeof(double), cmp_double);
+    for (int q = 0; q < 16; ++q) s[q] = v[(int64_t)floor((q + 0.5) * (double)D / 16.0)] / 10.0;
+    free(v);
+    double m1 = 0.0;
+    for (int64_t d = 0; d < D; ++d) {
+        int b = (int)floor(y[d] + 16.0);
+        if (b < 0) b = 0;
+        if (b > 31) b = 31;
+        s[16 + b] += 1.0;
+        m1 += y[d];
+    }
+    for (int b = 0; b < 32; ++b) s[16 + b] /= (double)D;
+    m1 /= (double)D;
+    double c2 = 0.0, c3 = 0.0, c4 = 0.0;
+    for (int64_t d = 0; d < D; ++d) { double r = y[d] - m1; c2 += r * r; c3 += r * r * r; c4 += r * r * r * r; }
+    c2 /= (double)D; c3 /= (double)D; c4 /= (double)D;
+    double sd = sqrt(c2);
+    s[48] = m1 / 10.0;
+    s[49] = sd / 10.0;
+    s[50] = c2 > 0 ? c3 / (c2 * sd) : 0.0;
+    s[51] = c2 > 0 ? (c4 / (c2 * c2) - 3.0) / 10.0 : 0.0;
+    s[52] = log((double)D) / 10.0;
+}
+
+/* One POLY training pair: theta = (n, c_0..c_4), summaries s[64].
+ * hyper = {sd, n_lo, n_hi, noise_sd}. */
+void or_sim_poly(uint64_t seed, uint32_t step, int64_t i0, int64_t B, int64_t D, const double *hyper,
+                 double *theta, double *summ)
+{
+#pragma omp parallel for schedule(dynamic, 16)
+    for (int64_t b = 0; b < B; ++b) {
+        uint32_t i = (uint32_t)(i0 + b), w[4];
+        draw4(seed, i, 0, step, 0, TAG_TRAIN, w);
+        int n = (int)or_uniform_discrete(w[0], (int64_t)hyper[1], (int64_t)hyper[2]);
+        double z[8];
+        draw4(seed, i, 1, step, 0, TAG_TRAIN, w); normals4_single(w, z);
+        draw4(seed, i, 2, step, 0, TAG_TRAIN, w); normals4_single(w, z + 4);
+        double c[5];
+        for (int j = 0; j < 5; ++j) c[j] = hyper[0] * z[j];
+        double *x = (double *)malloc(sizeof(double) * D), *y = (double *)malloc(sizeof(double) * D);
+        for (int64_t d = 0; d < D; d += 2) {
+            draw4(seed, i, (uint32_t)(8 + d / 2), step, 0, TAG_TRAIN, w);
+            double e0, e1;
+            or_box_muller(or_u01_single(w[2]), or_u01_single(w[3]), &e0, &e1);
+            for (int h = 0; h < 2 && d + h < D; ++h) {
+                double xv = 2.0 * or_u01_single(w[h]) - 1.0, p = 0.0;
+                for (int j = n - 1; j >= 0; --j) p = p * xv + c[j];
+                x[d + h] = xv;
+                y[d + h] = p + hyper[3] * (h ? e1 : e0);
+            }
+        }
+        theta[b * 6] = n;
+        for (int j = 0; j < 5; ++j) theta[b * 6 + 1 + j] = j < n ? c[j] : 0.0;
+        or_summary_poly(x, y, D, summ + b * SUMM);
+        free(x); free(y);
+    }
+}
+
+/* One GMM training pair: latents in the ordered unconstrained space
+ * u = (mu_(1), log(mu_(k) - mu_(k-1)) for k = 2..K, log pi_(k) - log pi_(K) for
+ * k = 1..K-1) (2K - 1 values), summaries s[64].  hyper = {mu_sd, comp_sd}. */
+void or_sim_gmm(uint64_t seed, uint32_t step, int64_t i0, int64_t B, int64_t D, int32_t K, const double *hyper,
+                double *u, double *summ)
+{
+#pragma omp parallel for schedule(dynamic, 16)
+    for (int64_t b = 0; b < B; ++b) {
+        uint32_t i = (uint32_t)(i0 + b), w[8], v[4];
+        draw4(seed, i, 0, step, 0, TAG_TRAIN, w);
+        draw4(seed, i, 1, step, 0, TAG_TRAIN, w + 4);
+        double E[8], tot = 0.0, pi[8], mu[8], z[8];
+        for (int k = 0; k < K; ++k) { E[k] = -log(or_u01_single(w[k])); tot += E[k]; }
+        for (int k = 0; k < K; ++k) pi[k] = E[k] / tot;
+        draw4(seed, i, 2, step, 0, TAG_TRAIN, v); normals4_single(v, z);
+        draw4(seed, i, 3, step, 0, TAG_TRAIN, v); normals4_single(v, z + 4);
+        for (int k = 0; k < K; ++k) mu[k] = hyper[0] * z[k];
+        double *y = (double *)malloc(sizeof(double) * D);
+        for (int64_t d = 0; d < D; d += 2) {
+            draw4(seed, i, (uint32_t)(8 + d / 2), step, 0, TAG_TRAIN, v);
+            double e0, e1;
+            or_box_muller(or_u01_single(v[2]), or_u01_single(v[3]), &e0, &e1);
+            for (int h = 0; h < 2 && d + h < D; ++h) {
+                int k = categorical(or_u01_single(v[h]), pi, K);
+                y[d + h] = mu[k] + hyper[1] * (h ? e1 : e0);
+            }
+        }
+        /* sort components by mean (insertion sort, ties keep index order) */
+        int ord[8] = {0, 1, 2, 3, 4, 5, 6, 7};
+        for (int a = 1; a < K; ++a)
+            for (int c = a; c > 0 && mu[ord[c]] < mu[ord[c - 1]]; --c) { int t = ord[c]; ord[c] = ord[c - 1]; ord[c - 1] = t; }
+        double *ub = u + b * (2 * K - 1);
+        ub[0] = mu[ord[0]];
+        for (int k = 1; k < K; ++k) ub[k] = log(mu[ord[k]] - mu[ord[k - 1]]);
+        for (int k = 0; k < K - 1; ++k) ub[K + k] = log(pi[ord[k]]) - log(pi[ord[K - 1]]);
+        or_summary_gmm(y, D, summ + b * SUMM);
+        free(y);
+    }
+}
+
+/* -------------------------------------------- learned proposal: weights -- */
+static double log_normal(double v, double m, double lsd)
+{
+    double r = (v - m) * exp(-lsd);
+    return -0.5 * r * r - lsd - 0.5 * log(2.0 * M_PI);
+}
+
+static double lse(const double *v, int n)
+{
+    double m = -INFINITY;
+    for (int k = 0; k < n; ++k) if (v[k] > m) m = v[k];
+    if (!(m > -INFINITY)) return -INFINITY;
+    double s = 0.0;
+    for (int k = 0; k < n; ++k) s += exp(v[k] - m);
+    return m + log(s);
+}
+
+/* log q(n, c) of the POLY proposal: params = {lognl[4] (log-softmax of the degree
+ * logits), logmix[8] (log-softmax of the mixture logits), mean[4][8][5], lsd[4][8][5]}. */
+double or_poly_logq(const double *params, int n, const double *c)
+{
+    const double *lnl = params, *lmix = params + 4, *mean = params + 12, *lsd = params + 12 + 160;
+    double t[8];
+    for (int m = 0; m < 8; ++m) {
+        t[m] = lmix[m];
+        for (int j = 0; j < n; ++j)
+            t[m] += log_normal(c[j], mean[((n - 2) * 8 + m) * 5 + j], lsd[((n - 2) * 8 + m) * 5 + j]);
+    }
+    return lnl[n - 2] + lse(t, 8);
+}
+
+/* Importance weights of the POLY model under the proposal (PROPOSAL stream:
+ * block 0 words 0, 1 -> degree and component; blocks 1, 2 -> normals; c_j =
+ * mean + exp(lsd) z_j in single precision as drawn, then everything in FP64):
+ * lw = log p(n, c) + log L(c) - log q(n, c).  hyper = {sd, n_lo, n_hi}. */
+void or_propose_poly(uint64_t seed, const double *params, const double *x, const double *y, int64_t D,
+                     const double *hyper, int64_t m, const int64_t *idx, double *lw, double *draw /* [m][6] */)
+{
+#pragma omp parallel for schedule(dynamic, 1)
+    for (int64_t r = 0; r < m; ++r) {
+        uint32_t i = (uint32_t)idx[r], w[4];
+        draw4(seed, i, 0, 0, 0, TAG_PROPOSAL, w);
+        double pn[4], pm[8];
+        for (int k = 0; k < 4; ++k) pn[k] = exp(params[k]);
+        for (int k = 0; k < 8; ++k) pm[k] = exp(params[4 + k]);
+        int n = 2 + categorical(or_u01_single(w[0]), pn, 4);
+        int comp = categorical(or_u01_single(w[1]), pm, 8);
+        double z[8], c[5];
+        draw4(seed, i, 1, 0, 0, TAG_PROPOSAL, w); normals4_single(w, z);
+        draw4(seed, i, 2, 0, 0, TAG_PROPOSAL, w); normals4_single(w, z + 4);
+        for (int j = 0; j < 5; ++j) {
+            const double *mean = params + 12, *lsd = params + 12 + 160;
+            int o = ((n - 2) * 8 + comp) * 5 + j;
+            c[j] = j < n ? mean[o] + exp(lsd[o]) * z[j] : 0.0;
+        }
+        double lp = -log(4.0);
+        for (int j = 0; j < n; ++j) lp += log_normal(c[j], 0.0, log(hyper[0]));
+        lw[r] = lp + or_poly_loglik(n, c, x, y, D) - or_poly_logq(params, n, c);
+        draw[r * 6] = n;
+        for (int j = 0; j < 5; ++j) draw[r * 6 + 1 + j] = c[j];
+    }
+}
+
+/* GMM (K components) proposal over the ordered unconstrained latents u (2K - 1):
+ * params = {logmix[8], mean[8][2K-1], lsd[8][2K-1]}. */
+double or_gmm_logq(const double *params, int32_t K, const double *u)
+{
+    const int d = 2 * K - 1;
+    const double *lmix = params, *mean = params + 8, *lsd = params + 8 + 8 * d;
+    double t[8];
+    for (int m = 0; m < 8; ++m) {
+        t[m] = lmix[m];
+        for (int i = 0; i < d; ++i) t[m] += log_normal(u[i], mean[m * d + i], lsd[m * d + i]);
+    }
+    return lse(t, 8);
+}
+
+/* Map u to (log pi, mu) and return the prior density of u:
+ * log p(u) = log (K-1)! [Dirichlet(1)] + log K! [ordering] + sum_k log N(mu_k; 0, mu_sd)
+ *          + sum_{k>=2} u_k [d mu / d gaps] + sum_k log pi_k [softmax Jacobian]. */
+double or_gmm_unpack(const double *u, int32_t K, double mu_sd, double *lpi, double *mu)
+{
+    mu[0] = u[0];
+    for (int k = 1; k < K; ++k) mu[k] = mu[k - 1] + exp(u[k]);
+    double lg[8];
+    for (int k = 0; k < K - 1; ++k) lg[k] = u[K + k];
+    lg[K - 1] = 0.0;
+    double z = lse(lg, K);
+    double lp = lgamma((double)K) + lgamma((double)K + 1.0);
+    for (int k = 0; k < K; ++k) {
+        lpi[k] = lg[k] - z;
+        lp += log_normal(mu[k], 0.0, log(mu_sd)) + lpi[k];
+        if (k >= 1) lp += u[k];
+    }
+    return lp;
+}
+
+/* Importance weights of the GMM model under the proposal (PROPOSAL stream:
+ * block 0 word 0 -> component; blocks 1..3 -> normals):
+ * lw = log p(u) + log L(u) - log q(u).  hyper = {mu_sd, comp_sd}. */
+void or_propose_gmm(uint64_t seed, const double *params, int32_t K, const double *y, int64_t D,
+                    const double *hyper, int64_t m, const int64_t *idx, double *lw, double *draw /* [m][2K-1] */)
+{
+    const int dim = 2 * K - 1;
+#pragma omp parallel for schedule(dynamic, 1)
+    for (int64_t r = 0; r < m; ++r) {
+        uint32_t i = (uint32_t)idx[r], w[4];
+        draw4(seed, i, 0, 0, 0, TAG_PROPOSAL, w);
+        double pm[8], z[12], u[15], lpi[8], mu[8];
+        for (int k = 0; k < 8; ++k) pm[k] = exp(params[k]);
+        int comp = categorical(or_u01_single(w[0]), pm, 8);
+        for (int b = 0; b < 3; ++b) { draw4(seed, i, (uint32_t)(1 + b), 0, 0, TAG_PROPOSAL, w); normals4_single(w, z + 4 * b); }
+        for (int k = 0; k < dim; ++k) u[k] = params[8 + comp * dim + k] + exp(params[8 + 8 * dim + comp * dim + k]) * z[k];
+        double lp = or_gmm_unpack(u, K, hyper[0], lpi, mu);
+        double ll = 0.0;
+        for (int64_t d = 0; d < D; ++d) ll += or_gmm_logfactor(K, lpi, mu, hyper[1], y[d]);
+        lw[r] = lp + ll - or_gmm_logq(params, K, u);
+        for (int k = 0; k < dim; ++k) draw[r * dim + k] = u[k];
+    }
+}
+
+/* Prior-proposal importance weights of the GMM model (PRIOR stream, the same
+ * draws as the SMC initial particles): lw = log L(pi, mu). */
+void or_gmm_prior_lw(uint64_t seed, int32_t K, const double *hyper, const double *y, int64_t D, int64_t m,
+                     const int64_t *idx, double *lw)
+{
+#pragma omp parallel for schedule(dynamic, 1)
+    for (int64_t r = 0; r < m; ++r) {
+        double lpi[8], mu[8];
+        gmm_init_particle(seed, idx[r], 0, K, hyper, lpi, mu);
+        double ll = 0.0;
+        for (int64_t d = 0; d < D; ++d) ll += or_gmm_logfactor(K, lpi, mu, hyper[1], y[d]);
+        lw[r] = ll;
+    }
+}
+
 int or_num_threads(void)
 {
 #ifdef _OPENMP
