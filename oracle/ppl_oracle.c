@@ -892,7 +892,7 @@ double or_gmm_unpack(const double *u, int32_t K, double mu_sd, double *lpi, doub
 }
 
 /* Importance weights of the GMM model under the proposal (PROPOSAL stream:
- * block 0 word 0 -> component; blocks 1..3 -> normals):
+ * block 0 word 0 -> component; blocks 1..4 -> sixteen normals, z_k for u_k):
  * lw = log p(u) + log L(u) - log q(u).  hyper = {mu_sd, comp_sd}. */
 void or_propose_gmm(uint64_t seed, const double *params, int32_t K, const double *y, int64_t D,
                     const double *hyper, int64_t m, const int64_t *idx, double *lw, double *draw /* [m][2K-1] */)
@@ -902,10 +902,10 @@ void or_propose_gmm(uint64_t seed, const double *params, int32_t K, const double
     for (int64_t r = 0; r < m; ++r) {
         uint32_t i = (uint32_t)idx[r], w[4];
         draw4(seed, i, 0, 0, 0, TAG_PROPOSAL, w);
-        double pm[8], z[12], u[15], lpi[8], mu[8];
+        double pm[8], z[16], u[15], lpi[8], mu[8];
         for (int k = 0; k < 8; ++k) pm[k] = exp(params[k]);
         int comp = categorical(or_u01_single(w[0]), pm, 8);
-        for (int b = 0; b < 3; ++b) { draw4(seed, i, (uint32_t)(1 + b), 0, 0, TAG_PROPOSAL, w); normals4_single(w, z + 4 * b); }
+        for (int b = 0; b < 4; ++b) { draw4(seed, i, (uint32_t)(1 + b), 0, 0, TAG_PROPOSAL, w); normals4_single(w, z + 4 * b); }
         for (int k = 0; k < dim; ++k) u[k] = params[8 + comp * dim + k] + exp(params[8 + 8 * dim + comp * dim + k]) * z[k];
         double lp = or_gmm_unpack(u, K, hyper[0], lpi, mu);
         double ll = 0.0;

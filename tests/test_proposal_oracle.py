@@ -198,3 +198,29 @@ def test_gmm_proposal_weights_agree_with_prior_is(pr):
     (a, ea), (b, eb) = est(lw), est(lp)
     assert ea > 1000 and eb > 100
     assert abs(a - b) < 4 * math.sqrt(1 / ea + 1 / eb)
+
+
+def test_glorot_init_is_uniform_within_bounds(pr):
+    """Weights are U(-a, a) with a = sqrt(6 / (in + out)) (variance 2 / (in + out)); biases zero."""
+    params = pr.init_params(3)
+    for l, (o, i) in enumerate(pr.SHAPES):
+        W, b = params[2 * l], params[2 * l + 1]
+        a = math.sqrt(6.0 / (i + o))
+        assert W.shape == (o, i) and np.all(b == 0)
+        assert np.all(np.abs(W) < a * (1 + 1e-6))
+        assert stats.kstest(W.ravel() / a, "uniform", args=(-1, 2)).pvalue > 1e-3
+        assert abs(W.var() / (2.0 / (i + o)) - 1) < 0.05
+
+
+def test_adam_with_a_constant_gradient_moves_lr_per_step(pr):
+    """Bias-corrected Adam under a constant gradient g: m_t / (1 - b1^t) = g and
+    v_t / (1 - b2^t) = g^2 at every step, so each step moves p by lr g / (|g| + eps)."""
+    g = [np.array([[3.0, -2e-3], [0.5, -7.0]]), np.array([1e-4, -40.0])]
+    p = [np.zeros((2, 2)), np.zeros(2)]
+    m = [np.zeros_like(x) for x in p]
+    v = [np.zeros_like(x) for x in p]
+    lr, eps = 1e-3, 1e-8
+    for t in range(1, 6):
+        p, m, v = pr.adam(p, g, m, v, t, lr=lr, eps=eps)
+        for pk, gk in zip(p, g):
+            np.testing.assert_allclose(pk, -t * lr * gk / (np.abs(gk) + eps), rtol=1e-10)
