@@ -28,8 +28,9 @@
  *     lives at [f * n_particles + i].
  *   - Random numbers: Philox4x32-10 (Salmon et al., SC'11) keyed by `seed`;
  *     counter = (particle or slot index, block index, step, instance << 8 | tag)
- *     with tags 0 = prior, 1 = proposal, 2 = resampling.  Results depend only
- *     on (seed, inputs), never on the launch configuration.
+ *     with tags 0 = prior, 1 = proposal, 2 = resampling, 4 = simulated
+ *     training pairs, 5 = network initialisation.  Results depend only on
+ *     (seed, inputs), never on the launch configuration.
  */
 #ifndef PPL_H
 #define PPL_H
@@ -128,12 +129,27 @@ typedef struct ppl_result {
 } ppl_result;
 
 /* Proposal for importance sampling (NULL or kind PPL_Q_PRIOR: the prior,
- * i.e. likelihood weighting).
+ * i.e. likelihood weighting).  Latents are drawn from the proposal stream
+ * (tag 1) and each log-weight is log p + log L - log q.
  * PPL_Q_GAUSS_FULL (BLR): d_params = float32 [d] mean followed by [d][d]
  *   row-major lower-triangular Cholesky factor L (positive diagonal);
- *   w = mean + L z with z ~ N(0, I) from the proposal stream, and each
- *   log-weight gains log p(w) - log q(w). */
-enum { PPL_Q_PRIOR = 0, PPL_Q_GAUSS_FULL = 1 };
+ *   w = mean + L z with z ~ N(0, I); dim = d.
+ * PPL_Q_POLY_MIX (POLY with degrees 2..5): d_params = float64 [332]:
+ *   lognl[4] (log-probabilities of n = 2..5), logmix[8] (log mixture weights),
+ *   mean[4][8][5], lsd[4][8][5] (log-scales), indexed [n - 2][component][j];
+ *   block 0 word 0 picks n and word 1 the component by inverse CDF, blocks 1, 2
+ *   give eight normals (single-precision-stream Box-Muller), c_j = mean +
+ *   exp(lsd) z_j for j < n; q(n, c) = P(n) sum_m w_m prod_j N(c_j; mean, e^lsd).
+ *   dim = 5.
+ * PPL_Q_GMM_MIX (GMM, K components): d_params = float64 [8 + 16 (2K - 1)]:
+ *   logmix[8], mean[8][2K-1], lsd[8][2K-1] over the ordered unconstrained
+ *   latents u = (mu_(1), log(mu_(k) - mu_(k-1)) for k = 2..K,
+ *   log pi_(k) - log pi_(K) for k = 1..K-1); block 0 word 0 picks the
+ *   component, blocks 1..4 give sixteen normals.  log p(u) includes log (K-1)!
+ *   (Dirichlet(1)), log K! (the orderings) and the Jacobians of the gap and
+ *   softmax maps.  dim = 2K - 1.
+ * These two are what ppl_proposal_infer decodes from the network output. */
+enum { PPL_Q_PRIOR = 0, PPL_Q_GAUSS_FULL = 1, PPL_Q_POLY_MIX = 2, PPL_Q_GMM_MIX = 3 };
 typedef struct ppl_proposal {
     int32_t kind;
     int32_t dim;
@@ -153,11 +169,15 @@ int ppl_workspace_size(int model, const ppl_data *data, int64_t n_particles, int
  * each execution's sample/factor calls give it a log-weight; the FP64
  * log-sum-exp normaliser gives log Z-hat = LSE(lw) - log N and
  * ESS = (sum w)^2 / sum w^2.
- * model: PPL_MODEL_POLY or PPL_MODEL_BLR.  n_particles in [1, 2^31).
+ * model: PPL_MODEL_POLY, PPL_MODEL_BLR or PPL_MODEL_GMM.  n_particles in [1, 2^31).
+ * GMM importance sampling runs in FP64 (data float32, upcast exactly); its
+ * latents are float64 [2K][N] (log pi_k, mu_k) and its prior draws are those
+ * of the SMC initial particles.
  * d_summaries (FP64):
  *   POLY: [0..3] P(n = 2..5 | y); [4 + 5(n-2) + j] E[c_j | n, y] (0 where that
  *         degree has no mass); [24 + j] E[c_j 1{j < n} | y]        -> 29 values
- *   BLR:  [0..d-1] E[w | y]                                          -> d values */
+ *   BLR:  [0..d-1] E[w | y]                                          -> d values
+ *   GMM:  [k] E[mu_(k) | y], the k-th smallest mean, k < K           -> 8 values */
 int ppl_importance(int model, const ppl_data *data, int64_t n_particles, uint64_t seed,
                    const ppl_proposal *q, void *d_ws, size_t ws_bytes, void *stream,
                    ppl_result *out);
@@ -261,6 +281,87 @@ int ppl_smc_batched(int model, int32_t n_inst, const ppl_instance *h_inst, const
 int ppl_smc_autotune(int model, int32_t n_inst, const ppl_instance *h_inst, const ppl_instance *d_inst,
                      uint64_t seed, double ess_frac, void *d_ws, size_t ws_bytes, void *stream,
                      ppl_batch_result *out, ppl_tune *best);
+
+/* --------------------------------------------------- learned proposal -- */
+/* A small network maps 64 summary statistics of a dataset to a Gaussian-
+ * mixture proposal over the model's latents (PPL_Q_POLY_MIX / PPL_Q_GMM_MIX):
+ * an MLP 64 -> 256 -> 256 -> 256 with ReLU after the first two layers, BF16
+ * matrix-core products accumulating in FP32.  It is trained on (latent, data)
+ * pairs simulated from the model's own prior by minimising -log q(latent | data)
+ * with Adam, then used as the importance-sampling proposal (Sec. 3.6.2 with a
+ * proposal other than the prior).  The prior proposal stays available through
+ * ppl_importance.
+ *
+ * Summaries (FP64, then BF16 at the network input):
+ *   POLY (42 used): mean x^j y / 10 (j = 0..7); mean x^k (k = 1..14);
+ *     mean y^2 / 100; least-squares coefficients for n = 2..5 / 10;
+ *     log(mean squared residual_n + 1e-3) / 10 for n = 2..5; log D / 10.
+ *   GMM (53 used): order statistics y_(floor((q + 1/2) D / 16)) / 10 (q < 16);
+ *     counts on the unit bins of [-16, 16), ends clamped, / D; mean / 10;
+ *     sd / 10; skewness; excess kurtosis / 10; log D / 10.
+ * Output head (network outputs o[256]):
+ *   POLY: o[0:4] degree logits; o[4:12] mixture logits; for degree n a block
+ *     at 12 + 8 (n - 2)(n + 1): 8n means (10 o) then 8n log-scales
+ *     (5 tanh(o / 5)), component-major.
+ *   GMM: o[0:8] mixture logits; 8(2K-1) means (5 o); 8(2K-1) log-scales. */
+
+/* Bytes of one parameter block (device, caller-owned, 256-byte aligned): FP32
+ * master weights and biases, Adam first and second moments, BF16 copies of
+ * the weights in [out][in] and [in][out] layouts, and the Adam step count. */
+size_t ppl_proposal_weights_bytes(void);
+
+/* Glorot-uniform initialisation: element e of W_l[out][in] (l = 0, 1, 2) is
+ * (2u - 1) sqrt(6 / (in + out)) in FP32, u from word e mod 4 of Philox block
+ * (e div 4, l, 0, tag 5); zero biases, moments and step count. */
+int ppl_proposal_init(void *d_weights, uint64_t seed, void *stream);
+
+/* Training configuration.  hyper (HOST) are the simulation hyper-parameters:
+ * POLY {sd, n_lo, n_hi, noise_sd} (default {10, 2, 5, 1}; 2 <= n_lo <= n_hi <= 5);
+ * GMM {mu_sd, comp_sd} (default {5, 1}).  Adam fields 0 take the defaults
+ * lr 1e-3, beta1 0.9, beta2 0.999, eps 1e-8. */
+typedef struct ppl_train_config {
+    int64_t n_pairs;         /* simulated pairs in this call, a multiple of batch */
+    int32_t batch;           /* pairs per Adam step: a multiple of 64 in [64, 65536] */
+    int32_t dim;             /* GMM: K in 1..8; POLY: 0 */
+    int64_t n_data;          /* points per simulated dataset: POLY >= 1, GMM 1..1024 */
+    double lr, beta1, beta2, eps;
+    const double *hyper;
+    int32_t n_hyper;
+    int32_t use_graph;       /* nonzero: capture one step as a HIP graph and replay it */
+} ppl_train_config;
+
+int ppl_proposal_train_workspace_size(int model, const ppl_train_config *cfg, size_t *bytes);
+
+/* n_pairs / batch Adam steps.  Step t (the block's step count, which
+ * persists across calls) simulates pairs i < batch from Philox tag 4 with
+ * counter (i, block, t, 4); the loss is the batch mean of -log q(latent_i |
+ * summaries_i).  d_loss_trace (optional, FP64 [n_pairs / batch]) receives each
+ * step's mean loss.  model: PPL_MODEL_POLY or PPL_MODEL_GMM. */
+int ppl_proposal_train(int model, const ppl_train_config *cfg, uint64_t seed, void *d_weights,
+                       double *d_loss_trace, void *d_ws, size_t ws_bytes, void *stream);
+
+/* One batch of step `step` at the current weights, without updating them (a
+ * checking aid; the workspace is that of ppl_proposal_train).  Outputs
+ * (any may be NULL):
+ *   d_grad [148224] FP32: gradient of the batch-mean loss, parameter order
+ *     W1[256][64], b1[256], W2[256][256], b2, W3[256][256], b3;
+ *   d_loss [1] FP64: the batch-mean loss;
+ *   d_summaries [batch][64] FP64; d_latents [batch][16] FP64 (POLY: n, c_0..c_4;
+ *     GMM: u_0..u_{2K-2}); d_outputs [256][batch] FP32 network outputs. */
+int ppl_proposal_gradient(int model, const ppl_train_config *cfg, uint64_t seed, uint32_t step,
+                          const void *d_weights, float *d_grad, double *d_loss, double *d_summaries,
+                          double *d_latents, float *d_outputs, void *d_ws, size_t ws_bytes, void *stream);
+
+int ppl_proposal_infer_workspace_size(int model, const ppl_data *data, int64_t n_particles, size_t *bytes);
+
+/* Amortised inference: summaries of the observed data, one forward pass,
+ * decode to PPL_Q_POLY_MIX / PPL_Q_GMM_MIX parameters, then importance
+ * sampling with that proposal (outputs as ppl_importance).  d_q_params
+ * (optional) receives the decoded parameters, d_data_summaries (optional) the
+ * 64 FP64 summaries.  POLY needs the degree range 2..5; GMM needs D <= 8192. */
+int ppl_proposal_infer(int model, const ppl_data *data, const void *d_weights, int64_t n_particles,
+                       uint64_t seed, double *d_q_params, double *d_data_summaries, void *d_ws,
+                       size_t ws_bytes, void *stream, ppl_result *out);
 
 /* Kernel timing (a measurement aid).  ppl_timing_enable(1) clears the
  * accumulators and makes the launchers bracket their dominant kernels

@@ -22,7 +22,7 @@ PPL_OK, PPL_E_ARG, PPL_E_MODEL, PPL_E_DEVICE, PPL_E_HIP = 0, -1, -2, -3, -4
 PPL_E_WORKSPACE, PPL_E_NONFINITE, PPL_E_ZERO_WEIGHT, PPL_E_UNSUPPORTED = -5, -6, -7, -8
 PPL_MODEL_POLY, PPL_MODEL_BLR, PPL_MODEL_LGSSM, PPL_MODEL_GMM = 1, 2, 3, 4
 PPL_F32, PPL_F64 = 1, 2
-PPL_Q_PRIOR, PPL_Q_GAUSS_FULL = 0, 1
+PPL_Q_PRIOR, PPL_Q_GAUSS_FULL, PPL_Q_POLY_MIX, PPL_Q_GMM_MIX = 0, 1, 2, 3
 PPL_ALGO_IS, PPL_ALGO_SMC, PPL_ALGO_LSE, PPL_ALGO_RESAMPLE = 0, 1, 2, 3
 
 # Exported C symbols (kept in step with include/ppl.h).
@@ -101,7 +101,8 @@ def _stream(stream):
 
 
 def make_data(x, y, n_data=None, dim=0, hyper=None, dtype=None):
-    """Build a ppl_data block from device tensors (keeps the hyper array alive)."""
+    """Build a ppl_data block from device tensors; the block holds references to
+    x, y and the hyper array so they outlive every call that uses it."""
     if dtype is None:
         dtype = PPL_F64 if y.dtype == torch.float64 else PPL_F32
     h = None
@@ -111,7 +112,7 @@ def make_data(x, y, n_data=None, dim=0, hyper=None, dtype=None):
                 n_data=int(y.numel() if n_data is None else n_data), dim=int(dim), dtype=dtype,
                 hyper=ctypes.cast(h, ctypes.POINTER(ctypes.c_double)) if h is not None else None,
                 n_hyper=0 if hyper is None else len(hyper))
-    d._keep = h
+    d._keep = (h, x, y)
     return d
 
 
@@ -126,16 +127,27 @@ def workspace(nbytes, device=None):
     return torch.empty(max(int(nbytes), 1), dtype=torch.uint8, device=device or "cuda")
 
 
+def _q_dim(kind, data):
+    if kind == PPL_Q_POLY_MIX:
+        return 5
+    if kind == PPL_Q_GMM_MIX:
+        return 2 * data.dim - 1
+    return data.dim
+
+
 def ppl_importance(model, data, n, seed, q=None, ws=None, stream=None, log_weights=None, latents=None,
-                   summaries=None, scalars=None, sync=False):
-    """Importance sampling; returns the ppl_result struct (host scalars when sync)."""
+                   summaries=None, scalars=None, sync=False, q_kind=None):
+    """Importance sampling; returns the ppl_result struct (host scalars when sync).
+    q: device parameter tensor of the proposal, of kind q_kind (default: the
+    BLR full Gaussian)."""
     if ws is None:
         ws = workspace(ppl_workspace_size(model, data, n, PPL_ALGO_IS))
     res = PplResult(sync_host=1 if sync else 0, d_scalars=_ptr(scalars), d_latents=_ptr(latents),
                     d_log_weights=_ptr(log_weights), d_summaries=_ptr(summaries))
     prop = None
     if q is not None:
-        prop = PplProposal(kind=PPL_Q_GAUSS_FULL, dim=data.dim, d_params=q.data_ptr())
+        kind = PPL_Q_GAUSS_FULL if q_kind is None else q_kind
+        prop = PplProposal(kind=kind, dim=_q_dim(kind, data), d_params=q.data_ptr())
     _check(lib.ppl_importance(model, ctypes.byref(data), int(n), int(seed) & (2 ** 64 - 1),
                               ctypes.byref(prop) if prop is not None else None, _ptr(ws), ws.numel(),
                               _stream(stream), ctypes.byref(res)))
@@ -301,3 +313,102 @@ def ppl_smc_autotune(model, table, seed, ess_frac=0.5, ws=None, stream=None, out
                                 float(ess_frac), _ptr(ws), ws.numel(), _stream(stream), ctypes.byref(res),
                                 ctypes.byref(best)))
     return (best.particles_per_lane, best.wgs_per_instance, best.spec_block)
+
+
+# ------------------------------------------------------- learned proposal --
+class PplTrainConfig(ctypes.Structure):
+    _fields_ = [("n_pairs", ctypes.c_int64), ("batch", ctypes.c_int32), ("dim", ctypes.c_int32),
+                ("n_data", ctypes.c_int64), ("lr", ctypes.c_double), ("beta1", ctypes.c_double),
+                ("beta2", ctypes.c_double), ("eps", ctypes.c_double), ("hyper", ctypes.POINTER(ctypes.c_double)),
+                ("n_hyper", ctypes.c_int32), ("use_graph", ctypes.c_int32)]
+
+
+def train_config(n_pairs, batch, n_data, dim=0, lr=0.0, beta1=0.0, beta2=0.0, eps=0.0, hyper=None, use_graph=False):
+    """Build a ppl_train_config (keeps the hyper array alive)."""
+    h = None
+    if hyper is not None:
+        h = (ctypes.c_double * len(hyper))(*[float(v) for v in hyper])
+    c = PplTrainConfig(n_pairs=int(n_pairs), batch=int(batch), dim=int(dim), n_data=int(n_data), lr=float(lr),
+                       beta1=float(beta1), beta2=float(beta2), eps=float(eps),
+                       hyper=ctypes.cast(h, ctypes.POINTER(ctypes.c_double)) if h is not None else None,
+                       n_hyper=0 if hyper is None else len(hyper), use_graph=1 if use_graph else 0)
+    c._keep = h
+    return c
+
+
+def _bind_proposal():
+    L, i32, i64, u32, u64 = lib, ctypes.c_int32, ctypes.c_int64, ctypes.c_uint32, ctypes.c_uint64
+    cfg, sz = ctypes.POINTER(PplTrainConfig), ctypes.c_size_t
+    L.ppl_proposal_weights_bytes.argtypes = []
+    L.ppl_proposal_weights_bytes.restype = sz
+    L.ppl_proposal_init.argtypes = [P, u64, P]
+    L.ppl_proposal_train_workspace_size.argtypes = [ctypes.c_int, cfg, ctypes.POINTER(sz)]
+    L.ppl_proposal_train.argtypes = [ctypes.c_int, cfg, u64, P, P, P, sz, P]
+    L.ppl_proposal_gradient.argtypes = [ctypes.c_int, cfg, u64, u32, P, P, P, P, P, P, P, sz, P]
+    L.ppl_proposal_infer_workspace_size.argtypes = [ctypes.c_int, ctypes.POINTER(PplData), i64, ctypes.POINTER(sz)]
+    L.ppl_proposal_infer.argtypes = [ctypes.c_int, ctypes.POINTER(PplData), P, i64, u64, P, P, P, sz, P,
+                                     ctypes.POINTER(PplResult)]
+    for n in ("ppl_proposal_init", "ppl_proposal_train_workspace_size", "ppl_proposal_train",
+              "ppl_proposal_gradient", "ppl_proposal_infer_workspace_size", "ppl_proposal_infer"):
+        getattr(L, n).restype = ctypes.c_int
+
+
+_bind_proposal()
+EXPORTS = EXPORTS + ("ppl_proposal_weights_bytes", "ppl_proposal_init", "ppl_proposal_train_workspace_size",
+                     "ppl_proposal_train", "ppl_proposal_gradient", "ppl_proposal_infer_workspace_size",
+                     "ppl_proposal_infer")
+N_PARAMS = 148224
+
+
+def ppl_proposal_weights_bytes():
+    return int(lib.ppl_proposal_weights_bytes())
+
+
+def ppl_proposal_init(seed, weights=None, stream=None):
+    """Initialised parameter block (a uint8 device tensor)."""
+    if weights is None:
+        weights = workspace(ppl_proposal_weights_bytes())
+    _check(lib.ppl_proposal_init(_ptr(weights), int(seed) & (2 ** 64 - 1), _stream(stream)))
+    return weights
+
+
+def ppl_proposal_train_workspace_size(model, cfg):
+    b = ctypes.c_size_t()
+    _check(lib.ppl_proposal_train_workspace_size(model, ctypes.byref(cfg), ctypes.byref(b)))
+    return b.value
+
+
+def ppl_proposal_train(model, cfg, seed, weights, loss_trace=None, ws=None, stream=None):
+    if ws is None:
+        ws = workspace(ppl_proposal_train_workspace_size(model, cfg))
+    _check(lib.ppl_proposal_train(model, ctypes.byref(cfg), int(seed) & (2 ** 64 - 1), _ptr(weights),
+                                  _ptr(loss_trace), _ptr(ws), ws.numel(), _stream(stream)))
+    return loss_trace
+
+
+def ppl_proposal_gradient(model, cfg, seed, step, weights, grad=None, loss=None, summaries=None, latents=None,
+                          outputs=None, ws=None, stream=None):
+    if ws is None:
+        ws = workspace(ppl_proposal_train_workspace_size(model, cfg))
+    _check(lib.ppl_proposal_gradient(model, ctypes.byref(cfg), int(seed) & (2 ** 64 - 1), int(step), _ptr(weights),
+                                     _ptr(grad), _ptr(loss), _ptr(summaries), _ptr(latents), _ptr(outputs),
+                                     _ptr(ws), ws.numel(), _stream(stream)))
+
+
+def ppl_proposal_infer_workspace_size(model, data, n):
+    b = ctypes.c_size_t()
+    _check(lib.ppl_proposal_infer_workspace_size(model, ctypes.byref(data), int(n), ctypes.byref(b)))
+    return b.value
+
+
+def ppl_proposal_infer(model, data, weights, n, seed, q_params=None, data_summaries=None, ws=None, stream=None,
+                       log_weights=None, latents=None, summaries=None, scalars=None, sync=False):
+    """Amortised importance sampling; returns the ppl_result struct."""
+    if ws is None:
+        ws = workspace(ppl_proposal_infer_workspace_size(model, data, n))
+    res = PplResult(sync_host=1 if sync else 0, d_scalars=_ptr(scalars), d_latents=_ptr(latents),
+                    d_log_weights=_ptr(log_weights), d_summaries=_ptr(summaries))
+    _check(lib.ppl_proposal_infer(model, ctypes.byref(data), _ptr(weights), int(n), int(seed) & (2 ** 64 - 1),
+                                  _ptr(q_params), _ptr(data_summaries), _ptr(ws), ws.numel(), _stream(stream),
+                                  ctypes.byref(res)))
+    return res

@@ -15,7 +15,9 @@
 #include "batched.h"
 #include "host.h"
 #include "kernels.h"
+#include "proposal.h"
 #include "smc.h"
+#include "timing.h"
 
 namespace ppl {
 
@@ -126,7 +128,11 @@ static int check_n(int64_t n) {
     return PPL_OK;
 }
 
-static size_t is_ws_bytes(int model, int dim, int64_t n) { return 256 + align_up(is_partial_bytes(model, dim, n), 256); }
+static size_t is_ws_bytes(int model, int dim, int64_t n) {
+    size_t part = model == PPL_MODEL_GMM ? prop_partial_bytes(model, n) : is_partial_bytes(model, dim, n);
+    if (model == PPL_MODEL_POLY) part = std::max(part, prop_partial_bytes(model, n));
+    return 256 + align_up(part, 256);
+}
 
 // Blocks on the stream and copies the device scalars into the host fields.
 static int sync_scalars(ppl_result *out, const double *d_scal, hipStream_t st) {
@@ -175,8 +181,8 @@ int ppl_workspace_size(int model, const ppl_data *data, int64_t n, int algo, siz
         case PPL_ALGO_RESAMPLE: *bytes = align_up(resample_ws_bytes(n), 256); return PPL_OK;
         case PPL_ALGO_IS: {
             double h[8];
-            if (model != PPL_MODEL_POLY && model != PPL_MODEL_BLR)
-                return fail(PPL_E_MODEL, "importance sampling supports POLY and BLR (got %d)", model);
+            if (model != PPL_MODEL_POLY && model != PPL_MODEL_BLR && model != PPL_MODEL_GMM)
+                return fail(PPL_E_MODEL, "importance sampling supports POLY, BLR and GMM (got %d)", model);
             if (int rc = check_model_data(model, data, h)) return rc;
             *bytes = is_ws_bytes(model, data->dim, n);
             return PPL_OK;
@@ -197,16 +203,26 @@ int ppl_importance(int model, const ppl_data *data, int64_t n, uint64_t seed, co
                    size_t ws_bytes, void *stream, ppl_result *out) {
     clear_error();
     if (!out) return fail(PPL_E_ARG, "out is NULL");
-    if (model != PPL_MODEL_POLY && model != PPL_MODEL_BLR)
-        return fail(model >= 1 && model <= 4 ? PPL_E_MODEL : PPL_E_MODEL,
-                    "importance sampling supports POLY and BLR (got %d)", model);
+    if (model != PPL_MODEL_POLY && model != PPL_MODEL_BLR && model != PPL_MODEL_GMM)
+        return fail(PPL_E_MODEL, "importance sampling supports POLY, BLR and GMM (got %d)", model);
     if (int rc = check_n(n)) return rc;
     IsArgs a{};
     if (int rc = check_model_data(model, data, a.hyper)) return rc;
+    bool mixture_path = model == PPL_MODEL_GMM;
     if (q && q->kind != PPL_Q_PRIOR) {
-        if (q->kind != PPL_Q_GAUSS_FULL || model != PPL_MODEL_BLR)
+        if (!q->d_params) return fail(PPL_E_ARG, "proposal parameters are NULL");
+        if (q->kind == PPL_Q_GAUSS_FULL && model == PPL_MODEL_BLR) {
+            if (q->dim != data->dim) return fail(PPL_E_ARG, "Gaussian proposal needs params of dim %d", data->dim);
+        } else if (q->kind == PPL_Q_POLY_MIX && model == PPL_MODEL_POLY) {
+            if (q->dim != 5) return fail(PPL_E_ARG, "POLY mixture proposal has dim 5 (got %d)", q->dim);
+            if (a.hyper[1] != 2.0 || a.hyper[2] != 5.0)
+                return fail(PPL_E_ARG, "the POLY mixture proposal covers degrees 2..5; the model range must be 2..5");
+            mixture_path = true;
+        } else if (q->kind == PPL_Q_GMM_MIX && model == PPL_MODEL_GMM) {
+            if (q->dim != 2 * data->dim - 1) return fail(PPL_E_ARG, "GMM mixture proposal has dim 2K - 1 = %d", 2 * data->dim - 1);
+        } else {
             return fail(PPL_E_UNSUPPORTED, "proposal kind %d is not available for model %d", q->kind, model);
-        if (!q->d_params || q->dim != data->dim) return fail(PPL_E_ARG, "Gaussian proposal needs params of dim %d", data->dim);
+        }
         a.q_params = q->d_params;
     }
     if (int rc = check_ws(ws, ws_bytes, is_ws_bytes(model, data->dim, n))) return rc;
@@ -224,7 +240,7 @@ int ppl_importance(int model, const ppl_data *data, int64_t n, uint64_t seed, co
     a.scalars = out->d_scalars ? out->d_scalars : (double *)ws;
     a.part = (double *)((char *)ws + 256);
     hipStream_t st = (hipStream_t)stream;
-    if (int rc = run_importance(a, st)) return rc;
+    if (int rc = mixture_path ? run_importance_q(a, st) : run_importance(a, st)) return rc;
     if (out->sync_host) return sync_scalars(out, a.scalars, st);
     return PPL_OK;
 }
@@ -407,6 +423,251 @@ int ppl_smc_autotune(int model, int32_t n, const ppl_instance *h, const ppl_inst
     *best = best_cfg;
     std::lock_guard<std::mutex> lk(g_tune_mu);
     g_tune_cache[batch_key(n, h)] = best_cfg;
+    return PPL_OK;
+}
+
+}  // extern "C"
+
+// ------------------------------------------------------ learned proposal --
+namespace ppl {
+
+struct TrainPlan {
+    SimSpec sim;
+    AdamSpec adam;
+    int B;
+    int64_t steps;
+};
+
+static int check_train(int model, const ppl_train_config *c, TrainPlan *p) {
+    if (!c) return fail(PPL_E_ARG, "training configuration is NULL");
+    if (model != PPL_MODEL_POLY && model != PPL_MODEL_GMM)
+        return fail(PPL_E_MODEL, "the learned proposal supports POLY and GMM (got %d)", model);
+    if (c->batch < 64 || c->batch > 65536 || c->batch % 64)
+        return fail(PPL_E_ARG, "batch %d must be a multiple of 64 in [64, 65536]", c->batch);
+    if (c->n_pairs < 0 || c->n_pairs % c->batch) return fail(PPL_E_ARG, "n_pairs must be a non-negative multiple of batch");
+    if (c->n_pairs / c->batch > 0x7fffffffLL) return fail(PPL_E_ARG, "too many training steps");
+    if (c->n_hyper < 0 || (c->n_hyper > 0 && !c->hyper)) return fail(PPL_E_ARG, "hyper is NULL with n_hyper > 0");
+    auto hy = [&](int i, double d) { return (c->hyper && c->n_hyper > i) ? c->hyper[i] : d; };
+    SimSpec &sp = p->sim;
+    sp = SimSpec{};
+    sp.model = model;
+    sp.D = c->n_data;
+    if (model == PPL_MODEL_POLY) {
+        sp.K = 0;
+        sp.hyper[0] = hy(0, 10.0);
+        sp.hyper[1] = hy(1, 2.0);
+        sp.hyper[2] = hy(2, 5.0);
+        sp.hyper[3] = hy(3, 1.0);
+        if (!finite_pos(sp.hyper[0]) || !isfinite(sp.hyper[3]) || sp.hyper[3] < 0)
+            return fail(PPL_E_ARG, "POLY simulation needs sd > 0 and noise_sd >= 0");
+        if (!is_int(sp.hyper[1]) || !is_int(sp.hyper[2]) || sp.hyper[1] < 2 || sp.hyper[2] > 5 || sp.hyper[1] > sp.hyper[2])
+            return fail(PPL_E_ARG, "the POLY proposal head covers degrees 2..5 (need 2 <= n_lo <= n_hi <= 5)");
+        if (c->n_data < 1 || c->n_data > 0x7fffffffLL) return fail(PPL_E_ARG, "n_data must be in [1, 2^31)");
+    } else {
+        if (c->dim < 1 || c->dim > 8) return fail(PPL_E_ARG, "GMM K must be in 1..8 (got %d)", c->dim);
+        sp.K = c->dim;
+        sp.hyper[0] = hy(0, 5.0);
+        sp.hyper[1] = hy(1, 1.0);
+        if (!finite_pos(sp.hyper[0]) || !finite_pos(sp.hyper[1])) return fail(PPL_E_ARG, "GMM sds must be positive");
+        if (c->n_data < 1 || c->n_data > kGmmTrainMaxD)
+            return fail(PPL_E_ARG, "GMM n_data must be in [1, %d]", kGmmTrainMaxD);
+    }
+    AdamSpec &ad = p->adam;
+    ad.lr = (float)(c->lr != 0.0 ? c->lr : 1e-3);
+    ad.b1 = (float)(c->beta1 != 0.0 ? c->beta1 : 0.9);
+    ad.b2 = (float)(c->beta2 != 0.0 ? c->beta2 : 0.999);
+    ad.eps = (float)(c->eps != 0.0 ? c->eps : 1e-8);
+    if (!(ad.lr > 0) || !(ad.b1 >= 0 && ad.b1 < 1) || !(ad.b2 >= 0 && ad.b2 < 1) || !(ad.eps > 0))
+        return fail(PPL_E_ARG, "Adam needs lr > 0, betas in [0, 1) and eps > 0");
+    p->B = c->batch;
+    p->steps = c->n_pairs / c->batch;
+    return PPL_OK;
+}
+
+static int check_weights(const void *w) {
+    if (!w) return fail(PPL_E_ARG, "d_weights is NULL");
+    if (((uintptr_t)w & 255) != 0) return fail(PPL_E_ARG, "d_weights must be 256-byte aligned");
+    return PPL_OK;
+}
+
+// One training step: simulate, forward, loss head, backward, Adam, bookkeeping.
+static int train_step(const TrainPlan &p, uint64_t seed, const MlpView &w, const TrainBufs &b, double *loss_trace,
+                      hipStream_t st) {
+    if (int rc = launch_simulate(p.sim, p.B, seed, w.step, b.x_row, b.x_col, b.theta, nullptr, st)) return rc;
+    if (int rc = launch_forward(w, b, true, st)) return rc;
+    if (int rc = launch_head_backward(p.sim.model, p.sim.K, w, b, st)) return rc;
+    if (int rc = launch_update(w, b, p.adam, nullptr, st)) return rc;
+    return launch_advance(w.step, b, loss_trace, st);
+}
+
+static int train_graph(const TrainPlan &p, uint64_t seed, const MlpView &w, const TrainBufs &b, double *loss_trace,
+                       hipStream_t st) {
+    hipStream_t cap = nullptr;
+    PPL_HIP(hipStreamCreateWithFlags(&cap, hipStreamNonBlocking));
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+    int rc = PPL_OK;
+    {
+        TimingSuspend quiet;
+        hipError_t e = hipStreamBeginCapture(cap, hipStreamCaptureModeThreadLocal);
+        if (e != hipSuccess) {
+            rc = fail(PPL_E_HIP, "hipStreamBeginCapture: %s", hipGetErrorString(e));
+        } else {
+            rc = train_step(p, seed, w, b, loss_trace, cap);
+            e = hipStreamEndCapture(cap, &graph);
+            if (!rc && e != hipSuccess) rc = fail(PPL_E_HIP, "hipStreamEndCapture: %s", hipGetErrorString(e));
+        }
+    }
+    if (!rc) {
+        hipError_t e = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+        if (e != hipSuccess) rc = fail(PPL_E_HIP, "hipGraphInstantiate: %s", hipGetErrorString(e));
+    }
+    for (int64_t s = 0; !rc && s < p.steps; ++s) {
+        KernelTimer timer("proposal_train_step", st);
+        hipError_t e = hipGraphLaunch(exec, st);
+        timer.stop();
+        if (e != hipSuccess) rc = fail(PPL_E_HIP, "hipGraphLaunch: %s", hipGetErrorString(e));
+    }
+    // the executable graph is released only after its launches have finished
+    if (exec) {
+        hipError_t e = hipStreamSynchronize(st);
+        if (!rc && e != hipSuccess) rc = fail(PPL_E_HIP, "hipStreamSynchronize: %s", hipGetErrorString(e));
+        (void)hipGraphExecDestroy(exec);
+    }
+    if (graph) (void)hipGraphDestroy(graph);
+    (void)hipStreamDestroy(cap);
+    return rc;
+}
+
+static size_t infer_ws_bytes(int model, int64_t n) {
+    return 256 + align_up(train_ws_bytes(64), 256) + 256 * 8 /* decoded q, <= 332 doubles */ * 2 +
+           align_up(prop_partial_bytes(model, n), 256);
+}
+
+}  // namespace ppl
+
+extern "C" {
+
+size_t ppl_proposal_weights_bytes(void) { return MlpParams::bytes(); }
+
+int ppl_proposal_init(void *d_weights, uint64_t seed, void *stream) {
+    clear_error();
+    if (int rc = check_weights(d_weights)) return rc;
+    if (int rc = check_device()) return rc;
+    return launch_init_weights(d_weights, seed, (hipStream_t)stream);
+}
+
+int ppl_proposal_train_workspace_size(int model, const ppl_train_config *cfg, size_t *bytes) {
+    clear_error();
+    if (!bytes) return fail(PPL_E_ARG, "bytes is NULL");
+    TrainPlan p;
+    if (int rc = check_train(model, cfg, &p)) return rc;
+    *bytes = train_ws_bytes(p.B);
+    return PPL_OK;
+}
+
+int ppl_proposal_train(int model, const ppl_train_config *cfg, uint64_t seed, void *d_weights, double *d_loss_trace,
+                       void *ws, size_t ws_bytes, void *stream) {
+    clear_error();
+    TrainPlan p;
+    if (int rc = check_train(model, cfg, &p)) return rc;
+    if (int rc = check_weights(d_weights)) return rc;
+    if (int rc = check_ws(ws, ws_bytes, train_ws_bytes(p.B))) return rc;
+    if (int rc = check_device()) return rc;
+    if (p.steps == 0) return PPL_OK;
+    hipStream_t st = (hipStream_t)stream;
+    const MlpView w = mlp_view(d_weights);
+    const TrainBufs b = train_bufs(ws, p.B);
+    if (int rc = launch_set_i64(b.local, 0, st)) return rc;
+    if (cfg->use_graph) return train_graph(p, seed, w, b, d_loss_trace, st);
+    for (int64_t s = 0; s < p.steps; ++s)
+        if (int rc = train_step(p, seed, w, b, d_loss_trace, st)) return rc;
+    return PPL_OK;
+}
+
+int ppl_proposal_gradient(int model, const ppl_train_config *cfg, uint64_t seed, uint32_t step, const void *d_weights,
+                          float *d_grad, double *d_loss, double *d_summaries, double *d_latents, float *d_outputs,
+                          void *ws, size_t ws_bytes, void *stream) {
+    clear_error();
+    TrainPlan p;
+    if (int rc = check_train(model, cfg, &p)) return rc;
+    if (int rc = check_weights(d_weights)) return rc;
+    if (int rc = check_ws(ws, ws_bytes, train_ws_bytes(p.B))) return rc;
+    if (int rc = check_device()) return rc;
+    hipStream_t st = (hipStream_t)stream;
+    const MlpView w = mlp_view(const_cast<void *>(d_weights));
+    const TrainBufs b = train_bufs(ws, p.B);
+    if (int rc = launch_set_i64(b.local, 0, st)) return rc;
+    if (int rc = launch_set_i64(b.local + 1, (int64_t)step, st)) return rc;
+    if (int rc = launch_simulate(p.sim, p.B, seed, b.local + 1, b.x_row, b.x_col, b.theta, d_summaries, st)) return rc;
+    if (int rc = launch_forward(w, b, true, st)) return rc;
+    if (int rc = launch_head_backward(model, p.sim.K, w, b, st)) return rc;
+    if (d_grad)
+        if (int rc = launch_update(w, b, p.adam, d_grad, st)) return rc;
+    if (int rc = launch_advance(nullptr, b, d_loss, st)) return rc;
+    if (d_latents)
+        PPL_HIP(hipMemcpyAsync(d_latents, b.theta, (size_t)p.B * kThetaStride * sizeof(double), hipMemcpyDeviceToDevice, st));
+    if (d_outputs)
+        PPL_HIP(hipMemcpyAsync(d_outputs, b.o_col, (size_t)p.B * kMlpOut * sizeof(float), hipMemcpyDeviceToDevice, st));
+    return PPL_OK;
+}
+
+int ppl_proposal_infer_workspace_size(int model, const ppl_data *data, int64_t n, size_t *bytes) {
+    clear_error();
+    if (!bytes) return fail(PPL_E_ARG, "bytes is NULL");
+    if (model != PPL_MODEL_POLY && model != PPL_MODEL_GMM)
+        return fail(PPL_E_MODEL, "the learned proposal supports POLY and GMM (got %d)", model);
+    if (int rc = check_n(n)) return rc;
+    double h[8];
+    if (int rc = check_model_data(model, data, h)) return rc;
+    *bytes = infer_ws_bytes(model, n);
+    return PPL_OK;
+}
+
+int ppl_proposal_infer(int model, const ppl_data *data, const void *d_weights, int64_t n, uint64_t seed,
+                       double *d_q_params, double *d_data_summaries, void *ws, size_t ws_bytes, void *stream,
+                       ppl_result *out) {
+    clear_error();
+    if (!out) return fail(PPL_E_ARG, "out is NULL");
+    if (model != PPL_MODEL_POLY && model != PPL_MODEL_GMM)
+        return fail(PPL_E_MODEL, "the learned proposal supports POLY and GMM (got %d)", model);
+    if (int rc = check_n(n)) return rc;
+    IsArgs a{};
+    if (int rc = check_model_data(model, data, a.hyper)) return rc;
+    if (model == PPL_MODEL_POLY && (a.hyper[1] != 2.0 || a.hyper[2] != 5.0))
+        return fail(PPL_E_ARG, "the POLY proposal covers degrees 2..5; the model range must be 2..5");
+    if (model == PPL_MODEL_GMM && data->n_data > kGmmSummaryMaxD)
+        return fail(PPL_E_ARG, "GMM summaries take at most %d points", kGmmSummaryMaxD);
+    if (int rc = check_weights(d_weights)) return rc;
+    if (int rc = check_ws(ws, ws_bytes, infer_ws_bytes(model, n))) return rc;
+    if (int rc = check_device()) return rc;
+    hipStream_t st = (hipStream_t)stream;
+    char *base = (char *)ws;
+    double *scal = (double *)base;
+    const TrainBufs b = train_bufs(base + 256, 64);
+    double *q = (double *)(base + 256 + align_up(train_ws_bytes(64), 256));
+    double *part = q + 512;
+    const MlpView w = mlp_view(const_cast<void *>(d_weights));
+    if (int rc = launch_observed_summary(model, data->x, data->y, data->n_data, b.x_row, d_data_summaries, st)) return rc;
+    if (int rc = launch_forward(w, b, false, st)) return rc;
+    if (int rc = launch_decode(model, data->dim, b.o_col, 64, q, st)) return rc;
+    const int nq = model == PPL_MODEL_POLY ? kPolyQParams : gmm_q_params(data->dim);
+    if (d_q_params) PPL_HIP(hipMemcpyAsync(d_q_params, q, (size_t)nq * sizeof(double), hipMemcpyDeviceToDevice, st));
+    a.model = model;
+    a.x = data->x;
+    a.y = data->y;
+    a.D = data->n_data;
+    a.dim = data->dim;
+    a.N = n;
+    a.seed = seed;
+    a.q_params = q;
+    a.lw_out = out->d_log_weights;
+    a.lat_out = out->d_latents;
+    a.summaries = out->d_summaries;
+    a.scalars = out->d_scalars ? out->d_scalars : scal;
+    a.part = part;
+    if (int rc = run_importance_q(a, st)) return rc;
+    if (out->sync_host) return sync_scalars(out, a.scalars, st);
     return PPL_OK;
 }
 

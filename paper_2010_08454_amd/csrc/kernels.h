@@ -14,7 +14,7 @@ struct IsArgs {
     double hyper[8];
     int64_t N;
     uint64_t seed;
-    const void *q_params;   // BLR Gaussian proposal (float32 mean + Cholesky) or null
+    const void *q_params;   // proposal parameters (BLR: float32 mean + Cholesky; POLY / GMM: FP64 mixture) or null
     void *lw_out, *lat_out;
     double *scalars;        // [8], device
     double *summaries;      // device or null
@@ -23,6 +23,10 @@ struct IsArgs {
 
 size_t is_partial_bytes(int model, int dim, int64_t N);
 int run_importance(const IsArgs &a, hipStream_t st);
+
+// Mixture-proposal importance sampling (POLY with q, GMM with or without q).
+size_t prop_partial_bytes(int model, int64_t N);
+int run_importance_q(const IsArgs &a, hipStream_t st);
 
 // Normaliser of a device log-weight vector (see ppl_lse_ess).
 size_t lse_ws_bytes(int64_t n);

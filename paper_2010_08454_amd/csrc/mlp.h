@@ -1,0 +1,97 @@
+// mlp.h -- BF16 MFMA building blocks of the learned proposal network.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace ppl {
+
+// Network shape: 64 -> 256 -> 256 -> 256, ReLU after layers 1 and 2.
+constexpr int kMlpIn = 64;
+constexpr int kMlpHid = 256;
+constexpr int kMlpOut = 256;
+constexpr int kMlpLayers = 3;
+
+// Parameter block (device, caller-owned), in this order:
+//   FP32 master copy of all parameters, Adam first and second moments (same
+//   layout), then BF16 copies of each weight matrix in two layouts:
+//   Wt[l] = [out][in] (row = output unit) and W[l] = [in][out].
+// Per layer l the FP32 parameters are W_l as [out][in] followed by b_l[out].
+struct MlpParams {
+    __host__ __device__ static constexpr int in(int l) { return l == 0 ? kMlpIn : kMlpHid; }
+    __host__ __device__ static constexpr int out(int l) { return l == 2 ? kMlpOut : kMlpHid; }
+    __host__ __device__ static constexpr int64_t w_off(int l) {
+        return l == 0 ? 0 : l == 1 ? (int64_t)kMlpIn * kMlpHid + kMlpHid
+                                   : (int64_t)kMlpIn * kMlpHid + kMlpHid + (int64_t)kMlpHid * kMlpHid + kMlpHid;
+    }
+    __host__ __device__ static constexpr int64_t b_off(int l) { return w_off(l) + (int64_t)in(l) * out(l); }
+    __host__ __device__ static constexpr int64_t count() { return b_off(2) + kMlpOut; }      // 148224
+    __host__ __device__ static constexpr int64_t bf16_w_off(int l) {                         // offsets within one BF16 layout
+        return l == 0 ? 0 : l == 1 ? (int64_t)kMlpIn * kMlpHid : (int64_t)kMlpIn * kMlpHid + (int64_t)kMlpHid * kMlpHid;
+    }
+    __host__ __device__ static constexpr int64_t bf16_count() { return bf16_w_off(2) + (int64_t)kMlpHid * kMlpOut; }
+    static constexpr size_t step_off() {                                  // int64 Adam step count
+        return (3 * count() * sizeof(float) + 2 * bf16_count() * sizeof(uint16_t) + 255) / 256 * 256;
+    }
+    static constexpr size_t bytes() { return step_off() + 256; }
+};
+
+// FP32 -> BF16 bit pattern, round to nearest even (NaN stays NaN).
+__host__ __device__ inline uint16_t f32_to_bf16(float f) {
+    uint32_t u;
+    __builtin_memcpy(&u, &f, 4);
+    if ((u & 0x7FFFFFFFu) > 0x7F800000u) return (uint16_t)((u >> 16) | 0x40u);
+    u += 0x7FFFu + ((u >> 16) & 1u);
+    return (uint16_t)(u >> 16);
+}
+
+__host__ __device__ inline float bf16_to_f32(uint16_t b) {
+    const uint32_t u = (uint32_t)b << 16;
+    float f;
+    __builtin_memcpy(&f, &u, 4);
+    return f;
+}
+
+struct MlpView {
+    float *master, *m, *v;
+    uint16_t *wt, *w;        // BF16 bit patterns: [out][in] and [in][out]
+    int64_t *step;           // completed Adam steps (device)
+};
+
+inline MlpView mlp_view(void *p) {
+    MlpView v;
+    v.master = (float *)p;
+    v.m = v.master + MlpParams::count();
+    v.v = v.m + MlpParams::count();
+    v.wt = (uint16_t *)(v.v + MlpParams::count());
+    v.w = v.wt + MlpParams::bf16_count();
+    v.step = (int64_t *)((char *)p + MlpParams::step_off());
+    return v;
+}
+
+// Epilogue of the NT GEMM C[M][N] = sum_r A[M][r] B[N][r] (+ bias[N]).
+enum MlpEpi : int {
+    kEpiRelu = 1,        // max(0, .)
+    kEpiOutRow = 2,      // BF16 row-major [M][N] output
+    kEpiOutCol = 4,      // BF16 column-major [N][M] output
+    kEpiOutF32 = 8,      // FP32 row-major output
+    kEpiMaskRow = 16,    // multiply by (mask[M][N] > 0), mask BF16 row-major (ReLU derivative)
+    kEpiBias = 32,
+    kEpiOutF32Col = 64,  // FP32 column-major [N][M] output
+};
+
+// Launch C = A B^T for BF16 operands stored with the reduction dimension
+// contiguous (A: [M][R], B: [N][R]); M, N multiples of 64, R multiple of 32.
+int mlp_gemm(const uint16_t *A, const uint16_t *B, int M, int N, int R, int lda, int ldb, int epi, const float *bias,
+             const uint16_t *mask, uint16_t *out_row, uint16_t *out_col, float *out_f32, hipStream_t st);
+
+// Split-R variant for weight gradients: partial[c][M][N] (FP32) over
+// R-chunks of `chunk` (a multiple of 32); the consumer sums the chunks in order.
+int mlp_gemm_splitr(const uint16_t *A, const uint16_t *B, int M, int N, int R, int lda, int ldb, int chunk,
+                    float *partial, hipStream_t st);
+
+// Number of R-chunks the split GEMM uses for an M x N output over R rows, and
+// the chunk length (both fixed by the shape, so every call sums in one order).
+void mlp_split_plan(int M, int N, int R, int *nchunks, int *chunk);
+
+}  // namespace ppl

@@ -1,0 +1,406 @@
+// simulate.hip -- training pairs drawn from the model's own prior, and the 64
+// data summaries the proposal network reads.  One wave per dataset: the lanes
+// stride over the data points, FP64 moment sums are combined by a butterfly,
+// and the per-dataset finishing work (least-squares fits, order statistics)
+// runs on a few lanes of the same wave.
+//
+// Training pair of step t, pair i (Philox tag 4, counter (i, block, t, 4)):
+//   POLY: block 0 word 0 -> degree n (uniform discrete); blocks 1, 2 -> eight
+//         normals (two single-precision-stream Box-Muller pairs each), c_j =
+//         sd z_j; block 8 + e -> points 2e, 2e + 1: x = 2u - 1 from words 0, 1
+//         and the observation noise from a Box-Muller pair on words 2, 3;
+//         y = poly_c(x) + noise_sd * eps.
+//   GMM:  blocks 0, 1 -> Exp(1) draws E_k = -ln u_k, pi = E / sum E (a
+//         Dirichlet(1) draw); blocks 2, 3 -> mu_k = mu_sd z_k; block 8 + e ->
+//         the components of points 2e, 2e + 1 (inverse CDF on pi, words 0, 1)
+//         and their noise (words 2, 3); latents returned in the ordered
+//         unconstrained space (mu_(1), log gaps, log pi_(k) - log pi_(K)).
+// Every step is in FP64 on uniforms that are exact in both precisions.
+#include "device.h"
+#include "host.h"
+#include "proposal.h"
+
+namespace ppl {
+
+constexpr uint32_t kTagTrain = 4;
+constexpr int kSimWaves = 4;
+
+__device__ __forceinline__ double u01(uint32_t w) { return (double)unit_f32(w); }
+
+// Index of the first cumulative probability above u (K - 1 if none).
+__device__ __forceinline__ int categorical8(double u, const double (&p)[8], int K) {
+    double c = 0.0;
+    int r = K - 1;
+    bool found = false;
+#pragma unroll
+    for (int k = 0; k < 8; ++k) {
+        if (k < K && !found) {
+            c += p[k];
+            if (u < c) {
+                r = k;
+                found = true;
+            }
+        }
+    }
+    return r;
+}
+
+__device__ __forceinline__ double pick8(const double (&v)[8], int k) {
+    double r = v[0];
+#pragma unroll
+    for (int j = 1; j < 8; ++j) r = (k == j) ? v[j] : r;
+    return r;
+}
+
+// ------------------------------------------------------------- POLY --
+// Moment accumulators: [0..7] sum x^j y, [8..22] sum x^k (k = 0..14), [23] sum y^2.
+constexpr int kPolyAcc = 24;
+
+__device__ __forceinline__ void poly_acc_point(double (&a)[kPolyAcc], double x, double y) {
+#pragma clang fp contract(off)
+    double p = 1.0;
+#pragma unroll
+    for (int k = 0; k <= 14; ++k) {
+        if (k < 8) a[k] += p * y;
+        a[8 + k] += p;
+        p *= x;
+    }
+    a[23] += y * y;
+}
+
+// Least-squares fit with n coefficients from the normalised moments
+// (normal equations G beta = m, G_ij = mean x^(i+j), m_i = mean x^i y) by a
+// Cholesky factorisation and two triangular solves.
+__device__ void poly_ls(int n, const double *gx, const double *mxy, double (&beta)[5]) {
+#pragma clang fp contract(off)
+    double L[5][5], z[5];
+#pragma unroll
+    for (int i = 0; i < 5; ++i) {
+#pragma unroll
+        for (int j = 0; j <= i; ++j) {
+            if (i < n) {
+                double s = gx[i + j];
+#pragma unroll
+                for (int k = 0; k < j; ++k) s -= L[i][k] * L[j][k];
+                L[i][j] = (i == j) ? sqrt(s > 1e-300 ? s : 1e-300) : s / L[j][j];
+            }
+        }
+    }
+#pragma unroll
+    for (int i = 0; i < 5; ++i) {
+        if (i < n) {
+            double s = mxy[i];
+#pragma unroll
+            for (int k = 0; k < i; ++k) s -= L[i][k] * z[k];
+            z[i] = s / L[i][i];
+        }
+    }
+#pragma unroll
+    for (int i = 4; i >= 0; --i) {
+        beta[i] = 0.0;
+        if (i < n) {
+            double s = z[i];
+#pragma unroll
+            for (int k = i + 1; k < 5; ++k)
+                if (k < n) s -= L[k][i] * beta[k];
+            beta[i] = s / L[i][i];
+        }
+    }
+}
+
+// Reduce the lane accumulators and write the 64 POLY summaries to s[]:
+//   [0..7] mean x^j y / 10; [8..21] mean x^k, k = 1..14; [22] mean y^2 / 100;
+//   [23..36] least-squares coefficients for n = 2..5 / 10;
+//   [37..40] log(mean residual^2 + 1e-3) / 10; [41] log D / 10; rest 0.
+__device__ void poly_finish(double (&a)[kPolyAcc], int64_t D, double *tot, double *s) {
+#pragma clang fp contract(off)
+    const int lane = threadIdx.x & 63;
+#pragma unroll
+    for (int k = 0; k < kPolyAcc; ++k) a[k] = wave_sum(a[k]);
+    if (lane == 0) {
+#pragma unroll
+        for (int k = 0; k < kPolyAcc; ++k) tot[k] = D > 0 ? a[k] / (double)D : 0.0;
+    }
+    __syncthreads();
+    const double *mxy = tot, *gx = tot + 8;
+    double v = 0.0;
+    if (D > 0) {
+        if (lane < 8) v = mxy[lane] / 10.0;
+        else if (lane < 22) v = gx[lane - 7];
+        else if (lane == 22) v = tot[23] / 100.0;
+        else if (lane == 41) v = log((double)D) / 10.0;
+    }
+    if (lane < 23 || lane >= 41) s[lane] = v;
+    if (lane < 4) {
+        const int n = 2 + lane;
+        double beta[5];
+        poly_ls(n, gx, mxy, beta);
+        double fit = 0.0;
+        const int o = 23 + (n - 2) * (n + 1) / 2;
+#pragma unroll
+        for (int j = 0; j < 5; ++j) {
+            if (j < n) {
+                s[o + j] = D > 0 ? beta[j] / 10.0 : 0.0;
+                fit += beta[j] * mxy[j];
+            }
+        }
+        double rss = tot[23] - fit;
+        if (rss < 0.0) rss = 0.0;
+        s[37 + n - 2] = D > 0 ? log(rss + 1e-3) / 10.0 : 0.0;
+    }
+    __syncthreads();
+}
+
+// ------------------------------------------------------------- GMM --
+// Summaries from the data in LDS ys[D] (FP64 simulated points, or the FP32
+// observed values, compared and summed in FP64):
+//   [0..15] order statistics y_(floor((q + 1/2) D / 16)) / 10;
+//   [16..47] counts on the unit bins of [-16, 16) (ends clamped) / D;
+//   [48] mean / 10, [49] sd / 10, [50] skewness, [51] excess kurtosis / 10,
+//   [52] log D / 10; rest 0.  hist is this wave's 32 LDS counters, already
+//   filled; sum_y the lane's sum of its points.
+template <typename T>
+__device__ void gmm_finish(const T *ys, int64_t D, const int *hist, double sum_y, double *s) {
+#pragma clang fp contract(off)
+    const int lane = threadIdx.x & 63;
+    const double m1 = D > 0 ? wave_sum(sum_y) / (double)D : 0.0;
+    double c2 = 0.0, c3 = 0.0, c4 = 0.0;
+    for (int64_t d = lane; d < D; d += 64) {
+        const double y = (double)ys[d];
+        int64_t r = 0;
+        for (int64_t e = 0; e < D; ++e) {
+            const double ye = (double)ys[e];
+            r += (ye < y) || (ye == y && e < d);
+        }
+#pragma unroll
+        for (int q = 0; q < 16; ++q)
+            if (r == (int64_t)floor((q + 0.5) * (double)D / 16.0)) s[q] = y / 10.0;
+        const double dv = y - m1;
+        c2 += dv * dv;
+        c3 += dv * dv * dv;
+        c4 += dv * dv * dv * dv;
+    }
+    c2 = wave_sum(c2);
+    c3 = wave_sum(c3);
+    c4 = wave_sum(c4);
+    if (D <= 0) {
+        if (lane < 16) s[lane] = 0.0;
+    }
+    if (lane < 32) s[16 + lane] = D > 0 ? (double)hist[lane] / (double)D : 0.0;
+    if (lane >= 53) s[lane] = 0.0;
+    if (lane == 0) {
+        double v2 = 0.0, v3 = 0.0, v4 = 0.0;
+        if (D > 0) {
+            v2 = c2 / (double)D;
+            v3 = c3 / (double)D;
+            v4 = c4 / (double)D;
+        }
+        const double sd = sqrt(v2);
+        s[48] = m1 / 10.0;
+        s[49] = sd / 10.0;
+        s[50] = v2 > 0 ? v3 / (v2 * sd) : 0.0;
+        s[51] = v2 > 0 ? (v4 / (v2 * v2) - 3.0) / 10.0 : 0.0;
+        s[52] = D > 0 ? log((double)D) / 10.0 : 0.0;
+    }
+    __syncthreads();
+}
+
+__device__ __forceinline__ void gmm_bin(int *hist, double y) {
+    int b = (int)floor(y + 16.0);
+    b = b < 0 ? 0 : (b > 31 ? 31 : b);
+    atomicAdd(&hist[b], 1);
+}
+
+// -------------------------------------------------- training simulation --
+template <int MODEL>
+__global__ __launch_bounds__(64 * kSimWaves) void simulate_kernel(SimSpec sp, int B, Key key,
+                                                                  const int64_t *__restrict__ step_ptr,
+                                                                  uint16_t *__restrict__ x_row,
+                                                                  uint16_t *__restrict__ x_col,
+                                                                  double *__restrict__ theta,
+                                                                  double *__restrict__ s64) {
+#pragma clang fp contract(off)
+    extern __shared__ double ys_all[];
+    __shared__ double tot_all[kSimWaves][kPolyAcc];
+    __shared__ double s_all[kSimWaves][kSummaryDim];
+    __shared__ int hist_all[kSimWaves][32];
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    const int b = blockIdx.x * kSimWaves + wv;
+    const uint32_t step = (uint32_t)*step_ptr;
+    const uint32_t pair = (uint32_t)b;
+    const int64_t D = sp.D;
+    double *s = s_all[wv];
+
+    if constexpr (MODEL == PPL_MODEL_POLY) {
+        const uint4 w0 = philox(pair, 0, step, kTagTrain, key);
+        const int n = uniform_discrete(w0.x, (int)sp.hyper[1], (uint32_t)((int)sp.hyper[2] - (int)sp.hyper[1] + 1));
+        double z[8];
+        {
+            const uint4 w1 = philox(pair, 1, step, kTagTrain, key), w2 = philox(pair, 2, step, kTagTrain, key);
+            box_muller(u01(w1.x), u01(w1.y), z[0], z[1]);
+            box_muller(u01(w1.z), u01(w1.w), z[2], z[3]);
+            box_muller(u01(w2.x), u01(w2.y), z[4], z[5]);
+            box_muller(u01(w2.z), u01(w2.w), z[6], z[7]);
+        }
+        double c[5];
+#pragma unroll
+        for (int j = 0; j < 5; ++j) c[j] = sp.hyper[0] * z[j];
+        double a[kPolyAcc];
+#pragma unroll
+        for (int k = 0; k < kPolyAcc; ++k) a[k] = 0.0;
+        for (int64_t e = lane; 2 * e < D; e += 64) {
+            const uint4 w = philox(pair, (uint32_t)(8 + e), step, kTagTrain, key);
+            double e0, e1;
+            box_muller(u01(w.z), u01(w.w), e0, e1);
+#pragma unroll
+            for (int h = 0; h < 2; ++h) {
+                if (2 * e + h < D) {
+                    const double x = 2.0 * u01(h ? w.y : w.x) - 1.0;
+                    double p = 0.0;
+#pragma unroll
+                    for (int j = 4; j >= 0; --j)
+                        if (j < n) p = p * x + c[j];
+                    const double y = p + sp.hyper[3] * (h ? e1 : e0);
+                    poly_acc_point(a, x, y);
+                }
+            }
+        }
+        poly_finish(a, D, tot_all[wv], s);
+        if (lane < 6) theta[(size_t)b * kThetaStride + lane] = lane == 0 ? (double)n : (lane - 1 < n ? c[lane - 1] : 0.0);
+    } else {
+        const int K = sp.K;
+        double *ys = ys_all + (size_t)wv * ((D + 1) & ~(int64_t)1);
+        int *hist = hist_all[wv];
+        if (lane < 32) hist[lane] = 0;
+        const uint4 wa = philox(pair, 0, step, kTagTrain, key), wb = philox(pair, 1, step, kTagTrain, key);
+        const uint32_t ew[8] = {wa.x, wa.y, wa.z, wa.w, wb.x, wb.y, wb.z, wb.w};
+        double E[8], pi[8], mu[8], z[8], tot = 0.0;
+#pragma unroll
+        for (int k = 0; k < 8; ++k) {
+            E[k] = k < K ? -log(u01(ew[k])) : 0.0;
+            if (k < K) tot += E[k];
+        }
+#pragma unroll
+        for (int k = 0; k < 8; ++k) pi[k] = k < K ? E[k] / tot : 0.0;
+        {
+            const uint4 w2 = philox(pair, 2, step, kTagTrain, key), w3 = philox(pair, 3, step, kTagTrain, key);
+            box_muller(u01(w2.x), u01(w2.y), z[0], z[1]);
+            box_muller(u01(w2.z), u01(w2.w), z[2], z[3]);
+            box_muller(u01(w3.x), u01(w3.y), z[4], z[5]);
+            box_muller(u01(w3.z), u01(w3.w), z[6], z[7]);
+        }
+#pragma unroll
+        for (int k = 0; k < 8; ++k) mu[k] = sp.hyper[0] * z[k];
+        __syncthreads();
+        double sum_y = 0.0;
+        for (int64_t e = lane; 2 * e < D; e += 64) {
+            const uint4 w = philox(pair, (uint32_t)(8 + e), step, kTagTrain, key);
+            double e0, e1;
+            box_muller(u01(w.z), u01(w.w), e0, e1);
+#pragma unroll
+            for (int h = 0; h < 2; ++h) {
+                if (2 * e + h < D) {
+                    const int k = categorical8(u01(h ? w.y : w.x), pi, K);
+                    const double y = pick8(mu, k) + sp.hyper[1] * (h ? e1 : e0);
+                    ys[2 * e + h] = y;
+                    sum_y += y;
+                    gmm_bin(hist, y);
+                }
+            }
+        }
+        __syncthreads();
+        gmm_finish(ys, D, hist, sum_y, s);
+        if (lane == 0) {
+            // order the components by mean (insertion sort; ties keep index order)
+            int ord[8] = {0, 1, 2, 3, 4, 5, 6, 7};
+            for (int q = 1; q < K; ++q)
+                for (int r = q; r > 0 && mu[ord[r]] < mu[ord[r - 1]]; --r) {
+                    const int t = ord[r];
+                    ord[r] = ord[r - 1];
+                    ord[r - 1] = t;
+                }
+            double *u = theta + (size_t)b * kThetaStride;
+            u[0] = mu[ord[0]];
+            for (int q = 1; q < K; ++q) u[q] = log(mu[ord[q]] - mu[ord[q - 1]]);
+            const double lk = log(pi[ord[K - 1]]);
+            for (int q = 0; q < K - 1; ++q) u[K + q] = log(pi[ord[q]]) - lk;
+        }
+    }
+    const double v = s[lane];
+    const uint16_t h = f32_to_bf16((float)v);
+    x_row[(size_t)b * kSummaryDim + lane] = h;
+    x_col[(size_t)lane * B + b] = h;
+    if (s64) s64[(size_t)b * kSummaryDim + lane] = v;
+}
+
+// ----------------------------------------------------- observed summary --
+template <int MODEL>
+__global__ __launch_bounds__(64) void observed_summary_kernel(const void *__restrict__ xv, const void *__restrict__ yv,
+                                                              int64_t D, uint16_t *__restrict__ x_row,
+                                                              double *__restrict__ s64) {
+#pragma clang fp contract(off)
+    extern __shared__ float ys[];
+    __shared__ double tot[kPolyAcc];
+    __shared__ double s[kSummaryDim];
+    __shared__ int hist[32];
+    const int lane = threadIdx.x;
+    if constexpr (MODEL == PPL_MODEL_POLY) {
+        const double *X = (const double *)xv, *Y = (const double *)yv;
+        double a[kPolyAcc];
+#pragma unroll
+        for (int k = 0; k < kPolyAcc; ++k) a[k] = 0.0;
+        for (int64_t d = lane; d < D; d += 64) poly_acc_point(a, X[d], Y[d]);
+        poly_finish(a, D, tot, s);
+    } else {
+        const float *Y = (const float *)yv;
+        if (lane < 32) hist[lane] = 0;
+        __syncthreads();
+        double sum_y = 0.0;
+        for (int64_t d = lane; d < D; d += 64) {
+            const float yf = Y[d];
+            ys[d] = yf;
+            sum_y += (double)yf;
+            gmm_bin(hist, (double)yf);
+        }
+        __syncthreads();
+        gmm_finish(ys, D, hist, sum_y, s);
+    }
+    const double v = s[lane];
+    x_row[lane] = f32_to_bf16((float)v);
+    for (int r = 1; r < 64; ++r) x_row[(size_t)r * kSummaryDim + lane] = 0;
+    if (s64) s64[lane] = v;
+}
+
+// ------------------------------------------------------------------ host --
+int launch_simulate(const SimSpec &sp, int B, uint64_t seed, const int64_t *step, uint16_t *x_row, uint16_t *x_col,
+                    double *theta, double *s64, hipStream_t st) {
+    if (B <= 0 || B % kSimWaves) return fail(PPL_E_ARG, "simulation batch %d is not a positive multiple of 4", B);
+    const dim3 grid((unsigned)(B / kSimWaves)), block(64 * kSimWaves);
+    if (sp.model == PPL_MODEL_POLY) {
+        hipLaunchKernelGGL(simulate_kernel<PPL_MODEL_POLY>, grid, block, 0, st, sp, B, make_key(seed), step, x_row,
+                           x_col, theta, s64);
+        PPL_LAUNCH_CHECK("simulate_kernel<POLY>");
+    } else {
+        if (sp.D > kGmmTrainMaxD) return fail(PPL_E_ARG, "mixture training datasets hold at most %d points", kGmmTrainMaxD);
+        const size_t lds = (size_t)kSimWaves * ((sp.D + 1) & ~(int64_t)1) * sizeof(double);
+        hipLaunchKernelGGL(simulate_kernel<PPL_MODEL_GMM>, grid, block, lds, st, sp, B, make_key(seed), step, x_row,
+                           x_col, theta, s64);
+        PPL_LAUNCH_CHECK("simulate_kernel<GMM>");
+    }
+    return PPL_OK;
+}
+
+int launch_observed_summary(int model, const void *x, const void *y, int64_t D, uint16_t *x_row, double *s64,
+                            hipStream_t st) {
+    if (model == PPL_MODEL_POLY) {
+        hipLaunchKernelGGL(observed_summary_kernel<PPL_MODEL_POLY>, dim3(1), dim3(64), 0, st, x, y, D, x_row, s64);
+    } else {
+        if (D > kGmmSummaryMaxD) return fail(PPL_E_ARG, "mixture summaries take at most %d points", kGmmSummaryMaxD);
+        const size_t lds = (size_t)(D > 0 ? D : 1) * sizeof(float);
+        hipLaunchKernelGGL(observed_summary_kernel<PPL_MODEL_GMM>, dim3(1), dim3(64), lds, st, x, y, D, x_row, s64);
+    }
+    PPL_LAUNCH_CHECK("observed_summary_kernel");
+    return PPL_OK;
+}
+
+}  // namespace ppl

@@ -18,4 +18,12 @@ private:
     hipEvent_t a_;
 };
 
+// While an instance lives on this thread, KernelTimer records nothing (used
+// while a stream is being captured into a graph).
+class TimingSuspend {
+public:
+    TimingSuspend();
+    ~TimingSuspend();
+};
+
 }  // namespace ppl

@@ -25,6 +25,7 @@ std::mutex g_mu;
 std::vector<Pending> g_pending;
 std::vector<hipEvent_t> g_pool;
 std::map<std::string, std::pair<double, int64_t>> g_acc;
+thread_local int t_suspended = 0;
 
 hipEvent_t take_event() {
     if (!g_pool.empty()) {
@@ -54,7 +55,7 @@ int drain_locked() {
 }  // namespace
 
 KernelTimer::KernelTimer(const char *name, hipStream_t st) : name_(name), st_(st), a_(nullptr) {
-    if (!g_on.load(std::memory_order_relaxed)) return;
+    if (!g_on.load(std::memory_order_relaxed) || t_suspended) return;
     std::lock_guard<std::mutex> lk(g_mu);
     a_ = take_event();
     if (a_ && hipEventRecord(a_, st_) != hipSuccess) {
@@ -75,6 +76,9 @@ void KernelTimer::stop() {
     }
     a_ = nullptr;
 }
+
+TimingSuspend::TimingSuspend() { ++t_suspended; }
+TimingSuspend::~TimingSuspend() { --t_suspended; }
 
 }  // namespace ppl
 

@@ -1,0 +1,478 @@
+// train.hip -- training of the proposal network: mixture-density loss head,
+// backward pass, Adam, weight initialisation and the decoded proposal.
+//
+// The network (64 -> 256 -> 256 -> 256, ReLU after the first two layers, BF16
+// MFMA products with FP32 accumulation) maps the summaries s(y) of a dataset
+// to the parameters of an 8-component diagonal Gaussian mixture q(theta | y)
+// over the model's latents; the loss is the mean of -log q(theta_i | y_i)
+// over pairs (theta_i, y_i) simulated from the model's prior.  BF16 is stored
+// at the network inputs, the weights, the hidden activations and the
+// back-propagated gradients; biases, FP32 master weights and Adam moments
+// stay FP32.
+//
+// Output head (256 network outputs o):
+//   POLY: o[0:4] degree logits (n = 2..5), o[4:12] mixture logits shared by
+//         all degrees; for degree n a block at 12 + 8 (n - 2)(n + 1) holding
+//         8n means (10 o) then 8n log-scales (5 tanh(o / 5)), component-major.
+//   GMM (K components, d = 2K - 1 ordered unconstrained latents): o[0:8]
+//         mixture logits, o[8 : 8 + 8d] means (5 o), then 8d log-scales.
+#include "device.h"
+#include "host.h"
+#include "proposal.h"
+#include "timing.h"
+
+namespace ppl {
+
+constexpr float kHalfLog2Pi = 0.91893853320467274f;
+constexpr uint32_t kTagInit = 5;
+constexpr int kLdsRow = 258;          // BF16 per LDS row of the head (odd word stride)
+
+__host__ __device__ constexpr int poly_head_off(int n) { return 12 + 8 * (n - 2) * (n + 1); }
+
+// ---------------------------------------------------------------- head --
+// One thread per training pair; 64 pairs per workgroup.  The gradient of the
+// loss w.r.t. the outputs, divided by the batch size, is rounded to BF16 and
+// staged in LDS so both the row-major and column-major copies are written
+// with coalesced stores.
+template <int MODEL>
+__global__ __launch_bounds__(64) void head_kernel(const float *__restrict__ o_col, int B,
+                                                  const double *__restrict__ theta, int K, float inv_b,
+                                                  uint16_t *__restrict__ do_row, uint16_t *__restrict__ do_col,
+                                                  double *__restrict__ lossp) {
+    __shared__ uint32_t lds32[64 * kLdsRow / 2];
+    uint16_t *lds = (uint16_t *)lds32;
+    const int lane = threadIdx.x;
+    const int b0 = blockIdx.x * 64, b = b0 + lane;
+    for (int k = 0; k < kLdsRow / 2; ++k) lds32[lane * (kLdsRow / 2) + k] = 0u;
+    uint16_t *g = lds + lane * kLdsRow;
+    const float *o = o_col + b;            // output k at o[k * B]
+    const double *th = theta + (size_t)b * kThetaStride;
+    float loss;
+    if constexpr (MODEL == PPL_MODEL_POLY) {
+        const int n = min(max((int)th[0], 2), 5);
+        float c[5];
+#pragma unroll
+        for (int j = 0; j < 5; ++j) c[j] = (float)th[1 + j];
+        float z[4], lm[8];
+        float mx = -INFINITY;
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+            z[k] = o[(size_t)k * B];
+            mx = fmaxf(mx, z[k]);
+        }
+        float se = 0.0f;
+#pragma unroll
+        for (int k = 0; k < 4; ++k) se += expf(z[k] - mx);
+        const float lse_n = mx + logf(se);
+        float mm = -INFINITY;
+#pragma unroll
+        for (int k = 0; k < 8; ++k) {
+            lm[k] = o[(size_t)(4 + k) * B];
+            mm = fmaxf(mm, lm[k]);
+        }
+        float sm = 0.0f;
+#pragma unroll
+        for (int k = 0; k < 8; ++k) sm += expf(lm[k] - mm);
+        const float lse_m = mm + logf(sm);
+#pragma unroll
+        for (int k = 0; k < 8; ++k) lm[k] -= lse_m;
+        const int off = poly_head_off(n);
+        float t[8];
+#pragma unroll
+        for (int m = 0; m < 8; ++m) {
+            float acc = lm[m];
+#pragma unroll
+            for (int j = 0; j < 5; ++j) {
+                if (j < n) {
+                    const float mu = 10.0f * o[(size_t)(off + m * n + j) * B];
+                    const float lsd = 5.0f * tanhf(o[(size_t)(off + 8 * n + m * n + j) * B] * 0.2f);
+                    const float r = (c[j] - mu) * expf(-lsd);
+                    acc += -0.5f * r * r - lsd - kHalfLog2Pi;
+                }
+            }
+            t[m] = acc;
+        }
+        float tm = -INFINITY;
+#pragma unroll
+        for (int m = 0; m < 8; ++m) tm = fmaxf(tm, t[m]);
+        float st = 0.0f;
+#pragma unroll
+        for (int m = 0; m < 8; ++m) st += expf(t[m] - tm);
+        const float L = tm + logf(st);
+        loss = -(z[n - 2] - lse_n) - L;
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+            const float gk = expf(z[k] - lse_n) - (k == n - 2 ? 1.0f : 0.0f);
+            g[k] = f32_to_bf16(gk * inv_b);
+        }
+#pragma unroll
+        for (int m = 0; m < 8; ++m) {
+            const float resp = expf(t[m] - L);
+            g[4 + m] = f32_to_bf16((expf(lm[m]) - resp) * inv_b);
+#pragma unroll
+            for (int j = 0; j < 5; ++j) {
+                if (j < n) {
+                    const int km = off + m * n + j, ks = off + 8 * n + m * n + j;
+                    const float mu = 10.0f * o[(size_t)km * B];
+                    const float th5 = tanhf(o[(size_t)ks * B] * 0.2f);
+                    const float iv = expf(-5.0f * th5);
+                    const float dv = c[j] - mu;
+                    const float r = dv * iv;
+                    g[km] = f32_to_bf16(-resp * dv * iv * iv * 10.0f * inv_b);
+                    g[ks] = f32_to_bf16(-resp * (r * r - 1.0f) * (1.0f - th5 * th5) * inv_b);
+                }
+            }
+        }
+    } else {
+        const int d = 2 * K - 1;
+        float lm[8];
+        float mm = -INFINITY;
+#pragma unroll
+        for (int k = 0; k < 8; ++k) {
+            lm[k] = o[(size_t)k * B];
+            mm = fmaxf(mm, lm[k]);
+        }
+        float sm = 0.0f;
+#pragma unroll
+        for (int k = 0; k < 8; ++k) sm += expf(lm[k] - mm);
+        const float lse_m = mm + logf(sm);
+#pragma unroll
+        for (int k = 0; k < 8; ++k) lm[k] -= lse_m;
+        float t[8];
+#pragma unroll
+        for (int m = 0; m < 8; ++m) {
+            float acc = lm[m];
+            for (int j = 0; j < d; ++j) {
+                const float mu = 5.0f * o[(size_t)(8 + m * d + j) * B];
+                const float lsd = 5.0f * tanhf(o[(size_t)(8 + 8 * d + m * d + j) * B] * 0.2f);
+                const float r = ((float)th[j] - mu) * expf(-lsd);
+                acc += -0.5f * r * r - lsd - kHalfLog2Pi;
+            }
+            t[m] = acc;
+        }
+        float tm = -INFINITY;
+#pragma unroll
+        for (int m = 0; m < 8; ++m) tm = fmaxf(tm, t[m]);
+        float st = 0.0f;
+#pragma unroll
+        for (int m = 0; m < 8; ++m) st += expf(t[m] - tm);
+        const float L = tm + logf(st);
+        loss = -L;
+#pragma unroll
+        for (int m = 0; m < 8; ++m) {
+            const float resp = expf(t[m] - L);
+            g[m] = f32_to_bf16((expf(lm[m]) - resp) * inv_b);
+            for (int j = 0; j < d; ++j) {
+                const int km = 8 + m * d + j, ks = 8 + 8 * d + m * d + j;
+                const float mu = 5.0f * o[(size_t)km * B];
+                const float th5 = tanhf(o[(size_t)ks * B] * 0.2f);
+                const float iv = expf(-5.0f * th5);
+                const float dv = (float)th[j] - mu;
+                const float r = dv * iv;
+                g[km] = f32_to_bf16(-resp * dv * iv * iv * 5.0f * inv_b);
+                g[ks] = f32_to_bf16(-resp * (r * r - 1.0f) * (1.0f - th5 * th5) * inv_b);
+            }
+        }
+    }
+    const double ls = wave_sum((double)loss);
+    if (lane == 0) lossp[blockIdx.x] = ls;
+    __syncthreads();
+    for (int k = 0; k < kMlpOut; ++k) do_col[(size_t)k * B + b] = lds[lane * kLdsRow + k];
+    for (int r = 0; r < 64; ++r)
+#pragma unroll
+        for (int q = 0; q < 4; ++q) do_row[(size_t)(b0 + r) * kMlpOut + q * 64 + lane] = lds[r * kLdsRow + q * 64 + lane];
+}
+
+// ------------------------------------------------------ bias gradients --
+// bgrad[l][o] = sum over the batch of the BF16 gradient column o of layer l
+// (FP32, a fixed order: 256 strided lane sums, then a tree).
+__global__ __launch_bounds__(256) void bias_grad_kernel(const uint16_t *__restrict__ g1, const uint16_t *__restrict__ g2,
+                                                        const uint16_t *__restrict__ g3, int B,
+                                                        float *__restrict__ bgrad) {
+    __shared__ float red[4];
+    const int unit = blockIdx.x, l = unit >> 8, o = unit & 255;
+    const uint16_t *g = (l == 0 ? g1 : (l == 1 ? g2 : g3)) + (size_t)o * B;
+    float s = 0.0f;
+    for (int b = threadIdx.x; b < B; b += 256) s += bf16_to_f32(g[b]);
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) s += __shfl_xor(s, off, 64);
+    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = s;
+    __syncthreads();
+    if (threadIdx.x == 0) bgrad[unit] = (red[0] + red[1]) + (red[2] + red[3]);
+}
+
+// ------------------------------------------------------------ update --
+struct SplitParts {
+    const float *p[3];
+    int nc[3];
+};
+
+// Gradient of parameter e: weights sum their split-R partials in chunk order,
+// biases come from bgrad.  grad != null: store it; else one Adam step
+// (bias-corrected moments, step t = completed steps + 1) and refresh both
+// BF16 weight layouts.
+__global__ __launch_bounds__(256) void adam_kernel(MlpView w, SplitParts sp, const float *__restrict__ bgrad, AdamSpec ad,
+                                                   float *__restrict__ grad) {
+    const int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (e >= MlpParams::count()) return;
+    int l = 0;
+    if (e >= MlpParams::w_off(2)) l = 2;
+    else if (e >= MlpParams::w_off(1)) l = 1;
+    const int in = MlpParams::in(l), out = MlpParams::out(l);
+    const int64_t local = e - MlpParams::w_off(l);
+    const bool is_w = local < (int64_t)in * out;
+    float gv;
+    if (is_w) {
+        const float *p = sp.p[l];
+        const int64_t sz = (int64_t)in * out;
+        gv = 0.0f;
+        for (int c = 0; c < sp.nc[l]; ++c) gv += p[(size_t)c * sz + local];
+    } else {
+        gv = bgrad[l * 256 + (int)(local - (int64_t)in * out)];
+    }
+    if (grad) {
+        grad[e] = gv;
+        return;
+    }
+    const double t = (double)(*w.step + 1);
+    const float bc1 = (float)(1.0 - pow((double)ad.b1, t));
+    const float bc2 = (float)(1.0 - pow((double)ad.b2, t));
+    const float m = ad.b1 * w.m[e] + (1.0f - ad.b1) * gv;
+    const float v = ad.b2 * w.v[e] + (1.0f - ad.b2) * gv * gv;
+    const float p = w.master[e] - ad.lr * (m / bc1) / (sqrtf(v / bc2) + ad.eps);
+    w.m[e] = m;
+    w.v[e] = v;
+    w.master[e] = p;
+    if (is_w) {
+        const int o = (int)(local / in), i = (int)(local % in);
+        const uint16_t h = f32_to_bf16(p);
+        w.wt[MlpParams::bf16_w_off(l) + local] = h;
+        w.w[MlpParams::bf16_w_off(l) + (int64_t)i * out + o] = h;
+    }
+}
+
+__global__ __launch_bounds__(64) void advance_kernel(int64_t *__restrict__ step, int64_t *__restrict__ local,
+                                                     const double *__restrict__ lossp, int nparts, double inv_b,
+                                                     double *__restrict__ loss_trace) {
+    double s = 0.0;
+    for (int k = threadIdx.x; k < nparts; k += 64) s += lossp[k];
+    s = wave_sum(s);
+    if (threadIdx.x == 0) {
+        const int64_t t = *local;
+        if (loss_trace) loss_trace[t] = s * inv_b;
+        *local = t + 1;
+        if (step) *step = *step + 1;
+    }
+}
+
+__global__ void set_i64_kernel(int64_t *p, int64_t v) { *p = v; }
+
+// Glorot-uniform weights: element e of W_l[out][in] takes word e mod 4 of
+// Philox block (e div 4, l, 0, tag 5), w = (2u - 1) sqrt(6 / (in + out)) in
+// FP32; zero biases and moments; zero step count.
+__global__ __launch_bounds__(256) void init_weights_kernel(MlpView w, Key key, float s0, float s1, float s2) {
+#pragma clang fp contract(off)
+    const int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (e == 0) *w.step = 0;
+    if (e >= MlpParams::count()) return;
+    int l = 0;
+    if (e >= MlpParams::w_off(2)) l = 2;
+    else if (e >= MlpParams::w_off(1)) l = 1;
+    const int in = MlpParams::in(l), out = MlpParams::out(l);
+    const int64_t local = e - MlpParams::w_off(l);
+    float p = 0.0f;
+    if (local < (int64_t)in * out) {
+        const uint4 q = philox((uint32_t)(local >> 2), (uint32_t)l, 0, kTagInit, key);
+        const uint32_t word = (local & 3) == 0 ? q.x : (local & 3) == 1 ? q.y : (local & 3) == 2 ? q.z : q.w;
+        const float scale = l == 0 ? s0 : (l == 1 ? s1 : s2);
+        p = (2.0f * unit_f32(word) - 1.0f) * scale;
+        const int o = (int)(local / in), i = (int)(local % in);
+        const uint16_t h = f32_to_bf16(p);
+        w.wt[MlpParams::bf16_w_off(l) + local] = h;
+        w.w[MlpParams::bf16_w_off(l) + (int64_t)i * out + o] = h;
+    }
+    w.master[e] = p;
+    w.m[e] = 0.0f;
+    w.v[e] = 0.0f;
+}
+
+// -------------------------------------------------------------- decode --
+// FP64 proposal parameters from network output column 0.
+//   POLY: {log-softmax of the degree logits [4], log-softmax of the mixture
+//          logits [8], mean[4][8][5], lsd[4][8][5]} (slots j >= n zero).
+//   GMM:  {log-softmax of the mixture logits [8], mean[8][d], lsd[8][d]}.
+__global__ __launch_bounds__(64) void decode_kernel(int model, int K, const float *__restrict__ o_col, int ld,
+                                                    double *__restrict__ q) {
+    const int lane = threadIdx.x;
+    auto O = [&](int k) { return (double)o_col[(size_t)k * ld]; };
+    auto logsoftmax = [&](int base, int n, double *dst) {
+        double m = -INFINITY;
+        for (int k = 0; k < n; ++k) m = fmax(m, O(base + k));
+        double s = 0.0;
+        for (int k = 0; k < n; ++k) s += exp(O(base + k) - m);
+        const double ls = log(s);
+        for (int k = 0; k < n; ++k) dst[k] = O(base + k) - m - ls;
+    };
+    if (model == PPL_MODEL_POLY) {
+        if (lane == 0) logsoftmax(0, 4, q);
+        if (lane == 1) logsoftmax(4, 8, q + 4);
+        for (int e = lane; e < 160; e += 64) {
+            const int n = 2 + e / 40, m = (e / 5) % 8, j = e % 5;
+            const int off = poly_head_off(n);
+            q[12 + e] = j < n ? 10.0 * O(off + m * n + j) : 0.0;
+            q[172 + e] = j < n ? 5.0 * tanh(O(off + 8 * n + m * n + j) / 5.0) : 0.0;
+        }
+    } else {
+        const int d = 2 * K - 1;
+        if (lane == 0) logsoftmax(0, 8, q);
+        for (int e = lane; e < 8 * d; e += 64) {
+            q[8 + e] = 5.0 * O(8 + e);
+            q[8 + 8 * d + e] = 5.0 * tanh(O(8 + 8 * d + e) / 5.0);
+        }
+    }
+}
+
+// ---------------------------------------------------------------- host --
+static size_t a256(size_t v) { return align_up(v, 256); }
+
+size_t train_ws_bytes(int B) {
+    int nc[3], ch[3];
+    mlp_split_plan(kMlpHid, kMlpIn, B, &nc[0], &ch[0]);
+    mlp_split_plan(kMlpHid, kMlpHid, B, &nc[1], &ch[1]);
+    mlp_split_plan(kMlpOut, kMlpHid, B, &nc[2], &ch[2]);
+    const size_t bB = (size_t)B;
+    size_t n = 0;
+    n += 2 * a256(bB * kSummaryDim * 2);                 // x row / col
+    n += a256(bB * kThetaStride * 8);                    // theta
+    n += 4 * a256(bB * kMlpHid * 2);                     // h1, h2 row / col
+    n += a256(bB * kMlpOut * 4);                         // o_col
+    n += 5 * a256(bB * kMlpOut * 2);                     // do row/col, dh2 row/col, dh1 col
+    n += a256((size_t)nc[0] * kMlpHid * kMlpIn * 4);
+    n += a256((size_t)nc[1] * kMlpHid * kMlpHid * 4);
+    n += a256((size_t)nc[2] * kMlpOut * kMlpHid * 4);
+    n += a256(3 * 256 * 4);                              // bgrad
+    n += a256((bB / 64 + 1) * 8);                        // loss partials
+    n += 256;                                            // local counter
+    return n;
+}
+
+TrainBufs train_bufs(void *ws, int B) {
+    TrainBufs t{};
+    t.B = B;
+    mlp_split_plan(kMlpHid, kMlpIn, B, &t.nchunks[0], &t.chunk[0]);
+    mlp_split_plan(kMlpHid, kMlpHid, B, &t.nchunks[1], &t.chunk[1]);
+    mlp_split_plan(kMlpOut, kMlpHid, B, &t.nchunks[2], &t.chunk[2]);
+    char *p = (char *)ws;
+    const size_t bB = (size_t)B;
+    auto take = [&](size_t bytes) {
+        char *r = p;
+        p += a256(bytes);
+        return (void *)r;
+    };
+    t.x_row = (uint16_t *)take(bB * kSummaryDim * 2);
+    t.x_col = (uint16_t *)take(bB * kSummaryDim * 2);
+    t.theta = (double *)take(bB * kThetaStride * 8);
+    t.h1_row = (uint16_t *)take(bB * kMlpHid * 2);
+    t.h1_col = (uint16_t *)take(bB * kMlpHid * 2);
+    t.h2_row = (uint16_t *)take(bB * kMlpHid * 2);
+    t.h2_col = (uint16_t *)take(bB * kMlpHid * 2);
+    t.o_col = (float *)take(bB * kMlpOut * 4);
+    t.do_row = (uint16_t *)take(bB * kMlpOut * 2);
+    t.do_col = (uint16_t *)take(bB * kMlpOut * 2);
+    t.dh2_row = (uint16_t *)take(bB * kMlpOut * 2);
+    t.dh2_col = (uint16_t *)take(bB * kMlpOut * 2);
+    t.dh1_col = (uint16_t *)take(bB * kMlpOut * 2);
+    t.part[0] = (float *)take((size_t)t.nchunks[0] * kMlpHid * kMlpIn * 4);
+    t.part[1] = (float *)take((size_t)t.nchunks[1] * kMlpHid * kMlpHid * 4);
+    t.part[2] = (float *)take((size_t)t.nchunks[2] * kMlpOut * kMlpHid * 4);
+    t.bgrad = (float *)take(3 * 256 * 4);
+    t.lossp = (double *)take((bB / 64 + 1) * 8);
+    t.local = (int64_t *)take(16);
+    return t;
+}
+
+int launch_forward(const MlpView &w, const TrainBufs &b, bool keep_cols, hipStream_t st) {
+    const int epi = kEpiBias | kEpiRelu | kEpiOutRow | (keep_cols ? kEpiOutCol : 0);
+    if (int rc = mlp_gemm(b.x_row, w.wt + MlpParams::bf16_w_off(0), b.B, kMlpHid, kMlpIn, kMlpIn, kMlpIn, epi,
+                          w.master + MlpParams::b_off(0), nullptr, b.h1_row, b.h1_col, nullptr, st))
+        return rc;
+    if (int rc = mlp_gemm(b.h1_row, w.wt + MlpParams::bf16_w_off(1), b.B, kMlpHid, kMlpHid, kMlpHid, kMlpHid, epi,
+                          w.master + MlpParams::b_off(1), nullptr, b.h2_row, b.h2_col, nullptr, st))
+        return rc;
+    return mlp_gemm(b.h2_row, w.wt + MlpParams::bf16_w_off(2), b.B, kMlpOut, kMlpHid, kMlpHid, kMlpHid,
+                    kEpiBias | kEpiOutF32Col, w.master + MlpParams::b_off(2), nullptr, nullptr, nullptr, b.o_col, st);
+}
+
+int launch_head_backward(int model, int K, const MlpView &w, const TrainBufs &b, hipStream_t st) {
+    const int B = b.B;
+    const float inv_b = 1.0f / (float)B;
+    {
+        KernelTimer timer("head_kernel", st);
+        if (model == PPL_MODEL_POLY)
+            hipLaunchKernelGGL(head_kernel<PPL_MODEL_POLY>, dim3(B / 64), dim3(64), 0, st, b.o_col, B, b.theta, K,
+                               inv_b, b.do_row, b.do_col, b.lossp);
+        else
+            hipLaunchKernelGGL(head_kernel<PPL_MODEL_GMM>, dim3(B / 64), dim3(64), 0, st, b.o_col, B, b.theta, K,
+                               inv_b, b.do_row, b.do_col, b.lossp);
+        timer.stop();
+        PPL_LAUNCH_CHECK("head_kernel");
+    }
+    // layer 3: dW3 = dO^T H2, dH2 = (dO W3) * [H2 > 0]
+    if (int rc = mlp_gemm_splitr(b.do_col, b.h2_col, kMlpOut, kMlpHid, B, B, B, b.chunk[2], b.part[2], st)) return rc;
+    if (int rc = mlp_gemm(b.do_row, w.w + MlpParams::bf16_w_off(2), B, kMlpHid, kMlpOut, kMlpOut, kMlpOut,
+                          kEpiMaskRow | kEpiOutRow | kEpiOutCol, nullptr, b.h2_row, b.dh2_row, b.dh2_col, nullptr, st))
+        return rc;
+    // layer 2: dW2 = dH2^T H1, dH1 = (dH2 W2) * [H1 > 0]
+    if (int rc = mlp_gemm_splitr(b.dh2_col, b.h1_col, kMlpHid, kMlpHid, B, B, B, b.chunk[1], b.part[1], st)) return rc;
+    if (int rc = mlp_gemm(b.dh2_row, w.w + MlpParams::bf16_w_off(1), B, kMlpHid, kMlpHid, kMlpHid, kMlpHid,
+                          kEpiMaskRow | kEpiOutCol, nullptr, b.h1_row, nullptr, b.dh1_col, nullptr, st))
+        return rc;
+    // layer 1: dW1 = dH1^T X
+    if (int rc = mlp_gemm_splitr(b.dh1_col, b.x_col, kMlpHid, kMlpIn, B, B, B, b.chunk[0], b.part[0], st)) return rc;
+    hipLaunchKernelGGL(bias_grad_kernel, dim3(3 * 256), dim3(256), 0, st, b.dh1_col, b.dh2_col, b.do_col, B, b.bgrad);
+    PPL_LAUNCH_CHECK("bias_grad_kernel");
+    return PPL_OK;
+}
+
+int launch_update(const MlpView &w, const TrainBufs &b, const AdamSpec &ad, float *grad, hipStream_t st) {
+    SplitParts sp;
+    for (int l = 0; l < 3; ++l) {
+        sp.p[l] = b.part[l];
+        sp.nc[l] = b.nchunks[l];
+    }
+    const int blocks = (int)((MlpParams::count() + 255) / 256);
+    hipLaunchKernelGGL(adam_kernel, dim3(blocks), dim3(256), 0, st, w, sp, (const float *)b.bgrad, ad, grad);
+    PPL_LAUNCH_CHECK("adam_kernel");
+    return PPL_OK;
+}
+
+int launch_advance(int64_t *step, const TrainBufs &b, double *loss_trace, hipStream_t st) {
+    hipLaunchKernelGGL(advance_kernel, dim3(1), dim3(64), 0, st, step, b.local, (const double *)b.lossp, b.B / 64,
+                       1.0 / (double)b.B, loss_trace);
+    PPL_LAUNCH_CHECK("advance_kernel");
+    return PPL_OK;
+}
+
+int launch_set_i64(int64_t *p, int64_t v, hipStream_t st) {
+    hipLaunchKernelGGL(set_i64_kernel, dim3(1), dim3(1), 0, st, p, v);
+    PPL_LAUNCH_CHECK("set_i64_kernel");
+    return PPL_OK;
+}
+
+int launch_init_weights(void *weights, uint64_t seed, hipStream_t st) {
+    const MlpView w = mlp_view(weights);
+    float s[3];
+    for (int l = 0; l < 3; ++l) s[l] = (float)sqrt(6.0 / (double)(MlpParams::in(l) + MlpParams::out(l)));
+    const int blocks = (int)((MlpParams::count() + 255) / 256);
+    hipLaunchKernelGGL(init_weights_kernel, dim3(blocks), dim3(256), 0, st, w, make_key(seed), s[0], s[1], s[2]);
+    PPL_LAUNCH_CHECK("init_weights_kernel");
+    return PPL_OK;
+}
+
+int launch_decode(int model, int K, const float *o_col, int ld, double *q, hipStream_t st) {
+    hipLaunchKernelGGL(decode_kernel, dim3(1), dim3(64), 0, st, model, K, o_col, ld, q);
+    PPL_LAUNCH_CHECK("decode_kernel");
+    return PPL_OK;
+}
+
+}  // namespace ppl

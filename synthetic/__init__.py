@@ -12,10 +12,12 @@ Workload recipes (sizes and distributions of the configurations measured):
   lgssm : x_0 = 0, x_t = 0.9 x_{t-1} + N(0, 1), y_t = x_t + N(0, 0.5^2)     (float32)
   gmm   : per instance K ~ U{3..8}, pi* ~ Dirichlet(1_K), mu* ~ N(0, 5^2),
           D = floor(10^U[2, 5]), z_d ~ Cat(pi*), y_d = mu*_{z_d} + N(0, 1)  (float32)
+  learned-proposal workloads: poly with D = 1000 (seed SEED_POLY_LEARN); one
+          gmm instance with K = 5 and D = 100 (gmm_learn_data)
 """
 import numpy as np
 
-SEED_POLY, SEED_BLR, SEED_LGSSM, SEED_GMM, SEED_POLY_LEARN = 1000, 1001, 1002, 1003, 1004
+SEED_POLY, SEED_BLR, SEED_LGSSM, SEED_GMM, SEED_POLY_LEARN, SEED_GMM_LEARN = 1000, 1001, 1002, 1003, 1004, 1005
 
 
 def poly_data(D=100, seed=SEED_POLY):
@@ -56,6 +58,15 @@ def gmm_instances(n_inst=256, seed=SEED_GMM, d_lo=2.0, d_hi=5.0, k_lo=3, k_hi=8,
         y = (mu[z] + g.standard_normal(D)).astype(np.float32)
         out.append(dict(K=K, D=D, y=y, pi=pi, mu=mu))
     return out
+
+
+def gmm_learn_data(K=5, D=100, seed=SEED_GMM_LEARN, mu_sd=5.0):
+    """One mixture dataset of the gmm recipe with fixed K and D (float32)."""
+    g = np.random.default_rng(seed)
+    pi = g.dirichlet(np.ones(K))
+    mu = mu_sd * g.standard_normal(K)
+    z = g.choice(K, size=D, p=pi)
+    return (mu[z] + g.standard_normal(D)).astype(np.float32)
 
 
 def logweights(n, kind="normal", seed=0, scale=10.0):
