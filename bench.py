@@ -15,7 +15,8 @@ Printed as one JSON line, with
                   1 FMA square-accumulate);
   cpu_baseline -- the CPU oracle on a bounded sample of the same workload.
 
-Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu] [--config blr|poly|poly-paper]
+Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu]
+                       [--config blr|poly|poly-paper|lgssm|gmm-batched|proposal-poly|proposal-gmm]
 """
 import argparse
 import json
@@ -43,7 +44,9 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--config", default="blr", choices=["blr", "poly", "poly-paper", "lgssm", "gmm-batched"])
+    ap.add_argument("--config", default="blr",
+                    choices=["blr", "poly", "poly-paper", "lgssm", "gmm-batched", "proposal-poly", "proposal-gmm"])
+    ap.add_argument("--batch", type=int, default=0, help="proposal: training batch (default 4096)")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--cpu-seconds", type=float, default=15.0, help="target length of the oracle sample")
     ap.add_argument("--particles", type=int, default=0, help="lgssm: particle count (default 2^20)")
@@ -137,6 +140,180 @@ def cpu_baseline_poly(x, y, n, seed):
             "kind": "oracle", "sample": f"{n} particles over all {y.size} points ({dt:.1f} s)"}
 
 
+BF16_MFMA_TFLOPS = 2500.0
+GEMM_FLOP_PER_PAIR = 2 * 425984      # forward 3 layers + 2 input-gradient + 3 weight-gradient products
+SEEDS_PER_RUNG = 16
+RMSE_TARGET = 0.05
+
+
+def lse_merge(parts):
+    """log-sum-exp merge of FP64 partials (max, s1, s2) over disjoint particle sets."""
+    m = max(p[0] for p in parts)
+    s1 = sum(p[1] * math.exp(p[0] - m) for p in parts)
+    s2 = sum(p[2] * math.exp(2 * (p[0] - m)) for p in parts)
+    return m, s1, s2
+
+
+def bench_proposal(args, ppl, synthetic, torch, dev, stream):
+    """Learned proposal against the prior proposal: ESS per second of the
+    inference call at the smallest power-of-two particle count whose log Z-hat
+    RMSE over 16 seeds is within 0.05 of the reference (the prior proposal's
+    FP64 estimate at 2^32 / 2^34 particles)."""
+    poly = args.config == "proposal-poly"
+    if poly:
+        x, y = synthetic.poly_data(D=1000, seed=synthetic.SEED_POLY_LEARN)
+        data = ppl.make_data(torch.from_numpy(x).to(dev), torch.from_numpy(y).to(dev))
+        model, D, K, ref_chunks = ppl.PPL_MODEL_POLY, 1000, 0, 4
+        kname, op_per_eval = "poly_mix_is_kernel", 10
+        workload = {"workload": "learned-proposal-poly", "model": "polynomial fit (degree ~ U{2..5})", "points": D}
+    else:
+        y = synthetic.gmm_learn_data(K=5, D=100)
+        data = ppl.make_data(None, torch.from_numpy(y).to(dev), dim=5)
+        model, D, K, ref_chunks = ppl.PPL_MODEL_GMM, 100, 5, 16
+        kname, op_per_eval = "gmm_mix_is_kernel", 7 * 5 + 2
+        workload = {"workload": "learned-proposal-gmm", "model": "Gaussian mixture, K = 5", "points": D}
+    chunk = 1 << 30
+    sc = torch.empty(8, dtype=torch.float64, device=dev)
+    ws = ppl.workspace(ppl.ppl_workspace_size(model, data, chunk, ppl.PPL_ALGO_IS), dev)
+    parts = []
+    for c in range(ref_chunks):
+        ppl.ppl_importance(model, data, chunk, 10_000 + c, ws=ws, stream=stream, scalars=sc)
+        parts.append(tuple(sc.cpu().numpy()[4:7]))
+    m, s1, s2 = lse_merge(parts)
+    ref = m + math.log(s1) - math.log(chunk * ref_chunks)
+    ref_ess = s1 * s1 / s2
+    del ws
+
+    # training defaults per model (a sweep of batch, learning rate and decay at 2^22 pairs)
+    B = args.batch or (512 if poly else 256)
+    lr, decay = (1e-3, False) if poly else (3e-3, True)
+    pairs = 1 << 22
+    cfg = ppl.train_config(pairs, B, D, dim=K, lr=lr, use_graph=True, lr_decay_steps=pairs // B if decay else 0,
+                           lr_final_frac=0.02)
+    wts = ppl.ppl_proposal_init(1, stream=stream)
+    tws = ppl.workspace(ppl.ppl_proposal_train_workspace_size(model, cfg), dev)
+    trace = torch.empty(pairs // B, dtype=torch.float64, device=dev)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    ppl.ppl_proposal_train(model, cfg, 1, wts, loss_trace=trace, ws=tws, stream=stream)
+    torch.cuda.synchronize()
+    train_ms = (time.perf_counter() - t0) * 1e3
+    tr = trace.cpu().numpy()
+    # MFMA rate of the network products: a few eager steps on a copy with kernel timing on
+    probe_steps = 16
+    wcopy = wts.clone()
+    pcfg = ppl.train_config(probe_steps * B, B, D, dim=K, lr=lr)
+    ppl.ppl_timing_enable(True)
+    ppl.ppl_proposal_train(model, pcfg, 1, wcopy, ws=tws, stream=stream)
+    torch.cuda.synchronize()
+    g_ms, g_n = ppl.ppl_timing_query("gemm_nt_kernel")
+    ppl.ppl_timing_enable(False)
+    gemm_tflops = GEMM_FLOP_PER_PAIR * B * probe_steps / (g_ms / 1e3) / 1e12
+    # adaptive tempering of the proposal for this dataset (pilot ESS, no reference)
+    t0 = time.perf_counter()
+    widen, pilot = ppl.ppl_proposal_pick_widen(model, data, wts, stream=stream)
+    pilot_ms = (time.perf_counter() - t0) * 1e3
+
+    def ladder(learned, n_lo, n_hi):
+        iws = None
+        for lg in range(n_lo, n_hi + 1):
+            N = 1 << lg
+            need = (ppl.ppl_proposal_infer_workspace_size(model, data, N) if learned
+                    else ppl.ppl_workspace_size(model, data, N, ppl.PPL_ALGO_IS))
+            iws = ppl.workspace(need, dev)
+            est, ess, ms = [], [], []
+            for sd in range(SEEDS_PER_RUNG):
+                e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+                e0.record(stream)
+                if learned:
+                    ppl.ppl_proposal_infer(model, data, wts, N, 100 + sd, ws=iws, stream=stream, scalars=sc,
+                                           widen=widen)
+                else:
+                    ppl.ppl_importance(model, data, N, 100 + sd, ws=iws, stream=stream, scalars=sc)
+                e1.record(stream)
+                torch.cuda.synchronize()
+                v = sc.cpu().numpy()
+                est.append(v[0])
+                ess.append(v[1])
+                ms.append(e0.elapsed_time(e1))
+            rmse = math.sqrt(sum((e - ref) ** 2 for e in est) / len(est))
+            if rmse <= RMSE_TARGET or lg == n_hi:
+                mean_ess, mean_ms = sum(ess) / len(ess), sum(ms) / len(ms)
+                return {"particles": N, "rmse": round(rmse, 4), "met": rmse <= RMSE_TARGET,
+                        "ess": round(mean_ess, 2), "ms_per_call": round(mean_ms, 4),
+                        "ess_per_s": mean_ess / (mean_ms / 1e3)}
+        return None
+
+    learned = ladder(True, 10, 24)
+    prior = ladder(False, 10, 30)
+    # kernel rate of the learned inference at its particle count
+    N = learned["particles"]
+    iws = ppl.workspace(ppl.ppl_proposal_infer_workspace_size(model, data, N), dev)
+    ppl.ppl_timing_enable(True)
+    for sd in range(args.steps):
+        ppl.ppl_proposal_infer(model, data, wts, N, 100 + sd, ws=iws, stream=stream, scalars=sc, widen=widen)
+    torch.cuda.synchronize()
+    k_ms, k_n = ppl.ppl_timing_query(kname)
+    ppl.ppl_timing_enable(False)
+    k_avg = k_ms / max(k_n, 1)
+    achieved = op_per_eval * N * D / (k_avg / 1e3) / 1e12
+    workload.update({"reference": {"log_evidence": round(ref, 5), "ess": round(ref_ess, 1),
+                                   "particles": chunk * ref_chunks, "proposal": "prior, fp64"},
+                     "training": {"pairs": pairs, "batch": B, "steps": pairs // B, "ms": round(train_ms, 2),
+                                  "loss_first": round(float(tr[:8].mean()), 4),
+                                  "loss_last": round(float(tr[-8:].mean()), 4),
+                                  "gemm_tflops": round(gemm_tflops, 2), "gemm_peak_tflops": BF16_MFMA_TFLOPS,
+                                  "gemm_frac": round(gemm_tflops / BF16_MFMA_TFLOPS, 4), "lr": lr,
+                                  "cosine_decay": decay},
+                     "widen": {"chosen": widen, "pilot_ess": [round(e, 1) for e in pilot],
+                               "candidates": list(ppl.WIDEN_CANDIDATES), "pilot_particles": 1 << 14,
+                               "ms": round(pilot_ms, 2)},
+                     "learned": learned, "prior": prior, "rmse_target": RMSE_TARGET,
+                     "seeds_per_rung": SEEDS_PER_RUNG})
+    out = {"metric": "ESS/s at log Z RMSE <= 0.05 (learned proposal)", "value": learned["ess_per_s"],
+           "unit": "ESS/s", "n_gpus": 1, "steps": args.steps, "warmup": 0,
+           "ms_per_step": learned["ms_per_call"], "higher_is_better": True, "scaling": "weak",
+           "vs_baseline": None, "dtype": "f64", "data": "synthetic (seeded generators, inputs resident in HBM)",
+           "config": workload,
+           "speedup_vs_prior": round(learned["ess_per_s"] / prior["ess_per_s"], 2) if prior else None,
+           "roofline": {"bound": "alu", "achieved": round(achieved, 3), "peak": FP64_VALU_TFLOPS, "unit": "TFLOP/s",
+                        "frac": round(achieved / FP64_VALU_TFLOPS, 4), "traffic": None, "kernel": kname,
+                        "kernel_ms": round(k_avg, 4), "kernel_launches": k_n,
+                        "flop_per_launch": op_per_eval * N * D}}
+    if not args.no_cpu:
+        out["cpu_baseline"] = cpu_baseline_prior_ess(poly, x if poly else None, y, D, target_s=args.cpu_seconds)
+    print(json.dumps(out), flush=True)
+
+
+def cpu_baseline_prior_ess(poly, x, y, D, target_s=15.0):
+    """The oracle's prior-proposal importance sampling on the same data: ESS per
+    second on a particle count sized to about target_s seconds."""
+    import numpy as np
+    import oracle
+    from oracle import proposal as opr
+    oracle.build()
+    n = 1 << 12
+    t0 = time.perf_counter()
+    if poly:
+        run = lambda k: oracle.importance(oracle.MODEL_POLY, x, y, k, 7)
+    else:
+        yd = np.asarray(y, dtype=np.float64)
+        run = lambda k: opr.gmm_prior_lw(7, 5, yd, np.arange(k))
+    run(n)
+    dt = time.perf_counter() - t0
+    n = max(n, int(n * target_s / max(dt, 1e-3)))
+    t0 = time.perf_counter()
+    r = run(n)
+    dt = time.perf_counter() - t0
+    if poly:
+        ess = float(r["ess"])
+    else:
+        w = np.exp(r - r.max())
+        ess = float(w.sum() ** 2 / (w * w).sum())
+    return {"value": ess / dt, "unit": "ESS/s", "cores": oracle.num_threads(), "kind": "oracle",
+            "sample": f"prior-proposal importance sampling, {n} particles, one seed ({dt:.1f} s)"}
+
+
 def main():
     args = parse()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
@@ -153,6 +330,9 @@ def main():
     dev = torch.device("cuda:0")
     torch.cuda.set_device(dev)
     stream = torch.cuda.current_stream()
+    if args.config.startswith("proposal"):
+        bench_proposal(args, ppl, synthetic, torch, dev, stream)
+        return
 
     if args.config == "blr":
         d, D, N, seed = 16, 10_000, 1 << 20, 1

@@ -318,7 +318,10 @@ int ppl_proposal_init(void *d_weights, uint64_t seed, void *stream);
 /* Training configuration.  hyper (HOST) are the simulation hyper-parameters:
  * POLY {sd, n_lo, n_hi, noise_sd} (default {10, 2, 5, 1}; 2 <= n_lo <= n_hi <= 5);
  * GMM {mu_sd, comp_sd} (default {5, 1}).  Adam fields 0 take the defaults
- * lr 1e-3, beta1 0.9, beta2 0.999, eps 1e-8. */
+ * lr 1e-3, beta1 0.9, beta2 0.999, eps 1e-8.  lr_decay_steps > 0 decays the
+ * learning rate along a half cosine from lr (at step count 0) to
+ * lr * lr_final_frac (at step count lr_decay_steps and after); the step count
+ * is the parameter block's, so the schedule continues across calls. */
 typedef struct ppl_train_config {
     int64_t n_pairs;         /* simulated pairs in this call, a multiple of batch */
     int32_t batch;           /* pairs per Adam step: a multiple of 64 in [64, 65536] */
@@ -328,6 +331,8 @@ typedef struct ppl_train_config {
     const double *hyper;
     int32_t n_hyper;
     int32_t use_graph;       /* nonzero: capture one step as a HIP graph and replay it */
+    int64_t lr_decay_steps;  /* 0: constant learning rate */
+    double lr_final_frac;    /* in [0, 1] */
 } ppl_train_config;
 
 int ppl_proposal_train_workspace_size(int model, const ppl_train_config *cfg, size_t *bytes);
@@ -356,12 +361,25 @@ int ppl_proposal_infer_workspace_size(int model, const ppl_data *data, int64_t n
 
 /* Amortised inference: summaries of the observed data, one forward pass,
  * decode to PPL_Q_POLY_MIX / PPL_Q_GMM_MIX parameters, then importance
- * sampling with that proposal (outputs as ppl_importance).  d_q_params
- * (optional) receives the decoded parameters, d_data_summaries (optional) the
- * 64 FP64 summaries.  POLY needs the degree range 2..5; GMM needs D <= 8192. */
+ * sampling with that proposal (outputs as ppl_importance).  widen >= 1
+ * multiplies every component's scales (log-scales + log widen; 1 = as
+ * trained), a tempering of the proposal for data unlike the training pairs.
+ * d_q_params (optional) receives the decoded parameters, d_data_summaries
+ * (optional) the 64 FP64 summaries.  POLY needs the degree range 2..5; GMM
+ * needs D <= 8192. */
 int ppl_proposal_infer(int model, const ppl_data *data, const void *d_weights, int64_t n_particles,
-                       uint64_t seed, double *d_q_params, double *d_data_summaries, void *d_ws,
-                       size_t ws_bytes, void *stream, ppl_result *out);
+                       uint64_t seed, double widen, double *d_q_params, double *d_data_summaries,
+                       void *d_ws, size_t ws_bytes, void *stream, ppl_result *out);
+
+/* Adaptive tempering: runs ppl_proposal_infer with n_pilot particles (Philox
+ * key `seed`) for each of the n_cand widen values in cand (HOST), and returns
+ * in *best the one whose pilot ESS is largest (ties: the earlier candidate),
+ * with the pilot ESS values in ess_out[n_cand] (HOST).  Needs no reference
+ * value.  Blocks on the stream; the workspace is that of ppl_proposal_infer
+ * for n_pilot particles.  n_cand in 1..16. */
+int ppl_proposal_pick_widen(int model, const ppl_data *data, const void *d_weights, int64_t n_pilot,
+                            uint64_t seed, const double *cand, int32_t n_cand, double *best, double *ess_out,
+                            void *d_ws, size_t ws_bytes, void *stream);
 
 /* Kernel timing (a measurement aid).  ppl_timing_enable(1) clears the
  * accumulators and makes the launchers bracket their dominant kernels

@@ -320,10 +320,12 @@ class PplTrainConfig(ctypes.Structure):
     _fields_ = [("n_pairs", ctypes.c_int64), ("batch", ctypes.c_int32), ("dim", ctypes.c_int32),
                 ("n_data", ctypes.c_int64), ("lr", ctypes.c_double), ("beta1", ctypes.c_double),
                 ("beta2", ctypes.c_double), ("eps", ctypes.c_double), ("hyper", ctypes.POINTER(ctypes.c_double)),
-                ("n_hyper", ctypes.c_int32), ("use_graph", ctypes.c_int32)]
+                ("n_hyper", ctypes.c_int32), ("use_graph", ctypes.c_int32),
+                ("lr_decay_steps", ctypes.c_int64), ("lr_final_frac", ctypes.c_double)]
 
 
-def train_config(n_pairs, batch, n_data, dim=0, lr=0.0, beta1=0.0, beta2=0.0, eps=0.0, hyper=None, use_graph=False):
+def train_config(n_pairs, batch, n_data, dim=0, lr=0.0, beta1=0.0, beta2=0.0, eps=0.0, hyper=None, use_graph=False,
+                 lr_decay_steps=0, lr_final_frac=0.0):
     """Build a ppl_train_config (keeps the hyper array alive)."""
     h = None
     if hyper is not None:
@@ -331,7 +333,8 @@ def train_config(n_pairs, batch, n_data, dim=0, lr=0.0, beta1=0.0, beta2=0.0, ep
     c = PplTrainConfig(n_pairs=int(n_pairs), batch=int(batch), dim=int(dim), n_data=int(n_data), lr=float(lr),
                        beta1=float(beta1), beta2=float(beta2), eps=float(eps),
                        hyper=ctypes.cast(h, ctypes.POINTER(ctypes.c_double)) if h is not None else None,
-                       n_hyper=0 if hyper is None else len(hyper), use_graph=1 if use_graph else 0)
+                       n_hyper=0 if hyper is None else len(hyper), use_graph=1 if use_graph else 0,
+                       lr_decay_steps=int(lr_decay_steps), lr_final_frac=float(lr_final_frac))
     c._keep = h
     return c
 
@@ -346,17 +349,21 @@ def _bind_proposal():
     L.ppl_proposal_train.argtypes = [ctypes.c_int, cfg, u64, P, P, P, sz, P]
     L.ppl_proposal_gradient.argtypes = [ctypes.c_int, cfg, u64, u32, P, P, P, P, P, P, P, sz, P]
     L.ppl_proposal_infer_workspace_size.argtypes = [ctypes.c_int, ctypes.POINTER(PplData), i64, ctypes.POINTER(sz)]
-    L.ppl_proposal_infer.argtypes = [ctypes.c_int, ctypes.POINTER(PplData), P, i64, u64, P, P, P, sz, P,
-                                     ctypes.POINTER(PplResult)]
+    L.ppl_proposal_infer.argtypes = [ctypes.c_int, ctypes.POINTER(PplData), P, i64, u64, ctypes.c_double, P, P, P,
+                                     sz, P, ctypes.POINTER(PplResult)]
+    L.ppl_proposal_pick_widen.argtypes = [ctypes.c_int, ctypes.POINTER(PplData), P, i64, u64,
+                                          ctypes.POINTER(ctypes.c_double), ctypes.c_int32,
+                                          ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_double), P, sz, P]
     for n in ("ppl_proposal_init", "ppl_proposal_train_workspace_size", "ppl_proposal_train",
-              "ppl_proposal_gradient", "ppl_proposal_infer_workspace_size", "ppl_proposal_infer"):
+              "ppl_proposal_gradient", "ppl_proposal_infer_workspace_size", "ppl_proposal_infer",
+              "ppl_proposal_pick_widen"):
         getattr(L, n).restype = ctypes.c_int
 
 
 _bind_proposal()
 EXPORTS = EXPORTS + ("ppl_proposal_weights_bytes", "ppl_proposal_init", "ppl_proposal_train_workspace_size",
                      "ppl_proposal_train", "ppl_proposal_gradient", "ppl_proposal_infer_workspace_size",
-                     "ppl_proposal_infer")
+                     "ppl_proposal_infer", "ppl_proposal_pick_widen")
 N_PARAMS = 148224
 
 
@@ -402,13 +409,31 @@ def ppl_proposal_infer_workspace_size(model, data, n):
 
 
 def ppl_proposal_infer(model, data, weights, n, seed, q_params=None, data_summaries=None, ws=None, stream=None,
-                       log_weights=None, latents=None, summaries=None, scalars=None, sync=False):
+                       log_weights=None, latents=None, summaries=None, scalars=None, sync=False, widen=1.0):
     """Amortised importance sampling; returns the ppl_result struct."""
     if ws is None:
         ws = workspace(ppl_proposal_infer_workspace_size(model, data, n))
     res = PplResult(sync_host=1 if sync else 0, d_scalars=_ptr(scalars), d_latents=_ptr(latents),
                     d_log_weights=_ptr(log_weights), d_summaries=_ptr(summaries))
     _check(lib.ppl_proposal_infer(model, ctypes.byref(data), _ptr(weights), int(n), int(seed) & (2 ** 64 - 1),
-                                  _ptr(q_params), _ptr(data_summaries), _ptr(ws), ws.numel(), _stream(stream),
-                                  ctypes.byref(res)))
+                                  float(widen), _ptr(q_params), _ptr(data_summaries), _ptr(ws), ws.numel(),
+                                  _stream(stream), ctypes.byref(res)))
     return res
+
+
+
+WIDEN_CANDIDATES = (1.0, 1.25, 1.5, 2.0)
+
+
+def ppl_proposal_pick_widen(model, data, weights, n_pilot=1 << 14, seed=0x51, candidates=WIDEN_CANDIDATES, ws=None,
+                            stream=None):
+    """Returns (chosen widen, [pilot ESS per candidate])."""
+    if ws is None:
+        ws = workspace(ppl_proposal_infer_workspace_size(model, data, n_pilot))
+    c = (ctypes.c_double * len(candidates))(*[float(v) for v in candidates])
+    ess = (ctypes.c_double * len(candidates))()
+    best = ctypes.c_double()
+    _check(lib.ppl_proposal_pick_widen(model, ctypes.byref(data), _ptr(weights), int(n_pilot),
+                                       int(seed) & (2 ** 64 - 1), c, len(candidates), ctypes.byref(best), ess,
+                                       _ptr(ws), ws.numel(), _stream(stream)))
+    return best.value, list(ess)

@@ -479,6 +479,10 @@ static int check_train(int model, const ppl_train_config *c, TrainPlan *p) {
     ad.eps = (float)(c->eps != 0.0 ? c->eps : 1e-8);
     if (!(ad.lr > 0) || !(ad.b1 >= 0 && ad.b1 < 1) || !(ad.b2 >= 0 && ad.b2 < 1) || !(ad.eps > 0))
         return fail(PPL_E_ARG, "Adam needs lr > 0, betas in [0, 1) and eps > 0");
+    if (c->lr_decay_steps < 0 || !(c->lr_final_frac >= 0.0 && c->lr_final_frac <= 1.0))
+        return fail(PPL_E_ARG, "lr_decay_steps must be >= 0 and lr_final_frac in [0, 1]");
+    ad.decay_steps = (double)c->lr_decay_steps;
+    ad.final_frac = c->lr_final_frac;
     p->B = c->batch;
     p->steps = c->n_pairs / c->batch;
     return PPL_OK;
@@ -624,7 +628,7 @@ int ppl_proposal_infer_workspace_size(int model, const ppl_data *data, int64_t n
     return PPL_OK;
 }
 
-int ppl_proposal_infer(int model, const ppl_data *data, const void *d_weights, int64_t n, uint64_t seed,
+int ppl_proposal_infer(int model, const ppl_data *data, const void *d_weights, int64_t n, uint64_t seed, double widen,
                        double *d_q_params, double *d_data_summaries, void *ws, size_t ws_bytes, void *stream,
                        ppl_result *out) {
     clear_error();
@@ -638,6 +642,7 @@ int ppl_proposal_infer(int model, const ppl_data *data, const void *d_weights, i
         return fail(PPL_E_ARG, "the POLY proposal covers degrees 2..5; the model range must be 2..5");
     if (model == PPL_MODEL_GMM && data->n_data > kGmmSummaryMaxD)
         return fail(PPL_E_ARG, "GMM summaries take at most %d points", kGmmSummaryMaxD);
+    if (!(widen >= 1.0 && widen <= 1e3)) return fail(PPL_E_ARG, "widen must be in [1, 1000]");
     if (int rc = check_weights(d_weights)) return rc;
     if (int rc = check_ws(ws, ws_bytes, infer_ws_bytes(model, n))) return rc;
     if (int rc = check_device()) return rc;
@@ -650,7 +655,7 @@ int ppl_proposal_infer(int model, const ppl_data *data, const void *d_weights, i
     const MlpView w = mlp_view(const_cast<void *>(d_weights));
     if (int rc = launch_observed_summary(model, data->x, data->y, data->n_data, b.x_row, d_data_summaries, st)) return rc;
     if (int rc = launch_forward(w, b, false, st)) return rc;
-    if (int rc = launch_decode(model, data->dim, b.o_col, 64, q, st)) return rc;
+    if (int rc = launch_decode(model, data->dim, b.o_col, 64, log(widen), q, st)) return rc;
     const int nq = model == PPL_MODEL_POLY ? kPolyQParams : gmm_q_params(data->dim);
     if (d_q_params) PPL_HIP(hipMemcpyAsync(d_q_params, q, (size_t)nq * sizeof(double), hipMemcpyDeviceToDevice, st));
     a.model = model;
@@ -668,6 +673,29 @@ int ppl_proposal_infer(int model, const ppl_data *data, const void *d_weights, i
     a.part = part;
     if (int rc = run_importance_q(a, st)) return rc;
     if (out->sync_host) return sync_scalars(out, a.scalars, st);
+    return PPL_OK;
+}
+
+int ppl_proposal_pick_widen(int model, const ppl_data *data, const void *d_weights, int64_t n_pilot, uint64_t seed,
+                            const double *cand, int32_t n_cand, double *best, double *ess_out, void *ws,
+                            size_t ws_bytes, void *stream) {
+    clear_error();
+    if (!cand || !best || n_cand < 1 || n_cand > 16) return fail(PPL_E_ARG, "need 1..16 candidates and a result pointer");
+    double ess[16];
+    for (int c = 0; c < n_cand; ++c) {
+        ppl_result r{};
+        r.sync_host = 1;
+        if (int rc = ppl_proposal_infer(model, data, d_weights, n_pilot, seed, cand[c], nullptr, nullptr, ws, ws_bytes,
+                                        stream, &r))
+            return rc;
+        ess[c] = r.ess;
+    }
+    int k = 0;
+    for (int c = 1; c < n_cand; ++c)
+        if (ess[c] > ess[k]) k = c;
+    *best = cand[k];
+    if (ess_out)
+        for (int c = 0; c < n_cand; ++c) ess_out[c] = ess[c];
     return PPL_OK;
 }
 

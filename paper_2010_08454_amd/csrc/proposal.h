@@ -59,6 +59,8 @@ TrainBufs train_bufs(void *ws, int B);
 
 struct AdamSpec {
     float lr, b1, b2, eps;
+    double decay_steps;      // > 0: half-cosine decay of lr over this many steps
+    double final_frac;       // lr multiplier reached at the end of the decay
 };
 
 // Forward pass of a batch whose summaries are already in bufs.x_row/x_col.
@@ -74,7 +76,8 @@ int launch_set_i64(int64_t *p, int64_t v, hipStream_t st);
 int launch_init_weights(void *weights, uint64_t seed, hipStream_t st);
 
 // Decode the network output column 0 of o_col[256][ld] into FP64 proposal
-// parameters (kPolyQParams or gmm_q_params(K) values).
-int launch_decode(int model, int K, const float *o_col, int ld, double *q, hipStream_t st);
+// parameters (kPolyQParams or gmm_q_params(K) values); log_widen is added to
+// every used log-scale.
+int launch_decode(int model, int K, const float *o_col, int ld, double log_widen, double *q, hipStream_t st);
 
 }  // namespace ppl

@@ -209,8 +209,9 @@ struct SplitParts {
 
 // Gradient of parameter e: weights sum their split-R partials in chunk order,
 // biases come from bgrad.  grad != null: store it; else one Adam step
-// (bias-corrected moments, step t = completed steps + 1) and refresh both
-// BF16 weight layouts.
+// (bias-corrected moments, step t = completed steps + 1, the learning rate
+// optionally on a half-cosine schedule of the completed steps) and refresh
+// both BF16 weight layouts.
 __global__ __launch_bounds__(256) void adam_kernel(MlpView w, SplitParts sp, const float *__restrict__ bgrad, AdamSpec ad,
                                                    float *__restrict__ grad) {
     const int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x;
@@ -234,12 +235,18 @@ __global__ __launch_bounds__(256) void adam_kernel(MlpView w, SplitParts sp, con
         grad[e] = gv;
         return;
     }
-    const double t = (double)(*w.step + 1);
+    const double done = (double)*w.step;
+    const double t = done + 1.0;
     const float bc1 = (float)(1.0 - pow((double)ad.b1, t));
     const float bc2 = (float)(1.0 - pow((double)ad.b2, t));
+    float lr = ad.lr;
+    if (ad.decay_steps > 0.0) {
+        const double x = fmin(done / ad.decay_steps, 1.0);
+        lr = (float)(ad.lr * (ad.final_frac + (1.0 - ad.final_frac) * 0.5 * (1.0 + cospi(x))));
+    }
     const float m = ad.b1 * w.m[e] + (1.0f - ad.b1) * gv;
     const float v = ad.b2 * w.v[e] + (1.0f - ad.b2) * gv * gv;
-    const float p = w.master[e] - ad.lr * (m / bc1) / (sqrtf(v / bc2) + ad.eps);
+    const float p = w.master[e] - lr * (m / bc1) / (sqrtf(v / bc2) + ad.eps);
     w.m[e] = m;
     w.v[e] = v;
     w.master[e] = p;
@@ -297,12 +304,13 @@ __global__ __launch_bounds__(256) void init_weights_kernel(MlpView w, Key key, f
 }
 
 // -------------------------------------------------------------- decode --
-// FP64 proposal parameters from network output column 0.
+// FP64 proposal parameters from network output column 0 (log-scales raised
+// by log_widen).
 //   POLY: {log-softmax of the degree logits [4], log-softmax of the mixture
 //          logits [8], mean[4][8][5], lsd[4][8][5]} (slots j >= n zero).
 //   GMM:  {log-softmax of the mixture logits [8], mean[8][d], lsd[8][d]}.
 __global__ __launch_bounds__(64) void decode_kernel(int model, int K, const float *__restrict__ o_col, int ld,
-                                                    double *__restrict__ q) {
+                                                    double log_widen, double *__restrict__ q) {
     const int lane = threadIdx.x;
     auto O = [&](int k) { return (double)o_col[(size_t)k * ld]; };
     auto logsoftmax = [&](int base, int n, double *dst) {
@@ -320,14 +328,14 @@ __global__ __launch_bounds__(64) void decode_kernel(int model, int K, const floa
             const int n = 2 + e / 40, m = (e / 5) % 8, j = e % 5;
             const int off = poly_head_off(n);
             q[12 + e] = j < n ? 10.0 * O(off + m * n + j) : 0.0;
-            q[172 + e] = j < n ? 5.0 * tanh(O(off + 8 * n + m * n + j) / 5.0) : 0.0;
+            q[172 + e] = j < n ? 5.0 * tanh(O(off + 8 * n + m * n + j) / 5.0) + log_widen : 0.0;
         }
     } else {
         const int d = 2 * K - 1;
         if (lane == 0) logsoftmax(0, 8, q);
         for (int e = lane; e < 8 * d; e += 64) {
             q[8 + e] = 5.0 * O(8 + e);
-            q[8 + 8 * d + e] = 5.0 * tanh(O(8 + 8 * d + e) / 5.0);
+            q[8 + 8 * d + e] = 5.0 * tanh(O(8 + 8 * d + e) / 5.0) + log_widen;
         }
     }
 }
@@ -469,8 +477,8 @@ int launch_init_weights(void *weights, uint64_t seed, hipStream_t st) {
     return PPL_OK;
 }
 
-int launch_decode(int model, int K, const float *o_col, int ld, double *q, hipStream_t st) {
-    hipLaunchKernelGGL(decode_kernel, dim3(1), dim3(64), 0, st, model, K, o_col, ld, q);
+int launch_decode(int model, int K, const float *o_col, int ld, double log_widen, double *q, hipStream_t st) {
+    hipLaunchKernelGGL(decode_kernel, dim3(1), dim3(64), 0, st, model, K, o_col, ld, log_widen, q);
     PPL_LAUNCH_CHECK("decode_kernel");
     return PPL_OK;
 }
