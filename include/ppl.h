@@ -295,7 +295,8 @@ int ppl_smc_autotune(int model, int32_t n_inst, const ppl_instance *h_inst, cons
  * Summaries (FP64, then BF16 at the network input):
  *   POLY (42 used): mean x^j y / 10 (j = 0..7); mean x^k (k = 1..14);
  *     mean y^2 / 100; least-squares coefficients for n = 2..5 / 10;
- *     log(mean squared residual_n + 1e-3) / 10 for n = 2..5; log D / 10.
+ *     log(1 + (RSS_n - RSS_5) / 2) / 10 for n = 2..5 (residual sums of squares
+ *     of the least-squares fits: the log-likelihood gaps); log D / 10.
  *   GMM (53 used): order statistics y_(floor((q + 1/2) D / 16)) / 10 (q < 16);
  *     counts on the unit bins of [-16, 16), ends clamped, / D; mean / 10;
  *     sd / 10; skewness; excess kurtosis / 10; log D / 10.

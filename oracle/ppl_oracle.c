@@ -642,7 +642,8 @@ static void chol_solve(int n, const double *G, const double *m, double *beta)
  *   [8..21]  (1/D) sum x^k, k = 1..14
  *   [22]     (1/D) sum y^2 / 100
  *   [23..36] least-squares coefficients for n = 2, 3, 4, 5 (n values each) / 10
- *   [37..40] log(RSS_n / D + 1e-3) / 10, RSS_n / D = (1/D) sum y^2 - beta_n . m_n
+ *   [37..40] log(1 + (RSS_n - RSS_5) / 2) / 10, RSS_n = D ((1/D) sum y^2 - beta_n . m_n)
+ *            clamped at 0: the log-likelihood gap of the n-coefficient fit
  *   [41]     log(D) / 10 */
 void or_summary_poly(const double *x, const double *y, int64_t D, double *s)
 {
@@ -665,16 +666,21 @@ void or_summary_poly(const double *x, const double *y, int64_t D, double *s)
     for (int k = 1; k <= 14; ++k) s[7 + k] = gx[k];
     s[22] = syy / 100.0;
     int o = 23;
+    double rss[4];
     for (int n = 2; n <= 5; ++n) {
         double G[25], beta[5];
         for (int i = 0; i < n; ++i) for (int j = 0; j < n; ++j) G[i * 5 + j] = gx[i + j];
         chol_solve(n, G, mxy, beta);
         double fit = 0.0;
         for (int j = 0; j < n; ++j) { s[o + j] = beta[j] / 10.0; fit += beta[j] * mxy[j]; }
-        double rss = syy - fit;
-        if (rss < 0.0) rss = 0.0;
-        s[37 + n - 2] = log(rss + 1e-3) / 10.0;
+        rss[n - 2] = syy - fit;
+        if (rss[n - 2] < 0.0) rss[n - 2] = 0.0;
         o += n;
+    }
+    for (int n = 2; n <= 5; ++n) {
+        double gap = (double)D * (rss[n - 2] - rss[3]) / 2.0;
+        if (gap < 0.0) gap = 0.0;
+        s[37 + n - 2] = log1p(gap) / 10.0;
     }
     s[41] = log((double)D) / 10.0;
 }

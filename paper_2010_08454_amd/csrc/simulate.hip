@@ -111,7 +111,9 @@ __device__ void poly_ls(int n, const double *gx, const double *mxy, double (&bet
 // Reduce the lane accumulators and write the 64 POLY summaries to s[]:
 //   [0..7] mean x^j y / 10; [8..21] mean x^k, k = 1..14; [22] mean y^2 / 100;
 //   [23..36] least-squares coefficients for n = 2..5 / 10;
-//   [37..40] log(mean residual^2 + 1e-3) / 10; [41] log D / 10; rest 0.
+//   [37..40] log(1 + (RSS_n - RSS_5) / 2) / 10 (RSS_n the residual sum of
+//   squares of the n-coefficient fit: the log-likelihood gap to the largest
+//   fit, independent of the absolute noise level); [41] log D / 10; rest 0.
 __device__ void poly_finish(double (&a)[kPolyAcc], int64_t D, double *tot, double *s) {
 #pragma clang fp contract(off)
     const int lane = threadIdx.x & 63;
@@ -131,6 +133,7 @@ __device__ void poly_finish(double (&a)[kPolyAcc], int64_t D, double *tot, doubl
         else if (lane == 41) v = log((double)D) / 10.0;
     }
     if (lane < 23 || lane >= 41) s[lane] = v;
+    double rss = 0.0;
     if (lane < 4) {
         const int n = 2 + lane;
         double beta[5];
@@ -144,9 +147,14 @@ __device__ void poly_finish(double (&a)[kPolyAcc], int64_t D, double *tot, doubl
                 fit += beta[j] * mxy[j];
             }
         }
-        double rss = tot[23] - fit;
+        rss = tot[23] - fit;
         if (rss < 0.0) rss = 0.0;
-        s[37 + n - 2] = D > 0 ? log(rss + 1e-3) / 10.0 : 0.0;
+    }
+    const double rss5 = __shfl(rss, 3, 64);
+    if (lane < 4) {
+        double gap = (double)D * (rss - rss5) / 2.0;
+        if (gap < 0.0) gap = 0.0;
+        s[37 + lane] = D > 0 ? log1p(gap) / 10.0 : 0.0;
     }
     __syncthreads();
 }

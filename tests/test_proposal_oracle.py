@@ -118,12 +118,15 @@ def test_poly_summaries_match_library_routines(pr):
     x, y = synthetic.poly_data(D=300, seed=4)
     s = pr.summary_poly(x, y)
     o = 23
+    rss = {}
     for n in range(2, 6):
         beta = np.linalg.lstsq(np.vander(x, n, increasing=True), y, rcond=None)[0]
         assert np.allclose(s[o:o + n] * 10, beta, atol=1e-9)
-        rss = ((y - np.vander(x, n, increasing=True) @ beta) ** 2).mean()
-        assert s[37 + n - 2] == pytest.approx(math.log(rss + 1e-3) / 10, abs=1e-9)
+        rss[n] = ((y - np.vander(x, n, increasing=True) @ beta) ** 2).sum()
         o += n
+    for n in range(2, 6):
+        assert s[37 + n - 2] == pytest.approx(math.log1p(max(rss[n] - rss[5], 0.0) / 2) / 10, abs=1e-7)
+    assert s[40] == 0.0
     assert s[41] == pytest.approx(math.log(300) / 10) and np.all(s[42:] == 0)
 
 
