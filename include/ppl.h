@@ -327,7 +327,7 @@ typedef struct ppl_train_config {
     int64_t n_pairs;         /* simulated pairs in this call, a multiple of batch */
     int32_t batch;           /* pairs per Adam step: a multiple of 64 in [64, 65536] */
     int32_t dim;             /* GMM: K in 1..8; POLY: 0 */
-    int64_t n_data;          /* points per simulated dataset: POLY >= 1, GMM 1..1024 */
+    int64_t n_data;          /* points per simulated dataset: POLY >= 1, GMM 1..4096 */
     double lr, beta1, beta2, eps;
     const double *hyper;
     int32_t n_hyper;

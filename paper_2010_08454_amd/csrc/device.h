@@ -215,4 +215,44 @@ __device__ __forceinline__ void partial_block_reduce_store(Partial<NF> &p, doubl
     }
 }
 
+// ------------------------------------------------ two-level partial merge --
+// Up to kMergeDirect block partials are merged by one wave; beyond that a first
+// pass of at most kMergeGroups workgroups merges fixed contiguous ranges (a
+// fixed order, so the result does not depend on timing) and the wave merges
+// those records.
+constexpr int kMergeGroups = 512;
+constexpr int64_t kMergeDirect = 8192;
+
+template <int NF>
+__global__ __launch_bounds__(256) void partial_merge_kernel(const double *__restrict__ in, int64_t n, int64_t per,
+                                                            double *__restrict__ out) {
+    Partial<NF> a = partial_empty<NF>();
+    const int64_t lo = (int64_t)blockIdx.x * per;
+    const int64_t hi = lo + per < n ? lo + per : n;
+    for (int64_t r = lo + threadIdx.x; r < hi; r += 256) {
+        Partial<NF> q = partial_load<NF>(in + (size_t)r * (4 + NF));
+        partial_merge(a, q);
+    }
+    partial_block_reduce_store<NF, 4>(a, out + (size_t)blockIdx.x * (4 + NF));
+}
+
+// Bytes of second-level records a merge of NF-field partials may need.
+inline size_t merge_scratch_bytes(int nf) { return (size_t)kMergeGroups * (4 + nf) * sizeof(double); }
+
+// Runs the first pass when nblocks is large; returns the records the final
+// wave merges and their count in *nrec.  scratch holds merge_scratch_bytes(NF).
+template <int NF>
+inline const double *merge_partials_first(const double *part, int64_t nblocks, double *scratch, int *nrec,
+                                          hipStream_t st) {
+    if (nblocks <= kMergeDirect) {
+        *nrec = (int)nblocks;
+        return part;
+    }
+    const int64_t per = (nblocks + kMergeGroups - 1) / kMergeGroups;
+    const int groups = (int)((nblocks + per - 1) / per);
+    hipLaunchKernelGGL(partial_merge_kernel<NF>, dim3(groups), dim3(256), 0, st, part, nblocks, per, scratch);
+    *nrec = groups;
+    return scratch;
+}
+
 }  // namespace ppl

@@ -271,7 +271,7 @@ size_t is_partial_bytes(int model, int dim, int64_t N) {
     const int P = model == PPL_MODEL_POLY ? 1 : 4;
     const int64_t blocks = (N + (int64_t)kIsThreads * P - 1) / ((int64_t)kIsThreads * P);
     const int nf = model == PPL_MODEL_POLY ? kPolyNF : dim;
-    return (size_t)blocks * (4 + nf) * sizeof(double);
+    return (size_t)blocks * (4 + nf) * sizeof(double) + merge_scratch_bytes(nf);
 }
 
 template <int DIM>
@@ -289,8 +289,11 @@ static int launch_blr(const IsArgs &a, double *part, int64_t blocks, hipStream_t
                            (float)a.hyper[0], a.hyper[1], nullptr, (double *)a.lw_out, (float *)a.lat_out, part);
     timer.stop();
     PPL_LAUNCH_CHECK("blr_is_kernel");
-    hipLaunchKernelGGL((is_finalize_kernel<DIM, PPL_MODEL_BLR>), dim3(1), dim3(64), 0, st, part, (int)blocks,
-                       a.N, a.scalars, a.summaries);
+    int nrec = 0;
+    const double *rec = merge_partials_first<DIM>(part, blocks, part + (size_t)blocks * (4 + DIM), &nrec, st);
+    PPL_LAUNCH_CHECK("partial_merge_kernel");
+    hipLaunchKernelGGL((is_finalize_kernel<DIM, PPL_MODEL_BLR>), dim3(1), dim3(64), 0, st, rec, nrec, a.N, a.scalars,
+                       a.summaries);
     PPL_LAUNCH_CHECK("is_finalize_kernel");
     return PPL_OK;
 }
@@ -307,8 +310,12 @@ int run_importance(const IsArgs &a, hipStream_t st) {
                            (double *)a.lat_out, a.part);
         timer.stop();
         PPL_LAUNCH_CHECK("poly_is_kernel");
-        hipLaunchKernelGGL((is_finalize_kernel<kPolyNF, PPL_MODEL_POLY>), dim3(1), dim3(64), 0, st, a.part,
-                           (int)blocks, a.N, a.scalars, a.summaries);
+        int nrec = 0;
+        const double *rec =
+            merge_partials_first<kPolyNF>(a.part, blocks, a.part + (size_t)blocks * (4 + kPolyNF), &nrec, st);
+        PPL_LAUNCH_CHECK("partial_merge_kernel");
+        hipLaunchKernelGGL((is_finalize_kernel<kPolyNF, PPL_MODEL_POLY>), dim3(1), dim3(64), 0, st, rec, nrec, a.N,
+                           a.scalars, a.summaries);
         PPL_LAUNCH_CHECK("is_finalize_kernel");
         return PPL_OK;
     }

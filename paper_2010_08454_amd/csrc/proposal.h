@@ -16,7 +16,7 @@ constexpr int kHeadComps = 8;        // mixture components of the proposal
 constexpr int kPolyQParams = 12 + 2 * 160;   // lognl[4], logmix[8], mean[4][8][5], lsd[4][8][5]
 inline int gmm_q_params(int K) { return 8 + 16 * (2 * K - 1); }
 constexpr int kGmmSummaryMaxD = 8192;        // observed-data limit of the mixture summaries (32 KB of LDS)
-constexpr int kGmmTrainMaxD = 1024;          // per simulated dataset (four per workgroup, 32 KB of LDS)
+constexpr int kGmmTrainMaxD = 4096;          // per simulated dataset (one per workgroup, 32 KB of LDS)
 
 // Simulation hyper-parameters.  POLY: {sd, n_lo, n_hi, noise_sd};
 // GMM: {mu_sd, comp_sd}, with K components.
@@ -30,7 +30,7 @@ struct SimSpec {
 // Simulate B training pairs of training step `*step` (Philox tag 4, counter
 // (pair, block, step, 4)) and write their summaries as BF16 rows x_row[B][64]
 // and columns x_col[64][B], the latents theta[B][16] (FP64) and, if s64 is not
-// null, the FP64 summaries s64[B][64].  B is a multiple of 4.
+// null, the FP64 summaries s64[B][64].
 int launch_simulate(const SimSpec &sp, int B, uint64_t seed, const int64_t *step, uint16_t *x_row, uint16_t *x_col,
                     double *theta, double *s64, hipStream_t st);
 
@@ -50,7 +50,7 @@ struct TrainBufs {
     float *part[3];                     // split-R partials of dW_l
     int nchunks[3], chunk[3];
     float *bgrad;                       // [3][256]
-    double *lossp;                      // [B / 64] per-workgroup loss sums
+    double *lossp;                      // [B / 32] per-workgroup loss sums
     int64_t *local;                     // [0]: steps taken in this call, [1]: a fixed step index
 };
 

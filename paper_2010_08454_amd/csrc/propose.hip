@@ -326,7 +326,8 @@ __global__ __launch_bounds__(64) void prop_finalize_kernel(const double *__restr
 // ---------------------------------------------------------------- host --
 size_t prop_partial_bytes(int model, int64_t N) {
     const int64_t blocks = (N + kPropThreads - 1) / kPropThreads;
-    return (size_t)blocks * (4 + (model == PPL_MODEL_POLY ? kPolyNFp : kGmmNF)) * sizeof(double);
+    const int nf = model == PPL_MODEL_POLY ? kPolyNFp : kGmmNF;
+    return (size_t)blocks * (4 + nf) * sizeof(double) + merge_scratch_bytes(nf);
 }
 
 int run_importance_q(const IsArgs &a, hipStream_t st) {
@@ -351,12 +352,20 @@ int run_importance_q(const IsArgs &a, hipStream_t st) {
         timer.stop();
         PPL_LAUNCH_CHECK(name);
     }
-    if (a.model == PPL_MODEL_POLY)
-        hipLaunchKernelGGL(prop_finalize_kernel<kPolyNFp>, dim3(1), dim3(64), 0, st, a.part, (int)blocks, a.N, a.model,
+    int nrec = 0;
+    if (a.model == PPL_MODEL_POLY) {
+        const double *rec =
+            merge_partials_first<kPolyNFp>(a.part, blocks, a.part + (size_t)blocks * (4 + kPolyNFp), &nrec, st);
+        PPL_LAUNCH_CHECK("partial_merge_kernel");
+        hipLaunchKernelGGL(prop_finalize_kernel<kPolyNFp>, dim3(1), dim3(64), 0, st, rec, nrec, a.N, a.model,
                            a.scalars, a.summaries);
-    else
-        hipLaunchKernelGGL(prop_finalize_kernel<kGmmNF>, dim3(1), dim3(64), 0, st, a.part, (int)blocks, a.N, a.model,
+    } else {
+        const double *rec =
+            merge_partials_first<kGmmNF>(a.part, blocks, a.part + (size_t)blocks * (4 + kGmmNF), &nrec, st);
+        PPL_LAUNCH_CHECK("partial_merge_kernel");
+        hipLaunchKernelGGL(prop_finalize_kernel<kGmmNF>, dim3(1), dim3(64), 0, st, rec, nrec, a.N, a.model,
                            a.scalars, a.summaries);
+    }
     PPL_LAUNCH_CHECK("prop_finalize_kernel");
     return PPL_OK;
 }

@@ -1,8 +1,9 @@
 // simulate.hip -- training pairs drawn from the model's own prior, and the 64
-// data summaries the proposal network reads.  One wave per dataset: the lanes
-// stride over the data points, FP64 moment sums are combined by a butterfly,
+// data summaries the proposal network reads.  One 256-thread workgroup per
+// dataset: the threads stride over the data points, FP64 moment sums are
+// combined by wave butterflies and a fixed-order sum of the four wave totals,
 // and the per-dataset finishing work (least-squares fits, order statistics)
-// runs on a few lanes of the same wave.
+// runs on the first wave.
 //
 // Training pair of step t, pair i (Philox tag 4, counter (i, block, t, 4)):
 //   POLY: block 0 word 0 -> degree n (uniform discrete); blocks 1, 2 -> eight
@@ -23,7 +24,8 @@
 namespace ppl {
 
 constexpr uint32_t kTagTrain = 4;
-constexpr int kSimWaves = 4;
+constexpr int kSumThreads = 256;     // one dataset per workgroup
+constexpr int kSumWaves = kSumThreads / 64;
 
 __device__ __forceinline__ double u01(uint32_t w) { return (double)unit_f32(w); }
 
@@ -108,53 +110,69 @@ __device__ void poly_ls(int n, const double *gx, const double *mxy, double (&bet
     }
 }
 
-// Reduce the lane accumulators and write the 64 POLY summaries to s[]:
+// Sum of one double per thread over the workgroup, returned to every thread:
+// wave butterflies, then the wave totals in a fixed order.  red holds
+// kSumWaves doubles.
+__device__ __forceinline__ double block_sum(double v, double *red) {
+    v = wave_sum(v);
+    __syncthreads();
+    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = v;
+    __syncthreads();
+    return (red[0] + red[1]) + (red[2] + red[3]);
+}
+
+// Reduce the thread accumulators and write the 64 POLY summaries to s[]:
 //   [0..7] mean x^j y / 10; [8..21] mean x^k, k = 1..14; [22] mean y^2 / 100;
 //   [23..36] least-squares coefficients for n = 2..5 / 10;
 //   [37..40] log(1 + (RSS_n - RSS_5) / 2) / 10 (RSS_n the residual sum of
 //   squares of the n-coefficient fit: the log-likelihood gap to the largest
 //   fit, independent of the absolute noise level); [41] log D / 10; rest 0.
-__device__ void poly_finish(double (&a)[kPolyAcc], int64_t D, double *tot, double *s) {
+__device__ void poly_finish(double (&a)[kPolyAcc], int64_t D, double (*wtot)[kPolyAcc], double *tot, double *s) {
 #pragma clang fp contract(off)
-    const int lane = threadIdx.x & 63;
+    const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
 #pragma unroll
     for (int k = 0; k < kPolyAcc; ++k) a[k] = wave_sum(a[k]);
     if (lane == 0) {
 #pragma unroll
-        for (int k = 0; k < kPolyAcc; ++k) tot[k] = D > 0 ? a[k] / (double)D : 0.0;
+        for (int k = 0; k < kPolyAcc; ++k) wtot[wv][k] = a[k];
     }
     __syncthreads();
-    const double *mxy = tot, *gx = tot + 8;
-    double v = 0.0;
-    if (D > 0) {
-        if (lane < 8) v = mxy[lane] / 10.0;
-        else if (lane < 22) v = gx[lane - 7];
-        else if (lane == 22) v = tot[23] / 100.0;
-        else if (lane == 41) v = log((double)D) / 10.0;
-    }
-    if (lane < 23 || lane >= 41) s[lane] = v;
-    double rss = 0.0;
-    if (lane < 4) {
-        const int n = 2 + lane;
-        double beta[5];
-        poly_ls(n, gx, mxy, beta);
-        double fit = 0.0;
-        const int o = 23 + (n - 2) * (n + 1) / 2;
-#pragma unroll
-        for (int j = 0; j < 5; ++j) {
-            if (j < n) {
-                s[o + j] = D > 0 ? beta[j] / 10.0 : 0.0;
-                fit += beta[j] * mxy[j];
-            }
+    if (tid < kPolyAcc)
+        tot[tid] = D > 0 ? ((wtot[0][tid] + wtot[1][tid]) + (wtot[2][tid] + wtot[3][tid])) / (double)D : 0.0;
+    __syncthreads();
+    if (wv == 0) {
+        const double *mxy = tot, *gx = tot + 8;
+        double v = 0.0;
+        if (D > 0) {
+            if (lane < 8) v = mxy[lane] / 10.0;
+            else if (lane < 22) v = gx[lane - 7];
+            else if (lane == 22) v = tot[23] / 100.0;
+            else if (lane == 41) v = log((double)D) / 10.0;
         }
-        rss = tot[23] - fit;
-        if (rss < 0.0) rss = 0.0;
-    }
-    const double rss5 = __shfl(rss, 3, 64);
-    if (lane < 4) {
-        double gap = (double)D * (rss - rss5) / 2.0;
-        if (gap < 0.0) gap = 0.0;
-        s[37 + lane] = D > 0 ? log1p(gap) / 10.0 : 0.0;
+        if (lane < 23 || lane >= 41) s[lane] = v;
+        double rss = 0.0;
+        if (lane < 4) {
+            const int n = 2 + lane;
+            double beta[5];
+            poly_ls(n, gx, mxy, beta);
+            double fit = 0.0;
+            const int o = 23 + (n - 2) * (n + 1) / 2;
+#pragma unroll
+            for (int j = 0; j < 5; ++j) {
+                if (j < n) {
+                    s[o + j] = D > 0 ? beta[j] / 10.0 : 0.0;
+                    fit += beta[j] * mxy[j];
+                }
+            }
+            rss = tot[23] - fit;
+            if (rss < 0.0) rss = 0.0;
+        }
+        const double rss5 = __shfl(rss, 3, 64);
+        if (lane < 4) {
+            double gap = (double)D * (rss - rss5) / 2.0;
+            if (gap < 0.0) gap = 0.0;
+            s[37 + lane] = D > 0 ? log1p(gap) / 10.0 : 0.0;
+        }
     }
     __syncthreads();
 }
@@ -165,15 +183,15 @@ __device__ void poly_finish(double (&a)[kPolyAcc], int64_t D, double *tot, doubl
 //   [0..15] order statistics y_(floor((q + 1/2) D / 16)) / 10;
 //   [16..47] counts on the unit bins of [-16, 16) (ends clamped) / D;
 //   [48] mean / 10, [49] sd / 10, [50] skewness, [51] excess kurtosis / 10,
-//   [52] log D / 10; rest 0.  hist is this wave's 32 LDS counters, already
-//   filled; sum_y the lane's sum of its points.
+//   [52] log D / 10; rest 0.  hist holds the workgroup's 32 bin counts,
+//   already filled; sum_y is the thread's sum of its points.
 template <typename T>
-__device__ void gmm_finish(const T *ys, int64_t D, const int *hist, double sum_y, double *s) {
+__device__ void gmm_finish(const T *ys, int64_t D, const int *hist, double sum_y, double *red, double *s) {
 #pragma clang fp contract(off)
-    const int lane = threadIdx.x & 63;
-    const double m1 = D > 0 ? wave_sum(sum_y) / (double)D : 0.0;
+    const int tid = threadIdx.x;
+    const double m1 = D > 0 ? block_sum(sum_y, red) / (double)D : 0.0;
     double c2 = 0.0, c3 = 0.0, c4 = 0.0;
-    for (int64_t d = lane; d < D; d += 64) {
+    for (int64_t d = tid; d < D; d += kSumThreads) {
         const double y = (double)ys[d];
         int64_t r = 0;
         for (int64_t e = 0; e < D; ++e) {
@@ -188,15 +206,13 @@ __device__ void gmm_finish(const T *ys, int64_t D, const int *hist, double sum_y
         c3 += dv * dv * dv;
         c4 += dv * dv * dv * dv;
     }
-    c2 = wave_sum(c2);
-    c3 = wave_sum(c3);
-    c4 = wave_sum(c4);
-    if (D <= 0) {
-        if (lane < 16) s[lane] = 0.0;
-    }
-    if (lane < 32) s[16 + lane] = D > 0 ? (double)hist[lane] / (double)D : 0.0;
-    if (lane >= 53) s[lane] = 0.0;
-    if (lane == 0) {
+    c2 = block_sum(c2, red);
+    c3 = block_sum(c3, red);
+    c4 = block_sum(c4, red);
+    if (D <= 0 && tid < 16) s[tid] = 0.0;
+    if (tid < 32) s[16 + tid] = D > 0 ? (double)hist[tid] / (double)D : 0.0;
+    if (tid >= 53 && tid < kSummaryDim) s[tid] = 0.0;
+    if (tid == 0) {
         double v2 = 0.0, v3 = 0.0, v4 = 0.0;
         if (D > 0) {
             v2 = c2 / (double)D;
@@ -221,23 +237,24 @@ __device__ __forceinline__ void gmm_bin(int *hist, double y) {
 
 // -------------------------------------------------- training simulation --
 template <int MODEL>
-__global__ __launch_bounds__(64 * kSimWaves) void simulate_kernel(SimSpec sp, int B, Key key,
-                                                                  const int64_t *__restrict__ step_ptr,
-                                                                  uint16_t *__restrict__ x_row,
-                                                                  uint16_t *__restrict__ x_col,
-                                                                  double *__restrict__ theta,
-                                                                  double *__restrict__ s64) {
+__global__ __launch_bounds__(kSumThreads) void simulate_kernel(SimSpec sp, int B, Key key,
+                                                               const int64_t *__restrict__ step_ptr,
+                                                               uint16_t *__restrict__ x_row,
+                                                               uint16_t *__restrict__ x_col,
+                                                               double *__restrict__ theta,
+                                                               double *__restrict__ s64) {
 #pragma clang fp contract(off)
-    extern __shared__ double ys_all[];
-    __shared__ double tot_all[kSimWaves][kPolyAcc];
-    __shared__ double s_all[kSimWaves][kSummaryDim];
-    __shared__ int hist_all[kSimWaves][32];
-    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-    const int b = blockIdx.x * kSimWaves + wv;
+    extern __shared__ double ys[];
+    __shared__ double wtot[kSumWaves][kPolyAcc];
+    __shared__ double tot[kPolyAcc];
+    __shared__ double s[kSummaryDim];
+    __shared__ double red[kSumWaves];
+    __shared__ int hist[32];
+    const int tid = threadIdx.x;
+    const int b = blockIdx.x;
     const uint32_t step = (uint32_t)*step_ptr;
     const uint32_t pair = (uint32_t)b;
     const int64_t D = sp.D;
-    double *s = s_all[wv];
 
     if constexpr (MODEL == PPL_MODEL_POLY) {
         const uint4 w0 = philox(pair, 0, step, kTagTrain, key);
@@ -256,7 +273,7 @@ __global__ __launch_bounds__(64 * kSimWaves) void simulate_kernel(SimSpec sp, in
         double a[kPolyAcc];
 #pragma unroll
         for (int k = 0; k < kPolyAcc; ++k) a[k] = 0.0;
-        for (int64_t e = lane; 2 * e < D; e += 64) {
+        for (int64_t e = tid; 2 * e < D; e += kSumThreads) {
             const uint4 w = philox(pair, (uint32_t)(8 + e), step, kTagTrain, key);
             double e0, e1;
             box_muller(u01(w.z), u01(w.w), e0, e1);
@@ -273,23 +290,21 @@ __global__ __launch_bounds__(64 * kSimWaves) void simulate_kernel(SimSpec sp, in
                 }
             }
         }
-        poly_finish(a, D, tot_all[wv], s);
-        if (lane < 6) theta[(size_t)b * kThetaStride + lane] = lane == 0 ? (double)n : (lane - 1 < n ? c[lane - 1] : 0.0);
+        poly_finish(a, D, wtot, tot, s);
+        if (tid < 6) theta[(size_t)b * kThetaStride + tid] = tid == 0 ? (double)n : (tid - 1 < n ? c[tid - 1] : 0.0);
     } else {
         const int K = sp.K;
-        double *ys = ys_all + (size_t)wv * ((D + 1) & ~(int64_t)1);
-        int *hist = hist_all[wv];
-        if (lane < 32) hist[lane] = 0;
+        if (tid < 32) hist[tid] = 0;
         const uint4 wa = philox(pair, 0, step, kTagTrain, key), wb = philox(pair, 1, step, kTagTrain, key);
         const uint32_t ew[8] = {wa.x, wa.y, wa.z, wa.w, wb.x, wb.y, wb.z, wb.w};
-        double E[8], pi[8], mu[8], z[8], tot = 0.0;
+        double E[8], pi[8], mu[8], z[8], etot = 0.0;
 #pragma unroll
         for (int k = 0; k < 8; ++k) {
             E[k] = k < K ? -log(u01(ew[k])) : 0.0;
-            if (k < K) tot += E[k];
+            if (k < K) etot += E[k];
         }
 #pragma unroll
-        for (int k = 0; k < 8; ++k) pi[k] = k < K ? E[k] / tot : 0.0;
+        for (int k = 0; k < 8; ++k) pi[k] = k < K ? E[k] / etot : 0.0;
         {
             const uint4 w2 = philox(pair, 2, step, kTagTrain, key), w3 = philox(pair, 3, step, kTagTrain, key);
             box_muller(u01(w2.x), u01(w2.y), z[0], z[1]);
@@ -301,7 +316,7 @@ __global__ __launch_bounds__(64 * kSimWaves) void simulate_kernel(SimSpec sp, in
         for (int k = 0; k < 8; ++k) mu[k] = sp.hyper[0] * z[k];
         __syncthreads();
         double sum_y = 0.0;
-        for (int64_t e = lane; 2 * e < D; e += 64) {
+        for (int64_t e = tid; 2 * e < D; e += kSumThreads) {
             const uint4 w = philox(pair, (uint32_t)(8 + e), step, kTagTrain, key);
             double e0, e1;
             box_muller(u01(w.z), u01(w.w), e0, e1);
@@ -317,8 +332,8 @@ __global__ __launch_bounds__(64 * kSimWaves) void simulate_kernel(SimSpec sp, in
             }
         }
         __syncthreads();
-        gmm_finish(ys, D, hist, sum_y, s);
-        if (lane == 0) {
+        gmm_finish(ys, D, hist, sum_y, red, s);
+        if (tid == 0) {
             // order the components by mean (insertion sort; ties keep index order)
             int ord[8] = {0, 1, 2, 3, 4, 5, 6, 7};
             for (int q = 1; q < K; ++q)
@@ -334,63 +349,68 @@ __global__ __launch_bounds__(64 * kSimWaves) void simulate_kernel(SimSpec sp, in
             for (int q = 0; q < K - 1; ++q) u[K + q] = log(pi[ord[q]]) - lk;
         }
     }
-    const double v = s[lane];
-    const uint16_t h = f32_to_bf16((float)v);
-    x_row[(size_t)b * kSummaryDim + lane] = h;
-    x_col[(size_t)lane * B + b] = h;
-    if (s64) s64[(size_t)b * kSummaryDim + lane] = v;
+    if (tid < kSummaryDim) {
+        const double v = s[tid];
+        const uint16_t h = f32_to_bf16((float)v);
+        x_row[(size_t)b * kSummaryDim + tid] = h;
+        x_col[(size_t)tid * B + b] = h;
+        if (s64) s64[(size_t)b * kSummaryDim + tid] = v;
+    }
 }
 
 // ----------------------------------------------------- observed summary --
 template <int MODEL>
-__global__ __launch_bounds__(64) void observed_summary_kernel(const void *__restrict__ xv, const void *__restrict__ yv,
-                                                              int64_t D, uint16_t *__restrict__ x_row,
-                                                              double *__restrict__ s64) {
+__global__ __launch_bounds__(kSumThreads) void observed_summary_kernel(const void *__restrict__ xv,
+                                                                       const void *__restrict__ yv, int64_t D,
+                                                                       uint16_t *__restrict__ x_row,
+                                                                       double *__restrict__ s64) {
 #pragma clang fp contract(off)
-    extern __shared__ float ys[];
+    extern __shared__ float ysf[];
+    __shared__ double wtot[kSumWaves][kPolyAcc];
     __shared__ double tot[kPolyAcc];
     __shared__ double s[kSummaryDim];
+    __shared__ double red[kSumWaves];
     __shared__ int hist[32];
-    const int lane = threadIdx.x;
+    const int tid = threadIdx.x;
     if constexpr (MODEL == PPL_MODEL_POLY) {
         const double *X = (const double *)xv, *Y = (const double *)yv;
         double a[kPolyAcc];
 #pragma unroll
         for (int k = 0; k < kPolyAcc; ++k) a[k] = 0.0;
-        for (int64_t d = lane; d < D; d += 64) poly_acc_point(a, X[d], Y[d]);
-        poly_finish(a, D, tot, s);
+        for (int64_t d = tid; d < D; d += kSumThreads) poly_acc_point(a, X[d], Y[d]);
+        poly_finish(a, D, wtot, tot, s);
     } else {
         const float *Y = (const float *)yv;
-        if (lane < 32) hist[lane] = 0;
+        if (tid < 32) hist[tid] = 0;
         __syncthreads();
         double sum_y = 0.0;
-        for (int64_t d = lane; d < D; d += 64) {
+        for (int64_t d = tid; d < D; d += kSumThreads) {
             const float yf = Y[d];
-            ys[d] = yf;
+            ysf[d] = yf;
             sum_y += (double)yf;
             gmm_bin(hist, (double)yf);
         }
         __syncthreads();
-        gmm_finish(ys, D, hist, sum_y, s);
+        gmm_finish(ysf, D, hist, sum_y, red, s);
     }
-    const double v = s[lane];
-    x_row[lane] = f32_to_bf16((float)v);
-    for (int r = 1; r < 64; ++r) x_row[(size_t)r * kSummaryDim + lane] = 0;
-    if (s64) s64[lane] = v;
+    // row 0 holds the summaries, rows 1..63 of the 64-row batch are cleared
+    for (int e = tid; e < 64 * kSummaryDim; e += kSumThreads)
+        x_row[e] = e < kSummaryDim ? f32_to_bf16((float)s[e]) : (uint16_t)0;
+    if (s64 && tid < kSummaryDim) s64[tid] = s[tid];
 }
 
 // ------------------------------------------------------------------ host --
 int launch_simulate(const SimSpec &sp, int B, uint64_t seed, const int64_t *step, uint16_t *x_row, uint16_t *x_col,
                     double *theta, double *s64, hipStream_t st) {
-    if (B <= 0 || B % kSimWaves) return fail(PPL_E_ARG, "simulation batch %d is not a positive multiple of 4", B);
-    const dim3 grid((unsigned)(B / kSimWaves)), block(64 * kSimWaves);
+    if (B <= 0) return fail(PPL_E_ARG, "simulation batch %d is not positive", B);
+    const dim3 grid((unsigned)B), block(kSumThreads);
     if (sp.model == PPL_MODEL_POLY) {
         hipLaunchKernelGGL(simulate_kernel<PPL_MODEL_POLY>, grid, block, 0, st, sp, B, make_key(seed), step, x_row,
                            x_col, theta, s64);
         PPL_LAUNCH_CHECK("simulate_kernel<POLY>");
     } else {
         if (sp.D > kGmmTrainMaxD) return fail(PPL_E_ARG, "mixture training datasets hold at most %d points", kGmmTrainMaxD);
-        const size_t lds = (size_t)kSimWaves * ((sp.D + 1) & ~(int64_t)1) * sizeof(double);
+        const size_t lds = (size_t)(sp.D > 0 ? sp.D : 1) * sizeof(double);
         hipLaunchKernelGGL(simulate_kernel<PPL_MODEL_GMM>, grid, block, lds, st, sp, B, make_key(seed), step, x_row,
                            x_col, theta, s64);
         PPL_LAUNCH_CHECK("simulate_kernel<GMM>");
@@ -401,11 +421,13 @@ int launch_simulate(const SimSpec &sp, int B, uint64_t seed, const int64_t *step
 int launch_observed_summary(int model, const void *x, const void *y, int64_t D, uint16_t *x_row, double *s64,
                             hipStream_t st) {
     if (model == PPL_MODEL_POLY) {
-        hipLaunchKernelGGL(observed_summary_kernel<PPL_MODEL_POLY>, dim3(1), dim3(64), 0, st, x, y, D, x_row, s64);
+        hipLaunchKernelGGL(observed_summary_kernel<PPL_MODEL_POLY>, dim3(1), dim3(kSumThreads), 0, st, x, y, D, x_row,
+                           s64);
     } else {
         if (D > kGmmSummaryMaxD) return fail(PPL_E_ARG, "mixture summaries take at most %d points", kGmmSummaryMaxD);
         const size_t lds = (size_t)(D > 0 ? D : 1) * sizeof(float);
-        hipLaunchKernelGGL(observed_summary_kernel<PPL_MODEL_GMM>, dim3(1), dim3(64), lds, st, x, y, D, x_row, s64);
+        hipLaunchKernelGGL(observed_summary_kernel<PPL_MODEL_GMM>, dim3(1), dim3(kSumThreads), lds, st, x, y, D,
+                           x_row, s64);
     }
     PPL_LAUNCH_CHECK("observed_summary_kernel");
     return PPL_OK;

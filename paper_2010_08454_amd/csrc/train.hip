@@ -30,157 +30,134 @@ constexpr int kLdsRow = 258;          // BF16 per LDS row of the head (odd word 
 __host__ __device__ constexpr int poly_head_off(int n) { return 12 + 8 * (n - 2) * (n + 1); }
 
 // ---------------------------------------------------------------- head --
-// One thread per training pair; 64 pairs per workgroup.  The gradient of the
+// Eight lanes per training pair, lane m owning mixture component m; 32 pairs
+// per 256-thread workgroup.  The component sums (log-softmax, log-sum-exp over
+// components) are butterflies within the 8-lane group.  The gradient of the
 // loss w.r.t. the outputs, divided by the batch size, is rounded to BF16 and
-// staged in LDS so both the row-major and column-major copies are written
-// with coalesced stores.
+// staged in LDS, so both the row-major and the column-major copies are
+// written with contiguous stores.
+constexpr int kHeadPairs = 32;
+
+__device__ __forceinline__ float group8_max(float v) {
+#pragma unroll
+    for (int o = 4; o > 0; o >>= 1) v = fmaxf(v, __shfl_xor(v, o, 64));
+    return v;
+}
+__device__ __forceinline__ float group8_sum(float v) {
+#pragma unroll
+    for (int o = 4; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+    return v;
+}
+
 template <int MODEL>
-__global__ __launch_bounds__(64) void head_kernel(const float *__restrict__ o_col, int B,
-                                                  const double *__restrict__ theta, int K, float inv_b,
-                                                  uint16_t *__restrict__ do_row, uint16_t *__restrict__ do_col,
-                                                  double *__restrict__ lossp) {
-    __shared__ uint32_t lds32[64 * kLdsRow / 2];
+__global__ __launch_bounds__(256) void head_kernel(const float *__restrict__ o_col, int B,
+                                                   const double *__restrict__ theta, int K, float inv_b,
+                                                   uint16_t *__restrict__ do_row, uint16_t *__restrict__ do_col,
+                                                   double *__restrict__ lossp) {
+    __shared__ uint32_t lds32[kHeadPairs * kLdsRow / 2];
+    __shared__ double red[4];
     uint16_t *lds = (uint16_t *)lds32;
-    const int lane = threadIdx.x;
-    const int b0 = blockIdx.x * 64, b = b0 + lane;
-    for (int k = 0; k < kLdsRow / 2; ++k) lds32[lane * (kLdsRow / 2) + k] = 0u;
-    uint16_t *g = lds + lane * kLdsRow;
+    const int tid = threadIdx.x, m = tid & 7, sl = tid >> 3;
+    const int b0 = blockIdx.x * kHeadPairs, b = b0 + sl;
+    for (int k = tid; k < kHeadPairs * kLdsRow / 2; k += 256) lds32[k] = 0u;
+    __syncthreads();
+    uint16_t *g = lds + sl * kLdsRow;
     const float *o = o_col + b;            // output k at o[k * B]
     const double *th = theta + (size_t)b * kThetaStride;
     float loss;
+    // mixture weights: lane m's log-softmax entry
+    const int mix0 = MODEL == PPL_MODEL_POLY ? 4 : 0;
+    const float zm = o[(size_t)(mix0 + m) * B];
+    const float mm = group8_max(zm);
+    const float lse_m = mm + logf(group8_sum(expf(zm - mm)));
+    const float lmix = zm - lse_m;
+    float t = lmix;
     if constexpr (MODEL == PPL_MODEL_POLY) {
         const int n = min(max((int)th[0], 2), 5);
-        float c[5];
+        const int off = poly_head_off(n);
 #pragma unroll
-        for (int j = 0; j < 5; ++j) c[j] = (float)th[1 + j];
-        float z[4], lm[8];
-        float mx = -INFINITY;
+        for (int j = 0; j < 5; ++j) {
+            if (j < n) {
+                const float mu = 10.0f * o[(size_t)(off + m * n + j) * B];
+                const float lsd = 5.0f * tanhf(o[(size_t)(off + 8 * n + m * n + j) * B] * 0.2f);
+                const float r = ((float)th[1 + j] - mu) * expf(-lsd);
+                t += -0.5f * r * r - lsd - kHalfLog2Pi;
+            }
+        }
+        const float tm = group8_max(t);
+        const float L = tm + logf(group8_sum(expf(t - tm)));
+        const float resp = expf(t - L);
+        // degree term: lanes 0..3 own degree n = 2 + m
+        float zn[4], mx = -INFINITY;
 #pragma unroll
         for (int k = 0; k < 4; ++k) {
-            z[k] = o[(size_t)k * B];
-            mx = fmaxf(mx, z[k]);
+            zn[k] = o[(size_t)k * B];
+            mx = fmaxf(mx, zn[k]);
         }
         float se = 0.0f;
 #pragma unroll
-        for (int k = 0; k < 4; ++k) se += expf(z[k] - mx);
+        for (int k = 0; k < 4; ++k) se += expf(zn[k] - mx);
         const float lse_n = mx + logf(se);
-        float mm = -INFINITY;
+        float zsel = zn[0];
 #pragma unroll
-        for (int k = 0; k < 8; ++k) {
-            lm[k] = o[(size_t)(4 + k) * B];
-            mm = fmaxf(mm, lm[k]);
+        for (int k = 1; k < 4; ++k) zsel = (k == n - 2) ? zn[k] : zsel;
+        loss = m == 0 ? -(zsel - lse_n) - L : 0.0f;
+        if (m < 4) {
+            float zk = zn[0];
+#pragma unroll
+            for (int k = 1; k < 4; ++k) zk = (k == m) ? zn[k] : zk;
+            g[m] = f32_to_bf16((expf(zk - lse_n) - (m == n - 2 ? 1.0f : 0.0f)) * inv_b);
         }
-        float sm = 0.0f;
+        g[4 + m] = f32_to_bf16((expf(lmix) - resp) * inv_b);
 #pragma unroll
-        for (int k = 0; k < 8; ++k) sm += expf(lm[k] - mm);
-        const float lse_m = mm + logf(sm);
-#pragma unroll
-        for (int k = 0; k < 8; ++k) lm[k] -= lse_m;
-        const int off = poly_head_off(n);
-        float t[8];
-#pragma unroll
-        for (int m = 0; m < 8; ++m) {
-            float acc = lm[m];
-#pragma unroll
-            for (int j = 0; j < 5; ++j) {
-                if (j < n) {
-                    const float mu = 10.0f * o[(size_t)(off + m * n + j) * B];
-                    const float lsd = 5.0f * tanhf(o[(size_t)(off + 8 * n + m * n + j) * B] * 0.2f);
-                    const float r = (c[j] - mu) * expf(-lsd);
-                    acc += -0.5f * r * r - lsd - kHalfLog2Pi;
-                }
-            }
-            t[m] = acc;
-        }
-        float tm = -INFINITY;
-#pragma unroll
-        for (int m = 0; m < 8; ++m) tm = fmaxf(tm, t[m]);
-        float st = 0.0f;
-#pragma unroll
-        for (int m = 0; m < 8; ++m) st += expf(t[m] - tm);
-        const float L = tm + logf(st);
-        loss = -(z[n - 2] - lse_n) - L;
-#pragma unroll
-        for (int k = 0; k < 4; ++k) {
-            const float gk = expf(z[k] - lse_n) - (k == n - 2 ? 1.0f : 0.0f);
-            g[k] = f32_to_bf16(gk * inv_b);
-        }
-#pragma unroll
-        for (int m = 0; m < 8; ++m) {
-            const float resp = expf(t[m] - L);
-            g[4 + m] = f32_to_bf16((expf(lm[m]) - resp) * inv_b);
-#pragma unroll
-            for (int j = 0; j < 5; ++j) {
-                if (j < n) {
-                    const int km = off + m * n + j, ks = off + 8 * n + m * n + j;
-                    const float mu = 10.0f * o[(size_t)km * B];
-                    const float th5 = tanhf(o[(size_t)ks * B] * 0.2f);
-                    const float iv = expf(-5.0f * th5);
-                    const float dv = c[j] - mu;
-                    const float r = dv * iv;
-                    g[km] = f32_to_bf16(-resp * dv * iv * iv * 10.0f * inv_b);
-                    g[ks] = f32_to_bf16(-resp * (r * r - 1.0f) * (1.0f - th5 * th5) * inv_b);
-                }
+        for (int j = 0; j < 5; ++j) {
+            if (j < n) {
+                const int km = off + m * n + j, ks = off + 8 * n + m * n + j;
+                const float mu = 10.0f * o[(size_t)km * B];
+                const float th5 = tanhf(o[(size_t)ks * B] * 0.2f);
+                const float iv = expf(-5.0f * th5);
+                const float dv = (float)th[1 + j] - mu;
+                const float r = dv * iv;
+                g[km] = f32_to_bf16(-resp * dv * iv * iv * 10.0f * inv_b);
+                g[ks] = f32_to_bf16(-resp * (r * r - 1.0f) * (1.0f - th5 * th5) * inv_b);
             }
         }
     } else {
         const int d = 2 * K - 1;
-        float lm[8];
-        float mm = -INFINITY;
-#pragma unroll
-        for (int k = 0; k < 8; ++k) {
-            lm[k] = o[(size_t)k * B];
-            mm = fmaxf(mm, lm[k]);
+        for (int j = 0; j < d; ++j) {
+            const float mu = 5.0f * o[(size_t)(8 + m * d + j) * B];
+            const float lsd = 5.0f * tanhf(o[(size_t)(8 + 8 * d + m * d + j) * B] * 0.2f);
+            const float r = ((float)th[j] - mu) * expf(-lsd);
+            t += -0.5f * r * r - lsd - kHalfLog2Pi;
         }
-        float sm = 0.0f;
-#pragma unroll
-        for (int k = 0; k < 8; ++k) sm += expf(lm[k] - mm);
-        const float lse_m = mm + logf(sm);
-#pragma unroll
-        for (int k = 0; k < 8; ++k) lm[k] -= lse_m;
-        float t[8];
-#pragma unroll
-        for (int m = 0; m < 8; ++m) {
-            float acc = lm[m];
-            for (int j = 0; j < d; ++j) {
-                const float mu = 5.0f * o[(size_t)(8 + m * d + j) * B];
-                const float lsd = 5.0f * tanhf(o[(size_t)(8 + 8 * d + m * d + j) * B] * 0.2f);
-                const float r = ((float)th[j] - mu) * expf(-lsd);
-                acc += -0.5f * r * r - lsd - kHalfLog2Pi;
-            }
-            t[m] = acc;
-        }
-        float tm = -INFINITY;
-#pragma unroll
-        for (int m = 0; m < 8; ++m) tm = fmaxf(tm, t[m]);
-        float st = 0.0f;
-#pragma unroll
-        for (int m = 0; m < 8; ++m) st += expf(t[m] - tm);
-        const float L = tm + logf(st);
-        loss = -L;
-#pragma unroll
-        for (int m = 0; m < 8; ++m) {
-            const float resp = expf(t[m] - L);
-            g[m] = f32_to_bf16((expf(lm[m]) - resp) * inv_b);
-            for (int j = 0; j < d; ++j) {
-                const int km = 8 + m * d + j, ks = 8 + 8 * d + m * d + j;
-                const float mu = 5.0f * o[(size_t)km * B];
-                const float th5 = tanhf(o[(size_t)ks * B] * 0.2f);
-                const float iv = expf(-5.0f * th5);
-                const float dv = (float)th[j] - mu;
-                const float r = dv * iv;
-                g[km] = f32_to_bf16(-resp * dv * iv * iv * 5.0f * inv_b);
-                g[ks] = f32_to_bf16(-resp * (r * r - 1.0f) * (1.0f - th5 * th5) * inv_b);
-            }
+        const float tm = group8_max(t);
+        const float L = tm + logf(group8_sum(expf(t - tm)));
+        const float resp = expf(t - L);
+        loss = m == 0 ? -L : 0.0f;
+        g[m] = f32_to_bf16((expf(lmix) - resp) * inv_b);
+        for (int j = 0; j < d; ++j) {
+            const int km = 8 + m * d + j, ks = 8 + 8 * d + m * d + j;
+            const float mu = 5.0f * o[(size_t)km * B];
+            const float th5 = tanhf(o[(size_t)ks * B] * 0.2f);
+            const float iv = expf(-5.0f * th5);
+            const float dv = (float)th[j] - mu;
+            const float r = dv * iv;
+            g[km] = f32_to_bf16(-resp * dv * iv * iv * 5.0f * inv_b);
+            g[ks] = f32_to_bf16(-resp * (r * r - 1.0f) * (1.0f - th5 * th5) * inv_b);
         }
     }
     const double ls = wave_sum((double)loss);
-    if (lane == 0) lossp[blockIdx.x] = ls;
+    if ((tid & 63) == 0) red[tid >> 6] = ls;
     __syncthreads();
-    for (int k = 0; k < kMlpOut; ++k) do_col[(size_t)k * B + b] = lds[lane * kLdsRow + k];
-    for (int r = 0; r < 64; ++r)
-#pragma unroll
-        for (int q = 0; q < 4; ++q) do_row[(size_t)(b0 + r) * kMlpOut + q * 64 + lane] = lds[r * kLdsRow + q * 64 + lane];
+    if (tid == 0) lossp[blockIdx.x] = (red[0] + red[1]) + (red[2] + red[3]);
+    for (int e = tid; e < kHeadPairs * kMlpOut; e += 256) {
+        const int k = e / kHeadPairs, q = e % kHeadPairs;
+        do_col[(size_t)k * B + b0 + q] = lds[q * kLdsRow + k];
+    }
+    for (int e = tid; e < kHeadPairs * kMlpOut; e += 256) {
+        const int q = e / kMlpOut, k = e % kMlpOut;
+        do_row[(size_t)(b0 + q) * kMlpOut + k] = lds[q * kLdsRow + k];
+    }
 }
 
 // ------------------------------------------------------ bias gradients --
@@ -359,7 +336,7 @@ size_t train_ws_bytes(int B) {
     n += a256((size_t)nc[1] * kMlpHid * kMlpHid * 4);
     n += a256((size_t)nc[2] * kMlpOut * kMlpHid * 4);
     n += a256(3 * 256 * 4);                              // bgrad
-    n += a256((bB / 64 + 1) * 8);                        // loss partials
+    n += a256((bB / kHeadPairs + 1) * 8);                // loss partials
     n += 256;                                            // local counter
     return n;
 }
@@ -394,7 +371,7 @@ TrainBufs train_bufs(void *ws, int B) {
     t.part[1] = (float *)take((size_t)t.nchunks[1] * kMlpHid * kMlpHid * 4);
     t.part[2] = (float *)take((size_t)t.nchunks[2] * kMlpOut * kMlpHid * 4);
     t.bgrad = (float *)take(3 * 256 * 4);
-    t.lossp = (double *)take((bB / 64 + 1) * 8);
+    t.lossp = (double *)take((bB / kHeadPairs + 1) * 8);
     t.local = (int64_t *)take(16);
     return t;
 }
@@ -417,11 +394,11 @@ int launch_head_backward(int model, int K, const MlpView &w, const TrainBufs &b,
     {
         KernelTimer timer("head_kernel", st);
         if (model == PPL_MODEL_POLY)
-            hipLaunchKernelGGL(head_kernel<PPL_MODEL_POLY>, dim3(B / 64), dim3(64), 0, st, b.o_col, B, b.theta, K,
-                               inv_b, b.do_row, b.do_col, b.lossp);
+            hipLaunchKernelGGL(head_kernel<PPL_MODEL_POLY>, dim3(B / kHeadPairs), dim3(256), 0, st, b.o_col, B,
+                               b.theta, K, inv_b, b.do_row, b.do_col, b.lossp);
         else
-            hipLaunchKernelGGL(head_kernel<PPL_MODEL_GMM>, dim3(B / 64), dim3(64), 0, st, b.o_col, B, b.theta, K,
-                               inv_b, b.do_row, b.do_col, b.lossp);
+            hipLaunchKernelGGL(head_kernel<PPL_MODEL_GMM>, dim3(B / kHeadPairs), dim3(256), 0, st, b.o_col, B,
+                               b.theta, K, inv_b, b.do_row, b.do_col, b.lossp);
         timer.stop();
         PPL_LAUNCH_CHECK("head_kernel");
     }
@@ -455,7 +432,8 @@ int launch_update(const MlpView &w, const TrainBufs &b, const AdamSpec &ad, floa
 }
 
 int launch_advance(int64_t *step, const TrainBufs &b, double *loss_trace, hipStream_t st) {
-    hipLaunchKernelGGL(advance_kernel, dim3(1), dim3(64), 0, st, step, b.local, (const double *)b.lossp, b.B / 64,
+    hipLaunchKernelGGL(advance_kernel, dim3(1), dim3(64), 0, st, step, b.local, (const double *)b.lossp,
+                       b.B / kHeadPairs,
                        1.0 / (double)b.B, loss_trace);
     PPL_LAUNCH_CHECK("advance_kernel");
     return PPL_OK;
