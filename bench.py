@@ -16,7 +16,7 @@ Printed as one JSON line, with
   cpu_baseline -- the CPU oracle on a bounded sample of the same workload.
 
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu]
-                       [--config blr|poly|poly-paper|lgssm|gmm-batched|proposal-poly|proposal-gmm]
+                       [--config blr|poly|poly-paper|lgssm|gmm-batched|proposal-poly|proposal-gmm|proposal-train]
 """
 import argparse
 import json
@@ -45,7 +45,10 @@ def parse():
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--config", default="blr",
-                    choices=["blr", "poly", "poly-paper", "lgssm", "gmm-batched", "proposal-poly", "proposal-gmm"])
+                    choices=["blr", "poly", "poly-paper", "lgssm", "gmm-batched", "proposal-poly", "proposal-gmm",
+                             "proposal-train"])
+    ap.add_argument("--pairs-log2", type=int, default=22, help="proposal-train: log2 of the simulated pairs")
+    ap.add_argument("--no-graph", action="store_true", help="proposal-train: launch each step's kernels eagerly")
     ap.add_argument("--batch", type=int, default=0, help="proposal: training batch (default 4096)")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--cpu-seconds", type=float, default=15.0, help="target length of the oracle sample")
@@ -285,6 +288,44 @@ def bench_proposal(args, ppl, synthetic, torch, dev, stream):
     print(json.dumps(out), flush=True)
 
 
+def bench_proposal_train(args, ppl, torch, dev, stream):
+    """Training of the POLY proposal network alone (the network products are the
+    MFMA work): simulated pairs per second, and the GEMM kernels' FLOP rate
+    against the BF16 dense MFMA peak."""
+    B = args.batch or 512
+    pairs = 1 << args.pairs_log2
+    steps = pairs // B
+    cfg = ppl.train_config(pairs, B, 1000, lr=1e-3, use_graph=not args.no_graph)
+    wts = ppl.ppl_proposal_init(1, stream=stream)
+    tws = ppl.workspace(ppl.ppl_proposal_train_workspace_size(ppl.PPL_MODEL_POLY, cfg), dev)
+    trace = torch.empty(steps, dtype=torch.float64, device=dev)
+    warm = ppl.train_config(8 * B, B, 1000, lr=1e-3)
+    ppl.ppl_proposal_train(ppl.PPL_MODEL_POLY, warm, 1, ppl.ppl_proposal_init(2, stream=stream), ws=tws, stream=stream)
+    torch.cuda.synchronize()
+    ppl.ppl_timing_enable(args.no_graph)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    ppl.ppl_proposal_train(ppl.PPL_MODEL_POLY, cfg, 1, wts, loss_trace=trace, ws=tws, stream=stream)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1)
+    out = {"metric": "simulated training pairs/s", "value": pairs / (ms / 1e3), "unit": "pairs/s", "n_gpus": 1,
+           "steps": steps, "warmup": 8, "ms_per_step": round(ms / steps, 4), "higher_is_better": True,
+           "scaling": "weak", "vs_baseline": None, "dtype": "bf16",
+           "data": "synthetic (pairs simulated from the model prior on the device)",
+           "config": {"workload": "learned-proposal-training-poly", "pairs": pairs, "batch": B,
+                      "graph": not args.no_graph, "loss_last": float(trace[-8:].mean())}}
+    if args.no_graph:
+        g_ms, g_n = ppl.ppl_timing_query("gemm_nt_kernel")
+        achieved = GEMM_FLOP_PER_PAIR * pairs / (g_ms / 1e3) / 1e12
+        out["roofline"] = {"bound": "mfma", "achieved": round(achieved, 3), "peak": BF16_MFMA_TFLOPS,
+                           "unit": "TFLOP/s", "frac": round(achieved / BF16_MFMA_TFLOPS, 5), "traffic": None,
+                           "kernel": "gemm_nt_kernel", "kernel_ms": round(g_ms / max(g_n, 1), 5),
+                           "kernel_launches": g_n, "flop_per_pair": GEMM_FLOP_PER_PAIR}
+    ppl.ppl_timing_enable(False)
+    print(json.dumps(out), flush=True)
+
+
 def cpu_baseline_prior_ess(poly, x, y, D, target_s=15.0):
     """The oracle's prior-proposal importance sampling on the same data: ESS per
     second on a particle count sized to about target_s seconds."""
@@ -330,6 +371,9 @@ def main():
     dev = torch.device("cuda:0")
     torch.cuda.set_device(dev)
     stream = torch.cuda.current_stream()
+    if args.config == "proposal-train":
+        bench_proposal_train(args, ppl, torch, dev, stream)
+        return
     if args.config.startswith("proposal"):
         bench_proposal(args, ppl, synthetic, torch, dev, stream)
         return

@@ -321,6 +321,7 @@ __global__ __launch_bounds__(kSmcThreads) void smc_persistent_kernel(SmcDev a) {
     __shared__ uint64_t ldsu[kSmcWaves];
     __shared__ float ybuf[kYChunk];
     __shared__ int s_rng[2];
+    __shared__ int s_cnt[kSmcWaves];
     // dynamic LDS: tile_end[nb] | tile_pre[nb] | stage[stage_cap] (u64) | s_anc[1024 P] (i32)
     extern __shared__ uint64_t dyn[];
     const int nb = gridDim.x;
@@ -453,16 +454,38 @@ __global__ __launch_bounds__(kSmcThreads) void smc_persistent_kernel(SmcDev a) {
             const uint64_t NN = (uint64_t)N;
             const uint64_t Sq = S / NN, Sr = S - Sq * NN;
 
-            // ancestor range of this block's slots (two searches, in different waves)
+            // ancestor range of this block's slots: the first and last slot's
+            // ancestors, each found by half of the block.  The ancestor's tile
+            // is the first with tile_end > tau (LDS); within it the prefix sums
+            // are non-decreasing, so the ancestor's offset is the number of
+            // entries <= tau, counted with one round of independent loads.
             const int js0 = blockIdx.x * kTile;
             const int js1 = (int)min((int64_t)js0 + kTile, N) - 1;
-            if (threadIdx.x == 0) {
-                const SlotThreshold t = slot_threshold((uint32_t)js0, Sr, U, NN);
-                s_rng[0] = find_ancestor_global((uint64_t)js0 * Sq + t.quo, N, nb, kTile, tile_end, tile_pre, a.qloc, -1);
-            }
-            if (threadIdx.x == 64) {
-                const SlotThreshold t = slot_threshold((uint32_t)js1, Sr, U, NN);
-                s_rng[1] = find_ancestor_global((uint64_t)js1 * Sq + t.quo, N, nb, kTile, tile_end, tile_pre, a.qloc, -1);
+            {
+                constexpr int kHalf = kSmcThreads / 2;
+                const int half = threadIdx.x / kHalf, hl = threadIdx.x % kHalf;
+                const uint32_t jsx = (uint32_t)(half ? js1 : js0);
+                const SlotThreshold t = slot_threshold(jsx, Sr, U, NN);
+                const uint64_t tau = (uint64_t)jsx * Sq + t.quo;
+                int lo = 0, hi = nb - 1;
+                while (lo < hi) {
+                    const int mid = (lo + hi) >> 1;
+                    if (tile_end[mid] > tau) hi = mid; else lo = mid + 1;
+                }
+                const int64_t tb = (int64_t)lo * kTile;
+                const int len = (int)min((int64_t)kTile, N - tb);
+                const uint64_t pre = tile_pre[lo];
+                int cnt = 0;
+                for (int i = hl; i < len; i += kHalf) cnt += (pre + a.qloc[tb + i] <= tau) ? 1 : 0;
+#pragma unroll
+                for (int o = 32; o > 0; o >>= 1) cnt += __shfl_xor(cnt, o, 64);
+                if ((threadIdx.x & 63) == 0) s_cnt[threadIdx.x >> 6] = cnt;
+                __syncthreads();
+                if (hl == 0) {
+                    int c = 0;
+                    for (int w = 0; w < kSmcWaves / 2; ++w) c += s_cnt[half * (kSmcWaves / 2) + w];
+                    s_rng[half] = (int)(tb + c);
+                }
             }
             __syncthreads();
             const int a_lo = s_rng[0], a_hi = s_rng[1];
