@@ -229,8 +229,8 @@ typedef struct ppl_instance {
 } ppl_instance;
 
 /* Launch configuration of the batched engine (0 fields = default/derived).
- * particles_per_lane P in {1,2,4,8}; wgs_per_instance W = 1024-thread
- * workgroups that hold one instance (W * 1024 * P >= max N_i, W <= 64);
+ * particles_per_lane P in {1,2,4,8}; wgs_per_instance W = 512-thread
+ * workgroups that hold one instance (W * 512 * P >= max N_i, W <= 64);
  * spec_block = largest number of factors advanced between synchronisations
  * (1..128).  Results are the SMC of each instance for any valid choice; the
  * choice only changes the order of the FP64 sums behind the resampling

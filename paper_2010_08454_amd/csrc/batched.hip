@@ -4,9 +4,11 @@
 // per-instance algorithm is the SMC of smc.hip (the particle method the paper
 // names as future work, Sec. 6, over the sample/factor semantics of Sec. 3.4).
 //
-// Mapping.  The grid (one 1024-thread workgroup per CU) is split into teams of
-// W workgroups; a team holds one instance at a time (slots j = w * 1024 P +
-// thread * P + p, P particles per thread, state in registers) and walks a list
+// Mapping.  The grid (one 512-thread workgroup per CU: each wave then has 256
+// registers, so the particle state and the speculative-block bookkeeping stay
+// out of scratch memory) is split into teams of W workgroups; a team holds one
+// instance at a time (slots j = w * 512 P + thread * P + p, P particles per
+// thread, state in registers) and walks a list
 // of instances assigned on the host by longest-processing-time-first, so the
 // makespan is balanced.  Teams never wait on each other.
 //
@@ -37,7 +39,7 @@
 
 namespace ppl {
 
-constexpr int kBtThreads = 1024;
+constexpr int kBtThreads = 512;
 constexpr int kBtWaves = kBtThreads / 64;
 constexpr int kBtMaxInst = 1024;
 constexpr int kBtMaxTeams = 256;
@@ -56,7 +58,7 @@ struct BtDev {
     int W;                   // workgroups per team
     int Bmax;                // speculative block limit
     int stage_cap;
-    int64_t cap;             // slots per team (W * 1024 * P)
+    int64_t cap;             // slots per team (W * kBtThreads * P)
     double *out;             // [n_inst][4]
     float *lw_out, *lat_out;
     double *ess_tr;
@@ -215,7 +217,7 @@ __global__ __launch_bounds__(kBtThreads) void smc_batched_kernel(BtDev a) {
     __shared__ int s_first;                            // first triggering factor in the block
     __shared__ int s_rng[2];
     __shared__ uint64_t tile_end[kBtMaxW], tile_pre[kBtMaxW];
-    extern __shared__ uint64_t dyn[];                  // stage[stage_cap] | s_anc[1024 P]
+    extern __shared__ uint64_t dyn[];                  // stage[stage_cap] | s_anc[kBtThreads P]
     uint64_t *stage = dyn;
     int32_t *s_anc = (int32_t *)(dyn + a.stage_cap);
 

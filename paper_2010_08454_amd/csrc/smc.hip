@@ -6,8 +6,12 @@
 // shared by all particles) plus fixed-size state held in registers across the
 // whole run; only resampling moves state through device memory.
 //
-// One workgroup of 1024 threads per CU, P particles per thread (slots
-// j = block * 1024 P + thread * P + p; a block's slots form one "tile").
+// One workgroup of 512 threads per CU, P particles per thread (slots
+// j = block * 512 P + thread * P + p; a block's slots form one "tile").
+// 512 threads leave each wave 256 registers, so the particle state, the
+// resampling variables and the FP64 normaliser calls fit without spilling
+// (spilled registers would be written back and refetched through HBM at
+// every grid barrier).
 // Per factor s:
 //   1. every particle advances to factor s and adds its log-factor (FP32);
 //   2. block partial {max lw, sum e, sum e^2}, e = exp(lw - max) -> memory;
@@ -37,7 +41,7 @@
 
 namespace ppl {
 
-constexpr int kSmcThreads = 1024;
+constexpr int kSmcThreads = 512;
 constexpr int kSmcWaves = kSmcThreads / 64;
 constexpr int kSmcMaxBlocks = 1024;
 constexpr int kBarGroup = 16;                 // blocks per barrier group
@@ -126,10 +130,16 @@ struct Lgssm {
         }
         st[0] = x;
     }
-    // Noise of slot j at factor s is normal (s mod 4) of block (j, 0, s div 4).
-    __device__ static float step(const SmcDev &a, int64_t s, uint32_t j, float st[NF], float zc[4], float ys) {
-        if ((s & 3) == 0) normals4(philox(j, 0, (uint32_t)(s >> 2), (a.inst << 8) | kTagPrior, a.key), zc);
-        const float x = fmaf(a.hyp[0], st[0], a.hyp[1] * zc[s & 3]);
+    // Noise of slot j at factor s is normal (s mod 4) of block (j, 0, s div 4):
+    // the first or second Box-Muller pair of the block, recomputed at every
+    // factor (keeping the block's four normals across factors costs four
+    // registers per particle, and the kernel would spill).
+    __device__ static float step(const SmcDev &a, int64_t s, uint32_t j, float st[NF], float ys) {
+        const uint4 w = philox(j, 0, (uint32_t)(s >> 2), (a.inst << 8) | kTagPrior, a.key);
+        float z0, z1;
+        if (s & 2) box_muller(unit_f32(w.z), unit_f32(w.w), z0, z1);
+        else box_muller(unit_f32(w.x), unit_f32(w.y), z0, z1);
+        const float x = fmaf(a.hyp[0], st[0], a.hyp[1] * ((s & 1) ? z1 : z0));
         st[0] = x;
         const float r = (ys - x) / a.hyp[2];
         return (float)a.lconst - 0.5f * r * r;
@@ -158,7 +168,7 @@ struct Gmm {
 #pragma unroll
         for (int k = 0; k < K; ++k) st[K + k] = a.hyp[0] * z[k];
     }
-    __device__ static float step(const SmcDev &a, int64_t, uint32_t, float st[NF], float *, float ys) {
+    __device__ static float step(const SmcDev &a, int64_t, uint32_t, float st[NF], float ys) {
         const float inv = 1.0f / a.hyp[1];
         float t[K], mx = -INFINITY;
 #pragma unroll
@@ -322,7 +332,7 @@ __global__ __launch_bounds__(kSmcThreads) void smc_persistent_kernel(SmcDev a) {
     __shared__ float ybuf[kYChunk];
     __shared__ int s_rng[2];
     __shared__ int s_cnt[kSmcWaves];
-    // dynamic LDS: tile_end[nb] | tile_pre[nb] | stage[stage_cap] (u64) | s_anc[1024 P] (i32)
+    // dynamic LDS: tile_end[nb] | tile_pre[nb] | stage[stage_cap] (u64) | s_anc[kSmcThreads P] (i32)
     extern __shared__ uint64_t dyn[];
     const int nb = gridDim.x;
     uint64_t *tile_end = dyn;
@@ -336,7 +346,6 @@ __global__ __launch_bounds__(kSmcThreads) void smc_persistent_kernel(SmcDev a) {
 
     float st[P][M::NF];
     float lw[P];
-    float zc[P][4];
     bool valid[P];
 #pragma unroll
     for (int p = 0; p < P; ++p) {
@@ -367,7 +376,7 @@ __global__ __launch_bounds__(kSmcThreads) void smc_persistent_kernel(SmcDev a) {
         asm volatile("" : "+v"(jb));
 #pragma unroll
         for (int p = 0; p < P; ++p) {
-            const float f = M::step(a, s, (uint32_t)(jb + p), st[p], zc[p], ys);
+            const float f = M::step(a, s, (uint32_t)(jb + p), st[p], ys);
             if (valid[p]) lw[p] += f;
         }
         // block partial for the ESS trigger
@@ -594,7 +603,7 @@ __global__ void smc_reset_kernel(unsigned *bar) {
 
 // ------------------------------------------------------------------ host --
 static int pick_p(int64_t N) {
-    // particles per thread so that one 1024-thread block per CU covers N (up to 8)
+    // particles per thread so that one block per CU covers N (up to 8)
     const int64_t per_cu = (N + 255) / 256;
     int P = 1;
     while (P < 8 && (int64_t)kSmcThreads * P < per_cu) P <<= 1;
@@ -677,9 +686,10 @@ int run_smc(const SmcArgs &a, hipStream_t st) {
     const int NF = a.model == PPL_MODEL_LGSSM ? 1 : 2 * a.K;
     const int P = pick_p(a.N);
     const int64_t nb = smc_blocks(a.N, P);
-    if (nb > kSmcMaxBlocks)
+    // every block merges the per-block partials one per thread
+    if (nb > kSmcMaxBlocks || nb > kSmcThreads)
         return fail(PPL_E_UNSUPPORTED, "SMC supports at most %lld particles",
-                    (long long)kSmcMaxBlocks * kSmcThreads * 8);
+                    (long long)std::min(kSmcMaxBlocks, kSmcThreads) * kSmcThreads * 8);
     if (a.T > 0x7fffffffLL) return fail(PPL_E_ARG, "too many factors");
     // the global barrier counter reaches (2 T + 1) * groups
     if ((2 * a.T + 2) * ((nb + kBarGroup - 1) / kBarGroup) >= 0xffffffffLL ||
