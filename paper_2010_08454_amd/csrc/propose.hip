@@ -99,8 +99,29 @@ __global__ __launch_bounds__(kPropThreads) void poly_mix_is_kernel(
 #pragma unroll
     for (int m = 0; m < 8; ++m) ts += exp(t[m] - tm);
     const double lq = lnl[n - 2] + tm + log(ts);
+    // Points in chunks of eight (one batch of scalar loads per chunk); the
+    // sum order is unchanged.
     double acc = 0.0;
-    for (int d = 0; d < D; ++d) {
+    int d = 0;
+    for (; d + 8 <= D; d += 8) {
+        double xs[8], ys[8];
+#pragma unroll
+        for (int k = 0; k < 8; ++k) {
+            xs[k] = X[d + k];
+            ys[k] = Y[d + k];
+        }
+#pragma unroll
+        for (int k = 0; k < 8; ++k) {
+            double v = c[4];
+            v = fma(v, xs[k], c[3]);
+            v = fma(v, xs[k], c[2]);
+            v = fma(v, xs[k], c[1]);
+            v = fma(v, xs[k], c[0]);
+            const double r = ys[k] - v;
+            acc = fma(r, r, acc);
+        }
+    }
+    for (; d < D; ++d) {
         const double xv = X[d], yv = Y[d];
         double v = c[4];
         v = fma(v, xv, c[3]);
@@ -143,26 +164,38 @@ __global__ __launch_bounds__(kPropThreads) void poly_mix_is_kernel(
 
 // --------------------------------------------------------------- GMM --
 // log sum_k pi_k Normal(y; mu_k, sd) with the max shift, summed over the data.
+__device__ __forceinline__ double gmm_point(double y, int K, const double (&lpi)[8], const double (&mu)[8],
+                                            double inv_sd, double cst) {
+    double t[8], mx = -INFINITY;
+#pragma unroll
+    for (int k = 0; k < 8; ++k) {
+        if (k < K) {
+            const double r = (y - mu[k]) * inv_sd;
+            t[k] = lpi[k] + cst - 0.5 * r * r;
+            mx = fmax(mx, t[k]);
+        }
+    }
+    double s = 0.0;
+#pragma unroll
+    for (int k = 0; k < 8; ++k)
+        if (k < K) s += exp(t[k] - mx);
+    return mx + log(s);
+}
+
+// Points in chunks of sixteen (one batch of scalar loads per chunk); the sum
+// order is unchanged.
 __device__ __forceinline__ double gmm_loglik(const float *__restrict__ Y, int D, int K, const double (&lpi)[8],
                                              const double (&mu)[8], double inv_sd, double cst) {
     double ll = 0.0;
-    for (int d = 0; d < D; ++d) {
-        const double y = (double)Y[d];
-        double t[8], mx = -INFINITY;
+    int d = 0;
+    for (; d + 16 <= D; d += 16) {
+        float ys[16];
 #pragma unroll
-        for (int k = 0; k < 8; ++k) {
-            if (k < K) {
-                const double r = (y - mu[k]) * inv_sd;
-                t[k] = lpi[k] + cst - 0.5 * r * r;
-                mx = fmax(mx, t[k]);
-            }
-        }
-        double s = 0.0;
-#pragma unroll
-        for (int k = 0; k < 8; ++k)
-            if (k < K) s += exp(t[k] - mx);
-        ll += mx + log(s);
+        for (int k = 0; k < 16; ++k) ys[k] = Y[d + k];
+#pragma unroll 1
+        for (int k = 0; k < 16; ++k) ll += gmm_point((double)ys[k], K, lpi, mu, inv_sd, cst);
     }
+    for (; d < D; ++d) ll += gmm_point((double)Y[d], K, lpi, mu, inv_sd, cst);
     return ll;
 }
 
