@@ -16,7 +16,8 @@ Printed as one JSON line, with
   cpu_baseline -- the CPU oracle on a bounded sample of the same workload.
 
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu]
-                       [--config blr|poly|poly-paper|lgssm|gmm-batched|proposal-poly|proposal-gmm|proposal-train]
+                       [--config blr|poly|poly-paper|lgssm|gmm-batched|resample-gather|proposal-poly|
+                                 proposal-gmm|proposal-train]
 """
 import argparse
 import json
@@ -45,14 +46,15 @@ def parse():
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--config", default="blr",
-                    choices=["blr", "poly", "poly-paper", "lgssm", "gmm-batched", "proposal-poly", "proposal-gmm",
-                             "proposal-train"])
+                    choices=["blr", "poly", "poly-paper", "lgssm", "gmm-batched", "resample-gather", "proposal-poly",
+                             "proposal-gmm", "proposal-train"])
     ap.add_argument("--pairs-log2", type=int, default=22, help="proposal-train: log2 of the simulated pairs")
     ap.add_argument("--no-graph", action="store_true", help="proposal-train: launch each step's kernels eagerly")
     ap.add_argument("--batch", type=int, default=0, help="proposal: training batch (default 4096)")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--cpu-seconds", type=float, default=15.0, help="target length of the oracle sample")
-    ap.add_argument("--particles", type=int, default=0, help="lgssm: particle count (default 2^20)")
+    ap.add_argument("--particles", type=int, default=0,
+                    help="lgssm: particle count (default 2^20); resample-gather: (default 2^24)")
     ap.add_argument("--ess-frac", type=float, default=0.5, help="lgssm: resampling threshold")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain 256 MiB device copy (reference for HBM byte counters)")
@@ -141,6 +143,95 @@ def cpu_baseline_poly(x, y, n, seed):
     dt = time.perf_counter() - t0
     return {"value": n * y.size / dt, "unit": "particle-likelihood evals/s", "cores": oracle.num_threads(),
             "kind": "oracle", "sample": f"{n} particles over all {y.size} points ({dt:.1f} s)"}
+
+
+HBM_GBS = 8000.0
+GATHER_FIELDS = 16
+RESAMPLE_SOURCES = ("paper_2010_08454_amd/csrc/resample.hip", "paper_2010_08454_amd/csrc/device.h")
+
+
+def bench_resample_gather(args, ppl, synthetic, torch, dev, stream):
+    """Systematic resampling fused with the gather of the particle state, at the
+    state size of the batched mixture workload: N = 2^24 particles x 16 FP32
+    fields (1.07 GB, the bytes of 256 instances x 2^16 particles x 2K = 16
+    fields), FP32 log-weights ~ N(0, 1).  One step = one ppl_resample_gather
+    call (quantisation, tile scans, tile prefix, fused ancestor search and
+    gather).  Roofline: ancestor_gather_kernel against HBM, algorithmic bytes
+    per particle 2 x 16 x 4 (state read + write) + 8 (its prefix-sum entry)."""
+    N, F, seed = args.particles or (1 << 24), GATHER_FIELDS, 1
+    lw_h = synthetic.logweights(N, "normal", seed=3, scale=1.0)
+    lw = torch.from_numpy(lw_h).to(dev)
+    gen = torch.Generator(device=dev)
+    gen.manual_seed(7)
+    state = torch.randn((F, N), generator=gen, device=dev, dtype=torch.float32)
+    out = torch.empty_like(state)
+    ws = ppl.workspace(ppl.ppl_workspace_size(0, None, N, ppl.PPL_ALGO_RESAMPLE), dev)
+
+    def step(k):
+        ppl.ppl_resample_gather(lw, state, seed, step=k, out=out, ws=ws, stream=stream)
+
+    for k in range(args.warmup):
+        step(k)
+    torch.cuda.synchronize()
+    ppl.ppl_timing_enable(True)
+    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    ev0.record(stream)
+    for k in range(args.steps):
+        step(args.warmup + k)
+    ev1.record(stream)
+    torch.cuda.synchronize()
+    total_ms = ev0.elapsed_time(ev1)
+    k_ms, k_n = ppl.ppl_timing_query("ancestor_gather_kernel")
+    ppl.ppl_timing_enable(False)
+    ms = total_ms / args.steps
+    k_avg = k_ms / max(k_n, 1)
+    bytes_per_launch = N * (2 * F * 4 + 8)
+    achieved = bytes_per_launch / (k_avg / 1e3) / 1e9
+    # whole call: log-weights read twice (tile maxima, quantised scan), prefix sums written once
+    call_bytes = N * (4 + 4 + 8) + bytes_per_launch
+    workload = {"workload": "resample-gather", "particles": N, "state_fields": F, "state_dtype": "f32",
+                "state_bytes": F * N * 4, "log_weights": "fp32 ~ N(0, 1)",
+                "call_gb_per_s": round(call_bytes / (ms / 1e3) / 1e9, 1)}
+    roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_GBS, "unit": "GB/s",
+                "frac": round(achieved / HBM_GBS, 4),
+                "traffic": measured_traffic("ancestor_gather_kernel", RESAMPLE_SOURCES),
+                "kernel": "ancestor_gather_kernel", "kernel_ms": round(k_avg, 4), "kernel_launches": k_n,
+                "bytes_per_launch": bytes_per_launch}
+    res = {"metric": "resampled particles/s", "value": N / (ms / 1e3), "unit": "particles/s", "n_gpus": 1,
+           "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(ms, 4), "higher_is_better": True,
+           "scaling": "weak", "vs_baseline": None, "dtype": "f32",
+           "data": "synthetic (seeded generators, inputs resident in HBM)", "config": workload,
+           "roofline": roofline}
+    if not args.no_cpu:
+        res["cpu_baseline"] = cpu_baseline_resample(lw_h, state.cpu().numpy(), seed)
+    print(json.dumps(res), flush=True)
+
+
+def cpu_baseline_resample(lw, state, seed, target_s=10.0):
+    """The oracle's resampling plus the gather by index on a particle sample
+    sized for about `target_s` seconds."""
+    import numpy as np
+    import oracle
+    oracle.build()
+    n = min(lw.size, 1 << 18)
+    t0 = time.perf_counter()
+    a, _ = oracle.resample(lw[:n].astype(np.float64), seed)
+    np.ascontiguousarray(state[:, :n][:, a])
+    dt = time.perf_counter() - t0
+    n = int(min(lw.size, max(n, 2 ** round(math.log2(n * target_s / max(dt, 1e-6))))))
+    lw64 = lw[:n].astype(np.float64)
+    sub = np.ascontiguousarray(state[:, :n])
+    reps, dt = 0, 0.0
+    while reps == 0 or (dt < target_s * 0.6 and reps < 20):
+        t0 = time.perf_counter()
+        a, _ = oracle.resample(lw64, seed)
+        np.ascontiguousarray(sub[:, a])
+        dt += time.perf_counter() - t0
+        reps += 1
+    what = "the full workload" if n == lw.size else f"{n} of the {lw.size} particles"
+    return {"value": reps * n / dt, "unit": "particles/s", "cores": 1, "kind": "oracle",
+            "sample": f"{what} ({state.shape[0]} fields), {reps} run(s): oracle resampling + gather by index "
+                      f"({dt:.1f} s)"}
 
 
 BF16_MFMA_TFLOPS = 2500.0
@@ -376,6 +467,9 @@ def main():
         return
     if args.config.startswith("proposal"):
         bench_proposal(args, ppl, synthetic, torch, dev, stream)
+        return
+    if args.config == "resample-gather":
+        bench_resample_gather(args, ppl, synthetic, torch, dev, stream)
         return
 
     if args.config == "blr":

@@ -199,6 +199,21 @@ int ppl_lse_ess(const void *d_lw, int dtype, int64_t n, double *d_out, void *d_w
 int ppl_resample(const void *d_lw, int dtype, int64_t n, uint64_t seed, uint32_t step,
                  uint32_t inst, int32_t *d_anc, void *d_ws, size_t ws_bytes, void *stream);
 
+/* Systematic resampling followed by the gather of the particle state, the
+ * resampling step between factors of particle-based inference (paper Sec. 6,
+ * future work).  Ancestors follow ppl_resample's rule with the same Philox
+ * block, so d_anc (optional, may be NULL) equals ppl_resample's output; then
+ *   d_state_out[f * n + j] = d_state_in[f * n + d_anc[j]],  f < n_fields, j < n
+ * for structure-of-arrays state of 32-bit words (FP32 or int32 fields), laid
+ * out [n_fields][n].  Both state buffers are caller-owned device memory of
+ * n_fields * n * 4 bytes and must not overlap (PPL_E_ARG).  Workspace: the
+ * PPL_ALGO_RESAMPLE size.  If every weight is zero, every d_anc[j] = -1 and
+ * every output word is a quiet NaN (0x7fc00000). */
+int ppl_resample_gather(const void *d_lw, int dtype, int64_t n, uint64_t seed, uint32_t step,
+                        uint32_t inst, int32_t n_fields, const void *d_state_in,
+                        void *d_state_out, int32_t *d_anc, void *d_ws, size_t ws_bytes,
+                        void *stream);
+
 /* Raw stream: d_out[4 i + r] = word r of Philox4x32-10 block
  * (i, c1, c2, c3) under key seed, for i < n. */
 int ppl_philox(uint64_t seed, uint32_t c1, uint32_t c2, uint32_t c3, int64_t n,

@@ -27,7 +27,7 @@ PPL_ALGO_IS, PPL_ALGO_SMC, PPL_ALGO_LSE, PPL_ALGO_RESAMPLE = 0, 1, 2, 3
 
 # Exported C symbols (kept in step with include/ppl.h).
 EXPORTS = ("ppl_status_string", "ppl_last_error", "ppl_version", "ppl_workspace_size",
-           "ppl_importance", "ppl_lse_ess", "ppl_resample", "ppl_philox", "ppl_smc",
+           "ppl_importance", "ppl_lse_ess", "ppl_resample", "ppl_resample_gather", "ppl_philox", "ppl_smc",
            "ppl_timing_enable", "ppl_timing_query")
 
 P = ctypes.c_void_p
@@ -70,6 +70,7 @@ def _load():
                                  P, ctypes.c_size_t, P, ctypes.POINTER(PplResult)]
     L.ppl_lse_ess.argtypes = [P, ctypes.c_int, i64, P, P, ctypes.c_size_t, P]
     L.ppl_resample.argtypes = [P, ctypes.c_int, i64, u64, u32, u32, P, P, ctypes.c_size_t, P]
+    L.ppl_resample_gather.argtypes = [P, ctypes.c_int, i64, u64, u32, u32, i32, P, P, P, P, ctypes.c_size_t, P]
     L.ppl_philox.argtypes = [u64, u32, u32, u32, i64, P, P]
     L.ppl_smc.argtypes = [ctypes.c_int, ctypes.POINTER(PplData), i64, u64, f64, P, ctypes.c_size_t, P,
                           ctypes.POINTER(PplResult)]
@@ -177,6 +178,22 @@ def ppl_resample(lw, seed, step=0, inst=0, anc=None, ws=None, stream=None):
     _check(lib.ppl_resample(_ptr(lw), dt, n, int(seed) & (2 ** 64 - 1), step, inst, _ptr(anc), _ptr(ws),
                             ws.numel(), _stream(stream)))
     return anc
+
+
+def ppl_resample_gather(lw, state, seed, step=0, inst=0, out=None, anc=None, ws=None, stream=None):
+    """Resampling fused with the gather of structure-of-arrays state [F][n] of
+    32-bit words; returns the gathered state (and fills anc when given)."""
+    n = lw.numel()
+    if state.dim() != 2 or state.shape[1] != n or state.element_size() != 4 or not state.is_contiguous():
+        raise ValueError("state must be a contiguous [F, n] tensor of 32-bit words")
+    if out is None:
+        out = torch.empty_like(state)
+    if ws is None:
+        ws = workspace(ppl_workspace_size(0, None, n, PPL_ALGO_RESAMPLE), lw.device)
+    dt = PPL_F64 if lw.dtype == torch.float64 else PPL_F32
+    _check(lib.ppl_resample_gather(_ptr(lw), dt, n, int(seed) & (2 ** 64 - 1), step, inst, state.shape[0],
+                                   _ptr(state), _ptr(out), _ptr(anc), _ptr(ws), ws.numel(), _stream(stream)))
+    return out
 
 
 def ppl_philox(seed, c1, c2, c3, n, out=None, stream=None):

@@ -267,6 +267,24 @@ int ppl_resample(const void *lw, int dtype, int64_t n, uint64_t seed, uint32_t s
     return run_resample(lw, dtype == PPL_F64, n, seed, step, inst, anc, ws, (hipStream_t)stream);
 }
 
+int ppl_resample_gather(const void *lw, int dtype, int64_t n, uint64_t seed, uint32_t step, uint32_t inst,
+                        int32_t n_fields, const void *state_in, void *state_out, int32_t *anc, void *ws,
+                        size_t ws_bytes, void *stream) {
+    clear_error();
+    if (!lw || !state_in || !state_out) return fail(PPL_E_ARG, "d_lw, d_state_in and d_state_out must be non-NULL");
+    if (dtype != PPL_F32 && dtype != PPL_F64) return fail(PPL_E_ARG, "dtype must be PPL_F32 or PPL_F64");
+    if (int rc = check_n(n)) return rc;
+    if (n_fields < 1 || n_fields > 4096) return fail(PPL_E_ARG, "n_fields %d out of range [1, 4096]", n_fields);
+    if (inst >= (1u << 24)) return fail(PPL_E_ARG, "instance id must be < 2^24");
+    const uintptr_t bytes = (uintptr_t)n_fields * (uintptr_t)n * 4u;
+    const uintptr_t i0 = (uintptr_t)state_in, o0 = (uintptr_t)state_out;
+    if (i0 < o0 + bytes && o0 < i0 + bytes) return fail(PPL_E_ARG, "d_state_in and d_state_out overlap");
+    if (int rc = check_ws(ws, ws_bytes, resample_ws_bytes(n))) return rc;
+    if (int rc = check_device()) return rc;
+    return run_resample_gather(lw, dtype == PPL_F64, n, seed, step, inst, n_fields, state_in, state_out, anc, ws,
+                               (hipStream_t)stream);
+}
+
 int ppl_philox(uint64_t seed, uint32_t c1, uint32_t c2, uint32_t c3, int64_t n, uint32_t *out, void *stream) {
     clear_error();
     if (!out) return fail(PPL_E_ARG, "d_out is NULL");

@@ -11,6 +11,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include "ppl.h"
+
 namespace ppl {
 
 // Philox S-box multipliers and Weyl key increments (SC'11).
@@ -111,65 +113,12 @@ __device__ __forceinline__ int wave_or(int v) {
 // ------------------------------------------- weighted-sum partial records --
 // A partial over a set of particles: {m = max lw, s1 = sum e, s2 = sum e^2,
 // nan = number of NaN log-weights, f[k] = sum e * f_k}, with e = exp(lw - m).
-// Two partials merge by rescaling to the larger maximum.
+// Partials merge by rescaling their sums to the largest maximum.
 template <int NF>
 struct Partial {
     double m, s1, s2, nan;
     double f[NF];
 };
-
-template <int NF>
-__device__ __forceinline__ void partial_merge(Partial<NF> &a, const Partial<NF> &b) {
-    a.nan += b.nan;
-    if (!(b.m > -INFINITY)) return;
-    if (!(a.m > -INFINITY)) {
-        a.m = b.m;
-        a.s1 = b.s1;
-        a.s2 = b.s2;
-#pragma unroll
-        for (int k = 0; k < NF; ++k) a.f[k] = b.f[k];
-        return;
-    }
-    const double M = fmax(a.m, b.m);
-    const double ca = exp(a.m - M), cb = exp(b.m - M);
-    a.s1 = a.s1 * ca + b.s1 * cb;
-    a.s2 = a.s2 * (ca * ca) + b.s2 * (cb * cb);
-#pragma unroll
-    for (int k = 0; k < NF; ++k) a.f[k] = a.f[k] * ca + b.f[k] * cb;
-    a.m = M;
-}
-
-template <int NF>
-__device__ __forceinline__ Partial<NF> partial_shfl_xor(const Partial<NF> &p, int o) {
-    Partial<NF> q;
-    q.m = __shfl_xor(p.m, o, 64);
-    q.s1 = __shfl_xor(p.s1, o, 64);
-    q.s2 = __shfl_xor(p.s2, o, 64);
-    q.nan = __shfl_xor(p.nan, o, 64);
-#pragma unroll
-    for (int k = 0; k < NF; ++k) q.f[k] = __shfl_xor(p.f[k], o, 64);
-    return q;
-}
-
-// Reduce a partial across the 64 lanes of a wave (fixed butterfly order).
-template <int NF>
-__device__ __forceinline__ void partial_wave_reduce(Partial<NF> &p) {
-#pragma unroll
-    for (int o = 32; o > 0; o >>= 1) {
-        Partial<NF> q = partial_shfl_xor(p, o);
-        partial_merge(p, q);
-    }
-}
-
-template <int NF>
-__device__ __forceinline__ void partial_store(double *dst, const Partial<NF> &p) {
-    dst[0] = p.m;
-    dst[1] = p.s1;
-    dst[2] = p.s2;
-    dst[3] = p.nan;
-#pragma unroll
-    for (int k = 0; k < NF; ++k) dst[4 + k] = p.f[k];
-}
 
 template <int NF>
 __device__ __forceinline__ Partial<NF> partial_load(const double *src) {
@@ -195,45 +144,138 @@ __device__ __forceinline__ Partial<NF> partial_empty() {
     return p;
 }
 
-// Block-level reduction of per-thread partials (blockDim = 64 * nwaves) into
-// one record written to dst by thread 0.  LDS scratch: nwaves records.
-template <int NF, int NWAVES>
-__device__ __forceinline__ void partial_block_reduce_store(Partial<NF> &p, double *dst) {
-    __shared__ double lds[NWAVES][4 + NF];
-    partial_wave_reduce(p);
-    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-    if (lane == 0) partial_store(lds[wv], p);
-    __syncthreads();
-    if (threadIdx.x == 0) {
-        Partial<NF> a = partial_load<NF>(lds[0]);
+// Reduce-scatter of F doubles across the 64 lanes of a wave by recursive
+// halving.  At each level a lane and its partner (lane ^ O) hold the same N
+// slots; the lane with bit O clear keeps the first ceil(N/2) slots, the other
+// the last ceil(N/2) (for odd N both keep the middle one), and each adds the
+// partner's copy of what it keeps.  Every add is a + b on one side and b + a on
+// the other, so a slot held by several lanes holds bitwise the same total.
+// A level costs ceil(N/2) shuffles instead of N, about 2F shuffles in all
+// instead of 6F for a butterfly.  On return slot j of the lane holds the
+// wave total of field lo + j (j < the final slot count).
+template <int F, int N, int O>
+struct WaveReduceScatter {
+    static constexpr int kFinal = WaveReduceScatter<F, N - N / 2, O / 2>::kFinal;
+    __device__ __forceinline__ static void run(double (&v)[F], int lane, int &lo) {
+        constexpr int H = N / 2, C = N - H;
+        const bool up = (lane & O) != 0;
 #pragma unroll
-        for (int w = 1; w < NWAVES; ++w) {
-            Partial<NF> b = partial_load<NF>(lds[w]);
-            partial_merge(a, b);
+        for (int j = 0; j < C; ++j) {
+            const double keep = up ? v[H + j] : v[j];
+            const double send = up ? v[j] : v[H + j];
+            v[j] = keep + __shfl_xor(send, O, 64);
         }
-        partial_store(dst, a);
+        if (up) lo += H;
+        WaveReduceScatter<F, C, O / 2>::run(v, lane, lo);
+    }
+};
+template <int F, int N>
+struct WaveReduceScatter<F, N, 0> {
+    static constexpr int kFinal = N;
+    __device__ __forceinline__ static void run(double (&)[F], int, int &) {}
+};
+
+// Block-wide maximum of one double per thread; every thread receives it.
+template <int NWAVES>
+__device__ __forceinline__ double block_max_f64(double v) {
+    __shared__ double lds_m[NWAVES];
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v = fmax(v, __shfl_xor(v, o, 64));
+    if ((threadIdx.x & 63) == 0) lds_m[threadIdx.x >> 6] = v;
+    __syncthreads();
+    double m = lds_m[0];
+#pragma unroll
+    for (int w = 1; w < NWAVES; ++w) m = fmax(m, lds_m[w]);
+    return m;
+}
+
+// Sum of F doubles per thread across the block (blockDim = 64 * NWAVES):
+// a reduce-scatter within each wave, then a fixed-order sum over the waves;
+// dst[t] receives the total of field t.  Called at most once per kernel.
+template <int F, int NWAVES>
+__device__ __forceinline__ void block_sum_store(double (&v)[F], double *dst) {
+    __shared__ double lds[NWAVES][F];
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    int lo = 0;
+    WaveReduceScatter<F, F, 32>::run(v, lane, lo);
+#pragma unroll
+    for (int j = 0; j < WaveReduceScatter<F, F, 32>::kFinal; ++j)
+        if (lo + j < F) lds[wv][lo + j] = v[j];
+    __syncthreads();
+    for (int t = threadIdx.x; t < F; t += 64 * NWAVES) {
+        double s = lds[0][t];
+#pragma unroll
+        for (int w = 1; w < NWAVES; ++w) s += lds[w][t];
+        dst[t] = s;
     }
 }
 
+// Block-level reduction of per-thread partials (blockDim = 64 * nwaves) into
+// one record at dst.  The block maximum M comes first; each thread rescales
+// its sums to M (one exp), and the sums then reduce with plain adds: a
+// reduce-scatter within each wave and a fixed-order sum over the waves.  The
+// result does not depend on timing.
+template <int NF, int NWAVES>
+__device__ __forceinline__ void partial_block_reduce_store(Partial<NF> &p, double *dst) {
+    constexpr int F = 3 + NF;  // s1, s2, nan, f[NF]
+    const double M = block_max_f64<NWAVES>(p.m);
+    const double c = (p.m > -INFINITY) ? exp(p.m - M) : 0.0;
+    double v[F];
+    v[0] = p.s1 * c;
+    v[1] = p.s2 * (c * c);
+    v[2] = p.nan;
+#pragma unroll
+    for (int k = 0; k < NF; ++k) v[3 + k] = p.f[k] * c;
+    block_sum_store<F, NWAVES>(v, dst + 1);
+    if (threadIdx.x == 0) dst[0] = M;
+}
+
+// Block-level merge of the records in[r], r in [lo, hi), each {m, s1, s2, nan,
+// f[NF]}, into one record at dst.  A first pass takes the maximum M of the
+// record maxima; a second scales each record to M (one exp per record) and
+// sums with plain adds.  Called at most once per kernel.
+template <int NF, int NWAVES>
+__device__ __forceinline__ void records_block_reduce_store(const double *__restrict__ in, int64_t lo, int64_t hi,
+                                                           double *dst) {
+    constexpr int F = 3 + NF;
+    constexpr int R = 4 + NF;
+    double m = -INFINITY;
+    for (int64_t r = lo + threadIdx.x; r < hi; r += 64 * NWAVES) m = fmax(m, in[(size_t)r * R]);
+    const double M = block_max_f64<NWAVES>(m);
+    double v[F];
+#pragma unroll
+    for (int k = 0; k < F; ++k) v[k] = 0.0;
+    for (int64_t r = lo + threadIdx.x; r < hi; r += 64 * NWAVES) {
+        const double *rec = in + (size_t)r * R;
+        const double mr = rec[0];
+        v[2] += rec[3];
+        if (mr > -INFINITY) {
+            const double c = exp(mr - M);
+            v[0] += rec[1] * c;
+            v[1] += rec[2] * (c * c);
+#pragma unroll
+            for (int k = 0; k < NF; ++k) v[3 + k] += rec[4 + k] * c;
+        }
+    }
+    block_sum_store<F, NWAVES>(v, dst + 1);
+    if (threadIdx.x == 0) dst[0] = M;
+}
+
 // ------------------------------------------------ two-level partial merge --
-// Up to kMergeDirect block partials are merged by one wave; beyond that a first
-// pass of at most kMergeGroups workgroups merges fixed contiguous ranges (a
-// fixed order, so the result does not depend on timing) and the wave merges
-// those records.
+// Up to kMergeDirect block partials are merged by the one workgroup of the
+// finalize kernel; beyond that a first pass of at most kMergeGroups workgroups
+// merges fixed contiguous ranges (a fixed order, so the result does not depend
+// on timing) and the finalize workgroup merges those records.
 constexpr int kMergeGroups = 512;
-constexpr int64_t kMergeDirect = 8192;
+constexpr int64_t kMergeDirect = 2048;
+constexpr int kFinalizeThreads = 256;
 
 template <int NF>
 __global__ __launch_bounds__(256) void partial_merge_kernel(const double *__restrict__ in, int64_t n, int64_t per,
                                                             double *__restrict__ out) {
-    Partial<NF> a = partial_empty<NF>();
     const int64_t lo = (int64_t)blockIdx.x * per;
     const int64_t hi = lo + per < n ? lo + per : n;
-    for (int64_t r = lo + threadIdx.x; r < hi; r += 256) {
-        Partial<NF> q = partial_load<NF>(in + (size_t)r * (4 + NF));
-        partial_merge(a, q);
-    }
-    partial_block_reduce_store<NF, 4>(a, out + (size_t)blockIdx.x * (4 + NF));
+    records_block_reduce_store<NF, 4>(in, lo, hi, out + (size_t)blockIdx.x * (4 + NF));
 }
 
 // Bytes of second-level records a merge of NF-field partials may need.
@@ -253,6 +295,49 @@ inline const double *merge_partials_first(const double *part, int64_t nblocks, d
     hipLaunchKernelGGL(partial_merge_kernel<NF>, dim3(groups), dim3(256), 0, st, part, nblocks, per, scratch);
     *nrec = groups;
     return scratch;
+}
+
+
+// ------------------------------------------------ importance finalize --
+// One workgroup merges the block partials and writes scalars[8] = {log Z-hat,
+// ESS, 0, status, M, s1, s2, N} and the model summaries: for the polynomial
+// model P(n | y) for n = 2..5, coefficient means per degree and overall
+// (29 fields); for the others the weighted mean of each field.
+template <int NF>
+__global__ __launch_bounds__(kFinalizeThreads) void weights_finalize_kernel(const double *__restrict__ part,
+                                                                          int nrec, int64_t N, int model,
+                                                                          double *__restrict__ scalars,
+                                                                          double *__restrict__ summaries) {
+    __shared__ double rec[4 + NF];
+    records_block_reduce_store<NF, kFinalizeThreads / 64>(part, 0, nrec, rec);
+    __syncthreads();
+    if (threadIdx.x != 0) return;
+    const Partial<NF> a = partial_load<NF>(rec);
+    int status = 0;
+    if (a.nan > 0) status = PPL_E_NONFINITE;
+    else if (!(a.m > -INFINITY)) status = PPL_E_ZERO_WEIGHT;
+    scalars[0] = status ? (a.nan > 0 ? NAN : -INFINITY) : a.m + log(a.s1) - log((double)N);
+    scalars[1] = status ? 0.0 : a.s1 * a.s1 / a.s2;
+    scalars[2] = 0.0;
+    scalars[3] = (double)status;
+    scalars[4] = a.m;
+    scalars[5] = a.s1;
+    scalars[6] = a.s2;
+    scalars[7] = (double)N;
+    if (!summaries) return;
+    if constexpr (NF == 29) {
+        if (model == PPL_MODEL_POLY) {
+            for (int s = 0; s < 4; ++s) {
+                const double mass = a.f[s];
+                summaries[s] = status ? 0.0 : mass / a.s1;
+                for (int j = 0; j < 5; ++j)
+                    summaries[4 + 5 * s + j] = (!status && mass > 0) ? a.f[4 + 5 * s + j] / mass : 0.0;
+            }
+            for (int j = 0; j < 5; ++j) summaries[24 + j] = status ? 0.0 : a.f[24 + j] / a.s1;
+            return;
+        }
+    }
+    for (int k = 0; k < NF; ++k) summaries[k] = status ? 0.0 : a.f[k] / a.s1;
 }
 
 }  // namespace ppl

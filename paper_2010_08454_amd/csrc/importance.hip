@@ -250,46 +250,6 @@ __global__ __launch_bounds__(kIsThreads) void poly_is_kernel(
     partial_block_reduce_store<kPolyNF, kIsWaves>(pp, part + (size_t)blockIdx.x * (4 + kPolyNF));
 }
 
-// ------------------------------------------------------------- finalize --
-// One wave merges the block partials (lane-strided, then a butterfly) and
-// writes scalars[8] and the model summaries.
-template <int NF, int MODEL>
-__global__ __launch_bounds__(64) void is_finalize_kernel(const double *__restrict__ part, int nblocks,
-                                                         int64_t N, double *__restrict__ scalars,
-                                                         double *__restrict__ summaries) {
-    const int lane = threadIdx.x;
-    Partial<NF> a = partial_empty<NF>();
-    for (int b = lane; b < nblocks; b += 64) {
-        Partial<NF> q = partial_load<NF>(part + (size_t)b * (4 + NF));
-        partial_merge(a, q);
-    }
-    partial_wave_reduce(a);
-    if (lane != 0) return;
-    int status = 0;
-    if (a.nan > 0) status = PPL_E_NONFINITE;
-    else if (!(a.m > -INFINITY)) status = PPL_E_ZERO_WEIGHT;
-    const double logz = status ? (a.nan > 0 ? NAN : -INFINITY) : a.m + log(a.s1) - log((double)N);
-    scalars[0] = logz;
-    scalars[1] = status ? 0.0 : a.s1 * a.s1 / a.s2;
-    scalars[2] = 0.0;
-    scalars[3] = (double)status;
-    scalars[4] = a.m;
-    scalars[5] = a.s1;
-    scalars[6] = a.s2;
-    scalars[7] = (double)N;
-    if (!summaries) return;
-    if (MODEL == PPL_MODEL_POLY) {
-        for (int s = 0; s < 4; ++s) {
-            const double mass = a.f[s];
-            summaries[s] = status ? 0.0 : mass / a.s1;
-            for (int j = 0; j < 5; ++j) summaries[4 + 5 * s + j] = (!status && mass > 0) ? a.f[4 + 5 * s + j] / mass : 0.0;
-        }
-        for (int j = 0; j < 5; ++j) summaries[24 + j] = status ? 0.0 : a.f[24 + j] / a.s1;
-    } else {
-        for (int k = 0; k < NF; ++k) summaries[k] = status ? 0.0 : a.f[k] / a.s1;
-    }
-}
-
 // ---------------------------------------------------------------- host --
 size_t is_partial_bytes(int model, int dim, int64_t N) {
     const int P = model == PPL_MODEL_POLY ? 1 : 4;
@@ -316,32 +276,35 @@ static int launch_blr(const IsArgs &a, double *part, int64_t blocks, hipStream_t
     int nrec = 0;
     const double *rec = merge_partials_first<DIM>(part, blocks, part + (size_t)blocks * (4 + DIM), &nrec, st);
     PPL_LAUNCH_CHECK("partial_merge_kernel");
-    hipLaunchKernelGGL((is_finalize_kernel<DIM, PPL_MODEL_BLR>), dim3(1), dim3(64), 0, st, rec, nrec, a.N, a.scalars,
-                       a.summaries);
-    PPL_LAUNCH_CHECK("is_finalize_kernel");
+    hipLaunchKernelGGL(weights_finalize_kernel<DIM>, dim3(1), dim3(kFinalizeThreads), 0, st, rec, nrec, a.N,
+                       (int)PPL_MODEL_BLR, a.scalars, a.summaries);
+    PPL_LAUNCH_CHECK("weights_finalize_kernel");
+    return PPL_OK;
+}
+
+static int launch_poly(const IsArgs &a, hipStream_t st) {
+    constexpr int P = 1;
+    const int64_t blocks = (a.N + kIsThreads * P - 1) / (kIsThreads * P);
+    if (int rc = check_grid("poly_is_kernel", blocks, kIsThreads)) return rc;
+    KernelTimer timer("poly_is_kernel", st);
+    hipLaunchKernelGGL((poly_is_kernel<P>), dim3((unsigned)blocks), dim3(kIsThreads), 0, st, (const double *)a.x,
+                       (const double *)a.y, (int)a.D, a.N, make_key(a.seed), a.hyper[0], (int)a.hyper[1],
+                       (int)a.hyper[2], (double *)a.lw_out, (double *)a.lat_out, a.part);
+    timer.stop();
+    PPL_LAUNCH_CHECK("poly_is_kernel");
+    int nrec = 0;
+    const double *rec =
+        merge_partials_first<kPolyNF>(a.part, blocks, a.part + (size_t)blocks * (4 + kPolyNF), &nrec, st);
+    PPL_LAUNCH_CHECK("partial_merge_kernel");
+    hipLaunchKernelGGL(weights_finalize_kernel<kPolyNF>, dim3(1), dim3(kFinalizeThreads), 0, st, rec, nrec, a.N,
+                       (int)PPL_MODEL_POLY, a.scalars, a.summaries);
+    PPL_LAUNCH_CHECK("weights_finalize_kernel");
     return PPL_OK;
 }
 
 int run_importance(const IsArgs &a, hipStream_t st) {
     if (a.model == PPL_MODEL_POLY) {
-        constexpr int P = 1;
-        const int64_t blocks = (a.N + kIsThreads * P - 1) / (kIsThreads * P);
-        if (int rc = check_grid("poly_is_kernel", blocks, kIsThreads)) return rc;
-        KernelTimer timer("poly_is_kernel", st);
-        hipLaunchKernelGGL((poly_is_kernel<P>), dim3((unsigned)blocks), dim3(kIsThreads), 0, st,
-                           (const double *)a.x, (const double *)a.y, (int)a.D, a.N, make_key(a.seed),
-                           a.hyper[0], (int)a.hyper[1], (int)a.hyper[2], (double *)a.lw_out,
-                           (double *)a.lat_out, a.part);
-        timer.stop();
-        PPL_LAUNCH_CHECK("poly_is_kernel");
-        int nrec = 0;
-        const double *rec =
-            merge_partials_first<kPolyNF>(a.part, blocks, a.part + (size_t)blocks * (4 + kPolyNF), &nrec, st);
-        PPL_LAUNCH_CHECK("partial_merge_kernel");
-        hipLaunchKernelGGL((is_finalize_kernel<kPolyNF, PPL_MODEL_POLY>), dim3(1), dim3(64), 0, st, rec, nrec, a.N,
-                           a.scalars, a.summaries);
-        PPL_LAUNCH_CHECK("is_finalize_kernel");
-        return PPL_OK;
+        return launch_poly(a, st);
     }
     constexpr int P = 4;
     const int64_t blocks = (a.N + kIsThreads * P - 1) / (kIsThreads * P);

@@ -36,6 +36,9 @@ int run_lse(const void *lw, bool f64, int64_t n, double *out5, void *ws, hipStre
 size_t resample_ws_bytes(int64_t n);
 int run_resample(const void *lw, bool f64, int64_t n, uint64_t seed, uint32_t step, uint32_t inst,
                  int32_t *anc, void *ws, hipStream_t st);
+// Resampling fused with the gather of nf 32-bit state fields (see ppl_resample_gather).
+int run_resample_gather(const void *lw, bool f64, int64_t n, uint64_t seed, uint32_t step, uint32_t inst, int nf,
+                        const void *state_in, void *state_out, int32_t *anc, void *ws, hipStream_t st);
 
 int run_philox(uint64_t seed, uint32_t c1, uint32_t c2, uint32_t c3, int64_t n, uint32_t *out, hipStream_t st);
 

@@ -319,43 +319,6 @@ __global__ __launch_bounds__(kPropThreads) void gmm_is_kernel(const float *__res
     partial_block_reduce_store<kGmmNF, kPropThreads / 64>(pp, part + (size_t)blockIdx.x * (4 + kGmmNF));
 }
 
-template <int NF>
-__global__ __launch_bounds__(64) void prop_finalize_kernel(const double *__restrict__ part, int nblocks, int64_t N,
-                                                           int model, double *__restrict__ scalars,
-                                                           double *__restrict__ summaries) {
-    const int lane = threadIdx.x;
-    Partial<NF> a = partial_empty<NF>();
-    for (int b = lane; b < nblocks; b += 64) {
-        Partial<NF> q = partial_load<NF>(part + (size_t)b * (4 + NF));
-        partial_merge(a, q);
-    }
-    partial_wave_reduce(a);
-    if (lane != 0) return;
-    int status = 0;
-    if (a.nan > 0) status = PPL_E_NONFINITE;
-    else if (!(a.m > -INFINITY)) status = PPL_E_ZERO_WEIGHT;
-    scalars[0] = status ? (a.nan > 0 ? NAN : -INFINITY) : a.m + log(a.s1) - log((double)N);
-    scalars[1] = status ? 0.0 : a.s1 * a.s1 / a.s2;
-    scalars[2] = 0.0;
-    scalars[3] = (double)status;
-    scalars[4] = a.m;
-    scalars[5] = a.s1;
-    scalars[6] = a.s2;
-    scalars[7] = (double)N;
-    if (!summaries) return;
-    if (model == PPL_MODEL_POLY) {
-        for (int s = 0; s < 4; ++s) {
-            const double mass = a.f[s];
-            summaries[s] = status ? 0.0 : mass / a.s1;
-            for (int j = 0; j < 5; ++j)
-                summaries[4 + 5 * s + j] = (!status && mass > 0) ? a.f[4 + 5 * s + j] / mass : 0.0;
-        }
-        for (int j = 0; j < 5; ++j) summaries[24 + j] = status ? 0.0 : a.f[24 + j] / a.s1;
-    } else {
-        for (int k = 0; k < NF; ++k) summaries[k] = status ? 0.0 : a.f[k] / a.s1;
-    }
-}
-
 // ---------------------------------------------------------------- host --
 size_t prop_partial_bytes(int model, int64_t N) {
     const int64_t blocks = (N + kPropThreads - 1) / kPropThreads;
@@ -390,16 +353,16 @@ int run_importance_q(const IsArgs &a, hipStream_t st) {
         const double *rec =
             merge_partials_first<kPolyNFp>(a.part, blocks, a.part + (size_t)blocks * (4 + kPolyNFp), &nrec, st);
         PPL_LAUNCH_CHECK("partial_merge_kernel");
-        hipLaunchKernelGGL(prop_finalize_kernel<kPolyNFp>, dim3(1), dim3(64), 0, st, rec, nrec, a.N, a.model,
+        hipLaunchKernelGGL(weights_finalize_kernel<kPolyNFp>, dim3(1), dim3(kFinalizeThreads), 0, st, rec, nrec, a.N, a.model,
                            a.scalars, a.summaries);
     } else {
         const double *rec =
             merge_partials_first<kGmmNF>(a.part, blocks, a.part + (size_t)blocks * (4 + kGmmNF), &nrec, st);
         PPL_LAUNCH_CHECK("partial_merge_kernel");
-        hipLaunchKernelGGL(prop_finalize_kernel<kGmmNF>, dim3(1), dim3(64), 0, st, rec, nrec, a.N, a.model,
+        hipLaunchKernelGGL(weights_finalize_kernel<kGmmNF>, dim3(1), dim3(kFinalizeThreads), 0, st, rec, nrec, a.N, a.model,
                            a.scalars, a.summaries);
     }
-    PPL_LAUNCH_CHECK("prop_finalize_kernel");
+    PPL_LAUNCH_CHECK("weights_finalize_kernel");
     return PPL_OK;
 }
 

@@ -9,12 +9,13 @@
 #include "device.h"
 #include "host.h"
 #include "kernels.h"
+#include "timing.h"
 
 namespace ppl {
 
 constexpr int kRedThreads = 256;
 constexpr int kRedBlocksMax = 1024;
-constexpr int kScanItems = 4;                          // items per thread in the scan
+constexpr int kScanItems = 8;                          // items per thread in the scan
 constexpr int kScanTile = kRedThreads * kScanItems;    // items per block
 
 // -------------------------------------------------------- normaliser ----
@@ -43,15 +44,13 @@ __global__ __launch_bounds__(kRedThreads) void lse_partial_kernel(const T *__res
     partial_block_reduce_store<0, kRedThreads / 64>(p, part + (size_t)blockIdx.x * 4);
 }
 
-__global__ __launch_bounds__(64) void lse_finalize_kernel(const double *__restrict__ part, int nb,
-                                                          double *__restrict__ out) {
-    Partial<0> a = partial_empty<0>();
-    for (int b = threadIdx.x; b < nb; b += 64) {
-        Partial<0> q = partial_load<0>(part + (size_t)b * 4);
-        partial_merge(a, q);
-    }
-    partial_wave_reduce(a);
+__global__ __launch_bounds__(kRedThreads) void lse_finalize_kernel(const double *__restrict__ part, int nb,
+                                                                   double *__restrict__ out) {
+    __shared__ double rec[4];
+    records_block_reduce_store<0, kRedThreads / 64>(part, 0, nb, rec);
+    __syncthreads();
     if (threadIdx.x) return;
+    const Partial<0> a = partial_load<0>(rec);
     if (a.nan > 0) {
         for (int k = 0; k < 5; ++k) out[k] = NAN;
     } else if (!(a.m > -INFINITY)) {
@@ -78,7 +77,7 @@ int run_lse(const void *lw, bool f64, int64_t n, double *out5, void *ws, hipStre
         hipLaunchKernelGGL(lse_partial_kernel<float>, dim3((unsigned)nb), dim3(kRedThreads), 0, st,
                            (const float *)lw, n, part);
     PPL_LAUNCH_CHECK("lse_partial_kernel");
-    hipLaunchKernelGGL(lse_finalize_kernel, dim3(1), dim3(64), 0, st, part, (int)nb, out5);
+    hipLaunchKernelGGL(lse_finalize_kernel, dim3(1), dim3(kRedThreads), 0, st, part, (int)nb, out5);
     PPL_LAUNCH_CHECK("lse_finalize_kernel");
     return PPL_OK;
 }
@@ -117,17 +116,21 @@ __host__ __device__ inline int quant_bits(int64_t n) {
     return 62 - c;
 }
 
-// Exact per-tile maximum (NaN entries are ignored here; run_resample rejects
-// NaN through the normaliser's flag).
+// Exact partial maxima of the log-weights, one per block of a grid of at most
+// kRedBlocksMax blocks (NaN entries are ignored here; run_resample rejects NaN
+// through the normaliser's flag).
 template <typename T>
 __global__ __launch_bounds__(kRedThreads) void tile_max_kernel(const T *__restrict__ lw, int64_t n,
                                                                double *__restrict__ blockmax) {
     __shared__ double red[kRedThreads / 64];
-    const int64_t base = (int64_t)blockIdx.x * kScanTile + threadIdx.x * kScanItems;
     double m = -INFINITY;
-#pragma unroll
-    for (int k = 0; k < kScanItems; ++k)
-        if (base + k < n) m = fmax(m, (double)lw[base + k]);
+    const int64_t stride = (int64_t)gridDim.x * kRedThreads;
+    int64_t i = (int64_t)blockIdx.x * kRedThreads + threadIdx.x;
+    for (; i + 3 * stride < n; i += 4 * stride) {   // four independent loads in flight
+        const double v0 = lw[i], v1 = lw[i + stride], v2 = lw[i + 2 * stride], v3 = lw[i + 3 * stride];
+        m = fmax(m, fmax(fmax(v0, v1), fmax(v2, v3)));
+    }
+    for (; i < n; i += stride) m = fmax(m, (double)lw[i]);
     m = wave_max(m);
     if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = m;
     __syncthreads();
@@ -149,16 +152,16 @@ __device__ __forceinline__ uint64_t wave_inclusive_scan_u64(uint64_t v) {
 }
 
 // Quantise and scan one tile: qloc[i] = inclusive sum of q within the tile,
-// total[b] = tile sum.  Every block first reduces the tile maxima itself.
+// total[b] = tile sum.  Every block first reduces the nm partial maxima itself.
 template <typename T>
-__global__ __launch_bounds__(kRedThreads) void quant_scan_kernel(const T *__restrict__ lw, int64_t n, int nb,
+__global__ __launch_bounds__(kRedThreads) void quant_scan_kernel(const T *__restrict__ lw, int64_t n, int nm,
                                                                  const double *__restrict__ blockmax, int kbits,
                                                                  uint64_t *__restrict__ qloc,
                                                                  uint64_t *__restrict__ total) {
     __shared__ double smax[kRedThreads / 64];
     __shared__ uint64_t wsum[kRedThreads / 64];
     double m = -INFINITY;
-    for (int b = threadIdx.x; b < nb; b += kRedThreads) m = fmax(m, blockmax[b]);
+    for (int b = threadIdx.x; b < nm; b += kRedThreads) m = fmax(m, blockmax[b]);
     m = wave_max(m);
     if ((threadIdx.x & 63) == 0) smax[threadIdx.x >> 6] = m;
     __syncthreads();
@@ -166,17 +169,26 @@ __global__ __launch_bounds__(kRedThreads) void quant_scan_kernel(const T *__rest
 #pragma unroll
     for (int w = 1; w < kRedThreads / 64; ++w) m = fmax(m, smax[w]);
 
-    const int64_t base = (int64_t)blockIdx.x * kScanTile + threadIdx.x * kScanItems;
+    // Quantise with striped (coalesced) loads, then scan in blocked order: the
+    // tile passes through LDS both ways so loads and stores stay coalesced.
+    __shared__ uint64_t sbuf[kScanTile];
+    const int64_t tile0 = (int64_t)blockIdx.x * kScanTile;
+#pragma unroll
+    for (int k = 0; k < kScanItems; ++k) {
+        const int64_t i = tile0 + k * kRedThreads + threadIdx.x;
+        uint64_t v = 0;
+        if (i < n) {
+            const double e = exp((double)lw[i] - m);
+            if (e >= 0.0) v = (uint64_t)floor(ldexp(e, kbits));   // NaN entries carry no weight
+        }
+        sbuf[k * kRedThreads + threadIdx.x] = v;
+    }
+    __syncthreads();
     uint64_t q[kScanItems];
     uint64_t run = 0;
 #pragma unroll
     for (int k = 0; k < kScanItems; ++k) {
-        uint64_t v = 0;
-        if (base + k < n) {
-            const double e = exp((double)lw[base + k] - m);
-            if (e >= 0.0) v = (uint64_t)floor(ldexp(e, kbits));   // NaN entries carry no weight
-        }
-        run += v;
+        run += sbuf[threadIdx.x * kScanItems + k];
         q[k] = run;
     }
     const uint64_t incl = wave_inclusive_scan_u64(run);
@@ -186,36 +198,56 @@ __global__ __launch_bounds__(kRedThreads) void quant_scan_kernel(const T *__rest
     uint64_t off = incl - run;
     for (int w = 0; w < wv; ++w) off += wsum[w];
 #pragma unroll
-    for (int k = 0; k < kScanItems; ++k)
-        if (base + k < n) qloc[base + k] = q[k] + off;
+    for (int k = 0; k < kScanItems; ++k) sbuf[threadIdx.x * kScanItems + k] = q[k] + off;
+    __syncthreads();
+#pragma unroll
+    for (int k = 0; k < kScanItems; ++k) {
+        const int64_t i = tile0 + k * kRedThreads + threadIdx.x;
+        if (i < n) qloc[i] = sbuf[k * kRedThreads + threadIdx.x];
+    }
     if (threadIdx.x == kRedThreads - 1) total[blockIdx.x] = off + run;
 }
 
-// Exclusive prefix of the tile totals, S, and U = floor(R S / 2^64).
-__global__ __launch_bounds__(kRedThreads) void tile_prefix_kernel(const uint64_t *__restrict__ total, int nb,
-                                                                  Key key, uint32_t step, uint32_t inst,
-                                                                  uint64_t *__restrict__ prefix,
-                                                                  uint64_t *__restrict__ meta) {
-    __shared__ uint64_t wsum[kRedThreads / 64];
-    __shared__ uint64_t carry;
-    if (threadIdx.x == 0) carry = 0;
-    __syncthreads();
-    for (int b0 = 0; b0 < nb; b0 += kRedThreads) {
-        const int b = b0 + threadIdx.x;
-        const uint64_t v = b < nb ? total[b] : 0;
-        const uint64_t incl = wave_inclusive_scan_u64(v);
-        const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-        if (lane == 63) wsum[wv] = incl;
-        __syncthreads();
-        uint64_t off = carry + incl - v;
-        for (int w = 0; w < wv; ++w) off += wsum[w];
-        if (b < nb) prefix[b] = off;
-        __syncthreads();
-        if (threadIdx.x == kRedThreads - 1) carry = off + v;
-        __syncthreads();
+// Exclusive prefix of the tile totals, S, and U = floor(R S / 2^64).  One
+// workgroup: each thread sums a contiguous chunk of tiles, the chunk sums are
+// scanned across the workgroup, and each thread writes its chunk's prefixes.
+constexpr int kPrefixThreads = 1024;
+
+__global__ __launch_bounds__(kPrefixThreads) void tile_prefix_kernel(const uint64_t *__restrict__ total, int nb,
+                                                                     Key key, uint32_t step, uint32_t inst,
+                                                                     uint64_t *__restrict__ prefix,
+                                                                     uint64_t *__restrict__ meta) {
+    __shared__ uint64_t wsum[kPrefixThreads / 64];
+    const int per = (nb + kPrefixThreads - 1) / kPrefixThreads;
+    const int b0 = threadIdx.x * per;
+    const int b1 = b0 + per < nb ? b0 + per : nb;
+    // chunk loads in batches of eight independent loads
+    uint64_t sum = 0;
+    for (int b = b0; b < b1; b += 8) {
+        uint64_t v[8];
+#pragma unroll
+        for (int k = 0; k < 8; ++k) v[k] = b + k < b1 ? total[b + k] : 0;
+#pragma unroll
+        for (int k = 0; k < 8; ++k) sum += v[k];
     }
-    if (threadIdx.x == 0) {
-        const uint64_t S = carry;
+    const uint64_t incl = wave_inclusive_scan_u64(sum);
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    if (lane == 63) wsum[wv] = incl;
+    __syncthreads();
+    uint64_t off = incl - sum;
+    for (int w = 0; w < wv; ++w) off += wsum[w];
+    for (int b = b0; b < b1; b += 8) {
+        uint64_t v[8];
+#pragma unroll
+        for (int k = 0; k < 8; ++k) v[k] = b + k < b1 ? total[b + k] : 0;
+#pragma unroll
+        for (int k = 0; k < 8; ++k) {
+            if (b + k < b1) prefix[b + k] = off;
+            off += v[k];
+        }
+    }
+    if (threadIdx.x == kPrefixThreads - 1) {
+        const uint64_t S = off;   // the last thread's running sum ends at the grand total
         const uint4 w = philox(0, 0, step, (inst << 8) | kTagResample, key);
         const uint64_t R = ((uint64_t)w.y << 32) | w.x;
         meta[0] = S;
@@ -223,18 +255,11 @@ __global__ __launch_bounds__(kRedThreads) void tile_prefix_kernel(const uint64_t
     }
 }
 
-// a(j) = min{a : n * Q_a > j * S + U}: binary search over the tile ends, then
-// over the tile's local prefix sums.
-__global__ __launch_bounds__(kRedThreads) void ancestor_search_kernel(
-    int64_t n, int nb, const uint64_t *__restrict__ prefix, const uint64_t *__restrict__ total,
-    const uint64_t *__restrict__ qloc, const uint64_t *__restrict__ meta, int32_t *__restrict__ anc) {
-    const int64_t j = (int64_t)blockIdx.x * kRedThreads + threadIdx.x;
-    if (j >= n) return;
-    const uint64_t S = meta[0], U = meta[1];
-    if (S == 0) {           // every weight is zero: no ancestor exists
-        anc[j] = -1;
-        return;
-    }
+// a(j) = min{a : n * Q_a > j * S + U} for S > 0: binary search over the tile
+// ends, then over the tile's local prefix sums.
+__device__ __forceinline__ int64_t find_ancestor(int64_t j, int64_t n, int nb, const uint64_t *__restrict__ prefix,
+                                                 const uint64_t *__restrict__ total,
+                                                 const uint64_t *__restrict__ qloc, uint64_t S, uint64_t U) {
     const unsigned __int128 t = (unsigned __int128)(uint64_t)j * S + U;
     const unsigned __int128 nn = (unsigned __int128)(uint64_t)n;
     // tile: smallest b with n * (prefix[b] + total[b]) > t
@@ -254,35 +279,185 @@ __global__ __launch_bounds__(kRedThreads) void ancestor_search_kernel(
         if (nn * (pre + qloc[mid]) > t) a1 = mid;
         else a0 = mid + 1;
     }
-    anc[j] = (int32_t)a0;
+    return a0;
+}
+
+// Workgroup-cooperative search for a(j) (S > 0; blockDim = kRedThreads): each
+// round probes kRedThreads evenly spaced sources of the interval known to hold
+// a(j) and keeps the segment before the first probe whose n * Q exceeds the
+// slot point (the probe results are monotone, so a ballot count finds it).
+// An interval of length L shrinks to at most ceil(L / 256) per round: four
+// rounds cover n < 2^31.  Every thread of the workgroup must call it.
+__device__ __forceinline__ int64_t block_find_ancestor(int64_t j, int64_t n, const uint64_t *__restrict__ prefix,
+                                                       const uint64_t *__restrict__ qloc, uint64_t S, uint64_t U) {
+    __shared__ int cnt[kRedThreads / 64];
+    const unsigned __int128 t = (unsigned __int128)(uint64_t)j * S + U;
+    const unsigned __int128 nn = (unsigned __int128)(uint64_t)n;
+    int64_t lo = 0, hi = n - 1;
+#pragma unroll 1
+    for (int round = 0; round < 4; ++round) {
+        const int64_t step = (hi - lo + kRedThreads) / kRedThreads;
+        int64_t p = lo + (int64_t)threadIdx.x * step + step - 1;
+        if (p > hi) p = hi;
+        const bool le = !(nn * (prefix[p / kScanTile] + qloc[p]) > t);
+        const uint64_t bal = __ballot(le);
+        if ((threadIdx.x & 63) == 0) cnt[threadIdx.x >> 6] = __popcll(bal);
+        __syncthreads();
+        int c = 0;
+#pragma unroll
+        for (int w = 0; w < kRedThreads / 64; ++w) c += cnt[w];
+        __syncthreads();
+        // probes 0 .. c-1 lie at or below the slot point, probe c above it (c < kRedThreads: the
+        // last probe is hi, and n * Q_hi exceeds it)
+        const int64_t pc = lo + (int64_t)c * step + step - 1;
+        if (c > 0) lo = lo + (int64_t)(c - 1) * step + step;
+        hi = pc < hi ? pc : hi;
+    }
+    return lo;
+}
+
+// Ancestor search fused with the gather of nf 32-bit fields of structure-of-
+// arrays state: out[f][j] = in[f][a(j)] (nf = 0: the search alone).  A
+// workgroup owns kGatherOut consecutive outputs.  Ancestors are non-decreasing
+// in j, so the block's ancestors start at a_lo = a(j_first): the workgroup
+// finds a_lo cooperatively, stages the prefix sums Q_a for a >= a_lo in LDS
+// with coalesced loads until they cover the block's last output (at most
+// kGatherStage of them), and each output binary-searches LDS.  A block whose
+// ancestors span more sources (a long run of zero weights inside it) falls
+// back to a global search per output; both give the same a(j).  Reads of the
+// state then run over consecutive or repeated source words and writes over
+// consecutive destination words.  With no ancestor (all weights zero) the
+// outputs are NaN words and anc[j] = -1.
+constexpr int kGatherPer = 4;
+constexpr int kGatherOut = kRedThreads * kGatherPer;
+constexpr int kGatherStage = 2 * kGatherOut;
+
+__global__ __launch_bounds__(kRedThreads) void ancestor_gather_kernel(
+    int64_t n, int nb, const uint64_t *__restrict__ prefix, const uint64_t *__restrict__ total,
+    const uint64_t *__restrict__ qloc, const uint64_t *__restrict__ meta, int nf, const uint32_t *__restrict__ in,
+    uint32_t *__restrict__ out, int32_t *__restrict__ anc) {
+    __shared__ uint64_t sq[kGatherStage];
+    const int64_t j0 = (int64_t)blockIdx.x * kGatherOut;
+    const int64_t jn = n - j0 < kGatherOut ? n - j0 : kGatherOut;
+    const uint64_t S = meta[0], U = meta[1];
+    if (S == 0) {
+        for (int r = 0; r < kGatherPer; ++r) {
+            const int64_t j = j0 + r * kRedThreads + threadIdx.x;
+            if (j >= n) break;
+            if (anc) anc[j] = -1;
+            for (int f = 0; f < nf; ++f) out[(size_t)f * n + j] = 0x7fc00000u;
+        }
+        return;
+    }
+    const unsigned __int128 nn = (unsigned __int128)(uint64_t)n;
+    const int64_t a_lo = block_find_ancestor(j0, n, prefix, qloc, S, U);
+    const unsigned __int128 t_last = (unsigned __int128)(uint64_t)(j0 + jn - 1) * S + U;
+    // Stage Q_{a_lo + i} in rounds of kGatherOut entries until the last staged
+    // one exceeds the block's last slot point.  Entries past n - 1 repeat
+    // Q_{n-1} = S, which exceeds every slot point.
+    int staged = 0;
+    bool covered = false;
+#pragma unroll 1
+    while (!covered && staged < kGatherStage) {
+#pragma unroll
+        for (int k = 0; k < kGatherPer; ++k) {
+            int64_t a = a_lo + staged + k * kRedThreads + threadIdx.x;
+            if (a > n - 1) a = n - 1;
+            sq[staged + k * kRedThreads + threadIdx.x] = prefix[a / kScanTile] + qloc[a];
+        }
+        __syncthreads();
+        staged += kGatherOut;
+        covered = nn * sq[staged - 1] > t_last;
+    }
+    int64_t a_of[kGatherPer];
+#pragma unroll
+    for (int r = 0; r < kGatherPer; ++r) {
+        const int64_t j = j0 + r * kRedThreads + threadIdx.x;
+        a_of[r] = 0;
+        if (j >= n) continue;
+        if (covered) {
+            // smallest i < staged with n * Q_{a_lo + i} > j S + U (exists: i = staged - 1)
+            const unsigned __int128 t = (unsigned __int128)(uint64_t)j * S + U;
+            int lo = 0, hi = staged - 1;
+            while (lo < hi) {
+                const int mid = (lo + hi) >> 1;
+                if (nn * sq[mid] > t) hi = mid;
+                else lo = mid + 1;
+            }
+            a_of[r] = a_lo + lo;
+        } else {
+            a_of[r] = find_ancestor(j, n, nb, prefix, total, qloc, S, U);
+        }
+        if (anc) anc[j] = (int32_t)a_of[r];
+    }
+    int f = 0;
+    for (; f + 4 <= nf; f += 4) {
+        uint32_t v[kGatherPer][4];
+#pragma unroll
+        for (int r = 0; r < kGatherPer; ++r)
+#pragma unroll
+            for (int k = 0; k < 4; ++k)
+                v[r][k] = (j0 + r * kRedThreads + threadIdx.x < n) ? in[(size_t)(f + k) * n + a_of[r]] : 0u;
+#pragma unroll
+        for (int r = 0; r < kGatherPer; ++r) {
+            const int64_t j = j0 + r * kRedThreads + threadIdx.x;
+            if (j >= n) continue;
+#pragma unroll
+            for (int k = 0; k < 4; ++k) out[(size_t)(f + k) * n + j] = v[r][k];
+        }
+    }
+    for (; f < nf; ++f) {
+#pragma unroll
+        for (int r = 0; r < kGatherPer; ++r) {
+            const int64_t j = j0 + r * kRedThreads + threadIdx.x;
+            if (j < n) out[(size_t)f * n + j] = in[(size_t)f * n + a_of[r]];
+        }
+    }
+}
+
+// Quantisation, tile scans and the tile prefix with the draw of U: everything
+// before the ancestor search.
+static int resample_prologue(const void *lw, bool f64, int64_t n, uint64_t seed, uint32_t step, uint32_t inst,
+                             const ResampleWs &w, hipStream_t st) {
+    const int64_t nb = scan_blocks(n);
+    if (int rc = check_grid("quant_scan_kernel", nb, kRedThreads)) return rc;
+    const int kb = quant_bits(n);
+    const int nm = (int)(nb < kRedBlocksMax ? nb : kRedBlocksMax);
+    if (f64) {
+        hipLaunchKernelGGL(tile_max_kernel<double>, dim3((unsigned)nm), dim3(kRedThreads), 0, st,
+                           (const double *)lw, n, w.blockmax);
+        hipLaunchKernelGGL(quant_scan_kernel<double>, dim3((unsigned)nb), dim3(kRedThreads), 0, st,
+                           (const double *)lw, n, nm, w.blockmax, kb, w.qloc, w.total);
+    } else {
+        hipLaunchKernelGGL(tile_max_kernel<float>, dim3((unsigned)nm), dim3(kRedThreads), 0, st,
+                           (const float *)lw, n, w.blockmax);
+        hipLaunchKernelGGL(quant_scan_kernel<float>, dim3((unsigned)nb), dim3(kRedThreads), 0, st,
+                           (const float *)lw, n, nm, w.blockmax, kb, w.qloc, w.total);
+    }
+    PPL_LAUNCH_CHECK("quant_scan_kernel");
+    hipLaunchKernelGGL(tile_prefix_kernel, dim3(1), dim3(kPrefixThreads), 0, st, w.total, (int)nb,
+                       make_key(seed), step, inst, w.prefix, w.meta);
+    PPL_LAUNCH_CHECK("tile_prefix_kernel");
+    return PPL_OK;
 }
 
 int run_resample(const void *lw, bool f64, int64_t n, uint64_t seed, uint32_t step, uint32_t inst,
                  int32_t *anc, void *ws, hipStream_t st) {
-    const int64_t nb = scan_blocks(n);
-    if (int rc = check_grid("quant_scan_kernel", nb, kRedThreads)) return rc;
-    ResampleWs w = resample_layout(ws, n);
-    const int kb = quant_bits(n);
-    if (f64) {
-        hipLaunchKernelGGL(tile_max_kernel<double>, dim3((unsigned)nb), dim3(kRedThreads), 0, st,
-                           (const double *)lw, n, w.blockmax);
-        hipLaunchKernelGGL(quant_scan_kernel<double>, dim3((unsigned)nb), dim3(kRedThreads), 0, st,
-                           (const double *)lw, n, (int)nb, w.blockmax, kb, w.qloc, w.total);
-    } else {
-        hipLaunchKernelGGL(tile_max_kernel<float>, dim3((unsigned)nb), dim3(kRedThreads), 0, st,
-                           (const float *)lw, n, w.blockmax);
-        hipLaunchKernelGGL(quant_scan_kernel<float>, dim3((unsigned)nb), dim3(kRedThreads), 0, st,
-                           (const float *)lw, n, (int)nb, w.blockmax, kb, w.qloc, w.total);
-    }
-    PPL_LAUNCH_CHECK("quant_scan_kernel");
-    hipLaunchKernelGGL(tile_prefix_kernel, dim3(1), dim3(kRedThreads), 0, st, w.total, (int)nb,
-                       make_key(seed), step, inst, w.prefix, w.meta);
-    PPL_LAUNCH_CHECK("tile_prefix_kernel");
-    const int64_t sb = (n + kRedThreads - 1) / kRedThreads;
-    if (int rc = check_grid("ancestor_search_kernel", sb, kRedThreads)) return rc;
-    hipLaunchKernelGGL(ancestor_search_kernel, dim3((unsigned)sb), dim3(kRedThreads), 0, st, n, (int)nb,
-                       w.prefix, w.total, w.qloc, w.meta, anc);
-    PPL_LAUNCH_CHECK("ancestor_search_kernel");
+    return run_resample_gather(lw, f64, n, seed, step, inst, 0, nullptr, nullptr, anc, ws, st);
+}
+
+int run_resample_gather(const void *lw, bool f64, int64_t n, uint64_t seed, uint32_t step, uint32_t inst, int nf,
+                        const void *state_in, void *state_out, int32_t *anc, void *ws, hipStream_t st) {
+    const ResampleWs w = resample_layout(ws, n);
+    if (int rc = resample_prologue(lw, f64, n, seed, step, inst, w, st)) return rc;
+    const int64_t sb = (n + kGatherOut - 1) / kGatherOut;
+    if (int rc = check_grid("ancestor_gather_kernel", sb, kRedThreads)) return rc;
+    KernelTimer timer("ancestor_gather_kernel", st);
+    hipLaunchKernelGGL(ancestor_gather_kernel, dim3((unsigned)sb), dim3(kRedThreads), 0, st, n,
+                       (int)scan_blocks(n), w.prefix, w.total, w.qloc, w.meta, nf, (const uint32_t *)state_in,
+                       (uint32_t *)state_out, anc);
+    timer.stop();
+    PPL_LAUNCH_CHECK("ancestor_gather_kernel");
     return PPL_OK;
 }
 

@@ -27,7 +27,7 @@ def ppl():
 
 def test_header_declares_the_entry_points():
     names = declared_functions()
-    for n in ("ppl_importance", "ppl_smc", "ppl_lse_ess", "ppl_resample", "ppl_workspace_size",
+    for n in ("ppl_importance", "ppl_smc", "ppl_lse_ess", "ppl_resample", "ppl_resample_gather", "ppl_workspace_size",
               "ppl_last_error", "ppl_status_string"):
         assert n in names
 
@@ -126,6 +126,14 @@ def test_other_entry_points_validate(ppl):
     assert L.ppl_resample(256, 1, 10, 1, 0, 1 << 24, 256, 256, 1 << 20, None) == ppl.PPL_E_ARG
     assert L.ppl_resample(256, 1, 1 << 20, 1, 0, 0, 256, 256, 64, None) == ppl.PPL_E_WORKSPACE
     assert L.ppl_philox(1, 0, 0, 0, 0, 256, None) == ppl.PPL_E_ARG
+    # resample + gather: NULL state, field count, overlapping state buffers, workspace
+    G = L.ppl_resample_gather
+    assert G(256, 1, 10, 1, 0, 0, 4, None, 4096, None, 256, 1 << 20, None) == ppl.PPL_E_ARG
+    assert G(256, 1, 10, 1, 0, 0, 0, 1024, 4096, None, 256, 1 << 20, None) == ppl.PPL_E_ARG
+    assert G(256, 1, 10, 1, 0, 0, 4, 1024, 1024 + 4 * 10 * 4 - 4, None, 256, 1 << 20, None) == ppl.PPL_E_ARG
+    assert G(256, 1, 10, 1, 0, 0, 4, 1024 + 4 * 10 * 4 - 4, 1024, None, 256, 1 << 20, None) == ppl.PPL_E_ARG
+    assert G(256, 1, 1 << 20, 1, 0, 0, 4, 1 << 30, 1 << 34, None, 256, 64, None) == ppl.PPL_E_WORKSPACE
+    assert G(256, 1, 10, 1, 0, 0, 4, 1024, 1024 + 4 * 10 * 4, None, 256, 1 << 20, None) == ppl.PPL_E_DEVICE
     res = ppl.PplResult()
     lg = _data(ppl, y=256, n_data=1000, dtype=ppl.PPL_F32)
     assert L.ppl_smc(ppl.PPL_MODEL_LGSSM, ctypes.byref(lg), 1000, 1, 1.5, 256, 1 << 20, None, ctypes.byref(res)) == ppl.PPL_E_ARG

@@ -257,3 +257,38 @@ def test_resample_all_zero_weight(ppl, dev):
     import torch
     anc = ppl.ppl_resample(torch.full((513,), -float("inf"), device=dev), seed=1)
     assert torch.all(anc == -1).item()
+
+
+@pytest.mark.parametrize("kind", ["normal", "dominant", "neginf"])
+@pytest.mark.parametrize("n,nf", [(1, 1), (1000, 3), (4099, 16), ((1 << 20) + 3, 9)])
+def test_resample_gather(ppl, orc, dev, kind, n, nf):
+    """Fused resampling + gather: the ancestors are ppl_resample's (bit-exact,
+    and the oracle's outside its tie band) and the state is the exact gather
+    out[f][j] = in[f][anc[j]] of 32-bit words."""
+    import torch
+    v = synthetic.logweights(n, kind, seed=n % 29, scale=4.0)
+    t = torch.from_numpy(v).to(dev)
+    g = np.random.default_rng(n)
+    state = g.standard_normal((nf, n)).astype(np.float32)
+    ts = torch.from_numpy(state).to(dev)
+    anc = torch.empty(n, dtype=torch.int32, device=dev)
+    out = ppl.ppl_resample_gather(t, ts, seed=5, step=4, inst=2, anc=anc).cpu().numpy()
+    a = anc.cpu().numpy()
+    assert np.array_equal(a, ppl.ppl_resample(t, seed=5, step=4, inst=2).cpu().numpy())
+    kb = orc.quant_bits(n)
+    ref, tie = orc.resample(v.astype(np.float64), seed=5, step=4, inst=2, band=4.0 * n * 2.0 ** -kb + 1e-15)
+    assert not np.any((a != ref) & ~tie)
+    assert np.array_equal(out.view(np.uint32), state[:, a].view(np.uint32))
+    # without the ancestor output, into a reused buffer
+    out2 = torch.full_like(ts, 7.0)
+    ppl.ppl_resample_gather(t, ts, seed=5, step=4, inst=2, out=out2)
+    assert np.array_equal(out2.cpu().numpy().view(np.uint32), out.view(np.uint32))
+
+
+def test_resample_gather_all_zero_weight(ppl, dev):
+    import torch
+    anc = torch.empty(300, dtype=torch.int32, device=dev)
+    out = ppl.ppl_resample_gather(torch.full((300,), -float("inf"), device=dev), torch.ones((2, 300), device=dev),
+                                  seed=1, anc=anc)
+    assert torch.all(anc == -1).item()
+    assert np.all(out.cpu().numpy().view(np.uint32) == 0x7FC00000)
