@@ -17,6 +17,9 @@ constexpr int kRedThreads = 256;
 constexpr int kRedBlocksMax = 1024;
 constexpr int kScanItems = 8;                          // items per thread in the scan
 constexpr int kScanTile = kRedThreads * kScanItems;    // items per block
+constexpr int kGatherPer = 4;                          // outputs per thread of the gather
+constexpr int kGatherOut = kRedThreads * kGatherPer;   // outputs per gather workgroup
+constexpr int kGatherStage = 2 * kGatherOut;           // staged prefix sums per workgroup
 
 // -------------------------------------------------------- normaliser ----
 template <typename T>
@@ -84,13 +87,16 @@ int run_lse(const void *lw, bool f64, int64_t n, double *out5, void *ws, hipStre
 
 // -------------------------------------------------------- resampling ----
 // Workspace layout (all 256-byte aligned):
-//   blockmax [nb] double | total [nb] u64 | prefix [nb] u64 | meta [4] u64 | qloc [n] u64
+//   blockmax [nb] double | total [nb] u64 | prefix [nb] u64 | meta [4] u64 |
+//   ends [ng + 1] i64 | qloc [n] u64
 struct ResampleWs {
     double *blockmax;
     uint64_t *total, *prefix, *meta, *qloc;
+    int64_t *ends;
 };
 
 static int64_t scan_blocks(int64_t n) { return (n + kScanTile - 1) / kScanTile; }
+static int64_t gather_blocks(int64_t n) { return (n + kGatherOut - 1) / kGatherOut; }
 
 static ResampleWs resample_layout(void *ws, int64_t n) {
     const int64_t nb = scan_blocks(n);
@@ -100,6 +106,7 @@ static ResampleWs resample_layout(void *ws, int64_t n) {
     r.total = (uint64_t *)p; p += align_up(nb * sizeof(uint64_t), 256);
     r.prefix = (uint64_t *)p; p += align_up(nb * sizeof(uint64_t), 256);
     r.meta = (uint64_t *)p; p += 256;
+    r.ends = (int64_t *)p; p += align_up((gather_blocks(n) + 1) * sizeof(int64_t), 256);
     r.qloc = (uint64_t *)p;
     return r;
 }
@@ -107,7 +114,7 @@ static ResampleWs resample_layout(void *ws, int64_t n) {
 size_t resample_ws_bytes(int64_t n) {
     const int64_t nb = scan_blocks(n);
     return align_up(nb * sizeof(double), 256) + 2 * align_up(nb * sizeof(uint64_t), 256) + 256 +
-           align_up(n * sizeof(uint64_t), 256);
+           align_up((gather_blocks(n) + 1) * sizeof(int64_t), 256) + align_up(n * sizeof(uint64_t), 256);
 }
 
 __host__ __device__ inline int quant_bits(int64_t n) {
@@ -282,63 +289,40 @@ __device__ __forceinline__ int64_t find_ancestor(int64_t j, int64_t n, int nb, c
     return a0;
 }
 
-// Workgroup-cooperative search for a(j) (S > 0; blockDim = kRedThreads): each
-// round probes kRedThreads evenly spaced sources of the interval known to hold
-// a(j) and keeps the segment before the first probe whose n * Q exceeds the
-// slot point (the probe results are monotone, so a ballot count finds it).
-// An interval of length L shrinks to at most ceil(L / 256) per round: four
-// rounds cover n < 2^31.  Every thread of the workgroup must call it.
-__device__ __forceinline__ int64_t block_find_ancestor(int64_t j, int64_t n, const uint64_t *__restrict__ prefix,
-                                                       const uint64_t *__restrict__ qloc, uint64_t S, uint64_t U) {
-    __shared__ int cnt[kRedThreads / 64];
-    const unsigned __int128 t = (unsigned __int128)(uint64_t)j * S + U;
-    const unsigned __int128 nn = (unsigned __int128)(uint64_t)n;
-    int64_t lo = 0, hi = n - 1;
-#pragma unroll 1
-    for (int round = 0; round < 4; ++round) {
-        const int64_t step = (hi - lo + kRedThreads) / kRedThreads;
-        int64_t p = lo + (int64_t)threadIdx.x * step + step - 1;
-        if (p > hi) p = hi;
-        const bool le = !(nn * (prefix[p / kScanTile] + qloc[p]) > t);
-        const uint64_t bal = __ballot(le);
-        if ((threadIdx.x & 63) == 0) cnt[threadIdx.x >> 6] = __popcll(bal);
-        __syncthreads();
-        int c = 0;
-#pragma unroll
-        for (int w = 0; w < kRedThreads / 64; ++w) c += cnt[w];
-        __syncthreads();
-        // probes 0 .. c-1 lie at or below the slot point, probe c above it (c < kRedThreads: the
-        // last probe is hi, and n * Q_hi exceeds it)
-        const int64_t pc = lo + (int64_t)c * step + step - 1;
-        if (c > 0) lo = lo + (int64_t)(c - 1) * step + step;
-        hi = pc < hi ? pc : hi;
-    }
-    return lo;
+// Ancestors of the gather workgroups' range ends: ends[k] = a(k kGatherOut)
+// for k < ng and ends[ng] = a(n - 1), one global search per thread (S > 0).
+__global__ __launch_bounds__(kRedThreads) void gather_ends_kernel(int64_t n, int nb, int64_t ng,
+                                                                  const uint64_t *__restrict__ prefix,
+                                                                  const uint64_t *__restrict__ total,
+                                                                  const uint64_t *__restrict__ qloc,
+                                                                  const uint64_t *__restrict__ meta,
+                                                                  int64_t *__restrict__ ends) {
+    const int64_t k = (int64_t)blockIdx.x * kRedThreads + threadIdx.x;
+    if (k > ng) return;
+    const uint64_t S = meta[0], U = meta[1];
+    if (S == 0) return;   // the gather writes its no-ancestor outputs without reading ends
+    const int64_t j = k < ng ? k * kGatherOut : n - 1;
+    ends[k] = find_ancestor(j, n, nb, prefix, total, qloc, S, U);
 }
 
 // Ancestor search fused with the gather of nf 32-bit fields of structure-of-
 // arrays state: out[f][j] = in[f][a(j)] (nf = 0: the search alone).  A
 // workgroup owns kGatherOut consecutive outputs.  Ancestors are non-decreasing
-// in j, so the block's ancestors start at a_lo = a(j_first): the workgroup
-// finds a_lo cooperatively, stages the prefix sums Q_a for a >= a_lo in LDS
-// with coalesced loads until they cover the block's last output (at most
-// kGatherStage of them), and each output binary-searches LDS.  A block whose
-// ancestors span more sources (a long run of zero weights inside it) falls
-// back to a global search per output; both give the same a(j).  Reads of the
-// state then run over consecutive or repeated source words and writes over
-// consecutive destination words.  With no ancestor (all weights zero) the
-// outputs are NaN words and anc[j] = -1.
-constexpr int kGatherPer = 4;
-constexpr int kGatherOut = kRedThreads * kGatherPer;
-constexpr int kGatherStage = 2 * kGatherOut;
-
+// in j, so the workgroup's ancestors lie in [ends[k], ends[k + 1]] (the
+// ancestors of its first output and of the next workgroup's first output, or
+// of the last output): it stages the prefix sums Q_a of that range in LDS with
+// coalesced loads and each output binary-searches LDS.  A range longer than
+// kGatherStage (a long run of zero weights inside the block) falls back to a
+// global search per output; both give the same a(j).  Reads of the state then
+// run over consecutive or repeated source words and writes over consecutive
+// destination words.  With no ancestor (all weights zero) the outputs are NaN
+// words and anc[j] = -1.
 __global__ __launch_bounds__(kRedThreads) void ancestor_gather_kernel(
     int64_t n, int nb, const uint64_t *__restrict__ prefix, const uint64_t *__restrict__ total,
-    const uint64_t *__restrict__ qloc, const uint64_t *__restrict__ meta, int nf, const uint32_t *__restrict__ in,
-    uint32_t *__restrict__ out, int32_t *__restrict__ anc) {
+    const uint64_t *__restrict__ qloc, const uint64_t *__restrict__ meta, const int64_t *__restrict__ ends, int nf,
+    const uint32_t *__restrict__ in, uint32_t *__restrict__ out, int32_t *__restrict__ anc) {
     __shared__ uint64_t sq[kGatherStage];
     const int64_t j0 = (int64_t)blockIdx.x * kGatherOut;
-    const int64_t jn = n - j0 < kGatherOut ? n - j0 : kGatherOut;
     const uint64_t S = meta[0], U = meta[1];
     if (S == 0) {
         for (int r = 0; r < kGatherPer; ++r) {
@@ -350,35 +334,26 @@ __global__ __launch_bounds__(kRedThreads) void ancestor_gather_kernel(
         return;
     }
     const unsigned __int128 nn = (unsigned __int128)(uint64_t)n;
-    const int64_t a_lo = block_find_ancestor(j0, n, prefix, qloc, S, U);
-    const unsigned __int128 t_last = (unsigned __int128)(uint64_t)(j0 + jn - 1) * S + U;
-    // Stage Q_{a_lo + i} in rounds of kGatherOut entries until the last staged
-    // one exceeds the block's last slot point.  Entries past n - 1 repeat
-    // Q_{n-1} = S, which exceeds every slot point.
-    int staged = 0;
-    bool covered = false;
-#pragma unroll 1
-    while (!covered && staged < kGatherStage) {
-#pragma unroll
-        for (int k = 0; k < kGatherPer; ++k) {
-            int64_t a = a_lo + staged + k * kRedThreads + threadIdx.x;
-            if (a > n - 1) a = n - 1;
-            sq[staged + k * kRedThreads + threadIdx.x] = prefix[a / kScanTile] + qloc[a];
+    const int64_t a_lo = ends[blockIdx.x];
+    const int64_t range = ends[blockIdx.x + 1] - a_lo + 1;
+    const bool staged = range <= kGatherStage;
+    if (staged) {
+        for (int i = threadIdx.x; i < range; i += kRedThreads) {
+            const int64_t a = a_lo + i;
+            sq[i] = prefix[a / kScanTile] + qloc[a];
         }
-        __syncthreads();
-        staged += kGatherOut;
-        covered = nn * sq[staged - 1] > t_last;
     }
+    __syncthreads();
     int64_t a_of[kGatherPer];
 #pragma unroll
     for (int r = 0; r < kGatherPer; ++r) {
         const int64_t j = j0 + r * kRedThreads + threadIdx.x;
         a_of[r] = 0;
         if (j >= n) continue;
-        if (covered) {
-            // smallest i < staged with n * Q_{a_lo + i} > j S + U (exists: i = staged - 1)
+        if (staged) {
+            // smallest i < range with n * Q_{a_lo + i} > j S + U (exists: i = range - 1)
             const unsigned __int128 t = (unsigned __int128)(uint64_t)j * S + U;
-            int lo = 0, hi = staged - 1;
+            int lo = 0, hi = (int)range - 1;
             while (lo < hi) {
                 const int mid = (lo + hi) >> 1;
                 if (nn * sq[mid] > t) hi = mid;
@@ -450,12 +425,15 @@ int run_resample_gather(const void *lw, bool f64, int64_t n, uint64_t seed, uint
                         const void *state_in, void *state_out, int32_t *anc, void *ws, hipStream_t st) {
     const ResampleWs w = resample_layout(ws, n);
     if (int rc = resample_prologue(lw, f64, n, seed, step, inst, w, st)) return rc;
-    const int64_t sb = (n + kGatherOut - 1) / kGatherOut;
-    if (int rc = check_grid("ancestor_gather_kernel", sb, kRedThreads)) return rc;
+    const int64_t ng = gather_blocks(n);
+    if (int rc = check_grid("ancestor_gather_kernel", ng, kRedThreads)) return rc;
+    hipLaunchKernelGGL(gather_ends_kernel, dim3((unsigned)((ng + kRedThreads) / kRedThreads)), dim3(kRedThreads), 0,
+                       st, n, (int)scan_blocks(n), ng, w.prefix, w.total, w.qloc, w.meta, w.ends);
+    PPL_LAUNCH_CHECK("gather_ends_kernel");
     KernelTimer timer("ancestor_gather_kernel", st);
-    hipLaunchKernelGGL(ancestor_gather_kernel, dim3((unsigned)sb), dim3(kRedThreads), 0, st, n,
-                       (int)scan_blocks(n), w.prefix, w.total, w.qloc, w.meta, nf, (const uint32_t *)state_in,
-                       (uint32_t *)state_out, anc);
+    hipLaunchKernelGGL(ancestor_gather_kernel, dim3((unsigned)ng), dim3(kRedThreads), 0, st, n,
+                       (int)scan_blocks(n), w.prefix, w.total, w.qloc, w.meta, w.ends, nf,
+                       (const uint32_t *)state_in, (uint32_t *)state_out, anc);
     timer.stop();
     PPL_LAUNCH_CHECK("ancestor_gather_kernel");
     return PPL_OK;
