@@ -17,7 +17,7 @@ Printed as one JSON line, with
 
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu]
                        [--config blr|poly|poly-paper|lgssm|gmm-batched|resample-gather|proposal-poly|
-                                 proposal-gmm|proposal-train]
+                                 proposal-gmm|proposal-train|peaks]
 """
 import argparse
 import json
@@ -47,7 +47,7 @@ def parse():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--config", default="blr",
                     choices=["blr", "poly", "poly-paper", "lgssm", "gmm-batched", "resample-gather", "proposal-poly",
-                             "proposal-gmm", "proposal-train"])
+                             "proposal-gmm", "proposal-train", "peaks"])
     ap.add_argument("--pairs-log2", type=int, default=22, help="proposal-train: log2 of the simulated pairs")
     ap.add_argument("--no-graph", action="store_true", help="proposal-train: launch each step's kernels eagerly")
     ap.add_argument("--batch", type=int, default=0, help="proposal: training batch (default 4096)")
@@ -72,6 +72,60 @@ def copy_calibration():
         b.copy_(a)
     torch.cuda.synchronize()
     print(json.dumps({"copy_calibration_bytes_read": 4 * n, "copy_calibration_bytes_written": 4 * n}), flush=True)
+
+
+# Micro-benchmark kinds of libppl_peaks.so: (name, FLOP or ops per lane-instruction, unit, published peak)
+PEAK_KINDS = [("fma_f32", 2, "TFLOP/s", 157.3), ("fma_f64", 2, "TFLOP/s", 78.6), ("exp_f32", 1, "Top/s", None),
+              ("log_f32", 1, "Top/s", None), ("sin_f32", 1, "Top/s", None), ("mulhi_u32", 1, "Top/s", None),
+              ("mfma_bf16", 16 * 16 * 32 * 2 // 64, "TFLOP/s", 2500.0)]
+
+
+def bench_peaks(torch, dev, stream):
+    """Measured rates of the instruction kinds the roofline fractions are priced
+    against (libppl_peaks.so), beside MI355X's published figures: 2048
+    workgroups of 256 lanes, eight independent chains per lane, each kernel
+    sized to about 20 ms and timed with HIP events; and a 1 GiB device copy."""
+    import ctypes
+    L = ctypes.CDLL(os.path.join(ROOT, "paper_2010_08454_amd", "libppl_peaks.so"))
+    L.peak_alu.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_void_p, ctypes.c_void_p]
+    L.peak_copy.argtypes = [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int64, ctypes.c_int, ctypes.c_void_p]
+    blocks = CU * 8
+    out = torch.empty(blocks * 256, device=dev)
+    sp = ctypes.c_void_p(stream.cuda_stream)
+
+    def timed(fn, reps):
+        ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        fn()
+        torch.cuda.synchronize()
+        ev0.record(stream)
+        for _ in range(reps):
+            fn()
+        ev1.record(stream)
+        torch.cuda.synchronize()
+        return ev0.elapsed_time(ev1) / reps
+
+    res = {}
+    for kind, (name, per, unit, pub) in enumerate(PEAK_KINDS):
+        per_iter = L.peak_ops_per_iter(kind)
+
+        def run(it):
+            assert L.peak_alu(kind, blocks, it, ctypes.c_void_p(out.data_ptr()), sp) == 0
+        iters = 64
+        ms = timed(lambda: run(iters), 1)
+        iters = max(64, int(iters * 20.0 / max(ms, 1e-3)))
+        ms = timed(lambda: run(iters), 5)
+        rate = blocks * 256 * iters * per_iter * per / (ms / 1e3) / 1e12
+        res[name] = {"rate": round(rate, 2), "unit": unit, "published": pub, "ms": round(ms, 3), "iters": iters}
+    n4 = (1 << 30) // 16
+    src = torch.ones(n4 * 4, dtype=torch.float32, device=dev)
+    dst = torch.empty_like(src)
+    for cb in (CU * 4, CU * 16):
+        ms = timed(lambda: L.peak_copy(ctypes.c_void_p(src.data_ptr()), ctypes.c_void_p(dst.data_ptr()), n4, cb, sp), 10)
+        res[f"hbm_copy_{cb}wg"] = {"rate": round(2 * n4 * 16 / (ms / 1e3) / 1e9, 1), "unit": "GB/s", "published": 8000.0,
+                                   "ms": round(ms, 4)}
+    print(json.dumps({"metric": "measured peak rates", "n_gpus": 1, "data": "synthetic", "peaks": res,
+                      "note": "fp32 FMA issue without packed FP32 (disabled in this build) peaks at 78.64 TFLOP/s; "
+                              "the published 157.3 assumes packed FP32"}), flush=True)
 
 
 def cpu_baseline_blr(X, y, n_full, seed, target_s=15.0):
@@ -467,6 +521,9 @@ def main():
         return
     if args.config.startswith("proposal"):
         bench_proposal(args, ppl, synthetic, torch, dev, stream)
+        return
+    if args.config == "peaks":
+        bench_peaks(torch, dev, stream)
         return
     if args.config == "resample-gather":
         bench_resample_gather(args, ppl, synthetic, torch, dev, stream)

@@ -1,4 +1,5 @@
-"""Build step of libppl: compiles the HIP sources for gfx950 into libppl.so (in-tree).
+"""Build step of libppl: compiles the HIP sources for gfx950 into libppl.so (in-tree),
+and the rate micro-benchmarks (csrc/peaks/) into libppl_peaks.so.
 
 Run as ``python paper_2010_08454_amd/build.py`` (by path: importing the package
 loads the library it builds).  Packed-FP32 instructions are disabled
@@ -12,6 +13,7 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 OUT = os.path.join(HERE, "libppl.so")
+PEAKS_OUT = os.path.join(HERE, "libppl_peaks.so")
 
 HIPCC_FLAGS = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-shared",
                "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
@@ -22,10 +24,10 @@ def sources():
     return sorted(glob.glob(os.path.join(HERE, "csrc", "*.hip")))
 
 
-def build(verbose=False):
+def _hipcc(srcs, out, verbose):
     hipcc = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
-    tmp = OUT + ".tmp"
-    cmd = [hipcc] + HIPCC_FLAGS + ["-o", tmp] + sources()
+    tmp = out + ".tmp"
+    cmd = [hipcc] + HIPCC_FLAGS + ["-o", tmp] + srcs
     if verbose:
         print(" ".join(cmd), flush=True)
     r = subprocess.run(cmd, capture_output=True, text=True)
@@ -35,8 +37,13 @@ def build(verbose=False):
         raise RuntimeError("hipcc failed:\n" + "\n".join(msgs))
     if verbose and msgs:
         print("\n".join(msgs))
-    os.replace(tmp, OUT)
-    return OUT
+    os.replace(tmp, out)
+    return out
+
+
+def build(verbose=False):
+    _hipcc(sorted(glob.glob(os.path.join(HERE, "csrc", "peaks", "*.hip"))), PEAKS_OUT, verbose)
+    return _hipcc(sources(), OUT, verbose)
 
 
 if __name__ == "__main__":
