@@ -115,6 +115,52 @@ def test_poly_paper_scale_sampled(ppl, orc, dev):
     assert abs(res.log_evidence - ex["log_z"]) < 4 * math.sqrt(1 / res.ess)
 
 
+N_MAX = (1 << 31) - 1      # the largest particle count the ABI takes
+
+
+def test_poly_max_particles_sampled(ppl, orc, dev):
+    """N = 2^31 - 1 (two-level block merge, 64-bit offsets, the last particle):
+    sampled log-weights against the oracle one by one, log Z-hat against an
+    FP64 log-sum-exp of the returned log-weights, and the estimate against
+    exact enumeration."""
+    import torch
+    from oracle import closed_forms as cf
+    x, y = synthetic.poly_data()
+    seed = 11
+    data = ppl.make_data(torch.from_numpy(x).to(dev), torch.from_numpy(y).to(dev))
+    lw = torch.empty(N_MAX, dtype=torch.float64, device=dev)
+    res = ppl.ppl_importance(ppl.PPL_MODEL_POLY, data, N_MAX, seed, log_weights=lw, sync=True)
+    g = np.random.default_rng(1)
+    idx = np.unique(np.concatenate([[0, 1, 255, 256, N_MAX - 257, N_MAX - 2, N_MAX - 1],
+                                    g.integers(0, N_MAX, 300)]))
+    got = lw[torch.from_numpy(idx).to(dev)].cpu().numpy()
+    rlw, _ = orc.particle_logweights(orc.MODEL_POLY, x, y, idx, seed)
+    assert mixed_err(got, rlw) < 1e-12
+    lse = float(torch.logsumexp(lw, 0).item())
+    del lw
+    assert abs(res.log_evidence - (lse - math.log(N_MAX))) < 1e-10 * abs(res.log_evidence)
+    assert abs(res.log_evidence - cf.poly_exact(x, y)["log_z"]) < 4 * math.sqrt(1 / res.ess)
+
+
+def test_blr_max_particles_sampled(ppl, orc, dev):
+    """N = 2^31 - 1 for the FP32 BLR likelihood (64 rows): sampled log-weights
+    against the oracle one by one, including the last particle."""
+    import torch
+    X, y, _ = synthetic.blr_data(D=64, d=16)
+    seed = 13
+    data = ppl.make_data(torch.from_numpy(X).to(dev), torch.from_numpy(y).to(dev), dim=16)
+    lw = torch.empty(N_MAX, dtype=torch.float64, device=dev)
+    res = ppl.ppl_importance(ppl.PPL_MODEL_BLR, data, N_MAX, seed, log_weights=lw, sync=True)
+    g = np.random.default_rng(2)
+    idx = np.unique(np.concatenate([[0, 1023, 1024, N_MAX - 1025, N_MAX - 2, N_MAX - 1],
+                                    g.integers(0, N_MAX, 200)]))
+    got = lw[torch.from_numpy(idx).to(dev)].cpu().numpy()
+    del lw
+    rlw, _ = orc.particle_logweights(orc.MODEL_BLR, X, y, idx, seed, dim=16)
+    assert mixed_err(got, rlw) < 1e-5
+    assert math.isfinite(res.log_evidence) and res.ess >= 1.0
+
+
 # -------------------------------------------------------------------- BLR --
 def run_blr(ppl, dev, X, y, n, seed, q=None):
     import torch
@@ -283,6 +329,25 @@ def test_resample_gather(ppl, orc, dev, kind, n, nf):
     out2 = torch.full_like(ts, 7.0)
     ppl.ppl_resample_gather(t, ts, seed=5, step=4, inst=2, out=out2)
     assert np.array_equal(out2.cpu().numpy().view(np.uint32), out.view(np.uint32))
+
+
+def test_resample_gather_max_n(ppl, dev):
+    """n = 2^31 - 1 with weights whose ancestors are exact at any size: equal
+    weights keep every particle in its slot (q_a = 2^31 for all a, so
+    a(j) = j), and a single positive weight at the last index sends every slot
+    to it.  The state holds each particle's index, so the gathered state equals
+    the ancestors."""
+    import torch
+    n = N_MAX
+    lw = torch.zeros(n, dtype=torch.float32, device=dev)
+    state = torch.arange(n, dtype=torch.int32, device=dev).view(1, n)
+    anc = torch.empty(n, dtype=torch.int32, device=dev)
+    out = ppl.ppl_resample_gather(lw, state, seed=3, step=1, anc=anc)
+    assert torch.equal(anc, state[0]) and torch.equal(out, state)
+    lw.fill_(-float("inf"))
+    lw[n - 1] = 0.0
+    ppl.ppl_resample_gather(lw, state, seed=3, step=2, out=out, anc=anc)
+    assert bool((anc == n - 1).all()) and bool((out == n - 1).all())
 
 
 def test_resample_gather_all_zero_weight(ppl, dev):
