@@ -36,8 +36,17 @@ FP32_VALU_PUBLISHED_TFLOPS = 157.3        # needs packed FP32, which this build 
 FP64_VALU_TFLOPS = 78.6
 
 FLOP_PER_EVAL_BLR = 34                    # 17 FMA per (particle, row) at d = 16
-# sources whose hash keys the committed PMC byte counts of the importance kernels
-KERNEL_SOURCES = ("paper_2010_08454_amd/csrc/importance.hip", "paper_2010_08454_amd/csrc/device.h")
+# Committed PMC byte counts per configuration: (summary file under profiles/, the
+# sources whose hash keys it).  A count is used only while the hash matches.
+_CS = "paper_2010_08454_amd/csrc/"
+TRAFFIC_FILES = {
+    "blr": ("blr_is_kernel_traffic.txt", (_CS + "importance.hip", _CS + "device.h")),
+    "lgssm": ("smc_persistent_kernel_traffic_lgssm-N2p20-T1000.txt",
+              (_CS + "smc.hip", _CS + "smc.h", _CS + "device.h")),
+    "gmm-batched": ("smc_batched_kernel_traffic_gmm-batched-256inst-N2p16.txt",
+                    (_CS + "batched.hip", _CS + "batched.h", _CS + "device.h")),
+    "resample-gather": ("ancestor_gather_kernel_traffic.txt", (_CS + "resample.hip", _CS + "device.h")),
+}
 
 
 def parse():
@@ -166,11 +175,15 @@ def cpu_baseline_lgssm(y, seed, target_s=15.0):
             "kind": "oracle", "sample": f"{n} of the 2^20 particles over all {y.size} steps, FP64 oracle, {dt:.1f} s"}
 
 
-def measured_traffic(kernel, sources):
-    """HBM bytes per launch from the committed rocprofv3 PMC summary of `kernel`,
-    or None when the kernel's sources changed since the counters were taken."""
+def measured_traffic(config):
+    """HBM bytes per launch from the committed rocprofv3 PMC summary of the
+    configuration's dominant kernel, or None when there is none or the kernel's
+    sources changed since the counters were taken."""
     import hashlib
-    path = os.path.join(ROOT, "profiles", f"{kernel}_traffic.txt")
+    if config not in TRAFFIC_FILES:
+        return None
+    fname, sources = TRAFFIC_FILES[config]
+    path = os.path.join(ROOT, "profiles", fname)
     if not os.path.exists(path):
         return None
     kv = {}
@@ -201,7 +214,6 @@ def cpu_baseline_poly(x, y, n, seed):
 
 HBM_GBS = 8000.0
 GATHER_FIELDS = 16
-RESAMPLE_SOURCES = ("paper_2010_08454_amd/csrc/resample.hip", "paper_2010_08454_amd/csrc/device.h")
 
 
 def bench_resample_gather(args, ppl, synthetic, torch, dev, stream):
@@ -248,7 +260,7 @@ def bench_resample_gather(args, ppl, synthetic, torch, dev, stream):
                 "call_gb_per_s": round(call_bytes / (ms / 1e3) / 1e9, 1)}
     roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_GBS, "unit": "GB/s",
                 "frac": round(achieved / HBM_GBS, 4),
-                "traffic": measured_traffic("ancestor_gather_kernel", RESAMPLE_SOURCES),
+                "traffic": measured_traffic("resample-gather"),
                 "kernel": "ancestor_gather_kernel", "kernel_ms": round(k_avg, 4), "kernel_launches": k_n,
                 "bytes_per_launch": bytes_per_launch}
     res = {"metric": "resampled particles/s", "value": N / (ms / 1e3), "unit": "particles/s", "n_gpus": 1,
@@ -634,7 +646,7 @@ def main():
         assert s[3] == 0 and math.isfinite(s[0]), f"device status {s[3]}"
 
     roofline = {"bound": bound, "achieved": round(achieved, 3), "peak": round(peak, 2), "unit": unit,
-                "frac": round(achieved / peak, 4), "traffic": measured_traffic(kname, KERNEL_SOURCES),
+                "frac": round(achieved / peak, 4), "traffic": measured_traffic(args.config),
                 "kernel": kname, "kernel_ms": round(k_avg_ms, 4), "kernel_launches": k_n,
                 "flop_per_launch": flop_per_launch}
     if args.config == "blr":
