@@ -170,9 +170,11 @@ int ppl_workspace_size(int model, const ppl_data *data, int64_t n_particles, int
  * log-sum-exp normaliser gives log Z-hat = LSE(lw) - log N and
  * ESS = (sum w)^2 / sum w^2.
  * model: PPL_MODEL_POLY, PPL_MODEL_BLR or PPL_MODEL_GMM.  n_particles in [1, 2^31).
- * GMM importance sampling runs in FP64 (data float32, upcast exactly); its
- * latents are float64 [2K][N] (log pi_k, mu_k) and its prior draws are those
- * of the SMC initial particles.
+ * GMM importance sampling draws its latents and evaluates the prior and
+ * proposal densities in FP64; the likelihood is FP32 per datum (hardware exp
+ * and log, as in the SMC), summed in FP32 within blocks of 16 data and in
+ * FP64 across blocks.  Its latents are float64 [2K][N] (log pi_k, mu_k) and
+ * its prior draws are those of the SMC initial particles.
  * d_summaries (FP64):
  *   POLY: [0..3] P(n = 2..5 | y); [4 + 5(n-2) + j] E[c_j | n, y] (0 where that
  *         degree has no mass); [24 + j] E[c_j 1{j < n} | y]        -> 29 values

@@ -36,9 +36,21 @@ __device__ __forceinline__ void normals4_d(uint4 w, double *z) {
     box_muller(u01d(w.z), u01d(w.w), z[2], z[3]);
 }
 
-__device__ __forceinline__ double log_normal(double v, double m, double lsd) {
-    const double r = (v - m) * exp(-lsd);
+// log Normal(v; m, exp(lsd)) given isd = exp(-lsd).
+__device__ __forceinline__ double log_normal(double v, double m, double lsd, double isd) {
+    const double r = (v - m) * isd;
     return -0.5 * r * r - lsd - kHalfLog2PiD;
+}
+
+// exp(lsd) and exp(-lsd) of the proposal's ns log-scales, computed once per
+// workgroup into LDS (every particle of the workgroup uses the same table).
+// Every thread of the workgroup must call it.
+__device__ __forceinline__ void stage_scales(const double *__restrict__ lsdv, int ns, double *sdv, double *isdv) {
+    for (int t = threadIdx.x; t < ns; t += kPropThreads) {
+        sdv[t] = exp(lsdv[t]);
+        isdv[t] = exp(-lsdv[t]);
+    }
+    __syncthreads();
 }
 
 template <int KMAX>
@@ -67,6 +79,8 @@ __global__ __launch_bounds__(kPropThreads) void poly_mix_is_kernel(
     const bool live = i < N;
     const uint32_t ii = (uint32_t)i;
     const double *lnl = q, *lmix = q + 4, *mean = q + 12, *lsdv = q + 172;
+    __shared__ double sdv[160], isdv[160];
+    stage_scales(lsdv, 160, sdv, isdv);
     const uint4 w0 = philox(ii, 0, 0, kTagProposal, key);
     const int n = 2 + categorical_exp<4>(u01d(w0.x), lnl, 4);
     const int comp = categorical_exp<8>(u01d(w0.y), lmix, 8);
@@ -75,12 +89,12 @@ __global__ __launch_bounds__(kPropThreads) void poly_mix_is_kernel(
     normals4_d(philox(ii, 2, 0, kTagProposal, key), z + 4);
     double c[5];
     double lp = -log(4.0);
-    const double lsd0 = log(sd);
+    const double lsd0 = log(sd), isd0 = exp(-lsd0);
 #pragma unroll
     for (int j = 0; j < 5; ++j) {
         const int o = ((n - 2) * 8 + comp) * 5 + j;
-        c[j] = j < n ? mean[o] + exp(lsdv[o]) * z[j] : 0.0;
-        if (j < n) lp += log_normal(c[j], 0.0, lsd0);
+        c[j] = j < n ? mean[o] + sdv[o] * z[j] : 0.0;
+        if (j < n) lp += log_normal(c[j], 0.0, lsd0, isd0);
     }
     // log q(n, c): degree term plus the mixture over components.
     double t[8], tm = -INFINITY;
@@ -90,7 +104,7 @@ __global__ __launch_bounds__(kPropThreads) void poly_mix_is_kernel(
 #pragma unroll
         for (int j = 0; j < 5; ++j) {
             const int o = ((n - 2) * 8 + m) * 5 + j;
-            if (j < n) a += log_normal(c[j], mean[o], lsdv[o]);
+            if (j < n) a += log_normal(c[j], mean[o], lsdv[o], isdv[o]);
         }
         t[m] = a;
         tm = fmax(tm, a);
@@ -163,39 +177,53 @@ __global__ __launch_bounds__(kPropThreads) void poly_mix_is_kernel(
 }
 
 // --------------------------------------------------------------- GMM --
-// log sum_k pi_k Normal(y; mu_k, sd) with the max shift, summed over the data.
-__device__ __forceinline__ double gmm_point(double y, int K, const double (&lpi)[8], const double (&mu)[8],
-                                            double inv_sd, double cst) {
-    double t[8], mx = -INFINITY;
+// One datum's log-factor, log sum_k pi_k Normal(y; mu_k, sd), in FP32 with the
+// max shift and the hardware exp and log, as in the batched mixture SMC;
+// c[k] = log pi_k - log(sd sqrt(2 pi)).
+__device__ __forceinline__ float gmm_point(float y, int K, const float (&c)[8], const float (&mu)[8], float inv_sd) {
+    float t[8], mx = -INFINITY;
 #pragma unroll
     for (int k = 0; k < 8; ++k) {
         if (k < K) {
-            const double r = (y - mu[k]) * inv_sd;
-            t[k] = lpi[k] + cst - 0.5 * r * r;
-            mx = fmax(mx, t[k]);
+            const float r = (y - mu[k]) * inv_sd;
+            t[k] = fmaf(-0.5f * r, r, c[k]);
+            mx = fmaxf(mx, t[k]);
         }
     }
-    double s = 0.0;
+    float s = 0.0f;
 #pragma unroll
     for (int k = 0; k < 8; ++k)
-        if (k < K) s += exp(t[k] - mx);
-    return mx + log(s);
+        if (k < K) s += __expf(t[k] - mx);
+    return mx + __logf(s);
 }
 
-// Points in chunks of sixteen (one batch of scalar loads per chunk); the sum
-// order is unchanged.
+// Sum of the log-factors over the data: FP32 within blocks of 16 points (one
+// batch of scalar loads each), FP64 across blocks.
 __device__ __forceinline__ double gmm_loglik(const float *__restrict__ Y, int D, int K, const double (&lpi)[8],
                                              const double (&mu)[8], double inv_sd, double cst) {
+    float c[8], muf[8];
+#pragma unroll
+    for (int k = 0; k < 8; ++k) {
+        c[k] = k < K ? (float)(lpi[k] + cst) : 0.0f;
+        muf[k] = k < K ? (float)mu[k] : 0.0f;
+    }
+    const float isd = (float)inv_sd;
     double ll = 0.0;
     int d = 0;
     for (; d + 16 <= D; d += 16) {
         float ys[16];
 #pragma unroll
         for (int k = 0; k < 16; ++k) ys[k] = Y[d + k];
-#pragma unroll 1
-        for (int k = 0; k < 16; ++k) ll += gmm_point((double)ys[k], K, lpi, mu, inv_sd, cst);
+        float sb = 0.0f;
+#pragma unroll 4
+        for (int k = 0; k < 16; ++k) sb += gmm_point(ys[k], K, c, muf, isd);
+        ll += (double)sb;
     }
-    for (; d < D; ++d) ll += gmm_point((double)Y[d], K, lpi, mu, inv_sd, cst);
+    if (d < D) {
+        float sb = 0.0f;
+        for (; d < D; ++d) sb += gmm_point(Y[d], K, c, muf, isd);
+        ll += (double)sb;
+    }
     return ll;
 }
 
@@ -208,6 +236,8 @@ __global__ __launch_bounds__(kPropThreads) void gmm_is_kernel(const float *__res
     const bool live = i < N;
     const uint32_t ii = (uint32_t)i;
     double lpi[8], mu[8], extra = 0.0;
+    __shared__ double sdv[PROP ? 8 * 15 : 1], isdv[PROP ? 8 * 15 : 1];
+    if constexpr (PROP) stage_scales(q + 8 + 8 * (2 * K - 1), 8 * (2 * K - 1), sdv, isdv);
     if constexpr (!PROP) {
         // Prior draws (the SMC initial particles): Dirichlet(1) weights as
         // normalised Exp(1) draws, means mu_sd z.
@@ -237,7 +267,7 @@ __global__ __launch_bounds__(kPropThreads) void gmm_is_kernel(const float *__res
         normals4_d(philox(ii, 3, 0, kTagProposal, key), z + 8);
         normals4_d(philox(ii, 4, 0, kTagProposal, key), z + 12);
 #pragma unroll
-        for (int k = 0; k < 15; ++k) u[k] = k < d ? mean[comp * d + k] + exp(lsdv[comp * d + k]) * z[k] : 0.0;
+        for (int k = 0; k < 15; ++k) u[k] = k < d ? mean[comp * d + k] + sdv[comp * d + k] * z[k] : 0.0;
         // prior density of u and the map to (log pi, mu)
         double lg[8], lgm = -INFINITY;
 #pragma unroll
@@ -251,7 +281,7 @@ __global__ __launch_bounds__(kPropThreads) void gmm_is_kernel(const float *__res
             if (k < K) lgs += exp(lg[k] - lgm);
         const double lz = lgm + log(lgs);
         double lp = lgamma((double)K) + lgamma((double)K + 1.0);
-        const double lmu = log(mu_sd);
+        const double lmu = log(mu_sd), imu = exp(-lmu);
         double prev = 0.0;
 #pragma unroll
         for (int k = 0; k < 8; ++k) {
@@ -259,7 +289,7 @@ __global__ __launch_bounds__(kPropThreads) void gmm_is_kernel(const float *__res
                 mu[k] = k == 0 ? u[0] : prev + exp(u[k]);
                 prev = mu[k];
                 lpi[k] = lg[k] - lz;
-                lp += log_normal(mu[k], 0.0, lmu) + lpi[k];
+                lp += log_normal(mu[k], 0.0, lmu, imu) + lpi[k];
                 if (k >= 1) lp += u[k];
             } else {
                 mu[k] = 0.0;
@@ -271,7 +301,7 @@ __global__ __launch_bounds__(kPropThreads) void gmm_is_kernel(const float *__res
 #pragma unroll
         for (int m = 0; m < 8; ++m) {
             double a = lmix[m];
-            for (int k = 0; k < d; ++k) a += log_normal(u[k], mean[m * d + k], lsdv[m * d + k]);
+            for (int k = 0; k < d; ++k) a += log_normal(u[k], mean[m * d + k], lsdv[m * d + k], isdv[m * d + k]);
             t[m] = a;
             tm = fmax(tm, a);
         }

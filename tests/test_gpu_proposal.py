@@ -9,8 +9,12 @@ What is compared (same seeds, the oracle computing everything itself):
     oracle's BF16 emulation: relative 2-norm error <= 1e-3 per tensor;
   - one Adam step: moments within the gradient tolerance, updates within
     1e-3 lr where the gradient is well away from zero;
-  - mixture-proposal and mixture-prior importance sampling (FP64): discrete
-    draws bit-exact, latents 1e-12, log-weights 1e-10 mixed, log Z-hat 1e-9;
+  - polynomial mixture-proposal importance sampling (FP64): discrete draws
+    bit-exact, latents 1e-12, log-weights 1e-10 mixed, log Z-hat 1e-9;
+  - mixture-model importance sampling (FP64 draws and densities, FP32
+    likelihood): latents 1e-12, log-weights and log Z-hat 1e-5 mixed (the FP32
+    class; the FP32 per-datum error is about 1e-6 and the 16-datum FP32 block
+    sums add a few 1e-6, far inside it);
   - amortised inference: the data summaries 1e-10, the decoded proposal 1e-4.
 Training itself is checked by a falling loss, bit-identical results with and
 without graph replay, and the gain over the prior proposal on the 1000-point
@@ -302,9 +306,9 @@ def test_gmm_is_matches_oracle(ppl, pr, K, prop):
         from oracle import gmm_init
         state = gmm_init(seed, 0, K, N)
         assert mixed_err(lat.cpu().numpy(), state) <= 1e-12
-    assert mixed_err(lw.cpu().numpy(), lwo) <= 1e-10
+    assert mixed_err(lw.cpu().numpy(), lwo) <= 1e-5
     logz = lse(lwo) - math.log(N)
-    assert abs(sc[0].item() - logz) <= 1e-9 * max(1.0, abs(logz))
+    assert abs(sc[0].item() - logz) <= 1e-5 * max(1.0, abs(logz))
 
 
 # ---------------------------------------------------------- amortised run --
