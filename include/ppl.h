@@ -249,7 +249,7 @@ typedef struct ppl_instance {
  * particles_per_lane P in {1,2,4,8}; wgs_per_instance W = 512-thread
  * workgroups that hold one instance (W * 512 * P >= max N_i, W <= 64);
  * spec_block = largest number of factors advanced between synchronisations
- * (1..128).  Results are the SMC of each instance for any valid choice; the
+ * (1..256).  Results are the SMC of each instance for any valid choice; the
  * choice only changes the order of the FP64 sums behind the resampling
  * trigger (so a decision within rounding of the threshold may differ). */
 typedef struct ppl_tune {

@@ -43,7 +43,7 @@ constexpr int kBtThreads = 512;
 constexpr int kBtWaves = kBtThreads / 64;
 constexpr int kBtMaxInst = 1024;
 constexpr int kBtMaxTeams = 256;
-constexpr int kBtMaxB = 128;                  // largest speculative block
+constexpr int kBtMaxB = 256;                  // largest speculative block
 constexpr int kBtMaxW = 64;                   // largest team
 constexpr int kBtStage = 8192;                // prefix sums staged for the ancestor search
 constexpr int kBtNF = 16;                     // state floats per particle (2 K, K <= 8)
@@ -294,7 +294,7 @@ __global__ __launch_bounds__(kBtThreads) void smc_batched_kernel(BtDev a) {
                     ml = fmaxf(ml, lw[p]);
                     nan_seen |= isnan(lw[p]) ? 1 : 0;
                 }
-                const float mw = wave_max(ml);
+                const float mw = wave_max_dpp(ml);
                 float s1 = 0.0f, s2 = 0.0f;
                 if (mw > -INFINITY) {
 #pragma unroll
@@ -304,12 +304,9 @@ __global__ __launch_bounds__(kBtThreads) void smc_batched_kernel(BtDev a) {
                         s2 = fmaf(e, e, s2);
                     }
                 }
-#pragma unroll
-                for (int o = 32; o > 0; o >>= 1) {
-                    s1 += __shfl_xor(s1, o, 64);
-                    s2 += __shfl_xor(s2, o, 64);
-                }
-                if (wave_or(nan_seen)) s1 = NAN;      // a NaN log-weight poisons the factor's statistics
+                s1 = wave_sum_dpp(s1);
+                s2 = wave_sum_dpp(s2);
+                if (__ballot(nan_seen != 0)) s1 = NAN;   // a NaN log-weight poisons the factor's statistics
                 if (lane == 0) {
                     wpart[t][wave][0] = mw;
                     wpart[t][wave][1] = s1;

@@ -104,6 +104,35 @@ __device__ __forceinline__ float wave_max(float v) {
     for (int o = 32; o > 0; o >>= 1) v = fmaxf(v, __shfl_xor(v, o, 64));
     return v;
 }
+// Wave-wide FP32 reductions through DPP row operations (full-rate VALU
+// moves, no LDS permute): two quad permutations, the half-row and row
+// mirrors, then the row-15 and row-31 broadcasts (rows left out of a
+// broadcast keep the identity), which leave the total in lane 63; one
+// v_readlane returns it to every lane.  All 64 lanes must be active.
+template <int CTRL, int ROWS>
+__device__ __forceinline__ float dpp_f32(float v, float identity) {
+    return __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(__builtin_bit_cast(int, identity),
+                                                                 __builtin_bit_cast(int, v), CTRL, ROWS, 0xF, false));
+}
+__device__ __forceinline__ float wave_max_dpp(float v) {
+    const float id = -INFINITY;
+    v = fmaxf(v, dpp_f32<0xB1, 0xF>(v, id));    // quad_perm [1,0,3,2]
+    v = fmaxf(v, dpp_f32<0x4E, 0xF>(v, id));    // quad_perm [2,3,0,1]
+    v = fmaxf(v, dpp_f32<0x141, 0xF>(v, id));   // row_half_mirror
+    v = fmaxf(v, dpp_f32<0x140, 0xF>(v, id));   // row_mirror
+    v = fmaxf(v, dpp_f32<0x142, 0xA>(v, id));   // row_bcast15 into rows 1, 3
+    v = fmaxf(v, dpp_f32<0x143, 0xC>(v, id));   // row_bcast31 into rows 2, 3
+    return __builtin_bit_cast(float, __builtin_amdgcn_readlane(__builtin_bit_cast(int, v), 63));
+}
+__device__ __forceinline__ float wave_sum_dpp(float v) {
+    v += dpp_f32<0xB1, 0xF>(v, 0.0f);
+    v += dpp_f32<0x4E, 0xF>(v, 0.0f);
+    v += dpp_f32<0x141, 0xF>(v, 0.0f);
+    v += dpp_f32<0x140, 0xF>(v, 0.0f);
+    v += dpp_f32<0x142, 0xA>(v, 0.0f);
+    v += dpp_f32<0x143, 0xC>(v, 0.0f);
+    return __builtin_bit_cast(float, __builtin_amdgcn_readlane(__builtin_bit_cast(int, v), 63));
+}
 __device__ __forceinline__ int wave_or(int v) {
 #pragma unroll
     for (int o = 32; o > 0; o >>= 1) v |= __shfl_xor(v, o, 64);

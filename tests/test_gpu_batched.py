@@ -104,7 +104,7 @@ SPECS = [(5, 150, 4096), (1, 40, 3000), (8, 200, 5000), (3, 1, 1000), (6, 0, 204
          (4, 400, 8192), (7, 33, 700), (5, 260, 4096), (3, 90, 1500)]
 
 
-@pytest.mark.parametrize("tune", [None, (4, 0, 64, 0), (2, 0, 16, 0), (1, 0, 128, 0), (8, 0, 1, 0)])
+@pytest.mark.parametrize("tune", [None, (4, 0, 64, 0), (2, 0, 16, 0), (1, 0, 128, 0), (4, 0, 256, 0), (8, 0, 1, 0)])
 def test_batched_parity_with_oracle(ppl, orc, tune):
     batch = make_batch(SPECS)
     seed = 21
