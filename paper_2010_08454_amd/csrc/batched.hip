@@ -129,27 +129,82 @@ struct BtGmm {
             st[8 + k] = mu_sd * z[k];
         }
     }
-    // log sum_k pi_k N(y; mu_k, sd), shifted by the largest term.  The
-    // exponentials and the logarithm are the hardware's (v_exp_f32 /
-    // v_log_f32, about 1 ulp); their error is far below the FP32 rounding of
-    // the log-weight sum over the data.
-    __device__ static float factor(const float st[kBtNF], int K, float inv_sd, float lconst, float ys) {
-        float t[8], mx = -INFINITY;
+};
+
+// log sum_k pi_k N(y; mu_k, sd), shifted by the largest term, for a
+// compile-time component count KK (fully unrolled: no per-component branch
+// and no padding of the term array).  The exponentials and the logarithm are
+// the hardware's (v_exp_f32 / v_log_f32, about 1 ulp); their error is far
+// below the FP32 rounding of the log-weight sum over the data.
+template <int KK>
+__device__ __forceinline__ float bt_factor(const float st[kBtNF], float inv_sd, float lconst, float ys) {
+    float t[KK];
 #pragma unroll
-        for (int k = 0; k < 8; ++k) {
-            if (k < K) {
-                const float r = (ys - st[8 + k]) * inv_sd;
-                t[k] = fmaf(-0.5f * r, r, st[k]);
-                mx = fmaxf(mx, t[k]);
+    for (int k = 0; k < KK; ++k) {
+        const float r = (ys - st[8 + k]) * inv_sd;
+        t[k] = fmaf(-0.5f * r, r, st[k]);
+    }
+    float mx = t[0];
+#pragma unroll
+    for (int k = 1; k < KK; ++k) mx = fmaxf(mx, t[k]);
+    float s = 0.0f;
+#pragma unroll
+    for (int k = 0; k < KK; ++k) s += __expf(t[k] - mx);
+    return lconst + mx + __logf(s);
+}
+
+// One speculative block: advance every particle's log-weight over the tb
+// data in ybuf and record, per factor, the wave's {max, s1, s2} of the
+// log-weights in wpart (a NaN log-weight poisons s1).
+template <int P, int KK>
+__device__ __forceinline__ void bt_block_factors(const float (&st)[P][kBtNF], const bool (&valid)[P], float (&lw)[P],
+                                                 const float *ybuf, int tb, float inv_sd, float lconst,
+                                                 float (*wpart)[kBtWaves][3], int wave, int lane) {
+    for (int t = 0; t < tb; ++t) {
+        const float ys = ybuf[t];
+        float ml = -INFINITY;
+        int nan_seen = 0;
+#pragma unroll
+        for (int p = 0; p < P; ++p) {
+            const float f = bt_factor<KK>(st[p], inv_sd, lconst, ys);
+            if (valid[p]) lw[p] += f;
+            ml = fmaxf(ml, lw[p]);
+            nan_seen |= isnan(lw[p]) ? 1 : 0;
+        }
+        const float mw = wave_max_dpp(ml);
+        float s1 = 0.0f, s2 = 0.0f;
+        if (mw > -INFINITY) {
+#pragma unroll
+            for (int p = 0; p < P; ++p) {
+                const float e = __expf(lw[p] - mw);
+                s1 += e;
+                s2 = fmaf(e, e, s2);
             }
         }
-        float s = 0.0f;
-#pragma unroll
-        for (int k = 0; k < 8; ++k)
-            if (k < K) s += __expf(t[k] - mx);
-        return lconst + mx + __logf(s);
+        s1 = wave_sum_dpp(s1);
+        s2 = wave_sum_dpp(s2);
+        if (__ballot(nan_seen != 0)) s1 = NAN;
+        if (lane == 0) {
+            wpart[t][wave][0] = mw;
+            wpart[t][wave][1] = s1;
+            wpart[t][wave][2] = s2;
+        }
     }
-};
+}
+
+// Recompute the log-weights over the block's first nt data (after a rollback).
+template <int P, int KK>
+__device__ __forceinline__ void bt_block_redo(const float (&st)[P][kBtNF], const bool (&valid)[P], float (&lw)[P],
+                                              const float *ybuf, int nt, float inv_sd, float lconst) {
+    for (int t = 0; t < nt; ++t) {
+        const float ys = ybuf[t];
+#pragma unroll
+        for (int p = 0; p < P; ++p) {
+            const float f = bt_factor<KK>(st[p], inv_sd, lconst, ys);
+            if (valid[p]) lw[p] += f;
+        }
+    }
+}
 
 // --------------------------------------------------------- LDS helpers ----
 __device__ __forceinline__ float bt_block_max(float v, float *lds) {
@@ -283,35 +338,12 @@ __global__ __launch_bounds__(kBtThreads) void smc_batched_kernel(BtDev a) {
             float *s_lw0 = (float *)s_anc;
 #pragma unroll
             for (int p = 0; p < P; ++p) s_lw0[threadIdx.x * P + p] = lw[p];
-            for (int t = 0; t < tb; ++t) {
-                const float ys = ybuf[t];
-                float ml = -INFINITY;
-                int nan_seen = 0;
-#pragma unroll
-                for (int p = 0; p < P; ++p) {
-                    const float f = BtGmm::factor(st[p], K, inv_sd, lconst, ys);
-                    if (valid[p]) lw[p] += f;
-                    ml = fmaxf(ml, lw[p]);
-                    nan_seen |= isnan(lw[p]) ? 1 : 0;
-                }
-                const float mw = wave_max_dpp(ml);
-                float s1 = 0.0f, s2 = 0.0f;
-                if (mw > -INFINITY) {
-#pragma unroll
-                    for (int p = 0; p < P; ++p) {
-                        const float e = __expf(lw[p] - mw);
-                        s1 += e;
-                        s2 = fmaf(e, e, s2);
-                    }
-                }
-                s1 = wave_sum_dpp(s1);
-                s2 = wave_sum_dpp(s2);
-                if (__ballot(nan_seen != 0)) s1 = NAN;   // a NaN log-weight poisons the factor's statistics
-                if (lane == 0) {
-                    wpart[t][wave][0] = mw;
-                    wpart[t][wave][1] = s1;
-                    wpart[t][wave][2] = s2;
-                }
+            switch (K) {   // the component count is the same for every thread of the team
+#define PPL_BT_CASE(KK) \
+                case KK: bt_block_factors<P, KK>(st, valid, lw, ybuf, tb, inv_sd, lconst, wpart, wave, lane); break;
+                PPL_BT_CASE(1) PPL_BT_CASE(2) PPL_BT_CASE(3) PPL_BT_CASE(4)
+                PPL_BT_CASE(5) PPL_BT_CASE(6) PPL_BT_CASE(7) PPL_BT_CASE(8)
+#undef PPL_BT_CASE
             }
             __syncthreads();
             // workgroup partial per factor: merge the waves in order
@@ -376,13 +408,12 @@ __global__ __launch_bounds__(kBtThreads) void smc_batched_kernel(BtDev a) {
             if (tf < tb - 1) {
 #pragma unroll
                 for (int p = 0; p < P; ++p) lw[p] = s_lw0[threadIdx.x * P + p];
-                for (int t = 0; t <= tf; ++t) {
-                    const float ys = ybuf[t];
-#pragma unroll
-                    for (int p = 0; p < P; ++p) {
-                        const float f = BtGmm::factor(st[p], K, inv_sd, lconst, ys);
-                        if (valid[p]) lw[p] += f;
-                    }
+                switch (K) {
+#define PPL_BT_CASE(KK) \
+                    case KK: bt_block_redo<P, KK>(st, valid, lw, ybuf, tf + 1, inv_sd, lconst); break;
+                    PPL_BT_CASE(1) PPL_BT_CASE(2) PPL_BT_CASE(3) PPL_BT_CASE(4)
+                    PPL_BT_CASE(5) PPL_BT_CASE(6) PPL_BT_CASE(7) PPL_BT_CASE(8)
+#undef PPL_BT_CASE
                 }
             }
             // ---- resampling at factor s = t0 + tf
