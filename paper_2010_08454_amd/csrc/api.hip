@@ -328,7 +328,7 @@ namespace {
 // Candidate configurations the autotuner times (the workspace covers them all).
 const ppl_tune kCandidates[] = {
     {4, 0, 64, 0}, {4, 0, 128, 0}, {4, 0, 256, 0}, {2, 0, 64, 0}, {2, 0, 128, 0}, {8, 0, 64, 0}, {8, 0, 128, 0},
-    {1, 0, 64, 0}, {4, 0, 16, 0},
+    {8, 0, 256, 0}, {1, 0, 64, 0}, {4, 0, 16, 0},
 };
 constexpr int kNumCandidates = sizeof(kCandidates) / sizeof(kCandidates[0]);
 
