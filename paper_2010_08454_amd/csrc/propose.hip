@@ -179,35 +179,29 @@ __global__ __launch_bounds__(kPropThreads) void poly_mix_is_kernel(
 // --------------------------------------------------------------- GMM --
 // One datum's log-factor, log sum_k pi_k Normal(y; mu_k, sd), in FP32 with the
 // max shift and the hardware exp and log, as in the batched mixture SMC;
-// c[k] = log pi_k - log(sd sqrt(2 pi)).
-__device__ __forceinline__ float gmm_point(float y, int K, const float (&c)[8], const float (&mu)[8], float inv_sd) {
-    float t[8], mx = -INFINITY;
+// c[k] = log pi_k - log(sd sqrt(2 pi)).  KK components, fully unrolled.
+template <int KK>
+__device__ __forceinline__ float gmm_point(float y, const float (&c)[8], const float (&mu)[8], float inv_sd) {
+    float t[KK];
 #pragma unroll
-    for (int k = 0; k < 8; ++k) {
-        if (k < K) {
-            const float r = (y - mu[k]) * inv_sd;
-            t[k] = fmaf(-0.5f * r, r, c[k]);
-            mx = fmaxf(mx, t[k]);
-        }
+    for (int k = 0; k < KK; ++k) {
+        const float r = (y - mu[k]) * inv_sd;
+        t[k] = fmaf(-0.5f * r, r, c[k]);
     }
+    float mx = t[0];
+#pragma unroll
+    for (int k = 1; k < KK; ++k) mx = fmaxf(mx, t[k]);
     float s = 0.0f;
 #pragma unroll
-    for (int k = 0; k < 8; ++k)
-        if (k < K) s += __expf(t[k] - mx);
+    for (int k = 0; k < KK; ++k) s += __expf(t[k] - mx);
     return mx + __logf(s);
 }
 
 // Sum of the log-factors over the data: FP32 within blocks of 16 points (one
 // batch of scalar loads each), FP64 across blocks.
-__device__ __forceinline__ double gmm_loglik(const float *__restrict__ Y, int D, int K, const double (&lpi)[8],
-                                             const double (&mu)[8], double inv_sd, double cst) {
-    float c[8], muf[8];
-#pragma unroll
-    for (int k = 0; k < 8; ++k) {
-        c[k] = k < K ? (float)(lpi[k] + cst) : 0.0f;
-        muf[k] = k < K ? (float)mu[k] : 0.0f;
-    }
-    const float isd = (float)inv_sd;
+template <int KK>
+__device__ __forceinline__ double gmm_loglik(const float *__restrict__ Y, int D, const float (&c)[8],
+                                             const float (&mu)[8], float isd) {
     double ll = 0.0;
     int d = 0;
     for (; d + 16 <= D; d += 16) {
@@ -216,15 +210,37 @@ __device__ __forceinline__ double gmm_loglik(const float *__restrict__ Y, int D,
         for (int k = 0; k < 16; ++k) ys[k] = Y[d + k];
         float sb = 0.0f;
 #pragma unroll 4
-        for (int k = 0; k < 16; ++k) sb += gmm_point(ys[k], K, c, muf, isd);
+        for (int k = 0; k < 16; ++k) sb += gmm_point<KK>(ys[k], c, mu, isd);
         ll += (double)sb;
     }
     if (d < D) {
         float sb = 0.0f;
-        for (; d < D; ++d) sb += gmm_point(Y[d], K, c, muf, isd);
+        for (; d < D; ++d) sb += gmm_point<KK>(Y[d], c, mu, isd);
         ll += (double)sb;
     }
     return ll;
+}
+
+// The likelihood for the run's component count K (the same for every thread).
+__device__ __forceinline__ double gmm_loglik_k(const float *__restrict__ Y, int D, int K, const double (&lpi)[8],
+                                               const double (&mu)[8], double inv_sd, double cst) {
+    float c[8], muf[8];
+#pragma unroll
+    for (int k = 0; k < 8; ++k) {
+        c[k] = k < K ? (float)(lpi[k] + cst) : 0.0f;
+        muf[k] = k < K ? (float)mu[k] : 0.0f;
+    }
+    const float isd = (float)inv_sd;
+    switch (K) {
+        case 1: return gmm_loglik<1>(Y, D, c, muf, isd);
+        case 2: return gmm_loglik<2>(Y, D, c, muf, isd);
+        case 3: return gmm_loglik<3>(Y, D, c, muf, isd);
+        case 4: return gmm_loglik<4>(Y, D, c, muf, isd);
+        case 5: return gmm_loglik<5>(Y, D, c, muf, isd);
+        case 6: return gmm_loglik<6>(Y, D, c, muf, isd);
+        case 7: return gmm_loglik<7>(Y, D, c, muf, isd);
+        default: return gmm_loglik<8>(Y, D, c, muf, isd);
+    }
 }
 
 template <bool PROP>
@@ -311,7 +327,7 @@ __global__ __launch_bounds__(kPropThreads) void gmm_is_kernel(const float *__res
         extra = lp - (tm + log(ts));
     }
     const double cst = -kHalfLog2PiD - log(comp_sd);
-    const double ll = gmm_loglik(Y, D, K, lpi, mu, 1.0 / comp_sd, cst);
+    const double ll = gmm_loglik_k(Y, D, K, lpi, mu, 1.0 / comp_sd, cst);
     const double lw = live ? ll + extra : -INFINITY;
     if (live) {
         if (lw_out) lw_out[i] = lw;
