@@ -208,7 +208,7 @@ __device__ __forceinline__ void bt_block_redo(const float (&st)[P][kBtNF], const
 
 // --------------------------------------------------------- LDS helpers ----
 __device__ __forceinline__ float bt_block_max(float v, float *lds) {
-    v = wave_max(v);
+    v = wave_max_dpp(v);
     if ((threadIdx.x & 63) == 0) lds[threadIdx.x >> 6] = v;
     __syncthreads();
     float m = lds[0];
@@ -219,8 +219,8 @@ __device__ __forceinline__ float bt_block_max(float v, float *lds) {
 }
 
 __device__ __forceinline__ void bt_block_sum2(double &u, double &v, double *lds) {
-    u = wave_sum(u);
-    v = wave_sum(v);
+    u = wave_sum_dpp(u);
+    v = wave_sum_dpp(v);
     if ((threadIdx.x & 63) == 0) {
         lds[threadIdx.x >> 6] = u;
         lds[kBtWaves + (threadIdx.x >> 6)] = v;

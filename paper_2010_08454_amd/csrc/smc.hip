@@ -191,7 +191,7 @@ __device__ __noinline__ double exp_f64(double v) { return exp(v); }
 
 // ------------------------------------------------------ block helpers --
 __device__ __forceinline__ float block_max_f32(float v, float *lds) {
-    v = wave_max(v);
+    v = wave_max_dpp(v);
     if ((threadIdx.x & 63) == 0) lds[threadIdx.x >> 6] = v;
     __syncthreads();
     float m = lds[0];
@@ -202,7 +202,7 @@ __device__ __forceinline__ float block_max_f32(float v, float *lds) {
 }
 
 __device__ __forceinline__ double block_sum_f64(double v, double *lds) {
-    v = wave_sum(v);
+    v = wave_sum_dpp(v);
     if ((threadIdx.x & 63) == 0) lds[threadIdx.x >> 6] = v;
     __syncthreads();
     double s = 0.0;
@@ -214,8 +214,8 @@ __device__ __forceinline__ double block_sum_f64(double v, double *lds) {
 
 // Two sums in one pass (lds holds 2 * kSmcWaves doubles).
 __device__ __forceinline__ void block_sum2_f64(double &u, double &v, double *lds) {
-    u = wave_sum(u);
-    v = wave_sum(v);
+    u = wave_sum_dpp(u);
+    v = wave_sum_dpp(v);
     if ((threadIdx.x & 63) == 0) {
         lds[threadIdx.x >> 6] = u;
         lds[kSmcWaves + (threadIdx.x >> 6)] = v;
