@@ -262,7 +262,6 @@ __device__ __forceinline__ uint64_t bt_block_exscan(uint64_t v, uint64_t *lds, u
 // ---------------------------------------------------------------- kernel --
 template <int P>
 __global__ __launch_bounds__(kBtThreads) void smc_batched_kernel(BtDev a) {
-    __shared__ float ldsf[kBtWaves];
     __shared__ double ldsd[2 * kBtWaves];
     __shared__ uint64_t ldsu[kBtWaves];
     __shared__ float ybuf[kBtMaxB];
