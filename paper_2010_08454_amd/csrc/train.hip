@@ -204,7 +204,17 @@ __global__ __launch_bounds__(256) void adam_kernel(MlpView w, SplitParts sp, con
         const float *p = sp.p[l];
         const int64_t sz = (int64_t)in * out;
         gv = 0.0f;
-        for (int c = 0; c < sp.nc[l]; ++c) gv += p[(size_t)c * sz + local];
+        // loads in groups of four, the adds in the same order as one at a time
+        int c = 0;
+        for (; c + 4 <= sp.nc[l]; c += 4) {
+            const float x0 = p[(size_t)c * sz + local], x1 = p[(size_t)(c + 1) * sz + local];
+            const float x2 = p[(size_t)(c + 2) * sz + local], x3 = p[(size_t)(c + 3) * sz + local];
+            gv += x0;
+            gv += x1;
+            gv += x2;
+            gv += x3;
+        }
+        for (; c < sp.nc[l]; ++c) gv += p[(size_t)c * sz + local];
     } else {
         gv = bgrad[l * 256 + (int)(local - (int64_t)in * out)];
     }
