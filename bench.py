@@ -15,6 +15,15 @@ Printed as one JSON line, with
                   1 FMA square-accumulate);
   cpu_baseline -- the CPU oracle on a bounded sample of the same workload.
 
+Other configurations print the same fields for their own workload:
+  poly, poly-paper  polynomial fit IS (FP64), 10^4 and 2 x 10^6 particles
+  lgssm             bootstrap SMC on the linear-Gaussian state space model
+  gmm-batched       batched SMC over 256 mixture instances (autotuned first)
+  resample-gather   resampling fused with the state gather, roofline against HBM
+  proposal-poly/gmm ESS/s of the learned proposal at fixed log-evidence error
+  proposal-train    simulated training pairs per second (MFMA rate with --no-graph)
+  peaks             measured instruction and copy rates (not a hot-path line)
+
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu]
                        [--config blr|poly|poly-paper|lgssm|gmm-batched|resample-gather|proposal-poly|
                                  proposal-gmm|proposal-train|peaks]
