@@ -5,8 +5,9 @@
 // names as future work, Sec. 6, over the sample/factor semantics of Sec. 3.4).
 //
 // Mapping.  The grid (one 512-thread workgroup per CU: each wave then has 256
-// registers, so the particle state and the speculative-block bookkeeping stay
-// out of scratch memory) is split into teams of W workgroups; a team holds one
+// registers, so with up to four particles per lane the particle state and the
+// speculative-block bookkeeping stay out of scratch memory; eight per lane
+// spill some of it) is split into teams of W workgroups; a team holds one
 // instance at a time (slots j = w * 512 P + thread * P + p, P particles per
 // thread, state in registers) and walks a list
 // of instances assigned on the host by longest-processing-time-first, so the

@@ -3,7 +3,9 @@
 // in place of the prior, and prior importance sampling of the mixture model.
 // Each particle draws its latents from q (Philox tag 1), and its log-weight is
 // log p(latents) + log L(latents) - log q(latents); the block partials and the
-// finalize step are those of the prior importance sampler.  FP64 throughout.
+// finalize step are those of the prior importance sampler.  FP64 throughout,
+// except the mixture model's likelihood: FP32 per datum (hardware exp and
+// log), summed in FP32 within 16-datum blocks and in FP64 across them.
 //
 // Proposal parameter blocks (FP64, device):
 //   POLY (degrees 2..5): lognl[4], logmix[8], mean[4][8][5], lsd[4][8][5];

@@ -1,5 +1,6 @@
 // resample.hip -- FP64 log-sum-exp / ESS normaliser, integer-rule systematic
-// resampling and the raw Philox stream entry.
+// resampling, resampling fused with the gather of structure-of-arrays state,
+// and the raw Philox stream entry.
 //
 // The normaliser is the weight normalisation of importance sampling (paper
 // Sec. 3.6.2); resampling between factors is the particle-based inference the
