@@ -184,6 +184,20 @@ def cpu_baseline_lgssm(y, seed, target_s=15.0):
             "kind": "oracle", "sample": f"{n} of the 2^20 particles over all {y.size} steps, FP64 oracle, {dt:.1f} s"}
 
 
+def code_hash(sources):
+    """SHA-256 of the sources with their comments removed: counter summaries
+    stay valid across comment edits and go stale on any change to the code."""
+    import hashlib
+    import re
+    h = hashlib.sha256()
+    for src in sources:
+        text = open(os.path.join(ROOT, src)).read()
+        text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+        text = re.sub(r"//[^\n]*", "", text)
+        h.update("\n".join(ln.rstrip() for ln in text.splitlines() if ln.strip()).encode())
+    return h.hexdigest()
+
+
 def measured_traffic(config):
     """HBM bytes per launch from the committed rocprofv3 PMC summary of the
     configuration's dominant kernel, or None when there is none or the kernel's
@@ -200,10 +214,7 @@ def measured_traffic(config):
         if ":" in ln and not ln.startswith("#"):
             k, v = ln.split(":", 1)
             kv[k.strip()] = v.strip()
-    h = hashlib.sha256()
-    for s in sources:
-        h.update(open(os.path.join(ROOT, s), "rb").read())
-    if kv.get("source_sha256") != h.hexdigest():
+    if kv.get("source_sha256") != code_hash(sources):
         return None
     try:
         return int(float(kv["fetch_bytes_per_launch"]) + float(kv["write_bytes_per_launch"]))
