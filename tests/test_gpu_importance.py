@@ -71,8 +71,8 @@ def run_poly(ppl, dev, x, y, n, seed):
     return res, lw.cpu().numpy(), lat.cpu().numpy(), summ.cpu().numpy(), scal.cpu().numpy()
 
 
-# (2^21 + 77 particles: more than 8192 block partials, so the two-level merge runs)
-@pytest.mark.parametrize("n,D", [(10_000, 100), (1, 100), (1037, 37), (300, 1), ((1 << 21) + 77, 100)])
+# (2^21 + 77 particles: more than 2048 block partials, so the two-level merge runs)
+@pytest.mark.parametrize("n,D", [(10_000, 100), (1, 100), (1037, 37), (300, 1), (100_000, 100), ((1 << 21) + 77, 100)])
 def test_poly_parity(ppl, orc, dev, n, D):
     x, y = synthetic.poly_data(D=D)
     seed = 1
