@@ -520,7 +520,25 @@ __global__ __launch_bounds__(kSmcThreads) void smc_persistent_kernel(SmcDev a) {
                 const uint64_t tau = (uint64_t)j * Sq + th.quo;
                 int anc;
                 if (staged) {
+                    // The thread's first slot searches the whole staged range.  Later
+                    // slots gallop from the previous slot's ancestor (ancestors do
+                    // not decrease with the slot and are usually a few entries
+                    // apart) and finish with a binary search: the same index as a
+                    // plain binary search, with fewer dependent LDS loads.
                     int lo = prev - a_lo, hi = span - 1;
+                    if (p > 0 && lo < hi) {
+                        if (stage[lo] > tau) {
+                            hi = lo;
+                        } else {
+                            int step = 1;
+                            while (lo + step < hi && !(stage[lo + step] > tau)) {
+                                lo += step;
+                                step <<= 1;
+                            }
+                            hi = min(lo + step, hi);
+                            ++lo;
+                        }
+                    }
                     while (lo < hi) {
                         const int mid = (lo + hi) >> 1;
                         if (stage[mid] > tau) hi = mid; else lo = mid + 1;
