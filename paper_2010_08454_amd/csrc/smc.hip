@@ -25,7 +25,7 @@
 //      prefix sums in LDS, and every slot binary-searches its ancestor there
 //      and gathers the ancestor's state; lw = 0.
 // The grid barrier counts arrivals on one cache line and publishes the epoch
-// on another, and spins a bounded number of times: if a wait exceeds the limit, the block
+// on another.  Its spin is bounded: if a wait exceeds the limit, the block
 // raises the abort flag and every block leaves its loop at its next barrier,
 // so the grid always drains.
 #include <math.h>
