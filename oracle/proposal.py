@@ -36,11 +36,15 @@ TAG_INIT = 5
 
 
 def bf16(x):
-    """Round to FP32, then to BF16 with round-to-nearest-even; returns float64."""
+    """Round to FP32, then to BF16 with round-to-nearest-even; returns float64.
+    A NaN stays a NaN (IEEE conversion of a NaN gives a NaN; carrying its low
+    bits into the exponent would turn it into an infinity or a zero)."""
     f = np.ascontiguousarray(x, dtype=np.float32)
     u = f.view(np.uint32).astype(np.uint64)
     u = ((u + 0x7FFF + ((u >> 16) & 1)) >> 16) << 16
-    return u.astype(np.uint32).view(np.float32).astype(np.float64)
+    with np.errstate(invalid="ignore"):
+        r = u.astype(np.uint32).view(np.float32).astype(np.float64)
+    return np.where(np.isnan(f), np.nan, r)
 
 
 def _round(x, on):

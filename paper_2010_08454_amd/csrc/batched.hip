@@ -67,7 +67,7 @@ struct BtDev {
     int32_t *anc_out;        // [max_events * sum N], instance i at max_events * P_i as [max_events][N_i]
     int64_t max_events;
     unsigned *bar;          // [1 + teams] lines: line 0 word 1 = abort flag; line 1 + t = team t counter
-    double *part;            // [teams][W][Bmax][3]
+    double *part;            // [teams][2][W][Bmax][3]: two copies, picked by barrier-epoch parity
     uint64_t *tot;           // [teams][W]
     double *esum;            // [teams][W]
     double *fin;             // [teams][W][2]
@@ -283,7 +283,13 @@ __global__ __launch_bounds__(kBtThreads) void smc_batched_kernel(BtDev a) {
     unsigned epoch = 0;
     bool alive = true;
 
-    double *tpart = a.part + (size_t)team * W * a.Bmax * 3;
+    // Per-factor partials have two copies, used alternately by consecutive block
+    // barriers (copy = parity of the barrier epoch the writes precede).  After a
+    // committed block a workgroup writes the next block's partials while a
+    // slower one may still be merging this block's; the copies keep them apart.
+    // Reuse of a copy is two barriers later, which every workgroup has passed
+    // only after all merges of the earlier block are done.
+    double *tpart2 = a.part + (size_t)team * 2 * W * a.Bmax * 3;
     uint64_t *ttot = a.tot + (size_t)team * W;
     double *tesum = a.esum + (size_t)team * W;
     double *tfin = a.fin + (size_t)team * W * 2;
@@ -347,6 +353,7 @@ __global__ __launch_bounds__(kBtThreads) void smc_batched_kernel(BtDev a) {
             }
             __syncthreads();
             // workgroup partial per factor: merge the waves in order
+            double *tpart = tpart2 + (size_t)((epoch + 1) & 1) * W * a.Bmax * 3;
             for (int t = threadIdx.x; t < tb; t += kBtThreads) {
                 float m = -INFINITY;
                 for (int w = 0; w < kBtWaves; ++w) m = fmaxf(m, wpart[t][w][0]);
@@ -628,7 +635,7 @@ static BtLayout bt_layout(void *ws, int teams, int W, int Bmax, int64_t cap) {
     size_t o = 0;
     auto take = [&](size_t n) { char *r = p + o; o += align_up(n, 256); return r; };
     L.bar = (unsigned *)take((size_t)kBtBarLine * (1 + teams) * sizeof(unsigned));
-    L.part = (double *)take((size_t)teams * W * Bmax * 3 * sizeof(double));
+    L.part = (double *)take((size_t)teams * 2 * W * Bmax * 3 * sizeof(double));
     L.esum = (double *)take((size_t)teams * W * sizeof(double));
     L.fin = (double *)take((size_t)teams * W * 2 * sizeof(double));
     L.tot = (uint64_t *)take((size_t)teams * W * sizeof(uint64_t));

@@ -227,3 +227,145 @@ def test_adam_with_a_constant_gradient_moves_lr_per_step(pr):
         p, m, v = pr.adam(p, g, m, v, t, lr=lr, eps=eps)
         for pk, gk in zip(p, g):
             np.testing.assert_allclose(pk, -t * lr * gk / (np.abs(gk) + eps), rtol=1e-10)
+
+
+def test_bf16_rounding_matches_torch(pr):
+    """The oracle's BF16 rounding (round to nearest, ties to even, applied where
+    the GPU stores BF16) against torch's float32 -> bfloat16 conversion on the
+    CPU: random values over the whole exponent range, exact halfway cases with
+    an even and an odd kept bit, values just either side of a halfway point,
+    subnormals, overflow to infinity, signed zeros, infinities and NaNs."""
+    import torch
+    g = np.random.default_rng(17)
+    bits = [g.integers(0, 2 ** 32, size=200_000, dtype=np.uint64).astype(np.uint32)]
+    kept = g.integers(0, 2 ** 16, size=4000, dtype=np.uint64).astype(np.uint32) << 16
+    for low in (0x8000, 0x7FFF, 0x8001, 0x0000, 0xFFFF):      # halfway, just below, just above, exact, top
+        bits.append(kept | np.uint32(low))
+    specials = [0x00000000, 0x80000000, 0x7F800000, 0xFF800000, 0x7FC00000, 0xFFC00000, 0x7FFFFFFF,
+                0x7F800001, 0x00000001, 0x00008000, 0x00018000, 0x007FFFFF, 0x00800000, 0x7F7FFFFF,
+                0x7F7F8000, 0x7F7F7FFF, 0xFF7FFFFF, 0x3F808000, 0x3F818000, 0x3F7FFFFF]
+    bits.append(np.array(specials, dtype=np.uint32))
+    f = np.concatenate(bits).view(np.float32)
+    ours = pr.bf16(f)
+    ref = torch.from_numpy(f.copy()).to(torch.bfloat16).to(torch.float64).numpy()
+    nan = np.isnan(ref)
+    assert np.array_equal(np.isnan(ours), nan)
+    assert np.array_equal(ours[~nan], ref[~nan])
+    assert np.array_equal(np.signbit(ours[~nan]), np.signbit(ref[~nan]))       # -0 stays -0
+
+
+def _box_muller(w1, w2):
+    """Single-precision-stream uniforms ((w >> 9) + 1/2) 2^-23 and the textbook
+    Box-Muller pair (written here from its definition, not taken from the oracle)."""
+    u1 = ((np.asarray(w1, np.uint64) >> 9).astype(np.float64) + 0.5) * 2.0 ** -23
+    u2 = ((np.asarray(w2, np.uint64) >> 9).astype(np.float64) + 0.5) * 2.0 ** -23
+    r = np.sqrt(-2.0 * np.log(u1))
+    return r * np.cos(2 * np.pi * u2), r * np.sin(2 * np.pi * u2)
+
+
+def _u01(w):
+    return ((np.asarray(w, np.uint64) >> 9).astype(np.float64) + 0.5) * 2.0 ** -23
+
+
+def _words(orc, seed, i, blocks, step):
+    ctr = np.zeros((len(blocks), 4), dtype=np.uint32)
+    ctr[:, 0] = i
+    ctr[:, 1] = blocks
+    ctr[:, 2] = step
+    ctr[:, 3] = 4                      # training-simulation tag
+    return orc.philox(ctr, seed)
+
+
+def _rebuild_poly_pair(orc, seed, step, i, D, sd=10.0, noise_sd=1.0):
+    """Data of one simulated polynomial pair from its stream words: block 0 word 0
+    gives the degree, blocks 1-2 the coefficient normals, block 8 + e the points
+    2e, 2e + 1 (x = 2u - 1 from words 0, 1; noise from the Box-Muller pair of
+    words 2, 3)."""
+    w0 = _words(orc, seed, i, [0, 1, 2], step)
+    n = 2 + int((int(w0[0, 0]) * 4) >> 32)
+    z = []
+    for b in (1, 2):
+        for (a, c) in ((0, 1), (2, 3)):
+            z0, z1 = _box_muller(w0[b, a], w0[b, c])
+            z += [float(z0), float(z1)]
+    c = sd * np.array(z[:5])
+    ne = (D + 1) // 2
+    wd = _words(orc, seed, i, 8 + np.arange(ne), step)
+    x = (2.0 * _u01(wd[:, :2]) - 1.0).ravel()[:D]
+    e0, e1 = _box_muller(wd[:, 2], wd[:, 3])
+    eps = np.stack([e0, e1], axis=1).ravel()[:D]
+    mean = np.polynomial.polynomial.polyval(x, c[:n])
+    return n, c, x, mean + noise_sd * eps, eps
+
+
+def test_poly_simulator_data_rebuilt_from_the_stream(orc, pr):
+    """The simulator's data (x, y) is what its documented word table says: the
+    summaries of data rebuilt here from the Philox words (independently of the
+    oracle's simulator) equal the summaries the simulator returns, and over many
+    pairs x is uniform on [-1, 1] and the residuals (y - poly(x)) / noise_sd are
+    standard normal."""
+    seed, step, D, B = 23, 7, 9, 40
+    th, S = pr.sim_poly(seed, step, 0, B, D=D)
+    xs, res = [], []
+    for i in range(B):
+        n, c, x, y, eps = _rebuild_poly_pair(orc, seed, step, i, D)
+        assert th[i, 0] == n
+        assert np.allclose(th[i, 1:1 + n], c[:n], rtol=1e-13, atol=1e-13)
+        assert np.all(th[i, 1 + n:] == 0.0)
+        s = pr.summary_poly(x, y)
+        assert np.max(np.abs(s - S[i]) / np.maximum(1.0, np.abs(S[i]))) < 1e-12, i
+        xs.append(x)
+        res.append(y - np.polynomial.polynomial.polyval(x, c[:n]))
+    # distributions over a larger draw (no summaries needed)
+    big_x, big_r = [], []
+    for i in range(B, B + 60):
+        n, c, x, y, eps = _rebuild_poly_pair(orc, seed, step, i, 200)
+        big_x.append(x)
+        big_r.append(y - np.polynomial.polynomial.polyval(x, c[:n]))
+    big_x, big_r = np.concatenate(big_x), np.concatenate(big_r)
+    assert stats.kstest((big_x + 1) / 2, "uniform").pvalue > 1e-3
+    assert stats.kstest(big_r / 1.0, "norm").pvalue > 1e-3
+
+
+def test_gmm_simulator_data_rebuilt_from_the_stream(orc, pr):
+    """The mixture simulator: blocks 0-1 give Exp(1) draws (pi = E / sum E),
+    blocks 2-3 the component means, block 8 + e the components of points 2e,
+    2e + 1 (categorical on pi from words 0, 1) and their noise (words 2, 3).
+    Summaries of the rebuilt data equal the simulator's; its ordered latents are
+    those of the rebuilt parameters; components follow pi (chi-square) and the
+    residuals are standard normal (KS)."""
+    seed, step, D, K, B = 31, 4, 50, 5, 30
+    U, S = pr.sim_gmm(seed, step, 0, B, D=D, K=K)
+    comp_counts, comp_exp, resid = np.zeros(K), np.zeros(K), []
+    for i in range(B + 200):
+        w = _words(orc, seed, i, [0, 1, 2, 3], step)
+        E = -np.log(_u01(np.concatenate([w[0], w[1]])[:K]))
+        pi = E / E.sum()
+        z = []
+        for b in (2, 3):
+            for (a, c) in ((0, 1), (2, 3)):
+                z0, z1 = _box_muller(w[b, a], w[b, c])
+                z += [float(z0), float(z1)]
+        mu = 5.0 * np.array(z[:K])
+        Dn = D if i < B else 200
+        wd = _words(orc, seed, i, 8 + np.arange((Dn + 1) // 2), step)
+        uc = _u01(wd[:, :2]).ravel()[:Dn]
+        cum = np.cumsum(pi)
+        k = np.minimum(np.searchsorted(cum, uc, side="right"), K - 1)   # first k with u < C_k
+        e0, e1 = _box_muller(wd[:, 2], wd[:, 3])
+        eps = np.stack([e0, e1], axis=1).ravel()[:Dn]
+        y = mu[k] + eps
+        if i < B:
+            s = pr.summary_gmm(y)
+            assert np.max(np.abs(s - S[i]) / np.maximum(1.0, np.abs(S[i]))) < 1e-12, i
+            o = np.argsort(mu, kind="stable")
+            ref = np.concatenate([[mu[o[0]]], np.log(np.diff(mu[o])), np.log(pi[o[:-1]]) - np.log(pi[o[-1]])])
+            assert np.allclose(U[i], ref, rtol=1e-12, atol=1e-12), i
+        else:
+            comp_counts += np.bincount(k, minlength=K)
+            comp_exp += pi * Dn
+            resid.append(y - mu[k])
+    # per-dataset weights differ, so compare the pooled counts with their pooled expectation
+    chi2 = float(np.sum((comp_counts - comp_exp) ** 2 / comp_exp))
+    assert stats.chi2.sf(chi2, K - 1) > 1e-4
+    assert stats.kstest(np.concatenate(resid), "norm").pvalue > 1e-3
