@@ -68,6 +68,7 @@ def lib():
                              P, P, P, P, P, P, P, P]
         L.or_smc.restype = ctypes.c_int
         L.or_num_threads.restype = ctypes.c_int
+        L.or_set_num_threads.argtypes = [ctypes.c_int]
         _lib = L
     return _lib
 
@@ -82,6 +83,11 @@ def _f64(a):
 
 def num_threads():
     return lib().or_num_threads()
+
+
+def set_num_threads(n):
+    """Host threads of the oracle's particle loops (n < 1: all available)."""
+    lib().or_set_num_threads(int(n))
 
 
 # ------------------------------------------------------------------ streams --

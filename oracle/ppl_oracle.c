@@ -944,3 +944,14 @@ int or_num_threads(void)
     return 1;
 #endif
 }
+
+/* Host threads for the particle loops of later calls (n < 1: all available). */
+void or_set_num_threads(int n)
+{
+#ifdef _OPENMP
+    if (n < 1) n = omp_get_num_procs();
+    omp_set_num_threads(n);
+#else
+    (void)n;
+#endif
+}
