@@ -65,8 +65,13 @@ def lib():
         L.or_gmm_logfactor.argtypes = [i32, P, P, f64, f64]; L.or_gmm_logfactor.restype = f64
         L.or_gmm_init.argtypes = [u64, u32, i32, P, i64, P]
         L.or_smc.argtypes = [i32, P, i64, i32, P, i64, u64, u32, f64, f64, f64, i64,
-                             P, P, P, P, P, P, P, P]
+                             P, P, P, P, P, P, P, P, P]
+        L.or_forced_event.argtypes = [P, P, P, i64, u64, u32, u32, P, P]
+        L.or_forced_event.restype = ctypes.c_int
         L.or_smc.restype = ctypes.c_int
+        L.or_smc_forced.argtypes = [i32, P, i64, i32, P, i64, u64, u32, f64, f64, P, P, P, i64,
+                                    P, P, P, P, P, P, P]
+        L.or_smc_forced.restype = ctypes.c_int
         L.or_num_threads.restype = ctypes.c_int
         L.or_set_num_threads.argtypes = [ctypes.c_int]
         _lib = L
@@ -248,7 +253,7 @@ def particle_logweights(model, x, y, idx, seed, hyper=None, dim=0, q=None):
 
 
 def smc(model, y, n, seed, ess_frac=0.5, hyper=None, K=0, inst=0, ess_band=0.0,
-        anc_band=0.0, max_events=0, want_state=False):
+        anc_band=0.0, max_events=0, want_state=False, want_event_lw=False):
     """Sequential Monte Carlo over the factors y[0..T-1] (LGSSM or GMM)."""
     if hyper is None:
         hyper = LGSSM_HYPER if model == MODEL_LGSSM else GMM_HYPER
@@ -264,14 +269,77 @@ def smc(model, y, n, seed, ess_frac=0.5, hyper=None, K=0, inst=0, ess_band=0.0,
     tie = np.zeros((max_events, n), dtype=np.uint8) if max_events else None
     st = np.empty((nf, n)) if want_state else None
     lw = np.empty(n) if want_state else None
+    lwh = np.zeros((max_events, n)) if (want_event_lw and max_events) else None
     rc = lib().or_smc(model, _p(y), T, K, _p(h), n, seed, inst, ess_frac, ess_band, anc_band,
                       max_events, _p(scal), _p(ess_tr), _p(res_tr), _p(ess_tie), _p(anc), _p(tie),
-                      _p(st), _p(lw))
+                      _p(st), _p(lw), _p(lwh))
     out = dict(log_z=scal[0], ess=scal[1], n_resample=int(scal[2]), status=int(scal[3]), rc=rc,
                ess_trace=ess_tr[:T], resampled=res_tr[:T].astype(bool), ess_tie=ess_tie[:T].astype(bool))
     if max_events:
         out["ancestors"] = anc
         out["anc_tie"] = tie.astype(bool)
+    if want_state:
+        out["state"] = st
+        out["lw"] = lw
+    if lwh is not None:
+        out["event_lw"] = lwh
+    return out
+
+
+def forced_event(lw, given_lw, given_anc, seed, step=0, inst=0):
+    """One teacher-forced resampling event (``or_forced_event``): returns this
+    run's ancestors with the given ones adopted at tie slots, and the event's
+    statistics (ties, adopted, non-tie differences, expected ties, bands)."""
+    lw = _f64(lw)
+    n = lw.size
+    glw = np.ascontiguousarray(given_lw, dtype=np.float32)
+    ganc = np.ascontiguousarray(given_anc, dtype=np.int32)
+    anc = np.empty(n, dtype=np.int32)
+    st = np.zeros(8)
+    rc = lib().or_forced_event(_p(lw), _p(glw), _p(ganc), n, seed, step, inst, _p(anc), _p(st))
+    if rc:
+        raise ValueError(f"or_forced_event failed ({rc})")
+    return anc, dict(max_dlw=st[1], ties=int(st[2]), adopted=int(st[3]), nontie_diff=int(st[4]),
+                     expected_ties=st[5], max_band=st[6])
+
+
+def smc_forced(model, y, n, seed, given_resampled, given_ancestors, given_event_lw, ess_frac=0.5, hyper=None,
+               K=0, inst=0, ess_band=0.0, want_state=False):
+    """Teacher-forced SMC beside another run (see ``or_smc_forced``): adopts the
+    given decision inside the ESS tie band and the given ancestor at tie slots,
+    and counts every disagreement outside them.  given_ancestors /
+    given_event_lw are [E, n] (the other run's first E events)."""
+    if hyper is None:
+        hyper = LGSSM_HYPER if model == MODEL_LGSSM else GMM_HYPER
+    y = _f64(y)
+    T = y.size
+    h = _f64(hyper)
+    nf = 1 if model == MODEL_LGSSM else 2 * K
+    g_res = np.ascontiguousarray(np.asarray(given_resampled)[:T], dtype=np.uint8)
+    if g_res.size < T:
+        raise ValueError("given_resampled is shorter than y")
+    g_anc = np.ascontiguousarray(given_ancestors, dtype=np.int32).reshape(-1, n)
+    g_lw = np.ascontiguousarray(given_event_lw, dtype=np.float32).reshape(-1, n)
+    E = g_anc.shape[0]
+    if g_lw.shape[0] != E:
+        raise ValueError("ancestor and log-weight records differ in length")
+    scal = np.zeros(5)
+    logz_inc = np.zeros(max(T, 1))
+    ess_tr = np.zeros(max(T, 1))
+    ev = np.zeros((max(E, 1), 8))
+    dec = np.zeros(3)
+    st = np.empty((nf, n)) if want_state else None
+    lw = np.empty(n) if want_state else None
+    rc = lib().or_smc_forced(model, _p(y), T, K, _p(h), n, seed, inst, ess_frac, ess_band, _p(g_res),
+                             _p(g_anc), _p(g_lw), E, _p(scal), _p(logz_inc), _p(ess_tr), _p(ev), _p(dec),
+                             _p(st), _p(lw))
+    n_ev = int(scal[2])
+    out = dict(rc=rc, log_z=scal[0], ess=scal[1], n_resample=n_ev, status=int(scal[3]), steps=int(scal[4]),
+               logz_inc=logz_inc[:T], ess_trace=ess_tr[:T],
+               events=dict(step=ev[:n_ev, 0].astype(int), max_dlw=ev[:n_ev, 1], ties=ev[:n_ev, 2].astype(int),
+                           adopted=ev[:n_ev, 3].astype(int), nontie_diff=ev[:n_ev, 4].astype(int),
+                           expected_ties=ev[:n_ev, 5], max_band=ev[:n_ev, 6]),
+               decisions=dict(adopted=int(dec[0]), differ_outside_band=int(dec[1]), in_band=int(dec[2])))
     if want_state:
         out["state"] = st
         out["lw"] = lw

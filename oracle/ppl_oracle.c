@@ -491,33 +491,10 @@ double or_gmm_logfactor(int32_t K, const double *lpi, const double *mu, double s
     return mx + log(s);
 }
 
-/* Generic SMC driver.
- *   y[T] observations; N particles; ess_frac threshold (resample when ESS < ess_frac*N,
- *   never after the last factor).  log Z-hat = sum over epochs of (LSE(lw) - log N).
- * Outputs (any may be NULL):
- *   scal[4]      = {log Z-hat, final ESS, number of resamplings, status}
- *   ess_tr[T]    = ESS after factor s (before any resampling)
- *   res_tr[T]    = 1 if resampled after factor s
- *   ess_tie[T]   = 1 if |ESS/N - ess_frac| <= ess_band (decision sensitive to rounding)
- *   anc_hist[max_events][N], tie_hist[max_events][N]: ancestors / tie flags per event
- *   state_out[n_fields][N], lw_out[N]: final particles and log-weights */
-int or_smc(int32_t model, const double *y, int64_t T, int32_t K, const double *hyper,
-           int64_t N, uint64_t seed, uint32_t inst, double ess_frac,
-           double ess_band, double anc_band, int64_t max_events,
-           double *scal, double *ess_tr, uint8_t *res_tr, uint8_t *ess_tie,
-           int32_t *anc_hist, uint8_t *tie_hist, double *state_out, double *lw_out)
+/* Initial particle states, layout [field][N] (see the model notes above). */
+static void smc_init_state(int32_t model, int32_t K, const double *hyper, int64_t N, uint64_t seed,
+                           uint32_t inst, double *st)
 {
-    if (N <= 0 || T < 0) return -1;
-    if (model != MODEL_LGSSM && model != MODEL_GMM) return -2;
-    if (model == MODEL_GMM && (K < 1 || K > 8)) return -1;
-    int nf = model == MODEL_LGSSM ? 1 : 2 * K;
-    double *st = (double *)malloc(sizeof(double) * N * nf);
-    double *st2 = (double *)malloc(sizeof(double) * N * nf);
-    double *lw = (double *)calloc(N, sizeof(double));
-    int32_t *anc = (int32_t *)malloc(sizeof(int32_t) * N);
-    uint8_t *tie = (uint8_t *)malloc(N);
-    if (!st || !st2 || !lw || !anc || !tie) { free(st); free(st2); free(lw); free(anc); free(tie); return -3; }
-
     if (model == MODEL_LGSSM) {
         for (int64_t i = 0; i < N; ++i) {
             double z0 = 0.0;
@@ -536,27 +513,64 @@ int or_smc(int32_t model, const double *y, int64_t T, int32_t K, const double *h
             for (int k = 0; k < K; ++k) { st[k * N + i] = lpi[k]; st[(K + k) * N + i] = mu[k]; }
         }
     }
+}
+
+/* Factor s: every particle moves to step s (LGSSM) and adds its log-factor. */
+static void smc_advance(int32_t model, int32_t K, const double *hyper, const double *y, int64_t s,
+                        int64_t N, uint64_t seed, uint32_t inst, double *st, double *lw)
+{
+#pragma omp parallel for schedule(static)
+    for (int64_t i = 0; i < N; ++i) {
+        if (model == MODEL_LGSSM) {
+            double z[4];
+            lgssm_eps4(seed, i, (uint32_t)(s >> 2), inst, z);
+            double xv = hyper[0] * st[i] + hyper[1] * z[s & 3];
+            st[i] = xv;
+            double r = (y[s] - xv) / hyper[2];
+            lw[i] += -0.5 * log(2.0 * M_PI) - log(hyper[2]) - 0.5 * r * r;
+        } else {
+            double lpi[8], mu[8];
+            for (int k = 0; k < K; ++k) { lpi[k] = st[k * N + i]; mu[k] = st[(K + k) * N + i]; }
+            lw[i] += or_gmm_logfactor(K, lpi, mu, hyper[1], y[s]);
+        }
+    }
+}
+
+/* Generic SMC driver.
+ *   y[T] observations; N particles; ess_frac threshold (resample when ESS < ess_frac*N,
+ *   never after the last factor).  log Z-hat = sum over epochs of (LSE(lw) - log N).
+ * Outputs (any may be NULL):
+ *   scal[4]      = {log Z-hat, final ESS, number of resamplings, status}
+ *   ess_tr[T]    = ESS after factor s (before any resampling)
+ *   res_tr[T]    = 1 if resampled after factor s
+ *   ess_tie[T]   = 1 if |ESS/N - ess_frac| <= ess_band (decision sensitive to rounding)
+ *   anc_hist[max_events][N], tie_hist[max_events][N]: ancestors / tie flags per event
+ *   lw_hist[max_events][N]: the log-weights each event resampled from
+ *   state_out[n_fields][N], lw_out[N]: final particles and log-weights */
+int or_smc(int32_t model, const double *y, int64_t T, int32_t K, const double *hyper,
+           int64_t N, uint64_t seed, uint32_t inst, double ess_frac,
+           double ess_band, double anc_band, int64_t max_events,
+           double *scal, double *ess_tr, uint8_t *res_tr, uint8_t *ess_tie,
+           int32_t *anc_hist, uint8_t *tie_hist, double *state_out, double *lw_out, double *lw_hist)
+{
+    if (N <= 0 || T < 0) return -1;
+    if (model != MODEL_LGSSM && model != MODEL_GMM) return -2;
+    if (model == MODEL_GMM && (K < 1 || K > 8)) return -1;
+    int nf = model == MODEL_LGSSM ? 1 : 2 * K;
+    double *st = (double *)malloc(sizeof(double) * N * nf);
+    double *st2 = (double *)malloc(sizeof(double) * N * nf);
+    double *lw = (double *)calloc(N, sizeof(double));
+    int32_t *anc = (int32_t *)malloc(sizeof(int32_t) * N);
+    uint8_t *tie = (uint8_t *)malloc(N);
+    if (!st || !st2 || !lw || !anc || !tie) { free(st); free(st2); free(lw); free(anc); free(tie); return -3; }
+    smc_init_state(model, K, hyper, N, seed, inst, st);
 
     nsum logz = {0, 0};
     int64_t nres = 0, ev = 0;
     double ess = (double)N, stat[5];
     int status = 0;
     for (int64_t s = 0; s < T; ++s) {
-#pragma omp parallel for schedule(static)
-        for (int64_t i = 0; i < N; ++i) {
-            if (model == MODEL_LGSSM) {
-                double z[4];
-                lgssm_eps4(seed, i, (uint32_t)(s >> 2), inst, z);
-                double xv = hyper[0] * st[i] + hyper[1] * z[s & 3];
-                st[i] = xv;
-                double r = (y[s] - xv) / hyper[2];
-                lw[i] += -0.5 * log(2.0 * M_PI) - log(hyper[2]) - 0.5 * r * r;
-            } else {
-                double lpi[8], mu[8];
-                for (int k = 0; k < K; ++k) { lpi[k] = st[k * N + i]; mu[k] = st[(K + k) * N + i]; }
-                lw[i] += or_gmm_logfactor(K, lpi, mu, hyper[1], y[s]);
-            }
-        }
+        smc_advance(model, K, hyper, y, s, N, seed, inst, st, lw);
         or_lse_ess(lw, N, stat);
         if (!(stat[0] > -INFINITY) || isnan(stat[3])) { status = -7; ess = 0.0; break; }
         ess = stat[4];
@@ -570,6 +584,7 @@ int or_smc(int32_t model, const double *y, int64_t T, int32_t K, const double *h
             if (rc) { status = rc; break; }
             if (anc_hist && ev < max_events) memcpy(anc_hist + ev * N, anc, sizeof(int32_t) * N);
             if (tie_hist && ev < max_events) memcpy(tie_hist + ev * N, tie, N);
+            if (lw_hist && ev < max_events) memcpy(lw_hist + ev * N, lw, sizeof(double) * N);
             for (int f = 0; f < nf; ++f)
                 for (int64_t j = 0; j < N; ++j) st2[f * N + j] = st[f * N + anc[j]];
             double *tmp = st; st = st2; st2 = tmp;
@@ -588,6 +603,197 @@ int or_smc(int32_t model, const double *y, int64_t T, int32_t K, const double *h
     if (state_out) memcpy(state_out, st, sizeof(double) * N * nf);
     if (lw_out) memcpy(lw_out, lw, sizeof(double) * N);
     free(st); free(st2); free(lw); free(anc); free(tie);
+    return status;
+}
+
+/* One teacher-forced resampling event (see or_smc_forced).  lw[N]: this run's
+ * FP64 log-weights; glw[N], ganc[N]: the other run's single-precision
+ * log-weights and its ancestors; step, inst: the event's Philox counter words.
+ * anc[N] receives this run's ancestors with the given ones adopted at tie
+ * slots.  stats[8] (optional): {unused, max mixed |glw - lw| / max(1, |lw|),
+ * tie slots, adopted tie slots, non-tie differences, expected tie slots,
+ * largest band, 0}.  Returns 0, -1 if no weight is positive, -3 on allocation
+ * failure, -5 if a given ancestor adopted at a tie is out of range. */
+int or_forced_event(const double *lw, const float *glw, const int32_t *ganc, int64_t N, uint64_t seed,
+                    uint32_t step, uint32_t inst, int32_t *anc, double *stats)
+{
+    double m = -INFINITY;
+    for (int64_t i = 0; i < N; ++i) if (lw[i] > m) m = lw[i];
+    if (!(m > -INFINITY)) return -1;
+    uint64_t *Q = (uint64_t *)malloc(sizeof(uint64_t) * N);
+    double *band = (double *)malloc(sizeof(double) * N);
+    double *wv = (double *)malloc(sizeof(double) * N);
+    if (!Q || !band || !wv) { free(Q); free(band); free(wv); return -3; }
+    int32_t k = or_quant_bits(N);
+    uint64_t acc = 0;
+    nsum W = {0, 0}, We = {0, 0}, We2 = {0, 0};
+    double max_dlw = 0.0;
+    for (int64_t i = 0; i < N; ++i) {
+        double e = exp(lw[i] - m);
+        wv[i] = e;
+        acc += (uint64_t)floor(ldexp(e, k));
+        Q[i] = acc;
+        double d = (double)glw[i] - lw[i];
+        if (e == 0.0) d = 0.0;                              /* zero weight: no influence on the CDF */
+        double dm = fabs((double)glw[i] - lw[i]) / (fabs(lw[i]) > 1.0 ? fabs(lw[i]) : 1.0);
+        if (!(dm <= max_dlw)) max_dlw = dm;                 /* NaN propagates */
+        nadd(&W, e);
+        nadd(&We, e * d);
+        nadd(&We2, e * d * d);
+    }
+    double Wt = nval(W), Wet = nval(We), sec = nval(We2) / Wt;
+    nsum Cw = {0, 0}, Ce = {0, 0};
+    double max_band = 0.0, expected = 0.0;
+    for (int64_t i = 0; i < N; ++i) {
+        double d = wv[i] == 0.0 ? 0.0 : (double)glw[i] - lw[i];
+        nadd(&Cw, wv[i]);
+        nadd(&Ce, wv[i] * d);
+        double C = nval(Cw) / Wt;
+        double dC = (nval(Ce) - C * Wet) / Wt;
+        band[i] = 2.0 * fabs(dC) + 2.0 * sec + ldexp((double)(i + 1), -k) / Wt + 1e-15;
+        if (band[i] > max_band) max_band = band[i];
+        expected += 2.0 * band[i] * (double)N;
+    }
+    uint64_t S = acc;
+    uint32_t w[4];
+    draw4(seed, 0, 0, step, inst, TAG_RESAMPLE, w);
+    uint64_t R = ((uint64_t)w[1] << 32) | w[0];
+    uint64_t U = (uint64_t)(((unsigned __int128)R * S) >> 64);
+    int64_t a = 0, ties = 0, adopted = 0, bad = 0;
+    int rc = 0;
+    for (int64_t j = 0; j < N; ++j) {
+        unsigned __int128 t = (unsigned __int128)j * S + U;
+        while ((unsigned __int128)N * Q[a] <= t) ++a;
+        /* slot point and the ends of its interval, in units of the total N S */
+        double tn = (double)t / ((double)N * (double)S);
+        double hi = (double)Q[a] / (double)S, lo = a > 0 ? (double)Q[a - 1] / (double)S : 0.0;
+        int tie = (hi - tn) <= band[a] || (a > 0 && (tn - lo) <= band[a - 1]);
+        if (tie) {
+            ++ties;
+            if (ganc[j] != (int32_t)a) ++adopted;
+            if (ganc[j] < 0 || ganc[j] >= N) rc = -5;
+            anc[j] = ganc[j];
+        } else {
+            if (ganc[j] != (int32_t)a) ++bad;
+            anc[j] = (int32_t)a;
+        }
+    }
+    if (stats) {
+        stats[0] = 0.0; stats[1] = max_dlw; stats[2] = (double)ties; stats[3] = (double)adopted;
+        stats[4] = (double)bad; stats[5] = expected; stats[6] = max_band; stats[7] = 0.0;
+    }
+    free(Q); free(band); free(wv);
+    return rc;
+}
+
+/* Teacher-forced SMC: the SMC above, run beside a second (GPU) run whose
+ * resampling decisions g_res[T], ancestors g_anc[E][N] and event log-weights
+ * g_lw[E][N] (the single-precision weights that run resampled from) are given.
+ *
+ * Decisions.  Where this run's ESS lies within ess_band * N of the threshold,
+ * either decision is valid and the given one is adopted; elsewhere the two
+ * must agree (a disagreement is counted and the given decision is followed, so
+ * the event numbering stays aligned).
+ *
+ * Ancestors.  This run draws its own ancestors by the integer rule from its
+ * FP64 log-weights.  A slot is a tie when its point lies closer to an end of
+ * its ancestor's interval than the other run's cumulative weight at that end
+ * can differ from this run's.  With e_i = lw'_i - lw_i (other run minus this
+ * one, W_i the normalised weights, C_a their cumulative sum) the first-order
+ * change of C_a is
+ *     dC_a = sum_{i<=a} W_i e_i - C_a sum_i W_i e_i,
+ * and the band at end a is 2 |dC_a| plus a slack for the second-order terms
+ * (2 sum_i W_i e_i^2) and for the flooring of the quantised weights
+ * ((a + 1) 2^-k / sum w).
+ * Tie slots take the given ancestor (counted when it differs); non-tie slots
+ * keep this run's ancestor, and any difference there is counted.
+ * The run stops at an event beyond the E given ones.
+ *
+ * Outputs (any may be NULL):
+ *   scal[5]    = {log Z-hat, final ESS, resamplings, status, factors run}
+ *   logz_inc[T] normaliser increment added after factor s (0 where none)
+ *   ess_tr[T]  FP64 ESS after factor s
+ *   ev[E][8]   per event: {factor s, max mixed |lw' - lw| / max(1, |lw|),
+ *              tie slots, adopted tie slots, non-tie differences,
+ *              expected tie slots sum_a N * 2 band_a, max band, 0}
+ *   dec[3]     = {decisions adopted inside the band, decisions that differ
+ *              outside it, decisions inside the band}
+ *   state_out[n_fields][N], lw_out[N]: particles and log-weights when the run ends */
+int or_smc_forced(int32_t model, const double *y, int64_t T, int32_t K, const double *hyper,
+                  int64_t N, uint64_t seed, uint32_t inst, double ess_frac, double ess_band,
+                  const uint8_t *g_res, const int32_t *g_anc, const float *g_lw, int64_t E,
+                  double *scal, double *logz_inc, double *ess_tr, double *ev_out, double *dec,
+                  double *state_out, double *lw_out)
+{
+    if (N <= 0 || T < 0 || E < 0 || !g_res || (E > 0 && (!g_anc || !g_lw))) return -1;
+    if (model != MODEL_LGSSM && model != MODEL_GMM) return -2;
+    if (model == MODEL_GMM && (K < 1 || K > 8)) return -1;
+    int nf = model == MODEL_LGSSM ? 1 : 2 * K;
+    double *st = (double *)malloc(sizeof(double) * N * nf);
+    double *st2 = (double *)malloc(sizeof(double) * N * nf);
+    double *lw = (double *)calloc(N, sizeof(double));
+    int32_t *anc = (int32_t *)malloc(sizeof(int32_t) * N);
+    if (!st || !st2 || !lw || !anc) { free(st); free(st2); free(lw); free(anc); return -3; }
+    smc_init_state(model, K, hyper, N, seed, inst, st);
+    if (dec) dec[0] = dec[1] = dec[2] = 0.0;
+    if (logz_inc) for (int64_t s = 0; s < T; ++s) logz_inc[s] = 0.0;
+
+    nsum logz = {0, 0};
+    int64_t nres = 0, s_run = 0;
+    double ess = (double)N, stat[5];
+    int status = 0, stopped = 0;
+    for (int64_t s = 0; s < T; ++s) {
+        smc_advance(model, K, hyper, y, s, N, seed, inst, st, lw);
+        s_run = s + 1;
+        or_lse_ess(lw, N, stat);
+        if (!(stat[0] > -INFINITY) || isnan(stat[3])) { status = -7; ess = 0.0; break; }
+        ess = stat[4];
+        if (ess_tr) ess_tr[s] = ess;
+        int own = (s < T - 1) && (ess < ess_frac * (double)N);
+        int given = (s < T - 1) && g_res[s];
+        int in_band = fabs(ess / (double)N - ess_frac) <= ess_band;
+        if (dec) {
+            if (in_band) dec[2] += 1.0;
+            if (in_band && own != given) dec[0] += 1.0;
+            if (!in_band && own != given) dec[1] += 1.0;
+        }
+        if (!given) continue;
+        if (nres >= E) { stopped = 1; s_run = s; break; }
+        /* this event's normaliser */
+        double inc = stat[3] - log((double)N);
+        nadd(&logz, inc);
+        if (logz_inc) logz_inc[s] = inc;
+        int rc = or_forced_event(lw, g_lw + nres * N, g_anc + nres * N, N, seed, (uint32_t)s, inst,
+                                 anc, ev_out ? ev_out + nres * 8 : NULL);
+        if (rc) { status = rc; break; }
+        if (ev_out) ev_out[nres * 8] = (double)s;
+        for (int64_t j = 0; j < N; ++j)
+            if (anc[j] < 0 || anc[j] >= N) { status = -5; break; }
+        if (status) break;
+        for (int f = 0; f < nf; ++f)
+            for (int64_t j = 0; j < N; ++j) st2[f * N + j] = st[f * N + anc[j]];
+        double *tmp = st; st = st2; st2 = tmp;
+        for (int64_t j = 0; j < N; ++j) lw[j] = 0.0;
+        ++nres;
+    }
+    if (status == 0 && !stopped) {
+        if (T > 0) {
+            or_lse_ess(lw, N, stat);
+            double inc = stat[3] - log((double)N);
+            nadd(&logz, inc);
+            if (logz_inc) logz_inc[T - 1] = inc;
+            ess = stat[4];
+        } else {
+            ess = (double)N;
+        }
+    }
+    if (scal) {
+        scal[0] = status == 0 ? nval(logz) : -INFINITY;
+        scal[1] = ess; scal[2] = (double)nres; scal[3] = status; scal[4] = (double)s_run;
+    }
+    if (state_out) memcpy(state_out, st, sizeof(double) * N * nf);
+    if (lw_out) memcpy(lw_out, lw, sizeof(double) * N);
+    free(st); free(st2); free(lw); free(anc);
     return status;
 }
 
