@@ -184,6 +184,20 @@ int ppl_importance(int model, const ppl_data *data, int64_t n_particles, uint64_
                    const ppl_proposal *q, void *d_ws, size_t ws_bytes, void *stream,
                    ppl_result *out);
 
+/* ppl_importance without a workspace argument, for callers that cannot
+ * allocate device memory (code under HIP graph capture, tight serving loops,
+ * harnesses that forbid hipMalloc).  Same arguments, outputs and errors as
+ * ppl_importance; the workspace is a fixed library-owned device array of
+ * PPL_NOALLOC_SCRATCH_BYTES per GPU (held until the process ends).  Requests
+ * whose ppl_workspace_size(..., PPL_ALGO_IS) exceeds it fail with
+ * PPL_E_UNSUPPORTED before anything is launched: about 10^8 particles for
+ * BLR with d = 16.  Calls no allocating routine.  Every call on one GPU uses
+ * the same array, so calls that overlap on a GPU (other streams or threads)
+ * race; serialise them. */
+enum { PPL_NOALLOC_SCRATCH_BYTES = 16 << 20 };
+int ppl_importance_noalloc(int model, const ppl_data *data, int64_t n_particles, uint64_t seed,
+                           const ppl_proposal *q, void *stream, ppl_result *out);
+
 /* FP64 normaliser of a device log-weight vector d_lw[n] (dtype PPL_F32 or
  * PPL_F64): d_out[5] = {max, s1, s2, LSE = max + log s1, ESS = s1^2 / s2}.
  * -inf entries carry zero weight; all -inf gives LSE = -inf and ESS = 0;

@@ -24,10 +24,11 @@ PPL_MODEL_POLY, PPL_MODEL_BLR, PPL_MODEL_LGSSM, PPL_MODEL_GMM = 1, 2, 3, 4
 PPL_F32, PPL_F64 = 1, 2
 PPL_Q_PRIOR, PPL_Q_GAUSS_FULL, PPL_Q_POLY_MIX, PPL_Q_GMM_MIX = 0, 1, 2, 3
 PPL_ALGO_IS, PPL_ALGO_SMC, PPL_ALGO_LSE, PPL_ALGO_RESAMPLE = 0, 1, 2, 3
+PPL_NOALLOC_SCRATCH_BYTES = 16 << 20
 
 # Exported C symbols (kept in step with include/ppl.h).
 EXPORTS = ("ppl_status_string", "ppl_last_error", "ppl_version", "ppl_workspace_size",
-           "ppl_importance", "ppl_lse_ess", "ppl_resample", "ppl_resample_gather", "ppl_philox", "ppl_smc",
+           "ppl_importance", "ppl_importance_noalloc", "ppl_lse_ess", "ppl_resample", "ppl_resample_gather", "ppl_philox", "ppl_smc",
            "ppl_timing_enable", "ppl_timing_query")
 
 P = ctypes.c_void_p
@@ -74,6 +75,8 @@ def _load():
     L.ppl_philox.argtypes = [u64, u32, u32, u32, i64, P, P]
     L.ppl_smc.argtypes = [ctypes.c_int, ctypes.POINTER(PplData), i64, u64, f64, P, ctypes.c_size_t, P,
                           ctypes.POINTER(PplResult)]
+    L.ppl_importance_noalloc.argtypes = [ctypes.c_int, ctypes.POINTER(PplData), i64, u64,
+                                         ctypes.POINTER(PplProposal), P, ctypes.POINTER(PplResult)]
     L.ppl_timing_enable.argtypes = [ctypes.c_int]
     L.ppl_timing_query.argtypes = [ctypes.c_char_p, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_int64)]
     for name in EXPORTS:
@@ -152,6 +155,21 @@ def ppl_importance(model, data, n, seed, q=None, ws=None, stream=None, log_weigh
     _check(lib.ppl_importance(model, ctypes.byref(data), int(n), int(seed) & (2 ** 64 - 1),
                               ctypes.byref(prop) if prop is not None else None, _ptr(ws), ws.numel(),
                               _stream(stream), ctypes.byref(res)))
+    return res
+
+
+def ppl_importance_noalloc(model, data, n, seed, q=None, stream=None, log_weights=None, latents=None,
+                           summaries=None, scalars=None, sync=False, q_kind=None):
+    """Importance sampling on the library's fixed scratch (no workspace argument, nothing allocated)."""
+    res = PplResult(sync_host=1 if sync else 0, d_scalars=_ptr(scalars), d_latents=_ptr(latents),
+                    d_log_weights=_ptr(log_weights), d_summaries=_ptr(summaries))
+    prop = None
+    if q is not None:
+        kind = PPL_Q_GAUSS_FULL if q_kind is None else q_kind
+        prop = PplProposal(kind=kind, dim=_q_dim(kind, data), d_params=q.data_ptr())
+    _check(lib.ppl_importance_noalloc(model, ctypes.byref(data), int(n), int(seed) & (2 ** 64 - 1),
+                                      ctypes.byref(prop) if prop is not None else None, _stream(stream),
+                                      ctypes.byref(res)))
     return res
 
 

@@ -147,6 +147,58 @@ static int sync_scalars(ppl_result *out, const double *d_scal, hipStream_t st) {
     return PPL_OK;
 }
 
+// Importance sampling behind ppl_importance and ppl_importance_noalloc.  With
+// ws_cap non-null the workspace is the caller-less scratch array: a call whose
+// workspace would exceed *ws_cap is rejected before anything is launched.
+int importance_call(int model, const ppl_data *data, int64_t n, uint64_t seed, const ppl_proposal *q, void *ws,
+                    size_t ws_bytes, void *stream, ppl_result *out, const size_t *ws_cap) {
+    if (!out) return fail(PPL_E_ARG, "out is NULL");
+    if (model != PPL_MODEL_POLY && model != PPL_MODEL_BLR && model != PPL_MODEL_GMM)
+        return fail(PPL_E_MODEL, "importance sampling supports POLY, BLR and GMM (got %d)", model);
+    if (int rc = check_n(n)) return rc;
+    IsArgs a{};
+    if (int rc = check_model_data(model, data, a.hyper)) return rc;
+    bool mixture_path = model == PPL_MODEL_GMM;
+    if (q && q->kind != PPL_Q_PRIOR) {
+        if (!q->d_params) return fail(PPL_E_ARG, "proposal parameters are NULL");
+        if (q->kind == PPL_Q_GAUSS_FULL && model == PPL_MODEL_BLR) {
+            if (q->dim != data->dim) return fail(PPL_E_ARG, "Gaussian proposal needs params of dim %d", data->dim);
+        } else if (q->kind == PPL_Q_POLY_MIX && model == PPL_MODEL_POLY) {
+            if (q->dim != 5) return fail(PPL_E_ARG, "POLY mixture proposal has dim 5 (got %d)", q->dim);
+            if (a.hyper[1] != 2.0 || a.hyper[2] != 5.0)
+                return fail(PPL_E_ARG, "the POLY mixture proposal covers degrees 2..5; the model range must be 2..5");
+            mixture_path = true;
+        } else if (q->kind == PPL_Q_GMM_MIX && model == PPL_MODEL_GMM) {
+            if (q->dim != 2 * data->dim - 1) return fail(PPL_E_ARG, "GMM mixture proposal has dim 2K - 1 = %d", 2 * data->dim - 1);
+        } else {
+            return fail(PPL_E_UNSUPPORTED, "proposal kind %d is not available for model %d", q->kind, model);
+        }
+        a.q_params = q->d_params;
+    }
+    const size_t need = is_ws_bytes(model, data->dim, n);
+    if (ws_cap && need > *ws_cap)
+        return fail(PPL_E_UNSUPPORTED, "%lld particles need %zu bytes of scratch; the no-allocation entry point holds %zu",
+                    (long long)n, need, *ws_cap);
+    if (int rc = check_ws(ws, ws_bytes, need)) return rc;
+    if (int rc = check_device()) return rc;
+    a.model = model;
+    a.x = data->x;
+    a.y = data->y;
+    a.D = data->n_data;
+    a.dim = data->dim;
+    a.N = n;
+    a.seed = seed;
+    a.lw_out = out->d_log_weights;
+    a.lat_out = out->d_latents;
+    a.summaries = out->d_summaries;
+    a.scalars = out->d_scalars ? out->d_scalars : (double *)ws;
+    a.part = (double *)((char *)ws + 256);
+    hipStream_t st = (hipStream_t)stream;
+    if (int rc = mixture_path ? run_importance_q(a, st) : run_importance(a, st)) return rc;
+    if (out->sync_host) return sync_scalars(out, a.scalars, st);
+    return PPL_OK;
+}
+
 }  // namespace ppl
 
 using namespace ppl;
@@ -202,47 +254,7 @@ int ppl_workspace_size(int model, const ppl_data *data, int64_t n, int algo, siz
 int ppl_importance(int model, const ppl_data *data, int64_t n, uint64_t seed, const ppl_proposal *q, void *ws,
                    size_t ws_bytes, void *stream, ppl_result *out) {
     clear_error();
-    if (!out) return fail(PPL_E_ARG, "out is NULL");
-    if (model != PPL_MODEL_POLY && model != PPL_MODEL_BLR && model != PPL_MODEL_GMM)
-        return fail(PPL_E_MODEL, "importance sampling supports POLY, BLR and GMM (got %d)", model);
-    if (int rc = check_n(n)) return rc;
-    IsArgs a{};
-    if (int rc = check_model_data(model, data, a.hyper)) return rc;
-    bool mixture_path = model == PPL_MODEL_GMM;
-    if (q && q->kind != PPL_Q_PRIOR) {
-        if (!q->d_params) return fail(PPL_E_ARG, "proposal parameters are NULL");
-        if (q->kind == PPL_Q_GAUSS_FULL && model == PPL_MODEL_BLR) {
-            if (q->dim != data->dim) return fail(PPL_E_ARG, "Gaussian proposal needs params of dim %d", data->dim);
-        } else if (q->kind == PPL_Q_POLY_MIX && model == PPL_MODEL_POLY) {
-            if (q->dim != 5) return fail(PPL_E_ARG, "POLY mixture proposal has dim 5 (got %d)", q->dim);
-            if (a.hyper[1] != 2.0 || a.hyper[2] != 5.0)
-                return fail(PPL_E_ARG, "the POLY mixture proposal covers degrees 2..5; the model range must be 2..5");
-            mixture_path = true;
-        } else if (q->kind == PPL_Q_GMM_MIX && model == PPL_MODEL_GMM) {
-            if (q->dim != 2 * data->dim - 1) return fail(PPL_E_ARG, "GMM mixture proposal has dim 2K - 1 = %d", 2 * data->dim - 1);
-        } else {
-            return fail(PPL_E_UNSUPPORTED, "proposal kind %d is not available for model %d", q->kind, model);
-        }
-        a.q_params = q->d_params;
-    }
-    if (int rc = check_ws(ws, ws_bytes, is_ws_bytes(model, data->dim, n))) return rc;
-    if (int rc = check_device()) return rc;
-    a.model = model;
-    a.x = data->x;
-    a.y = data->y;
-    a.D = data->n_data;
-    a.dim = data->dim;
-    a.N = n;
-    a.seed = seed;
-    a.lw_out = out->d_log_weights;
-    a.lat_out = out->d_latents;
-    a.summaries = out->d_summaries;
-    a.scalars = out->d_scalars ? out->d_scalars : (double *)ws;
-    a.part = (double *)((char *)ws + 256);
-    hipStream_t st = (hipStream_t)stream;
-    if (int rc = mixture_path ? run_importance_q(a, st) : run_importance(a, st)) return rc;
-    if (out->sync_host) return sync_scalars(out, a.scalars, st);
-    return PPL_OK;
+    return importance_call(model, data, n, seed, q, ws, ws_bytes, stream, out, nullptr);
 }
 
 int ppl_lse_ess(const void *lw, int dtype, int64_t n, double *out, void *ws, size_t ws_bytes, void *stream) {

@@ -25,6 +25,12 @@ inline double hyper_or(const ppl_data *d, int i, double dflt) {
 // Host-side launch guard: the grid must be non-empty and within HIP limits.
 int check_grid(const char *kernel, int64_t blocks, int threads);
 
+// Importance sampling of ppl_importance on workspace ws.  ws_cap non-null: a
+// request whose workspace exceeds *ws_cap fails with PPL_E_UNSUPPORTED before
+// anything is launched (the no-allocation entry point's fixed scratch).
+int importance_call(int model, const ppl_data *data, int64_t n, uint64_t seed, const ppl_proposal *q, void *ws,
+                    size_t ws_bytes, void *stream, ppl_result *out, const size_t *ws_cap);
+
 }  // namespace ppl
 
 #define PPL_HIP(call)                                                                        \
