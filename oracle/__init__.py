@@ -65,12 +65,14 @@ def lib():
         L.or_gmm_logfactor.argtypes = [i32, P, P, f64, f64]; L.or_gmm_logfactor.restype = f64
         L.or_gmm_init.argtypes = [u64, u32, i32, P, i64, P]
         L.or_smc.argtypes = [i32, P, i64, i32, P, i64, u64, u32, f64, f64, f64, i64,
-                             P, P, P, P, P, P, P, P, P]
+                             P, P, P, P, P, P, P, P, P, i32, f64, P]
         L.or_forced_event.argtypes = [P, P, P, i64, u64, u32, u32, P, P]
         L.or_forced_event.restype = ctypes.c_int
         L.or_smc.restype = ctypes.c_int
         L.or_smc_forced.argtypes = [i32, P, i64, i32, P, i64, u64, u32, f64, f64, P, P, P, i64,
-                                    P, P, P, P, P, P, P]
+                                    P, P, P, P, P, P, P, i32, f64, P, P]
+        L.or_move_scales.argtypes = [i32, i64, P, f64, P, P]
+        L.or_gmm_move_population.argtypes = [i32, P, P, i64, i64, u64, u32, i32, f64, P, P]
         L.or_smc_forced.restype = ctypes.c_int
         L.or_num_threads.restype = ctypes.c_int
         L.or_set_num_threads.argtypes = [ctypes.c_int]
@@ -253,8 +255,11 @@ def particle_logweights(model, x, y, idx, seed, hyper=None, dim=0, q=None):
 
 
 def smc(model, y, n, seed, ess_frac=0.5, hyper=None, K=0, inst=0, ess_band=0.0,
-        anc_band=0.0, max_events=0, want_state=False, want_event_lw=False):
-    """Sequential Monte Carlo over the factors y[0..T-1] (LGSSM or GMM)."""
+        anc_band=0.0, max_events=0, want_state=False, want_event_lw=False, move_steps=0, move_scale=0.0,
+        want_alpha=False):
+    """Sequential Monte Carlo over the factors y[0..T-1] (LGSSM or GMM); with
+    move_steps > 0 (GMM) every resampling is followed by that many
+    Metropolis-Hastings moves per particle (resample-move)."""
     if hyper is None:
         hyper = LGSSM_HYPER if model == MODEL_LGSSM else GMM_HYPER
     y = _f64(y)
@@ -270,9 +275,10 @@ def smc(model, y, n, seed, ess_frac=0.5, hyper=None, K=0, inst=0, ess_band=0.0,
     st = np.empty((nf, n)) if want_state else None
     lw = np.empty(n) if want_state else None
     lwh = np.zeros((max_events, n)) if (want_event_lw and max_events) else None
+    ah = np.zeros((max_events, move_steps, n)) if (want_alpha and max_events and move_steps) else None
     rc = lib().or_smc(model, _p(y), T, K, _p(h), n, seed, inst, ess_frac, ess_band, anc_band,
                       max_events, _p(scal), _p(ess_tr), _p(res_tr), _p(ess_tie), _p(anc), _p(tie),
-                      _p(st), _p(lw), _p(lwh))
+                      _p(st), _p(lw), _p(lwh), int(move_steps), float(move_scale), _p(ah))
     out = dict(log_z=scal[0], ess=scal[1], n_resample=int(scal[2]), status=int(scal[3]), rc=rc,
                ess_trace=ess_tr[:T], resampled=res_tr[:T].astype(bool), ess_tie=ess_tie[:T].astype(bool))
     if max_events:
@@ -283,7 +289,28 @@ def smc(model, y, n, seed, ess_frac=0.5, hyper=None, K=0, inst=0, ess_band=0.0,
         out["lw"] = lw
     if lwh is not None:
         out["event_lw"] = lwh
+    if ah is not None:
+        out["alpha"] = ah
     return out
+
+
+def move_scales(K, s, hyper=GMM_HYPER, lam=0.0):
+    """Random-walk scales (h_b, h_mu) of the resample-move step after factor s."""
+    hb, hm = ctypes.c_double(), ctypes.c_double()
+    lib().or_move_scales(int(K), int(s), _p(_f64(hyper)), float(lam), ctypes.byref(hb), ctypes.byref(hm))
+    return hb.value, hm.value
+
+
+def gmm_move_population(state, K, y, s, seed, M, inst=0, hyper=GMM_HYPER, lam=0.0, want_alpha=False):
+    """M resample-move MH steps (after factor s) applied to the population
+    state [2K, N] (log pi_k then mu_k); returns the new state (and the log
+    alphas [M, N])."""
+    st = np.array(state, dtype=np.float64, order="C", copy=True)
+    N = st.shape[1]
+    al = np.zeros((M, N)) if want_alpha else None
+    lib().or_gmm_move_population(int(K), _p(_f64(hyper)), _p(_f64(y)), int(s), N, seed, int(inst), int(M),
+                                 float(lam), _p(st), _p(al))
+    return (st, al) if want_alpha else st
 
 
 def forced_event(lw, given_lw, given_anc, seed, step=0, inst=0):
@@ -304,7 +331,7 @@ def forced_event(lw, given_lw, given_anc, seed, step=0, inst=0):
 
 
 def smc_forced(model, y, n, seed, given_resampled, given_ancestors, given_event_lw, ess_frac=0.5, hyper=None,
-               K=0, inst=0, ess_band=0.0, want_state=False):
+               K=0, inst=0, ess_band=0.0, want_state=False, move_steps=0, move_scale=0.0, given_alpha=None):
     """Teacher-forced SMC beside another run (see ``or_smc_forced``): adopts the
     given decision inside the ESS tie band and the given ancestor at tie slots,
     and counts every disagreement outside them.  given_ancestors /
@@ -323,6 +350,12 @@ def smc_forced(model, y, n, seed, given_resampled, given_ancestors, given_event_
     E = g_anc.shape[0]
     if g_lw.shape[0] != E:
         raise ValueError("ancestor and log-weight records differ in length")
+    g_al = None
+    if move_steps:
+        g_al = np.ascontiguousarray(given_alpha, dtype=np.float64).reshape(-1, move_steps, n)
+        if g_al.shape[0] < E:
+            raise ValueError("fewer move records than events")
+    mv = np.zeros((max(E, 1), 4))
     scal = np.zeros(5)
     logz_inc = np.zeros(max(T, 1))
     ess_tr = np.zeros(max(T, 1))
@@ -332,14 +365,16 @@ def smc_forced(model, y, n, seed, given_resampled, given_ancestors, given_event_
     lw = np.empty(n) if want_state else None
     rc = lib().or_smc_forced(model, _p(y), T, K, _p(h), n, seed, inst, ess_frac, ess_band, _p(g_res),
                              _p(g_anc), _p(g_lw), E, _p(scal), _p(logz_inc), _p(ess_tr), _p(ev), _p(dec),
-                             _p(st), _p(lw))
+                             _p(st), _p(lw), int(move_steps), float(move_scale), _p(g_al), _p(mv))
     n_ev = int(scal[2])
     out = dict(rc=rc, log_z=scal[0], ess=scal[1], n_resample=n_ev, status=int(scal[3]), steps=int(scal[4]),
                logz_inc=logz_inc[:T], ess_trace=ess_tr[:T],
                events=dict(step=ev[:n_ev, 0].astype(int), max_dlw=ev[:n_ev, 1], ties=ev[:n_ev, 2].astype(int),
                            adopted=ev[:n_ev, 3].astype(int), nontie_diff=ev[:n_ev, 4].astype(int),
                            expected_ties=ev[:n_ev, 5], max_band=ev[:n_ev, 6]),
-               decisions=dict(adopted=int(dec[0]), differ_outside_band=int(dec[1]), in_band=int(dec[2])))
+               decisions=dict(adopted=int(dec[0]), differ_outside_band=int(dec[1]), in_band=int(dec[2])),
+               moves=dict(ties=mv[:n_ev, 0].astype(int), adopted=mv[:n_ev, 1].astype(int),
+                          nontie_diff=mv[:n_ev, 2].astype(int), max_dalpha=mv[:n_ev, 3]))
     if want_state:
         out["state"] = st
         out["lw"] = lw

@@ -124,3 +124,20 @@ def lgssm_logz_mvn(y, a=0.9, q_sd=1.0, r_sd=0.5, m0=0.0, p0=0.0):
     C += r_sd ** 2 * np.eye(T)
     mean = m0 * a ** np.arange(1, T + 1)
     return multivariate_normal(mean, C).logpdf(y)
+
+
+def gmm1_exact(y, mu_sd=5.0, comp_sd=1.0):
+    """The mixture model with one component: mu ~ N(0, mu_sd^2), y_d ~ N(mu,
+    comp_sd^2) is Gaussian-conjugate.  Returns (log Z, posterior mean,
+    posterior variance) of mu given y: precision 1/mu_sd^2 + D/comp_sd^2;
+    y ~ N(0, comp_sd^2 I + mu_sd^2 1 1^T), whose log density uses the
+    matrix-determinant lemma and the Sherman-Morrison inverse."""
+    y = np.asarray(y, dtype=np.float64)
+    D = y.size
+    prec = 1.0 / mu_sd ** 2 + D / comp_sd ** 2
+    mean = (y.sum() / comp_sd ** 2) / prec
+    s2, t2 = comp_sd ** 2, mu_sd ** 2
+    logdet = D * math.log(s2) + math.log1p(D * t2 / s2)
+    quad = (y @ y) / s2 - (t2 / s2 ** 2) * y.sum() ** 2 / (1.0 + D * t2 / s2)
+    logz = -0.5 * (D * math.log(2 * math.pi) + logdet + quad)
+    return logz, mean, 1.0 / prec

@@ -536,6 +536,143 @@ static void smc_advance(int32_t model, int32_t K, const double *hyper, const dou
     }
 }
 
+/* ------------------------------------------------ resample-move (GMM) -- */
+/* Resample-move: after each resampling at factor s the mixture particles take
+ * M Metropolis-Hastings steps whose target is the posterior given the data
+ * seen so far, p(theta) prod_{d <= s} f(y_d | theta) -- particle inference
+ * (named as future work in Sec. 6) with the Metropolis-Hastings acceptance
+ * rule of the paper's third inference method (Sec. 3.6.3).  The move leaves
+ * the equally weighted population's target invariant, so log-weights stay 0.
+ *
+ * Readings (the paper gives no move kernel):
+ *   - unconstrained coordinates u = (b_1..b_{K-1}, mu_1..mu_K) with
+ *     b_k = log pi_k - log pi_K; log pi_k = b_k - log(1 + sum_j e^{b_j});
+ *   - prior density of u: Dirichlet(1) gives log (K-1)! + sum_k log pi_k (the
+ *     softmax Jacobian), plus sum_k log Normal(mu_k; 0, mu_sd);
+ *   - Gaussian random walk u' = u + h z, symmetric, with scales fixed by s:
+ *     h_mu = lam / sqrt(1/mu_sd^2 + (s+1)/(K comp_sd^2)),
+ *     h_b  = lam / sqrt(3/pi^2 + (s+1)/(2K))
+ *     (the posterior sds if each component held (s+1)/K of the data; pi^2/3
+ *     is the prior variance of b_k), lam = 2.38 / sqrt(2K - 1) unless given;
+ *   - accept when log v < log alpha = [l(u') + log p(u')] - [l(u) + log p(u)],
+ *     l the log-likelihood of y_0..y_s;
+ *   - words: move m of slot j at factor s uses Philox blocks
+ *     (j, 8m + b, s, inst << 8 | 7): blocks b = 0..3 give 16 normals
+ *     (single-precision Box-Muller pairs, the first 2K - 1 used), word 0 of
+ *     block 4 the uniform v. */
+#define TAG_MOVE 7
+
+static double gmm_loglik_upto(int32_t K, const double *lpi, const double *mu, double sd, const double *y, int64_t s)
+{
+    double l = 0.0;
+    for (int64_t d = 0; d <= s; ++d) l += or_gmm_logfactor(K, lpi, mu, sd, y[d]);
+    return l;
+}
+
+static double gmm_log_prior(int32_t K, const double *lpi, const double *mu, double mu_sd)
+{
+    double l = 0.0;
+    for (int k = 0; k < K; ++k) l += lpi[k] - 0.5 * (mu[k] / mu_sd) * (mu[k] / mu_sd);
+    return l;           /* constants (log (K-1)!, the normal's) cancel in the ratio */
+}
+
+void or_move_scales(int32_t K, int64_t s, const double *hyper, double lam, double *h_b, double *h_mu)
+{
+    if (!(lam > 0.0)) lam = 2.38 / sqrt(2.0 * K - 1.0);
+    double n = (double)(s + 1);
+    *h_mu = lam / sqrt(1.0 / (hyper[0] * hyper[0]) + n / ((double)K * hyper[1] * hyper[1]));
+    *h_b = lam / sqrt(3.0 / (M_PI * M_PI) + n / (2.0 * K));
+}
+
+/* One particle's proposal for move m: u' = u + h z, mapped back to (log pi, mu). */
+static void gmm_move_propose(uint64_t seed, int64_t j, int m, int64_t s, uint32_t inst, int32_t K, double h_b,
+                             double h_mu, const double *lpi, const double *mu, double *lpi2, double *mu2,
+                             double *logv)
+{
+    uint32_t w[4];
+    double z[16];
+    for (int b = 0; b < 4; ++b) {
+        draw4(seed, (uint32_t)j, (uint32_t)(8 * m + b), (uint32_t)s, inst, TAG_MOVE, w);
+        normals4_single(w, z + 4 * b);
+    }
+    draw4(seed, (uint32_t)j, (uint32_t)(8 * m + 4), (uint32_t)s, inst, TAG_MOVE, w);
+    *logv = log(or_u01_single(w[0]));
+    double b2[8], mx = 0.0;
+    for (int k = 0; k < K - 1; ++k) {
+        b2[k] = (lpi[k] - lpi[K - 1]) + h_b * z[k];
+        if (b2[k] > mx) mx = b2[k];
+    }
+    double se = exp(-mx);                    /* the fixed coordinate b_K = 0 */
+    for (int k = 0; k < K - 1; ++k) se += exp(b2[k] - mx);
+    double lse = mx + log(se);
+    for (int k = 0; k < K - 1; ++k) lpi2[k] = b2[k] - lse;
+    lpi2[K - 1] = -lse;
+    for (int k = 0; k < K; ++k) mu2[k] = mu[k] + h_mu * z[K - 1 + k];
+}
+
+/* M moves of every particle after the resampling at factor s (state
+ * [2K][N], see the model notes).  alpha_out[M][N] (optional): this run's
+ * log alpha.  Forcing (g_alpha non-NULL, [M][N], the other run's FP64
+ * log alpha): where |log alpha - log v| <= 2 |g_alpha - log alpha| + 1e-12
+ * (1 + |log alpha|) the decision is a tie and the other run's decision
+ * (log v < g_alpha) is adopted; elsewhere a differing decision is counted.
+ * stats[4] (optional, with forcing): {tie decisions, adopted, non-tie
+ * differences, max |g_alpha - log alpha| / (1 + |l(u)|)}. */
+static void gmm_moves(int32_t K, const double *hyper, const double *y, int64_t s, int64_t N, uint64_t seed,
+                      uint32_t inst, int32_t M, double lam, double *st, double *alpha_out, const double *g_alpha,
+                      double *stats)
+{
+    double h_b, h_mu;
+    or_move_scales(K, s, hyper, lam, &h_b, &h_mu);
+    int64_t ties = 0, adopted = 0, bad = 0;
+    double maxd = 0.0;
+#pragma omp parallel for schedule(dynamic, 256) reduction(+:ties, adopted, bad) reduction(max:maxd)
+    for (int64_t j = 0; j < N; ++j) {
+        double lpi[8], mu[8], lpi2[8], mu2[8], logv;
+        for (int k = 0; k < K; ++k) { lpi[k] = st[k * N + j]; mu[k] = st[(K + k) * N + j]; }
+        double ll = gmm_loglik_upto(K, lpi, mu, hyper[1], y, s);
+        double lp = gmm_log_prior(K, lpi, mu, hyper[0]);
+        for (int m = 0; m < M; ++m) {
+            gmm_move_propose(seed, j, m, s, inst, K, h_b, h_mu, lpi, mu, lpi2, mu2, &logv);
+            double ll2 = gmm_loglik_upto(K, lpi2, mu2, hyper[1], y, s);
+            double lp2 = gmm_log_prior(K, lpi2, mu2, hyper[0]);
+            double la = (ll2 + lp2) - (ll + lp);
+            if (alpha_out) alpha_out[(size_t)m * N + j] = la;
+            int acc = logv < la;
+            if (g_alpha) {
+                double ga = g_alpha[(size_t)m * N + j];
+                double dv = fabs(ga - la);
+                double rel = dv / (1.0 + fabs(ll));
+                if (!(rel <= maxd)) maxd = rel;
+                int given = logv < ga;
+                if (fabs(la - logv) <= 2.0 * dv + 1e-12 * (1.0 + fabs(la))) {
+                    ++ties;
+                    if (given != acc) ++adopted;
+                    acc = given;
+                } else if (given != acc) {
+                    ++bad;
+                }
+            }
+            if (acc) {
+                for (int k = 0; k < K; ++k) { lpi[k] = lpi2[k]; mu[k] = mu2[k]; }
+                ll = ll2;
+                lp = lp2;
+            }
+        }
+        for (int k = 0; k < K; ++k) { st[k * N + j] = lpi[k]; st[(K + k) * N + j] = mu[k]; }
+    }
+    if (stats) { stats[0] = (double)ties; stats[1] = (double)adopted; stats[2] = (double)bad; stats[3] = maxd; }
+}
+
+/* The moves of one event applied to a given population st[2K][N] (the
+ * state layout of the SMC), with this run's log alphas in alpha_out[M][N]
+ * (optional): the MH kernel on its own, for the tests that pin it. */
+void or_gmm_move_population(int32_t K, const double *hyper, const double *y, int64_t s, int64_t N,
+                            uint64_t seed, uint32_t inst, int32_t M, double lam, double *st, double *alpha_out)
+{
+    gmm_moves(K, hyper, y, s, N, seed, inst, M, lam, st, alpha_out, NULL, NULL);
+}
+
 /* Generic SMC driver.
  *   y[T] observations; N particles; ess_frac threshold (resample when ESS < ess_frac*N,
  *   never after the last factor).  log Z-hat = sum over epochs of (LSE(lw) - log N).
@@ -551,10 +688,12 @@ int or_smc(int32_t model, const double *y, int64_t T, int32_t K, const double *h
            int64_t N, uint64_t seed, uint32_t inst, double ess_frac,
            double ess_band, double anc_band, int64_t max_events,
            double *scal, double *ess_tr, uint8_t *res_tr, uint8_t *ess_tie,
-           int32_t *anc_hist, uint8_t *tie_hist, double *state_out, double *lw_out, double *lw_hist)
+           int32_t *anc_hist, uint8_t *tie_hist, double *state_out, double *lw_out, double *lw_hist,
+           int32_t move_steps, double move_scale, double *alpha_hist)
 {
-    if (N <= 0 || T < 0) return -1;
+    if (N <= 0 || T < 0 || move_steps < 0) return -1;
     if (model != MODEL_LGSSM && model != MODEL_GMM) return -2;
+    if (move_steps > 0 && model != MODEL_GMM) return -2;
     if (model == MODEL_GMM && (K < 1 || K > 8)) return -1;
     int nf = model == MODEL_LGSSM ? 1 : 2 * K;
     double *st = (double *)malloc(sizeof(double) * N * nf);
@@ -588,6 +727,10 @@ int or_smc(int32_t model, const double *y, int64_t T, int32_t K, const double *h
             for (int f = 0; f < nf; ++f)
                 for (int64_t j = 0; j < N; ++j) st2[f * N + j] = st[f * N + anc[j]];
             double *tmp = st; st = st2; st2 = tmp;
+            if (move_steps > 0)
+                gmm_moves(K, hyper, y, s, N, seed, inst, move_steps, move_scale, st,
+                          (alpha_hist && ev < max_events) ? alpha_hist + (size_t)ev * move_steps * N : NULL,
+                          NULL, NULL);
             for (int64_t j = 0; j < N; ++j) lw[j] = 0.0;
             ++nres; ++ev;
         }
@@ -718,14 +861,20 @@ int or_forced_event(const double *lw, const float *glw, const int32_t *ganc, int
  *              expected tie slots sum_a N * 2 band_a, max band, 0}
  *   dec[3]     = {decisions adopted inside the band, decisions that differ
  *              outside it, decisions inside the band}
+ *   mv_out[E][4] with move_steps > 0: per event the move statistics of
+ *              gmm_moves (tie decisions, adopted, non-tie differences, max
+ *              relative log-alpha difference); g_alpha[E][M][N] the other
+ *              run's FP64 log alphas
  *   state_out[n_fields][N], lw_out[N]: particles and log-weights when the run ends */
 int or_smc_forced(int32_t model, const double *y, int64_t T, int32_t K, const double *hyper,
                   int64_t N, uint64_t seed, uint32_t inst, double ess_frac, double ess_band,
                   const uint8_t *g_res, const int32_t *g_anc, const float *g_lw, int64_t E,
                   double *scal, double *logz_inc, double *ess_tr, double *ev_out, double *dec,
-                  double *state_out, double *lw_out)
+                  double *state_out, double *lw_out,
+                  int32_t move_steps, double move_scale, const double *g_alpha, double *mv_out)
 {
-    if (N <= 0 || T < 0 || E < 0 || !g_res || (E > 0 && (!g_anc || !g_lw))) return -1;
+    if (N <= 0 || T < 0 || E < 0 || move_steps < 0 || !g_res || (E > 0 && (!g_anc || !g_lw))) return -1;
+    if (move_steps > 0 && (model != MODEL_GMM || (E > 0 && !g_alpha))) return -1;
     if (model != MODEL_LGSSM && model != MODEL_GMM) return -2;
     if (model == MODEL_GMM && (K < 1 || K > 8)) return -1;
     int nf = model == MODEL_LGSSM ? 1 : 2 * K;
@@ -773,6 +922,9 @@ int or_smc_forced(int32_t model, const double *y, int64_t T, int32_t K, const do
         for (int f = 0; f < nf; ++f)
             for (int64_t j = 0; j < N; ++j) st2[f * N + j] = st[f * N + anc[j]];
         double *tmp = st; st = st2; st2 = tmp;
+        if (move_steps > 0)
+            gmm_moves(K, hyper, y, s, N, seed, inst, move_steps, move_scale, st, NULL,
+                      g_alpha + (size_t)nres * move_steps * N, mv_out ? mv_out + nres * 4 : NULL);
         for (int64_t j = 0; j < N; ++j) lw[j] = 0.0;
         ++nres;
     }
