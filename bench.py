@@ -18,6 +18,10 @@ Printed as one JSON line, with
   cpu_baseline -- the CPU oracle on a bounded sample of the same workload.
 
 Other configurations print the same fields for their own workload:
+  blr-stats         the same BLR workload with the likelihood from sufficient
+                    statistics (X^T X, X^T y, y^T y once per call, then O(d^2)
+                    FP64 per particle): particles per second, roofline of the
+                    particle kernel against HBM (latents and log-weights written)
   poly, poly-paper  polynomial fit IS (FP64), 10^4 and 2 x 10^6 particles
   lgssm             bootstrap SMC on the linear-Gaussian state space model
   gmm-batched       batched SMC over 256 mixture instances (autotuned first)
@@ -27,7 +31,7 @@ Other configurations print the same fields for their own workload:
   peaks             measured instruction and copy rates (not a hot-path line)
 
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu]
-                       [--config blr|poly|poly-paper|lgssm|gmm-batched|resample-gather|proposal-poly|
+                       [--config blr|blr-stats|poly|poly-paper|lgssm|gmm-batched|resample-gather|proposal-poly|
                                  proposal-gmm|proposal-train|peaks]
 """
 import argparse
@@ -66,7 +70,8 @@ def parse():
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--config", default="blr",
-                    choices=["blr", "poly", "poly-paper", "lgssm", "gmm-batched", "resample-gather", "proposal-poly",
+                    choices=["blr", "blr-stats", "poly", "poly-paper", "lgssm", "gmm-batched", "resample-gather",
+                             "proposal-poly",
                              "proposal-gmm", "proposal-train", "peaks"])
     ap.add_argument("--pairs-log2", type=int, default=22, help="proposal-train: log2 of the simulated pairs")
     ap.add_argument("--no-graph", action="store_true", help="proposal-train: launch each step's kernels eagerly")
@@ -653,6 +658,20 @@ def main():
                     "precision": "fp32 likelihood, fp64 normaliser"}
         flop_per_launch = FLOP_PER_EVAL_BLR * N * D
         peak, bound, unit, dtype = FP32_VALU_PUBLISHED_TFLOPS, "alu", "TFLOP/s", "f32"
+    elif args.config == "blr-stats":
+        d, D, N, seed = 16, 10_000, args.particles or (1 << 20), 1
+        X, y, _ = synthetic.blr_data(D=D, d=d)
+        dX, dy = torch.from_numpy(X).to(dev), torch.from_numpy(y).to(dev)
+        data = ppl.make_data(dX, dy, dim=d)
+        model, kname = ppl.PPL_MODEL_BLR_STATS, "blr_stats_is_kernel"
+        nsum = d
+        workload = {"workload": "blr-stats-importance-sampling",
+                    "model": "conjugate Bayesian linear regression, likelihood from sufficient statistics",
+                    "d": d, "rows": D, "particles": N, "proposal": "prior",
+                    "precision": "fp32 latents, fp64 statistics, quadratic form and normaliser"}
+        # algorithmic HBM bytes of the particle kernel: d FP32 latents and one FP64 log-weight written per particle
+        flop_per_launch = (4 * d + 8) * N
+        peak, bound, unit, dtype = 8000.0, "hbm", "GB/s", "f64"
     elif args.config == "lgssm":
         T, N, seed = 1000, args.particles or (1 << 20), 1
         y = synthetic.lgssm_data(T=T)
@@ -736,7 +755,7 @@ def main():
     evals = N * D
     value = evals / (ms_per_step / 1e3)
     k_avg_ms = k_ms / max(k_n, 1)
-    achieved = flop_per_launch / (k_avg_ms / 1e3) / 1e12
+    achieved = flop_per_launch / (k_avg_ms / 1e3) / (1e9 if unit == "GB/s" else 1e12)
     if args.config == "gmm-batched":
         ob = outb.cpu().numpy()
         assert (ob[:, 3] == 0).all(), "device status"
@@ -765,9 +784,20 @@ def main():
     if args.config == "lgssm":
         out["n_resample"] = int(s[2])
         out["metric"] = "particle-step evals/s"
+    if args.config == "blr-stats":
+        # the statistics replace the per-row loop: the rate is in particles, not (particle, row) terms
+        out["metric"], out["unit"], out["value"] = "particles/s", "particles/s", N / (ms_per_step / 1e3)
+        out["evals_equivalent"] = value
+        roofline["bytes_per_launch"] = roofline.pop("flop_per_launch")
     if not args.no_cpu:
         if args.config == "blr":
             out["cpu_baseline"] = cpu_baseline_blr(X, y, N, seed, target_s=args.cpu_seconds)
+        elif args.config == "blr-stats":
+            cb = cpu_baseline_blr(X, y, N, seed, target_s=args.cpu_seconds)
+            for k in ("value", "value_1_thread"):
+                cb[k] /= D                      # the oracle's row-by-row likelihood, per particle
+            cb["unit"] = "particles/s"
+            out["cpu_baseline"] = cb
         elif args.config == "lgssm":
             out["cpu_baseline"] = cpu_baseline_lgssm(y, seed, target_s=args.cpu_seconds)
         else:

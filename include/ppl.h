@@ -86,7 +86,14 @@ enum {
      * log sum_k pi_k Normal(y_d; mu_k, comp_sd).  FP32 state.
      * data: y[D] float32, dim = K; hyper = {mu_sd, comp_sd} (default {5, 1}).
      * latents [2K][N] float32: log pi_0..log pi_{K-1}, mu_0..mu_{K-1}. */
-    PPL_MODEL_GMM = 4
+    PPL_MODEL_GMM = 4,
+    /* The BLR model of PPL_MODEL_BLR (same data, hyper-parameters, latents,
+     * draws, proposals and summaries), with the likelihood evaluated from
+     * sufficient statistics: A = X^T X, b = X^T y, c = y^T y are formed once
+     * per call in FP64 (O(D d^2)), then each particle's residual sum of
+     * squares is c - 2 w.b + w^T A w in FP64 (O(d^2) instead of O(D d)).
+     * Importance sampling only. */
+    PPL_MODEL_BLR_STATS = 5
 };
 
 enum { PPL_F32 = 1, PPL_F64 = 2 };
@@ -125,7 +132,14 @@ typedef struct ppl_result {
     double *d_ess_trace;      /* [T]: ESS after factor t, before resampling */
     uint8_t *d_resampled;     /* [T]: 1 if resampled after factor t */
     int32_t *d_ancestors;     /* [max_events][N]: ancestor vector of each resampling event */
-    int64_t max_events;       /* rows available in d_ancestors */
+    int64_t max_events;       /* rows available in d_ancestors and d_event_lw */
+    float *d_event_lw;        /* [max_events][N]: the log-weights each resampling event resampled from
+                               * (FP32, as the event saw them); needs max_events > 0 */
+    double *d_logz_trace;     /* [T]: the normaliser increment LSE(lw) - log N added to log Z-hat after
+                               * factor t (at each resampling and after the last factor), 0 elsewhere;
+                               * entries after a failing factor are not written */
+    double *d_move_log_alpha; /* [max_events][move_steps][N]: log acceptance ratio of each
+                               * resample-move step (ppl_smc_ex with move_steps > 0) */
 } ppl_result;
 
 /* Proposal for importance sampling (NULL or kind PPL_Q_PRIOR: the prior,
@@ -169,7 +183,8 @@ int ppl_workspace_size(int model, const ppl_data *data, int64_t n_particles, int
  * each execution's sample/factor calls give it a log-weight; the FP64
  * log-sum-exp normaliser gives log Z-hat = LSE(lw) - log N and
  * ESS = (sum w)^2 / sum w^2.
- * model: PPL_MODEL_POLY, PPL_MODEL_BLR or PPL_MODEL_GMM.  n_particles in [1, 2^31).
+ * model: PPL_MODEL_POLY, PPL_MODEL_BLR, PPL_MODEL_BLR_STATS or PPL_MODEL_GMM.
+ * n_particles in [1, 2^31).
  * GMM importance sampling draws its latents and evaluates the prior and
  * proposal densities in FP64; the likelihood is FP32 per datum (hardware exp
  * and log, as in the SMC), summed in FP32 within blocks of 16 data and in
@@ -178,7 +193,7 @@ int ppl_workspace_size(int model, const ppl_data *data, int64_t n_particles, int
  * d_summaries (FP64):
  *   POLY: [0..3] P(n = 2..5 | y); [4 + 5(n-2) + j] E[c_j | n, y] (0 where that
  *         degree has no mass); [24 + j] E[c_j 1{j < n} | y]        -> 29 values
- *   BLR:  [0..d-1] E[w | y]                                          -> d values
+ *   BLR, BLR_STATS: [0..d-1] E[w | y]                                -> d values
  *   GMM:  [k] E[mu_(k) | y], the k-th smallest mean, k < K           -> 8 values */
 int ppl_importance(int model, const ppl_data *data, int64_t n_particles, uint64_t seed,
                    const ppl_proposal *q, void *d_ws, size_t ws_bytes, void *stream,
@@ -244,6 +259,37 @@ int ppl_philox(uint64_t seed, uint32_t c1, uint32_t c2, uint32_t c3, int64_t n,
 int ppl_smc(int model, const ppl_data *data, int64_t n_particles, uint64_t seed,
             double ess_frac, void *d_ws, size_t ws_bytes, void *stream, ppl_result *out);
 
+/* Options of ppl_smc_ex. */
+typedef struct ppl_smc_options {
+    double ess_frac;          /* resample when ESS < ess_frac N; in [0, 1] */
+    int32_t move_steps;       /* resample-move: Metropolis-Hastings steps per particle after each
+                               * resampling (0: none); PPL_MODEL_GMM only; 0..64 */
+    int32_t reserved;
+    double move_scale;        /* random-walk scale factor lambda (0: 2.38 / sqrt(2K - 1)) */
+} ppl_smc_options;
+
+/* ppl_smc with options; resample-move for the mixture model.  After each
+ * resampling at factor s every particle takes move_steps Metropolis-Hastings
+ * steps (the acceptance rule of the paper's MH method, Sec. 3.6.3) whose
+ * target is the posterior given y_0..y_s, so particles that resampling made
+ * identical spread out again (particle inference, Sec. 6).  The log-weights
+ * stay 0 (the moves keep the equally weighted population's target).
+ *   coordinates u = (log pi_k - log pi_K for k < K, mu_k for k <= K); prior
+ *     density Dirichlet(1) x Normal(0, mu_sd)^K, with the softmax Jacobian;
+ *   proposal u' = u + h z, z standard normal, h fixed by s:
+ *     h_mu = lambda / sqrt(1 / mu_sd^2 + (s + 1) / (K comp_sd^2)),
+ *     h_b  = lambda / sqrt(3 / pi^2 + (s + 1) / (2K));
+ *   accept when log v < log alpha = [l(u') + log p(u')] - [l(u) + log p(u)]
+ *     in FP64, l the log-likelihood of y_0..y_s (FP32 factors summed in FP32
+ *     within blocks of 16 data and in FP64 across blocks);
+ *   words: move m of slot j uses Philox blocks (j, 8m + b, s, inst << 8 | 7),
+ *     b < 4 for sixteen normals (the first 2K - 1 used), word 0 of block
+ *     8m + 4 for the uniform v.
+ * Each move costs O(s K) per particle.  d_move_log_alpha (with max_events)
+ * records log alpha per event, step and particle. */
+int ppl_smc_ex(int model, const ppl_data *data, int64_t n_particles, uint64_t seed, const ppl_smc_options *opt,
+               void *d_ws, size_t ws_bytes, void *stream, ppl_result *out);
+
 /* ------------------------------------------------------ batched SMC -- */
 /* One model instance of a batched run.  The caller passes the same table
  * twice: a HOST copy (validated and used for scheduling) and a DEVICE copy
@@ -255,17 +301,27 @@ typedef struct ppl_instance {
     int64_t n_data;           /* D_i (factors) */
     int64_t n_particles;      /* N_i */
     int32_t dim;              /* GMM: K_i in 1..8 */
-    int32_t reserved;
+    int32_t flags;            /* 0 or PPL_INST_NO_RECORD */
     double hyper[2];          /* GMM: {mu_sd, comp_sd}; 0 = default {5, 1} */
+    int32_t move_steps;       /* resample-move steps per particle after each resampling (0..64; see ppl_smc_ex) */
+    int32_t reserved;
+    double move_scale;        /* random-walk scale factor (0: 2.38 / sqrt(2K - 1)) */
 } ppl_instance;
+
+/* The instance's resampling events are not recorded: it has no rows in
+ * d_ancestors / d_event_lw of ppl_batch_result (see there). */
+enum { PPL_INST_NO_RECORD = 1 };
 
 /* Launch configuration of the batched engine (0 fields = default/derived).
  * particles_per_lane P in {1,2,4,8}; wgs_per_instance W = 512-thread
  * workgroups that hold one instance (W * 512 * P >= max N_i, W <= 64);
  * spec_block = largest number of factors advanced between synchronisations
- * (1..256).  Results are the SMC of each instance for any valid choice; the
- * choice only changes the order of the FP64 sums behind the resampling
- * trigger (so a decision within rounding of the threshold may differ). */
+ * (1..256).  For every valid choice the outputs are the same bits: log-weights,
+ * latents, ancestors, decisions, normaliser increments, log Z-hat and final
+ * ESS (the normaliser sums weights as exact 128-bit fixed-point integers).
+ * Only the trigger ESS values (d_ess_trace) follow the launch shape in their
+ * last bits, through the order of their FP32 / FP64 partial sums; a decision
+ * whose ESS lies within that rounding of ess_frac N may therefore differ. */
 typedef struct ppl_tune {
     int32_t particles_per_lane;
     int32_t wgs_per_instance;
@@ -278,10 +334,18 @@ typedef struct ppl_tune {
  *   d_log_weights [sum N_i] float32, instance i at offset P_i = sum_{k<i} N_k;
  *   d_latents [16 * sum N_i] float32, instance i at 16 P_i as [2 K_i][N_i]
  *             (log pi_k then mu_k);
- *   d_ess_trace / d_resampled [sum D_i], instance i at offset sum_{k<i} D_k;
- *   d_ancestors [max_events * sum N_i] int32, instance i at max_events * P_i as
+ *   d_ess_trace / d_resampled / d_logz_trace [sum D_i], instance i at offset
+ *             sum_{k<i} D_k (d_logz_trace as in ppl_result);
+ *   d_ancestors [max_events * sum' N_i] int32 and d_event_lw [max_events *
+ *             sum' N_i] float32, where sum' runs over the recorded instances
+ *             (flags without PPL_INST_NO_RECORD): recorded instance i at
+ *             max_events * R_i, R_i = sum' over recorded k < i of N_k, as
  *             [max_events][N_i]: the ancestor vectors of its first max_events
- *             resampling events. */
+ *             resampling events and the log-weights they resampled from;
+ *   d_move_log_alpha [max_events * sum' M_i N_i] FP64: recorded instance i
+ *             with M_i = move_steps > 0 at max_events * sum' over recorded
+ *             k < i of M_k N_k, as [max_events][M_i][N_i]: the log acceptance
+ *             ratios of its resample-move steps. */
 typedef struct ppl_batch_result {
     double *d_out;
     float *d_log_weights;
@@ -290,6 +354,9 @@ typedef struct ppl_batch_result {
     uint8_t *d_resampled;
     int32_t *d_ancestors;
     int64_t max_events;
+    float *d_event_lw;
+    double *d_logz_trace;
+    double *d_move_log_alpha;
 } ppl_batch_result;
 
 /* Workspace bytes for a batched run with configuration `tune` (NULL: enough
@@ -306,12 +373,28 @@ int ppl_smc_batched(int model, int32_t n_inst, const ppl_instance *h_inst, const
                     void *stream, ppl_batch_result *out);
 
 /* Autotuner: times each candidate configuration once on this batch (after a
- * warm-up run, synchronising the stream), returns the fastest in *best and
- * caches it for batches of the same shape (instance count, particle and data
- * totals, largest instance).  Writes the outputs like ppl_smc_batched. */
+ * warm-up run, synchronising the stream): P in {1, 2, 4, 8} with speculative
+ * blocks of 16..256 factors, each with the smallest team W that holds the
+ * largest instance and with 2 W.  Returns the fastest in *best and caches it
+ * for batches of the same shape (instance count, particle and data totals,
+ * largest instance), in the process and in the PPL_TUNE_CACHE file (see
+ * ppl_smc_tune_lookup).  Writes the outputs like ppl_smc_batched. */
 int ppl_smc_autotune(int model, int32_t n_inst, const ppl_instance *h_inst, const ppl_instance *d_inst,
                      uint64_t seed, double ess_frac, void *d_ws, size_t ws_bytes, void *stream,
                      ppl_batch_result *out, ppl_tune *best);
+
+/* The configuration a call with tune == NULL would use for this batch shape
+ * (instance count, particle and data totals, largest instance): the
+ * autotuner's result cached in this process, or a line of the persisted
+ * cache.  PPL_E_UNSUPPORTED if there is none (the call would use the
+ * defaults).  Persisted cache: when the environment variable PPL_TUNE_CACHE
+ * names a file, ppl_smc_autotune appends each result to it (keyed by the
+ * device architecture and compute-unit count and the batch shape), and
+ * lookups merge that file's lines for the current device into the process
+ * cache the first time they see it.  An unreadable file counts as empty. */
+int ppl_smc_tune_lookup(int model, int32_t n_inst, const ppl_instance *h_inst, ppl_tune *out);
+/* Forgets the process cache (the next lookup re-reads PPL_TUNE_CACHE). */
+void ppl_smc_tune_cache_clear(void);
 
 /* --------------------------------------------------- learned proposal -- */
 /* A small network maps 64 summary statistics of a dataset to a Gaussian-

@@ -21,14 +21,17 @@ LIB_PATH = os.path.join(_HERE, "libppl.so")
 PPL_OK, PPL_E_ARG, PPL_E_MODEL, PPL_E_DEVICE, PPL_E_HIP = 0, -1, -2, -3, -4
 PPL_E_WORKSPACE, PPL_E_NONFINITE, PPL_E_ZERO_WEIGHT, PPL_E_UNSUPPORTED = -5, -6, -7, -8
 PPL_MODEL_POLY, PPL_MODEL_BLR, PPL_MODEL_LGSSM, PPL_MODEL_GMM = 1, 2, 3, 4
+PPL_MODEL_BLR_STATS = 5
 PPL_F32, PPL_F64 = 1, 2
 PPL_Q_PRIOR, PPL_Q_GAUSS_FULL, PPL_Q_POLY_MIX, PPL_Q_GMM_MIX = 0, 1, 2, 3
 PPL_ALGO_IS, PPL_ALGO_SMC, PPL_ALGO_LSE, PPL_ALGO_RESAMPLE = 0, 1, 2, 3
+PPL_INST_NO_RECORD = 1
 PPL_NOALLOC_SCRATCH_BYTES = 16 << 20
 
 # Exported C symbols (kept in step with include/ppl.h).
 EXPORTS = ("ppl_status_string", "ppl_last_error", "ppl_version", "ppl_workspace_size",
            "ppl_importance", "ppl_importance_noalloc", "ppl_lse_ess", "ppl_resample", "ppl_resample_gather", "ppl_philox", "ppl_smc",
+           "ppl_smc_ex",
            "ppl_timing_enable", "ppl_timing_query")
 
 P = ctypes.c_void_p
@@ -44,11 +47,17 @@ class PplResult(ctypes.Structure):
     _fields_ = [("log_evidence", ctypes.c_double), ("ess", ctypes.c_double),
                 ("n_resample", ctypes.c_int64), ("status", ctypes.c_int32), ("sync_host", ctypes.c_int32),
                 ("d_scalars", P), ("d_latents", P), ("d_log_weights", P), ("d_summaries", P),
-                ("d_ess_trace", P), ("d_resampled", P), ("d_ancestors", P), ("max_events", ctypes.c_int64)]
+                ("d_ess_trace", P), ("d_resampled", P), ("d_ancestors", P), ("max_events", ctypes.c_int64),
+                ("d_event_lw", P), ("d_logz_trace", P), ("d_move_log_alpha", P)]
 
 
 class PplProposal(ctypes.Structure):
     _fields_ = [("kind", ctypes.c_int32), ("dim", ctypes.c_int32), ("d_params", P)]
+
+
+class PplSmcOptions(ctypes.Structure):
+    _fields_ = [("ess_frac", ctypes.c_double), ("move_steps", ctypes.c_int32), ("reserved", ctypes.c_int32),
+                ("move_scale", ctypes.c_double)]
 
 
 class PplError(RuntimeError):
@@ -75,6 +84,8 @@ def _load():
     L.ppl_philox.argtypes = [u64, u32, u32, u32, i64, P, P]
     L.ppl_smc.argtypes = [ctypes.c_int, ctypes.POINTER(PplData), i64, u64, f64, P, ctypes.c_size_t, P,
                           ctypes.POINTER(PplResult)]
+    L.ppl_smc_ex.argtypes = [ctypes.c_int, ctypes.POINTER(PplData), i64, u64, ctypes.POINTER(PplSmcOptions), P,
+                             ctypes.c_size_t, P, ctypes.POINTER(PplResult)]
     L.ppl_importance_noalloc.argtypes = [ctypes.c_int, ctypes.POINTER(PplData), i64, u64,
                                          ctypes.POINTER(PplProposal), P, ctypes.POINTER(PplResult)]
     L.ppl_timing_enable.argtypes = [ctypes.c_int]
@@ -223,15 +234,22 @@ def ppl_philox(seed, c1, c2, c3, n, out=None, stream=None):
 
 
 def ppl_smc(model, data, n, seed, ess_frac=0.5, ws=None, stream=None, log_weights=None, latents=None,
-            scalars=None, ess_trace=None, resampled=None, ancestors=None, sync=False):
-    """Sequential Monte Carlo; returns the ppl_result struct (host scalars when sync)."""
+            scalars=None, ess_trace=None, resampled=None, ancestors=None, sync=False, event_lw=None,
+            logz_trace=None, move_steps=0, move_scale=0.0, move_log_alpha=None):
+    """Sequential Monte Carlo (ppl_smc_ex); returns the ppl_result struct (host
+    scalars when sync).  ancestors / event_lw: [max_events, n] and
+    move_log_alpha: [max_events, move_steps, n] records of the first
+    resampling events.  move_steps > 0: resample-move (mixture model)."""
     if ws is None:
         ws = workspace(ppl_workspace_size(model, data, n, PPL_ALGO_SMC))
+    rec = next((t for t in (ancestors, event_lw, move_log_alpha) if t is not None), None)
     res = PplResult(sync_host=1 if sync else 0, d_scalars=_ptr(scalars), d_latents=_ptr(latents),
                     d_log_weights=_ptr(log_weights), d_ess_trace=_ptr(ess_trace), d_resampled=_ptr(resampled),
-                    d_ancestors=_ptr(ancestors), max_events=0 if ancestors is None else ancestors.shape[0])
-    _check(lib.ppl_smc(model, ctypes.byref(data), int(n), int(seed) & (2 ** 64 - 1), float(ess_frac), _ptr(ws),
-                       ws.numel(), _stream(stream), ctypes.byref(res)))
+                    d_ancestors=_ptr(ancestors), max_events=0 if rec is None else rec.shape[0],
+                    d_event_lw=_ptr(event_lw), d_logz_trace=_ptr(logz_trace), d_move_log_alpha=_ptr(move_log_alpha))
+    opt = PplSmcOptions(ess_frac=float(ess_frac), move_steps=int(move_steps), move_scale=float(move_scale))
+    _check(lib.ppl_smc_ex(model, ctypes.byref(data), int(n), int(seed) & (2 ** 64 - 1), ctypes.byref(opt), _ptr(ws),
+                          ws.numel(), _stream(stream), ctypes.byref(res)))
     return res
 
 
@@ -250,7 +268,8 @@ def ppl_timing_query(kernel):
 # ----------------------------------------------------------- batched SMC --
 class PplInstance(ctypes.Structure):
     _fields_ = [("y", P), ("n_data", ctypes.c_int64), ("n_particles", ctypes.c_int64), ("dim", ctypes.c_int32),
-                ("reserved", ctypes.c_int32), ("hyper", ctypes.c_double * 2)]
+                ("flags", ctypes.c_int32), ("hyper", ctypes.c_double * 2), ("move_steps", ctypes.c_int32),
+                ("reserved", ctypes.c_int32), ("move_scale", ctypes.c_double)]
 
 
 class PplTune(ctypes.Structure):
@@ -260,7 +279,8 @@ class PplTune(ctypes.Structure):
 
 class PplBatchResult(ctypes.Structure):
     _fields_ = [("d_out", P), ("d_log_weights", P), ("d_latents", P), ("d_ess_trace", P), ("d_resampled", P),
-                ("d_ancestors", P), ("max_events", ctypes.c_int64)]
+                ("d_ancestors", P), ("max_events", ctypes.c_int64), ("d_event_lw", P), ("d_logz_trace", P),
+                ("d_move_log_alpha", P)]
 
 
 def _bind_batched():
@@ -273,26 +293,38 @@ def _bind_batched():
     L.ppl_smc_autotune.argtypes = [ctypes.c_int, ctypes.c_int32, ctypes.POINTER(PplInstance), P, ctypes.c_uint64,
                                    ctypes.c_double, P, ctypes.c_size_t, P, ctypes.POINTER(PplBatchResult),
                                    ctypes.POINTER(PplTune)]
-    for n in ("ppl_smc_batched_workspace_size", "ppl_smc_batched", "ppl_smc_autotune"):
+    L.ppl_smc_tune_lookup.argtypes = [ctypes.c_int, ctypes.c_int32, ctypes.POINTER(PplInstance),
+                                      ctypes.POINTER(PplTune)]
+    L.ppl_smc_tune_cache_clear.argtypes = []
+    L.ppl_smc_tune_cache_clear.restype = None
+    for n in ("ppl_smc_batched_workspace_size", "ppl_smc_batched", "ppl_smc_autotune", "ppl_smc_tune_lookup"):
         getattr(L, n).restype = ctypes.c_int
 
 
 _bind_batched()
-EXPORTS = EXPORTS + ("ppl_smc_batched_workspace_size", "ppl_smc_batched", "ppl_smc_autotune")
+EXPORTS = EXPORTS + ("ppl_smc_batched_workspace_size", "ppl_smc_batched", "ppl_smc_autotune", "ppl_smc_tune_lookup",
+                     "ppl_smc_tune_cache_clear")
 
 
 class InstanceTable:
     """Host and device copies of a ppl_instance table (the device copy holds the same bytes)."""
 
-    def __init__(self, ys, ks, n_particles, hypers=None, device="cuda"):
+    def __init__(self, ys, ks, n_particles, hypers=None, device="cuda", record=None, move_steps=0, move_scale=0.0):
+        """record: optional list of instance indices whose resampling events are
+        recorded (the others get PPL_INST_NO_RECORD); None records every instance.
+        move_steps: resample-move steps (one value for all instances or a list)."""
         n = len(ys)
+        rec = set(range(n)) if record is None else set(int(i) for i in record)
         self.host = (PplInstance * n)()
         self._ys = ys                                  # keep the device observation tensors alive
         for i, (y, k) in enumerate(zip(ys, ks)):
             h = hypers[i] if hypers is not None else (0.0, 0.0)
             np_ = n_particles[i] if hasattr(n_particles, "__len__") else n_particles
             self.host[i] = PplInstance(y=y.data_ptr() if y.numel() else None, n_data=y.numel(), n_particles=int(np_),
-                                       dim=int(k), reserved=0, hyper=(ctypes.c_double * 2)(*h))
+                                       dim=int(k), flags=0 if i in rec else PPL_INST_NO_RECORD,
+                                       hyper=(ctypes.c_double * 2)(*h),
+                                       move_steps=int(move_steps[i] if hasattr(move_steps, "__len__") else move_steps),
+                                       move_scale=float(move_scale))
         raw = bytes(self.host)
         self.device = torch.frombuffer(bytearray(raw), dtype=torch.uint8).to(device)
         self.n = n
@@ -321,7 +353,8 @@ def ppl_smc_batched_workspace_size(model, table, tune=None):
 
 
 def ppl_smc_batched(model, table, seed, ess_frac=0.5, tune=None, ws=None, stream=None, out=None, log_weights=None,
-                    latents=None, ess_trace=None, resampled=None, ancestors=None, max_events=0):
+                    latents=None, ess_trace=None, resampled=None, ancestors=None, max_events=0, event_lw=None,
+                    logz_trace=None, move_log_alpha=None):
     """Batched SMC; returns the [n_inst, 4] FP64 device tensor (log Z, ESS, resamplings, status)."""
     if ws is None:
         ws = workspace(ppl_smc_batched_workspace_size(model, table, tune))
@@ -329,7 +362,9 @@ def ppl_smc_batched(model, table, seed, ess_frac=0.5, tune=None, ws=None, stream
         out = torch.empty((table.n, 4), dtype=torch.float64, device=ws.device)
     res = PplBatchResult(d_out=_ptr(out), d_log_weights=_ptr(log_weights), d_latents=_ptr(latents),
                          d_ess_trace=_ptr(ess_trace), d_resampled=_ptr(resampled), d_ancestors=_ptr(ancestors),
-                         max_events=int(max_events) if ancestors is not None else 0)
+                         max_events=int(max_events) if any(t is not None for t in (ancestors, event_lw, move_log_alpha))
+                         else 0, d_event_lw=_ptr(event_lw), d_logz_trace=_ptr(logz_trace),
+                         d_move_log_alpha=_ptr(move_log_alpha))
     tp, _keep = _tune_ptr(tune)
     _check(lib.ppl_smc_batched(model, table.n, table.host, _ptr(table.device), int(seed) & (2 ** 64 - 1),
                                float(ess_frac), tp, _ptr(ws), ws.numel(), _stream(stream), ctypes.byref(res)))
@@ -348,6 +383,20 @@ def ppl_smc_autotune(model, table, seed, ess_frac=0.5, ws=None, stream=None, out
                                 float(ess_frac), _ptr(ws), ws.numel(), _stream(stream), ctypes.byref(res),
                                 ctypes.byref(best)))
     return (best.particles_per_lane, best.wgs_per_instance, best.spec_block)
+
+
+def ppl_smc_tune_lookup(model, table):
+    """The (P, W, spec_block) a tune=None call would use, or None if the batch shape has no tuned entry."""
+    t = PplTune()
+    rc = lib.ppl_smc_tune_lookup(model, table.n, table.host, ctypes.byref(t))
+    if rc == PPL_E_UNSUPPORTED:
+        return None
+    _check(rc)
+    return (t.particles_per_lane, t.wgs_per_instance, t.spec_block)
+
+
+def ppl_smc_tune_cache_clear():
+    lib.ppl_smc_tune_cache_clear()
 
 
 # ------------------------------------------------------- learned proposal --

@@ -10,7 +10,9 @@
 #include <atomic>
 #include <map>
 #include <mutex>
+#include <string>
 #include <tuple>
+#include <vector>
 
 #include "batched.h"
 #include "host.h"
@@ -91,6 +93,7 @@ static int check_model_data(int model, const ppl_data *d, double hyper[8]) {
                 return fail(PPL_E_ARG, "POLY degree range must satisfy 1 <= n_lo <= n_hi <= 5");
             return PPL_OK;
         case PPL_MODEL_BLR:
+        case PPL_MODEL_BLR_STATS:
             if (d->dtype != PPL_F32) return fail(PPL_E_ARG, "BLR data must be PPL_F32");
             if (d->dim != 4 && d->dim != 8 && d->dim != 12 && d->dim != 16)
                 return fail(PPL_E_ARG, "BLR dim must be 4, 8, 12 or 16 (got %d)", d->dim);
@@ -128,7 +131,12 @@ static int check_n(int64_t n) {
     return PPL_OK;
 }
 
-static size_t is_ws_bytes(int model, int dim, int64_t n) {
+static bool is_model(int model) {
+    return model == PPL_MODEL_POLY || model == PPL_MODEL_BLR || model == PPL_MODEL_BLR_STATS || model == PPL_MODEL_GMM;
+}
+
+static size_t is_ws_bytes(int model, int dim, int64_t n, int64_t D) {
+    if (model == PPL_MODEL_BLR_STATS) return 256 + align_up(blr_stats_ws_bytes(dim, n, D), 256);
     size_t part = model == PPL_MODEL_GMM ? prop_partial_bytes(model, n) : is_partial_bytes(model, dim, n);
     if (model == PPL_MODEL_POLY) part = std::max(part, prop_partial_bytes(model, n));
     return 256 + align_up(part, 256);
@@ -153,15 +161,15 @@ static int sync_scalars(ppl_result *out, const double *d_scal, hipStream_t st) {
 int importance_call(int model, const ppl_data *data, int64_t n, uint64_t seed, const ppl_proposal *q, void *ws,
                     size_t ws_bytes, void *stream, ppl_result *out, const size_t *ws_cap) {
     if (!out) return fail(PPL_E_ARG, "out is NULL");
-    if (model != PPL_MODEL_POLY && model != PPL_MODEL_BLR && model != PPL_MODEL_GMM)
-        return fail(PPL_E_MODEL, "importance sampling supports POLY, BLR and GMM (got %d)", model);
+    if (!is_model(model))
+        return fail(PPL_E_MODEL, "importance sampling supports POLY, BLR, BLR_STATS and GMM (got %d)", model);
     if (int rc = check_n(n)) return rc;
     IsArgs a{};
     if (int rc = check_model_data(model, data, a.hyper)) return rc;
     bool mixture_path = model == PPL_MODEL_GMM;
     if (q && q->kind != PPL_Q_PRIOR) {
         if (!q->d_params) return fail(PPL_E_ARG, "proposal parameters are NULL");
-        if (q->kind == PPL_Q_GAUSS_FULL && model == PPL_MODEL_BLR) {
+        if (q->kind == PPL_Q_GAUSS_FULL && (model == PPL_MODEL_BLR || model == PPL_MODEL_BLR_STATS)) {
             if (q->dim != data->dim) return fail(PPL_E_ARG, "Gaussian proposal needs params of dim %d", data->dim);
         } else if (q->kind == PPL_Q_POLY_MIX && model == PPL_MODEL_POLY) {
             if (q->dim != 5) return fail(PPL_E_ARG, "POLY mixture proposal has dim 5 (got %d)", q->dim);
@@ -175,7 +183,7 @@ int importance_call(int model, const ppl_data *data, int64_t n, uint64_t seed, c
         }
         a.q_params = q->d_params;
     }
-    const size_t need = is_ws_bytes(model, data->dim, n);
+    const size_t need = is_ws_bytes(model, data->dim, n, data->n_data);
     if (ws_cap && need > *ws_cap)
         return fail(PPL_E_UNSUPPORTED, "%lld particles need %zu bytes of scratch; the no-allocation entry point holds %zu",
                     (long long)n, need, *ws_cap);
@@ -194,7 +202,10 @@ int importance_call(int model, const ppl_data *data, int64_t n, uint64_t seed, c
     a.scalars = out->d_scalars ? out->d_scalars : (double *)ws;
     a.part = (double *)((char *)ws + 256);
     hipStream_t st = (hipStream_t)stream;
-    if (int rc = mixture_path ? run_importance_q(a, st) : run_importance(a, st)) return rc;
+    const int rc = mixture_path ? run_importance_q(a, st)
+                   : model == PPL_MODEL_BLR_STATS ? run_importance_blr_stats(a, st)
+                                                  : run_importance(a, st);
+    if (rc) return rc;
     if (out->sync_host) return sync_scalars(out, a.scalars, st);
     return PPL_OK;
 }
@@ -233,10 +244,10 @@ int ppl_workspace_size(int model, const ppl_data *data, int64_t n, int algo, siz
         case PPL_ALGO_RESAMPLE: *bytes = align_up(resample_ws_bytes(n), 256); return PPL_OK;
         case PPL_ALGO_IS: {
             double h[8];
-            if (model != PPL_MODEL_POLY && model != PPL_MODEL_BLR && model != PPL_MODEL_GMM)
-                return fail(PPL_E_MODEL, "importance sampling supports POLY, BLR and GMM (got %d)", model);
+            if (!is_model(model))
+                return fail(PPL_E_MODEL, "importance sampling supports POLY, BLR, BLR_STATS and GMM (got %d)", model);
             if (int rc = check_model_data(model, data, h)) return rc;
-            *bytes = is_ws_bytes(model, data->dim, n);
+            *bytes = is_ws_bytes(model, data->dim, n, data->n_data);
             return PPL_OK;
         }
         case PPL_ALGO_SMC: {
@@ -305,18 +316,23 @@ int ppl_philox(uint64_t seed, uint32_t c1, uint32_t c2, uint32_t c3, int64_t n, 
     return run_philox(seed, c1, c2, c3, n, out, (hipStream_t)stream);
 }
 
-int ppl_smc(int model, const ppl_data *data, int64_t n, uint64_t seed, double ess_frac, void *ws, size_t ws_bytes,
-            void *stream, ppl_result *out) {
+int ppl_smc_ex(int model, const ppl_data *data, int64_t n, uint64_t seed, const ppl_smc_options *opt, void *ws,
+               size_t ws_bytes, void *stream, ppl_result *out) {
     clear_error();
-    if (!out) return fail(PPL_E_ARG, "out is NULL");
+    if (!out || !opt) return fail(PPL_E_ARG, "out and opt must be non-NULL");
     if (model != PPL_MODEL_LGSSM && model != PPL_MODEL_GMM)
         return fail(PPL_E_MODEL, "SMC supports LGSSM and GMM (got %d)", model);
     if (int rc = check_n(n)) return rc;
     SmcArgs a{};
     if (int rc = check_model_data(model, data, a.hyper)) return rc;
+    const double ess_frac = opt->ess_frac;
     if (!(ess_frac >= 0.0 && ess_frac <= 1.0)) return fail(PPL_E_ARG, "ess_frac must be in [0, 1]");
-    if (out->max_events < 0 || (out->max_events > 0 && !out->d_ancestors))
-        return fail(PPL_E_ARG, "d_ancestors is NULL with max_events > 0");
+    if (opt->move_steps < 0 || opt->move_steps > 64) return fail(PPL_E_ARG, "move_steps must be in 0..64");
+    if (opt->move_steps > 0 && model != PPL_MODEL_GMM)
+        return fail(PPL_E_UNSUPPORTED, "resample-move is implemented for the mixture model");
+    if (!(opt->move_scale >= 0.0) || !isfinite(opt->move_scale)) return fail(PPL_E_ARG, "move_scale must be >= 0");
+    if (out->max_events < 0 || (out->max_events > 0 && !out->d_ancestors && !out->d_event_lw && !out->d_move_log_alpha))
+        return fail(PPL_E_ARG, "max_events > 0 with no event record buffer");
     if (int rc = check_ws(ws, ws_bytes, smc_ws_bytes(model, data->dim, n))) return rc;
     if (int rc = check_device()) return rc;
     a.model = model;
@@ -327,7 +343,10 @@ int ppl_smc(int model, const ppl_data *data, int64_t n, uint64_t seed, double es
     a.seed = seed;
     a.inst = 0;
     a.ess_frac = ess_frac;
+    a.move_steps = opt->move_steps;
+    a.move_scale = opt->move_scale;
     a.out = *out;
+    if (a.move_steps == 0) a.out.d_move_log_alpha = nullptr;
     a.ws = ws;
     hipStream_t st = (hipStream_t)stream;
     if (int rc = run_smc(a, st)) return rc;
@@ -335,33 +354,117 @@ int ppl_smc(int model, const ppl_data *data, int64_t n, uint64_t seed, double es
     return PPL_OK;
 }
 
+int ppl_smc(int model, const ppl_data *data, int64_t n, uint64_t seed, double ess_frac, void *ws, size_t ws_bytes,
+            void *stream, ppl_result *out) {
+    const ppl_smc_options opt{ess_frac, 0, 0, 0.0};
+    return ppl_smc_ex(model, data, n, seed, &opt, ws, ws_bytes, stream, out);
+}
+
 // ------------------------------------------------------------ batched SMC --
 namespace {
-// Candidate configurations the autotuner times (the workspace covers them all).
-const ppl_tune kCandidates[] = {
+// Base configurations the autotuner times, each with the smallest team that
+// holds the largest instance and with twice that (fewer, wider teams).
+const ppl_tune kBaseCandidates[] = {
     {4, 0, 64, 0}, {4, 0, 128, 0}, {4, 0, 256, 0}, {2, 0, 64, 0}, {2, 0, 128, 0}, {8, 0, 64, 0}, {8, 0, 128, 0},
     {8, 0, 256, 0}, {1, 0, 64, 0}, {4, 0, 16, 0},
 };
-constexpr int kNumCandidates = sizeof(kCandidates) / sizeof(kCandidates[0]);
+
+std::vector<ppl_tune> tuner_candidates(int n, const ppl_instance *h) {
+    int64_t nmax = 1;
+    for (int i = 0; i < n; ++i) nmax = std::max<int64_t>(nmax, h[i].n_particles);
+    std::vector<ppl_tune> out;
+    for (const ppl_tune &b : kBaseCandidates) {
+        const int64_t need = (nmax + 512LL * b.particles_per_lane - 1) / (512LL * b.particles_per_lane);
+        for (int64_t w : {need, 2 * need})
+            if (w <= 64) out.push_back(ppl_tune{b.particles_per_lane, (int32_t)w, b.spec_block, 0});
+    }
+    return out;
+}
 
 struct BatchKey {
     int n;
-    int64_t sum_n, sum_d, max_n;
+    int64_t sum_n, sum_d, max_n, moves;    // moves: sum of move steps x data x K (resample-move work)
     bool operator<(const BatchKey &o) const {
-        return std::tie(n, sum_n, sum_d, max_n) < std::tie(o.n, o.sum_n, o.sum_d, o.max_n);
+        return std::tie(n, sum_n, sum_d, max_n, moves) < std::tie(o.n, o.sum_n, o.sum_d, o.max_n, o.moves);
     }
 };
 std::mutex g_tune_mu;
 std::map<BatchKey, ppl_tune> g_tune_cache;
+std::string g_cache_loaded_from;   // the cache file merged into g_tune_cache ("" = none yet)
 
 BatchKey batch_key(int n, const ppl_instance *h) {
-    BatchKey k{n, 0, 0, 0};
+    BatchKey k{n, 0, 0, 0, 0};
     for (int i = 0; i < n; ++i) {
         k.sum_n += h[i].n_particles;
         k.sum_d += h[i].n_data * h[i].dim;
         k.max_n = std::max<int64_t>(k.max_n, h[i].n_particles);
+        k.moves += (int64_t)h[i].move_steps * h[i].n_data * h[i].dim;
     }
     return k;
+}
+
+// The persisted cache: when PPL_TUNE_CACHE names a file, every autotuner
+// result is appended to it as one line
+//   ppl-tune <arch> <CUs> <n> <sum N> <sum D K> <max N> <sum M D K> <P> <W> <B>
+// and lines for the current device (architecture and CU count) are merged
+// into the in-memory cache the first time a lookup sees that file.  Lines
+// that do not parse are skipped; a file that cannot be read or written is
+// treated as absent (the cache only saves tuning time).
+bool device_tag(std::string &arch, int &cus) {
+    int dev = 0;
+    hipDeviceProp_t prop;
+    if (hipGetDevice(&dev) != hipSuccess || hipGetDeviceProperties(&prop, dev) != hipSuccess) return false;
+    arch = prop.gcnArchName;
+    const size_t colon = arch.find(':');
+    if (colon != std::string::npos) arch.resize(colon);
+    cus = prop.multiProcessorCount;
+    return true;
+}
+
+void cache_merge_file_locked() {
+    const char *path = getenv("PPL_TUNE_CACHE");
+    if (!path || !*path || g_cache_loaded_from == path) return;
+    g_cache_loaded_from = path;
+    std::string arch;
+    int cus = 0;
+    if (!device_tag(arch, cus)) return;
+    FILE *f = fopen(path, "r");
+    if (!f) return;
+    char line[512], a[128];
+    while (fgets(line, sizeof line, f)) {
+        int c = 0, n = 0, P = 0, W = 0, B = 0;
+        long long sn = 0, sd = 0, mn = 0, mv = 0;
+        if (sscanf(line, "ppl-tune %127s %d %d %lld %lld %lld %lld %d %d %d", a, &c, &n, &sn, &sd, &mn, &mv, &P, &W,
+                   &B) != 10)
+            continue;
+        if (arch != a || c != cus) continue;
+        g_tune_cache[BatchKey{n, sn, sd, mn, mv}] = ppl_tune{P, W, B, 0};
+    }
+    fclose(f);
+}
+
+void cache_store_locked(const BatchKey &k, const ppl_tune &t) {
+    g_tune_cache[k] = t;
+    const char *path = getenv("PPL_TUNE_CACHE");
+    if (!path || !*path) return;
+    std::string arch;
+    int cus = 0;
+    if (!device_tag(arch, cus)) return;
+    FILE *f = fopen(path, "a");
+    if (!f) return;
+    fprintf(f, "ppl-tune %s %d %d %lld %lld %lld %lld %d %d %d\n", arch.c_str(), cus, k.n, (long long)k.sum_n,
+            (long long)k.sum_d, (long long)k.max_n, (long long)k.moves, t.particles_per_lane, t.wgs_per_instance,
+            t.spec_block);
+    fclose(f);
+}
+
+bool cache_lookup(int n, const ppl_instance *h, ppl_tune &out) {
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    cache_merge_file_locked();
+    auto it = g_tune_cache.find(batch_key(n, h));
+    if (it == g_tune_cache.end()) return false;
+    out = it->second;
+    return true;
 }
 
 int check_batch_args(int model, int32_t n, const ppl_instance *h, const ppl_instance *d, double ess_frac) {
@@ -382,7 +485,7 @@ int ppl_smc_batched_workspace_size(int model, int32_t n, const ppl_instance *h, 
         if (!need) return fail(PPL_E_ARG, "configuration does not fit these instances");
     } else {
         need = bt_ws_bytes_for(h, n, nullptr);
-        for (const ppl_tune &c : kCandidates) need = std::max(need, bt_ws_bytes_for(h, n, &c));
+        for (const ppl_tune &c : tuner_candidates(n, h)) need = std::max(need, bt_ws_bytes_for(h, n, &c));
         if (!need) return fail(PPL_E_UNSUPPORTED, "no configuration fits these instances");
     }
     *bytes = need;
@@ -396,14 +499,7 @@ int ppl_smc_batched(int model, int32_t n, const ppl_instance *h, const ppl_insta
     if (!out) return fail(PPL_E_ARG, "out is NULL");
     if (int rc = check_batch_args(model, n, h, d, ess_frac)) return rc;
     ppl_tune cached{};
-    if (!tune) {
-        std::lock_guard<std::mutex> lk(g_tune_mu);
-        auto it = g_tune_cache.find(batch_key(n, h));
-        if (it != g_tune_cache.end()) {
-            cached = it->second;
-            tune = &cached;
-        }
-    }
+    if (!tune && cache_lookup(n, h, cached)) tune = &cached;
     const size_t need = bt_ws_bytes_for(h, n, tune);
     if (!need) return fail(PPL_E_ARG, "configuration does not fit these instances");
     if (int rc = check_ws(ws, ws_bytes, need)) return rc;
@@ -426,15 +522,16 @@ int ppl_smc_autotune(int model, int32_t n, const ppl_instance *h, const ppl_inst
     float best_ms = -1.0f;
     ppl_tune best_cfg{};
     int rc = PPL_OK;
-    for (int c = 0; c < kNumCandidates && rc == PPL_OK; ++c) {
-        const size_t need = bt_ws_bytes_for(h, n, &kCandidates[c]);
+    const std::vector<ppl_tune> cands = tuner_candidates(n, h);
+    for (size_t c = 0; c < cands.size() && rc == PPL_OK; ++c) {
+        const size_t need = bt_ws_bytes_for(h, n, &cands[c]);
         if (!need || need > ws_bytes) continue;
         ppl_tune used{};
-        rc = run_smc_batched(n, h, d, seed, ess_frac, &kCandidates[c], ws, ws_bytes, st, *out, &used);
-        if (rc == PPL_E_UNSUPPORTED) { rc = PPL_OK; continue; }     // does not fit the device
+        rc = run_smc_batched(n, h, d, seed, ess_frac, &cands[c], ws, ws_bytes, st, *out, &used);
+        if (rc == PPL_E_UNSUPPORTED || rc == PPL_E_ARG) { rc = PPL_OK; clear_error(); continue; }   // does not fit
         if (rc) break;
         if (hipEventRecord(e0, st) != hipSuccess) { rc = fail(PPL_E_HIP, "hipEventRecord failed"); break; }
-        rc = run_smc_batched(n, h, d, seed, ess_frac, &kCandidates[c], ws, ws_bytes, st, *out, &used);
+        rc = run_smc_batched(n, h, d, seed, ess_frac, &cands[c], ws, ws_bytes, st, *out, &used);
         if (rc) break;
         float ms = 0.0f;
         if (hipEventRecord(e1, st) != hipSuccess || hipEventSynchronize(e1) != hipSuccess ||
@@ -453,8 +550,23 @@ int ppl_smc_autotune(int model, int32_t n, const ppl_instance *h, const ppl_inst
     if (best_ms < 0.0f) return fail(PPL_E_UNSUPPORTED, "no candidate configuration fits the workspace and device");
     *best = best_cfg;
     std::lock_guard<std::mutex> lk(g_tune_mu);
-    g_tune_cache[batch_key(n, h)] = best_cfg;
+    cache_store_locked(batch_key(n, h), best_cfg);
     return PPL_OK;
+}
+
+int ppl_smc_tune_lookup(int model, int32_t n, const ppl_instance *h, ppl_tune *out) {
+    clear_error();
+    if (!out) return fail(PPL_E_ARG, "out is NULL");
+    if (int rc = bt_check(model, n, h)) return rc;
+    if (int rc = check_device()) return rc;
+    if (!cache_lookup(n, h, *out)) return fail(PPL_E_UNSUPPORTED, "no tuned configuration for this batch shape");
+    return PPL_OK;
+}
+
+void ppl_smc_tune_cache_clear(void) {
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    g_tune_cache.clear();
+    g_cache_loaded_from.clear();
 }
 
 }  // extern "C"

@@ -54,6 +54,7 @@ constexpr int kBtBarLine = 32;
 struct BtDev {
     const ppl_instance *inst;
     int n_inst;
+    int any_moves;           // some instance has move_steps > 0 (selects the resample-move kernel)
     Key key;
     float ess_frac;
     int W;                   // workgroups per team
@@ -64,15 +65,19 @@ struct BtDev {
     float *lw_out, *lat_out;
     double *ess_tr;
     uint8_t *res_tr;
-    int32_t *anc_out;        // [max_events * sum N], instance i at max_events * P_i as [max_events][N_i]
+    int32_t *anc_out;        // [max_events * sum' N]: recorded instance i at max_events * R_i as [max_events][N_i]
+    float *elw_out;          // same layout: the log-weights each event resampled from
+    double *logz_tr;         // [sum D]: normaliser increment added after each factor
+    double *alpha_out;       // resample-move log acceptance ratios, [max_events][M_i][N_i] per recorded instance
     int64_t max_events;
     unsigned *bar;          // [1 + teams] lines: line 0 word 1 = abort flag; line 1 + t = team t counter
     double *part;            // [teams][2][W][Bmax][3]: two copies, picked by barrier-epoch parity
     uint64_t *tot;           // [teams][W]
-    double *esum;            // [teams][W]
-    double *fin;             // [teams][W][2]
+    uint64_t *esum;          // [teams][W][2]: 128-bit fixed-point sum of the event's weights
+    uint64_t *fin;           // [teams][W][4]: 128-bit fixed-point sums of e and e^2 at the end
     uint64_t *qloc;          // [teams][cap]
     float *xbuf;             // [teams][NF][cap]
+    float *xbuf2;            // [teams][NF][cap]: gathered particles while they move (resample-move)
     uint16_t order[kBtMaxInst];           // instances in scheduling order
     uint16_t team_off[kBtMaxTeams + 1];   // team t runs order[team_off[t] .. team_off[t+1])
 };
@@ -107,6 +112,66 @@ __device__ __forceinline__ bool team_barrier(unsigned *bar, int team, unsigned t
 
 __device__ __noinline__ double bt_log(double v) { return log(v); }
 __device__ __noinline__ double bt_exp(double v) { return exp(v); }
+
+// ------------------------------------------------ exact normaliser sums ----
+// The normaliser sums the FP64 weights e = exp(lw - max) in [0, 1] as the
+// integers floor(e 2^F), F = 126 - ceil(log2 N) = 64 + k (k the quantisation
+// exponent of the resampling weights), in 128 bits.  Integer sums
+// do not depend on the order of the additions, so log Z-hat and the final ESS
+// are the same bits for every launch configuration (particles per lane,
+// workgroups per instance).  The sum stays below 2^126, and what the floors
+// drop is at most N 2^-F <= 2^-64 of a sum that is at least 1 (the largest
+// weight is 1): below FP64 rounding.
+typedef unsigned __int128 u128;
+
+// Adds floor(e 2^(k + 64)) to the 128-bit sum (hi, lo) for e in [0, 1]:
+// x = e 2^k is exact, its integer part goes to hi and its fraction, exact in
+// FP64 (x - floor(x) keeps a subset of x's bits), is scaled by 2^64 and
+// truncated into lo.  A NaN e adds nothing (the NaN status is raised elsewhere).
+__device__ __forceinline__ void bt_fix_add(uint64_t &hi, uint64_t &lo, double e, int k) {
+    if (!(e >= 0.0)) return;
+    const double x = ldexp(e, k), xi = floor(x);
+    const uint64_t l = (uint64_t)ldexp(x - xi, 64);
+    lo += l;
+    hi += (uint64_t)xi + (lo < l ? 1u : 0u);
+}
+
+__device__ __forceinline__ double bt_unfix(u128 v, int F) {
+    const double hi = (double)(uint64_t)(v >> 64), lo = (double)(uint64_t)v;
+    return ldexp(fma(hi, 18446744073709551616.0, lo), -F);
+}
+
+__device__ __forceinline__ u128 bt_wave_sum_u128(u128 v) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) {
+        const uint64_t lo = __shfl_xor((uint64_t)v, o, 64), hi = __shfl_xor((uint64_t)(v >> 64), o, 64);
+        v += ((u128)hi << 64) | lo;
+    }
+    return v;
+}
+
+// Sum over the workgroup of two 128-bit values (lds: 4 * kBtWaves words).
+__device__ __forceinline__ void bt_block_sum_u128x2(u128 &u, u128 &v, uint64_t *lds) {
+    u = bt_wave_sum_u128(u);
+    v = bt_wave_sum_u128(v);
+    const int wv = threadIdx.x >> 6;
+    if ((threadIdx.x & 63) == 0) {
+        lds[4 * wv] = (uint64_t)u;
+        lds[4 * wv + 1] = (uint64_t)(u >> 64);
+        lds[4 * wv + 2] = (uint64_t)v;
+        lds[4 * wv + 3] = (uint64_t)(v >> 64);
+    }
+    __syncthreads();
+    u128 a = 0, b = 0;
+#pragma unroll
+    for (int w = 0; w < kBtWaves; ++w) {
+        a += ((u128)lds[4 * w + 1] << 64) | lds[4 * w];
+        b += ((u128)lds[4 * w + 3] << 64) | lds[4 * w + 2];
+    }
+    __syncthreads();
+    u = a;
+    v = b;
+}
 
 // --------------------------------------------------------------- model ----
 // Mixture with K <= 8 known components, runtime K.  State: log pi_k (k < K),
@@ -154,11 +219,108 @@ __device__ __forceinline__ float bt_factor(const float st[kBtNF], float inv_sd, 
     return lconst + mx + __logf(s);
 }
 
+// ------------------------------------------------------- resample-move --
+// The move step of ppl_smc_ex (see there and smc.hip) for a team's particles:
+// after the resampling at factor s each particle takes M Metropolis-Hastings
+// steps whose target is the posterior given y_0..y_s, with the mixture factor
+// of this engine (FP32, summed in FP32 within blocks of 16 data and in FP64
+// across them).  State: log pi_k at [k], mu_k at [8 + k].
+template <int KK>
+__device__ double bt_loglik_upto(const float st[kBtNF], const float *__restrict__ y, int64_t s, float inv_sd,
+                                 float lconst) {
+    double tot = 0.0;
+    float blk = 0.0f;
+    int c = 0;
+    for (int64_t d = 0; d <= s; ++d) {
+        blk += bt_factor<KK>(st, inv_sd, lconst, y[d]);
+        if (++c == 16) {
+            tot += (double)blk;
+            blk = 0.0f;
+            c = 0;
+        }
+    }
+    return tot + (double)blk;
+}
+
+template <int KK>
+__device__ __forceinline__ double bt_log_prior(const float st[kBtNF], float inv_mu_sd) {
+    double l = 0.0;
+#pragma unroll
+    for (int k = 0; k < KK; ++k) {
+        const float r = st[8 + k] * inv_mu_sd;
+        l += (double)st[k] - 0.5 * (double)(r * r);
+    }
+    return l;
+}
+
+struct BtMove {
+    int M;
+    float h_b, h_mu, inv_mu_sd, inv_sd, lconst;
+    uint32_t c3;
+    Key key;
+    const float *y;
+};
+
+// One particle's moves; its state is read from and written back to g[f * stride].
+template <int KK>
+__device__ void bt_move(float *g, size_t stride, int64_t s, uint32_t j, BtMove mv, double *alpha_row,
+                                     int64_t N) {
+    float st[kBtNF];
+#pragma unroll
+    for (int k = 0; k < KK; ++k) {
+        st[k] = g[k * stride];
+        st[8 + k] = g[(8 + k) * stride];
+    }
+    double ll = bt_loglik_upto<KK>(st, mv.y, s, mv.inv_sd, mv.lconst);
+    double lp = bt_log_prior<KK>(st, mv.inv_mu_sd);
+    for (int m = 0; m < mv.M; ++m) {
+        float z[16];
+#pragma unroll
+        for (int b = 0; b < 4; ++b) normals4(philox(j, (uint32_t)(8 * m + b), (uint32_t)s, mv.c3, mv.key), z + 4 * b);
+        const float v = unit_f32(philox(j, (uint32_t)(8 * m + 4), (uint32_t)s, mv.c3, mv.key).x);
+        float st2[kBtNF];
+        float mx = 0.0f;
+#pragma unroll
+        for (int k = 0; k < KK - 1; ++k) {
+            st2[k] = fmaf(mv.h_b, z[k], st[k] - st[KK - 1]);
+            mx = fmaxf(mx, st2[k]);
+        }
+        float se = expf(-mx);
+#pragma unroll
+        for (int k = 0; k < KK - 1; ++k) se += expf(st2[k] - mx);
+        const float lse = mx + logf(se);
+#pragma unroll
+        for (int k = 0; k < KK - 1; ++k) st2[k] -= lse;
+        st2[KK - 1] = -lse;
+#pragma unroll
+        for (int k = 0; k < KK; ++k) st2[8 + k] = fmaf(mv.h_mu, z[KK - 1 + k], st[8 + k]);
+        const double ll2 = bt_loglik_upto<KK>(st2, mv.y, s, mv.inv_sd, mv.lconst);
+        const double lp2 = bt_log_prior<KK>(st2, mv.inv_mu_sd);
+        const double la = (ll2 + lp2) - (ll + lp);
+        if (alpha_row) alpha_row[(size_t)m * N + j] = la;
+        if (log((double)v) < la) {
+#pragma unroll
+            for (int k = 0; k < KK; ++k) {
+                st[k] = st2[k];
+                st[8 + k] = st2[8 + k];
+            }
+            ll = ll2;
+            lp = lp2;
+        }
+    }
+#pragma unroll
+    for (int k = 0; k < KK; ++k) {
+        g[k * stride] = st[k];
+        g[(8 + k) * stride] = st[8 + k];
+    }
+}
+
 // One speculative block: advance every particle's log-weight over the tb
 // data in ybuf and record, per factor, the wave's {max, s1, s2} of the
 // log-weights in wpart (a NaN log-weight poisons s1).
 template <int P, int KK>
 __device__ __forceinline__ void bt_block_factors(const float (&st)[P][kBtNF], const bool (&valid)[P], float (&lw)[P],
+                                                 float (&lwc)[P],
                                                  const float *ybuf, int tb, float inv_sd, float lconst,
                                                  float (*wpart)[kBtWaves][3], int wave, int lane) {
     for (int t = 0; t < tb; ++t) {
@@ -168,7 +330,7 @@ __device__ __forceinline__ void bt_block_factors(const float (&st)[P][kBtNF], co
 #pragma unroll
         for (int p = 0; p < P; ++p) {
             const float f = bt_factor<KK>(st[p], inv_sd, lconst, ys);
-            if (valid[p]) lw[p] += f;
+            if (valid[p]) kahan_add(lw[p], lwc[p], f);
             ml = fmaxf(ml, lw[p]);
             nan_seen |= isnan(lw[p]) ? 1 : 0;
         }
@@ -196,13 +358,14 @@ __device__ __forceinline__ void bt_block_factors(const float (&st)[P][kBtNF], co
 // Recompute the log-weights over the block's first nt data (after a rollback).
 template <int P, int KK>
 __device__ __forceinline__ void bt_block_redo(const float (&st)[P][kBtNF], const bool (&valid)[P], float (&lw)[P],
+                                              float (&lwc)[P],
                                               const float *ybuf, int nt, float inv_sd, float lconst) {
     for (int t = 0; t < nt; ++t) {
         const float ys = ybuf[t];
 #pragma unroll
         for (int p = 0; p < P; ++p) {
             const float f = bt_factor<KK>(st[p], inv_sd, lconst, ys);
-            if (valid[p]) lw[p] += f;
+            if (valid[p]) kahan_add(lw[p], lwc[p], f);
         }
     }
 }
@@ -217,25 +380,6 @@ __device__ __forceinline__ float bt_block_max(float v, float *lds) {
     for (int w = 1; w < kBtWaves; ++w) m = fmaxf(m, lds[w]);
     __syncthreads();
     return m;
-}
-
-__device__ __forceinline__ void bt_block_sum2(double &u, double &v, double *lds) {
-    u = wave_sum_dpp(u);
-    v = wave_sum_dpp(v);
-    if ((threadIdx.x & 63) == 0) {
-        lds[threadIdx.x >> 6] = u;
-        lds[kBtWaves + (threadIdx.x >> 6)] = v;
-    }
-    __syncthreads();
-    double a = 0.0, b = 0.0;
-#pragma unroll
-    for (int w = 0; w < kBtWaves; ++w) {
-        a += lds[w];
-        b += lds[kBtWaves + w];
-    }
-    __syncthreads();
-    u = a;
-    v = b;
 }
 
 __device__ __forceinline__ uint64_t bt_block_exscan(uint64_t v, uint64_t *lds, uint64_t &total) {
@@ -261,10 +405,12 @@ __device__ __forceinline__ uint64_t bt_block_exscan(uint64_t v, uint64_t *lds, u
 }
 
 // ---------------------------------------------------------------- kernel --
-template <int P>
+// MOVES: the resample-move instantiation (a separate kernel, so the moves'
+// registers never add to the plain engine's).
+template <int P, bool MOVES>
 __global__ __launch_bounds__(kBtThreads) void smc_batched_kernel(BtDev a) {
-    __shared__ double ldsd[2 * kBtWaves];
     __shared__ uint64_t ldsu[kBtWaves];
+    __shared__ uint64_t lds4[4 * kBtWaves];
     __shared__ float ybuf[kBtMaxB];
     __shared__ float wpart[kBtMaxB][kBtWaves][3];     // per-factor wave partials {max, s1, s2}
     __shared__ float sM[kBtMaxB];                      // merged max per factor
@@ -272,9 +418,10 @@ __global__ __launch_bounds__(kBtThreads) void smc_batched_kernel(BtDev a) {
     __shared__ int s_first;                            // first triggering factor in the block
     __shared__ int s_rng[2];
     __shared__ uint64_t tile_end[kBtMaxW], tile_pre[kBtMaxW];
-    extern __shared__ uint64_t dyn[];                  // stage[stage_cap] | s_anc[kBtThreads P]
+    extern __shared__ uint64_t dyn[];                  // stage[stage_cap] | s_anc[kBtThreads P] | s_c0[kBtThreads P]
     uint64_t *stage = dyn;
     int32_t *s_anc = (int32_t *)(dyn + a.stage_cap);
+    float *s_c0 = (float *)(s_anc + kBtThreads * P);
 
     const int W = a.W;
     const int team = blockIdx.x / W, wg = blockIdx.x % W;
@@ -291,10 +438,11 @@ __global__ __launch_bounds__(kBtThreads) void smc_batched_kernel(BtDev a) {
     // only after all merges of the earlier block are done.
     double *tpart2 = a.part + (size_t)team * 2 * W * a.Bmax * 3;
     uint64_t *ttot = a.tot + (size_t)team * W;
-    double *tesum = a.esum + (size_t)team * W;
-    double *tfin = a.fin + (size_t)team * W * 2;
+    uint64_t *tesum = a.esum + (size_t)team * W * 2;
+    uint64_t *tfin = a.fin + (size_t)team * W * 4;
     uint64_t *tq = a.qloc + (size_t)team * a.cap;
     float *tx = a.xbuf + (size_t)team * kBtNF * a.cap;
+    float *tx2 = a.xbuf2 + (size_t)team * kBtNF * a.cap;
 
     for (int idx = a.team_off[team]; idx < a.team_off[team + 1] && alive; ++idx) {
         const int i = a.order[idx];
@@ -306,26 +454,33 @@ __global__ __launch_bounds__(kBtThreads) void smc_batched_kernel(BtDev a) {
         const float inv_sd = (float)(1.0 / comp_sd);
         const float lconst = (float)(-0.5 * log(2.0 * M_PI) - log(comp_sd));
         const uint32_t c3 = ((uint32_t)i << 8) | kTagPrior;
-        // particle and data offsets of this instance in the concatenated outputs
-        int64_t poff = 0, doff = 0;
+        // particle, data and event-record offsets of this instance in the concatenated outputs
+        int64_t poff = 0, doff = 0, roff = 0, aoff = 0;
         for (int k = 0; k < i; ++k) {
             poff += a.inst[k].n_particles;
             doff += a.inst[k].n_data;
+            if (!(a.inst[k].flags & PPL_INST_NO_RECORD)) {
+                roff += a.inst[k].n_particles;
+                aoff += (int64_t)a.inst[k].move_steps * a.inst[k].n_particles;
+            }
         }
+        const bool record = !(I.flags & PPL_INST_NO_RECORD);
         int c = 0;
         while (((int64_t)1 << c) < N) ++c;
         const int kbits = 62 - c;
+        const int F = 64 + kbits;                    // fixed-point scale of the normaliser sums
         const double logN = bt_log((double)N);
 
         const int jb0 = wg * kTile + threadIdx.x * P;
         float st[P][kBtNF];
-        float lw[P];
+        float lw[P], lwc[P];     // log-weight and its compensation term
         bool valid[P];
 #pragma unroll
         for (int p = 0; p < P; ++p) {
             valid[p] = jb0 + p < N;
             BtGmm::init((uint32_t)(jb0 + p), c3, a.key, K, mu_sd, st[p]);
             lw[p] = valid[p] ? 0.0f : -INFINITY;
+            lwc[p] = 0.0f;
         }
 
         double logz = 0.0;
@@ -342,11 +497,15 @@ __global__ __launch_bounds__(kBtThreads) void smc_batched_kernel(BtDev a) {
             // block-start log-weights, kept in LDS for a rollback (the ancestor
             // area is free until resampling, which only starts after the rollback)
             float *s_lw0 = (float *)s_anc;
+            float *s_lwc0 = s_c0;
 #pragma unroll
-            for (int p = 0; p < P; ++p) s_lw0[threadIdx.x * P + p] = lw[p];
+            for (int p = 0; p < P; ++p) {
+                s_lw0[threadIdx.x * P + p] = lw[p];
+                s_lwc0[threadIdx.x * P + p] = lwc[p];
+            }
             switch (K) {   // the component count is the same for every thread of the team
 #define PPL_BT_CASE(KK) \
-                case KK: bt_block_factors<P, KK>(st, valid, lw, ybuf, tb, inv_sd, lconst, wpart, wave, lane); break;
+                case KK: bt_block_factors<P, KK>(st, valid, lw, lwc, ybuf, tb, inv_sd, lconst, wpart, wave, lane); break;
                 PPL_BT_CASE(1) PPL_BT_CASE(2) PPL_BT_CASE(3) PPL_BT_CASE(4)
                 PPL_BT_CASE(5) PPL_BT_CASE(6) PPL_BT_CASE(7) PPL_BT_CASE(8)
 #undef PPL_BT_CASE
@@ -399,6 +558,8 @@ __global__ __launch_bounds__(kBtThreads) void smc_batched_kernel(BtDev a) {
             if (tf == tb) {                    // no trigger: commit the block
                 if (wg == 0 && a.res_tr)
                     for (int t = threadIdx.x; t < tb; t += kBtThreads) a.res_tr[doff + t0 + t] = 0;
+                if (wg == 0 && a.logz_tr)
+                    for (int t = threadIdx.x; t < tb; t += kBtThreads) a.logz_tr[doff + t0 + t] = 0.0;
                 Mlast = sM[tb - 1];
                 t0 += tb;
                 B = std::min(2 * B, a.Bmax);
@@ -411,13 +572,18 @@ __global__ __launch_bounds__(kBtThreads) void smc_batched_kernel(BtDev a) {
             }
             if (wg == 0 && a.res_tr)
                 for (int t = threadIdx.x; t <= tf; t += kBtThreads) a.res_tr[doff + t0 + t] = t == tf ? 1 : 0;
+            if (wg == 0 && a.logz_tr)
+                for (int t = threadIdx.x; t < tf; t += kBtThreads) a.logz_tr[doff + t0 + t] = 0.0;
             // roll back to the block start and recompute up to factor tf
             if (tf < tb - 1) {
 #pragma unroll
-                for (int p = 0; p < P; ++p) lw[p] = s_lw0[threadIdx.x * P + p];
+                for (int p = 0; p < P; ++p) {
+                    lw[p] = s_lw0[threadIdx.x * P + p];
+                    lwc[p] = s_lwc0[threadIdx.x * P + p];
+                }
                 switch (K) {
 #define PPL_BT_CASE(KK) \
-                    case KK: bt_block_redo<P, KK>(st, valid, lw, ybuf, tf + 1, inv_sd, lconst); break;
+                    case KK: bt_block_redo<P, KK>(st, valid, lw, lwc, ybuf, tf + 1, inv_sd, lconst); break;
                     PPL_BT_CASE(1) PPL_BT_CASE(2) PPL_BT_CASE(3) PPL_BT_CASE(4)
                     PPL_BT_CASE(5) PPL_BT_CASE(6) PPL_BT_CASE(7) PPL_BT_CASE(8)
 #undef PPL_BT_CASE
@@ -425,48 +591,57 @@ __global__ __launch_bounds__(kBtThreads) void smc_batched_kernel(BtDev a) {
             }
             // ---- resampling at factor s = t0 + tf
             const int64_t s = t0 + tf;
-            uint64_t q[P];
-            uint64_t run = 0;
-            double esl = 0.0;
-#pragma unroll
-            for (int p = 0; p < P; ++p) {
-                const double e = valid[p] ? bt_exp((double)lw[p] - (double)Mg) : 0.0;
-                esl += e;
-                if (e >= 0.0) run += (uint64_t)floor(ldexp(e, kbits));
-                q[p] = run;
-            }
-            uint64_t btot;
-            const uint64_t off = bt_block_exscan(run, ldsu, btot);
-            double eb = esl, unused = 0.0;
-            bt_block_sum2(eb, unused, ldsd);
+            // The state goes to the staging buffer first: it is dead in registers
+            // until the gather refills it, which keeps the scan below out of scratch.
             int jb = jb0;
             asm volatile("" : "+v"(jb));
 #pragma unroll
             for (int p = 0; p < P; ++p) {
                 if (valid[p]) {
-                    tq[jb + p] = off + q[p];
 #pragma unroll
                     for (int f = 0; f < kBtNF; ++f) tx[(size_t)f * a.cap + jb + p] = st[p][f];
+                    if (a.elw_out && record && nres < a.max_events)
+                        a.elw_out[(size_t)a.max_events * roff + (size_t)nres * N + jb + p] = lw[p];
                 }
             }
+            uint64_t q[P];
+            uint64_t run = 0, fhi = 0, flo = 0;
+#pragma unroll
+            for (int p = 0; p < P; ++p) {
+                const double e = valid[p] ? bt_exp((double)lw[p] - (double)Mg) : 0.0;
+                bt_fix_add(fhi, flo, e, kbits);
+                if (e >= 0.0) run += (uint64_t)floor(ldexp(e, kbits));
+                q[p] = run;
+            }
+            uint64_t btot;
+            const uint64_t off = bt_block_exscan(run, ldsu, btot);
+#pragma unroll
+            for (int p = 0; p < P; ++p)
+                if (valid[p]) tq[jb + p] = off + q[p];
+            u128 esl = ((u128)fhi << 64) | flo, unused = 0;
+            bt_block_sum_u128x2(esl, unused, lds4);
             if (threadIdx.x == 0) {
                 ttot[wg] = btot;
-                tesum[wg] = eb;
+                tesum[2 * wg] = (uint64_t)esl;
+                tesum[2 * wg + 1] = (uint64_t)(esl >> 64);
             }
             if (!team_barrier(a.bar, team, ++epoch * (unsigned)W)) { alive = false; break; }
             {
                 const uint64_t v = threadIdx.x < W ? ttot[threadIdx.x] : 0;
-                double ev = threadIdx.x < W ? tesum[threadIdx.x] : 0.0, zero = 0.0;
+                u128 ev = threadIdx.x < W ? (((u128)tesum[2 * threadIdx.x + 1] << 64) | tesum[2 * threadIdx.x]) : 0,
+                     zero = 0;
                 uint64_t S;
                 const uint64_t ex = bt_block_exscan(v, ldsu, S);
                 if (threadIdx.x < W) {
                     tile_pre[threadIdx.x] = ex;
                     tile_end[threadIdx.x] = ex + v;
                 }
-                bt_block_sum2(ev, zero, ldsd);
+                bt_block_sum_u128x2(ev, zero, lds4);
                 const uint4 rw = philox(0, 0, (uint32_t)s, ((uint32_t)i << 8) | kTagResample, a.key);
                 const uint64_t U = __umul64hi(((uint64_t)rw.y << 32) | rw.x, S);
-                logz += (double)Mg + bt_log(ev) - logN;
+                const double inc = (double)Mg + bt_log(bt_unfix(ev, F)) - logN;
+                logz += inc;
+                if (a.logz_tr && wg == 0 && threadIdx.x == 0) a.logz_tr[doff + s] = inc;
                 ++nres;
                 const uint64_t NN = (uint64_t)N;
                 const uint64_t Sq = S / NN, Sr = S - Sq * NN;
@@ -498,8 +673,8 @@ __global__ __launch_bounds__(kBtThreads) void smc_batched_kernel(BtDev a) {
                     const int a_lo = s_rng[0], a_hi = s_rng[1];
                     const int span = a_hi - a_lo + 1;
                     const bool staged = span <= a.stage_cap;
-                    int32_t *anc_row = (a.anc_out && nres - 1 < a.max_events)
-                                           ? a.anc_out + (size_t)a.max_events * poff + (size_t)(nres - 1) * N
+                    int32_t *anc_row = (a.anc_out && record && nres - 1 < a.max_events)
+                                           ? a.anc_out + (size_t)a.max_events * roff + (size_t)(nres - 1) * N
                                            : nullptr;
                     if (staged)
                         for (int k = threadIdx.x; k < span; k += kBtThreads) {
@@ -548,13 +723,61 @@ __global__ __launch_bounds__(kBtThreads) void smc_batched_kernel(BtDev a) {
                     __syncthreads();
                 }
             }
+            if (!MOVES || I.move_steps == 0) {
+                // gather (slots past N take zeros: their state is never used)
 #pragma unroll
-            for (int p = 0; p < P; ++p) {
-                if (!valid[p]) continue;
-                const int anc = s_anc[threadIdx.x * P + p];
+                for (int p = 0; p < P; ++p) {
+                    const int anc = valid[p] ? s_anc[threadIdx.x * P + p] : 0;
 #pragma unroll
-                for (int f = 0; f < kBtNF; ++f) st[p][f] = tx[(size_t)f * a.cap + anc];
-                lw[p] = 0.0f;
+                    for (int f = 0; f < kBtNF; ++f) st[p][f] = valid[p] ? tx[(size_t)f * a.cap + anc] : 0.0f;
+                    if (valid[p]) lw[p] = 0.0f;
+                    lwc[p] = 0.0f;
+                }
+            } else if constexpr (MOVES) {
+                // resample-move: the gathered particles go through memory one at a
+                // time, so only the moving particle's state occupies registers
+#pragma unroll
+                for (int p = 0; p < P; ++p) {
+                    if (!valid[p]) continue;
+                    const int anc = s_anc[threadIdx.x * P + p];
+#pragma unroll
+                    for (int f = 0; f < kBtNF; ++f) tx2[(size_t)f * a.cap + jb + p] = tx[(size_t)f * a.cap + anc];
+                    lw[p] = 0.0f;
+                    lwc[p] = 0.0f;
+                }
+                const double nd = (double)(s + 1);
+                const double lam = I.move_scale > 0.0 ? I.move_scale : 2.38 / sqrt(2.0 * K - 1.0);
+                BtMove mv;
+                mv.M = I.move_steps;
+                mv.h_mu = (float)(lam / sqrt(1.0 / ((double)mu_sd * (double)mu_sd) + nd / ((double)K * comp_sd * comp_sd)));
+                mv.h_b = (float)(lam / sqrt(3.0 / (M_PI * M_PI) + nd / (2.0 * K)));
+                mv.inv_mu_sd = 1.0f / mu_sd;
+                mv.inv_sd = inv_sd;
+                mv.lconst = lconst;
+                mv.c3 = ((uint32_t)i << 8) | kTagMove;
+                mv.key = a.key;
+                mv.y = I.y;
+                double *arow = (a.alpha_out && record && nres - 1 < a.max_events)
+                                   ? a.alpha_out + (size_t)a.max_events * aoff + (size_t)(nres - 1) * I.move_steps * N
+                                   : nullptr;
+#pragma unroll 1
+                for (int p = 0; p < P; ++p) {
+                    const int j = jb + p;
+                    if (j >= N) break;
+                    float *g = tx2 + j;
+                    switch (K) {
+#define PPL_BT_CASE(KK) \
+                        case KK: bt_move<KK>(g, (size_t)a.cap, s, (uint32_t)j, mv, arow, N); break;
+                        PPL_BT_CASE(1) PPL_BT_CASE(2) PPL_BT_CASE(3) PPL_BT_CASE(4)
+                        PPL_BT_CASE(5) PPL_BT_CASE(6) PPL_BT_CASE(7) PPL_BT_CASE(8)
+#undef PPL_BT_CASE
+                    }
+                }
+#pragma unroll
+                for (int p = 0; p < P; ++p) {
+#pragma unroll
+                    for (int f = 0; f < kBtNF; ++f) st[p][f] = valid[p] ? tx2[(size_t)f * a.cap + jb + p] : 0.0f;
+                }
             }
             t0 = s + 1;
             B = 1;
@@ -563,28 +786,35 @@ __global__ __launch_bounds__(kBtThreads) void smc_batched_kernel(BtDev a) {
         // ---- final normaliser over the last epoch
         double ess_final = (double)N;
         if (alive && status == 0 && D > 0) {
-            double e1 = 0.0, e2 = 0.0;
+            uint64_t h1 = 0, l1 = 0, h2 = 0, l2 = 0;
 #pragma unroll
             for (int p = 0; p < P; ++p) {
                 if (valid[p]) {
                     const double e = bt_exp((double)lw[p] - (double)Mlast);
-                    e1 += e;
-                    e2 += e * e;
+                    bt_fix_add(h1, l1, e, kbits);
+                    bt_fix_add(h2, l2, e * e, kbits);
                 }
             }
-            bt_block_sum2(e1, e2, ldsd);
+            u128 e1 = ((u128)h1 << 64) | l1, e2 = ((u128)h2 << 64) | l2;
+            bt_block_sum_u128x2(e1, e2, lds4);
             if (threadIdx.x == 0) {
-                tfin[2 * wg] = e1;
-                tfin[2 * wg + 1] = e2;
+                tfin[4 * wg] = (uint64_t)e1;
+                tfin[4 * wg + 1] = (uint64_t)(e1 >> 64);
+                tfin[4 * wg + 2] = (uint64_t)e2;
+                tfin[4 * wg + 3] = (uint64_t)(e2 >> 64);
             }
             if (!team_barrier(a.bar, team, ++epoch * (unsigned)W)) {
                 alive = false;
             } else {
-                double t1 = threadIdx.x < W ? tfin[2 * threadIdx.x] : 0.0;
-                double t2 = threadIdx.x < W ? tfin[2 * threadIdx.x + 1] : 0.0;
-                bt_block_sum2(t1, t2, ldsd);
-                logz += (double)Mlast + bt_log(t1) - logN;
-                ess_final = t1 * t1 / t2;
+                const int w = threadIdx.x;
+                u128 t1 = w < W ? (((u128)tfin[4 * w + 1] << 64) | tfin[4 * w]) : 0;
+                u128 t2 = w < W ? (((u128)tfin[4 * w + 3] << 64) | tfin[4 * w + 2]) : 0;
+                bt_block_sum_u128x2(t1, t2, lds4);
+                const double s1 = bt_unfix(t1, F), s2 = bt_unfix(t2, F);
+                const double inc = (double)Mlast + bt_log(s1) - logN;
+                logz += inc;
+                if (a.logz_tr && wg == 0 && threadIdx.x == 0) a.logz_tr[doff + D - 1] = inc;
+                ess_final = s1 * s1 / s2;
             }
         }
         if (!alive) status = PPL_E_HIP;
@@ -623,9 +853,10 @@ __global__ void smc_batched_reset_kernel(unsigned *bar, int words) {
 // ------------------------------------------------------------------ host --
 struct BtLayout {
     unsigned *bar;
-    double *part, *esum, *fin;
+    double *part;
+    uint64_t *esum, *fin;
     uint64_t *tot, *qloc;
-    float *xbuf;
+    float *xbuf, *xbuf2;
     size_t bytes;
 };
 
@@ -636,11 +867,12 @@ static BtLayout bt_layout(void *ws, int teams, int W, int Bmax, int64_t cap) {
     auto take = [&](size_t n) { char *r = p + o; o += align_up(n, 256); return r; };
     L.bar = (unsigned *)take((size_t)kBtBarLine * (1 + teams) * sizeof(unsigned));
     L.part = (double *)take((size_t)teams * 2 * W * Bmax * 3 * sizeof(double));
-    L.esum = (double *)take((size_t)teams * W * sizeof(double));
-    L.fin = (double *)take((size_t)teams * W * 2 * sizeof(double));
+    L.esum = (uint64_t *)take((size_t)teams * W * 2 * sizeof(uint64_t));
+    L.fin = (uint64_t *)take((size_t)teams * W * 4 * sizeof(uint64_t));
     L.tot = (uint64_t *)take((size_t)teams * W * sizeof(uint64_t));
     L.qloc = (uint64_t *)take((size_t)teams * cap * sizeof(uint64_t));
     L.xbuf = (float *)take((size_t)teams * kBtNF * cap * sizeof(float));
+    L.xbuf2 = (float *)take((size_t)teams * kBtNF * cap * sizeof(float));
     L.bytes = o;
     return L;
 }
@@ -695,6 +927,9 @@ int bt_check(int model, int n, const ppl_instance *h) {
         if (I.n_data < 0 || I.n_data > 0x7fffffffLL) return fail(PPL_E_ARG, "instance %d: bad data length", i);
         if (I.n_data > 0 && !I.y) return fail(PPL_E_ARG, "instance %d: y is NULL", i);
         if (I.dim < 1 || I.dim > 8) return fail(PPL_E_ARG, "instance %d: K must be in 1..8", i);
+        if (I.move_steps < 0 || I.move_steps > 64) return fail(PPL_E_ARG, "instance %d: move_steps must be in 0..64", i);
+        if (!(I.move_scale >= 0.0) || !isfinite(I.move_scale))
+            return fail(PPL_E_ARG, "instance %d: move_scale must be finite and >= 0", i);
         if (!(I.hyper[0] >= 0) || !(I.hyper[1] >= 0) || !isfinite(I.hyper[0]) || !isfinite(I.hyper[1]))
             return fail(PPL_E_ARG, "instance %d: hyper-parameters must be finite and non-negative (0 = default)", i);
     }
@@ -703,16 +938,16 @@ int bt_check(int model, int n, const ppl_instance *h) {
 
 template <int P>
 static int bt_launch(BtDev &d, int nblocks, hipStream_t st) {
-    auto kern = smc_batched_kernel<P>;
+    auto kern = d.any_moves ? smc_batched_kernel<P, true> : smc_batched_kernel<P, false>;
     int dev = 0, ncu = 0, occ = 0, max_lds = 0;
     PPL_HIP(hipGetDevice(&dev));
     PPL_HIP(hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev));
     PPL_HIP(hipDeviceGetAttribute(&max_lds, hipDeviceAttributeMaxSharedMemoryPerBlock, dev));
     hipFuncAttributes fa;
     PPL_HIP(hipFuncGetAttributes(&fa, (const void *)kern));
-    const int64_t fixed = (int64_t)fa.sharedSizeBytes + (int64_t)kBtThreads * P * sizeof(int32_t);
+    const int64_t fixed = (int64_t)fa.sharedSizeBytes + (int64_t)kBtThreads * P * 2 * sizeof(int32_t);
     d.stage_cap = (int)std::max<int64_t>(0, std::min<int64_t>(kBtStage, (max_lds - fixed) / 8));
-    const size_t lds = (size_t)d.stage_cap * sizeof(uint64_t) + (size_t)kBtThreads * P * sizeof(int32_t);
+    const size_t lds = (size_t)d.stage_cap * sizeof(uint64_t) + (size_t)kBtThreads * P * 2 * sizeof(int32_t);
     PPL_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, kern, kBtThreads, lds));
     if ((int64_t)occ * ncu < nblocks)
         return fail(PPL_E_UNSUPPORTED, "batched SMC needs %d co-resident workgroups, device holds %d", nblocks, occ * ncu);
@@ -757,6 +992,7 @@ int run_smc_batched(int n, const ppl_instance *h, const ppl_instance *d_inst, ui
     d.team_off[teams] = (uint16_t)pos;
     d.inst = d_inst;
     d.n_inst = n;
+    for (int i = 0; i < n; ++i) d.any_moves |= h[i].move_steps > 0 ? 1 : 0;
     d.key = make_key(seed);
     d.ess_frac = (float)ess_frac;
     d.W = W;
@@ -768,7 +1004,10 @@ int run_smc_batched(int n, const ppl_instance *h, const ppl_instance *d_inst, ui
     d.ess_tr = out.d_ess_trace;
     d.res_tr = out.d_resampled;
     d.anc_out = out.d_ancestors;
-    d.max_events = out.d_ancestors ? out.max_events : 0;
+    d.elw_out = out.d_event_lw;
+    d.logz_tr = out.d_logz_trace;
+    d.alpha_out = out.d_move_log_alpha;
+    d.max_events = (out.d_ancestors || out.d_event_lw || out.d_move_log_alpha) ? out.max_events : 0;
     d.bar = L.bar;
     d.part = L.part;
     d.tot = L.tot;
@@ -776,6 +1015,7 @@ int run_smc_batched(int n, const ppl_instance *h, const ppl_instance *d_inst, ui
     d.fin = L.fin;
     d.qloc = L.qloc;
     d.xbuf = L.xbuf;
+    d.xbuf2 = L.xbuf2;
     hipLaunchKernelGGL(smc_batched_reset_kernel, dim3(1), dim3(256), 0, st, L.bar, kBtBarLine * (1 + teams));
     PPL_LAUNCH_CHECK("smc_batched_reset_kernel");
     if (used) *used = cfg;

@@ -21,7 +21,19 @@ constexpr uint32_t kPhiloxMulB = 0xCD9E8D57u;
 constexpr uint32_t kPhiloxWeylA = 0x9E3779B9u;
 constexpr uint32_t kPhiloxWeylB = 0xBB67AE85u;
 
-enum : uint32_t { kTagPrior = 0, kTagProposal = 1, kTagResample = 2 };
+enum : uint32_t { kTagPrior = 0, kTagProposal = 1, kTagResample = 2, kTagMove = 7 };
+
+// Compensated (Kahan) FP32 accumulation: sum += v with the running rounding
+// error kept in c.  The error of the sum stays near 2 ulp of sum |v| however
+// many terms are added, where a plain FP32 running sum loses up to a
+// relative L 2^-24 over L terms (the SMC log-weights add one term per factor
+// for as long as an epoch lasts).
+__device__ __forceinline__ void kahan_add(float &sum, float &c, float v) {
+    const float y = v - c;
+    const float t = sum + y;
+    c = (t - sum) - y;
+    sum = t;
+}
 
 struct Key {
     uint32_t k0, k1;

@@ -10,6 +10,7 @@
 // datum for different particles), so they are read with scalar loads into
 // SGPRs and used directly as the scalar operand of v_fma_f32; per-particle
 // state stays in VGPRs for the whole data loop.
+#include "blr.h"
 #include "device.h"
 #include "host.h"
 #include "kernels.h"
@@ -34,33 +35,7 @@ __global__ __launch_bounds__(kIsThreads) void blr_is_kernel(
 
     float w[P][DIM];
     double extra[P];
-#pragma unroll
-    for (int p = 0; p < P; ++p) {
-        const uint32_t i = (uint32_t)(base + p * kIsThreads + tid);
-        float z[DIM];
-#pragma unroll
-        for (int b = 0; b < DIM / 4; ++b) normals4(philox(i, b, 0, PROP ? kTagProposal : kTagPrior, key), z + 4 * b);
-        if constexpr (PROP) {
-            // w = mean + L z; extra = log p(w) - log q(w) (normalising constants cancel).
-            double zz = 0.0, ww = 0.0, logdet = 0.0;
-#pragma unroll
-            for (int r = 0; r < DIM; ++r) {
-                float v = qp[r];
-#pragma unroll
-                for (int k = 0; k <= r; ++k) v = fmaf(qp[DIM + r * DIM + k], z[k], v);
-                w[p][r] = v;
-                zz += (double)z[r] * z[r];
-                ww += (double)v * v;
-                logdet += log((double)qp[DIM + r * DIM + r]);
-            }
-            const double s = prior_sd;
-            extra[p] = (-0.5 * ww / (s * s) - DIM * log(s)) - (-0.5 * zz - logdet);
-        } else {
-#pragma unroll
-            for (int k = 0; k < DIM; ++k) w[p][k] = prior_sd * z[k];
-            extra[p] = 0.0;
-        }
-    }
+    blr_draw<P, DIM, PROP, kIsThreads>(base, tid, key, prior_sd, qp, w, extra);
 
     double acc[P];
 #pragma unroll
@@ -107,34 +82,9 @@ __global__ __launch_bounds__(kIsThreads) void blr_is_kernel(
     const double var = noise_sd * noise_sd;
     const double cterm = (double)D * (-0.5 * log(2.0 * M_PI * var));
     double lw[P];
-    Partial<DIM> part_p = partial_empty<DIM>();
-    double mloc = -INFINITY;
 #pragma unroll
-    for (int p = 0; p < P; ++p) {
-        const int64_t i = base + p * kIsThreads + tid;
-        lw[p] = (i < N) ? cterm - acc[p] / (2.0 * var) + extra[p] : -INFINITY;
-        if (i < N && isnan(lw[p])) part_p.nan += 1.0;
-        if (lw[p] > mloc) mloc = lw[p];
-        if (i < N) {
-            if (lw_out) lw_out[i] = lw[p];
-            if (lat_out) {
-#pragma unroll
-                for (int k = 0; k < DIM; ++k) lat_out[(size_t)k * N + i] = w[p][k];
-            }
-        }
-    }
-    part_p.m = mloc;
-    if (mloc > -INFINITY) {
-#pragma unroll
-        for (int p = 0; p < P; ++p) {
-            const double e = exp(lw[p] - mloc);
-            part_p.s1 += e;
-            part_p.s2 += e * e;
-#pragma unroll
-            for (int k = 0; k < DIM; ++k) part_p.f[k] += e * (double)w[p][k];
-        }
-    }
-    partial_block_reduce_store<DIM, kIsWaves>(part_p, part + (size_t)blockIdx.x * (4 + DIM));
+    for (int p = 0; p < P; ++p) lw[p] = cterm - acc[p] / (2.0 * var) + extra[p];
+    blr_finish<P, DIM, kIsThreads, kIsWaves>(base, tid, N, w, lw, lw_out, lat_out, part);
 }
 
 // ----------------------------------------------------------------- POLY --

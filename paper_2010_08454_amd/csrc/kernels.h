@@ -28,6 +28,12 @@ int run_importance(const IsArgs &a, hipStream_t st);
 size_t prop_partial_bytes(int model, int64_t N);
 int run_importance_q(const IsArgs &a, hipStream_t st);
 
+// BLR with the likelihood from sufficient statistics (PPL_MODEL_BLR_STATS):
+// workspace bytes after the 256-byte scalar slot, and the launcher (a.part is
+// that workspace).
+size_t blr_stats_ws_bytes(int dim, int64_t N, int64_t D);
+int run_importance_blr_stats(const IsArgs &a, hipStream_t st);
+
 // Normaliser of a device log-weight vector (see ppl_lse_ess).
 size_t lse_ws_bytes(int64_t n);
 int run_lse(const void *lw, bool f64, int64_t n, double *out5, void *ws, hipStream_t st);

@@ -17,6 +17,8 @@ struct SmcArgs {
     uint64_t seed;
     uint32_t inst;       // instance id carried in Philox counter word 3
     double ess_frac;
+    int move_steps;      // resample-move: MH steps per particle after each resampling (GMM)
+    double move_scale;   // random-walk scale factor (0: 2.38 / sqrt(2K - 1))
     double hyper[8];
     ppl_result out;      // caller's output pointers
     void *ws;

@@ -13,7 +13,8 @@
 // (spilled registers would be written back and refetched through HBM at
 // every grid barrier).
 // Per factor s:
-//   1. every particle advances to factor s and adds its log-factor (FP32);
+//   1. every particle advances to factor s and adds its log-factor (FP32,
+//      compensated summation);
 //   2. block partial {max lw, sum e, sum e^2}, e = exp(lw - max) -> memory;
 //      grid barrier; every block merges the partials in the same order, so
 //      every block takes the same ESS decision;
@@ -66,7 +67,13 @@ struct SmcDev {
     double *ess_trace;
     uint8_t *resampled;
     int32_t *anc_out;
+    float *elw_out;          // [max_events][N] log-weights each event resampled from
+    double *logz_tr;         // [T] normaliser increment added after factor s
+    double *alpha_out;       // [max_events][move_steps][N] log acceptance ratios of the moves
     int64_t max_events;
+    int move_steps;          // resample-move steps per particle after each resampling
+    double move_lam;         // random-walk scale factor
+    double hyp64[2];         // GMM {mu_sd, comp_sd} in FP64 (move scales)
     // workspace
     unsigned *bar;           // [0] published epoch, [1] abort flag, [32] arrival counter
     double *part;            // [2][nb][3]
@@ -75,6 +82,7 @@ struct SmcDev {
     double *fin;             // [nb][2]
     uint64_t *qloc;          // [N] tile-local inclusive prefix sums of q
     float *xbuf;             // [NF][N]
+    float *xbuf2;            // [NF][N] gathered particles while they move (resample-move)
 };
 
 // ------------------------------------------------------------- barrier --
@@ -182,6 +190,110 @@ struct Gmm {
 #pragma unroll
         for (int k = 0; k < K; ++k) s += expf(t[k] - mx);
         return (float)a.lconst + mx + logf(s);
+    }
+};
+
+// ------------------------------------------------------- resample-move --
+// After each resampling at factor s a mixture particle takes move_steps
+// Metropolis-Hastings steps whose target is the posterior given y_0..y_s
+// (particle inference of Sec. 6 with the acceptance rule of the paper's
+// Metropolis-Hastings method, Sec. 3.6.3).  Coordinates u = (log pi_k -
+// log pi_K for k < K, mu_k); prior density Dirichlet(1) (the softmax
+// Jacobian sum_k log pi_k) times Normal(0, mu_sd) per mean; symmetric Gaussian
+// random walk u' = u + h z with
+//   h_mu = lam / sqrt(1/mu_sd^2 + (s+1)/(K comp_sd^2)),
+//   h_b  = lam / sqrt(3/pi^2 + (s+1)/(2K)),
+// accepted when log v < log alpha (FP64).  Move m of slot j draws sixteen
+// normals from Philox blocks (j, 8m + b, s, inst << 8 | 7), b < 4, and v
+// from word 0 of block 8m + 4.  The log-likelihood of y_0..y_s sums the
+// model's FP32 factor within blocks of 16 data and in FP64 across blocks.
+template <int K>
+__device__ double gmm_loglik_upto(const SmcDev &a, int64_t s, const float st[2 * K]) {
+    double tot = 0.0;
+    float blk = 0.0f;
+    int c = 0;
+    for (int64_t d = 0; d <= s; ++d) {
+        blk += Gmm<K>::step(a, d, 0, const_cast<float *>(st), a.y[d]);
+        if (++c == 16) {
+            tot += (double)blk;
+            blk = 0.0f;
+            c = 0;
+        }
+    }
+    return tot + (double)blk;
+}
+
+template <int K>
+__device__ __forceinline__ double gmm_log_prior(const float st[2 * K], float inv_mu_sd) {
+    double l = 0.0;
+#pragma unroll
+    for (int k = 0; k < K; ++k) {
+        const float r = st[K + k] * inv_mu_sd;
+        l += (double)st[k] - 0.5 * (double)(r * r);
+    }
+    return l;
+}
+
+// One particle's moves; its state is read from and written back to g[f * stride].
+template <int K>
+__device__ void gmm_move(const SmcDev &a, int64_t s, uint32_t j, float *g, size_t stride,
+                                      double *alpha_row, int64_t N) {
+    float st[2 * K];
+#pragma unroll
+    for (int f = 0; f < 2 * K; ++f) st[f] = g[f * stride];
+    const double n = (double)(s + 1);
+    const float h_mu = (float)(a.move_lam / sqrt(1.0 / (a.hyp64[0] * a.hyp64[0]) +
+                                                n / ((double)K * a.hyp64[1] * a.hyp64[1])));
+    const float h_b = (float)(a.move_lam / sqrt(3.0 / (M_PI * M_PI) + n / (2.0 * K)));
+    const float inv_mu_sd = 1.0f / a.hyp[0];
+    const uint32_t c3 = (a.inst << 8) | kTagMove;
+    double ll = gmm_loglik_upto<K>(a, s, st);
+    double lp = gmm_log_prior<K>(st, inv_mu_sd);
+    for (int m = 0; m < a.move_steps; ++m) {
+        float z[16];
+#pragma unroll
+        for (int b = 0; b < 4; ++b) normals4(philox(j, (uint32_t)(8 * m + b), (uint32_t)s, c3, a.key), z + 4 * b);
+        const float v = unit_f32(philox(j, (uint32_t)(8 * m + 4), (uint32_t)s, c3, a.key).x);
+        float st2[2 * K];
+        float mx = 0.0f;
+#pragma unroll
+        for (int k = 0; k < K - 1; ++k) {
+            st2[k] = fmaf(h_b, z[k], st[k] - st[K - 1]);
+            mx = fmaxf(mx, st2[k]);
+        }
+        float se = expf(-mx);
+#pragma unroll
+        for (int k = 0; k < K - 1; ++k) se += expf(st2[k] - mx);
+        const float lse = mx + logf(se);
+#pragma unroll
+        for (int k = 0; k < K - 1; ++k) st2[k] -= lse;
+        st2[K - 1] = -lse;
+#pragma unroll
+        for (int k = 0; k < K; ++k) st2[K + k] = fmaf(h_mu, z[K - 1 + k], st[K + k]);
+        const double ll2 = gmm_loglik_upto<K>(a, s, st2);
+        const double lp2 = gmm_log_prior<K>(st2, inv_mu_sd);
+        const double la = (ll2 + lp2) - (ll + lp);
+        if (alpha_row) alpha_row[(size_t)m * N + j] = la;
+        if (log((double)v) < la) {
+#pragma unroll
+            for (int k = 0; k < 2 * K; ++k) st[k] = st2[k];
+            ll = ll2;
+            lp = lp2;
+        }
+    }
+#pragma unroll
+    for (int f = 0; f < 2 * K; ++f) g[f * stride] = st[f];
+}
+
+template <class M>
+struct MoveOf {
+    __device__ static void run(const SmcDev &, int64_t, uint32_t, float *, size_t, double *, int64_t) {}
+};
+template <int K>
+struct MoveOf<Gmm<K>> {
+    __device__ static void run(const SmcDev &a, int64_t s, uint32_t j, float *g, size_t stride, double *alpha_row,
+                               int64_t N) {
+        gmm_move<K>(a, s, j, g, stride, alpha_row, N);
     }
 };
 
@@ -325,7 +437,9 @@ __device__ __forceinline__ int find_ancestor_global(uint64_t tau, int64_t N, int
 }
 
 // ---------------------------------------------------------------- kernel --
-template <class M, int P>
+// MOVES: the resample-move instantiation (a separate kernel, so the moves'
+// registers never add to the plain filter's).
+template <class M, int P, bool MOVES>
 __global__ __launch_bounds__(kSmcThreads) void smc_persistent_kernel(SmcDev a) {
     __shared__ float ldsf[kSmcWaves];
     __shared__ double ldsd[2 * kSmcWaves];
@@ -346,13 +460,14 @@ __global__ __launch_bounds__(kSmcThreads) void smc_persistent_kernel(SmcDev a) {
     const int64_t base = (int64_t)blockIdx.x * kTile + (int64_t)threadIdx.x * P;
 
     float st[P][M::NF];
-    float lw[P];
+    float lw[P], lwc[P];     // log-weight and its compensation term
     bool valid[P];
 #pragma unroll
     for (int p = 0; p < P; ++p) {
         valid[p] = base + p < N;
         M::init(a, (uint32_t)(base + p), st[p]);
         lw[p] = valid[p] ? 0.0f : -INFINITY;
+        lwc[p] = 0.0f;
     }
 
     unsigned epoch = 0;
@@ -378,7 +493,7 @@ __global__ __launch_bounds__(kSmcThreads) void smc_persistent_kernel(SmcDev a) {
 #pragma unroll
         for (int p = 0; p < P; ++p) {
             const float f = M::step(a, s, (uint32_t)(jb + p), st[p], ys);
-            if (valid[p]) lw[p] += f;
+            if (valid[p]) kahan_add(lw[p], lwc[p], f);
         }
         // block partial for the ESS trigger
         float ml = -INFINITY;
@@ -415,8 +530,14 @@ __global__ __launch_bounds__(kSmcThreads) void smc_persistent_kernel(SmcDev a) {
         if (blockIdx.x == 0 && threadIdx.x == 0) {
             if (a.ess_trace) a.ess_trace[s] = ess;
             if (a.resampled) a.resampled[s] = res ? 1 : 0;
+            if (a.logz_tr && !res) a.logz_tr[s] = 0.0;
         }
         if (!res) continue;
+        if (a.elw_out && nres < a.max_events) {
+#pragma unroll
+            for (int p = 0; p < P; ++p)
+                if (valid[p]) a.elw_out[(size_t)nres * N + jb + p] = lw[p];
+        }
 
         // ---- resampling: FP64 weights, normaliser, integer quantisation, tile scan
         uint64_t q[P];
@@ -459,7 +580,9 @@ __global__ __launch_bounds__(kSmcThreads) void smc_persistent_kernel(SmcDev a) {
             const double ev = block_sum_f64(ev0, ldsd);     // contains the barrier for tile_*
             const uint4 rw = philox(0, 0, (uint32_t)s, (a.inst << 8) | kTagResample, a.key);
             const uint64_t U = __umul64hi(((uint64_t)rw.y << 32) | rw.x, S);
-            logz += (double)Mg + log_f64(ev) - logN;
+            const double inc = (double)Mg + log_f64(ev) - logN;
+            logz += inc;
+            if (a.logz_tr && blockIdx.x == 0 && threadIdx.x == 0) a.logz_tr[s] = inc;
             ++nres;
             const uint64_t NN = (uint64_t)N;
             const uint64_t Sq = S / NN, Sr = S - Sq * NN;
@@ -552,14 +675,42 @@ __global__ __launch_bounds__(kSmcThreads) void smc_persistent_kernel(SmcDev a) {
                 prev = anc;
             }
         }
-        // gather the ancestors' state
+        if constexpr (!MOVES) {
+            // gather the ancestors' state
 #pragma unroll
-        for (int p = 0; p < P; ++p) {
-            if (!valid[p]) continue;
-            const int anc = s_anc[threadIdx.x * P + p];
+            for (int p = 0; p < P; ++p) {
+                if (!valid[p]) continue;
+                const int anc = s_anc[threadIdx.x * P + p];
 #pragma unroll
-            for (int f = 0; f < M::NF; ++f) st[p][f] = a.xbuf[(size_t)f * N + anc];
-            lw[p] = 0.0f;
+                for (int f = 0; f < M::NF; ++f) st[p][f] = a.xbuf[(size_t)f * N + anc];
+                lw[p] = 0.0f;
+                lwc[p] = 0.0f;
+            }
+        } else {
+            // resample-move: the gathered particles go through memory one at a
+            // time, so only the moving particle's state occupies registers
+#pragma unroll
+            for (int p = 0; p < P; ++p) {
+                if (!valid[p]) continue;
+                const int anc = s_anc[threadIdx.x * P + p];
+#pragma unroll
+                for (int f = 0; f < M::NF; ++f) a.xbuf2[(size_t)f * N + jb + p] = a.xbuf[(size_t)f * N + anc];
+                lw[p] = 0.0f;
+                lwc[p] = 0.0f;
+            }
+            double *arow = (a.alpha_out && nres - 1 < a.max_events)
+                               ? a.alpha_out + (size_t)(nres - 1) * a.move_steps * N : nullptr;
+#pragma unroll 1
+            for (int p = 0; p < P; ++p) {
+                const int j = jb + p;
+                if (j >= N) break;
+                MoveOf<M>::run(a, s, (uint32_t)j, a.xbuf2 + j, (size_t)N, arow, N);
+            }
+#pragma unroll
+            for (int p = 0; p < P; ++p) {
+#pragma unroll
+                for (int f = 0; f < M::NF; ++f) st[p][f] = valid[p] ? a.xbuf2[(size_t)f * N + jb + p] : 0.0f;
+            }
         }
     }
 
@@ -586,7 +737,9 @@ __global__ __launch_bounds__(kSmcThreads) void smc_persistent_kernel(SmcDev a) {
             double t1 = threadIdx.x < nb ? a.fin[2 * threadIdx.x] : 0.0;
             double t2 = threadIdx.x < nb ? a.fin[2 * threadIdx.x + 1] : 0.0;
             block_sum2_f64(t1, t2, ldsd);
-            logz += (double)Mlast + log_f64(t1) - logN;
+            const double inc = (double)Mlast + log_f64(t1) - logN;
+            logz += inc;
+            if (a.logz_tr && blockIdx.x == 0 && threadIdx.x == 0) a.logz_tr[a.T - 1] = inc;
             ess_final = t1 * t1 / t2;
         }
     }
@@ -636,7 +789,7 @@ struct SmcLayout {
     unsigned *bar;
     double *part, *esum, *fin;
     uint64_t *tot, *qloc;
-    float *xbuf;
+    float *xbuf, *xbuf2;
     size_t bytes;
 };
 
@@ -653,6 +806,7 @@ static SmcLayout smc_layout(void *ws, int NF, int64_t N, int64_t nb) {
     L.tot = (uint64_t *)take(nb * sizeof(uint64_t));
     L.qloc = (uint64_t *)take(N * sizeof(uint64_t));
     L.xbuf = (float *)take((size_t)NF * N * sizeof(float));
+    L.xbuf2 = NF > 1 ? (float *)take((size_t)NF * N * sizeof(float)) : nullptr;   // mixture models only
     L.bytes = o;
     return L;
 }
@@ -667,7 +821,7 @@ double *smc_scalars_ptr(const SmcArgs &a) { return a.out.d_scalars ? a.out.d_sca
 
 template <class M, int P>
 static int launch(SmcDev &d, int64_t nb, hipStream_t st) {
-    auto kern = smc_persistent_kernel<M, P>;
+    auto kern = d.move_steps > 0 ? smc_persistent_kernel<M, P, true> : smc_persistent_kernel<M, P, false>;
     int dev = 0, ncu = 0, occ = 0;
     PPL_HIP(hipGetDevice(&dev));
     PPL_HIP(hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev));
@@ -733,7 +887,14 @@ int run_smc(const SmcArgs &a, hipStream_t st) {
     d.ess_trace = a.out.d_ess_trace;
     d.resampled = a.out.d_resampled;
     d.anc_out = a.out.d_ancestors;
+    d.elw_out = a.out.d_event_lw;
+    d.logz_tr = a.out.d_logz_trace;
+    d.alpha_out = a.out.d_move_log_alpha;
     d.max_events = a.out.max_events;
+    d.move_steps = a.move_steps;
+    d.move_lam = a.move_scale > 0.0 ? a.move_scale : 2.38 / sqrt(2.0 * a.K - 1.0);
+    d.hyp64[0] = a.hyper[0];
+    d.hyp64[1] = a.hyper[1];
     d.bar = L.bar;
     d.part = L.part;
     d.tot = L.tot;
@@ -741,6 +902,7 @@ int run_smc(const SmcArgs &a, hipStream_t st) {
     d.fin = L.fin;
     d.qloc = L.qloc;
     d.xbuf = L.xbuf;
+    d.xbuf2 = L.xbuf2;
     if (a.model == PPL_MODEL_LGSSM) return launch_p<Lgssm>(d, P, nb, st);
     switch (a.K) {
         case 1: return launch_p<Gmm<1>>(d, P, nb, st);

@@ -162,7 +162,7 @@ def test_blr_max_particles_sampled(ppl, orc, dev):
 
 
 # -------------------------------------------------------------------- BLR --
-def run_blr(ppl, dev, X, y, n, seed, q=None):
+def run_blr(ppl, dev, X, y, n, seed, q=None, model=None):
     import torch
     d = X.shape[1]
     dX, dy = torch.from_numpy(X).to(dev), torch.from_numpy(y).to(dev)
@@ -173,8 +173,8 @@ def run_blr(ppl, dev, X, y, n, seed, q=None):
     qt = None
     if q is not None:
         qt = torch.from_numpy(np.concatenate([q[0], q[1].ravel()]).astype(np.float32)).to(dev)
-    res = ppl.ppl_importance(ppl.PPL_MODEL_BLR, data, n, seed, q=qt, log_weights=lw, latents=lat,
-                             summaries=summ, sync=True)
+    res = ppl.ppl_importance(ppl.PPL_MODEL_BLR if model is None else model, data, n, seed, q=qt, log_weights=lw,
+                             latents=lat, summaries=summ, sync=True)
     return res, lw.cpu().numpy(), lat.cpu().numpy().astype(np.float64), summ.cpu().numpy()
 
 
@@ -251,6 +251,69 @@ def test_blr_nan_data_flags_nonfinite(ppl, dev):
     with pytest.raises(ppl.PplError) as e:
         ppl.ppl_importance(ppl.PPL_MODEL_BLR, data, 2048, 1, sync=True)
     assert e.value.code == ppl.PPL_E_NONFINITE
+
+
+# ---------------------------------------------- BLR, sufficient statistics --
+def _plain_loglik(orc, lat, X, y, idx):
+    """The plain row-by-row FP64 log-likelihood at the GPU's own latents."""
+    return np.array([orc.blr_loglik(lat[:, i], X, y) for i in idx])
+
+
+@pytest.mark.parametrize("d,D,n", [(16, 1013, 3000), (4, 77, 1025), (8, 32, 1), (12, 5, 700), (16, 10_000, 1 << 20)])
+def test_blr_stats_parity(ppl, orc, dev, d, D, n):
+    """The sufficient-statistics likelihood: the same latents as the BLR
+    model; log-weights equal to the plain FP64 likelihood at those latents to
+    1e-11 (both FP64; only the algebra differs), and within the FP32 class of
+    the oracle's own run; the normaliser consistent with the log-weights."""
+    X, y, _ = synthetic.blr_data(D=D, d=d, seed=11)
+    seed = 7
+    res, lw, lat, summ = run_blr(ppl, dev, X, y, n, seed, model=ppl.PPL_MODEL_BLR_STATS)
+    _, lw_rows, lat_rows, _ = run_blr(ppl, dev, X, y, n, seed)
+    assert np.array_equal(lat, lat_rows)
+    g = np.random.default_rng(d + D)
+    idx = np.unique(np.concatenate([[0, n - 1], g.integers(0, n, 200), [int(np.argmax(lw))]]))
+    assert mixed_err(lw[idx], _plain_loglik(orc, lat, X, y, idx)) < 1e-11
+    assert mixed_err(lw, lw_rows) < 1e-5
+    rlw, rlat = orc.particle_logweights(orc.MODEL_BLR, X, y, idx, seed, dim=d)
+    assert mixed_err(lw[idx], rlw) < 1e-5
+    assert mixed_err(lat[:, idx].T, rlat) < 2e-6
+    assert abs(res.log_evidence - (lse_np(lw) - math.log(n))) < 1e-10 * max(1.0, abs(res.log_evidence))
+    mean_gpu, ess_gpu = weighted_summary(lw, lat)
+    assert abs(res.ess - ess_gpu) < 1e-9 * ess_gpu
+    assert mixed_err(summ, mean_gpu) < 1e-9
+
+
+def test_blr_stats_posterior_proposal_and_closed_form(ppl, orc, dev):
+    """q = N(mu, 1.2^2 Sigma) on the full data: the log-evidence agrees with
+    the closed form within 4 standard errors, the posterior mean within 5,
+    and the log-weights with the oracle's run of the same draws."""
+    from oracle import closed_forms as cf
+    X, y, _ = synthetic.blr_data()
+    ex = cf.blr_exact(X, y)
+    L = np.linalg.cholesky(1.44 * ex["cov"])
+    n, seed = 1 << 16, 3
+    res, lw, lat, summ = run_blr(ppl, dev, X, y, n, seed, q=(ex["mean"], L), model=ppl.PPL_MODEL_BLR_STATS)
+    q32 = (ex["mean"].astype(np.float32).astype(np.float64), L.astype(np.float32).astype(np.float64))
+    idx = np.unique(np.concatenate([[0, n - 1], np.random.default_rng(5).integers(0, n, 200)]))
+    rlw, _ = orc.particle_logweights(orc.MODEL_BLR, X, y, idx, seed, dim=16, q=q32)
+    assert mixed_err(lw[idx], rlw) < 1e-5
+    assert res.ess > 0.2 * n
+    sig = math.sqrt(1 / res.ess - 1 / n)
+    assert abs(res.log_evidence - ex["log_z"]) < 4 * sig
+    se = np.sqrt(np.diag(ex["cov"]) / res.ess)
+    assert np.all(np.abs(summ - ex["mean"]) < 5 * se)
+
+
+def test_blr_stats_no_data_is_exact(ppl, dev):
+    """No rows: every log-weight is 0, log Z-hat = 0 and ESS = N exactly."""
+    import torch
+    X = np.zeros((0, 16), np.float32)
+    y = np.zeros(0, np.float32)
+    data = ppl.make_data(torch.zeros(16, device=dev), torch.zeros(1, device=dev), n_data=0, dim=16)
+    lw = torch.empty(5000, dtype=torch.float64, device=dev)
+    res = ppl.ppl_importance(ppl.PPL_MODEL_BLR_STATS, data, 5000, 2, log_weights=lw, sync=True)
+    assert res.log_evidence == 0.0 and res.ess == 5000.0 and X.size == y.size == 0
+    assert np.all(lw.cpu().numpy() == 0.0)
 
 
 # ------------------------------------------------------------- normaliser --

@@ -14,6 +14,7 @@ import numpy as np
 import pytest
 
 import synthetic
+from forced_check import check_forced
 
 pytestmark = pytest.mark.gpu
 
@@ -31,7 +32,7 @@ def ppl():
     return p
 
 
-def run_gpu(ppl, model, y, n, seed, ess_frac=0.5, K=0, max_events=0):
+def run_gpu(ppl, model, y, n, seed, ess_frac=0.5, K=0, max_events=0, records=False, move_steps=0):
     import torch
     dev = torch.device("cuda:0")
     dy = torch.from_numpy(np.ascontiguousarray(y, dtype=np.float32)).to(dev)
@@ -44,13 +45,23 @@ def run_gpu(ppl, model, y, n, seed, ess_frac=0.5, K=0, max_events=0):
     ess = torch.zeros(T, dtype=torch.float64, device=dev)
     res_flag = torch.zeros(T, dtype=torch.uint8, device=dev)
     anc = torch.full((max_events, n), -7, dtype=torch.int32, device=dev) if max_events else None
+    elw = torch.full((max_events, n), float("nan"), dtype=torch.float32, device=dev) if records else None
+    lzt = torch.full((T,), float("nan"), dtype=torch.float64, device=dev)
+    alpha = (torch.full((max_events, move_steps, n), float("nan"), dtype=torch.float64, device=dev)
+             if (records and move_steps) else None)
     r = ppl.ppl_smc(model, data, n, seed, ess_frac, log_weights=lw, latents=lat, scalars=scal, ess_trace=ess,
-                    resampled=res_flag, ancestors=anc, sync=True)
+                    resampled=res_flag, ancestors=anc, sync=True, event_lw=elw, logz_trace=lzt,
+                    move_steps=move_steps, move_log_alpha=alpha)
     out = dict(log_z=r.log_evidence, ess=r.ess, n_resample=r.n_resample, lw=lw.cpu().numpy().astype(np.float64),
                state=lat.cpu().numpy().astype(np.float64), ess_trace=ess.cpu().numpy()[:y.size],
-               resampled=res_flag.cpu().numpy()[:y.size].astype(bool), scalars=scal.cpu().numpy())
+               resampled=res_flag.cpu().numpy()[:y.size].astype(bool), scalars=scal.cpu().numpy(),
+               logz_trace=lzt.cpu().numpy()[:y.size])
     if max_events:
         out["ancestors"] = anc.cpu().numpy()
+    if records:
+        out["event_lw"] = elw.cpu().numpy()
+    if alpha is not None:
+        out["alpha"] = alpha[: max(r.n_resample, 1)].cpu().numpy()
     return out
 
 
@@ -179,3 +190,89 @@ def test_gmm_no_resampling_parity(ppl, orc):
     assert mixed_err(g["state"], o["state"]) < 2e-6 * 5
     assert mixed_err(g["lw"], o["lw"]) < LW_TOL
     assert abs(g["log_z"] - o["log_z"]) < LW_TOL * max(1.0, abs(o["log_z"]))
+
+
+def _pick_p(n):
+    """Particles per thread of the persistent SMC kernel: one 512-thread
+    workgroup per CU (256 CUs) covers n with P in {1, 2, 4, 8}."""
+    per_cu, p = -(-n // 256), 1
+    while p < 8 and 512 * p < per_cu:
+        p *= 2
+    return p
+
+
+@pytest.mark.parametrize("n,T,p", [((1 << 17) + 3, 200, 2), ((1 << 18) + 7, 150, 4), ((1 << 19) + 5, 100, 8),
+                                   (1 << 20, 200, 8)])
+def test_lgssm_teacher_forced(ppl, orc, n, T, p):
+    """Teacher-forced parity over the whole run at the particle counts that
+    select 2, 4 and 8 particles per thread (the galloping ancestor search and
+    the incremental slot thresholds run only there; ragged last tiles), and
+    at the measured N = 2^20: every non-tie ancestor at every event, the
+    event log-weights, the normaliser increments, the final particles and
+    log Z-hat."""
+    assert _pick_p(n) == p
+    y = synthetic.lgssm_data(T=T, seed=41)
+    seed = 13
+    g = run_gpu(ppl, ppl.PPL_MODEL_LGSSM, y, n, seed, ess_frac=0.5, max_events=T, records=True)
+    E = g["n_resample"]
+    assert E >= T // 3
+    f = orc.smc_forced(orc.MODEL_LGSSM, y.astype(np.float64), n, seed, g["resampled"], g["ancestors"][:E],
+                       g["event_lw"][:E], ess_band=ESS_BAND, want_state=True)
+    print(check_forced(g, f, n, full=True, min_events=T // 3))
+
+
+@pytest.mark.parametrize("K,D,n,p", [(5, 300, (1 << 17) + 3, 2), (8, 120, (1 << 19) + 5, 8)])
+def test_gmm_teacher_forced(ppl, orc, K, D, n, p):
+    assert _pick_p(n) == p
+    inst = synthetic.gmm_instances(1, seed=K * 100 + D, d_lo=math.log10(D), d_hi=math.log10(D) + 1e-9, k_lo=K, k_hi=K)[0]
+    y = inst["y"][:D]
+    seed = 17
+    g = run_gpu(ppl, ppl.PPL_MODEL_GMM, y, n, seed, K=K, max_events=D, records=True)
+    E = g["n_resample"]
+    f = orc.smc_forced(orc.MODEL_GMM, y.astype(np.float64), n, seed, g["resampled"], g["ancestors"][:E],
+                       g["event_lw"][:E], K=K, ess_band=ESS_BAND, want_state=True)
+    print(check_forced(g, f, n, full=True, min_events=5))
+
+
+@pytest.mark.parametrize("K,D,n,M", [(3, 120, 4096, 2), (1, 60, 3000, 3), (8, 80, 20_000, 1), (5, 150, (1 << 17) + 3, 1)])
+def test_gmm_resample_move_teacher_forced(ppl, orc, K, D, n, M):
+    """Resample-move: after each resampling every particle takes M
+    Metropolis-Hastings steps.  Teacher-forced against the oracle over the
+    whole run: ancestors, event log-weights and normaliser increments as for
+    plain SMC, and every accept decision outside the tie band of the two
+    runs' log acceptance ratios, which agree to FP32 rounding."""
+    inst = synthetic.gmm_instances(1, seed=K * 31 + D, d_lo=math.log10(D), d_hi=math.log10(D) + 1e-9, k_lo=K, k_hi=K)[0]
+    y = inst["y"][:D]
+    seed = 29
+    g = run_gpu(ppl, ppl.PPL_MODEL_GMM, y, n, seed, K=K, max_events=D, records=True, move_steps=M)
+    E = g["n_resample"]
+    assert E >= 3
+    f = orc.smc_forced(orc.MODEL_GMM, y.astype(np.float64), n, seed, g["resampled"], g["ancestors"][:E],
+                       g["event_lw"][:E], K=K, ess_band=ESS_BAND, want_state=True, move_steps=M,
+                       given_alpha=g["alpha"][:E])
+    summary = check_forced(g, f, n, full=True, min_events=3)
+    mv = f["moves"]
+    assert np.all(mv["nontie_diff"] == 0), mv["nontie_diff"]
+    assert float(mv["max_dalpha"].max()) <= 1e-5
+    decisions = E * M * n
+    assert mv["ties"].sum() <= 1e-3 * decisions + 10
+    a = g["alpha"][:E]
+    assert np.all(np.isfinite(a))
+    rate = float(np.mean(np.minimum(1.0, np.exp(a))))
+    assert 0.02 < rate < 0.98
+    summary.update(move_ties=int(mv["ties"].sum()), move_adopted=int(mv["adopted"].sum()), accept_rate=round(rate, 3))
+    print(summary)
+
+
+def test_gmm_resample_move_keeps_particles_distinct(ppl):
+    """Without moves the static-parameter particles collapse onto a few
+    values; with moves they stay distinct (the reason for the move step).
+    (A collapsed population has ESS = N, so it resamples less often.)"""
+    inst = synthetic.gmm_instances(1, seed=8, d_lo=math.log10(300), d_hi=math.log10(300) + 1e-9, k_lo=4, k_hi=4)[0]
+    y = inst["y"][:300]
+    n = 1 << 16
+    plain = run_gpu(ppl, ppl.PPL_MODEL_GMM, y, n, 3, K=4)
+    moved = run_gpu(ppl, ppl.PPL_MODEL_GMM, y, n, 3, K=4, move_steps=2)
+    d_plain = np.unique(plain["state"][4]).size
+    d_moved = np.unique(moved["state"][4]).size
+    assert d_moved > 100 * d_plain and d_moved > n // 4, (d_plain, d_moved)
