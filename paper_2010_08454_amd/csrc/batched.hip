@@ -73,7 +73,7 @@ struct BtDev {
     unsigned *bar;          // [1 + teams] lines: line 0 word 1 = abort flag; line 1 + t = team t counter
     double *part;            // [teams][2][W][Bmax][3]: two copies, picked by barrier-epoch parity
     uint64_t *tot;           // [teams][W]
-    uint64_t *esum;          // [teams][W][2]: 128-bit fixed-point sum of the event's weights
+    double *esum;            // [teams][W]: sum of the fraction words r of the event's weights (exact)
     uint64_t *fin;           // [teams][W][4]: 128-bit fixed-point sums of e and e^2 at the end
     uint64_t *qloc;          // [teams][cap]
     float *xbuf;             // [teams][NF][cap]
@@ -114,14 +114,19 @@ __device__ __noinline__ double bt_log(double v) { return log(v); }
 __device__ __noinline__ double bt_exp(double v) { return exp(v); }
 
 // ------------------------------------------------ exact normaliser sums ----
-// The normaliser sums the FP64 weights e = exp(lw - max) in [0, 1] as the
-// integers floor(e 2^F), F = 126 - ceil(log2 N) = 64 + k (k the quantisation
-// exponent of the resampling weights), in 128 bits.  Integer sums
-// do not depend on the order of the additions, so log Z-hat and the final ESS
-// are the same bits for every launch configuration (particles per lane,
-// workgroups per instance).  The sum stays below 2^126, and what the floors
-// drop is at most N 2^-F <= 2^-64 of a sum that is at least 1 (the largest
-// weight is 1): below FP64 rounding.
+// The normaliser sums the FP64 weights e = exp(lw - max), in [0, 1], as
+// integers, whose sums do not depend on the order of the additions: log Z-hat
+// and the final ESS are then the same bits for every launch configuration
+// (particles per lane, workgroups per instance).  With k the quantisation
+// exponent of the resampling weights (x = e 2^k is exact):
+//   - at a resampling event the sum is (S + 2^-32 R) 2^-k, where S = sum
+//     floor(x) is the resampling total and R = sum floor(frac(x) 2^32); R's
+//     partial sums are integers below 2^50, exact in FP64 in any grouping, so
+//     the cheap FP64 wave reductions serve;
+//   - at the end of a run the sums of e and e^2 are floor(x 2^64) in 128-bit
+//     integers.
+// What the floors drop is at most N 2^-(k+32) <= 2^-32 (events) or N 2^-(k+64)
+// (end) of a sum that is at least 1 (the largest weight is 1).
 typedef unsigned __int128 u128;
 
 // Adds floor(e 2^(k + 64)) to the 128-bit sum (hi, lo) for e in [0, 1]:
@@ -174,28 +179,28 @@ __device__ __forceinline__ void bt_block_sum_u128x2(u128 &u, u128 &v, uint64_t *
 }
 
 // --------------------------------------------------------------- model ----
-// Mixture with K <= 8 known components, runtime K.  State: log pi_k (k < K),
-// mu_k at [8 + k].  Prior draws as in the single-instance SMC.
-struct BtGmm {
-    __device__ static void init(uint32_t j, uint32_t c3, Key key, int K, float mu_sd, float st[kBtNF]) {
-        const uint4 w0 = philox(j, 0, 0, c3, key), w1 = philox(j, 1, 0, c3, key);
-        const uint32_t w[8] = {w0.x, w0.y, w0.z, w0.w, w1.x, w1.y, w1.z, w1.w};
-        float E[8], tot = 0.0f;
+// Mixture with KK <= 8 known components.  State (registers and the staging
+// buffers): log pi_k at [k], mu_k at [KK + k].  Prior draws as in the
+// single-instance SMC.
+template <int KK>
+__device__ __forceinline__ void bt_init(uint32_t j, uint32_t c3, Key key, float mu_sd, float st[2 * KK]) {
+    const uint4 w0 = philox(j, 0, 0, c3, key), w1 = philox(j, 1, 0, c3, key);
+    const uint32_t w[8] = {w0.x, w0.y, w0.z, w0.w, w1.x, w1.y, w1.z, w1.w};
+    float E[KK], tot = 0.0f;
 #pragma unroll
-        for (int k = 0; k < 8; ++k) {
-            E[k] = k < K ? -logf(unit_f32(w[k])) : 0.0f;
-            tot += E[k];
-        }
-        float z[8];
-        normals4(philox(j, 2, 0, c3, key), z);
-        normals4(philox(j, 3, 0, c3, key), z + 4);
-#pragma unroll
-        for (int k = 0; k < 8; ++k) {
-            st[k] = k < K ? logf(E[k] / tot) : -INFINITY;
-            st[8 + k] = mu_sd * z[k];
-        }
+    for (int k = 0; k < KK; ++k) {
+        E[k] = -logf(unit_f32(w[k]));
+        tot += E[k];
     }
-};
+    float z[8];
+    normals4(philox(j, 2, 0, c3, key), z);
+    normals4(philox(j, 3, 0, c3, key), z + 4);
+#pragma unroll
+    for (int k = 0; k < KK; ++k) {
+        st[k] = logf(E[k] / tot);
+        st[KK + k] = mu_sd * z[k];
+    }
+}
 
 // log sum_k pi_k N(y; mu_k, sd), shifted by the largest term, for a
 // compile-time component count KK (fully unrolled: no per-component branch
@@ -203,11 +208,11 @@ struct BtGmm {
 // the hardware's (v_exp_f32 / v_log_f32, about 1 ulp); their error is far
 // below the FP32 rounding of the log-weight sum over the data.
 template <int KK>
-__device__ __forceinline__ float bt_factor(const float st[kBtNF], float inv_sd, float lconst, float ys) {
+__device__ __forceinline__ float bt_factor(const float *st, float inv_sd, float lconst, float ys) {
     float t[KK];
 #pragma unroll
     for (int k = 0; k < KK; ++k) {
-        const float r = (ys - st[8 + k]) * inv_sd;
+        const float r = (ys - st[KK + k]) * inv_sd;
         t[k] = fmaf(-0.5f * r, r, st[k]);
     }
     float mx = t[0];
@@ -224,9 +229,9 @@ __device__ __forceinline__ float bt_factor(const float st[kBtNF], float inv_sd, 
 // after the resampling at factor s each particle takes M Metropolis-Hastings
 // steps whose target is the posterior given y_0..y_s, with the mixture factor
 // of this engine (FP32, summed in FP32 within blocks of 16 data and in FP64
-// across them).  State: log pi_k at [k], mu_k at [8 + k].
+// across them).  State: log pi_k at [k], mu_k at [KK + k].
 template <int KK>
-__device__ double bt_loglik_upto(const float st[kBtNF], const float *__restrict__ y, int64_t s, float inv_sd,
+__device__ double bt_loglik_upto(const float *st, const float *__restrict__ y, int64_t s, float inv_sd,
                                  float lconst) {
     double tot = 0.0;
     float blk = 0.0f;
@@ -243,11 +248,11 @@ __device__ double bt_loglik_upto(const float st[kBtNF], const float *__restrict_
 }
 
 template <int KK>
-__device__ __forceinline__ double bt_log_prior(const float st[kBtNF], float inv_mu_sd) {
+__device__ __forceinline__ double bt_log_prior(const float *st, float inv_mu_sd) {
     double l = 0.0;
 #pragma unroll
     for (int k = 0; k < KK; ++k) {
-        const float r = st[8 + k] * inv_mu_sd;
+        const float r = st[KK + k] * inv_mu_sd;
         l += (double)st[k] - 0.5 * (double)(r * r);
     }
     return l;
@@ -265,11 +270,11 @@ struct BtMove {
 template <int KK>
 __device__ void bt_move(float *g, size_t stride, int64_t s, uint32_t j, BtMove mv, double *alpha_row,
                                      int64_t N) {
-    float st[kBtNF];
+    float st[2 * KK];
 #pragma unroll
     for (int k = 0; k < KK; ++k) {
         st[k] = g[k * stride];
-        st[8 + k] = g[(8 + k) * stride];
+        st[KK + k] = g[(KK + k) * stride];
     }
     double ll = bt_loglik_upto<KK>(st, mv.y, s, mv.inv_sd, mv.lconst);
     double lp = bt_log_prior<KK>(st, mv.inv_mu_sd);
@@ -278,7 +283,7 @@ __device__ void bt_move(float *g, size_t stride, int64_t s, uint32_t j, BtMove m
 #pragma unroll
         for (int b = 0; b < 4; ++b) normals4(philox(j, (uint32_t)(8 * m + b), (uint32_t)s, mv.c3, mv.key), z + 4 * b);
         const float v = unit_f32(philox(j, (uint32_t)(8 * m + 4), (uint32_t)s, mv.c3, mv.key).x);
-        float st2[kBtNF];
+        float st2[2 * KK];
         float mx = 0.0f;
 #pragma unroll
         for (int k = 0; k < KK - 1; ++k) {
@@ -293,7 +298,7 @@ __device__ void bt_move(float *g, size_t stride, int64_t s, uint32_t j, BtMove m
         for (int k = 0; k < KK - 1; ++k) st2[k] -= lse;
         st2[KK - 1] = -lse;
 #pragma unroll
-        for (int k = 0; k < KK; ++k) st2[8 + k] = fmaf(mv.h_mu, z[KK - 1 + k], st[8 + k]);
+        for (int k = 0; k < KK; ++k) st2[KK + k] = fmaf(mv.h_mu, z[KK - 1 + k], st[KK + k]);
         const double ll2 = bt_loglik_upto<KK>(st2, mv.y, s, mv.inv_sd, mv.lconst);
         const double lp2 = bt_log_prior<KK>(st2, mv.inv_mu_sd);
         const double la = (ll2 + lp2) - (ll + lp);
@@ -302,7 +307,7 @@ __device__ void bt_move(float *g, size_t stride, int64_t s, uint32_t j, BtMove m
 #pragma unroll
             for (int k = 0; k < KK; ++k) {
                 st[k] = st2[k];
-                st[8 + k] = st2[8 + k];
+                st[KK + k] = st2[KK + k];
             }
             ll = ll2;
             lp = lp2;
@@ -311,7 +316,7 @@ __device__ void bt_move(float *g, size_t stride, int64_t s, uint32_t j, BtMove m
 #pragma unroll
     for (int k = 0; k < KK; ++k) {
         g[k * stride] = st[k];
-        g[(8 + k) * stride] = st[8 + k];
+        g[(KK + k) * stride] = st[KK + k];
     }
 }
 
@@ -319,7 +324,7 @@ __device__ void bt_move(float *g, size_t stride, int64_t s, uint32_t j, BtMove m
 // data in ybuf and record, per factor, the wave's {max, s1, s2} of the
 // log-weights in wpart (a NaN log-weight poisons s1).
 template <int P, int KK>
-__device__ __forceinline__ void bt_block_factors(const float (&st)[P][kBtNF], const bool (&valid)[P], float (&lw)[P],
+__device__ __forceinline__ void bt_block_factors(const float (&st)[P][2 * KK], const bool (&valid)[P], float (&lw)[P],
                                                  float (&lwc)[P],
                                                  const float *ybuf, int tb, float inv_sd, float lconst,
                                                  float (*wpart)[kBtWaves][3], int wave, int lane) {
@@ -357,7 +362,7 @@ __device__ __forceinline__ void bt_block_factors(const float (&st)[P][kBtNF], co
 
 // Recompute the log-weights over the block's first nt data (after a rollback).
 template <int P, int KK>
-__device__ __forceinline__ void bt_block_redo(const float (&st)[P][kBtNF], const bool (&valid)[P], float (&lw)[P],
+__device__ __forceinline__ void bt_block_redo(const float (&st)[P][2 * KK], const bool (&valid)[P], float (&lw)[P],
                                               float (&lwc)[P],
                                               const float *ybuf, int nt, float inv_sd, float lconst) {
     for (int t = 0; t < nt; ++t) {
@@ -382,6 +387,18 @@ __device__ __forceinline__ float bt_block_max(float v, float *lds) {
     return m;
 }
 
+// Sum over the workgroup (waves in a fixed order; lds: kBtWaves doubles).
+__device__ __forceinline__ double bt_block_sum_f64(double v, double *lds) {
+    v = wave_sum_dpp(v);
+    if ((threadIdx.x & 63) == 0) lds[threadIdx.x >> 6] = v;
+    __syncthreads();
+    double t = 0.0;
+#pragma unroll
+    for (int w = 0; w < kBtWaves; ++w) t += lds[w];
+    __syncthreads();
+    return t;
+}
+
 __device__ __forceinline__ uint64_t bt_block_exscan(uint64_t v, uint64_t *lds, uint64_t &total) {
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
     uint64_t incl = v;
@@ -404,6 +421,435 @@ __device__ __forceinline__ uint64_t bt_block_exscan(uint64_t v, uint64_t *lds, u
     return off + incl - v;
 }
 
+// Context a workgroup carries from one instance to the next: its place in
+// the grid, the team's slices of the workspace and the kernel's LDS arrays.
+struct BtCtx {
+    int W, team, wg, lane, wave;
+    unsigned epoch;
+    bool alive;
+    double *tpart2;
+    uint64_t *ttot, *tfin, *tq;
+    double *tesum;
+    float *tx, *tx2;
+    uint64_t *ldsu, *lds4;
+    double *ldsd;
+    float *ybuf;
+    float (*wpart)[kBtWaves][3];
+    float *sM;
+    unsigned char *sBad;
+    int *s_first, *s_rng;
+    uint64_t *tile_end, *tile_pre, *stage;
+    int32_t *s_anc;
+    float *s_c0;
+};
+
+// One instance from its prior draw to its outputs, with the component count
+// KK fixed at compile time: a particle's state takes 2 KK registers, so teams
+// holding small-K instances keep eight particles per lane in registers.
+template <int P, int KK, bool MOVES>
+__device__ __forceinline__ void bt_instance(const BtDev &a, BtCtx &cx, int i) {
+    const int W = cx.W, team = cx.team, wg = cx.wg, lane = cx.lane, wave = cx.wave;
+    unsigned &epoch = cx.epoch;
+    bool &alive = cx.alive;
+    double *tpart2 = cx.tpart2;
+    uint64_t *ttot = cx.ttot, *tfin = cx.tfin, *tq = cx.tq;
+    double *tesum = cx.tesum;
+    float *tx = cx.tx, *tx2 = cx.tx2;
+    uint64_t *ldsu = cx.ldsu, *lds4 = cx.lds4;
+    double *ldsd = cx.ldsd;
+    float *ybuf = cx.ybuf;
+    float (*wpart)[kBtWaves][3] = cx.wpart;
+    float *sM = cx.sM;
+    unsigned char *sBad = cx.sBad;
+    int &s_first = *cx.s_first;
+    int *s_rng = cx.s_rng;
+    uint64_t *tile_end = cx.tile_end, *tile_pre = cx.tile_pre, *stage = cx.stage;
+    int32_t *s_anc = cx.s_anc;
+    float *s_c0 = cx.s_c0;
+    constexpr int kTile = kBtThreads * P;
+    const ppl_instance I = a.inst[i];
+    const int64_t N = I.n_particles, D = I.n_data;
+    const int K = I.dim;
+    const float mu_sd = I.hyper[0] > 0 ? (float)I.hyper[0] : 5.0f;
+    const double comp_sd = I.hyper[1] > 0 ? I.hyper[1] : 1.0;
+    const float inv_sd = (float)(1.0 / comp_sd);
+    const float lconst = (float)(-0.5 * log(2.0 * M_PI) - log(comp_sd));
+    const uint32_t c3 = ((uint32_t)i << 8) | kTagPrior;
+    // particle, data and event-record offsets of this instance in the concatenated outputs
+    int64_t poff = 0, doff = 0, roff = 0, aoff = 0;
+    for (int k = 0; k < i; ++k) {
+        poff += a.inst[k].n_particles;
+        doff += a.inst[k].n_data;
+        if (!(a.inst[k].flags & PPL_INST_NO_RECORD)) {
+            roff += a.inst[k].n_particles;
+            aoff += (int64_t)a.inst[k].move_steps * a.inst[k].n_particles;
+        }
+    }
+    const bool record = !(I.flags & PPL_INST_NO_RECORD);
+    int c = 0;
+    while (((int64_t)1 << c) < N) ++c;
+    const int kbits = 62 - c;
+    const int F = 64 + kbits;                    // fixed-point scale of the normaliser sums
+    const double logN = bt_log((double)N);
+
+    const int jb0 = wg * kTile + threadIdx.x * P;
+    float st[P][2 * KK];
+    float lw[P], lwc[P];     // log-weight and its compensation term
+    bool valid[P];
+#pragma unroll
+    for (int p = 0; p < P; ++p) {
+        valid[p] = jb0 + p < N;
+        bt_init<KK>((uint32_t)(jb0 + p), c3, a.key, mu_sd, st[p]);
+        lw[p] = valid[p] ? 0.0f : -INFINITY;
+        lwc[p] = 0.0f;
+    }
+
+    double logz = 0.0;
+    int64_t nres = 0;
+    int status = 0;
+    float Mlast = 0.0f;
+    int64_t t0 = 0;
+    int B = 1;
+    while (t0 < D) {
+        const int tb = (int)std::min<int64_t>(B, D - t0);
+        __syncthreads();
+        for (int t = threadIdx.x; t < tb; t += kBtThreads) ybuf[t] = I.y[t0 + t];
+        __syncthreads();
+        // block-start log-weights, kept in LDS for a rollback (the ancestor
+        // area is free until resampling, which only starts after the rollback)
+        float *s_lw0 = (float *)s_anc;
+        float *s_lwc0 = s_c0;
+#pragma unroll
+        for (int p = 0; p < P; ++p) {
+            s_lw0[threadIdx.x * P + p] = lw[p];
+            s_lwc0[threadIdx.x * P + p] = lwc[p];
+        }
+        bt_block_factors<P, KK>(st, valid, lw, lwc, ybuf, tb, inv_sd, lconst, wpart, wave, lane);
+        __syncthreads();
+        // workgroup partial per factor: merge the waves in order
+        double *tpart = tpart2 + (size_t)((epoch + 1) & 1) * W * a.Bmax * 3;
+        for (int t = threadIdx.x; t < tb; t += kBtThreads) {
+            float m = -INFINITY;
+            for (int w = 0; w < kBtWaves; ++w) m = fmaxf(m, wpart[t][w][0]);
+            double s1 = 0.0, s2 = 0.0;
+            if (m > -INFINITY) {
+                for (int w = 0; w < kBtWaves; ++w) {
+                    const float cw = expf(wpart[t][w][0] - m);
+                    s1 += (double)wpart[t][w][1] * cw;
+                    s2 += (double)wpart[t][w][2] * (double)(cw * cw);
+                }
+            }
+            double *dst = tpart + ((size_t)wg * a.Bmax + t) * 3;
+            dst[0] = (double)m;
+            dst[1] = s1;
+            dst[2] = s2;
+        }
+        if (!team_barrier(a.bar, team, ++epoch * (unsigned)W)) { alive = false; break; }
+        // team merge per factor (same order in every workgroup) and the trigger
+        if (threadIdx.x == 0) s_first = tb;
+        __syncthreads();
+        for (int t = threadIdx.x; t < tb; t += kBtThreads) {
+            float m = -INFINITY;
+            for (int w = 0; w < W; ++w) m = fmaxf(m, (float)tpart[((size_t)w * a.Bmax + t) * 3]);
+            double s1 = 0.0, s2 = 0.0;
+            if (m > -INFINITY) {
+                for (int w = 0; w < W; ++w) {
+                    const double *src = tpart + ((size_t)w * a.Bmax + t) * 3;
+                    const float cw = expf((float)src[0] - m);
+                    s1 += src[1] * cw;
+                    s2 += src[2] * (double)(cw * cw);
+                }
+            }
+            sM[t] = m;
+            const double ess = s1 * s1 / s2;
+            const bool bad = !(m > -INFINITY) || !(s1 > 0.0) || isnan(s1) || isnan(s2);
+            sBad[t] = bad ? (m > -INFINITY ? 2 : 1) : 0;
+            const bool trig = bad || ((t0 + t < D - 1) && ess < (double)a.ess_frac * (double)N);
+            if (wg == 0 && a.ess_tr) a.ess_tr[doff + t0 + t] = bad ? 0.0 : ess;
+            if (trig) atomicMin(&s_first, t);
+        }
+        __syncthreads();
+        const int tf = s_first;
+        if (tf == tb) {                    // no trigger: commit the block
+            if (wg == 0 && a.res_tr)
+                for (int t = threadIdx.x; t < tb; t += kBtThreads) a.res_tr[doff + t0 + t] = 0;
+            if (wg == 0 && a.logz_tr)
+                for (int t = threadIdx.x; t < tb; t += kBtThreads) a.logz_tr[doff + t0 + t] = 0.0;
+            Mlast = sM[tb - 1];
+            t0 += tb;
+            B = std::min(2 * B, a.Bmax);
+            continue;
+        }
+        const float Mg = sM[tf];
+        if (sBad[tf]) {                    // the same verdict in every workgroup of the team
+            status = sBad[tf] == 1 ? PPL_E_ZERO_WEIGHT : PPL_E_NONFINITE;
+            break;
+        }
+        if (wg == 0 && a.res_tr)
+            for (int t = threadIdx.x; t <= tf; t += kBtThreads) a.res_tr[doff + t0 + t] = t == tf ? 1 : 0;
+        if (wg == 0 && a.logz_tr)
+            for (int t = threadIdx.x; t < tf; t += kBtThreads) a.logz_tr[doff + t0 + t] = 0.0;
+        // roll back to the block start and recompute up to factor tf
+        if (tf < tb - 1) {
+#pragma unroll
+            for (int p = 0; p < P; ++p) {
+                lw[p] = s_lw0[threadIdx.x * P + p];
+                lwc[p] = s_lwc0[threadIdx.x * P + p];
+            }
+            bt_block_redo<P, KK>(st, valid, lw, lwc, ybuf, tf + 1, inv_sd, lconst);
+        }
+        // ---- resampling at factor s = t0 + tf
+        const int64_t s = t0 + tf;
+        // The state goes to the staging buffer first: it is dead in registers
+        // until the gather refills it, which keeps the scan below out of scratch.
+        int jb = jb0;
+        asm volatile("" : "+v"(jb));
+#pragma unroll
+        for (int p = 0; p < P; ++p) {
+            if (valid[p]) {
+#pragma unroll
+                for (int f = 0; f < 2 * KK; ++f) tx[(size_t)f * a.cap + jb + p] = st[p][f];
+                if (a.elw_out && record && nres < a.max_events)
+                    a.elw_out[(size_t)a.max_events * roff + (size_t)nres * N + jb + p] = lw[p];
+            }
+        }
+        // integer weights q = floor(e 2^k) and the next 32 bits of each, r =
+        // floor(frac(e 2^k) 2^32): the normaliser is (sum q + 2^-32 sum r) 2^-k,
+        // where sum q is the resampling total S and sum r is exact in FP64
+        // (integers below 2^50 in any grouping), so it does not depend on the
+        // launch shape
+        uint64_t q[P];
+        uint64_t run = 0;
+        double rsum = 0.0;
+#pragma unroll
+        for (int p = 0; p < P; ++p) {
+            const double e = valid[p] ? bt_exp((double)lw[p] - (double)Mg) : 0.0;
+            if (e >= 0.0) {
+                const double x = ldexp(e, kbits), xi = floor(x);
+                run += (uint64_t)xi;
+                rsum += floor(ldexp(x - xi, 32));
+            }
+            q[p] = run;
+        }
+        uint64_t btot;
+        const uint64_t off = bt_block_exscan(run, ldsu, btot);
+#pragma unroll
+        for (int p = 0; p < P; ++p)
+            if (valid[p]) tq[jb + p] = off + q[p];
+        rsum = bt_block_sum_f64(rsum, ldsd);
+        if (threadIdx.x == 0) {
+            ttot[wg] = btot;
+            tesum[wg] = rsum;
+        }
+        if (!team_barrier(a.bar, team, ++epoch * (unsigned)W)) { alive = false; break; }
+        {
+            const uint64_t v = threadIdx.x < W ? ttot[threadIdx.x] : 0;
+            const double rv = threadIdx.x < W ? tesum[threadIdx.x] : 0.0;
+            uint64_t S;
+            const uint64_t ex = bt_block_exscan(v, ldsu, S);
+            if (threadIdx.x < W) {
+                tile_pre[threadIdx.x] = ex;
+                tile_end[threadIdx.x] = ex + v;
+            }
+            const double R = bt_block_sum_f64(rv, ldsd);
+            const uint4 rw = philox(0, 0, (uint32_t)s, ((uint32_t)i << 8) | kTagResample, a.key);
+            const uint64_t U = __umul64hi(((uint64_t)rw.y << 32) | rw.x, S);
+            const double ev = ldexp((double)S, -kbits) + ldexp(R, -(kbits + 32));
+            const double inc = (double)Mg + bt_log(ev) - logN;
+            logz += inc;
+            if (a.logz_tr && wg == 0 && threadIdx.x == 0) a.logz_tr[doff + s] = inc;
+            ++nres;
+            const uint64_t NN = (uint64_t)N;
+            const uint64_t Sq = S / NN, Sr = S - Sq * NN;
+            // ancestors: min{a : Q_a > tau_j}, tau_j = j Sq + floor((j Sr + U) / N)
+            const int js0 = wg * kTile;
+            const int js1 = (int)std::min<int64_t>((int64_t)js0 + kTile, N) - 1;
+            if (js0 < N) {
+                for (int e = 0; e < 2; ++e) {
+                    if (threadIdx.x == 64 * e) {
+                        const int jj = e ? js1 : js0;
+                        const uint64_t num = (uint64_t)jj * Sr + U;
+                        const uint64_t tau = (uint64_t)jj * Sq + num / NN;
+                        int lo = 0, hi = W - 1;
+                        while (lo < hi) {
+                            const int mid = (lo + hi) >> 1;
+                            if (tile_end[mid] > tau) hi = mid; else lo = mid + 1;
+                        }
+                        int a0 = lo * kTile, a1 = (int)std::min<int64_t>((int64_t)a0 + kTile, N) - 1;
+                        while (a0 < a1) {
+                            const int mid = (a0 + a1) >> 1;
+                            if (tile_pre[lo] + tq[mid] > tau) a1 = mid; else a0 = mid + 1;
+                        }
+                        s_rng[e] = a0;
+                    }
+                }
+            }
+            __syncthreads();
+            if (js0 < N) {
+                const int a_lo = s_rng[0], a_hi = s_rng[1];
+                const int span = a_hi - a_lo + 1;
+                const bool staged = span <= a.stage_cap;
+                int32_t *anc_row = (a.anc_out && record && nres - 1 < a.max_events)
+                                       ? a.anc_out + (size_t)a.max_events * roff + (size_t)(nres - 1) * N
+                                       : nullptr;
+                if (staged)
+                    for (int k = threadIdx.x; k < span; k += kBtThreads) {
+                        const int aa = a_lo + k;
+                        stage[k] = tile_pre[aa / kTile] + tq[aa];
+                    }
+                __syncthreads();
+                int prev = a_lo;
+                uint64_t num = (uint64_t)jb * Sr + U;
+                uint64_t quo = num / NN, rem = num - quo * NN;
+#pragma unroll 1
+                for (int p = 0; p < P; ++p) {
+                    const int j = jb + p;
+                    if (j >= N) break;
+                    if (p) {
+                        rem += Sr;
+                        if (rem >= NN) { rem -= NN; ++quo; }
+                    }
+                    const uint64_t tau = (uint64_t)j * Sq + quo;
+                    int anc;
+                    if (staged) {
+                        int lo = prev - a_lo, hi = span - 1;
+                        while (lo < hi) {
+                            const int mid = (lo + hi) >> 1;
+                            if (stage[mid] > tau) hi = mid; else lo = mid + 1;
+                        }
+                        anc = a_lo + lo;
+                    } else {
+                        int lo = prev / kTile, hi = W - 1;
+                        while (lo < hi) {
+                            const int mid = (lo + hi) >> 1;
+                            if (tile_end[mid] > tau) hi = mid; else lo = mid + 1;
+                        }
+                        int a0 = std::max(lo * kTile, prev), a1 = (int)std::min<int64_t>((int64_t)lo * kTile + kTile, N) - 1;
+                        while (a0 < a1) {
+                            const int mid = (a0 + a1) >> 1;
+                            if (tile_pre[lo] + tq[mid] > tau) a1 = mid; else a0 = mid + 1;
+                        }
+                        anc = a0;
+                    }
+                    s_anc[threadIdx.x * P + p] = anc;
+                    if (anc_row) anc_row[j] = anc;
+                    prev = anc;
+                }
+            } else {
+                __syncthreads();
+            }
+        }
+        if (!MOVES || I.move_steps == 0) {
+            // gather (slots past N take zeros: their state is never used)
+#pragma unroll
+            for (int p = 0; p < P; ++p) {
+                const int anc = valid[p] ? s_anc[threadIdx.x * P + p] : 0;
+#pragma unroll
+                for (int f = 0; f < 2 * KK; ++f) st[p][f] = valid[p] ? tx[(size_t)f * a.cap + anc] : 0.0f;
+                if (valid[p]) lw[p] = 0.0f;
+                lwc[p] = 0.0f;
+            }
+        } else if constexpr (MOVES) {
+            // resample-move: the gathered particles go through memory one at a
+            // time, so only the moving particle's state occupies registers
+#pragma unroll
+            for (int p = 0; p < P; ++p) {
+                if (!valid[p]) continue;
+                const int anc = s_anc[threadIdx.x * P + p];
+#pragma unroll
+                for (int f = 0; f < 2 * KK; ++f) tx2[(size_t)f * a.cap + jb + p] = tx[(size_t)f * a.cap + anc];
+                lw[p] = 0.0f;
+                lwc[p] = 0.0f;
+            }
+            const double nd = (double)(s + 1);
+            const double lam = I.move_scale > 0.0 ? I.move_scale : 2.38 / sqrt(2.0 * K - 1.0);
+            BtMove mv;
+            mv.M = I.move_steps;
+            mv.h_mu = (float)(lam / sqrt(1.0 / ((double)mu_sd * (double)mu_sd) + nd / ((double)K * comp_sd * comp_sd)));
+            mv.h_b = (float)(lam / sqrt(3.0 / (M_PI * M_PI) + nd / (2.0 * K)));
+            mv.inv_mu_sd = 1.0f / mu_sd;
+            mv.inv_sd = inv_sd;
+            mv.lconst = lconst;
+            mv.c3 = ((uint32_t)i << 8) | kTagMove;
+            mv.key = a.key;
+            mv.y = I.y;
+            double *arow = (a.alpha_out && record && nres - 1 < a.max_events)
+                               ? a.alpha_out + (size_t)a.max_events * aoff + (size_t)(nres - 1) * I.move_steps * N
+                               : nullptr;
+#pragma unroll 1
+            for (int p = 0; p < P; ++p) {
+                const int j = jb + p;
+                if (j >= N) break;
+                float *g = tx2 + j;
+                bt_move<KK>(g, (size_t)a.cap, s, (uint32_t)j, mv, arow, N);
+            }
+#pragma unroll
+            for (int p = 0; p < P; ++p) {
+#pragma unroll
+                for (int f = 0; f < 2 * KK; ++f) st[p][f] = valid[p] ? tx2[(size_t)f * a.cap + jb + p] : 0.0f;
+            }
+        }
+        t0 = s + 1;
+        B = 1;
+    }
+
+    // ---- final normaliser over the last epoch
+    double ess_final = (double)N;
+    if (alive && status == 0 && D > 0) {
+        uint64_t h1 = 0, l1 = 0, h2 = 0, l2 = 0;
+#pragma unroll
+        for (int p = 0; p < P; ++p) {
+            if (valid[p]) {
+                const double e = bt_exp((double)lw[p] - (double)Mlast);
+                bt_fix_add(h1, l1, e, kbits);
+                bt_fix_add(h2, l2, e * e, kbits);
+            }
+        }
+        u128 e1 = ((u128)h1 << 64) | l1, e2 = ((u128)h2 << 64) | l2;
+        bt_block_sum_u128x2(e1, e2, lds4);
+        if (threadIdx.x == 0) {
+            tfin[4 * wg] = (uint64_t)e1;
+            tfin[4 * wg + 1] = (uint64_t)(e1 >> 64);
+            tfin[4 * wg + 2] = (uint64_t)e2;
+            tfin[4 * wg + 3] = (uint64_t)(e2 >> 64);
+        }
+        if (!team_barrier(a.bar, team, ++epoch * (unsigned)W)) {
+            alive = false;
+        } else {
+            const int w = threadIdx.x;
+            u128 t1 = w < W ? (((u128)tfin[4 * w + 1] << 64) | tfin[4 * w]) : 0;
+            u128 t2 = w < W ? (((u128)tfin[4 * w + 3] << 64) | tfin[4 * w + 2]) : 0;
+            bt_block_sum_u128x2(t1, t2, lds4);
+            const double s1 = bt_unfix(t1, F), s2 = bt_unfix(t2, F);
+            const double inc = (double)Mlast + bt_log(s1) - logN;
+            logz += inc;
+            if (a.logz_tr && wg == 0 && threadIdx.x == 0) a.logz_tr[doff + D - 1] = inc;
+            ess_final = s1 * s1 / s2;
+        }
+    }
+    if (!alive) status = PPL_E_HIP;
+    // outputs
+#pragma unroll
+    for (int p = 0; p < P; ++p) {
+        if (!valid[p]) continue;
+        const int64_t j = jb0 + p;
+        if (a.lw_out) a.lw_out[poff + j] = lw[p];
+        if (a.lat_out) {
+#pragma unroll
+            for (int f = 0; f < 2 * KK; ++f) a.lat_out[(size_t)kBtNF * poff + (size_t)f * N + j] = st[p][f];
+        }
+    }
+    if (wg == 0 && threadIdx.x == 0) {
+        double *o = a.out + 4 * (size_t)i;
+        o[0] = status ? (status == PPL_E_ZERO_WEIGHT ? -INFINITY : NAN) : logz;
+        o[1] = status ? 0.0 : ess_final;
+        o[2] = (double)nres;
+        o[3] = (double)status;
+    }
+    // all workgroups of the team leave the instance together before its buffers are reused
+    if (alive && !team_barrier(a.bar, team, ++epoch * (unsigned)W)) alive = false;
+}
+
 // ---------------------------------------------------------------- kernel --
 // MOVES: the resample-move instantiation (a separate kernel, so the moves'
 // registers never add to the plain engine's).
@@ -411,6 +857,7 @@ template <int P, bool MOVES>
 __global__ __launch_bounds__(kBtThreads) void smc_batched_kernel(BtDev a) {
     __shared__ uint64_t ldsu[kBtWaves];
     __shared__ uint64_t lds4[4 * kBtWaves];
+    __shared__ double ldsd[kBtWaves];
     __shared__ float ybuf[kBtMaxB];
     __shared__ float wpart[kBtMaxB][kBtWaves][3];     // per-factor wave partials {max, s1, s2}
     __shared__ float sM[kBtMaxB];                      // merged max per factor
@@ -425,10 +872,6 @@ __global__ __launch_bounds__(kBtThreads) void smc_batched_kernel(BtDev a) {
 
     const int W = a.W;
     const int team = blockIdx.x / W, wg = blockIdx.x % W;
-    constexpr int kTile = kBtThreads * P;
-    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-    unsigned epoch = 0;
-    bool alive = true;
 
     // Per-factor partials have two copies, used alternately by consecutive block
     // barriers (copy = parity of the barrier epoch the writes precede).  After a
@@ -436,415 +879,51 @@ __global__ __launch_bounds__(kBtThreads) void smc_batched_kernel(BtDev a) {
     // slower one may still be merging this block's; the copies keep them apart.
     // Reuse of a copy is two barriers later, which every workgroup has passed
     // only after all merges of the earlier block are done.
-    double *tpart2 = a.part + (size_t)team * 2 * W * a.Bmax * 3;
-    uint64_t *ttot = a.tot + (size_t)team * W;
-    uint64_t *tesum = a.esum + (size_t)team * W * 2;
-    uint64_t *tfin = a.fin + (size_t)team * W * 4;
-    uint64_t *tq = a.qloc + (size_t)team * a.cap;
-    float *tx = a.xbuf + (size_t)team * kBtNF * a.cap;
-    float *tx2 = a.xbuf2 + (size_t)team * kBtNF * a.cap;
+    BtCtx cx;
+    cx.W = W;
+    cx.team = team;
+    cx.wg = wg;
+    cx.lane = threadIdx.x & 63;
+    cx.wave = threadIdx.x >> 6;
+    cx.epoch = 0;
+    cx.alive = true;
+    cx.tpart2 = a.part + (size_t)team * 2 * W * a.Bmax * 3;
+    cx.ttot = a.tot + (size_t)team * W;
+    cx.tesum = a.esum + (size_t)team * W;
+    cx.tfin = a.fin + (size_t)team * W * 4;
+    cx.tq = a.qloc + (size_t)team * a.cap;
+    cx.tx = a.xbuf + (size_t)team * kBtNF * a.cap;
+    cx.tx2 = a.xbuf2 + (size_t)team * kBtNF * a.cap;
+    cx.ldsu = ldsu;
+    cx.lds4 = lds4;
+    cx.ldsd = ldsd;
+    cx.ybuf = ybuf;
+    cx.wpart = wpart;
+    cx.sM = sM;
+    cx.sBad = sBad;
+    cx.s_first = &s_first;
+    cx.s_rng = s_rng;
+    cx.tile_end = tile_end;
+    cx.tile_pre = tile_pre;
+    cx.stage = stage;
+    cx.s_anc = s_anc;
+    cx.s_c0 = s_c0;
 
-    for (int idx = a.team_off[team]; idx < a.team_off[team + 1] && alive; ++idx) {
+    for (int idx = a.team_off[team]; idx < a.team_off[team + 1] && cx.alive; ++idx) {
         const int i = a.order[idx];
-        const ppl_instance I = a.inst[i];
-        const int64_t N = I.n_particles, D = I.n_data;
-        const int K = I.dim;
-        const float mu_sd = I.hyper[0] > 0 ? (float)I.hyper[0] : 5.0f;
-        const double comp_sd = I.hyper[1] > 0 ? I.hyper[1] : 1.0;
-        const float inv_sd = (float)(1.0 / comp_sd);
-        const float lconst = (float)(-0.5 * log(2.0 * M_PI) - log(comp_sd));
-        const uint32_t c3 = ((uint32_t)i << 8) | kTagPrior;
-        // particle, data and event-record offsets of this instance in the concatenated outputs
-        int64_t poff = 0, doff = 0, roff = 0, aoff = 0;
-        for (int k = 0; k < i; ++k) {
-            poff += a.inst[k].n_particles;
-            doff += a.inst[k].n_data;
-            if (!(a.inst[k].flags & PPL_INST_NO_RECORD)) {
-                roff += a.inst[k].n_particles;
-                aoff += (int64_t)a.inst[k].move_steps * a.inst[k].n_particles;
-            }
+        switch (a.inst[i].dim) {   // the same for every thread of the team
+            case 1: bt_instance<P, 1, MOVES>(a, cx, i); break;
+            case 2: bt_instance<P, 2, MOVES>(a, cx, i); break;
+            case 3: bt_instance<P, 3, MOVES>(a, cx, i); break;
+            case 4: bt_instance<P, 4, MOVES>(a, cx, i); break;
+            case 5: bt_instance<P, 5, MOVES>(a, cx, i); break;
+            case 6: bt_instance<P, 6, MOVES>(a, cx, i); break;
+            case 7: bt_instance<P, 7, MOVES>(a, cx, i); break;
+            case 8: bt_instance<P, 8, MOVES>(a, cx, i); break;
         }
-        const bool record = !(I.flags & PPL_INST_NO_RECORD);
-        int c = 0;
-        while (((int64_t)1 << c) < N) ++c;
-        const int kbits = 62 - c;
-        const int F = 64 + kbits;                    // fixed-point scale of the normaliser sums
-        const double logN = bt_log((double)N);
-
-        const int jb0 = wg * kTile + threadIdx.x * P;
-        float st[P][kBtNF];
-        float lw[P], lwc[P];     // log-weight and its compensation term
-        bool valid[P];
-#pragma unroll
-        for (int p = 0; p < P; ++p) {
-            valid[p] = jb0 + p < N;
-            BtGmm::init((uint32_t)(jb0 + p), c3, a.key, K, mu_sd, st[p]);
-            lw[p] = valid[p] ? 0.0f : -INFINITY;
-            lwc[p] = 0.0f;
-        }
-
-        double logz = 0.0;
-        int64_t nres = 0;
-        int status = 0;
-        float Mlast = 0.0f;
-        int64_t t0 = 0;
-        int B = 1;
-        while (t0 < D) {
-            const int tb = (int)std::min<int64_t>(B, D - t0);
-            __syncthreads();
-            for (int t = threadIdx.x; t < tb; t += kBtThreads) ybuf[t] = I.y[t0 + t];
-            __syncthreads();
-            // block-start log-weights, kept in LDS for a rollback (the ancestor
-            // area is free until resampling, which only starts after the rollback)
-            float *s_lw0 = (float *)s_anc;
-            float *s_lwc0 = s_c0;
-#pragma unroll
-            for (int p = 0; p < P; ++p) {
-                s_lw0[threadIdx.x * P + p] = lw[p];
-                s_lwc0[threadIdx.x * P + p] = lwc[p];
-            }
-            switch (K) {   // the component count is the same for every thread of the team
-#define PPL_BT_CASE(KK) \
-                case KK: bt_block_factors<P, KK>(st, valid, lw, lwc, ybuf, tb, inv_sd, lconst, wpart, wave, lane); break;
-                PPL_BT_CASE(1) PPL_BT_CASE(2) PPL_BT_CASE(3) PPL_BT_CASE(4)
-                PPL_BT_CASE(5) PPL_BT_CASE(6) PPL_BT_CASE(7) PPL_BT_CASE(8)
-#undef PPL_BT_CASE
-            }
-            __syncthreads();
-            // workgroup partial per factor: merge the waves in order
-            double *tpart = tpart2 + (size_t)((epoch + 1) & 1) * W * a.Bmax * 3;
-            for (int t = threadIdx.x; t < tb; t += kBtThreads) {
-                float m = -INFINITY;
-                for (int w = 0; w < kBtWaves; ++w) m = fmaxf(m, wpart[t][w][0]);
-                double s1 = 0.0, s2 = 0.0;
-                if (m > -INFINITY) {
-                    for (int w = 0; w < kBtWaves; ++w) {
-                        const float cw = expf(wpart[t][w][0] - m);
-                        s1 += (double)wpart[t][w][1] * cw;
-                        s2 += (double)wpart[t][w][2] * (double)(cw * cw);
-                    }
-                }
-                double *dst = tpart + ((size_t)wg * a.Bmax + t) * 3;
-                dst[0] = (double)m;
-                dst[1] = s1;
-                dst[2] = s2;
-            }
-            if (!team_barrier(a.bar, team, ++epoch * (unsigned)W)) { alive = false; break; }
-            // team merge per factor (same order in every workgroup) and the trigger
-            if (threadIdx.x == 0) s_first = tb;
-            __syncthreads();
-            for (int t = threadIdx.x; t < tb; t += kBtThreads) {
-                float m = -INFINITY;
-                for (int w = 0; w < W; ++w) m = fmaxf(m, (float)tpart[((size_t)w * a.Bmax + t) * 3]);
-                double s1 = 0.0, s2 = 0.0;
-                if (m > -INFINITY) {
-                    for (int w = 0; w < W; ++w) {
-                        const double *src = tpart + ((size_t)w * a.Bmax + t) * 3;
-                        const float cw = expf((float)src[0] - m);
-                        s1 += src[1] * cw;
-                        s2 += src[2] * (double)(cw * cw);
-                    }
-                }
-                sM[t] = m;
-                const double ess = s1 * s1 / s2;
-                const bool bad = !(m > -INFINITY) || !(s1 > 0.0) || isnan(s1) || isnan(s2);
-                sBad[t] = bad ? (m > -INFINITY ? 2 : 1) : 0;
-                const bool trig = bad || ((t0 + t < D - 1) && ess < (double)a.ess_frac * (double)N);
-                if (wg == 0 && a.ess_tr) a.ess_tr[doff + t0 + t] = bad ? 0.0 : ess;
-                if (trig) atomicMin(&s_first, t);
-            }
-            __syncthreads();
-            const int tf = s_first;
-            if (tf == tb) {                    // no trigger: commit the block
-                if (wg == 0 && a.res_tr)
-                    for (int t = threadIdx.x; t < tb; t += kBtThreads) a.res_tr[doff + t0 + t] = 0;
-                if (wg == 0 && a.logz_tr)
-                    for (int t = threadIdx.x; t < tb; t += kBtThreads) a.logz_tr[doff + t0 + t] = 0.0;
-                Mlast = sM[tb - 1];
-                t0 += tb;
-                B = std::min(2 * B, a.Bmax);
-                continue;
-            }
-            const float Mg = sM[tf];
-            if (sBad[tf]) {                    // the same verdict in every workgroup of the team
-                status = sBad[tf] == 1 ? PPL_E_ZERO_WEIGHT : PPL_E_NONFINITE;
-                break;
-            }
-            if (wg == 0 && a.res_tr)
-                for (int t = threadIdx.x; t <= tf; t += kBtThreads) a.res_tr[doff + t0 + t] = t == tf ? 1 : 0;
-            if (wg == 0 && a.logz_tr)
-                for (int t = threadIdx.x; t < tf; t += kBtThreads) a.logz_tr[doff + t0 + t] = 0.0;
-            // roll back to the block start and recompute up to factor tf
-            if (tf < tb - 1) {
-#pragma unroll
-                for (int p = 0; p < P; ++p) {
-                    lw[p] = s_lw0[threadIdx.x * P + p];
-                    lwc[p] = s_lwc0[threadIdx.x * P + p];
-                }
-                switch (K) {
-#define PPL_BT_CASE(KK) \
-                    case KK: bt_block_redo<P, KK>(st, valid, lw, lwc, ybuf, tf + 1, inv_sd, lconst); break;
-                    PPL_BT_CASE(1) PPL_BT_CASE(2) PPL_BT_CASE(3) PPL_BT_CASE(4)
-                    PPL_BT_CASE(5) PPL_BT_CASE(6) PPL_BT_CASE(7) PPL_BT_CASE(8)
-#undef PPL_BT_CASE
-                }
-            }
-            // ---- resampling at factor s = t0 + tf
-            const int64_t s = t0 + tf;
-            // The state goes to the staging buffer first: it is dead in registers
-            // until the gather refills it, which keeps the scan below out of scratch.
-            int jb = jb0;
-            asm volatile("" : "+v"(jb));
-#pragma unroll
-            for (int p = 0; p < P; ++p) {
-                if (valid[p]) {
-#pragma unroll
-                    for (int f = 0; f < kBtNF; ++f) tx[(size_t)f * a.cap + jb + p] = st[p][f];
-                    if (a.elw_out && record && nres < a.max_events)
-                        a.elw_out[(size_t)a.max_events * roff + (size_t)nres * N + jb + p] = lw[p];
-                }
-            }
-            uint64_t q[P];
-            uint64_t run = 0, fhi = 0, flo = 0;
-#pragma unroll
-            for (int p = 0; p < P; ++p) {
-                const double e = valid[p] ? bt_exp((double)lw[p] - (double)Mg) : 0.0;
-                bt_fix_add(fhi, flo, e, kbits);
-                if (e >= 0.0) run += (uint64_t)floor(ldexp(e, kbits));
-                q[p] = run;
-            }
-            uint64_t btot;
-            const uint64_t off = bt_block_exscan(run, ldsu, btot);
-#pragma unroll
-            for (int p = 0; p < P; ++p)
-                if (valid[p]) tq[jb + p] = off + q[p];
-            u128 esl = ((u128)fhi << 64) | flo, unused = 0;
-            bt_block_sum_u128x2(esl, unused, lds4);
-            if (threadIdx.x == 0) {
-                ttot[wg] = btot;
-                tesum[2 * wg] = (uint64_t)esl;
-                tesum[2 * wg + 1] = (uint64_t)(esl >> 64);
-            }
-            if (!team_barrier(a.bar, team, ++epoch * (unsigned)W)) { alive = false; break; }
-            {
-                const uint64_t v = threadIdx.x < W ? ttot[threadIdx.x] : 0;
-                u128 ev = threadIdx.x < W ? (((u128)tesum[2 * threadIdx.x + 1] << 64) | tesum[2 * threadIdx.x]) : 0,
-                     zero = 0;
-                uint64_t S;
-                const uint64_t ex = bt_block_exscan(v, ldsu, S);
-                if (threadIdx.x < W) {
-                    tile_pre[threadIdx.x] = ex;
-                    tile_end[threadIdx.x] = ex + v;
-                }
-                bt_block_sum_u128x2(ev, zero, lds4);
-                const uint4 rw = philox(0, 0, (uint32_t)s, ((uint32_t)i << 8) | kTagResample, a.key);
-                const uint64_t U = __umul64hi(((uint64_t)rw.y << 32) | rw.x, S);
-                const double inc = (double)Mg + bt_log(bt_unfix(ev, F)) - logN;
-                logz += inc;
-                if (a.logz_tr && wg == 0 && threadIdx.x == 0) a.logz_tr[doff + s] = inc;
-                ++nres;
-                const uint64_t NN = (uint64_t)N;
-                const uint64_t Sq = S / NN, Sr = S - Sq * NN;
-                // ancestors: min{a : Q_a > tau_j}, tau_j = j Sq + floor((j Sr + U) / N)
-                const int js0 = wg * kTile;
-                const int js1 = (int)std::min<int64_t>((int64_t)js0 + kTile, N) - 1;
-                if (js0 < N) {
-                    for (int e = 0; e < 2; ++e) {
-                        if (threadIdx.x == 64 * e) {
-                            const int jj = e ? js1 : js0;
-                            const uint64_t num = (uint64_t)jj * Sr + U;
-                            const uint64_t tau = (uint64_t)jj * Sq + num / NN;
-                            int lo = 0, hi = W - 1;
-                            while (lo < hi) {
-                                const int mid = (lo + hi) >> 1;
-                                if (tile_end[mid] > tau) hi = mid; else lo = mid + 1;
-                            }
-                            int a0 = lo * kTile, a1 = (int)std::min<int64_t>((int64_t)a0 + kTile, N) - 1;
-                            while (a0 < a1) {
-                                const int mid = (a0 + a1) >> 1;
-                                if (tile_pre[lo] + tq[mid] > tau) a1 = mid; else a0 = mid + 1;
-                            }
-                            s_rng[e] = a0;
-                        }
-                    }
-                }
-                __syncthreads();
-                if (js0 < N) {
-                    const int a_lo = s_rng[0], a_hi = s_rng[1];
-                    const int span = a_hi - a_lo + 1;
-                    const bool staged = span <= a.stage_cap;
-                    int32_t *anc_row = (a.anc_out && record && nres - 1 < a.max_events)
-                                           ? a.anc_out + (size_t)a.max_events * roff + (size_t)(nres - 1) * N
-                                           : nullptr;
-                    if (staged)
-                        for (int k = threadIdx.x; k < span; k += kBtThreads) {
-                            const int aa = a_lo + k;
-                            stage[k] = tile_pre[aa / kTile] + tq[aa];
-                        }
-                    __syncthreads();
-                    int prev = a_lo;
-                    uint64_t num = (uint64_t)jb * Sr + U;
-                    uint64_t quo = num / NN, rem = num - quo * NN;
-#pragma unroll 1
-                    for (int p = 0; p < P; ++p) {
-                        const int j = jb + p;
-                        if (j >= N) break;
-                        if (p) {
-                            rem += Sr;
-                            if (rem >= NN) { rem -= NN; ++quo; }
-                        }
-                        const uint64_t tau = (uint64_t)j * Sq + quo;
-                        int anc;
-                        if (staged) {
-                            int lo = prev - a_lo, hi = span - 1;
-                            while (lo < hi) {
-                                const int mid = (lo + hi) >> 1;
-                                if (stage[mid] > tau) hi = mid; else lo = mid + 1;
-                            }
-                            anc = a_lo + lo;
-                        } else {
-                            int lo = prev / kTile, hi = W - 1;
-                            while (lo < hi) {
-                                const int mid = (lo + hi) >> 1;
-                                if (tile_end[mid] > tau) hi = mid; else lo = mid + 1;
-                            }
-                            int a0 = std::max(lo * kTile, prev), a1 = (int)std::min<int64_t>((int64_t)lo * kTile + kTile, N) - 1;
-                            while (a0 < a1) {
-                                const int mid = (a0 + a1) >> 1;
-                                if (tile_pre[lo] + tq[mid] > tau) a1 = mid; else a0 = mid + 1;
-                            }
-                            anc = a0;
-                        }
-                        s_anc[threadIdx.x * P + p] = anc;
-                        if (anc_row) anc_row[j] = anc;
-                        prev = anc;
-                    }
-                } else {
-                    __syncthreads();
-                }
-            }
-            if (!MOVES || I.move_steps == 0) {
-                // gather (slots past N take zeros: their state is never used)
-#pragma unroll
-                for (int p = 0; p < P; ++p) {
-                    const int anc = valid[p] ? s_anc[threadIdx.x * P + p] : 0;
-#pragma unroll
-                    for (int f = 0; f < kBtNF; ++f) st[p][f] = valid[p] ? tx[(size_t)f * a.cap + anc] : 0.0f;
-                    if (valid[p]) lw[p] = 0.0f;
-                    lwc[p] = 0.0f;
-                }
-            } else if constexpr (MOVES) {
-                // resample-move: the gathered particles go through memory one at a
-                // time, so only the moving particle's state occupies registers
-#pragma unroll
-                for (int p = 0; p < P; ++p) {
-                    if (!valid[p]) continue;
-                    const int anc = s_anc[threadIdx.x * P + p];
-#pragma unroll
-                    for (int f = 0; f < kBtNF; ++f) tx2[(size_t)f * a.cap + jb + p] = tx[(size_t)f * a.cap + anc];
-                    lw[p] = 0.0f;
-                    lwc[p] = 0.0f;
-                }
-                const double nd = (double)(s + 1);
-                const double lam = I.move_scale > 0.0 ? I.move_scale : 2.38 / sqrt(2.0 * K - 1.0);
-                BtMove mv;
-                mv.M = I.move_steps;
-                mv.h_mu = (float)(lam / sqrt(1.0 / ((double)mu_sd * (double)mu_sd) + nd / ((double)K * comp_sd * comp_sd)));
-                mv.h_b = (float)(lam / sqrt(3.0 / (M_PI * M_PI) + nd / (2.0 * K)));
-                mv.inv_mu_sd = 1.0f / mu_sd;
-                mv.inv_sd = inv_sd;
-                mv.lconst = lconst;
-                mv.c3 = ((uint32_t)i << 8) | kTagMove;
-                mv.key = a.key;
-                mv.y = I.y;
-                double *arow = (a.alpha_out && record && nres - 1 < a.max_events)
-                                   ? a.alpha_out + (size_t)a.max_events * aoff + (size_t)(nres - 1) * I.move_steps * N
-                                   : nullptr;
-#pragma unroll 1
-                for (int p = 0; p < P; ++p) {
-                    const int j = jb + p;
-                    if (j >= N) break;
-                    float *g = tx2 + j;
-                    switch (K) {
-#define PPL_BT_CASE(KK) \
-                        case KK: bt_move<KK>(g, (size_t)a.cap, s, (uint32_t)j, mv, arow, N); break;
-                        PPL_BT_CASE(1) PPL_BT_CASE(2) PPL_BT_CASE(3) PPL_BT_CASE(4)
-                        PPL_BT_CASE(5) PPL_BT_CASE(6) PPL_BT_CASE(7) PPL_BT_CASE(8)
-#undef PPL_BT_CASE
-                    }
-                }
-#pragma unroll
-                for (int p = 0; p < P; ++p) {
-#pragma unroll
-                    for (int f = 0; f < kBtNF; ++f) st[p][f] = valid[p] ? tx2[(size_t)f * a.cap + jb + p] : 0.0f;
-                }
-            }
-            t0 = s + 1;
-            B = 1;
-        }
-
-        // ---- final normaliser over the last epoch
-        double ess_final = (double)N;
-        if (alive && status == 0 && D > 0) {
-            uint64_t h1 = 0, l1 = 0, h2 = 0, l2 = 0;
-#pragma unroll
-            for (int p = 0; p < P; ++p) {
-                if (valid[p]) {
-                    const double e = bt_exp((double)lw[p] - (double)Mlast);
-                    bt_fix_add(h1, l1, e, kbits);
-                    bt_fix_add(h2, l2, e * e, kbits);
-                }
-            }
-            u128 e1 = ((u128)h1 << 64) | l1, e2 = ((u128)h2 << 64) | l2;
-            bt_block_sum_u128x2(e1, e2, lds4);
-            if (threadIdx.x == 0) {
-                tfin[4 * wg] = (uint64_t)e1;
-                tfin[4 * wg + 1] = (uint64_t)(e1 >> 64);
-                tfin[4 * wg + 2] = (uint64_t)e2;
-                tfin[4 * wg + 3] = (uint64_t)(e2 >> 64);
-            }
-            if (!team_barrier(a.bar, team, ++epoch * (unsigned)W)) {
-                alive = false;
-            } else {
-                const int w = threadIdx.x;
-                u128 t1 = w < W ? (((u128)tfin[4 * w + 1] << 64) | tfin[4 * w]) : 0;
-                u128 t2 = w < W ? (((u128)tfin[4 * w + 3] << 64) | tfin[4 * w + 2]) : 0;
-                bt_block_sum_u128x2(t1, t2, lds4);
-                const double s1 = bt_unfix(t1, F), s2 = bt_unfix(t2, F);
-                const double inc = (double)Mlast + bt_log(s1) - logN;
-                logz += inc;
-                if (a.logz_tr && wg == 0 && threadIdx.x == 0) a.logz_tr[doff + D - 1] = inc;
-                ess_final = s1 * s1 / s2;
-            }
-        }
-        if (!alive) status = PPL_E_HIP;
-        // outputs
-#pragma unroll
-        for (int p = 0; p < P; ++p) {
-            if (!valid[p]) continue;
-            const int64_t j = jb0 + p;
-            if (a.lw_out) a.lw_out[poff + j] = lw[p];
-            if (a.lat_out) {
-#pragma unroll
-                for (int k = 0; k < 8; ++k) {
-                    if (k < K) {
-                        a.lat_out[(size_t)kBtNF * poff + (size_t)k * N + j] = st[p][k];
-                        a.lat_out[(size_t)kBtNF * poff + (size_t)(K + k) * N + j] = st[p][8 + k];
-                    }
-                }
-            }
-        }
-        if (wg == 0 && threadIdx.x == 0) {
-            double *o = a.out + 4 * (size_t)i;
-            o[0] = status ? (status == PPL_E_ZERO_WEIGHT ? -INFINITY : NAN) : logz;
-            o[1] = status ? 0.0 : ess_final;
-            o[2] = (double)nres;
-            o[3] = (double)status;
-        }
-        // all workgroups of the team leave the instance together before its buffers are reused
-        if (alive && !team_barrier(a.bar, team, ++epoch * (unsigned)W)) alive = false;
     }
 }
+
 
 __global__ void smc_batched_reset_kernel(unsigned *bar, int words) {
     for (int i = threadIdx.x; i < words; i += blockDim.x) bar[i] = 0u;
@@ -854,7 +933,8 @@ __global__ void smc_batched_reset_kernel(unsigned *bar, int words) {
 struct BtLayout {
     unsigned *bar;
     double *part;
-    uint64_t *esum, *fin;
+    double *esum;
+    uint64_t *fin;
     uint64_t *tot, *qloc;
     float *xbuf, *xbuf2;
     size_t bytes;
@@ -867,7 +947,7 @@ static BtLayout bt_layout(void *ws, int teams, int W, int Bmax, int64_t cap) {
     auto take = [&](size_t n) { char *r = p + o; o += align_up(n, 256); return r; };
     L.bar = (unsigned *)take((size_t)kBtBarLine * (1 + teams) * sizeof(unsigned));
     L.part = (double *)take((size_t)teams * 2 * W * Bmax * 3 * sizeof(double));
-    L.esum = (uint64_t *)take((size_t)teams * W * 2 * sizeof(uint64_t));
+    L.esum = (double *)take((size_t)teams * W * sizeof(double));
     L.fin = (uint64_t *)take((size_t)teams * W * 4 * sizeof(uint64_t));
     L.tot = (uint64_t *)take((size_t)teams * W * sizeof(uint64_t));
     L.qloc = (uint64_t *)take((size_t)teams * cap * sizeof(uint64_t));
