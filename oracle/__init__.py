@@ -72,6 +72,8 @@ def lib():
         L.or_smc_forced.argtypes = [i32, P, i64, i32, P, i64, u64, u32, f64, f64, P, P, P, i64,
                                     P, P, P, P, P, P, P, i32, f64, P, P]
         L.or_move_scales.argtypes = [i32, i64, P, f64, P, P]
+        L.or_mcmc_poly.argtypes = [P, P, i64, P, i64, i64, i64, u64, P, P, P, P, P, P, P]
+        L.or_mcmc_poly.restype = ctypes.c_int
         L.or_gmm_move_population.argtypes = [i32, P, P, i64, i64, u64, u32, i32, f64, P, P]
         L.or_smc_forced.restype = ctypes.c_int
         L.or_num_threads.restype = ctypes.c_int
@@ -311,6 +313,30 @@ def gmm_move_population(state, K, y, s, seed, M, inst=0, hyper=GMM_HYPER, lam=0.
     lib().or_gmm_move_population(int(K), _p(_f64(hyper)), _p(_f64(y)), int(s), N, seed, int(inst), int(M),
                                  float(lam), _p(st), _p(al))
     return (st, al) if want_alpha else st
+
+
+def mcmc_poly(x, y, n_chains, n_iters, seed, burn_in=0, hyper=POLY_HYPER, want_trace=False, given_la=None):
+    """Lightweight Metropolis-Hastings chains on the polynomial model (see
+    ``or_mcmc_poly``).  Returns final states [6, chains], accepted counts,
+    the 29 summaries, and with want_trace the per-iteration n and log alpha
+    [iters, chains]; given_la forces ties to another run's decisions."""
+    x, y, h = _f64(x), _f64(y), _f64(hyper)
+    st = np.empty((6, n_chains))
+    acc = np.empty(n_chains, dtype=np.int64)
+    summ = np.empty(29)
+    ntr = np.empty((n_iters, n_chains), dtype=np.int8) if want_trace else None
+    latr = np.empty((n_iters, n_chains)) if want_trace else None
+    g = None if given_la is None else np.ascontiguousarray(given_la, dtype=np.float64).reshape(n_iters, n_chains)
+    ts = np.zeros(3, dtype=np.int64)
+    rc = lib().or_mcmc_poly(_p(x), _p(y), y.size, _p(h), int(n_chains), int(n_iters), int(burn_in), seed, _p(st),
+                            _p(acc), _p(summ), _p(ntr), _p(latr), _p(g), _p(ts))
+    if rc:
+        raise ValueError(f"or_mcmc_poly failed ({rc})")
+    out = dict(state=st, accepts=acc, summaries=summ, ties=int(ts[0]), adopted=int(ts[1]), nontie_diff=int(ts[2]))
+    if want_trace:
+        out["n_trace"] = ntr
+        out["la_trace"] = latr
+    return out
 
 
 def forced_event(lw, given_lw, given_anc, seed, step=0, inst=0):

@@ -536,6 +536,144 @@ static void smc_advance(int32_t model, int32_t K, const double *hyper, const dou
     }
 }
 
+/* ----------------------------------------- lightweight MH (POLY model) -- */
+/* Lightweight Metropolis-Hastings (paper Sec. 3.6.3) on the polynomial model,
+ * many independent chains.  A chain's trace holds the sites the execution
+ * reached: n and c_0..c_{n-1} (n + 1 sites).  One iteration picks a site of
+ * the trace uniformly, resamples it from its prior and re-executes: when n
+ * changes, the coefficients both executions reach keep their values, those
+ * only the new one reaches are drawn fresh from their prior, and those only
+ * the old one reached are dropped.  With prior proposals every prior density
+ * cancels, and the acceptance ratio is
+ *     alpha = L(x') / L(x) * (n + 1) / (n' + 1)
+ * (the likelihood ratio times the ratio of the site counts).
+ *
+ * Words of iteration t of chain c (tag 8): block (c, 3t, 0) word 0 picks the
+ * site (uniform discrete over 0..n; 0 is n, j + 1 is c_j), word 1 the
+ * proposed n' (uniform discrete over n_lo..n_hi), word 2 the acceptance
+ * uniform v (single-precision stream); blocks (c, 3t + 1, 0) and (c, 3t + 2, 0)
+ * give one double-precision Box-Muller pair each, z_0..z_3: a resampled c_j is
+ * sd z_0, fresh coefficients c_n, c_{n+1}, ... are sd z_1, sd z_2, sd z_3.
+ * The chain starts from the prior draw of the importance sampler (particle c);
+ * unused coefficient slots hold 0.  Accepted when log v < log alpha. */
+#define TAG_MCMC 8
+
+/* One chain.  Outputs per iteration (optional): n_tr[t], la_tr[t] (log alpha).
+ * g_la (optional): the other run's log alpha per iteration; where
+ * |log alpha - log v| <= 2 |g_la - log alpha| + 1e-9 (1 + |l(x)|) the other
+ * run's decision (log v < g_la) is taken (a tie).  st[5] and acc return the
+ * chain's final coefficients and accepted count; sums[29] accumulate, over
+ * iterations t >= burn_in: [n - 2] += 1, [4 + 5 (n - 2) + j] += c_j,
+ * [24 + j] += c_j 1{j < n}.  tstats[3]: {ties, adopted, non-tie differences}. */
+static void mcmc_chain(const double *x, const double *y, int64_t D, const double *hyper, int64_t c,
+                       int64_t n_iters, int64_t burn_in, uint64_t seed, int32_t *n_io, double *st, int64_t *acc,
+                       double *sums, int8_t *n_tr, double *la_tr, const double *g_la, int64_t stride,
+                       int64_t *tstats)
+{
+    int32_t n = *n_io;
+    double ll = or_poly_loglik(n, st, x, y, D);
+    for (int64_t t = 0; t < n_iters; ++t) {
+        uint32_t w[4], b1[4], b2[4];
+        draw4(seed, (uint32_t)c, (uint32_t)(3 * t), 0, 0, TAG_MCMC, w);
+        draw4(seed, (uint32_t)c, (uint32_t)(3 * t + 1), 0, 0, TAG_MCMC, b1);
+        draw4(seed, (uint32_t)c, (uint32_t)(3 * t + 2), 0, 0, TAG_MCMC, b2);
+        double z[4];
+        or_box_muller(or_u01_double(b1[0], b1[1]), or_u01_double(b1[2], b1[3]), &z[0], &z[1]);
+        or_box_muller(or_u01_double(b2[0], b2[1]), or_u01_double(b2[2], b2[3]), &z[2], &z[3]);
+        int64_t site = or_uniform_discrete(w[0], 0, n);
+        double c2[5];
+        for (int j = 0; j < 5; ++j) c2[j] = st[j];
+        int32_t n2 = n;
+        if (site == 0) {
+            n2 = (int32_t)or_uniform_discrete(w[1], (int64_t)hyper[1], (int64_t)hyper[2]);
+            for (int32_t j = n; j < n2; ++j) c2[j] = hyper[0] * z[1 + (j - n)];
+            for (int32_t j = n2; j < 5; ++j) c2[j] = 0.0;
+        } else {
+            c2[site - 1] = hyper[0] * z[0];
+        }
+        double ll2 = or_poly_loglik(n2, c2, x, y, D);
+        double la = (ll2 - ll) + (log((double)(n + 1)) - log((double)(n2 + 1)));
+        double lv = log(or_u01_single(w[2]));
+        int a = lv < la;
+        if (g_la) {
+            double ga = g_la[t * stride + c];
+            double dv = fabs(ga - la);
+            int given = lv < ga;
+            if (fabs(la - lv) <= 2.0 * dv + 1e-9 * (1.0 + fabs(ll))) {
+                ++tstats[0];
+                if (given != a) ++tstats[1];
+                a = given;
+            } else if (given != a) {
+                ++tstats[2];
+            }
+        }
+        if (la_tr) la_tr[t * stride + c] = la;
+        if (a) {
+            n = n2;
+            for (int j = 0; j < 5; ++j) st[j] = c2[j];
+            ll = ll2;
+            ++*acc;
+        }
+        if (n_tr) n_tr[t * stride + c] = (int8_t)n;
+        if (t >= burn_in && sums) {
+            sums[n - 2] += 1.0;
+            for (int j = 0; j < n; ++j) { sums[4 + 5 * (n - 2) + j] += st[j]; sums[24 + j] += st[j]; }
+        }
+    }
+    *n_io = n;
+}
+
+/* n_chains chains of n_iters iterations each.  Outputs (any may be NULL):
+ * state_out[6][n_chains] final n and c_0..c_4 (unused slots 0); accepts
+ * [n_chains]; summaries[29] over all chains' iterations t >= burn_in: P(n | y)
+ * for n = 2..5, E[c_j | n, y] (0 where n has no mass), E[c_j 1{j < n} | y]
+ * (the layout of importance sampling); n_trace / la_trace [n_iters][n_chains];
+ * g_la [n_iters][n_chains] and tstats[3] for a forced run beside another.
+ * Returns 0 or -1 on bad arguments, -3 on allocation failure. */
+int or_mcmc_poly(const double *x, const double *y, int64_t D, const double *hyper, int64_t n_chains, int64_t n_iters,
+                 int64_t burn_in, uint64_t seed, double *state_out, int64_t *accepts, double *summaries,
+                 int8_t *n_trace, double *la_trace, const double *g_la, int64_t *tstats)
+{
+    if (n_chains <= 0 || n_iters < 0 || burn_in < 0 || D < 0) return -1;
+    if (hyper[1] < 1 || hyper[2] > 5 || hyper[1] > hyper[2]) return -1;
+    double *sums = (double *)calloc((size_t)n_chains * 29, sizeof(double));
+    if (!sums) return -3;
+    int64_t ties = 0, adopted = 0, bad = 0;
+#pragma omp parallel for schedule(dynamic, 64) reduction(+:ties, adopted, bad)
+    for (int64_t c = 0; c < n_chains; ++c) {
+        int32_t n;
+        double cc[6];
+        or_poly_draw(seed, c, TAG_PRIOR, hyper, &n, cc);
+        for (int j = n; j < 5; ++j) cc[j] = 0.0;
+        int64_t acc = 0, ts[3] = {0, 0, 0};
+        mcmc_chain(x, y, D, hyper, c, n_iters, burn_in, seed, &n, cc, &acc, sums + (size_t)c * 29, n_trace, la_trace,
+                   g_la, n_chains, ts);
+        ties += ts[0]; adopted += ts[1]; bad += ts[2];
+        if (state_out) {
+            state_out[c] = (double)n;
+            for (int j = 0; j < 5; ++j) state_out[(size_t)(1 + j) * n_chains + c] = cc[j];
+        }
+        if (accepts) accepts[c] = acc;
+    }
+    if (summaries) {
+        double tot[29];
+        for (int k = 0; k < 29; ++k) {
+            nsum a = {0, 0};
+            for (int64_t c = 0; c < n_chains; ++c) nadd(&a, sums[(size_t)c * 29 + k]);
+            tot[k] = nval(a);
+        }
+        double all = tot[0] + tot[1] + tot[2] + tot[3];
+        for (int m = 0; m < 4; ++m) {
+            summaries[m] = all > 0 ? tot[m] / all : 0.0;
+            for (int j = 0; j < 5; ++j) summaries[4 + 5 * m + j] = tot[m] > 0 ? tot[4 + 5 * m + j] / tot[m] : 0.0;
+        }
+        for (int j = 0; j < 5; ++j) summaries[24 + j] = all > 0 ? tot[24 + j] / all : 0.0;
+    }
+    if (tstats) { tstats[0] = ties; tstats[1] = adopted; tstats[2] = bad; }
+    free(sums);
+    return 0;
+}
+
 /* ------------------------------------------------ resample-move (GMM) -- */
 /* Resample-move: after each resampling at factor s the mixture particles take
  * M Metropolis-Hastings steps whose target is the posterior given the data
