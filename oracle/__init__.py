@@ -74,6 +74,8 @@ def lib():
         L.or_move_scales.argtypes = [i32, i64, P, f64, P, P]
         L.or_mcmc_poly.argtypes = [P, P, i64, P, i64, i64, i64, u64, P, P, P, P, P, P, P]
         L.or_mcmc_poly.restype = ctypes.c_int
+        L.or_enumerate_hmm.argtypes = [P, i64, P, P, P, P]
+        L.or_enumerate_hmm.restype = ctypes.c_int
         L.or_gmm_move_population.argtypes = [i32, P, P, i64, i64, u64, u32, i32, f64, P, P]
         L.or_smc_forced.restype = ctypes.c_int
         L.or_num_threads.restype = ctypes.c_int
@@ -337,6 +339,27 @@ def mcmc_poly(x, y, n_chains, n_iters, seed, burn_in=0, hyper=POLY_HYPER, want_t
         out["n_trace"] = ntr
         out["la_trace"] = latr
     return out
+
+
+def hmm_hyper(pi0, A, mu, sigma=1.0):
+    """The hyper-parameter array of the hidden Markov model: {K, sigma, pi0, A, mu}."""
+    pi0, A, mu = np.asarray(pi0, np.float64), np.asarray(A, np.float64), np.asarray(mu, np.float64)
+    return np.concatenate([[pi0.size, sigma], pi0, A.ravel(), mu])
+
+
+def enumerate_hmm(y, hyper):
+    """Exact inference by enumerating every path of the hidden Markov model:
+    log Z, the number of paths, P(z_t = k | y) [T, K], the MAP path and its
+    log joint."""
+    y, h = _f64(y), _f64(hyper)
+    K = int(h[0])
+    scal = np.empty(4)
+    marg = np.empty((y.size, K))
+    mp = np.empty(y.size, dtype=np.int32)
+    rc = lib().or_enumerate_hmm(_p(y), y.size, _p(h), _p(scal), _p(marg), _p(mp))
+    if rc:
+        raise ValueError(f"or_enumerate_hmm failed ({rc})")
+    return dict(log_z=scal[0], paths=scal[1], map_lw=scal[2], marginals=marg, map=mp)
 
 
 def forced_event(lw, given_lw, given_anc, seed, step=0, inst=0):

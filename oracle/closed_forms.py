@@ -141,3 +141,47 @@ def gmm1_exact(y, mu_sd=5.0, comp_sd=1.0):
     quad = (y @ y) / s2 - (t2 / s2 ** 2) * y.sum() ** 2 / (1.0 + D * t2 / s2)
     logz = -0.5 * (D * math.log(2 * math.pi) + logdet + quad)
     return logz, mean, 1.0 / prec
+
+
+def hmm_forward_backward(y, pi0, A, mu, sigma=1.0):
+    """Textbook forward-backward recursions of a hidden Markov model with
+    Gaussian emissions (scaled to avoid underflow): log Z and the posterior
+    marginals P(z_t = k | y)."""
+    y = np.asarray(y, np.float64)
+    pi0, A, mu = np.asarray(pi0, np.float64), np.asarray(A, np.float64), np.asarray(mu, np.float64)
+    T, K = y.size, pi0.size
+    from scipy.stats import norm
+    e = norm.pdf(y[:, None], mu[None, :], sigma)          # [T, K]
+    alpha = np.zeros((T, K))
+    c = np.zeros(T)
+    a = pi0 * e[0]
+    c[0] = a.sum()
+    alpha[0] = a / c[0]
+    for t in range(1, T):
+        a = (alpha[t - 1] @ A) * e[t]
+        c[t] = a.sum()
+        alpha[t] = a / c[t]
+    beta = np.ones((T, K))
+    for t in range(T - 2, -1, -1):
+        beta[t] = (A @ (e[t + 1] * beta[t + 1])) / c[t + 1]
+    return float(np.log(c).sum()), alpha * beta
+
+
+def hmm_viterbi(y, pi0, A, mu, sigma=1.0):
+    """Textbook Viterbi recursion: the most probable path and its log joint."""
+    y = np.asarray(y, np.float64)
+    from scipy.stats import norm
+    le = norm.logpdf(y[:, None], np.asarray(mu)[None, :], sigma)
+    lA = np.log(np.asarray(A, np.float64))
+    T, K = le.shape
+    d = np.log(np.asarray(pi0, np.float64)) + le[0]
+    back = np.zeros((T, K), dtype=int)
+    for t in range(1, T):
+        cand = d[:, None] + lA
+        back[t] = np.argmax(cand, axis=0)
+        d = cand[back[t], np.arange(K)] + le[t]
+    path = np.zeros(T, dtype=int)
+    path[-1] = int(np.argmax(d))
+    for t in range(T - 1, 0, -1):
+        path[t - 1] = back[t, path[t]]
+    return path, float(d.max())

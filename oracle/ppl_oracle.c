@@ -536,6 +536,106 @@ static void smc_advance(int32_t model, int32_t K, const double *hyper, const dou
     }
 }
 
+/* ------------------------------------------------- enumeration (HMM) -- */
+/* Exact inference by enumeration (paper Sec. 3.6.1): every execution of a
+ * model whose sample sites all have finite support, each weighted by the
+ * product of its sample probabilities and factors.  Model: a hidden Markov
+ * chain of K states over T steps, z_0 ~ Cat(pi0), z_t ~ Cat(A[z_{t-1}]),
+ * observe(Normal(mu[z_t], sigma), y_t).  An execution is a path z; its
+ * index is sum_t z_t K^(T-1-t).  hyper = {K, sigma, pi0[K], A[K][K]
+ * (row = from), mu[K]}.  Outputs: scal[4] = {log Z, paths, log joint of the
+ * MAP path, 0}; marg[T][K] = P(z_t = k | y); map[T] the most probable path
+ * (the lowest index among equals).  Plain: the paths in index order, the
+ * log-sum-exp with compensated sums (max first).  Returns -1 on bad
+ * arguments, -3 on allocation failure. */
+static double hmm_path_lw(int32_t K, int64_t T, const double *lpi, const double *lA, const double *y,
+                          const double *mu, double sigma, const int32_t *z)
+{
+    double lw = lpi[z[0]];
+    for (int64_t t = 0; t < T; ++t) {
+        if (t > 0) lw += lA[z[t - 1] * K + z[t]];
+        double r = (y[t] - mu[z[t]]) / sigma;
+        lw += -0.5 * log(2.0 * M_PI) - log(sigma) - 0.5 * r * r;
+    }
+    return lw;
+}
+
+int or_enumerate_hmm(const double *y, int64_t T, const double *hyper, double *scal, double *marg, int32_t *map)
+{
+    int32_t K = (int32_t)hyper[0];
+    if (K < 1 || K > 8 || T < 1 || T > 40) return -1;
+    double paths = pow((double)K, (double)T);
+    if (paths > 4e12) return -1;
+    double sigma = hyper[1];
+    const double *pi0 = hyper + 2, *A = hyper + 2 + K, *mu = hyper + 2 + K + K * K;
+    double lpi[8], lA[64];
+    for (int k = 0; k < K; ++k) lpi[k] = log(pi0[k]);
+    for (int k = 0; k < K * K; ++k) lA[k] = log(A[k]);
+    int64_t P = (int64_t)paths;
+    /* pass 1: the largest log-weight and the MAP path */
+    double m = -INFINITY;
+    int64_t best = 0;
+#pragma omp parallel
+    {
+        double ml = -INFINITY;
+        int64_t bl = 0;
+        int32_t z[40];
+#pragma omp for schedule(static)
+        for (int64_t p = 0; p < P; ++p) {
+            int64_t q = p;
+            for (int64_t t = T - 1; t >= 0; --t) { z[t] = (int32_t)(q % K); q /= K; }
+            double lw = hmm_path_lw(K, T, lpi, lA, y, mu, sigma, z);
+            if (lw > ml) { ml = lw; bl = p; }
+        }
+#pragma omp critical
+        { if (ml > m || (ml == m && bl < best)) { m = ml; best = bl; } }
+    }
+    /* pass 2: sums of exp(lw - m), overall and per (t, k) */
+    int nth = 1;
+#ifdef _OPENMP
+    nth = omp_get_max_threads();
+#endif
+    double *part = (double *)calloc((size_t)nth * (1 + T * K), sizeof(double));
+    if (!part) return -3;
+#pragma omp parallel
+    {
+        int th = 0;
+#ifdef _OPENMP
+        th = omp_get_thread_num();
+#endif
+        double *mine = part + (size_t)th * (1 + T * K);
+        int32_t z[40];
+        /* static schedule: thread th takes one contiguous range of paths, in order */
+#pragma omp for schedule(static)
+        for (int64_t p = 0; p < P; ++p) {
+            int64_t q = p;
+            for (int64_t t = T - 1; t >= 0; --t) { z[t] = (int32_t)(q % K); q /= K; }
+            double e = exp(hmm_path_lw(K, T, lpi, lA, y, mu, sigma, z) - m);
+            mine[0] += e;
+            for (int64_t t = 0; t < T; ++t) mine[1 + t * K + z[t]] += e;
+        }
+    }
+    double tot[1 + 40 * 8];
+    for (int64_t f = 0; f < 1 + T * K; ++f) {
+        nsum a = {0, 0};
+        for (int th = 0; th < nth; ++th) nadd(&a, part[(size_t)th * (1 + T * K) + f]);
+        tot[f] = nval(a);
+    }
+    free(part);
+    if (scal) {
+        scal[0] = m + log(tot[0]);
+        scal[1] = paths;
+        scal[2] = m;
+        scal[3] = 0.0;
+    }
+    if (marg) for (int64_t f = 0; f < T * K; ++f) marg[f] = tot[1 + f] / tot[0];
+    if (map) {
+        int64_t q = best;
+        for (int64_t t = T - 1; t >= 0; --t) { map[t] = (int32_t)(q % K); q /= K; }
+    }
+    return 0;
+}
+
 /* ----------------------------------------- lightweight MH (POLY model) -- */
 /* Lightweight Metropolis-Hastings (paper Sec. 3.6.3) on the polynomial model,
  * many independent chains.  A chain's trace holds the sites the execution

@@ -18,6 +18,7 @@ Workload recipes (sizes and distributions of the configurations measured):
 import numpy as np
 
 SEED_POLY, SEED_BLR, SEED_LGSSM, SEED_GMM, SEED_POLY_LEARN, SEED_GMM_LEARN = 1000, 1001, 1002, 1003, 1004, 1005
+SEED_HMM = 1006
 
 
 def poly_data(D=100, seed=SEED_POLY):
@@ -67,6 +68,25 @@ def gmm_learn_data(K=5, D=100, seed=SEED_GMM_LEARN, mu_sd=5.0):
     mu = mu_sd * g.standard_normal(K)
     z = g.choice(K, size=D, p=pi)
     return (mu[z] + g.standard_normal(D)).astype(np.float32)
+
+
+def hmm_instance(K=4, T=14, seed=SEED_HMM, sigma=1.0):
+    """A hidden Markov model with K states and T observations: pi0 ~
+    Dirichlet(1); transition rows ~ Dirichlet(1) plus 3 on the diagonal
+    (sticky), normalised; state means spaced 2 apart with jitter; a path
+    drawn from the chain and y_t = mu[z_t] + N(0, sigma^2).
+    Returns (pi0, A, mu, sigma, y, z)."""
+    g = np.random.default_rng(seed + 31 * K + T)
+    pi0 = g.dirichlet(np.ones(K))
+    A = g.dirichlet(np.ones(K), size=K) + 3.0 * np.eye(K)
+    A /= A.sum(1, keepdims=True)
+    mu = 2.0 * (np.arange(K) - (K - 1) / 2.0) + 0.3 * g.standard_normal(K)
+    z = np.zeros(T, dtype=int)
+    z[0] = g.choice(K, p=pi0)
+    for t in range(1, T):
+        z[t] = g.choice(K, p=A[z[t - 1]])
+    y = mu[z] + sigma * g.standard_normal(T)
+    return pi0, A, mu, sigma, y.astype(np.float64), z
 
 
 def logweights(n, kind="normal", seed=0, scale=10.0):
