@@ -21,8 +21,11 @@ Other configurations print the same fields for their own workload:
   blr-stats         the same BLR workload with the likelihood from sufficient
                     statistics (X^T X, X^T y, y^T y once per call, then O(d^2)
                     FP64 per particle): particles per second, roofline of the
-                    particle kernel against HBM (latents and log-weights written)
+                    particle kernel's quadratic form against the FP64 peak
   poly, poly-paper  polynomial fit IS (FP64), 10^4 and 2 x 10^6 particles
+  mcmc-poly         lightweight Metropolis-Hastings on the polynomial model (FP64):
+                    2^16 chains x 1000 iterations over the C0 data, chain
+                    iterations per second
   lgssm             bootstrap SMC on the linear-Gaussian state space model
   gmm-batched       batched SMC over 256 mixture instances (autotuned first)
   resample-gather   resampling fused with the state gather, roofline against HBM
@@ -31,7 +34,7 @@ Other configurations print the same fields for their own workload:
   peaks             measured instruction and copy rates (not a hot-path line)
 
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu]
-                       [--config blr|blr-stats|poly|poly-paper|lgssm|gmm-batched|resample-gather|proposal-poly|
+                       [--config blr|blr-stats|poly|poly-paper|mcmc-poly|lgssm|gmm-batched|resample-gather|proposal-poly|
                                  proposal-gmm|proposal-train|peaks]
 """
 import argparse
@@ -55,7 +58,8 @@ FLOP_PER_EVAL_BLR = 34                    # 17 FMA per (particle, row) at d = 16
 # sources whose hash keys it).  A count is used only while the hash matches.
 _CS = "paper_2010_08454_amd/csrc/"
 TRAFFIC_FILES = {
-    "blr": ("blr_is_kernel_traffic.txt", (_CS + "importance.hip", _CS + "device.h")),
+    "blr": ("blr_is_kernel_traffic.txt", (_CS + "importance.hip", _CS + "blr.h", _CS + "device.h")),
+    "blr-stats": ("blr_stats_is_kernel_traffic.txt", (_CS + "blr_stats.hip", _CS + "blr.h", _CS + "device.h")),
     "lgssm": ("smc_persistent_kernel_traffic_lgssm-N2p20-T1000.txt",
               (_CS + "smc.hip", _CS + "smc.h", _CS + "device.h")),
     "gmm-batched": ("smc_batched_kernel_traffic_gmm-batched-256inst-N2p16.txt",
@@ -70,7 +74,8 @@ def parse():
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--config", default="blr",
-                    choices=["blr", "blr-stats", "poly", "poly-paper", "lgssm", "gmm-batched", "resample-gather",
+                    choices=["blr", "blr-stats", "poly", "poly-paper", "mcmc-poly", "lgssm", "gmm-batched",
+                             "resample-gather",
                              "proposal-poly",
                              "proposal-gmm", "proposal-train", "peaks"])
     ap.add_argument("--pairs-log2", type=int, default=22, help="proposal-train: log2 of the simulated pairs")
@@ -210,6 +215,14 @@ def cpu_baseline_blr(X, y, n_full, seed, target_s=15.0):
     run = lambda n: oracle.importance(oracle.MODEL_BLR, X, y, n, seed, dim=X.shape[1])
     what = lambda n: ("the full workload" if n == n_full else f"{n} of the {n_full} particles") + f" over all {y.size} rows"
     return cpu_record(run, 1 << 12, n_full, y.size, "particle-likelihood evals/s", what, target_s)
+
+
+def cpu_baseline_mcmc(x, y, C, T, burn, seed, target_s=15.0):
+    """The oracle's chains (all T iterations each) on a sample of the chains."""
+    import oracle
+    run = lambda k: oracle.mcmc_poly(x, y, k, T, seed, burn_in=burn)
+    what = lambda k: f"{k} of the {C} chains, {T} iterations each"
+    return cpu_record(run, 64, C, T, "chain-iterations/s", what, target_s)
 
 
 def cpu_baseline_lgssm(y, seed, target_s=15.0):
@@ -669,9 +682,22 @@ def main():
                     "model": "conjugate Bayesian linear regression, likelihood from sufficient statistics",
                     "d": d, "rows": D, "particles": N, "proposal": "prior",
                     "precision": "fp32 latents, fp64 statistics, quadratic form and normaliser"}
-        # algorithmic HBM bytes of the particle kernel: d FP32 latents and one FP64 log-weight written per particle
-        flop_per_launch = (4 * d + 8) * N
-        peak, bound, unit, dtype = 8000.0, "hbm", "GB/s", "f64"
+        # algorithmic work of the particle kernel: the FP64 quadratic form c - 2 w.b + w^T A w, 2 (d^2 + d)
+        # FLOP per particle (the prior draw is not counted, as for the row-by-row line)
+        flop_per_launch = 2 * (d * d + d) * N
+        peak, bound, unit, dtype = FP64_VALU_TFLOPS, "alu", "TFLOP/s", "f64"
+    elif args.config == "mcmc-poly":
+        D, C, T, burn, seed = 100, args.particles or (1 << 16), 1000, 200, 1
+        x, y = synthetic.poly_data(D=D)
+        dx, dy = torch.from_numpy(x).to(dev), torch.from_numpy(y).to(dev)
+        data = ppl.make_data(dx, dy)
+        model, kname = ppl.PPL_MODEL_POLY, "mcmc_poly_kernel"
+        N = C
+        workload = {"workload": "mcmc-poly", "model": "polynomial fit, lightweight Metropolis-Hastings",
+                    "points": D, "chains": C, "iterations": T, "burn_in": burn, "precision": "fp64"}
+        # the proposal's likelihood per iteration: 4 FMA Horner + sub + FMA square per point = 10 FLOP
+        flop_per_launch = 10 * D * C * T
+        peak, bound, unit, dtype = FP64_VALU_TFLOPS, "alu", "TFLOP/s", "f64"
     elif args.config == "lgssm":
         T, N, seed = 1000, args.particles or (1 << 20), 1
         y = synthetic.lgssm_data(T=T)
@@ -725,6 +751,12 @@ def main():
 
         def step():
             ppl.ppl_smc_batched(model, table, seed, 0.5, tune=tuned + (0,), ws=ws, stream=stream, out=outb)
+    elif args.config == "mcmc-poly":
+        ws = ppl.workspace(ppl.ppl_workspace_size(model, data, C, ppl.PPL_ALGO_MCMC), dev)
+        summ = torch.empty(29, dtype=torch.float64, device=dev)
+
+        def step():
+            ppl.ppl_mcmc(model, data, C, T, seed, burn_in=burn, ws=ws, stream=stream, scalars=scal, summaries=summ)
     elif args.config == "lgssm":
         ws = ppl.workspace(ppl.ppl_workspace_size(model, data, N, ppl.PPL_ALGO_SMC), dev)
 
@@ -752,7 +784,7 @@ def main():
     k_ms, k_n = ppl.ppl_timing_query(kname)
     ppl.ppl_timing_enable(False)
     ms_per_step = total_ms / args.steps
-    evals = N * D
+    evals = N * D * (T if args.config == "mcmc-poly" else 1)
     value = evals / (ms_per_step / 1e3)
     k_avg_ms = k_ms / max(k_n, 1)
     achieved = flop_per_launch / (k_avg_ms / 1e3) / (1e9 if unit == "GB/s" else 1e12)
@@ -784,14 +816,20 @@ def main():
     if args.config == "lgssm":
         out["n_resample"] = int(s[2])
         out["metric"] = "particle-step evals/s"
+    if args.config == "mcmc-poly":
+        out["metric"], out["unit"], out["value"] = "MH iterations/s", "chain-iterations/s", C * T / (ms_per_step / 1e3)
+        out["evals_equivalent"] = value
+        out["accept_rate"] = float(s[0])
+        out.pop("log_evidence"), out.pop("ess")
     if args.config == "blr-stats":
         # the statistics replace the per-row loop: the rate is in particles, not (particle, row) terms
         out["metric"], out["unit"], out["value"] = "particles/s", "particles/s", N / (ms_per_step / 1e3)
         out["evals_equivalent"] = value
-        roofline["bytes_per_launch"] = roofline.pop("flop_per_launch")
     if not args.no_cpu:
         if args.config == "blr":
             out["cpu_baseline"] = cpu_baseline_blr(X, y, N, seed, target_s=args.cpu_seconds)
+        elif args.config == "mcmc-poly":
+            out["cpu_baseline"] = cpu_baseline_mcmc(x, y, C, T, burn, seed, target_s=args.cpu_seconds)
         elif args.config == "blr-stats":
             cb = cpu_baseline_blr(X, y, N, seed, target_s=args.cpu_seconds)
             for k in ("value", "value_1_thread"):

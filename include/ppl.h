@@ -170,7 +170,7 @@ typedef struct ppl_proposal {
     const void *d_params;
 } ppl_proposal;
 
-enum { PPL_ALGO_IS = 0, PPL_ALGO_SMC = 1, PPL_ALGO_LSE = 2, PPL_ALGO_RESAMPLE = 3 };
+enum { PPL_ALGO_IS = 0, PPL_ALGO_SMC = 1, PPL_ALGO_LSE = 2, PPL_ALGO_RESAMPLE = 3, PPL_ALGO_MCMC = 4 };
 
 /* Bytes of device workspace an entry point needs for (model, data, N).
  * The workspace is a caller-owned device buffer, at least 256-byte aligned,
@@ -289,6 +289,42 @@ typedef struct ppl_smc_options {
  * records log alpha per event, step and particle. */
 int ppl_smc_ex(int model, const ppl_data *data, int64_t n_particles, uint64_t seed, const ppl_smc_options *opt,
                void *d_ws, size_t ws_bytes, void *stream, ppl_result *out);
+
+/* ------------------------------------------- Metropolis-Hastings -- */
+/* Outputs of ppl_mcmc (any pointer may be NULL).
+ * d_scalars (DEVICE, 4 doubles): {acceptance rate, samples kept (chains x
+ *   iterations after the burn-in), chains, status}. */
+typedef struct ppl_mcmc_result {
+    double accept_rate;       /* host copy of d_scalars[0] (sync_host only) */
+    int32_t sync_host;
+    int32_t reserved;
+    double *d_scalars;        /* [4] */
+    double *d_state;          /* [6][n_chains] final n and c_0..c_4 (slots j >= n hold 0) */
+    int64_t *d_accepts;       /* [n_chains] accepted proposals per chain */
+    double *d_summaries;      /* [29], the layout of ppl_importance's POLY summaries, from every chain's
+                               * states after the burn-in */
+    int8_t *d_n_trace;        /* [n_iters][n_chains] n after each iteration */
+    double *d_log_alpha;      /* [n_iters][n_chains] log acceptance ratio of each proposal */
+} ppl_mcmc_result;
+
+/* Lightweight Metropolis-Hastings (paper Sec. 3.6.3): n_chains independent
+ * chains of n_iters iterations, one chain per GPU lane.  A chain's trace is
+ * the set of sites its execution reached; an iteration picks one uniformly,
+ * resamples it from its prior and re-executes the model, keeping the values
+ * of sites both executions reach, drawing sites only the new one reaches
+ * fresh from their prior and dropping the others; accepted when
+ * log v < log L(x') - log L(x) + log |trace(x)| - log |trace(x')|.
+ * model: PPL_MODEL_POLY (trace n, c_0..c_{n-1}; data and hyper-parameters as
+ * for importance sampling).  Words of iteration t of chain c (tag 8): block
+ * (c, 3t, 0) word 0 the site (0 is n, j + 1 is c_j), word 1 the proposed n,
+ * word 2 the uniform v; blocks (c, 3t + 1, 0) and (c, 3t + 2, 0) one
+ * double-precision Box-Muller pair each (z_0 for a resampled coefficient,
+ * z_1.. for fresh ones).  Chain c starts from the prior draw of importance
+ * sampling's execution c.  FP64 throughout.  n_chains in [1, 2^31),
+ * n_iters >= 0, 0 <= burn_in <= n_iters.  Workspace: PPL_ALGO_MCMC bytes
+ * for n_chains (ppl_workspace_size with n_particles = n_chains). */
+int ppl_mcmc(int model, const ppl_data *data, int64_t n_chains, int64_t n_iters, int64_t burn_in, uint64_t seed,
+             void *d_ws, size_t ws_bytes, void *stream, ppl_mcmc_result *out);
 
 /* ------------------------------------------------------ batched SMC -- */
 /* One model instance of a batched run.  The caller passes the same table

@@ -24,14 +24,14 @@ PPL_MODEL_POLY, PPL_MODEL_BLR, PPL_MODEL_LGSSM, PPL_MODEL_GMM = 1, 2, 3, 4
 PPL_MODEL_BLR_STATS = 5
 PPL_F32, PPL_F64 = 1, 2
 PPL_Q_PRIOR, PPL_Q_GAUSS_FULL, PPL_Q_POLY_MIX, PPL_Q_GMM_MIX = 0, 1, 2, 3
-PPL_ALGO_IS, PPL_ALGO_SMC, PPL_ALGO_LSE, PPL_ALGO_RESAMPLE = 0, 1, 2, 3
+PPL_ALGO_IS, PPL_ALGO_SMC, PPL_ALGO_LSE, PPL_ALGO_RESAMPLE, PPL_ALGO_MCMC = 0, 1, 2, 3, 4
 PPL_INST_NO_RECORD = 1
 PPL_NOALLOC_SCRATCH_BYTES = 16 << 20
 
 # Exported C symbols (kept in step with include/ppl.h).
 EXPORTS = ("ppl_status_string", "ppl_last_error", "ppl_version", "ppl_workspace_size",
            "ppl_importance", "ppl_importance_noalloc", "ppl_lse_ess", "ppl_resample", "ppl_resample_gather", "ppl_philox", "ppl_smc",
-           "ppl_smc_ex",
+           "ppl_smc_ex", "ppl_mcmc",
            "ppl_timing_enable", "ppl_timing_query")
 
 P = ctypes.c_void_p
@@ -60,6 +60,12 @@ class PplSmcOptions(ctypes.Structure):
                 ("move_scale", ctypes.c_double)]
 
 
+class PplMcmcResult(ctypes.Structure):
+    _fields_ = [("accept_rate", ctypes.c_double), ("sync_host", ctypes.c_int32), ("reserved", ctypes.c_int32),
+                ("d_scalars", P), ("d_state", P), ("d_accepts", P), ("d_summaries", P), ("d_n_trace", P),
+                ("d_log_alpha", P)]
+
+
 class PplError(RuntimeError):
     def __init__(self, code, msg):
         super().__init__(f"libppl error {code}: {msg}")
@@ -84,6 +90,8 @@ def _load():
     L.ppl_philox.argtypes = [u64, u32, u32, u32, i64, P, P]
     L.ppl_smc.argtypes = [ctypes.c_int, ctypes.POINTER(PplData), i64, u64, f64, P, ctypes.c_size_t, P,
                           ctypes.POINTER(PplResult)]
+    L.ppl_mcmc.argtypes = [ctypes.c_int, ctypes.POINTER(PplData), i64, i64, i64, u64, P, ctypes.c_size_t, P,
+                           ctypes.POINTER(PplMcmcResult)]
     L.ppl_smc_ex.argtypes = [ctypes.c_int, ctypes.POINTER(PplData), i64, u64, ctypes.POINTER(PplSmcOptions), P,
                              ctypes.c_size_t, P, ctypes.POINTER(PplResult)]
     L.ppl_importance_noalloc.argtypes = [ctypes.c_int, ctypes.POINTER(PplData), i64, u64,
@@ -250,6 +258,19 @@ def ppl_smc(model, data, n, seed, ess_frac=0.5, ws=None, stream=None, log_weight
     opt = PplSmcOptions(ess_frac=float(ess_frac), move_steps=int(move_steps), move_scale=float(move_scale))
     _check(lib.ppl_smc_ex(model, ctypes.byref(data), int(n), int(seed) & (2 ** 64 - 1), ctypes.byref(opt), _ptr(ws),
                           ws.numel(), _stream(stream), ctypes.byref(res)))
+    return res
+
+
+def ppl_mcmc(model, data, n_chains, n_iters, seed, burn_in=0, ws=None, stream=None, state=None, accepts=None,
+             summaries=None, scalars=None, n_trace=None, log_alpha=None, sync=False):
+    """Lightweight Metropolis-Hastings chains; returns the ppl_mcmc_result struct."""
+    if ws is None:
+        ws = workspace(ppl_workspace_size(model, data, n_chains, PPL_ALGO_MCMC))
+    res = PplMcmcResult(sync_host=1 if sync else 0, d_scalars=_ptr(scalars), d_state=_ptr(state),
+                        d_accepts=_ptr(accepts), d_summaries=_ptr(summaries), d_n_trace=_ptr(n_trace),
+                        d_log_alpha=_ptr(log_alpha))
+    _check(lib.ppl_mcmc(model, ctypes.byref(data), int(n_chains), int(n_iters), int(burn_in),
+                        int(seed) & (2 ** 64 - 1), _ptr(ws), ws.numel(), _stream(stream), ctypes.byref(res)))
     return res
 
 

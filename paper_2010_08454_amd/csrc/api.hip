@@ -17,6 +17,7 @@
 #include "batched.h"
 #include "host.h"
 #include "kernels.h"
+#include "mcmc.h"
 #include "proposal.h"
 #include "smc.h"
 #include "timing.h"
@@ -250,6 +251,13 @@ int ppl_workspace_size(int model, const ppl_data *data, int64_t n, int algo, siz
             *bytes = is_ws_bytes(model, data->dim, n, data->n_data);
             return PPL_OK;
         }
+        case PPL_ALGO_MCMC: {
+            double h[8];
+            if (model != PPL_MODEL_POLY) return fail(PPL_E_MODEL, "MCMC supports POLY (got %d)", model);
+            if (int rc = check_model_data(model, data, h)) return rc;
+            *bytes = mcmc_ws_bytes(n);
+            return PPL_OK;
+        }
         case PPL_ALGO_SMC: {
             double h[8];
             if (model != PPL_MODEL_LGSSM && model != PPL_MODEL_GMM)
@@ -358,6 +366,45 @@ int ppl_smc(int model, const ppl_data *data, int64_t n, uint64_t seed, double es
             void *stream, ppl_result *out) {
     const ppl_smc_options opt{ess_frac, 0, 0, 0.0};
     return ppl_smc_ex(model, data, n, seed, &opt, ws, ws_bytes, stream, out);
+}
+
+int ppl_mcmc(int model, const ppl_data *data, int64_t n_chains, int64_t n_iters, int64_t burn_in, uint64_t seed,
+             void *ws, size_t ws_bytes, void *stream, ppl_mcmc_result *out) {
+    clear_error();
+    if (!out) return fail(PPL_E_ARG, "out is NULL");
+    if (model != PPL_MODEL_POLY) return fail(PPL_E_MODEL, "MCMC supports POLY (got %d)", model);
+    if (int rc = check_n(n_chains)) return rc;
+    if (n_iters < 0 || n_iters > 0x7fffffffLL / 3) return fail(PPL_E_ARG, "n_iters %lld out of range", (long long)n_iters);
+    if (burn_in < 0 || burn_in > n_iters) return fail(PPL_E_ARG, "burn_in must be in [0, n_iters]");
+    McmcArgs a{};
+    if (int rc = check_model_data(model, data, a.hyper)) return rc;
+    if ((out->d_n_trace || out->d_log_alpha) && (double)n_iters * (double)n_chains > 4e12)
+        return fail(PPL_E_ARG, "trace of %lld x %lld entries is too large", (long long)n_iters, (long long)n_chains);
+    if (int rc = check_ws(ws, ws_bytes, mcmc_ws_bytes(n_chains))) return rc;
+    if (int rc = check_device()) return rc;
+    a.x = (const double *)data->x;
+    a.y = (const double *)data->y;
+    a.D = data->n_data;
+    a.C = n_chains;
+    a.T = n_iters;
+    a.burn = burn_in;
+    a.seed = seed;
+    a.state_out = out->d_state;
+    a.acc_out = out->d_accepts;
+    a.n_trace = out->d_n_trace;
+    a.la_trace = out->d_log_alpha;
+    a.summaries = out->d_summaries;
+    a.scalars = out->d_scalars ? out->d_scalars : (double *)ws;
+    a.ws = ws;
+    hipStream_t st = (hipStream_t)stream;
+    if (int rc = run_mcmc_poly(a, st)) return rc;
+    if (out->sync_host) {
+        double h[4];
+        PPL_HIP(hipMemcpyAsync(h, a.scalars, sizeof(h), hipMemcpyDeviceToHost, st));
+        PPL_HIP(hipStreamSynchronize(st));
+        out->accept_rate = h[0];
+    }
+    return PPL_OK;
 }
 
 // ------------------------------------------------------------ batched SMC --

@@ -27,10 +27,10 @@
 namespace ppl {
 
 constexpr int kStatsThreads = 256;
-constexpr int kStatsRows = 512;            // rows per workgroup of the statistics pass
+constexpr int kStatsRows = 64;             // rows per workgroup of the statistics pass
 constexpr int kSsThreads = 256;
 constexpr int kSsWaves = kSsThreads / 64;
-constexpr int kSsP = 2;                    // particles per thread
+constexpr int kSsP = 4;                    // particles per thread
 
 // Statistic e of a DIM-column problem: e < DIM^2 -> A[e / DIM][e % DIM];
 // e < DIM^2 + DIM -> b[e - DIM^2]; e == DIM^2 + DIM -> c.

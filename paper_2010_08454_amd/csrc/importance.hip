@@ -14,6 +14,7 @@
 #include "device.h"
 #include "host.h"
 #include "kernels.h"
+#include "poly.h"
 #include "timing.h"
 
 namespace ppl {
@@ -101,17 +102,7 @@ __global__ __launch_bounds__(kIsThreads) void poly_is_kernel(
     int nn[P];
 #pragma unroll
     for (int p = 0; p < P; ++p) {
-        const uint32_t i = (uint32_t)(base + p * kIsThreads + tid);
-        const uint4 w0 = philox(i, 0, 0, kTagPrior, key);
-        nn[p] = uniform_discrete(w0.x, n_lo, (uint32_t)(n_hi - n_lo + 1));
-        double z[6];
-#pragma unroll
-        for (int b = 1; b <= 3; ++b) {
-            const uint4 w = philox(i, b, 0, kTagPrior, key);
-            box_muller(unit_f64(w.x, w.y), unit_f64(w.z, w.w), z[2 * (b - 1)], z[2 * (b - 1) + 1]);
-        }
-#pragma unroll
-        for (int j = 0; j < 5; ++j) c[p][j] = sd * z[j];
+        poly_prior_draw((uint32_t)(base + p * kIsThreads + tid), key, sd, n_lo, n_hi, nn[p], c[p]);
     }
     double pc[P][5];
 #pragma unroll
