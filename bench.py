@@ -26,6 +26,10 @@ Other configurations print the same fields for their own workload:
   mcmc-poly         lightweight Metropolis-Hastings on the polynomial model (FP64):
                     2^16 chains x 1000 iterations over the C0 data, chain
                     iterations per second
+  enum-hmm          exact inference by enumeration: every path of a 4-state
+                    hidden Markov model over 20 steps (2^40 paths, FP64), paths
+                    per second; roofline of the summing pass (two FMA per path)
+                    against the FP64 vector peak
   lgssm             bootstrap SMC on the linear-Gaussian state space model
   gmm-batched       batched SMC over 256 mixture instances (autotuned first)
   resample-gather   resampling fused with the state gather, roofline against HBM
@@ -34,7 +38,7 @@ Other configurations print the same fields for their own workload:
   peaks             measured instruction and copy rates (not a hot-path line)
 
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu]
-                       [--config blr|blr-stats|poly|poly-paper|mcmc-poly|lgssm|gmm-batched|resample-gather|proposal-poly|
+                       [--config blr|blr-stats|poly|poly-paper|mcmc-poly|enum-hmm|lgssm|gmm-batched|resample-gather|proposal-poly|
                                  proposal-gmm|proposal-train|peaks]
 """
 import argparse
@@ -74,7 +78,7 @@ def parse():
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--config", default="blr",
-                    choices=["blr", "blr-stats", "poly", "poly-paper", "mcmc-poly", "lgssm", "gmm-batched",
+                    choices=["blr", "blr-stats", "poly", "poly-paper", "mcmc-poly", "enum-hmm", "lgssm", "gmm-batched",
                              "resample-gather",
                              "proposal-poly",
                              "proposal-gmm", "proposal-train", "peaks"])
@@ -281,6 +285,104 @@ def cpu_baseline_poly(x, y, n, seed, target_s=15.0):
 
 HBM_GBS = 8000.0
 GATHER_FIELDS = 16
+
+
+def cpu_baseline_enum(y, pi0, A, mu, sigma, target_s=15.0):
+    """The oracle's enumeration on the first T' steps of the same model, T' the
+    largest length it finishes in about target_s seconds.  Its cost per path
+    grows linearly with the length, so the rate is scaled by T' / T to paths of
+    the full length."""
+    import oracle
+    oracle.build()
+    K, T = len(pi0), len(y)
+    hyper = oracle.hmm_hyper(pi0, A, mu, sigma)
+
+    def measure(budget, threads):
+        prev = oracle.num_threads()
+        if threads is not None:
+            oracle.set_num_threads(threads)
+        try:
+            used = oracle.num_threads()
+            Tp = min(T, max(2, int(math.log(2e5) / math.log(K))))
+            t0 = time.perf_counter()
+            oracle.enumerate_hmm(y[:Tp], hyper)
+            per_path = (time.perf_counter() - t0) / K ** Tp
+            while Tp < T and per_path * K ** (Tp + 1) <= budget:
+                Tp += 1
+            t0 = time.perf_counter()
+            oracle.enumerate_hmm(y[:Tp], hyper)
+            dt = time.perf_counter() - t0
+            return K ** Tp / dt * Tp / T, Tp, dt, used
+        finally:
+            oracle.set_num_threads(prev)
+
+    v, Tp, dt, used = measure(target_s, None)
+    v1, Tp1, dt1, _ = measure(target_s / 3, 1)
+    return {"value": v, "unit": "paths/s", "cores": used, "kind": "oracle", "value_1_thread": v1,
+            "cpu_model": cpu_model(), "usable_cores": len(os.sched_getaffinity(0)),
+            "sample": f"all {K}^{Tp} paths of the first {Tp} steps ({dt:.1f} s, {used} threads); 1 thread: "
+                      f"{K}^{Tp1} paths of {Tp1} steps ({dt1:.1f} s); rates scaled by T'/{T} to {T}-step paths; "
+                      "FP64 oracle"}
+
+
+def bench_enum(args, ppl, synthetic, torch, dev, stream):
+    """Exact inference by enumeration over a hidden Markov model: K = 4 states,
+    T = 20 steps, 2^40 paths (synthetic chain and observations, see
+    synthetic.hmm_instance).  One step = one ppl_enumerate call (emission
+    table, the maximum pass, the summing pass, merges).  Roofline: the summing
+    pass at two FP64 FMA (4 FLOP) per path against the FP64 vector peak; the
+    maximum pass (an add and a max per path) is reported beside it."""
+    K, T = 4, 20
+    pi0, A, mu, sigma, y, _ = synthetic.hmm_instance(K, T)
+    dy = torch.from_numpy(y).to(dev)
+    data = ppl.hmm_data(dy, pi0, A, mu, sigma)
+    ws = ppl.workspace(ppl.ppl_workspace_size(ppl.PPL_MODEL_HMM, data, 1, ppl.PPL_ALGO_ENUM), dev)
+    scal = torch.empty(4, dtype=torch.float64, device=dev)
+    marg = torch.empty((T, K), dtype=torch.float64, device=dev)
+    mp = torch.empty(T, dtype=torch.int32, device=dev)
+
+    def step():
+        ppl.ppl_enumerate(ppl.PPL_MODEL_HMM, data, ws=ws, stream=stream, scalars=scal, marginals=marg, map_path=mp)
+
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    ppl.ppl_timing_enable(True)
+    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    ev0.record(stream)
+    for _ in range(args.steps):
+        step()
+    ev1.record(stream)
+    torch.cuda.synchronize()
+    total_ms = ev0.elapsed_time(ev1)
+    s_ms, s_n = ppl.ppl_timing_query("enum_sum_kernel")
+    m_ms, m_n = ppl.ppl_timing_query("enum_max_kernel")
+    ppl.ppl_timing_enable(False)
+    sc = scal.cpu().numpy()
+    assert sc[3] == 0 and math.isfinite(sc[0]), f"device status {sc[3]}"
+    paths = float(K) ** T
+    ms_per_step = total_ms / args.steps
+    s_avg, m_avg = s_ms / max(s_n, 1), m_ms / max(m_n, 1)
+    flop_per_launch = 4 * paths
+    achieved = flop_per_launch / (s_avg / 1e3) / 1e12
+    out = {"metric": "paths/s", "value": paths / (ms_per_step / 1e3), "unit": "paths/s", "n_gpus": 1,
+           "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(ms_per_step, 4),
+           "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f64",
+           "data": "synthetic (seeded generators, inputs resident in HBM)",
+           "config": {"workload": "enum-hmm", "model": "hidden Markov model, Gaussian emissions",
+                      "states": K, "steps": T, "paths": paths, "precision": "fp64"},
+           "log_evidence": float(sc[0]), "map_log_joint": float(sc[2]),
+           "roofline": {"bound": "alu", "achieved": round(achieved, 3), "peak": FP64_VALU_TFLOPS, "unit": "TFLOP/s",
+                        "frac": round(achieved / FP64_VALU_TFLOPS, 4), "traffic": None,
+                        "kernel": "enum_sum_kernel", "kernel_ms": round(s_avg, 4), "kernel_launches": s_n,
+                        "flop_per_launch": flop_per_launch,
+                        "max_pass": {"kernel": "enum_max_kernel", "kernel_ms": round(m_avg, 4),
+                                     "ops_per_path": 2,
+                                     "achieved_top_s": round(2 * paths / (m_avg / 1e3) / 1e12, 3),
+                                     "peak_top_s": round(FP64_VALU_TFLOPS / 2, 2)}}}
+    if not args.no_cpu:
+        out["cpu_baseline"] = cpu_baseline_enum(y, pi0, A, mu, sigma, target_s=args.cpu_seconds)
+    print(json.dumps(out), flush=True)
 
 
 def bench_resample_gather(args, ppl, synthetic, torch, dev, stream):
@@ -657,6 +759,9 @@ def main():
         return
     if args.config == "resample-gather":
         bench_resample_gather(args, ppl, synthetic, torch, dev, stream)
+        return
+    if args.config == "enum-hmm":
+        bench_enum(args, ppl, synthetic, torch, dev, stream)
         return
 
     if args.config == "blr":

@@ -93,7 +93,16 @@ enum {
      * per call in FP64 (O(D d^2)), then each particle's residual sum of
      * squares is c - 2 w.b + w^T A w in FP64 (O(d^2) instead of O(D d)).
      * Importance sampling only. */
-    PPL_MODEL_BLR_STATS = 5
+    PPL_MODEL_BLR_STATS = 5,
+    /* Hidden Markov model with K discrete states over T steps (1 <= K <= 8,
+     * 1 <= T <= 40): z_0 ~ Categorical(pi0), z_t ~ Categorical(A[z_{t-1}]),
+     * observe(Normal(mu[z_t], sigma), y_t).  Every sample site has finite
+     * support, so exact inference by enumeration applies (ppl_enumerate).
+     * FP64 throughout.  data: y[T] float64, x = NULL, dim = K, dtype PPL_F64;
+     * hyper = {K, sigma, pi0[K], A[K][K] (row = previous state), mu[K]}
+     * (n_hyper = 2 + 2K + K^2, required; probabilities >= 0 and finite,
+     * sigma > 0). */
+    PPL_MODEL_HMM = 6
 };
 
 enum { PPL_F32 = 1, PPL_F64 = 2 };
@@ -170,7 +179,7 @@ typedef struct ppl_proposal {
     const void *d_params;
 } ppl_proposal;
 
-enum { PPL_ALGO_IS = 0, PPL_ALGO_SMC = 1, PPL_ALGO_LSE = 2, PPL_ALGO_RESAMPLE = 3, PPL_ALGO_MCMC = 4 };
+enum { PPL_ALGO_IS = 0, PPL_ALGO_SMC = 1, PPL_ALGO_LSE = 2, PPL_ALGO_RESAMPLE = 3, PPL_ALGO_MCMC = 4, PPL_ALGO_ENUM = 5 };
 
 /* Bytes of device workspace an entry point needs for (model, data, N).
  * The workspace is a caller-owned device buffer, at least 256-byte aligned,
@@ -325,6 +334,31 @@ typedef struct ppl_mcmc_result {
  * for n_chains (ppl_workspace_size with n_particles = n_chains). */
 int ppl_mcmc(int model, const ppl_data *data, int64_t n_chains, int64_t n_iters, int64_t burn_in, uint64_t seed,
              void *d_ws, size_t ws_bytes, void *stream, ppl_mcmc_result *out);
+
+/* ------------------------------------------------------ enumeration -- */
+/* Outputs of ppl_enumerate (any device pointer may be NULL). */
+typedef struct ppl_enum_result {
+    double log_evidence;      /* host copies of d_scalars[0], [2], [3] (sync_host only) */
+    double map_log_joint;
+    int32_t status;
+    int32_t sync_host;
+    double *d_scalars;        /* [4]: log Z, number of paths K^T, log joint of the most probable
+                               * path, status (0, PPL_E_ZERO_WEIGHT or PPL_E_NONFINITE) */
+    double *d_marginals;      /* [T][K]: P(z_t = k | y) */
+    int32_t *d_map;           /* [T]: the most probable path (the lowest path index among equal
+                               * log joints; index = sum_t z_t K^(T-1-t)) */
+} ppl_enum_result;
+
+/* Exact inference by enumeration (paper Sec. 3.6.1): every execution of the
+ * model, i.e. every path z in {0..K-1}^T, weighted by the product of its
+ * sample probabilities and its factors; Z = sum_z exp(lw(z)).  Every path is
+ * evaluated (no dynamic programming over the chain structure).  Sums are FP64
+ * relative to the largest log-weight; a NaN log-weight makes the status
+ * PPL_E_NONFINITE and log Z NaN; all weights zero: PPL_E_ZERO_WEIGHT and
+ * log Z = -inf.  model: PPL_MODEL_HMM; K^T <= 2^50.  Workspace:
+ * ppl_workspace_size(PPL_MODEL_HMM, data, 1, PPL_ALGO_ENUM).  With sync_host
+ * the call blocks on the stream and returns the device status. */
+int ppl_enumerate(int model, const ppl_data *data, void *d_ws, size_t ws_bytes, void *stream, ppl_enum_result *out);
 
 /* ------------------------------------------------------ batched SMC -- */
 /* One model instance of a batched run.  The caller passes the same table

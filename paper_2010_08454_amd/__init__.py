@@ -22,16 +22,17 @@ PPL_OK, PPL_E_ARG, PPL_E_MODEL, PPL_E_DEVICE, PPL_E_HIP = 0, -1, -2, -3, -4
 PPL_E_WORKSPACE, PPL_E_NONFINITE, PPL_E_ZERO_WEIGHT, PPL_E_UNSUPPORTED = -5, -6, -7, -8
 PPL_MODEL_POLY, PPL_MODEL_BLR, PPL_MODEL_LGSSM, PPL_MODEL_GMM = 1, 2, 3, 4
 PPL_MODEL_BLR_STATS = 5
+PPL_MODEL_HMM = 6
 PPL_F32, PPL_F64 = 1, 2
 PPL_Q_PRIOR, PPL_Q_GAUSS_FULL, PPL_Q_POLY_MIX, PPL_Q_GMM_MIX = 0, 1, 2, 3
-PPL_ALGO_IS, PPL_ALGO_SMC, PPL_ALGO_LSE, PPL_ALGO_RESAMPLE, PPL_ALGO_MCMC = 0, 1, 2, 3, 4
+PPL_ALGO_IS, PPL_ALGO_SMC, PPL_ALGO_LSE, PPL_ALGO_RESAMPLE, PPL_ALGO_MCMC, PPL_ALGO_ENUM = 0, 1, 2, 3, 4, 5
 PPL_INST_NO_RECORD = 1
 PPL_NOALLOC_SCRATCH_BYTES = 16 << 20
 
 # Exported C symbols (kept in step with include/ppl.h).
 EXPORTS = ("ppl_status_string", "ppl_last_error", "ppl_version", "ppl_workspace_size",
            "ppl_importance", "ppl_importance_noalloc", "ppl_lse_ess", "ppl_resample", "ppl_resample_gather", "ppl_philox", "ppl_smc",
-           "ppl_smc_ex", "ppl_mcmc",
+           "ppl_smc_ex", "ppl_mcmc", "ppl_enumerate",
            "ppl_timing_enable", "ppl_timing_query")
 
 P = ctypes.c_void_p
@@ -66,6 +67,11 @@ class PplMcmcResult(ctypes.Structure):
                 ("d_log_alpha", P)]
 
 
+class PplEnumResult(ctypes.Structure):
+    _fields_ = [("log_evidence", ctypes.c_double), ("map_log_joint", ctypes.c_double), ("status", ctypes.c_int32),
+                ("sync_host", ctypes.c_int32), ("d_scalars", P), ("d_marginals", P), ("d_map", P)]
+
+
 class PplError(RuntimeError):
     def __init__(self, code, msg):
         super().__init__(f"libppl error {code}: {msg}")
@@ -92,6 +98,8 @@ def _load():
                           ctypes.POINTER(PplResult)]
     L.ppl_mcmc.argtypes = [ctypes.c_int, ctypes.POINTER(PplData), i64, i64, i64, u64, P, ctypes.c_size_t, P,
                            ctypes.POINTER(PplMcmcResult)]
+    L.ppl_enumerate.argtypes = [ctypes.c_int, ctypes.POINTER(PplData), P, ctypes.c_size_t, P,
+                                ctypes.POINTER(PplEnumResult)]
     L.ppl_smc_ex.argtypes = [ctypes.c_int, ctypes.POINTER(PplData), i64, u64, ctypes.POINTER(PplSmcOptions), P,
                              ctypes.c_size_t, P, ctypes.POINTER(PplResult)]
     L.ppl_importance_noalloc.argtypes = [ctypes.c_int, ctypes.POINTER(PplData), i64, u64,
@@ -271,6 +279,24 @@ def ppl_mcmc(model, data, n_chains, n_iters, seed, burn_in=0, ws=None, stream=No
                         d_log_alpha=_ptr(log_alpha))
     _check(lib.ppl_mcmc(model, ctypes.byref(data), int(n_chains), int(n_iters), int(burn_in),
                         int(seed) & (2 ** 64 - 1), _ptr(ws), ws.numel(), _stream(stream), ctypes.byref(res)))
+    return res
+
+
+def hmm_data(y, pi0, A, mu, sigma=1.0):
+    """ppl_data of the hidden Markov model: y a float64 device tensor [T];
+    hyper = {K, sigma, pi0, A (row = previous state), mu}."""
+    K = len(pi0)
+    hyper = [K, sigma] + [float(v) for v in pi0] + [float(v) for row in A for v in row] + [float(v) for v in mu]
+    return make_data(None, y, dim=K, hyper=hyper, dtype=PPL_F64)
+
+
+def ppl_enumerate(model, data, ws=None, stream=None, scalars=None, marginals=None, map_path=None, sync=False):
+    """Exact inference by enumerating every path; returns the ppl_enum_result struct."""
+    if ws is None:
+        ws = workspace(ppl_workspace_size(model, data, 1, PPL_ALGO_ENUM))
+    res = PplEnumResult(sync_host=1 if sync else 0, d_scalars=_ptr(scalars), d_marginals=_ptr(marginals),
+                        d_map=_ptr(map_path))
+    _check(lib.ppl_enumerate(model, ctypes.byref(data), _ptr(ws), ws.numel(), _stream(stream), ctypes.byref(res)))
     return res
 
 

@@ -211,6 +211,35 @@ int importance_call(int model, const ppl_data *data, int64_t n, uint64_t seed, c
     return PPL_OK;
 }
 
+// Validates PPL_MODEL_HMM data; fills the argument block's sizes and host views.
+static int check_hmm(const ppl_data *d, EnumArgs &a) {
+    if (!d) return fail(PPL_E_ARG, "data is NULL");
+    if (!d->hyper || d->n_hyper < 2) return fail(PPL_E_ARG, "the HMM needs hyper = {K, sigma, pi0, A, mu}");
+    const double *h = d->hyper;
+    const int K = (int)h[0];
+    if (h[0] != (double)K || K < 1 || K > 8) return fail(PPL_E_ARG, "HMM K must be an integer in 1..8");
+    if (d->dim != K) return fail(PPL_E_ARG, "data dim %d differs from hyper K %d", d->dim, K);
+    if (d->n_hyper != 2 + 2 * K + K * K) return fail(PPL_E_ARG, "HMM hyper needs %d values (got %d)", 2 + 2 * K + K * K, d->n_hyper);
+    if (d->n_data < 1 || d->n_data > 40) return fail(PPL_E_ARG, "HMM T must be in 1..40 (got %lld)", (long long)d->n_data);
+    if (!d->y) return fail(PPL_E_ARG, "HMM needs y");
+    if (d->dtype != PPL_F64) return fail(PPL_E_ARG, "HMM data are float64");
+    if (!finite_pos(h[1])) return fail(PPL_E_ARG, "HMM sigma must be positive");
+    for (int i = 2; i < 2 + K + K * K; ++i)
+        if (!(h[i] >= 0.0) || !std::isfinite(h[i])) return fail(PPL_E_ARG, "HMM probabilities must be finite and >= 0");
+    for (int i = 2 + K + K * K; i < 2 + 2 * K + K * K; ++i)
+        if (!std::isfinite(h[i])) return fail(PPL_E_ARG, "HMM means must be finite");
+    const int T = (int)d->n_data;
+    if ((double)T * std::log2((double)K) > 50.0) return fail(PPL_E_UNSUPPORTED, "%d^%d paths exceed 2^50", K, T);
+    a.K = K;
+    a.T = T;
+    a.y = (const double *)d->y;
+    a.sigma = h[1];
+    a.pi0 = h + 2;
+    a.A = h + 2 + K;
+    a.mu = h + 2 + K + K * K;
+    return PPL_OK;
+}
+
 }  // namespace ppl
 
 using namespace ppl;
@@ -256,6 +285,13 @@ int ppl_workspace_size(int model, const ppl_data *data, int64_t n, int algo, siz
             if (model != PPL_MODEL_POLY) return fail(PPL_E_MODEL, "MCMC supports POLY (got %d)", model);
             if (int rc = check_model_data(model, data, h)) return rc;
             *bytes = mcmc_ws_bytes(n);
+            return PPL_OK;
+        }
+        case PPL_ALGO_ENUM: {
+            EnumArgs a{};
+            if (model != PPL_MODEL_HMM) return fail(PPL_E_MODEL, "enumeration supports HMM (got %d)", model);
+            if (int rc = check_hmm(data, a)) return rc;
+            *bytes = enum_ws_bytes(a.K, a.T);
             return PPL_OK;
         }
         case PPL_ALGO_SMC: {
@@ -403,6 +439,32 @@ int ppl_mcmc(int model, const ppl_data *data, int64_t n_chains, int64_t n_iters,
         PPL_HIP(hipMemcpyAsync(h, a.scalars, sizeof(h), hipMemcpyDeviceToHost, st));
         PPL_HIP(hipStreamSynchronize(st));
         out->accept_rate = h[0];
+    }
+    return PPL_OK;
+}
+
+int ppl_enumerate(int model, const ppl_data *data, void *ws, size_t ws_bytes, void *stream, ppl_enum_result *out) {
+    clear_error();
+    if (!out) return fail(PPL_E_ARG, "out is NULL");
+    if (model != PPL_MODEL_HMM) return fail(PPL_E_MODEL, "enumeration supports HMM (got %d)", model);
+    EnumArgs a{};
+    if (int rc = check_hmm(data, a)) return rc;
+    if (int rc = check_ws(ws, ws_bytes, enum_ws_bytes(a.K, a.T))) return rc;
+    if (int rc = check_device()) return rc;
+    a.scalars = out->d_scalars ? out->d_scalars : (double *)ws;
+    a.marginals = out->d_marginals;
+    a.map = out->d_map;
+    a.ws = ws;
+    hipStream_t st = (hipStream_t)stream;
+    if (int rc = run_enumerate_hmm(a, st)) return rc;
+    if (out->sync_host) {
+        double h[4];
+        PPL_HIP(hipMemcpyAsync(h, a.scalars, sizeof(h), hipMemcpyDeviceToHost, st));
+        PPL_HIP(hipStreamSynchronize(st));
+        out->log_evidence = h[0];
+        out->map_log_joint = h[2];
+        out->status = (int32_t)h[3];
+        if (out->status) return fail(out->status, "device reported status %d (%s)", out->status, ppl_status_string(out->status));
     }
     return PPL_OK;
 }

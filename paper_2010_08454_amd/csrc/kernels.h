@@ -46,6 +46,20 @@ int run_resample(const void *lw, bool f64, int64_t n, uint64_t seed, uint32_t st
 int run_resample_gather(const void *lw, bool f64, int64_t n, uint64_t seed, uint32_t step, uint32_t inst, int nf,
                         const void *state_in, void *state_out, int32_t *anc, void *ws, hipStream_t st);
 
+// Enumeration of every path of a hidden Markov model (see ppl_enumerate).
+struct EnumArgs {
+    int K, T;
+    const double *y;            // [T] device
+    double sigma;
+    const double *pi0, *A, *mu; // host: [K], [K][K], [K]
+    double *scalars;            // [4] device
+    double *marginals;          // [T][K] device or null
+    int32_t *map;               // [T] device or null
+    void *ws;
+};
+size_t enum_ws_bytes(int K, int T);
+int run_enumerate_hmm(const EnumArgs &a, hipStream_t st);
+
 int run_philox(uint64_t seed, uint32_t c1, uint32_t c2, uint32_t c3, int64_t n, uint32_t *out, hipStream_t st);
 
 }  // namespace ppl

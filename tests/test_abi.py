@@ -140,3 +140,37 @@ def test_other_entry_points_validate(ppl):
     assert L.ppl_smc(ppl.PPL_MODEL_BLR, ctypes.byref(lg), 1000, 1, 0.5, 256, 1 << 20, None, ctypes.byref(res)) == ppl.PPL_E_MODEL
     g = _data(ppl, y=256, n_data=1000, dim=9, dtype=ppl.PPL_F32)
     assert L.ppl_smc(ppl.PPL_MODEL_GMM, ctypes.byref(g), 1000, 1, 0.5, 256, 1 << 20, None, ctypes.byref(res)) == ppl.PPL_E_ARG
+
+
+def _hmm(ppl, K=3, T=8, pi0=None, sigma=1.0, n_hyper=None, dtype=None):
+    pi0 = [1.0 / K] * K if pi0 is None else pi0
+    hyper = [K, sigma] + list(pi0) + [1.0 / K] * (K * K) + [0.0] * K
+    h = (ctypes.c_double * len(hyper))(*hyper)
+    d = ppl.PplData(x=None, y=256, n_data=T, dim=K, dtype=ppl.PPL_F64 if dtype is None else dtype,
+                    hyper=ctypes.cast(h, ctypes.POINTER(ctypes.c_double)),
+                    n_hyper=len(hyper) if n_hyper is None else n_hyper)
+    d._keep = h
+    return d
+
+
+def test_enumerate_validates(ppl):
+    """ppl_enumerate and its workspace size reject bad models before a launch."""
+    L = ppl.lib
+    res = ppl.PplEnumResult()
+    E = lambda d, ws=256, nb=1 << 20, model=ppl.PPL_MODEL_HMM: L.ppl_enumerate(model, ctypes.byref(d), ws, nb, None, ctypes.byref(res))
+    assert E(_hmm(ppl), model=ppl.PPL_MODEL_POLY) == ppl.PPL_E_MODEL
+    assert E(_hmm(ppl, K=9)) == ppl.PPL_E_ARG                       # K out of range
+    assert E(_hmm(ppl, T=0)) == ppl.PPL_E_ARG
+    assert E(_hmm(ppl, T=41)) == ppl.PPL_E_ARG
+    assert E(_hmm(ppl, n_hyper=10)) == ppl.PPL_E_ARG                # wrong hyper length
+    assert E(_hmm(ppl, sigma=0.0)) == ppl.PPL_E_ARG
+    assert E(_hmm(ppl, pi0=[0.5, -0.1, 0.6])) == ppl.PPL_E_ARG
+    assert E(_hmm(ppl, pi0=[0.5, float("nan"), 0.5])) == ppl.PPL_E_ARG
+    assert E(_hmm(ppl, dtype=ppl.PPL_F32)) == ppl.PPL_E_ARG
+    assert E(_hmm(ppl, K=3, T=32)) == ppl.PPL_E_UNSUPPORTED          # 3^32 > 2^50 paths
+    assert E(_hmm(ppl, K=2, T=40), ws=256, nb=64) == ppl.PPL_E_WORKSPACE
+    assert L.ppl_enumerate(ppl.PPL_MODEL_HMM, ctypes.byref(_hmm(ppl)), 256, 1 << 20, None, None) == ppl.PPL_E_ARG
+    assert _size(ppl, ppl.PPL_MODEL_HMM, _hmm(ppl, K=9), 1, ppl.PPL_ALGO_ENUM)[0] == ppl.PPL_E_ARG
+    assert _size(ppl, ppl.PPL_MODEL_GMM, _hmm(ppl), 1, ppl.PPL_ALGO_ENUM)[0] == ppl.PPL_E_MODEL
+    rc, nb = _size(ppl, ppl.PPL_MODEL_HMM, _hmm(ppl, K=4, T=18), 1, ppl.PPL_ALGO_ENUM)
+    assert rc == 0 and 256 < nb < 1 << 22
