@@ -21,13 +21,17 @@
 // (t, k).  Records are merged in workgroup order, so results do not depend on
 // timing.
 //
-// The last BD sites form a block whose K^BD suffixes are tabulated per state
-// j before it: their log-weights b[j][m] (the sum of c over the block's sites)
-// and, for the second pass, f[j][m] = exp(b[j][m] - q[j]) with q[j] = max_m
-// b[j][m].  Pass 1 then costs one add and one max per path; pass 2 takes one
-// exp per block, G = exp(lw_j + q[j] - M) (the weight of the block's best
-// path, at most 1, so it cannot overflow), and two fused multiply-adds per
-// path (G f[j][m] into its last site's sum and into the block subtotal).
+// The nested sites run in two forms.  Pass 1 stays in the log domain: one
+// add and one max per path.  Pass 2 runs in the linear domain from one exp
+// per prefix: each node carries the weight, relative to M, of the best path
+// below it, w = exp(lw_node + V_L[z] - M) <= 1, where V_L[j] is the largest
+// log-weight any completion from state j at nested level L can add (a max
+// over the suffix, tabulated per state).  A child's weight is the parent's
+// times F_L[j][k] = exp(c + V_{L+1}[k] - V_L[j]) <= 1, so no product
+// overflows, and a product that underflows belongs to a subtree whose every
+// path is below e^-745 of M.  The references set the scale only: every path's
+// weight is still formed and added (two FMAs at the last site: into its
+// site sum and into the parent's subtotal).
 #include "device.h"
 #include "host.h"
 #include "kernels.h"
@@ -39,7 +43,8 @@ constexpr int kEnThreads = 128;
 constexpr int kEnMaxT = 40;
 constexpr int kEnMaxGrid = 2048;
 constexpr int kEnMaxC = 1024;            // T K^2 at the path limit (K = 8, T = 16)
-constexpr int kEnMaxB = 512;             // K^(BD + 1)
+constexpr int kEnMaxTS = 12;             // nested sites
+constexpr int kEnMaxF = 256;             // TS K^2 factors
 
 __host__ __device__ constexpr uint64_t ipow(uint64_t b, int e) { return e == 0 ? 1 : b * ipow(b, e - 1); }
 
@@ -57,144 +62,46 @@ struct EnumDev {
 struct EnLds {
     double c[kEnMaxC];           // c[t][j][k], t >= 1
     double c0[8];                // site 0: log pi0[k] + le[0][k]
-    double b[kEnMaxB];           // block log-weights b[j][m]
-    double f[kEnMaxB];           // block factors f[j][m]
-    double q[8];
+    double cn[kEnMaxF];          // cn[L][j][k] = c[tail + L][j][k], nested level L (compile-time offsets)
+    double F[kEnMaxF];           // F[L][j][k], nested level L (site tail + L)
+    double V[(kEnMaxTS + 1) * 8];// V[L][j], V[TS][j] = 0
 };
 
-template <int K, int BD>
-__device__ void en_stage(EnLds &s, const EnumDev &a) {
-    constexpr int KB = (int)ipow(K, BD);
-    const int T = a.T;
+// Stages the tables: c for every site, and for the TS nested sites the
+// suffix maxima V and the linear-domain factors F (pass 2 only).
+template <int K, int TS>
+__device__ void en_stage(EnLds &s, const EnumDev &a, bool factors) {
+    const int T = a.T, tail = a.tail;
     for (int i = threadIdx.x; i < T * K * K; i += kEnThreads) {
         const int t = i / (K * K), j = (i / K) % K, k = i % K;
         s.c[i] = t == 0 ? 0.0 : a.lA[j * K + k] + a.le[t * K + k];
     }
     if (threadIdx.x < K) s.c0[threadIdx.x] = a.lpi[threadIdx.x] + a.le[threadIdx.x];
     __syncthreads();
-    {
-        // suffix m of the block (digits over sites T - BD .. T - 1) after state j
-        for (int i = threadIdx.x; i < K * KB; i += kEnThreads) {
-            const int j = i / KB;
-            int m = i % KB, prev = j, div = KB / K;      // BD = 0: the empty suffix, b = 0, f = 1
-            double v = 0.0;
-            for (int d = 0; d < BD; ++d) {
-                const int k = m / div;
-                m -= k * div;
-                div /= K;
-                v += s.c[(T - BD + d) * K * K + prev * K + k];
-                prev = k;
+    for (int i = threadIdx.x; i < TS * K * K; i += kEnThreads) s.cn[i] = s.c[tail * K * K + i];
+    __syncthreads();
+    if (!factors) return;
+    if (threadIdx.x == 0) {
+        for (int j = 0; j < K; ++j) s.V[TS * K + j] = 0.0;
+        for (int L = TS - 1; L >= 0; --L)
+            for (int j = 0; j < K; ++j) {
+                double v = -INFINITY;
+                for (int k = 0; k < K; ++k) v = fmax(v, s.c[((tail + L) * K + j) * K + k] + s.V[(L + 1) * K + k]);
+                s.V[L * K + j] = v;
             }
-            s.b[i] = v;
-        }
-        __syncthreads();
-        if (threadIdx.x < K) {
-            double q = -INFINITY;
-            for (int m = 0; m < KB; ++m) q = fmax(q, s.b[threadIdx.x * KB + m]);
-            s.q[threadIdx.x] = q;
-        }
-        __syncthreads();
-        for (int i = threadIdx.x; i < K * KB; i += kEnThreads) {
-            const double q = s.q[i / KB];
-            s.f[i] = q > -INFINITY ? exp(s.b[i] - q) : 0.0;
-        }
+    }
+    __syncthreads();
+    for (int i = threadIdx.x; i < TS * K * K; i += kEnThreads) {
+        const int L = i / (K * K), j = (i / K) % K, k = i % K;
+        const double vj = s.V[L * K + j];
+        s.F[i] = vj > -INFINITY ? exp(s.c[((tail + L) * K + j) * K + k] + s.V[(L + 1) * K + k] - vj) : 0.0;
     }
     __syncthreads();
 }
 
-// ---- pass 1: nested loops over the last TS sites.  Levels above the block's
-// root are runtime loops; the root level (TS - BD - 1) is unrolled so the
-// block's table row j is a compile-time index.
-template <int K, int BD, int D>
-struct BlockMax {
-    // largest log-weight of the block under state j with log-weight lw
-    __device__ static double run(const double *b, int m0, double lw) {
-        double v = -INFINITY;
-#pragma unroll
-        for (int k = 0; k < K; ++k) v = fmax(v, BlockMax<K, BD, D + 1>::run(b, m0 * K + k, lw));
-        return v;
-    }
-};
-template <int K, int BD>
-struct BlockMax<K, BD, BD> {
-    __device__ static double run(const double *b, int m, double lw) { return lw + b[m]; }
-};
-
-template <int K, int L, int TS, int BD>
-struct WalkMax {
-    __device__ static void run(const EnLds &s, int t, int prev, double lw, uint64_t idx, double &best,
-                               uint64_t &bidx) {
-        constexpr int KB = (int)ipow(K, BD);
-        if constexpr (L < TS - BD - 1) {
-#pragma unroll 1
-            for (int k = 0; k < K; ++k)
-                WalkMax<K, L + 1, TS, BD>::run(s, t + 1, k, lw + s.c[(t * K + prev) * K + k], idx * K + k, best,
-                                               bidx);
-        } else {
-#pragma unroll
-            for (int j = 0; j < K; ++j) {
-                const double lwj = lw + s.c[(t * K + prev) * K + j];
-                const double v = BlockMax<K, BD, 0>::run(s.b + j * KB, 0, lwj);
-                if (v > best) {
-                    int m = 0;
-                    while (m < KB - 1 && lwj + s.b[j * KB + m] != v) ++m;   // the first suffix reaching it
-                    best = v;
-                    bidx = (idx * K + j) * KB + m;
-                }
-            }
-        }
-    }
-};
-
-// ---- pass 2: the same loops; the block's paths in the linear domain.
-template <int K, int TS, int BD, int D>
-struct BlockSum {
-    // sum of the block's path weights G f[m] under suffix prefix m0, adding each site's share to marg
-    __device__ static double run(const double *f, int m0, double G, double (&marg)[TS][K]) {
-        double tot = 0.0;
-#pragma unroll
-        for (int k = 0; k < K; ++k) {
-            if constexpr (D == BD - 1) {
-                const double w = f[m0 * K + k];
-                marg[TS - 1][k] = fma(G, w, marg[TS - 1][k]);
-                tot = fma(G, w, tot);
-            } else {
-                const double sub = BlockSum<K, TS, BD, D + 1>::run(f, m0 * K + k, G, marg);
-                marg[TS - BD + D][k] += sub;
-                tot += sub;
-            }
-        }
-        return tot;
-    }
-};
-
-template <int K, int L, int TS, int BD>
-struct WalkSum {
-    __device__ static double run(const EnLds &s, int t, int prev, double lw, double M, double (&marg)[TS][K]) {
-        constexpr int KB = (int)ipow(K, BD);
-        double tot = 0.0;
-        if constexpr (L < TS - BD - 1) {
-#pragma unroll 1
-            for (int k = 0; k < K; ++k) {
-                const double sub =
-                    WalkSum<K, L + 1, TS, BD>::run(s, t + 1, k, lw + s.c[(t * K + prev) * K + k], M, marg);
-#pragma unroll
-                for (int kk = 0; kk < K; ++kk) marg[L][kk] += (k == kk) ? sub : 0.0;
-                tot += sub;
-            }
-        } else {
-#pragma unroll
-            for (int j = 0; j < K; ++j) {
-                const double G = exp(lw + s.c[(t * K + prev) * K + j] + s.q[j] - M);
-                double sub = G;
-                if constexpr (BD > 0) sub = BlockSum<K, TS, BD, 0>::run(s.f + j * KB, 0, G, marg);
-                marg[L][j] += sub;
-                tot += sub;
-            }
-        }
-        return tot;
-    }
-};
+// Innermost unrolled levels per state count (K^UL paths below the node the
+// runtime loops hand over: 64, 81, 64, then K^2).
+constexpr int en_ul_max(int K) { return K == 2 ? 6 : K == 3 ? 4 : K == 4 ? 3 : 2; }
 
 // Log-weight of prefix p (its digits are sites 0..tail-1) and its last state.
 template <int K>
@@ -210,16 +117,114 @@ __device__ __forceinline__ double en_prefix(const EnLds &s, int tail, uint64_t p
     return lw;
 }
 
+// ---- pass 1 (log domain).  Levels above TS - UL are runtime loops; the last
+// UL levels are unrolled, so their table rows are compile-time indices.
+template <int K, int L, int TS, int UL>
+struct WalkMax {
+    // largest log-weight below a node of an unrolled level
+    __device__ static double leafmax(const EnLds &s, int prev, double lw) {
+        double v = 0.0;
+#pragma unroll
+        for (int k = 0; k < K; ++k) {
+            const double lk = lw + s.cn[(L * K + prev) * K + k];
+            double x;
+            if constexpr (L == TS - 1)
+                x = lk;
+            else
+                x = WalkMax<K, L + 1, TS, UL>::leafmax(s, k, lk);
+            v = k == 0 ? x : fmax(v, x);
+        }
+        return v;
+    }
+    // Raises best to the largest log-weight below the node and, when it does,
+    // records the index of the node at level TS - UL that holds it.
+    __device__ static void run(const EnLds &s, int prev, double lw, uint64_t idx, double &best, uint64_t &bnode) {
+        if constexpr (L < TS - UL) {
+#pragma unroll 1
+            for (int k = 0; k < K; ++k)
+                WalkMax<K, L + 1, TS, UL>::run(s, k, lw + s.cn[(L * K + prev) * K + k], idx * K + k, best, bnode);
+        } else {
+            const double v = leafmax(s, prev, lw);
+            if (v > best) {
+                best = v;
+                bnode = idx;
+            }
+        }
+    }
+};
+
+// The path index of the largest log-weight v below node `node` (at level
+// TS - UL) of prefix p: the node's log-weight is re-summed in the walk's
+// order, then the first of its K^UL completions that reaches v is found.
+template <int K, int TS, int UL>
+__device__ uint64_t en_locate(const EnLds &s, int tail, uint64_t p, uint64_t node, double v) {
+    constexpr int NL = TS - UL;                  // runtime levels above the node
+    constexpr int n = (int)ipow(K, UL);
+    int prev;
+    double lw = en_prefix<K>(s, tail, p, prev);
+    uint64_t div = ipow(K, NL) / K;
+    for (int L = 0; L < NL; ++L, div /= K) {
+        const int k = (int)((node / div) % K);
+        lw = lw + s.cn[(L * K + prev) * K + k];
+        prev = k;
+    }
+    int m = 0;
+    for (; m < n - 1; ++m) {
+        double x = lw;
+        int pv = prev, r = m;
+        for (int d = 0, dv = n / K; d < UL; ++d, dv /= K) {
+            const int k = r / dv;
+            r -= k * dv;
+            x = x + s.cn[((NL + d) * K + pv) * K + k];
+            pv = k;
+        }
+        if (x == v) break;
+    }
+    return (p * ipow(K, NL) + node) * n + m;
+}
+
+// ---- pass 2 (linear domain): returns the sum of the path weights below the
+// node and adds each nested site's share to marg.
+template <int K, int L, int TS, int UL>
+struct WalkSum {
+    __device__ static double run(const EnLds &s, int prev, double w, double (&marg)[TS][K]) {
+        const double *F = s.F + (L * K + prev) * K;
+        double tot = 0.0;
+        if constexpr (L < TS - UL) {
+#pragma unroll 1
+            for (int k = 0; k < K; ++k) {
+                const double sub = WalkSum<K, L + 1, TS, UL>::run(s, k, w * F[k], marg);
+#pragma unroll
+                for (int kk = 0; kk < K; ++kk) marg[L][kk] += (k == kk) ? sub : 0.0;
+                tot += sub;
+            }
+        } else if constexpr (L == TS - 1) {
+#pragma unroll
+            for (int k = 0; k < K; ++k) {
+                marg[L][k] = fma(w, F[k], marg[L][k]);
+                tot = fma(w, F[k], tot);
+            }
+        } else {
+#pragma unroll
+            for (int k = 0; k < K; ++k) {
+                const double sub = WalkSum<K, L + 1, TS, UL>::run(s, k, w * F[k], marg);
+                marg[L][k] += sub;
+                tot += sub;
+            }
+        }
+        return tot;
+    }
+};
+
 // Pass 1: the largest log-weight and its path.
-template <int K, int TS, int BD>
+template <int K, int TS, int UL>
 __global__ __launch_bounds__(kEnThreads) void enum_max_kernel(EnumDev a) {
     __shared__ EnLds s;
     __shared__ double s_best[kEnThreads];
     __shared__ uint64_t s_idx[kEnThreads];
-    en_stage<K, BD>(s, a);
-    constexpr uint64_t kts = ipow(K, TS);
+    en_stage<K, TS>(s, a, false);
     double best = -INFINITY;
-    uint64_t bidx = 0;
+    uint64_t bidx = 0, bp = 0, bnode = 0;
     for (uint64_t tile = blockIdx.x; tile < a.n_tiles; tile += gridDim.x) {
         const uint64_t p = tile * kEnThreads + threadIdx.x;
         if (p >= a.n_prefix) continue;
@@ -228,12 +233,17 @@ __global__ __launch_bounds__(kEnThreads) void enum_max_kernel(EnumDev a) {
         if constexpr (TS == 0) {
             if (lw > best) { best = lw; bidx = p; }
         } else {
-            double bl = -INFINITY;
-            uint64_t bi = 0;
-            WalkMax<K, 0, TS, BD>::run(s, a.tail, last, lw, 0, bl, bi);
-            if (bl > best) { best = bl; bidx = p * kts + bi; }
+            const double before = best;
+            uint64_t node = 0;
+            WalkMax<K, 0, TS, UL>::run(s, last, lw, 0, best, node);
+            if (best > before) {
+                bp = p;
+                bnode = node;
+            }
         }
     }
+    if constexpr (TS > 0)
+        if (best > -INFINITY) bidx = en_locate<K, TS, UL>(s, a.tail, bp, bnode, best);
     s_best[threadIdx.x] = best;
     s_idx[threadIdx.x] = bidx;
     __syncthreads();
@@ -282,15 +292,18 @@ __global__ __launch_bounds__(256) void enum_merge_kernel(const double *__restric
 }
 
 // Pass 2: sums of exp(lw - M) in total and per (t, z_t).
-template <int K, int TS, int BD>
+template <int K, int TS, int UL>
 __global__ __launch_bounds__(kEnThreads) void enum_sum_kernel(EnumDev a) {
     constexpr int TSA = TS > 0 ? TS : 1;
+    constexpr int kWaves = kEnThreads / 64;
     __shared__ EnLds s;
     __shared__ double s_sub[kEnThreads];
-    en_stage<K, BD>(s, a);
+    __shared__ double s_wsum[kWaves];
+    en_stage<K, TS>(s, a, true);
     const double M = a.glob[0];
     const bool skip = !(M > -INFINITY) || a.glob[2] != 0.0;
     const int tail = a.tail, T = a.T;
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     double *rec = a.rec2 + (size_t)blockIdx.x * (1 + T * K);
     // owner entries e = t K + k of the prefix sites: this thread owns e = threadIdx.x + j kEnThreads
     constexpr int kOwn = (kEnMaxT * 8 + kEnThreads - 1) / kEnThreads;
@@ -313,13 +326,22 @@ __global__ __launch_bounds__(kEnThreads) void enum_sum_kernel(EnumDev a) {
             if constexpr (TS == 0) {
                 sub = exp(lw - M);
             } else {
-                sub = WalkSum<K, 0, TS, BD>::run(s, tail, last, lw, M, marg);
+                const double w = exp(lw + s.V[last] - M);      // the best path below the prefix, <= 1
+                sub = WalkSum<K, 0, TS, UL>::run(s, last, w, marg);
             }
         }
         tot += sub;
+        // the tile's total, the same bits in every lane (butterfly of commutative adds)
+        double ws = sub;
+#pragma unroll
+        for (int o = 32; o >= 1; o >>= 1) ws += __shfl_xor(ws, o);
         s_sub[threadIdx.x] = sub;
+        if (lane == 0) s_wsum[wave] = ws;
         __syncthreads();
-        // prefix site t has digit q (mod K) for threads i < c and q + 1 after (c = K^(tail-1-t) - base mod it)
+        double tile_tot = 0.0;
+#pragma unroll
+        for (int w = 0; w < kWaves; ++w) tile_tot += s_wsum[w];
+        // prefix site t of prefix base + i has digit (q + (r + i) div pw) mod K, q and r from base = q pw + r
 #pragma unroll
         for (int j = 0; j < kOwn; ++j) {
             const int e = threadIdx.x + j * kEnThreads;
@@ -328,18 +350,24 @@ __global__ __launch_bounds__(kEnThreads) void enum_sum_kernel(EnumDev a) {
                 uint64_t pw = 1;
                 for (int u = t + 1; u < tail; ++u) pw *= K;
                 const uint64_t q = base / pw, r = base - q * pw;
+                const int qm = (int)(q % K);
                 double acc = 0.0;
-                if (pw >= kEnThreads) {
-                    const int c = (int)std::min<uint64_t>(pw - r, kEnThreads);
-                    const int d0 = (int)(q % K), d1 = (int)((q + 1) % K);
-                    if (d0 == k)
+                if (pw - r >= (uint64_t)kEnThreads) {
+                    acc = qm == k ? tile_tot : 0.0;          // one digit over the whole tile
+                } else if (pw >= (uint64_t)kEnThreads) {
+                    // the digit steps once, at c = pw - r
+                    const int c = (int)(pw - r);
+                    if (qm == k)
                         for (int i = 0; i < c; ++i) acc += s_sub[i];
-                    if (d1 == k)
+                    if ((qm + 1) % K == k)
                         for (int i = c; i < kEnThreads; ++i) acc += s_sub[i];
                 } else {
-                    const uint32_t pw32 = (uint32_t)pw, r32 = (uint32_t)r, qm = (uint32_t)(q % K);
-                    for (int i = 0; i < kEnThreads; ++i)
-                        if ((qm + (r32 + (uint32_t)i) / pw32) % K == (uint32_t)k) acc += s_sub[i];
+                    // runs of pw prefixes per digit: those of digit k start at n pw - r, n = (k - qm) mod K + K i
+                    const int pw32 = (int)pw, r32 = (int)r;
+                    for (int n = (k - qm + K) % K; n * pw32 - r32 < kEnThreads; n += K) {
+                        const int lo = max(0, n * pw32 - r32), hi = min(kEnThreads, (n + 1) * pw32 - r32);
+                        for (int i = lo; i < hi; ++i) acc += s_sub[i];
+                    }
                 }
                 own[j] += acc;
             }
@@ -428,10 +456,9 @@ __global__ void enum_emission_kernel(const double *__restrict__ y, int T, int K,
 
 // ---------------------------------------------------------------- host --
 // Nested sites per state count (the paths below a prefix: 2^12, 3^7, 4^6,
-// 5^5, 6^5, 7^4, 8^4) and block sites (suffixes per state: 16, 27, then K^2).
+// 5^5, 6^5, 7^4, 8^4).
 constexpr int en_ts_max(int K) { return K == 2 ? 12 : K == 3 ? 7 : K == 4 ? 6 : K <= 6 ? 5 : 4; }
-constexpr int en_bd_max(int K) { return K == 2 ? 4 : K == 3 ? 3 : 2; }
-constexpr int en_bd(int K, int ts) { return ts <= 1 ? 0 : std::min(en_bd_max(K), ts - 1); }
+constexpr int en_ul(int K, int ts) { return std::min(en_ul_max(K), ts); }
 
 struct EnPlan {
     int Ts, tail, grid;
@@ -459,11 +486,11 @@ size_t enum_ws_bytes(int K, int T) {
 
 template <int K, int TS>
 static int en_launch(const EnumDev &d, const EnPlan &p, hipStream_t st) {
-    constexpr int BD = en_bd(K, TS);
-    static_assert(ipow(K, BD + 1) <= kEnMaxB, "block table exceeds its LDS slot");
+    constexpr int UL = en_ul(K, TS);
+    static_assert(TS <= kEnMaxTS && TS * K * K <= kEnMaxF, "nested tables exceed their LDS slots");
     {
         KernelTimer timer("enum_max_kernel", st);
-        hipLaunchKernelGGL((enum_max_kernel<K, TS, BD>), dim3((unsigned)p.grid), dim3(kEnThreads), 0, st, d);
+        hipLaunchKernelGGL((enum_max_kernel<K, TS, UL>), dim3((unsigned)p.grid), dim3(kEnThreads), 0, st, d);
         timer.stop();
     }
     PPL_LAUNCH_CHECK("enum_max_kernel");
@@ -471,7 +498,7 @@ static int en_launch(const EnumDev &d, const EnPlan &p, hipStream_t st) {
     PPL_LAUNCH_CHECK("enum_merge_kernel");
     {
         KernelTimer timer("enum_sum_kernel", st);
-        hipLaunchKernelGGL((enum_sum_kernel<K, TS, BD>), dim3((unsigned)p.grid), dim3(kEnThreads), 0, st, d);
+        hipLaunchKernelGGL((enum_sum_kernel<K, TS, UL>), dim3((unsigned)p.grid), dim3(kEnThreads), 0, st, d);
         timer.stop();
     }
     PPL_LAUNCH_CHECK("enum_sum_kernel");
