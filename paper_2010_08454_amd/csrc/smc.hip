@@ -25,10 +25,13 @@
 //      block finds the contiguous ancestor range of its slots, stages those
 //      prefix sums in LDS, and every slot binary-searches its ancestor there
 //      and gathers the ancestor's state; lw = 0.
-// The grid barrier counts arrivals on one cache line and publishes the epoch
-// on another.  Its spin is bounded: if a wait exceeds the limit, the block
-// raises the abort flag and every block leaves its loop at its next barrier,
-// so the grid always drains.
+// Blocks meet at a record barrier: each block stores its record (the partial
+// of step 2, the tile total of step 3, the final sums) on its own cache line
+// and then the barrier epoch; thread t of every block polls line t, so every
+// block holds every record when it leaves, with no shared counter.  The spin
+// is bounded: if a wait exceeds the limit, the block raises the abort flag
+// and every block leaves its loop at its next barrier, so the grid always
+// drains.
 #include <math.h>
 #include <string.h>
 
@@ -45,7 +48,8 @@ constexpr int kSmcThreads = 512;
 constexpr int kSmcWaves = kSmcThreads / 64;
 constexpr int kSmcMaxBlocks = 1024;
 constexpr int kBarLine = 32;                  // unsigned per 128-byte line
-constexpr int kBarWords = 2 * kBarLine;       // line 0: epoch, abort flag; line 1: arrival counter
+constexpr int kBarWords = kBarLine;           // word 1: abort flag
+constexpr int kRecWords = 16;                 // 64-bit words per 128-byte record line
 constexpr uint32_t kSpinLimit = 1u << 24;     // polls before a wait is declared hung (seconds)
 constexpr int kYChunk = 2048;                 // observations staged in LDS at a time
 constexpr int kStage = 8192;                  // most prefix sums staged in LDS for the ancestor search
@@ -75,56 +79,75 @@ struct SmcDev {
     double move_lam;         // random-walk scale factor
     double hyp64[2];         // GMM {mu_sd, comp_sd} in FP64 (move scales)
     // workspace
-    unsigned *bar;           // [0] published epoch, [1] abort flag, [32] arrival counter
-    double *part;            // [2][nb][3]
-    uint64_t *tot;           // [nb]
-    double *esum;            // [nb]
-    double *fin;             // [nb][2]
+    unsigned *bar;           // [1] abort flag
+    uint64_t *rec;           // [2][nb][16] record lines: word 0 the epoch, words 1..3 the record
     uint64_t *qloc;          // [N] tile-local inclusive prefix sums of q
     float *xbuf;             // [NF][N]
     float *xbuf2;            // [NF][N] gathered particles while they move (resample-move)
 };
 
 // ------------------------------------------------------------- barrier --
-// Returns false (uniformly in the block) once any block has aborted.  Every
-// block adds one to the arrival counter (acq_rel: its writes are released, and
-// the last arriver acquires everyone's); the last arriver of epoch e stores e
-// to the epoch word (release), which the others poll with relaxed
-// device-scope loads, followed by one acquire fence.  Arrivals and polls sit
-// on different cache lines: polling the line the atomics update slows every
-// arrival (measured 55 ms against 45 ms for the LGSSM run), and so does a
-// tree of group counters (48 ms with groups of 16 blocks), each level adding
-// an atomic's latency.
-__device__ __forceinline__ bool grid_barrier(unsigned *bar, unsigned epoch, int nb) {
-    __shared__ int s_ok;
+// Record barrier for epoch e.  Thread 0 stores the block's three record
+// words on its line of buffer e mod 2, then e in word 0 (release, after a
+// workgroup barrier, so every store the block made before it is released
+// too).  Thread t < nb polls line t with relaxed device-scope loads until it
+// reads e, then loads the record words with device-scope loads: they are
+// issued only after the epoch has been read, and the release put them at the
+// device's coherence point before the epoch, so they are the block's record.
+// With `acquire`, one acquire fence per block then makes every other store
+// the blocks released visible to plain loads (the resampling gather reads
+// other blocks' prefix sums and state).  Two buffers suffice: a block cannot
+// pass barrier e + 1 before every block has stored its record e + 1, which
+// each does only after reading all records e.  Returns false (uniformly in
+// the block) once any block has aborted.
+__device__ __forceinline__ bool record_barrier(uint64_t *rec, unsigned *bar, unsigned epoch, int nb, uint64_t w0,
+                                               uint64_t w1, uint64_t w2, uint64_t (&r)[3], bool acquire) {
+    __shared__ int s_bad;
+    unsigned *abort_flag = bar + 1;
+    uint64_t *buf = rec + (size_t)(epoch & 1u) * nb * kRecWords;
+    if (threadIdx.x == 0) s_bad = 0;
     __syncthreads();
     if (threadIdx.x == 0) {
-        unsigned *published = bar;
-        unsigned *abort_flag = bar + 1;
-        unsigned *arrived = bar + kBarLine;
-        const unsigned old = __hip_atomic_fetch_add(arrived, 1u, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
-        if (old + 1 == epoch * (unsigned)nb)
-            __hip_atomic_store(published, epoch, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+        uint64_t *mine = buf + (size_t)blockIdx.x * kRecWords;
+        __hip_atomic_store(mine + 1, w0, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        __hip_atomic_store(mine + 2, w1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        __hip_atomic_store(mine + 3, w2, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        __hip_atomic_store(mine, (uint64_t)epoch, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+    }
+    r[0] = r[1] = r[2] = 0;
+    if (threadIdx.x < nb) {          // nb <= kSmcThreads
+        uint64_t *line = buf + (size_t)threadIdx.x * kRecWords;
         uint32_t spins = 0;
-        int ok = 1;
-        while (__hip_atomic_load(published, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < epoch) {
+        bool ok = true;
+        while (__hip_atomic_load(line, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < (uint64_t)epoch) {
             __builtin_amdgcn_s_sleep(1);
             if ((++spins & 63) == 0) {
-                if (__hip_atomic_load(abort_flag, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) { ok = 0; break; }
+                if (__hip_atomic_load(abort_flag, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) { ok = false; break; }
                 if (spins > kSpinLimit) {
                     __hip_atomic_store(abort_flag, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-                    ok = 0;
+                    ok = false;
                     break;
                 }
             }
         }
-        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
-        if (ok && __hip_atomic_load(abort_flag, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) ok = 0;
-        s_ok = ok;
+        if (ok) {
+            r[0] = __hip_atomic_load(line + 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            r[1] = __hip_atomic_load(line + 2, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            r[2] = __hip_atomic_load(line + 3, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        } else {
+            s_bad = 1;
+        }
     }
     __syncthreads();
-    return s_ok != 0;
+    if (acquire) {
+        if (threadIdx.x == 0) __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+        __syncthreads();
+    }
+    return s_bad == 0;
 }
+
+__device__ __forceinline__ uint64_t dbits(double v) { return (uint64_t)__double_as_longlong(v); }
+__device__ __forceinline__ double dval(uint64_t v) { return __longlong_as_double((long long)v); }
 
 // --------------------------------------------------------------- models --
 struct Lgssm {
@@ -371,18 +394,13 @@ __device__ __forceinline__ uint64_t block_exclusive_scan_u64(uint64_t v, uint64_
 
 // Merge of the per-block partials {m, s1, s2} (identical in every block):
 // fixed order, FP32 rescale factors (this feeds the resampling trigger only).
-__device__ __forceinline__ void merge_partials(const double *part, int nb, float *ldsf, double *ldsd,
-                                               float &M, double &S1, double &S2) {
-    float mb = -INFINITY;
-    double p1 = 0.0, p2 = 0.0;
-    if (threadIdx.x < nb) {          // nb <= kSmcThreads
-        mb = (float)part[3 * threadIdx.x];
-        p1 = part[3 * threadIdx.x + 1];
-        p2 = part[3 * threadIdx.x + 2];
-    }
+// Merges the per-block partials {max, s1, s2} that thread t < nb holds for
+// block t, in the same order in every block.
+__device__ __forceinline__ void merge_partials(float mb, double p1, double p2, float *ldsf, double *ldsd, float &M,
+                                               double &S1, double &S2) {
     M = block_max_f32(mb, ldsf);
     double s1 = 0.0, s2 = 0.0;
-    if (M > -INFINITY && threadIdx.x < nb) {
+    if (M > -INFINITY && mb > -INFINITY) {
         const float c = expf(mb - M);
         s1 = p1 * (double)c;
         s2 = p2 * (double)(c * c);
@@ -511,17 +529,16 @@ __global__ __launch_bounds__(kSmcThreads) void smc_persistent_kernel(SmcDev a) {
         }
         double s1b = s1l, s2b = s2l;
         block_sum2_f64(s1b, s2b, ldsd);
-        double *pp = a.part + (size_t)(s & 1) * nb * 3;
-        if (threadIdx.x == 0) {
-            pp[3 * blockIdx.x] = (double)mb;
-            pp[3 * blockIdx.x + 1] = s1b;
-            pp[3 * blockIdx.x + 2] = s2b;
+        uint64_t rr[3];
+        if (!record_barrier(a.rec, a.bar, ++epoch, nb, (uint64_t)__float_as_uint(mb), dbits(s1b), dbits(s2b), rr,
+                            false)) {
+            alive = false;
+            break;
         }
-        if (!grid_barrier(a.bar, ++epoch, nb)) { alive = false; break; }
-
         float Mg;
         double S1, S2;
-        merge_partials(pp, nb, ldsf, ldsd, Mg, S1, S2);
+        merge_partials(threadIdx.x < nb ? __uint_as_float((uint32_t)rr[0]) : -INFINITY, dval(rr[1]), dval(rr[2]),
+                       ldsf, ldsd, Mg, S1, S2);
         Mlast = Mg;
         if (!(Mg > -INFINITY)) { status = PPL_E_ZERO_WEIGHT; break; }
         if (!(S1 > 0.0) || isnan(S1) || isnan(S2)) { status = PPL_E_NONFINITE; break; }
@@ -561,16 +578,12 @@ __global__ __launch_bounds__(kSmcThreads) void smc_persistent_kernel(SmcDev a) {
                 for (int f = 0; f < M::NF; ++f) a.xbuf[(size_t)f * N + jb + p] = st[p][f];
             }
         }
-        if (threadIdx.x == 0) {
-            a.tot[blockIdx.x] = btot;
-            a.esum[blockIdx.x] = eb;
-        }
-        if (!grid_barrier(a.bar, ++epoch, nb)) { alive = false; break; }
+        if (!record_barrier(a.rec, a.bar, ++epoch, nb, btot, dbits(eb), 0, rr, true)) { alive = false; break; }
 
         // tile prefixes (LDS) and the normaliser sum, in the same order in every block
         {
-            const uint64_t v = threadIdx.x < nb ? a.tot[threadIdx.x] : 0;
-            const double ev0 = threadIdx.x < nb ? a.esum[threadIdx.x] : 0.0;
+            const uint64_t v = threadIdx.x < nb ? rr[0] : 0;
+            const double ev0 = threadIdx.x < nb ? dval(rr[1]) : 0.0;
             uint64_t S;
             const uint64_t ex = block_exclusive_scan_u64(v, ldsu, S);
             if (threadIdx.x < nb) {
@@ -727,15 +740,12 @@ __global__ __launch_bounds__(kSmcThreads) void smc_persistent_kernel(SmcDev a) {
             }
         }
         block_sum2_f64(e1, e2, ldsd);
-        if (threadIdx.x == 0) {
-            a.fin[2 * blockIdx.x] = e1;
-            a.fin[2 * blockIdx.x + 1] = e2;
-        }
-        if (!grid_barrier(a.bar, ++epoch, nb)) {
+        uint64_t rr[3];
+        if (!record_barrier(a.rec, a.bar, ++epoch, nb, dbits(e1), dbits(e2), 0, rr, false)) {
             alive = false;
         } else {
-            double t1 = threadIdx.x < nb ? a.fin[2 * threadIdx.x] : 0.0;
-            double t2 = threadIdx.x < nb ? a.fin[2 * threadIdx.x + 1] : 0.0;
+            double t1 = threadIdx.x < nb ? dval(rr[0]) : 0.0;
+            double t2 = threadIdx.x < nb ? dval(rr[1]) : 0.0;
             block_sum2_f64(t1, t2, ldsd);
             const double inc = (double)Mlast + log_f64(t1) - logN;
             logz += inc;
@@ -767,10 +777,11 @@ __global__ __launch_bounds__(kSmcThreads) void smc_persistent_kernel(SmcDev a) {
     }
 }
 
-// Clears the barrier counters and abort flag (a fill kernel, so the launch
-// sequence stays capturable).
-__global__ void smc_reset_kernel(unsigned *bar) {
+// Clears the abort flag and the record lines' epochs (a fill kernel, so the
+// launch sequence stays capturable).
+__global__ void smc_reset_kernel(unsigned *bar, uint64_t *rec, int n_lines) {
     for (int i = threadIdx.x; i < kBarWords; i += blockDim.x) bar[i] = 0u;
+    for (int i = threadIdx.x; i < n_lines * kRecWords; i += blockDim.x) rec[i] = 0u;
 }
 
 // ------------------------------------------------------------------ host --
@@ -787,8 +798,7 @@ static int64_t smc_blocks(int64_t N, int P) { return (N + (int64_t)kSmcThreads *
 struct SmcLayout {
     double *scal;
     unsigned *bar;
-    double *part, *esum, *fin;
-    uint64_t *tot, *qloc;
+    uint64_t *rec, *qloc;
     float *xbuf, *xbuf2;
     size_t bytes;
 };
@@ -800,10 +810,7 @@ static SmcLayout smc_layout(void *ws, int NF, int64_t N, int64_t nb) {
     auto take = [&](size_t n) { char *r = p + o; o += align_up(n, 256); return r; };
     L.scal = (double *)take(8 * sizeof(double));
     L.bar = (unsigned *)take(kBarWords * sizeof(unsigned));
-    L.part = (double *)take(2 * nb * 3 * sizeof(double));
-    L.esum = (double *)take(nb * sizeof(double));
-    L.fin = (double *)take(2 * nb * sizeof(double));
-    L.tot = (uint64_t *)take(nb * sizeof(uint64_t));
+    L.rec = (uint64_t *)take((size_t)2 * nb * kRecWords * sizeof(uint64_t));
     L.qloc = (uint64_t *)take(N * sizeof(uint64_t));
     L.xbuf = (float *)take((size_t)NF * N * sizeof(float));
     L.xbuf2 = NF > 1 ? (float *)take((size_t)NF * N * sizeof(float)) : nullptr;   // mixture models only
@@ -835,7 +842,7 @@ static int launch(SmcDev &d, int64_t nb, hipStream_t st) {
     PPL_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, kern, kSmcThreads, lds));
     if ((int64_t)occ * ncu < nb)
         return fail(PPL_E_UNSUPPORTED, "SMC needs %lld co-resident blocks, device holds %d", (long long)nb, occ * ncu);
-    hipLaunchKernelGGL(smc_reset_kernel, dim3(1), dim3(256), 0, st, d.bar);
+    hipLaunchKernelGGL(smc_reset_kernel, dim3(1), dim3(256), 0, st, d.bar, d.rec, (int)(2 * nb));
     PPL_LAUNCH_CHECK("smc_reset_kernel");
     void *args[] = {&d};
     KernelTimer timer("smc_persistent_kernel", st);
@@ -864,8 +871,8 @@ int run_smc(const SmcArgs &a, hipStream_t st) {
         return fail(PPL_E_UNSUPPORTED, "SMC supports at most %lld particles",
                     (long long)std::min(kSmcMaxBlocks, kSmcThreads) * kSmcThreads * 8);
     if (a.T > 0x7fffffffLL) return fail(PPL_E_ARG, "too many factors");
-    // a run passes at most 2 T + 1 barriers; the arrival counter reaches that times nb
-    if ((2 * a.T + 2) * nb >= 0xffffffffLL) return fail(PPL_E_UNSUPPORTED, "barrier counter would overflow");
+    // a run passes at most 2 T + 1 barriers, each with its own epoch
+    if (2 * a.T + 2 >= 0xffffffffLL) return fail(PPL_E_UNSUPPORTED, "barrier epoch would overflow");
     SmcLayout L = smc_layout(a.ws, NF, a.N, nb);
     SmcDev d{};
     d.y = a.y;
@@ -896,10 +903,7 @@ int run_smc(const SmcArgs &a, hipStream_t st) {
     d.hyp64[0] = a.hyper[0];
     d.hyp64[1] = a.hyper[1];
     d.bar = L.bar;
-    d.part = L.part;
-    d.tot = L.tot;
-    d.esum = L.esum;
-    d.fin = L.fin;
+    d.rec = L.rec;
     d.qloc = L.qloc;
     d.xbuf = L.xbuf;
     d.xbuf2 = L.xbuf2;
