@@ -86,6 +86,8 @@ def parse():
     ap.add_argument("--no-graph", action="store_true", help="proposal-train: launch each step's kernels eagerly")
     ap.add_argument("--batch", type=int, default=0, help="proposal: training batch (default 4096)")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
+    ap.add_argument("--diagnose", action="store_true",
+                    help="proposal-gmm: ESS/N of the learned proposal on held-out prior datasets and on the observed one")
     ap.add_argument("--cpu-seconds", type=float, default=15.0, help="target length of the oracle sample")
     ap.add_argument("--particles", type=int, default=0,
                     help="lgssm: particle count (default 2^20); resample-gather: (default 2^24)")
@@ -606,6 +608,38 @@ def bench_proposal(args, ppl, synthetic, torch, dev, stream):
                         "ess_per_s": mean_ess / (mean_ms / 1e3)}
         return None
 
+    if args.diagnose and not poly:
+        # held-out datasets drawn from the prior by the observed dataset's recipe (other seeds): if the
+        # proposal is as poor there as on the observed dataset, the gap is the network's (capacity or
+        # parameterisation), not a mismatch between the observed data and the training distribution
+        Nd = 1 << 16
+        dws = ppl.workspace(ppl.ppl_proposal_infer_workspace_size(model, data, Nd), dev)
+        pws = ppl.workspace(ppl.ppl_workspace_size(model, data, Nd, ppl.PPL_ALGO_IS), dev)
+
+        def ess_frac(d, learned_q, w=1.0, sd=500):
+            if learned_q:
+                ppl.ppl_proposal_infer(model, d, wts, Nd, sd, ws=dws, stream=stream, scalars=sc, widen=w)
+            else:
+                ppl.ppl_importance(model, d, Nd, sd, ws=pws, stream=stream, scalars=sc)
+            return float(sc.cpu().numpy()[1]) / Nd
+
+        held, held_prior = [], []
+        for i in range(32):
+            yi = synthetic.gmm_learn_data(K=5, D=100, seed=synthetic.SEED_GMM_LEARN + 7919 * (i + 1))
+            di = ppl.make_data(None, torch.from_numpy(yi).to(dev), dim=5)
+            held.append(ess_frac(di, True, sd=500 + i))
+            held_prior.append(ess_frac(di, False, sd=500 + i))
+        q = lambda v, f: float(sorted(v)[int(f * (len(v) - 1))])
+        workload["diagnosis"] = {
+            "particles": Nd,
+            "held_out_learned_ess_over_n": {"min": q(held, 0), "median": q(held, 0.5), "max": q(held, 1)},
+            "held_out_prior_ess_over_n": {"min": q(held_prior, 0), "median": q(held_prior, 0.5),
+                                          "max": q(held_prior, 1)},
+            "observed_learned_ess_over_n": ess_frac(data, True),
+            "observed_learned_widened_ess_over_n": ess_frac(data, True, w=widen),
+            "observed_prior_ess_over_n": ess_frac(data, False)}
+        del dws, pws
+
     learned = ladder(True, 10, 24)
     prior = ladder(False, 10, 30)
     # kernel rate of the learned inference at its particle count
@@ -898,6 +932,16 @@ def main():
         assert (ob[:, 3] == 0).all(), "device status"
         s = [float(ob[:, 0].sum()), float(ob[:, 1].mean()), float(ob[:, 2].sum()), 0.0]
         evals = N * D
+        # work counters of one more run (outside the timed steps): factors evaluated in first passes and
+        # recomputed after rollbacks, against the algorithmic N D
+        cnt = torch.zeros(4, dtype=torch.int64, device=dev)
+        ppl.ppl_smc_batched(model, table, seed, 0.5, tune=tuned + (0,), ws=ws, stream=stream, out=outb, counters=cnt)
+        c = [int(v) for v in cnt.cpu().numpy()]
+        workload["work_counters"] = {"particle_factors_first_pass": c[0], "particle_factors_recomputed": c[1],
+                                     "speculative_blocks": c[2], "resampling_events": c[3],
+                                     "algorithmic_particle_factors": N * D,
+                                     "first_pass_over_algorithmic": round(c[0] / (N * D), 4),
+                                     "recomputed_over_algorithmic": round(c[1] / (N * D), 4)}
     else:
         s = scal.cpu().numpy()
         assert s[3] == 0 and math.isfinite(s[0]), f"device status {s[3]}"

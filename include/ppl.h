@@ -223,14 +223,17 @@ int ppl_importance_noalloc(int model, const ppl_data *data, int64_t n_particles,
                            const ppl_proposal *q, void *stream, ppl_result *out);
 
 /* FP64 normaliser of a device log-weight vector d_lw[n] (dtype PPL_F32 or
- * PPL_F64): d_out[5] = {max, s1, s2, LSE = max + log s1, ESS = s1^2 / s2}.
+ * PPL_F64), the normalisation step of importance sampling (paper Sec. 3.6.2:
+ * the weights of the executions are normalised over all of them):
+ * d_out[5] = {max, s1, s2, LSE = max + log s1, ESS = s1^2 / s2}.
  * -inf entries carry zero weight; all -inf gives LSE = -inf and ESS = 0;
  * a NaN entry makes every output NaN. */
 int ppl_lse_ess(const void *d_lw, int dtype, int64_t n, double *d_out, void *d_ws,
                 size_t ws_bytes, void *stream);
 
-/* Systematic resampling with integer-quantised weights (association-free, so
- * the result does not depend on the reduction order):
+/* Systematic resampling with integer-quantised weights, the resampling step
+ * of particle-based inference (paper Sec. 6, named there as future work);
+ * association-free, so the result does not depend on the reduction order:
  *   q_i = floor(exp(lw_i - max) * 2^k), k = 62 - ceil(log2 n);  Q = inclusive
  *   prefix sum, S = Q_{n-1};  R = 64-bit word from Philox block
  *   (0, 0, step, inst << 8 | 2);  U = floor(R S / 2^64);
@@ -255,7 +258,8 @@ int ppl_resample_gather(const void *d_lw, int dtype, int64_t n, uint64_t seed, u
                         void *stream);
 
 /* Raw stream: d_out[4 i + r] = word r of Philox4x32-10 block
- * (i, c1, c2, c3) under key seed, for i < n. */
+ * (i, c1, c2, c3) under key seed, for i < n.  Every random choice a sample
+ * site makes (paper Sec. 3.4) is drawn from these words. */
 int ppl_philox(uint64_t seed, uint32_t c1, uint32_t c2, uint32_t c3, int64_t n,
                uint32_t *d_out, void *stream);
 
@@ -415,7 +419,12 @@ typedef struct ppl_tune {
  *   d_move_log_alpha [max_events * sum' M_i N_i] FP64: recorded instance i
  *             with M_i = move_steps > 0 at max_events * sum' over recorded
  *             k < i of M_k N_k, as [max_events][M_i][N_i]: the log acceptance
- *             ratios of its resample-move steps. */
+ *             ratios of its resample-move steps;
+ *   d_counters [4] int64, work summed over the instances: particle-factors
+ *             evaluated in speculative blocks (first passes, including
+ *             factors past a trigger), particle-factors recomputed after a
+ *             rollback, speculative blocks (team merges), resampling events.
+ *             The algorithmic count is sum N_i D_i. */
 typedef struct ppl_batch_result {
     double *d_out;
     float *d_log_weights;
@@ -427,6 +436,7 @@ typedef struct ppl_batch_result {
     float *d_event_lw;
     double *d_logz_trace;
     double *d_move_log_alpha;
+    int64_t *d_counters;
 } ppl_batch_result;
 
 /* Workspace bytes for a batched run with configuration `tune` (NULL: enough
@@ -436,14 +446,16 @@ int ppl_smc_batched_workspace_size(int model, int32_t n_inst, const ppl_instance
 
 /* Batched SMC over n_inst independent mixture-model instances in one
  * persistent cooperative launch (same per-instance algorithm and outputs as
- * ppl_smc).  tune NULL: the autotuner's cached choice for this batch shape,
+ * ppl_smc: particle inference with a resampling step at the factors, paper
+ * Sec. 6; the factor of Sec. 3.4 is one datum's mixture density).  tune NULL: the autotuner's cached choice for this batch shape,
  * else the defaults.  model: PPL_MODEL_GMM.  n_inst in 1..1024. */
 int ppl_smc_batched(int model, int32_t n_inst, const ppl_instance *h_inst, const ppl_instance *d_inst,
                     uint64_t seed, double ess_frac, const ppl_tune *tune, void *d_ws, size_t ws_bytes,
                     void *stream, ppl_batch_result *out);
 
-/* Autotuner: times each candidate configuration once on this batch (after a
- * warm-up run, synchronising the stream): P in {1, 2, 4, 8} with speculative
+/* Autotuner for ppl_smc_batched (a launch-shape search with no counterpart
+ * in the paper): times each candidate configuration once on this batch
+ * (after a warm-up run, synchronising the stream): P in {1, 2, 4, 8} with speculative
  * blocks of 16..256 factors, each with the smallest team W that holds the
  * largest instance and with 2 W.  Returns the fastest in *best and caches it
  * for batches of the same shape (instance count, particle and data totals,

@@ -327,7 +327,7 @@ class PplTune(ctypes.Structure):
 class PplBatchResult(ctypes.Structure):
     _fields_ = [("d_out", P), ("d_log_weights", P), ("d_latents", P), ("d_ess_trace", P), ("d_resampled", P),
                 ("d_ancestors", P), ("max_events", ctypes.c_int64), ("d_event_lw", P), ("d_logz_trace", P),
-                ("d_move_log_alpha", P)]
+                ("d_move_log_alpha", P), ("d_counters", P)]
 
 
 def _bind_batched():
@@ -401,8 +401,10 @@ def ppl_smc_batched_workspace_size(model, table, tune=None):
 
 def ppl_smc_batched(model, table, seed, ess_frac=0.5, tune=None, ws=None, stream=None, out=None, log_weights=None,
                     latents=None, ess_trace=None, resampled=None, ancestors=None, max_events=0, event_lw=None,
-                    logz_trace=None, move_log_alpha=None):
-    """Batched SMC; returns the [n_inst, 4] FP64 device tensor (log Z, ESS, resamplings, status)."""
+                    logz_trace=None, move_log_alpha=None, counters=None):
+    """Batched SMC; returns the [n_inst, 4] FP64 device tensor (log Z, ESS, resamplings, status).
+    counters (int64 [4], optional): particle-factors in first passes, particle-factors recomputed,
+    speculative blocks, resampling events."""
     if ws is None:
         ws = workspace(ppl_smc_batched_workspace_size(model, table, tune))
     if out is None:
@@ -411,7 +413,7 @@ def ppl_smc_batched(model, table, seed, ess_frac=0.5, tune=None, ws=None, stream
                          d_ess_trace=_ptr(ess_trace), d_resampled=_ptr(resampled), d_ancestors=_ptr(ancestors),
                          max_events=int(max_events) if any(t is not None for t in (ancestors, event_lw, move_log_alpha))
                          else 0, d_event_lw=_ptr(event_lw), d_logz_trace=_ptr(logz_trace),
-                         d_move_log_alpha=_ptr(move_log_alpha))
+                         d_move_log_alpha=_ptr(move_log_alpha), d_counters=_ptr(counters))
     tp, _keep = _tune_ptr(tune)
     _check(lib.ppl_smc_batched(model, table.n, table.host, _ptr(table.device), int(seed) & (2 ** 64 - 1),
                                float(ess_frac), tp, _ptr(ws), ws.numel(), _stream(stream), ctypes.byref(res)))

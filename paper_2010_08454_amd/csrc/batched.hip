@@ -70,6 +70,7 @@ struct BtDev {
     double *logz_tr;         // [sum D]: normaliser increment added after each factor
     double *alpha_out;       // resample-move log acceptance ratios, [max_events][M_i][N_i] per recorded instance
     int64_t max_events;
+    unsigned long long *counters;   // [4] or null: work counters summed over instances (see ppl_batch_result)
     unsigned *bar;          // [1 + teams] lines: line 0 word 1 = abort flag; line 1 + t = team t counter
     double *part;            // [teams][2][W][Bmax][3]: two copies, picked by barrier-epoch parity
     uint64_t *tot;           // [teams][W]
@@ -510,8 +511,11 @@ __device__ __forceinline__ void bt_instance(const BtDev &a, BtCtx &cx, int i) {
     float Mlast = 0.0f;
     int64_t t0 = 0;
     int B = 1;
+    int64_t n_first = 0, n_redo = 0, n_blocks = 0;     // factors advanced, recomputed; speculative blocks
     while (t0 < D) {
         const int tb = (int)std::min<int64_t>(B, D - t0);
+        n_first += tb;
+        ++n_blocks;
         __syncthreads();
         for (int t = threadIdx.x; t < tb; t += kBtThreads) ybuf[t] = I.y[t0 + t];
         __syncthreads();
@@ -597,6 +601,7 @@ __device__ __forceinline__ void bt_instance(const BtDev &a, BtCtx &cx, int i) {
                 lwc[p] = s_lwc0[threadIdx.x * P + p];
             }
             bt_block_redo<P, KK>(st, valid, lw, lwc, ybuf, tf + 1, inv_sd, lconst);
+            n_redo += tf + 1;
         }
         // ---- resampling at factor s = t0 + tf
         const int64_t s = t0 + tf;
@@ -839,6 +844,12 @@ __device__ __forceinline__ void bt_instance(const BtDev &a, BtCtx &cx, int i) {
             for (int f = 0; f < 2 * KK; ++f) a.lat_out[(size_t)kBtNF * poff + (size_t)f * N + j] = st[p][f];
         }
     }
+    if (a.counters && wg == 0 && threadIdx.x == 0) {
+        atomicAdd(&a.counters[0], (unsigned long long)(n_first * N));
+        atomicAdd(&a.counters[1], (unsigned long long)(n_redo * N));
+        atomicAdd(&a.counters[2], (unsigned long long)n_blocks);
+        atomicAdd(&a.counters[3], (unsigned long long)nres);
+    }
     if (wg == 0 && threadIdx.x == 0) {
         double *o = a.out + 4 * (size_t)i;
         o[0] = status ? (status == PPL_E_ZERO_WEIGHT ? -INFINITY : NAN) : logz;
@@ -925,8 +936,9 @@ __global__ __launch_bounds__(kBtThreads) void smc_batched_kernel(BtDev a) {
 }
 
 
-__global__ void smc_batched_reset_kernel(unsigned *bar, int words) {
+__global__ void smc_batched_reset_kernel(unsigned *bar, int words, unsigned long long *counters) {
     for (int i = threadIdx.x; i < words; i += blockDim.x) bar[i] = 0u;
+    if (counters && threadIdx.x < 4) counters[threadIdx.x] = 0ull;
 }
 
 // ------------------------------------------------------------------ host --
@@ -1088,6 +1100,7 @@ int run_smc_batched(int n, const ppl_instance *h, const ppl_instance *d_inst, ui
     d.logz_tr = out.d_logz_trace;
     d.alpha_out = out.d_move_log_alpha;
     d.max_events = (out.d_ancestors || out.d_event_lw || out.d_move_log_alpha) ? out.max_events : 0;
+    d.counters = (unsigned long long *)out.d_counters;
     d.bar = L.bar;
     d.part = L.part;
     d.tot = L.tot;
@@ -1096,7 +1109,8 @@ int run_smc_batched(int n, const ppl_instance *h, const ppl_instance *d_inst, ui
     d.qloc = L.qloc;
     d.xbuf = L.xbuf;
     d.xbuf2 = L.xbuf2;
-    hipLaunchKernelGGL(smc_batched_reset_kernel, dim3(1), dim3(256), 0, st, L.bar, kBtBarLine * (1 + teams));
+    hipLaunchKernelGGL(smc_batched_reset_kernel, dim3(1), dim3(256), 0, st, L.bar, kBtBarLine * (1 + teams),
+                       (unsigned long long *)out.d_counters);
     PPL_LAUNCH_CHECK("smc_batched_reset_kernel");
     if (used) *used = cfg;
     const int nblocks = teams * W;

@@ -248,3 +248,29 @@ def test_batched_resample_move_parity(ppl, orc, tune):
             assert mv["ties"].sum() <= 1e-3 * E * M * N + 10
         events += E
     assert events >= 5
+
+
+@pytest.mark.parametrize("tune", [(4, 0, 64, 0), (2, 0, 1, 0)])
+def test_batched_work_counters(ppl, tune):
+    """The work counters account for the speculative blocks: every factor is
+    evaluated at least once in a first pass, recomputation never exceeds the
+    first passes, the event count equals the reported resamplings, and with
+    blocks of one factor nothing is evaluated twice."""
+    import torch
+    dev = torch.device("cuda:0")
+    batch = make_batch([(3, 300, 4096), (5, 700, 3000), (8, 120, 5000), (4, 1500, 2048)], seed=13)
+    ys = [torch.from_numpy(y).to(dev) for _, y, _ in batch]
+    table = ppl.InstanceTable(ys, [k for k, _, _ in batch], [n for _, _, n in batch])
+    out = torch.empty((len(batch), 4), dtype=torch.float64, device=dev)
+    cnt = torch.full((4,), -1, dtype=torch.int64, device=dev)
+    ws = ppl.workspace(ppl.ppl_smc_batched_workspace_size(ppl.PPL_MODEL_GMM, table, tune), dev)
+    ppl.ppl_smc_batched(ppl.PPL_MODEL_GMM, table, 3, 0.5, tune=tune, ws=ws, out=out, counters=cnt)
+    c = cnt.cpu().numpy()
+    o = out.cpu().numpy()
+    nd = sum(n * y.size for _, y, n in batch)
+    assert np.all(o[:, 3] == 0)
+    assert c[3] == int(o[:, 2].sum())
+    assert c[0] >= nd and 0 <= c[1] <= c[0]
+    assert c[2] >= sum(1 for _ in batch)
+    if tune[2] == 1:
+        assert c[0] == nd and c[1] == 0 and c[2] == sum(y.size for _, y, _ in batch)
