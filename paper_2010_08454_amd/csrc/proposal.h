@@ -67,6 +67,10 @@ struct AdamSpec {
 int launch_forward(const MlpView &w, const TrainBufs &b, bool keep_cols, hipStream_t st);
 // Loss head and backward pass (gradients left in the split partials and bgrad).
 int launch_head_backward(int model, int K, const MlpView &w, const TrainBufs &b, hipStream_t st);
+// The same in fewer launches: forward, head and input gradients fused per 32
+// pairs (bitwise the values of launch_forward + launch_head_backward), then
+// the weight-gradient products and bias sums.
+int launch_fused_pass(int model, int K, const MlpView &w, const TrainBufs &b, hipStream_t st);
 // grad != null: write the summed gradient [count] and stop; else Adam update.
 int launch_update(const MlpView &w, const TrainBufs &b, const AdamSpec &ad, float *grad, hipStream_t st);
 // Per-step bookkeeping: loss_trace[local] = mean loss, local += 1 and, if

@@ -49,25 +49,19 @@ __device__ __forceinline__ float group8_sum(float v) {
     return v;
 }
 
+// The loss of one training pair and its gradient w.r.t. the network outputs:
+// lane m (0..7) of the pair's 8-lane group owns mixture component m; output k
+// is o[k os]; the BF16 gradient (divided by the batch size) goes to g[k],
+// whose unused entries the caller has zeroed.  Returns the pair's loss on
+// lane 0 and 0 elsewhere.
 template <int MODEL>
-__global__ __launch_bounds__(256) void head_kernel(const float *__restrict__ o_col, int B,
-                                                   const double *__restrict__ theta, int K, float inv_b,
-                                                   uint16_t *__restrict__ do_row, uint16_t *__restrict__ do_col,
-                                                   double *__restrict__ lossp) {
-    __shared__ uint32_t lds32[kHeadPairs * kLdsRow / 2];
-    __shared__ double red[4];
-    uint16_t *lds = (uint16_t *)lds32;
-    const int tid = threadIdx.x, m = tid & 7, sl = tid >> 3;
-    const int b0 = blockIdx.x * kHeadPairs, b = b0 + sl;
-    for (int k = tid; k < kHeadPairs * kLdsRow / 2; k += 256) lds32[k] = 0u;
-    __syncthreads();
-    uint16_t *g = lds + sl * kLdsRow;
-    const float *o = o_col + b;            // output k at o[k * B]
-    const double *th = theta + (size_t)b * kThetaStride;
+__device__ __forceinline__ float head_pair(const float *o, int os, const double *th, int K, float inv_b, uint16_t *g,
+                                           int m) {
+    auto O = [&](int k) { return o[(size_t)k * os]; };
     float loss;
     // mixture weights: lane m's log-softmax entry
     const int mix0 = MODEL == PPL_MODEL_POLY ? 4 : 0;
-    const float zm = o[(size_t)(mix0 + m) * B];
+    const float zm = O(mix0 + m);
     const float mm = group8_max(zm);
     const float lse_m = mm + logf(group8_sum(expf(zm - mm)));
     const float lmix = zm - lse_m;
@@ -78,8 +72,8 @@ __global__ __launch_bounds__(256) void head_kernel(const float *__restrict__ o_c
 #pragma unroll
         for (int j = 0; j < 5; ++j) {
             if (j < n) {
-                const float mu = 10.0f * o[(size_t)(off + m * n + j) * B];
-                const float lsd = 5.0f * tanhf(o[(size_t)(off + 8 * n + m * n + j) * B] * 0.2f);
+                const float mu = 10.0f * O(off + m * n + j);
+                const float lsd = 5.0f * tanhf(O(off + 8 * n + m * n + j) * 0.2f);
                 const float r = ((float)th[1 + j] - mu) * expf(-lsd);
                 t += -0.5f * r * r - lsd - kHalfLog2Pi;
             }
@@ -91,7 +85,7 @@ __global__ __launch_bounds__(256) void head_kernel(const float *__restrict__ o_c
         float zn[4], mx = -INFINITY;
 #pragma unroll
         for (int k = 0; k < 4; ++k) {
-            zn[k] = o[(size_t)k * B];
+            zn[k] = O(k);
             mx = fmaxf(mx, zn[k]);
         }
         float se = 0.0f;
@@ -113,8 +107,8 @@ __global__ __launch_bounds__(256) void head_kernel(const float *__restrict__ o_c
         for (int j = 0; j < 5; ++j) {
             if (j < n) {
                 const int km = off + m * n + j, ks = off + 8 * n + m * n + j;
-                const float mu = 10.0f * o[(size_t)km * B];
-                const float th5 = tanhf(o[(size_t)ks * B] * 0.2f);
+                const float mu = 10.0f * O(km);
+                const float th5 = tanhf(O(ks) * 0.2f);
                 const float iv = expf(-5.0f * th5);
                 const float dv = (float)th[1 + j] - mu;
                 const float r = dv * iv;
@@ -125,8 +119,8 @@ __global__ __launch_bounds__(256) void head_kernel(const float *__restrict__ o_c
     } else {
         const int d = 2 * K - 1;
         for (int j = 0; j < d; ++j) {
-            const float mu = 5.0f * o[(size_t)(8 + m * d + j) * B];
-            const float lsd = 5.0f * tanhf(o[(size_t)(8 + 8 * d + m * d + j) * B] * 0.2f);
+            const float mu = 5.0f * O(8 + m * d + j);
+            const float lsd = 5.0f * tanhf(O(8 + 8 * d + m * d + j) * 0.2f);
             const float r = ((float)th[j] - mu) * expf(-lsd);
             t += -0.5f * r * r - lsd - kHalfLog2Pi;
         }
@@ -137,8 +131,8 @@ __global__ __launch_bounds__(256) void head_kernel(const float *__restrict__ o_c
         g[m] = f32_to_bf16((expf(lmix) - resp) * inv_b);
         for (int j = 0; j < d; ++j) {
             const int km = 8 + m * d + j, ks = 8 + 8 * d + m * d + j;
-            const float mu = 5.0f * o[(size_t)km * B];
-            const float th5 = tanhf(o[(size_t)ks * B] * 0.2f);
+            const float mu = 5.0f * O(km);
+            const float th5 = tanhf(O(ks) * 0.2f);
             const float iv = expf(-5.0f * th5);
             const float dv = (float)th[j] - mu;
             const float r = dv * iv;
@@ -146,6 +140,23 @@ __global__ __launch_bounds__(256) void head_kernel(const float *__restrict__ o_c
             g[ks] = f32_to_bf16(-resp * (r * r - 1.0f) * (1.0f - th5 * th5) * inv_b);
         }
     }
+    return loss;
+}
+
+template <int MODEL>
+__global__ __launch_bounds__(256) void head_kernel(const float *__restrict__ o_col, int B,
+                                                   const double *__restrict__ theta, int K, float inv_b,
+                                                   uint16_t *__restrict__ do_row, uint16_t *__restrict__ do_col,
+                                                   double *__restrict__ lossp) {
+    __shared__ uint32_t lds32[kHeadPairs * kLdsRow / 2];
+    __shared__ double red[4];
+    uint16_t *lds = (uint16_t *)lds32;
+    const int tid = threadIdx.x, m = tid & 7, sl = tid >> 3;
+    const int b0 = blockIdx.x * kHeadPairs, b = b0 + sl;
+    for (int k = tid; k < kHeadPairs * kLdsRow / 2; k += 256) lds32[k] = 0u;
+    __syncthreads();
+    const float loss = head_pair<MODEL>(o_col + b, B, theta + (size_t)b * kThetaStride, K, inv_b,
+                                        lds + sl * kLdsRow, m);
     const double ls = wave_sum((double)loss);
     if ((tid & 63) == 0) red[tid >> 6] = ls;
     __syncthreads();
@@ -158,6 +169,157 @@ __global__ __launch_bounds__(256) void head_kernel(const float *__restrict__ o_c
         const int q = e / kMlpOut, k = e % kMlpOut;
         do_row[(size_t)(b0 + q) * kMlpOut + k] = lds[q * kLdsRow + k];
     }
+}
+
+// ------------------------------------------------- fused training pass --
+// Forward pass, loss head and the input-gradient half of the backward pass for
+// 32 training pairs per 256-thread workgroup, in one launch: the hidden
+// activations, the network outputs and the output gradients stay in LDS
+// between layers (BF16 rows padded to 264 entries, so every 8-entry fragment
+// is one aligned 16-byte LDS load).  Each product is C[32][256] = A[32][K]
+// B[256][K]^T on v_mfma_f32_16x16x32_bf16, wave w computing columns 64 w ..
+// 64 w + 63; fragments and accumulation order over K are those of
+// gemm_nt_kernel, and the epilogues round at the same points, so every stored
+// value equals the separate launches' bit for bit.  The column-major copies
+// the weight gradients and bias sums read (h1, h2, dO, dH2, dH1) and the FP32
+// outputs go to global memory.
+constexpr int kFuseRows = 32;
+constexpr int kFusePad = 264;           // BF16 per LDS row
+constexpr int kFuseOPad = 260;          // FP32 per LDS row of the outputs
+
+typedef __bf16 fbf16x8_t __attribute__((ext_vector_type(8)));
+typedef float ffloatx4_t __attribute__((ext_vector_type(4)));
+
+// acc[i][j][q] = C[16 i + 4 (lane / 16) + q][64 wave + 16 j + lane % 16].
+template <int KD>
+__device__ __forceinline__ void fuse_gemm(const uint16_t *A, int lda, const uint16_t *Bw, ffloatx4_t (&acc)[2][4]) {
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int fr = lane & 15, fk = (lane >> 4) * 8;
+#pragma unroll
+    for (int i = 0; i < 2; ++i)
+#pragma unroll
+        for (int j = 0; j < 4; ++j) acc[i][j] = ffloatx4_t{0.f, 0.f, 0.f, 0.f};
+    for (int k0 = 0; k0 < KD; k0 += 32) {
+        fbf16x8_t fa[2], fb[4];
+#pragma unroll
+        for (int i = 0; i < 2; ++i) fa[i] = *(const fbf16x8_t *)(A + (size_t)(16 * i + fr) * lda + k0 + fk);
+#pragma unroll
+        for (int j = 0; j < 4; ++j) fb[j] = *(const fbf16x8_t *)(Bw + (size_t)(64 * wave + 16 * j + fr) * KD + k0 + fk);
+#pragma unroll
+        for (int i = 0; i < 2; ++i)
+#pragma unroll
+            for (int j = 0; j < 4; ++j) acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(fa[i], fb[j], acc[i][j], 0, 0, 0);
+    }
+}
+
+// Hidden-layer epilogue: relu(acc + bias) in BF16 to LDS rows and to the
+// column-major global copy [256][B] (columns b0 .. b0 + 31).
+__device__ __forceinline__ void fuse_store_hidden(const ffloatx4_t (&acc)[2][4], const float *bias, uint16_t *lds,
+                                                  uint16_t *col, int B, int b0) {
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int fr = lane & 15, rq = (lane >> 4) * 4;
+#pragma unroll
+    for (int i = 0; i < 2; ++i)
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            const int n = 64 * wave + 16 * j + fr, mb = 16 * i + rq;
+            const float bn = bias[n];
+            uint16_t h[4];
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                h[q] = f32_to_bf16(fmaxf(acc[i][j][q] + bn, 0.0f));
+                lds[(mb + q) * kFusePad + n] = h[q];
+            }
+            *(uint2 *)(col + (size_t)n * B + b0 + mb) =
+                make_uint2((uint32_t)h[0] | ((uint32_t)h[1] << 16), (uint32_t)h[2] | ((uint32_t)h[3] << 16));
+        }
+}
+
+// Input-gradient epilogue: acc masked by the ReLU derivative (nonzero BF16
+// activation in `mask`), in BF16 to LDS rows (if lds) and the column-major copy.
+__device__ __forceinline__ void fuse_store_masked(const ffloatx4_t (&acc)[2][4], const uint16_t *mask, uint16_t *lds,
+                                                  uint16_t *col, int B, int b0) {
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int fr = lane & 15, rq = (lane >> 4) * 4;
+#pragma unroll
+    for (int i = 0; i < 2; ++i)
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            const int n = 64 * wave + 16 * j + fr, mb = 16 * i + rq;
+            uint16_t h[4];
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                const float t = (mask[(mb + q) * kFusePad + n] & 0x7FFFu) ? acc[i][j][q] : 0.0f;
+                h[q] = f32_to_bf16(t);
+                if (lds) lds[(mb + q) * kFusePad + n] = h[q];
+            }
+            *(uint2 *)(col + (size_t)n * B + b0 + mb) =
+                make_uint2((uint32_t)h[0] | ((uint32_t)h[1] << 16), (uint32_t)h[2] | ((uint32_t)h[3] << 16));
+        }
+}
+
+template <int MODEL>
+__global__ __launch_bounds__(256) void fused_pass_kernel(MlpView w, TrainBufs b, int K, float inv_b) {
+    __shared__ __align__(16) uint16_t sH1[kFuseRows * kFusePad];
+    __shared__ __align__(16) uint16_t sH2[kFuseRows * kFusePad];
+    __shared__ __align__(16) uint16_t sG[kFuseRows * kFusePad];     // dO
+    __shared__ __align__(16) uint16_t sD2[kFuseRows * kFusePad];    // dH2
+    __shared__ __align__(16) float sO[kFuseRows * kFuseOPad];
+    __shared__ double red[4];
+    const int B = b.B, b0 = blockIdx.x * kFuseRows, tid = threadIdx.x;
+    const int lane = tid & 63, wave = tid >> 6;
+    ffloatx4_t acc[2][4];
+    // layer 1: H1 = relu(X W1^T + b1)
+    fuse_gemm<kMlpIn>(b.x_row + (size_t)b0 * kMlpIn, kMlpIn, w.wt + MlpParams::bf16_w_off(0), acc);
+    fuse_store_hidden(acc, w.master + MlpParams::b_off(0), sH1, b.h1_col, B, b0);
+    for (int k = tid; k < kFuseRows * kFusePad / 2; k += 256) ((uint32_t *)sG)[k] = 0u;
+    __syncthreads();
+    // layer 2: H2 = relu(H1 W2^T + b2)
+    fuse_gemm<kMlpHid>(sH1, kFusePad, w.wt + MlpParams::bf16_w_off(1), acc);
+    fuse_store_hidden(acc, w.master + MlpParams::b_off(1), sH2, b.h2_col, B, b0);
+    __syncthreads();
+    // layer 3: O = H2 W3^T + b3 (FP32)
+    fuse_gemm<kMlpHid>(sH2, kFusePad, w.wt + MlpParams::bf16_w_off(2), acc);
+    {
+        const int fr = lane & 15, rq = (lane >> 4) * 4;
+        const float *bias = w.master + MlpParams::b_off(2);
+#pragma unroll
+        for (int i = 0; i < 2; ++i)
+#pragma unroll
+            for (int j = 0; j < 4; ++j) {
+                const int n = 64 * wave + 16 * j + fr, mb = 16 * i + rq;
+                const float bn = bias[n];
+                float v[4];
+#pragma unroll
+                for (int q = 0; q < 4; ++q) {
+                    v[q] = acc[i][j][q] + bn;
+                    sO[(mb + q) * kFuseOPad + n] = v[q];
+                }
+                *(float4 *)(b.o_col + (size_t)n * B + b0 + mb) = make_float4(v[0], v[1], v[2], v[3]);
+            }
+    }
+    __syncthreads();
+    // loss head: pair tid / 8, component tid % 8; gradient rows into sG
+    {
+        const int m = tid & 7, sl = tid >> 3;
+        const float loss = head_pair<MODEL>(sO + sl * kFuseOPad, 1, b.theta + (size_t)(b0 + sl) * kThetaStride, K,
+                                            inv_b, sG + sl * kFusePad, m);
+        const double ls = wave_sum((double)loss);
+        if (lane == 0) red[wave] = ls;
+    }
+    __syncthreads();
+    if (tid == 0) b.lossp[blockIdx.x] = (red[0] + red[1]) + (red[2] + red[3]);
+    for (int e = tid; e < kFuseRows * kMlpOut; e += 256) {
+        const int k = e / kFuseRows, q = e % kFuseRows;
+        b.do_col[(size_t)k * B + b0 + q] = sG[q * kFusePad + k];
+    }
+    // layer 3 input gradient: dH2 = (dO W3) * [H2 > 0]
+    fuse_gemm<kMlpOut>(sG, kFusePad, w.w + MlpParams::bf16_w_off(2), acc);
+    fuse_store_masked(acc, sH2, sD2, b.dh2_col, B, b0);
+    __syncthreads();
+    // layer 2 input gradient: dH1 = (dH2 W2) * [H1 > 0]
+    fuse_gemm<kMlpHid>(sD2, kFusePad, w.w + MlpParams::bf16_w_off(1), acc);
+    fuse_store_masked(acc, sH1, nullptr, b.dh1_col, B, b0);
 }
 
 // ------------------------------------------------------ bias gradients --
@@ -423,6 +585,29 @@ int launch_head_backward(int model, int K, const MlpView &w, const TrainBufs &b,
                           kEpiMaskRow | kEpiOutCol, nullptr, b.h1_row, nullptr, b.dh1_col, nullptr, st))
         return rc;
     // layer 1: dW1 = dH1^T X
+    if (int rc = mlp_gemm_splitr(b.dh1_col, b.x_col, kMlpHid, kMlpIn, B, B, B, b.chunk[0], b.part[0], st)) return rc;
+    hipLaunchKernelGGL(bias_grad_kernel, dim3(3 * 256), dim3(256), 0, st, b.dh1_col, b.dh2_col, b.do_col, B, b.bgrad);
+    PPL_LAUNCH_CHECK("bias_grad_kernel");
+    return PPL_OK;
+}
+
+// The fused pass (forward, head, input gradients) then the weight-gradient
+// products and bias sums of launch_head_backward.
+int launch_fused_pass(int model, int K, const MlpView &w, const TrainBufs &b, hipStream_t st) {
+    const int B = b.B;
+    if (B % kFuseRows) return fail(PPL_E_ARG, "batch %d is not a multiple of %d", B, kFuseRows);
+    const float inv_b = 1.0f / (float)B;
+    {
+        KernelTimer timer("fused_pass_kernel", st);
+        if (model == PPL_MODEL_POLY)
+            hipLaunchKernelGGL(fused_pass_kernel<PPL_MODEL_POLY>, dim3(B / kFuseRows), dim3(256), 0, st, w, b, K, inv_b);
+        else
+            hipLaunchKernelGGL(fused_pass_kernel<PPL_MODEL_GMM>, dim3(B / kFuseRows), dim3(256), 0, st, w, b, K, inv_b);
+        timer.stop();
+        PPL_LAUNCH_CHECK("fused_pass_kernel");
+    }
+    if (int rc = mlp_gemm_splitr(b.do_col, b.h2_col, kMlpOut, kMlpHid, B, B, B, b.chunk[2], b.part[2], st)) return rc;
+    if (int rc = mlp_gemm_splitr(b.dh2_col, b.h1_col, kMlpHid, kMlpHid, B, B, B, b.chunk[1], b.part[1], st)) return rc;
     if (int rc = mlp_gemm_splitr(b.dh1_col, b.x_col, kMlpHid, kMlpIn, B, B, B, b.chunk[0], b.part[0], st)) return rc;
     hipLaunchKernelGGL(bias_grad_kernel, dim3(3 * 256), dim3(256), 0, st, b.dh1_col, b.dh2_col, b.do_col, B, b.bgrad);
     PPL_LAUNCH_CHECK("bias_grad_kernel");

@@ -177,6 +177,27 @@ def test_forward_and_gradient_match_oracle(ppl, pr, name):
         assert rel_norm(part, ref) <= 1e-3, (t, rel_norm(part, ref))
 
 
+@pytest.mark.parametrize("name,B", [("poly", 512), ("gmm", 256), ("poly", 64)])
+def test_fused_pass_equals_separate_launches(ppl, name, B, monkeypatch):
+    """The fused forward/head/input-gradient pass stores the same bits as one
+    launch per product: outputs, loss and every gradient entry are equal."""
+    torch = torch_()
+    spec = MODELS[name]
+    cfg = ppl.train_config(B, B, spec["D"], dim=spec["K"])
+    wts = ppl.ppl_proposal_init(SEED)
+    res = []
+    for unfused in ("0", "1"):
+        monkeypatch.setenv("PPL_TRAIN_UNFUSED", unfused)
+        grad = torch.empty(COUNT, dtype=torch.float32, device="cuda")
+        loss = torch.empty(1, dtype=torch.float64, device="cuda")
+        out = torch.empty((256, B), dtype=torch.float32, device="cuda")
+        ppl.ppl_proposal_gradient(model_id(ppl, name), cfg, SEED, 3, wts, grad=grad, loss=loss, outputs=out)
+        torch.cuda.synchronize()
+        res.append((grad.cpu().numpy(), loss.cpu().numpy(), out.cpu().numpy()))
+    for a, b in zip(res[0], res[1]):
+        np.testing.assert_array_equal(a, b)
+
+
 def test_adam_step_matches_oracle(ppl, pr):
     torch = torch_()
     B = 256
