@@ -279,7 +279,16 @@ typedef struct ppl_smc_options {
                                * resampling (0: none); PPL_MODEL_GMM only; 0..64 */
     int32_t reserved;
     double move_scale;        /* random-walk scale factor lambda (0: 2.38 / sqrt(2K - 1)) */
+    int64_t t_begin;          /* first factor of this call: 0, or > 0 to resume from d_checkpoint */
+    int64_t t_end;            /* factor to stop before (0: T); < T stores the run's state in d_checkpoint */
+    void *d_checkpoint;       /* DEVICE buffer of ppl_smc_checkpoint_bytes() (caller-owned), needed when
+                               * t_begin > 0 or t_end < T */
 } ppl_smc_options;
+
+/* Bytes of an SMC checkpoint: a 256-byte header (next factor, N, state fields,
+ * log Z so far, resamplings, last merged maximum, status) and per particle its
+ * state fields, log-weight and the log-weight's compensation term. */
+int ppl_smc_checkpoint_bytes(int model, const ppl_data *data, int64_t n_particles, size_t *bytes);
 
 /* ppl_smc with options; resample-move for the mixture model.  After each
  * resampling at factor s every particle takes move_steps Metropolis-Hastings
@@ -299,7 +308,18 @@ typedef struct ppl_smc_options {
  *     b < 4 for sixteen normals (the first 2K - 1 used), word 0 of block
  *     8m + 4 for the uniform v.
  * Each move costs O(s K) per particle.  d_move_log_alpha (with max_events)
- * records log alpha per event, step and particle. */
+ * records log alpha per event, step and particle.
+ * Stop and resume: a call runs factors t_begin .. t_end - 1.  With t_end < T
+ * it stores the run's state in d_checkpoint and reports the log Z-hat
+ * accumulated so far (the increments of the resamplings up to t_end - 1) with
+ * ESS 0; a later call with t_begin = that t_end (same model, data, N, seed and
+ * options) continues from it, and the pieces together give the same bits as
+ * one call over all T factors (every random word is a function of the factor
+ * index; the checkpoint holds the FP32 log-weights with their compensation
+ * terms and the FP64 log Z-hat exactly).  A checkpoint whose header does not
+ * match (next factor, N, state fields) makes the status PPL_E_ARG on the
+ * device.  Traces and event records are written for the factors and events
+ * of each call (event rows continue the checkpoint's count). */
 int ppl_smc_ex(int model, const ppl_data *data, int64_t n_particles, uint64_t seed, const ppl_smc_options *opt,
                void *d_ws, size_t ws_bytes, void *stream, ppl_result *out);
 

@@ -32,7 +32,7 @@ PPL_NOALLOC_SCRATCH_BYTES = 16 << 20
 # Exported C symbols (kept in step with include/ppl.h).
 EXPORTS = ("ppl_status_string", "ppl_last_error", "ppl_version", "ppl_workspace_size",
            "ppl_importance", "ppl_importance_noalloc", "ppl_lse_ess", "ppl_resample", "ppl_resample_gather", "ppl_philox", "ppl_smc",
-           "ppl_smc_ex", "ppl_mcmc", "ppl_enumerate",
+           "ppl_smc_ex", "ppl_smc_checkpoint_bytes", "ppl_mcmc", "ppl_enumerate",
            "ppl_timing_enable", "ppl_timing_query")
 
 P = ctypes.c_void_p
@@ -58,7 +58,8 @@ class PplProposal(ctypes.Structure):
 
 class PplSmcOptions(ctypes.Structure):
     _fields_ = [("ess_frac", ctypes.c_double), ("move_steps", ctypes.c_int32), ("reserved", ctypes.c_int32),
-                ("move_scale", ctypes.c_double)]
+                ("move_scale", ctypes.c_double), ("t_begin", ctypes.c_int64), ("t_end", ctypes.c_int64),
+                ("d_checkpoint", P)]
 
 
 class PplMcmcResult(ctypes.Structure):
@@ -98,6 +99,7 @@ def _load():
                           ctypes.POINTER(PplResult)]
     L.ppl_mcmc.argtypes = [ctypes.c_int, ctypes.POINTER(PplData), i64, i64, i64, u64, P, ctypes.c_size_t, P,
                            ctypes.POINTER(PplMcmcResult)]
+    L.ppl_smc_checkpoint_bytes.argtypes = [ctypes.c_int, ctypes.POINTER(PplData), i64, ctypes.POINTER(ctypes.c_size_t)]
     L.ppl_enumerate.argtypes = [ctypes.c_int, ctypes.POINTER(PplData), P, ctypes.c_size_t, P,
                                 ctypes.POINTER(PplEnumResult)]
     L.ppl_smc_ex.argtypes = [ctypes.c_int, ctypes.POINTER(PplData), i64, u64, ctypes.POINTER(PplSmcOptions), P,
@@ -251,11 +253,14 @@ def ppl_philox(seed, c1, c2, c3, n, out=None, stream=None):
 
 def ppl_smc(model, data, n, seed, ess_frac=0.5, ws=None, stream=None, log_weights=None, latents=None,
             scalars=None, ess_trace=None, resampled=None, ancestors=None, sync=False, event_lw=None,
-            logz_trace=None, move_steps=0, move_scale=0.0, move_log_alpha=None):
+            logz_trace=None, move_steps=0, move_scale=0.0, move_log_alpha=None, t_begin=0, t_end=0,
+            checkpoint=None):
     """Sequential Monte Carlo (ppl_smc_ex); returns the ppl_result struct (host
     scalars when sync).  ancestors / event_lw: [max_events, n] and
     move_log_alpha: [max_events, move_steps, n] records of the first
-    resampling events.  move_steps > 0: resample-move (mixture model)."""
+    resampling events.  move_steps > 0: resample-move (mixture model).
+    t_begin / t_end / checkpoint: run factors [t_begin, t_end) only, resuming
+    from and stopping into the checkpoint (ppl_smc_checkpoint_bytes)."""
     if ws is None:
         ws = workspace(ppl_workspace_size(model, data, n, PPL_ALGO_SMC))
     rec = next((t for t in (ancestors, event_lw, move_log_alpha) if t is not None), None)
@@ -263,10 +268,17 @@ def ppl_smc(model, data, n, seed, ess_frac=0.5, ws=None, stream=None, log_weight
                     d_log_weights=_ptr(log_weights), d_ess_trace=_ptr(ess_trace), d_resampled=_ptr(resampled),
                     d_ancestors=_ptr(ancestors), max_events=0 if rec is None else rec.shape[0],
                     d_event_lw=_ptr(event_lw), d_logz_trace=_ptr(logz_trace), d_move_log_alpha=_ptr(move_log_alpha))
-    opt = PplSmcOptions(ess_frac=float(ess_frac), move_steps=int(move_steps), move_scale=float(move_scale))
+    opt = PplSmcOptions(ess_frac=float(ess_frac), move_steps=int(move_steps), move_scale=float(move_scale),
+                        t_begin=int(t_begin), t_end=int(t_end), d_checkpoint=_ptr(checkpoint))
     _check(lib.ppl_smc_ex(model, ctypes.byref(data), int(n), int(seed) & (2 ** 64 - 1), ctypes.byref(opt), _ptr(ws),
                           ws.numel(), _stream(stream), ctypes.byref(res)))
     return res
+
+
+def ppl_smc_checkpoint_bytes(model, data, n):
+    b = ctypes.c_size_t()
+    _check(lib.ppl_smc_checkpoint_bytes(model, ctypes.byref(data), int(n), ctypes.byref(b)))
+    return b.value
 
 
 def ppl_mcmc(model, data, n_chains, n_iters, seed, burn_in=0, ws=None, stream=None, state=None, accepts=None,

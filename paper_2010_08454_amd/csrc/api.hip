@@ -378,6 +378,15 @@ int ppl_smc_ex(int model, const ppl_data *data, int64_t n, uint64_t seed, const 
     if (!(opt->move_scale >= 0.0) || !isfinite(opt->move_scale)) return fail(PPL_E_ARG, "move_scale must be >= 0");
     if (out->max_events < 0 || (out->max_events > 0 && !out->d_ancestors && !out->d_event_lw && !out->d_move_log_alpha))
         return fail(PPL_E_ARG, "max_events > 0 with no event record buffer");
+    const int64_t T = data->n_data;
+    const int64_t t_end = opt->t_end == 0 ? T : opt->t_end;
+    if (opt->t_begin < 0 || opt->t_begin > t_end || t_end > T || t_end < 0)
+        return fail(PPL_E_ARG, "need 0 <= t_begin <= t_end <= T (got %lld, %lld, T = %lld)", (long long)opt->t_begin,
+                    (long long)opt->t_end, (long long)T);
+    if ((opt->t_begin > 0 || t_end < T) && !opt->d_checkpoint)
+        return fail(PPL_E_ARG, "stopping before T or resuming needs d_checkpoint");
+    if (opt->d_checkpoint && ((uintptr_t)opt->d_checkpoint & 255))
+        return fail(PPL_E_ARG, "d_checkpoint must be 256-byte aligned");
     if (int rc = check_ws(ws, ws_bytes, smc_ws_bytes(model, data->dim, n))) return rc;
     if (int rc = check_device()) return rc;
     a.model = model;
@@ -390,6 +399,9 @@ int ppl_smc_ex(int model, const ppl_data *data, int64_t n, uint64_t seed, const 
     a.ess_frac = ess_frac;
     a.move_steps = opt->move_steps;
     a.move_scale = opt->move_scale;
+    a.t_begin = opt->t_begin;
+    a.t_end = t_end;
+    a.ckpt = opt->d_checkpoint;
     a.out = *out;
     if (a.move_steps == 0) a.out.d_move_log_alpha = nullptr;
     a.ws = ws;
@@ -401,8 +413,20 @@ int ppl_smc_ex(int model, const ppl_data *data, int64_t n, uint64_t seed, const 
 
 int ppl_smc(int model, const ppl_data *data, int64_t n, uint64_t seed, double ess_frac, void *ws, size_t ws_bytes,
             void *stream, ppl_result *out) {
-    const ppl_smc_options opt{ess_frac, 0, 0, 0.0};
+    const ppl_smc_options opt{ess_frac, 0, 0, 0.0, 0, 0, nullptr};
     return ppl_smc_ex(model, data, n, seed, &opt, ws, ws_bytes, stream, out);
+}
+
+int ppl_smc_checkpoint_bytes(int model, const ppl_data *data, int64_t n, size_t *bytes) {
+    clear_error();
+    if (!bytes) return fail(PPL_E_ARG, "bytes is NULL");
+    if (model != PPL_MODEL_LGSSM && model != PPL_MODEL_GMM)
+        return fail(PPL_E_MODEL, "SMC supports LGSSM and GMM (got %d)", model);
+    if (int rc = check_n(n)) return rc;
+    double h[8];
+    if (int rc = check_model_data(model, data, h)) return rc;
+    *bytes = smc_checkpoint_bytes(model, data->dim, n);
+    return PPL_OK;
 }
 
 int ppl_mcmc(int model, const ppl_data *data, int64_t n_chains, int64_t n_iters, int64_t burn_in, uint64_t seed,

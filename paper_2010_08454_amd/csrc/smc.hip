@@ -75,6 +75,8 @@ struct SmcDev {
     double *logz_tr;         // [T] normaliser increment added after factor s
     double *alpha_out;       // [max_events][move_steps][N] log acceptance ratios of the moves
     int64_t max_events;
+    int64_t t0, t1;          // factors of this launch [t0, t1)
+    char *ckpt;              // checkpoint: header then [NF][N] state, [N] lw, [N] compensation
     int move_steps;          // resample-move steps per particle after each resampling
     double move_lam;         // random-walk scale factor
     double hyp64[2];         // GMM {mu_sd, comp_sd} in FP64 (move scales)
@@ -85,6 +87,18 @@ struct SmcDev {
     float *xbuf;             // [NF][N]
     float *xbuf2;            // [NF][N] gathered particles while they move (resample-move)
 };
+
+// Checkpoint header (the first 256 bytes of a checkpoint).
+struct SmcCkpt {
+    int64_t t;               // next factor
+    int64_t N;
+    int64_t nres;
+    int32_t nf;
+    int32_t status;
+    double logz;
+    float mlast;
+};
+constexpr size_t kCkptHeader = 256;
 
 // ------------------------------------------------------------- barrier --
 // Record barrier for epoch e.  Thread 0 stores the block's three record
@@ -480,14 +494,6 @@ __global__ __launch_bounds__(kSmcThreads) void smc_persistent_kernel(SmcDev a) {
     float st[P][M::NF];
     float lw[P], lwc[P];     // log-weight and its compensation term
     bool valid[P];
-#pragma unroll
-    for (int p = 0; p < P; ++p) {
-        valid[p] = base + p < N;
-        M::init(a, (uint32_t)(base + p), st[p]);
-        lw[p] = valid[p] ? 0.0f : -INFINITY;
-        lwc[p] = 0.0f;
-    }
-
     unsigned epoch = 0;
     double logz = 0.0;
     int64_t nres = 0;
@@ -495,12 +501,42 @@ __global__ __launch_bounds__(kSmcThreads) void smc_persistent_kernel(SmcDev a) {
     float Mlast = 0.0f;
     bool alive = true;
     const double logN = log_f64((double)N);
+    if (a.t0 > 0) {
+        // resume: the run's scalars from the header, each particle from the checkpoint
+        const SmcCkpt *h = (const SmcCkpt *)a.ckpt;
+        const float *cs = (const float *)(a.ckpt + kCkptHeader);
+        if (h->t != a.t0 || h->N != N || h->nf != M::NF) {
+            status = PPL_E_ARG;
+        } else {
+            logz = h->logz;
+            nres = h->nres;
+            Mlast = h->mlast;
+            status = h->status;
+        }
+#pragma unroll
+        for (int p = 0; p < P; ++p) {
+            valid[p] = base + p < N;
+#pragma unroll
+            for (int f = 0; f < M::NF; ++f) st[p][f] = valid[p] ? cs[(size_t)f * N + base + p] : 0.0f;
+            lw[p] = valid[p] ? cs[(size_t)M::NF * N + base + p] : -INFINITY;
+            lwc[p] = valid[p] ? cs[(size_t)(M::NF + 1) * N + base + p] : 0.0f;
+        }
+    } else {
+#pragma unroll
+        for (int p = 0; p < P; ++p) {
+            valid[p] = base + p < N;
+            M::init(a, (uint32_t)(base + p), st[p]);
+            lw[p] = valid[p] ? 0.0f : -INFINITY;
+            lwc[p] = 0.0f;
+        }
+    }
 
-    for (int64_t s = 0; s < a.T; ++s) {
-        if ((s % kYChunk) == 0) {          // stage the next chunk of observations
+    for (int64_t s = a.t0; status == 0 && s < a.t1; ++s) {
+        if (s == a.t0 || (s % kYChunk) == 0) {     // stage the chunk of observations holding factor s
+            const int64_t c0 = s - s % kYChunk;
             __syncthreads();
             for (int i = threadIdx.x; i < kYChunk; i += kSmcThreads)
-                ybuf[i] = (s + i < a.T) ? a.y[s + i] : 0.0f;
+                ybuf[i] = (c0 + i < a.T) ? a.y[c0 + i] : 0.0f;
             __syncthreads();
         }
         const float ys = ybuf[s % kYChunk];
@@ -727,9 +763,32 @@ __global__ __launch_bounds__(kSmcThreads) void smc_persistent_kernel(SmcDev a) {
         }
     }
 
+    // ---- stop: the run's state into the checkpoint
+    const bool stopped = a.t1 < a.T;
+    if (stopped && alive) {
+        float *cs = (float *)(a.ckpt + kCkptHeader);
+#pragma unroll
+        for (int p = 0; p < P; ++p) {
+            if (!valid[p]) continue;
+#pragma unroll
+            for (int f = 0; f < M::NF; ++f) cs[(size_t)f * N + base + p] = st[p][f];
+            cs[(size_t)M::NF * N + base + p] = lw[p];
+            cs[(size_t)(M::NF + 1) * N + base + p] = lwc[p];
+        }
+        if (blockIdx.x == 0 && threadIdx.x == 0) {
+            SmcCkpt *h = (SmcCkpt *)a.ckpt;
+            h->t = a.t1;
+            h->N = N;
+            h->nres = nres;
+            h->nf = M::NF;
+            h->status = status;
+            h->logz = logz;
+            h->mlast = Mlast;
+        }
+    }
     // ---- final normaliser (FP64) over the last epoch
-    double ess_final = (double)N;
-    if (alive && status == 0 && a.T > 0) {
+    double ess_final = stopped ? 0.0 : (double)N;
+    if (alive && status == 0 && a.T > 0 && !stopped) {
         double e1 = 0.0, e2 = 0.0;
 #pragma unroll
         for (int p = 0; p < P; ++p) {
@@ -818,6 +877,11 @@ static SmcLayout smc_layout(void *ws, int NF, int64_t N, int64_t nb) {
     return L;
 }
 
+size_t smc_checkpoint_bytes(int model, int K, int64_t N) {
+    const int NF = model == PPL_MODEL_LGSSM ? 1 : 2 * K;
+    return kCkptHeader + align_up((size_t)(NF + 2) * N * sizeof(float), 256);
+}
+
 size_t smc_ws_bytes(int model, int K, int64_t N) {
     const int NF = model == PPL_MODEL_LGSSM ? 1 : 2 * K;
     const int P = pick_p(N);
@@ -898,6 +962,9 @@ int run_smc(const SmcArgs &a, hipStream_t st) {
     d.logz_tr = a.out.d_logz_trace;
     d.alpha_out = a.out.d_move_log_alpha;
     d.max_events = a.out.max_events;
+    d.t0 = a.t_begin;
+    d.t1 = a.t_end;
+    d.ckpt = (char *)a.ckpt;
     d.move_steps = a.move_steps;
     d.move_lam = a.move_scale > 0.0 ? a.move_scale : 2.38 / sqrt(2.0 * a.K - 1.0);
     d.hyp64[0] = a.hyper[0];

@@ -174,3 +174,27 @@ def test_enumerate_validates(ppl):
     assert _size(ppl, ppl.PPL_MODEL_GMM, _hmm(ppl), 1, ppl.PPL_ALGO_ENUM)[0] == ppl.PPL_E_MODEL
     rc, nb = _size(ppl, ppl.PPL_MODEL_HMM, _hmm(ppl, K=4, T=18), 1, ppl.PPL_ALGO_ENUM)
     assert rc == 0 and 256 < nb < 1 << 22
+
+
+def test_smc_stop_resume_validates(ppl):
+    """ppl_smc_ex's factor range and checkpoint arguments are checked before a launch."""
+    L = ppl.lib
+    res = ppl.PplResult()
+    lg = _data(ppl, y=256, n_data=1000, dtype=ppl.PPL_F32)
+    S = lambda **kw: L.ppl_smc_ex(ppl.PPL_MODEL_LGSSM, ctypes.byref(lg), 1000, 1,
+                                  ctypes.byref(ppl.PplSmcOptions(ess_frac=0.5, **kw)), 256, 1 << 24, None,
+                                  ctypes.byref(res))
+    assert S(t_begin=10, t_end=5) == ppl.PPL_E_ARG                 # begin after end
+    assert S(t_begin=0, t_end=1001) == ppl.PPL_E_ARG               # end past T
+    assert S(t_begin=-1) == ppl.PPL_E_ARG
+    assert S(t_begin=0, t_end=500) == ppl.PPL_E_ARG                # stopping needs a checkpoint
+    assert S(t_begin=500) == ppl.PPL_E_ARG                         # resuming needs a checkpoint
+    assert S(t_begin=500, d_checkpoint=4096 + 8) == ppl.PPL_E_ARG  # misaligned checkpoint
+    assert S(t_begin=500, d_checkpoint=4096) == ppl.PPL_E_DEVICE   # valid: reaches the device check
+    b = ctypes.c_size_t()
+    assert L.ppl_smc_checkpoint_bytes(ppl.PPL_MODEL_LGSSM, ctypes.byref(lg), 1000, ctypes.byref(b)) == 0
+    assert b.value >= 256 + 3 * 1000 * 4
+    g = _data(ppl, y=256, n_data=100, dim=5, dtype=ppl.PPL_F32)
+    assert L.ppl_smc_checkpoint_bytes(ppl.PPL_MODEL_GMM, ctypes.byref(g), 1000, ctypes.byref(b)) == 0
+    assert b.value >= 256 + 12 * 1000 * 4
+    assert L.ppl_smc_checkpoint_bytes(ppl.PPL_MODEL_BLR, ctypes.byref(g), 1000, ctypes.byref(b)) == ppl.PPL_E_MODEL
