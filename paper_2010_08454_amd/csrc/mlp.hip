@@ -124,11 +124,12 @@ int mlp_gemm_splitr(const uint16_t *A, const uint16_t *B, int M, int N, int R, i
     return PPL_OK;
 }
 
-// Enough chunks for about two workgroups per compute unit, each chunk a
-// multiple of 32 rows.
+// About 128 workgroups per product (each chunk a multiple of 32 rows): more
+// chunks spread the reduction over more compute units but write, and make the
+// Adam step read, one FP32 partial of the whole matrix per chunk.
 void mlp_split_plan(int M, int N, int R, int *nchunks, int *chunk) {
     const int tiles = (M / kGemmTile) * (N / kGemmTile);
-    int want = (512 + tiles - 1) / tiles;
+    int want = (128 + tiles - 1) / tiles;
     const int max_chunks = R / 32;
     if (want > max_chunks) want = max_chunks;
     if (want < 1) want = 1;
