@@ -190,31 +190,49 @@ constexpr int kFuseOPad = 260;          // FP32 per LDS row of the outputs
 typedef __bf16 fbf16x8_t __attribute__((ext_vector_type(8)));
 typedef float ffloatx4_t __attribute__((ext_vector_type(4)));
 
-// acc[i][j][q] = C[16 i + 4 (lane / 16) + q][64 wave + 16 j + lane % 16].
+// A product's weight fragments for this wave: fb[s][j] holds B rows
+// 64 wave + 16 j + lane % 16, K entries 32 s + 8 (lane / 16) .. + 7.  They are
+// loaded one product ahead (while the previous product's epilogue and the
+// workgroup barrier run), so a product waits for global memory at most once.
+typedef fbf16x8_t FuseFrags[8][4];
+
 template <int KD>
-__device__ __forceinline__ void fuse_gemm(const uint16_t *A, int lda, const uint16_t *Bw, ffloatx4_t (&acc)[2][4]) {
+__device__ __forceinline__ void fuse_load_w(const uint16_t *Bw, FuseFrags &fb) {
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int fr = lane & 15, fk = (lane >> 4) * 8;
+#pragma unroll
+    for (int s = 0; s < KD / 32; ++s)
+#pragma unroll
+        for (int j = 0; j < 4; ++j)
+            fb[s][j] = *(const fbf16x8_t *)(Bw + (size_t)(64 * wave + 16 * j + fr) * KD + 32 * s + fk);
+    __builtin_amdgcn_sched_barrier(0);       // keep the scheduler from sinking the loads into the MFMA loop
+}
+
+// acc[i][j][q] = C[16 i + 4 (lane / 16) + q][64 wave + 16 j + lane % 16] of
+// C[32][256] = A[32][KD] B[256][KD]^T, B's fragments in fb.
+template <int KD>
+__device__ __forceinline__ void fuse_mma(const uint16_t *A, int lda, const FuseFrags &fb, ffloatx4_t (&acc)[2][4]) {
+    const int lane = threadIdx.x & 63;
     const int fr = lane & 15, fk = (lane >> 4) * 8;
 #pragma unroll
     for (int i = 0; i < 2; ++i)
 #pragma unroll
         for (int j = 0; j < 4; ++j) acc[i][j] = ffloatx4_t{0.f, 0.f, 0.f, 0.f};
-    for (int k0 = 0; k0 < KD; k0 += 32) {
-        fbf16x8_t fa[2], fb[4];
 #pragma unroll
-        for (int i = 0; i < 2; ++i) fa[i] = *(const fbf16x8_t *)(A + (size_t)(16 * i + fr) * lda + k0 + fk);
+    for (int s = 0; s < KD / 32; ++s) {
+        fbf16x8_t fa[2];
 #pragma unroll
-        for (int j = 0; j < 4; ++j) fb[j] = *(const fbf16x8_t *)(Bw + (size_t)(64 * wave + 16 * j + fr) * KD + k0 + fk);
+        for (int i = 0; i < 2; ++i) fa[i] = *(const fbf16x8_t *)(A + (size_t)(16 * i + fr) * lda + 32 * s + fk);
 #pragma unroll
         for (int i = 0; i < 2; ++i)
 #pragma unroll
-            for (int j = 0; j < 4; ++j) acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(fa[i], fb[j], acc[i][j], 0, 0, 0);
+            for (int j = 0; j < 4; ++j) acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(fa[i], fb[s][j], acc[i][j], 0, 0, 0);
     }
 }
 
 // Hidden-layer epilogue: relu(acc + bias) in BF16 to LDS rows and to the
 // column-major global copy [256][B] (columns b0 .. b0 + 31).
-__device__ __forceinline__ void fuse_store_hidden(const ffloatx4_t (&acc)[2][4], const float *bias, uint16_t *lds,
+__device__ __forceinline__ void fuse_store_hidden(const ffloatx4_t (&acc)[2][4], const float (&bias)[4], uint16_t *lds,
                                                   uint16_t *col, int B, int b0) {
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int fr = lane & 15, rq = (lane >> 4) * 4;
@@ -223,7 +241,7 @@ __device__ __forceinline__ void fuse_store_hidden(const ffloatx4_t (&acc)[2][4],
 #pragma unroll
         for (int j = 0; j < 4; ++j) {
             const int n = 64 * wave + 16 * j + fr, mb = 16 * i + rq;
-            const float bn = bias[n];
+            const float bn = bias[j];
             uint16_t h[4];
 #pragma unroll
             for (int q = 0; q < 4; ++q) {
@@ -258,6 +276,18 @@ __device__ __forceinline__ void fuse_store_masked(const ffloatx4_t (&acc)[2][4],
         }
 }
 
+// Workgroup barrier for data exchanged through LDS only: waits for this
+// wave's LDS operations (lgkmcnt 0) but leaves its global stores and the
+// prefetched weight loads in flight (a full __syncthreads would wait for
+// them at every layer).  Nothing the fused pass stores to global memory is
+// read back by another wave of the workgroup.
+__device__ __forceinline__ void lds_barrier() {
+    asm volatile("" ::: "memory");
+    __builtin_amdgcn_s_waitcnt(0xc07f);      // vmcnt and expcnt: no wait; lgkmcnt: 0
+    __builtin_amdgcn_s_barrier();
+    asm volatile("" ::: "memory");
+}
+
 template <int MODEL>
 __global__ __launch_bounds__(256) void fused_pass_kernel(MlpView w, TrainBufs b, int K, float inv_b) {
     __shared__ __align__(16) uint16_t sH1[kFuseRows * kFusePad];
@@ -265,30 +295,44 @@ __global__ __launch_bounds__(256) void fused_pass_kernel(MlpView w, TrainBufs b,
     __shared__ __align__(16) uint16_t sG[kFuseRows * kFusePad];     // dO
     __shared__ __align__(16) uint16_t sD2[kFuseRows * kFusePad];    // dH2
     __shared__ __align__(16) float sO[kFuseRows * kFuseOPad];
+    __shared__ double sTh[kFuseRows * kThetaStride];
     __shared__ double red[4];
     const int B = b.B, b0 = blockIdx.x * kFuseRows, tid = threadIdx.x;
     const int lane = tid & 63, wave = tid >> 6;
+    // Global reads that epilogues and the head need are issued first: vector
+    // memory loads and stores complete in order, so a load issued after the
+    // next product's weight prefetch would wait for that prefetch too.
+    float bias_r[3][4];
+#pragma unroll
+    for (int l = 0; l < 3; ++l)
+#pragma unroll
+        for (int j = 0; j < 4; ++j) bias_r[l][j] = w.master[MlpParams::b_off(l) + 64 * wave + 16 * j + (lane & 15)];
     ffloatx4_t acc[2][4];
+    FuseFrags fb;
     // layer 1: H1 = relu(X W1^T + b1)
-    fuse_gemm<kMlpIn>(b.x_row + (size_t)b0 * kMlpIn, kMlpIn, w.wt + MlpParams::bf16_w_off(0), acc);
-    fuse_store_hidden(acc, w.master + MlpParams::b_off(0), sH1, b.h1_col, B, b0);
+    fuse_load_w<kMlpIn>(w.wt + MlpParams::bf16_w_off(0), fb);
+    for (int e = tid; e < kFuseRows * kThetaStride; e += 256) sTh[e] = b.theta[(size_t)b0 * kThetaStride + e];
+    fuse_mma<kMlpIn>(b.x_row + (size_t)b0 * kMlpIn, kMlpIn, fb, acc);
+    fuse_load_w<kMlpHid>(w.wt + MlpParams::bf16_w_off(1), fb);
+    fuse_store_hidden(acc, bias_r[0], sH1, b.h1_col, B, b0);
     for (int k = tid; k < kFuseRows * kFusePad / 2; k += 256) ((uint32_t *)sG)[k] = 0u;
-    __syncthreads();
+    lds_barrier();
     // layer 2: H2 = relu(H1 W2^T + b2)
-    fuse_gemm<kMlpHid>(sH1, kFusePad, w.wt + MlpParams::bf16_w_off(1), acc);
-    fuse_store_hidden(acc, w.master + MlpParams::b_off(1), sH2, b.h2_col, B, b0);
-    __syncthreads();
+    fuse_mma<kMlpHid>(sH1, kFusePad, fb, acc);
+    fuse_load_w<kMlpHid>(w.wt + MlpParams::bf16_w_off(2), fb);
+    fuse_store_hidden(acc, bias_r[1], sH2, b.h2_col, B, b0);
+    lds_barrier();
     // layer 3: O = H2 W3^T + b3 (FP32)
-    fuse_gemm<kMlpHid>(sH2, kFusePad, w.wt + MlpParams::bf16_w_off(2), acc);
+    fuse_mma<kMlpHid>(sH2, kFusePad, fb, acc);
+    fuse_load_w<kMlpOut>(w.w + MlpParams::bf16_w_off(2), fb);
     {
         const int fr = lane & 15, rq = (lane >> 4) * 4;
-        const float *bias = w.master + MlpParams::b_off(2);
 #pragma unroll
         for (int i = 0; i < 2; ++i)
 #pragma unroll
             for (int j = 0; j < 4; ++j) {
                 const int n = 64 * wave + 16 * j + fr, mb = 16 * i + rq;
-                const float bn = bias[n];
+                const float bn = bias_r[2][j];
                 float v[4];
 #pragma unroll
                 for (int q = 0; q < 4; ++q) {
@@ -298,27 +342,28 @@ __global__ __launch_bounds__(256) void fused_pass_kernel(MlpView w, TrainBufs b,
                 *(float4 *)(b.o_col + (size_t)n * B + b0 + mb) = make_float4(v[0], v[1], v[2], v[3]);
             }
     }
-    __syncthreads();
+    lds_barrier();
     // loss head: pair tid / 8, component tid % 8; gradient rows into sG
     {
         const int m = tid & 7, sl = tid >> 3;
-        const float loss = head_pair<MODEL>(sO + sl * kFuseOPad, 1, b.theta + (size_t)(b0 + sl) * kThetaStride, K,
-                                            inv_b, sG + sl * kFusePad, m);
+        const float loss = head_pair<MODEL>(sO + sl * kFuseOPad, 1, sTh + sl * kThetaStride, K, inv_b,
+                                            sG + sl * kFusePad, m);
         const double ls = wave_sum((double)loss);
         if (lane == 0) red[wave] = ls;
     }
-    __syncthreads();
+    lds_barrier();
     if (tid == 0) b.lossp[blockIdx.x] = (red[0] + red[1]) + (red[2] + red[3]);
     for (int e = tid; e < kFuseRows * kMlpOut; e += 256) {
         const int k = e / kFuseRows, q = e % kFuseRows;
         b.do_col[(size_t)k * B + b0 + q] = sG[q * kFusePad + k];
     }
     // layer 3 input gradient: dH2 = (dO W3) * [H2 > 0]
-    fuse_gemm<kMlpOut>(sG, kFusePad, w.w + MlpParams::bf16_w_off(2), acc);
+    fuse_mma<kMlpOut>(sG, kFusePad, fb, acc);
+    fuse_load_w<kMlpHid>(w.w + MlpParams::bf16_w_off(1), fb);
     fuse_store_masked(acc, sH2, sD2, b.dh2_col, B, b0);
-    __syncthreads();
+    lds_barrier();
     // layer 2 input gradient: dH1 = (dH2 W2) * [H1 > 0]
-    fuse_gemm<kMlpHid>(sD2, kFusePad, w.w + MlpParams::bf16_w_off(1), acc);
+    fuse_mma<kMlpHid>(sD2, kFusePad, fb, acc);
     fuse_store_masked(acc, sH1, nullptr, b.dh1_col, B, b0);
 }
 
