@@ -15,7 +15,8 @@
 // Kernels:
 //   blr_stats_partial_kernel: workgroup g sums rows [g R, (g + 1) R) of
 //     x x^T, x y and y^2 in FP64 (one thread per statistic);
-//   blr_stats_finalize_kernel: sums the workgroup partials in a fixed order;
+//   blr_stats_finalize_kernel: sums the workgroup partials in a fixed order,
+//     one wave per statistic;
 //   blr_stats_is_kernel: per particle draw, FP64 quadratic form, log-weight,
 //     and the normaliser's partial record (as blr_is_kernel).
 #include "blr.h"
@@ -63,15 +64,19 @@ __global__ __launch_bounds__(kStatsThreads) void blr_stats_partial_kernel(const 
     }
 }
 
+// One wave per statistic: lane l sums the partials of groups l, l + 64, ...
+// in order, then a fixed DPP reduction adds the lanes (a dependent chain of
+// one load per group would leave this launch latency-bound).
 template <int DIM>
 __global__ __launch_bounds__(kStatsThreads) void blr_stats_finalize_kernel(const double *__restrict__ part, int groups,
                                                                          double *__restrict__ stats) {
     constexpr int NS = ss_count(DIM);
-    for (int e = threadIdx.x; e < NS; e += kStatsThreads) {
-        double s = 0.0;
-        for (int g = 0; g < groups; ++g) s += part[(size_t)g * NS + e];
-        stats[e] = s;
-    }
+    const int e = blockIdx.x * (kStatsThreads / 64) + (threadIdx.x >> 6), lane = threadIdx.x & 63;
+    if (e >= NS) return;                     // whole waves leave together
+    double s = 0.0;
+    for (int g = lane; g < groups; g += 64) s += part[(size_t)g * NS + e];
+    s = wave_sum_dpp(s);
+    if (lane == 0) stats[e] = s;
 }
 
 template <int P, int DIM, bool PROP>
@@ -130,8 +135,9 @@ static int launch_blr_stats(const IsArgs &a, hipStream_t st) {
                            (const float *)a.x, (const float *)a.y, (int)a.D, sparts);
         PPL_LAUNCH_CHECK("blr_stats_partial_kernel");
     }
-    hipLaunchKernelGGL(blr_stats_finalize_kernel<DIM>, dim3(1), dim3(kStatsThreads), 0, st, sparts, (int)groups,
-                       stats);
+    constexpr int kWavesPerBlock = kStatsThreads / 64;
+    hipLaunchKernelGGL(blr_stats_finalize_kernel<DIM>, dim3((ss_count(DIM) + kWavesPerBlock - 1) / kWavesPerBlock),
+                       dim3(kStatsThreads), 0, st, sparts, (int)groups, stats);
     PPL_LAUNCH_CHECK("blr_stats_finalize_kernel");
     {
         KernelTimer timer("blr_stats_is_kernel", st);

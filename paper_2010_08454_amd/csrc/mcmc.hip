@@ -73,6 +73,18 @@ __global__ __launch_bounds__(kMcThreads) void mcmc_poly_kernel(
 #pragma unroll
     for (int k = 0; k < kMcNF; ++k) sums[k] = 0.0;
     const uint32_t range = (uint32_t)(n_hi - n_lo + 1);
+    // log(n + 1) for the trace-size ratio, n <= 5: the same values log() gives
+    // per iteration, computed once
+    double lsz[7];
+#pragma unroll
+    for (int k = 1; k <= 6; ++k) lsz[k] = log((double)k);
+    lsz[0] = 0.0;
+    auto log_size = [&](int k) {
+        double r = lsz[1];
+#pragma unroll
+        for (int q = 2; q <= 6; ++q) r = k == q ? lsz[q] : r;
+        return r;
+    };
 
     for (int64_t t = 0; t < T; ++t) {
         const uint4 w = philox((uint32_t)c, (uint32_t)(3 * t), 0, kTagMcmc, key);
@@ -106,7 +118,7 @@ __global__ __launch_bounds__(kMcThreads) void mcmc_poly_kernel(
             for (int j = 0; j < 5; ++j) c2[j] = (j == site - 1) ? sd * z[0] : pc[j];
         }
         const double ll2 = mc_loglik(c2, X, Y, D);
-        const double la = (ll2 - ll) + (log((double)(n + 1)) - log((double)(n2 + 1)));
+        const double la = (ll2 - ll) + (log_size(n + 1) - log_size(n2 + 1));
         const bool acc = log((double)unit_f32(w.z)) < la;
         if (valid && la_tr) la_tr[t * C + c] = la;
         if (acc) {
