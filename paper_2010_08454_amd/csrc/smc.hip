@@ -21,14 +21,17 @@
 //   3. if ESS < ess_frac N (and s is not the last factor): FP64 weights
 //      e = exp(lw - max) give the epoch normaliser and the quantised integer
 //      weights q; each block scans its q and publishes its tile total, its
-//      tile-local prefix sums and its particles' state; grid barrier; each
+//      tile-local exclusive prefix sums and its particles' state; grid barrier; each
 //      block finds the contiguous ancestor range of its slots, stages those
 //      prefix sums in LDS, and every slot binary-searches its ancestor there
 //      and gathers the ancestor's state; lw = 0.
 // Blocks meet at a record barrier: each block stores its record (the partial
 // of step 2, the tile total of step 3, the final sums) on its own cache line
-// and then the barrier epoch; thread t of every block polls line t, so every
-// block holds every record when it leaves, with no shared counter.  The spin
+// and thread t of every block polls line t, so every block holds every record
+// when it leaves, with no shared counter.  Every word a block publishes for
+// others (record words, the prefix sums and state of step 3) carries the tag
+// of its epoch or event, so a reader knows it has the current value without
+// any release or acquire, and a reader that is early polls again.  The spin
 // is bounded: if a wait exceeds the limit, the block raises the abort flag
 // and every block leaves its loop at its next barrier, so the grid always
 // drains.
@@ -83,8 +86,8 @@ struct SmcDev {
     // workspace
     unsigned *bar;           // [1] abort flag
     uint64_t *rec;           // [2][nb][16] record lines: word 0 the epoch, words 1..3 the record
-    uint64_t *qloc;          // [N] tile-local inclusive prefix sums of q
-    float *xbuf;             // [NF][N]
+    uint64_t *qtag;          // [N] tagged tile-local exclusive prefix sums of q
+    uint64_t *xtag;          // [NF][N] tagged particle state
     float *xbuf2;            // [NF][N] gathered particles while they move (resample-move)
 };
 
@@ -101,67 +104,75 @@ struct SmcCkpt {
 constexpr size_t kCkptHeader = 256;
 
 // ------------------------------------------------------------- barrier --
-// Record barrier for epoch e.  Thread 0 stores the block's three record
-// words on its line of buffer e mod 2, then e in word 0 (release, after a
-// workgroup barrier, so every store the block made before it is released
-// too).  Thread t < nb polls line t with relaxed device-scope loads until it
-// reads e, then loads the record words with device-scope loads: they are
-// issued only after the epoch has been read, and the release put them at the
-// device's coherence point before the epoch, so they are the block's record.
-// With `acquire`, one acquire fence per block then makes every other store
-// the blocks released visible to plain loads (the resampling gather reads
-// other blocks' prefix sums and state).  Two buffers suffice: a block cannot
-// pass barrier e + 1 before every block has stored its record e + 1, which
-// each does only after reading all records e.  Returns false (uniformly in
-// the block) once any block has aborted.
-__device__ __forceinline__ bool record_barrier(uint64_t *rec, unsigned *bar, unsigned epoch, int nb, uint64_t w0,
-                                               uint64_t w1, uint64_t w2, uint64_t (&r)[3], bool acquire) {
+// Record exchange for epoch e (a grid barrier that also hands every block
+// every block's record): thread 0 stores NW words on its line of buffer
+// e mod 2 with relaxed device-scope stores, each word holding e in its high
+// half and 32 bits of the record in its low half; thread t < nb polls line t
+// (its last word first) until every word of the line holds e.  Each word
+// validates itself, so the exchange needs no release and no acquire (a
+// device-scope release writes back the L2 of the issuing XCD, which at 256
+// workgroups costs more than the exchange itself).  Two buffers suffice: a
+// block cannot store record e + 2 before every block has stored record e + 1,
+// which each does only after reading all records e.  Returns false
+// (uniformly in the block) once any block has aborted.
+template <int NW>
+__device__ __forceinline__ bool tagged_barrier(uint64_t *rec, unsigned *bar, unsigned epoch, int nb,
+                                               const uint32_t (&w)[NW], uint32_t (&r)[NW]) {
+    static_assert(NW <= kRecWords, "record line overflow");
     __shared__ int s_bad;
     unsigned *abort_flag = bar + 1;
     uint64_t *buf = rec + (size_t)(epoch & 1u) * nb * kRecWords;
+    const uint64_t tag = (uint64_t)epoch << 32;
     if (threadIdx.x == 0) s_bad = 0;
     __syncthreads();
     if (threadIdx.x == 0) {
         uint64_t *mine = buf + (size_t)blockIdx.x * kRecWords;
-        __hip_atomic_store(mine + 1, w0, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        __hip_atomic_store(mine + 2, w1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        __hip_atomic_store(mine + 3, w2, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        __hip_atomic_store(mine, (uint64_t)epoch, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+#pragma unroll
+        for (int k = 0; k < NW; ++k) __hip_atomic_store(mine + k, tag | w[k], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     }
-    r[0] = r[1] = r[2] = 0;
+#pragma unroll
+    for (int k = 0; k < NW; ++k) r[k] = 0;
     if (threadIdx.x < nb) {          // nb <= kSmcThreads
         uint64_t *line = buf + (size_t)threadIdx.x * kRecWords;
         uint32_t spins = 0;
-        bool ok = true;
-        while (__hip_atomic_load(line, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < (uint64_t)epoch) {
+        while (true) {
+            const uint64_t last = __hip_atomic_load(line + NW - 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            if ((last >> 32) == (uint64_t)epoch) {
+                uint64_t v[NW];
+                bool all = true;
+#pragma unroll
+                for (int k = 0; k < NW - 1; ++k) {
+                    v[k] = __hip_atomic_load(line + k, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                    all = all && (v[k] >> 32) == (uint64_t)epoch;
+                }
+                v[NW - 1] = last;
+                if (all) {
+#pragma unroll
+                    for (int k = 0; k < NW; ++k) r[k] = (uint32_t)v[k];
+                    break;
+                }
+            }
             __builtin_amdgcn_s_sleep(1);
             if ((++spins & 63) == 0) {
-                if (__hip_atomic_load(abort_flag, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) { ok = false; break; }
+                if (__hip_atomic_load(abort_flag, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) { s_bad = 1; break; }
                 if (spins > kSpinLimit) {
                     __hip_atomic_store(abort_flag, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-                    ok = false;
+                    s_bad = 1;
                     break;
                 }
             }
         }
-        if (ok) {
-            r[0] = __hip_atomic_load(line + 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-            r[1] = __hip_atomic_load(line + 2, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-            r[2] = __hip_atomic_load(line + 3, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        } else {
-            s_bad = 1;
-        }
     }
     __syncthreads();
-    if (acquire) {
-        if (threadIdx.x == 0) __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
-        __syncthreads();
-    }
     return s_bad == 0;
 }
 
-__device__ __forceinline__ uint64_t dbits(double v) { return (uint64_t)__double_as_longlong(v); }
-__device__ __forceinline__ double dval(uint64_t v) { return __longlong_as_double((long long)v); }
+__device__ __forceinline__ uint32_t hi32(double v) { return (uint32_t)((uint64_t)__double_as_longlong(v) >> 32); }
+__device__ __forceinline__ uint32_t lo32(double v) { return (uint32_t)(uint64_t)__double_as_longlong(v); }
+__device__ __forceinline__ double from32(uint32_t hi, uint32_t lo) {
+    return __longlong_as_double((long long)(((uint64_t)hi << 32) | lo));
+}
+
 
 // --------------------------------------------------------------- models --
 struct Lgssm {
@@ -446,26 +457,80 @@ __device__ __forceinline__ void slot_threshold_next(SlotThreshold &t, uint64_t S
     }
 }
 
-// Ancestor of the slot with threshold tau over the whole population:
-// min{a : Q_a > tau}, with Q_a = tile_pre[b] + qloc[a] for a in tile b (tile
-// ends and exclusive tile prefixes are in LDS, qloc in device memory).
+// Resampling data carry their event's tag, so the readers need no acquire
+// (and the writers no release).  A prefix word holds the tag in its top two
+// bits (1 + r mod 3 for the (r + 1)-th event of the call: never 0, the value
+// the words are cleared to before the launch, and never the previous
+// event's) and the tile-local exclusive prefix (< 2^62) below; a state word
+// holds r + 1 in its high half and the FP32 bits in its low half.  A reader
+// that finds another tag (the store has not reached it yet) polls the word
+// again; after kSpinLimit polls, or once another block has aborted, it sets
+// `bad` and returns 0 (an in-range value, so every index derived from it
+// stays in bounds).
+constexpr int kQTagShift = 62;
+constexpr uint64_t kQMask = (1ull << kQTagShift) - 1;
+
+__device__ __forceinline__ uint64_t qtag_of(int64_t r) { return (uint64_t)(1 + r % 3) << kQTagShift; }
+
+__device__ __forceinline__ uint64_t read_q(const uint64_t *w, uint64_t tag, unsigned *abort_flag, bool &bad) {
+    uint64_t v = __hip_atomic_load(w, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    uint32_t spins = 0;
+    while ((v & ~kQMask) != tag) {
+        __builtin_amdgcn_s_sleep(1);
+        if ((++spins & 63) == 0 &&
+            (spins > kSpinLimit || __hip_atomic_load(abort_flag, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT))) {
+            __hip_atomic_store(abort_flag, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            bad = true;
+            return 0;
+        }
+        v = __hip_atomic_load(w, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    }
+    return v & kQMask;
+}
+
+__device__ __forceinline__ float read_x(const uint64_t *w, uint32_t tag, unsigned *abort_flag, bool &bad) {
+    uint64_t v = __hip_atomic_load(w, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    uint32_t spins = 0;
+    while ((uint32_t)(v >> 32) != tag) {
+        __builtin_amdgcn_s_sleep(1);
+        if ((++spins & 63) == 0 &&
+            (spins > kSpinLimit || __hip_atomic_load(abort_flag, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT))) {
+            __hip_atomic_store(abort_flag, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            bad = true;
+            return 0.0f;
+        }
+        v = __hip_atomic_load(w, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    }
+    return __uint_as_float((uint32_t)v);
+}
+
+// Ancestor of the slot with threshold tau over the whole population: the
+// last a with X_a <= tau, where X_a = tile_pre[b] + x_a is the exclusive
+// prefix of q before a (x_a tile-local, tagged in device memory; tile ends
+// and exclusive tile prefixes are in LDS).  This is min{a : Q_a > tau} for the
+// inclusive prefix Q: a particle of zero weight shares its prefix with the
+// next one.  lo_bound (the previous slot's ancestor, or -1) has X <= tau.
 __device__ __forceinline__ int find_ancestor_global(uint64_t tau, int64_t N, int nb, int tile, const uint64_t *tile_end,
-                                                    const uint64_t *tile_pre, const uint64_t *__restrict__ qloc,
-                                                    int lo_bound) {
+                                                    const uint64_t *tile_pre, const uint64_t *qt, uint64_t tag,
+                                                    int lo_bound, unsigned *abort_flag, bool &bad) {
     int lo = lo_bound < 0 ? 0 : lo_bound / tile, hi = nb - 1;
     while (lo < hi) {
         const int mid = (lo + hi) >> 1;
         if (tile_end[mid] > tau) hi = mid; else lo = mid + 1;
     }
     const uint64_t pre = tile_pre[lo];
-    int a0 = lo * tile, a1 = a0 + tile - 1;
-    if (a1 > (int)N - 1) a1 = (int)N - 1;
+    // X of the tile's first particle is tile_pre[lo] <= tau (tile lo is the first
+    // whose end exceeds tau), so the answer is in [a0, a1): search for the first
+    // index after a0 whose prefix exceeds tau
+    int a0 = lo * tile;
+    const int a1 = (int)min((int64_t)a0 + tile, N);
     if (lo_bound > a0) a0 = lo_bound;
-    while (a0 < a1) {
-        const int mid = (a0 + a1) >> 1;
-        if (pre + qloc[mid] > tau) a1 = mid; else a0 = mid + 1;
+    int l = a0 + 1, h = a1;
+    while (l < h) {
+        const int mid = (l + h) >> 1;
+        if (pre + read_q(qt + mid, tag, abort_flag, bad) > tau) h = mid; else l = mid + 1;
     }
-    return a0;
+    return l - 1;
 }
 
 // ---------------------------------------------------------------- kernel --
@@ -479,16 +544,25 @@ __global__ __launch_bounds__(kSmcThreads) void smc_persistent_kernel(SmcDev a) {
     __shared__ float ybuf[kYChunk];
     __shared__ int s_rng[2];
     __shared__ int s_cnt[kSmcWaves];
-    // dynamic LDS: tile_end[nb] | tile_pre[nb] | stage[stage_cap] (u64) | s_anc[kSmcThreads P] (i32)
+    // dynamic LDS: tile_end[nb] | tile_pre[nb] | stage[stage_cap] | own_q[kTile] (u64) |
+    // s_anc[kTile] (i32) | own_x[kTile] (FP32, one-field models only)
+    constexpr int kTile = kSmcThreads * P;
+    constexpr bool kOwnX = M::NF == 1;
     extern __shared__ uint64_t dyn[];
     const int nb = gridDim.x;
     uint64_t *tile_end = dyn;
     uint64_t *tile_pre = dyn + nb;
     uint64_t *stage = dyn + 2 * nb;
-    int32_t *s_anc = (int32_t *)(dyn + 2 * nb + a.stage_cap);
+    uint64_t *own_q = dyn + 2 * nb + a.stage_cap;
+    int32_t *s_anc = (int32_t *)(own_q + kTile);
+    float *own_x = (float *)(s_anc + kTile);
 
     const int64_t N = a.N;
-    constexpr int kTile = kSmcThreads * P;
+    const int64_t tile0 = (int64_t)blockIdx.x * kTile;                 // this block's first slot
+    const int tlen = (int)min((int64_t)kTile, N - tile0);               // and its slot count
+    // tagged prefix words loaded per round: all of them for the one-field model,
+    // fewer beside a larger particle state
+    constexpr int kLoadBatch = M::NF > 2 ? 4 : 16;
     const int64_t base = (int64_t)blockIdx.x * kTile + (int64_t)threadIdx.x * P;
 
     float st[P][M::NF];
@@ -565,16 +639,16 @@ __global__ __launch_bounds__(kSmcThreads) void smc_persistent_kernel(SmcDev a) {
         }
         double s1b = s1l, s2b = s2l;
         block_sum2_f64(s1b, s2b, ldsd);
-        uint64_t rr[3];
-        if (!record_barrier(a.rec, a.bar, ++epoch, nb, (uint64_t)__float_as_uint(mb), dbits(s1b), dbits(s2b), rr,
-                            false)) {
+        uint32_t rt[5];
+        if (!tagged_barrier<5>(a.rec, a.bar, ++epoch, nb,
+                               {__float_as_uint(mb), hi32(s1b), lo32(s1b), hi32(s2b), lo32(s2b)}, rt)) {
             alive = false;
             break;
         }
         float Mg;
         double S1, S2;
-        merge_partials(threadIdx.x < nb ? __uint_as_float((uint32_t)rr[0]) : -INFINITY, dval(rr[1]), dval(rr[2]),
-                       ldsf, ldsd, Mg, S1, S2);
+        merge_partials(threadIdx.x < nb ? __uint_as_float(rt[0]) : -INFINITY, from32(rt[1], rt[2]),
+                       from32(rt[3], rt[4]), ldsf, ldsd, Mg, S1, S2);
         Mlast = Mg;
         if (!(Mg > -INFINITY)) { status = PPL_E_ZERO_WEIGHT; break; }
         if (!(S1 > 0.0) || isnan(S1) || isnan(S2)) { status = PPL_E_NONFINITE; break; }
@@ -593,33 +667,62 @@ __global__ __launch_bounds__(kSmcThreads) void smc_persistent_kernel(SmcDev a) {
         }
 
         // ---- resampling: FP64 weights, normaliser, integer quantisation, tile scan
-        uint64_t q[P];
+        uint64_t qx[P];          // exclusive prefixes within the thread
         uint64_t run = 0;
         double esl = 0.0;
 #pragma unroll
         for (int p = 0; p < P; ++p) {
             const double e = valid[p] ? exp_f64((double)lw[p] - (double)Mg) : 0.0;
             esl += e;
+            qx[p] = run;
             run += (uint64_t)floor(ldexp(e, a.kbits));
-            q[p] = run;
         }
         uint64_t btot;
         const uint64_t off = block_exclusive_scan_u64(run, ldsu, btot);
         const double eb = block_sum_f64(esl, ldsd);
+        const uint64_t qtag = qtag_of(nres);
+        const uint32_t xtag = (uint32_t)(nres + 1);
+        // The tile's prefix sums (and a one-field state) go to LDS, where this
+        // block reads its own ancestors, and from there to memory with
+        // coalesced stores (whole lines; the particle-major layout of the
+        // registers would scatter each store over a wave's 64 particles).
 #pragma unroll
         for (int p = 0; p < P; ++p) {
-            if (valid[p]) {
-                a.qloc[jb + p] = off + q[p];
+            own_q[threadIdx.x * P + p] = off + qx[p];
+            if constexpr (kOwnX) own_x[threadIdx.x * P + p] = st[p][0];
+        }
+        if constexpr (!kOwnX) {
 #pragma unroll
-                for (int f = 0; f < M::NF; ++f) a.xbuf[(size_t)f * N + jb + p] = st[p][f];
+            for (int p = 0; p < P; ++p) {
+                if (valid[p]) {
+#pragma unroll
+                    for (int f = 0; f < M::NF; ++f)
+                        __hip_atomic_store(a.xtag + (size_t)f * N + jb + p,
+                                           ((uint64_t)xtag << 32) | __float_as_uint(st[p][f]), __ATOMIC_RELAXED,
+                                           __HIP_MEMORY_SCOPE_AGENT);
+                }
             }
         }
-        if (!record_barrier(a.rec, a.bar, ++epoch, nb, btot, dbits(eb), 0, rr, true)) { alive = false; break; }
+        __syncthreads();
+        for (int i = threadIdx.x; i < tlen; i += kSmcThreads) {
+            __hip_atomic_store(a.qtag + tile0 + i, qtag | own_q[i], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            if constexpr (kOwnX)
+                __hip_atomic_store(a.xtag + tile0 + i, ((uint64_t)xtag << 32) | __float_as_uint(own_x[i]),
+                                   __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        }
+        uint32_t rq[4];
+        if (!tagged_barrier<4>(a.rec, a.bar, ++epoch, nb,
+                               {(uint32_t)(btot >> 32), (uint32_t)btot, hi32(eb), lo32(eb)}, rq)) {
+            alive = false;
+            break;
+        }
+        unsigned *abort_flag = a.bar + 1;
+        bool bad = false;
 
         // tile prefixes (LDS) and the normaliser sum, in the same order in every block
         {
-            const uint64_t v = threadIdx.x < nb ? rr[0] : 0;
-            const double ev0 = threadIdx.x < nb ? dval(rr[1]) : 0.0;
+            const uint64_t v = threadIdx.x < nb ? ((uint64_t)rq[0] << 32) | rq[1] : 0;
+            const double ev0 = threadIdx.x < nb ? from32(rq[2], rq[3]) : 0.0;
             uint64_t S;
             const uint64_t ex = block_exclusive_scan_u64(v, ldsu, S);
             if (threadIdx.x < nb) {
@@ -638,9 +741,10 @@ __global__ __launch_bounds__(kSmcThreads) void smc_persistent_kernel(SmcDev a) {
 
             // ancestor range of this block's slots: the first and last slot's
             // ancestors, each found by half of the block.  The ancestor's tile
-            // is the first with tile_end > tau (LDS); within it the prefix sums
-            // are non-decreasing, so the ancestor's offset is the number of
-            // entries <= tau, counted with one round of independent loads.
+            // is the first with tile_end > tau (LDS); within it the exclusive
+            // prefix sums are non-decreasing and the first is <= tau, so the
+            // ancestor's offset is the number of entries <= tau, less one,
+            // counted with one round of independent loads.
             const int js0 = blockIdx.x * kTile;
             const int js1 = (int)min((int64_t)js0 + kTile, N) - 1;
             {
@@ -657,8 +761,35 @@ __global__ __launch_bounds__(kSmcThreads) void smc_persistent_kernel(SmcDev a) {
                 const int64_t tb = (int64_t)lo * kTile;
                 const int len = (int)min((int64_t)kTile, N - tb);
                 const uint64_t pre = tile_pre[lo];
+                // all loads first (clamped in range), then the count; a word that
+                // is not yet current sends the thread through the polling reads
+                constexpr int kPer = kTile / kHalf;
                 int cnt = 0;
-                for (int i = hl; i < len; i += kHalf) cnt += (pre + a.qloc[tb + i] <= tau) ? 1 : 0;
+                bool fresh = true;
+                if (lo == (int)blockIdx.x) {       // this block's own tile: its prefix sums are in LDS
+                    for (int i = hl; i < len; i += kHalf) cnt += (pre + own_q[i] <= tau) ? 1 : 0;
+                } else {
+#pragma unroll
+                for (int k0 = 0; k0 < kPer; k0 += kLoadBatch) {
+                    uint64_t v[kLoadBatch];
+#pragma unroll
+                    for (int k = 0; k < kLoadBatch; ++k)
+                        v[k] = __hip_atomic_load(a.qtag + tb + min(hl + (k0 + k) * kHalf, len - 1), __ATOMIC_RELAXED,
+                                                 __HIP_MEMORY_SCOPE_AGENT);
+#pragma unroll
+                    for (int k = 0; k < kLoadBatch; ++k) {
+                        if (k0 + k < kPer && hl + (k0 + k) * kHalf < len) {
+                            fresh = fresh && (v[k] & ~kQMask) == qtag;
+                            cnt += (pre + (v[k] & kQMask) <= tau) ? 1 : 0;
+                        }
+                    }
+                }
+                }
+                if (!fresh) {
+                    cnt = 0;
+                    for (int i = hl; i < len; i += kHalf)
+                        cnt += (pre + read_q(a.qtag + tb + i, qtag, abort_flag, bad) <= tau) ? 1 : 0;
+                }
 #pragma unroll
                 for (int o = 32; o > 0; o >>= 1) cnt += __shfl_xor(cnt, o, 64);
                 if ((threadIdx.x & 63) == 0) s_cnt[threadIdx.x >> 6] = cnt;
@@ -666,17 +797,43 @@ __global__ __launch_bounds__(kSmcThreads) void smc_persistent_kernel(SmcDev a) {
                 if (hl == 0) {
                     int c = 0;
                     for (int w = 0; w < kSmcWaves / 2; ++w) c += s_cnt[half * (kSmcWaves / 2) + w];
-                    s_rng[half] = (int)(tb + c);
+                    s_rng[half] = (int)(tb + c - 1);
                 }
             }
             __syncthreads();
             const int a_lo = s_rng[0], a_hi = s_rng[1];
             const int span = a_hi - a_lo + 1;
-            const bool staged = span <= a.stage_cap;
+            const bool staged = span >= 1 && span <= a.stage_cap;
             if (staged) {
-                for (int i = threadIdx.x; i < span; i += kSmcThreads) {
-                    const int aa = a_lo + i;
-                    stage[i] = tile_pre[aa / kTile] + a.qloc[aa];
+                constexpr int kPer = kStage / kSmcThreads;
+                bool fresh = true;
+#pragma unroll
+                for (int k0 = 0; k0 < kPer; k0 += kLoadBatch) {
+                    uint64_t v[kLoadBatch];
+#pragma unroll
+                    for (int k = 0; k < kLoadBatch; ++k) {
+                        const int aa = a_lo + min((int)threadIdx.x + (k0 + k) * kSmcThreads, span - 1);
+                        v[k] = (uint64_t)(aa - tile0) < (uint64_t)tlen
+                                   ? qtag | own_q[aa - tile0]
+                                   : __hip_atomic_load(a.qtag + aa, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                    }
+#pragma unroll
+                    for (int k = 0; k < kLoadBatch; ++k) {
+                        const int i = threadIdx.x + (k0 + k) * kSmcThreads;
+                        if (k0 + k < kPer && i < span) {
+                            fresh = fresh && (v[k] & ~kQMask) == qtag;
+                            stage[i] = tile_pre[(a_lo + i) / kTile] + (v[k] & kQMask);
+                        }
+                    }
+                }
+                if (!fresh) {
+                    for (int i = threadIdx.x; i < span; i += kSmcThreads) {
+                        const int aa = a_lo + i;
+                        const uint64_t x = (uint64_t)(aa - tile0) < (uint64_t)tlen
+                                               ? own_q[aa - tile0]
+                                               : read_q(a.qtag + aa, qtag, abort_flag, bad);
+                        stage[i] = tile_pre[aa / kTile] + x;
+                    }
                 }
             }
             __syncthreads();
@@ -692,12 +849,14 @@ __global__ __launch_bounds__(kSmcThreads) void smc_persistent_kernel(SmcDev a) {
                 const uint64_t tau = (uint64_t)j * Sq + th.quo;
                 int anc;
                 if (staged) {
-                    // The thread's first slot searches the whole staged range.  Later
-                    // slots gallop from the previous slot's ancestor (ancestors do
-                    // not decrease with the slot and are usually a few entries
-                    // apart) and finish with a binary search: the same index as a
-                    // plain binary search, with fewer dependent LDS loads.
-                    int lo = prev - a_lo, hi = span - 1;
+                    // The ancestor is the last staged entry <= tau: one before the
+                    // first entry > tau (span if none), searched after the previous
+                    // slot's ancestor (whose entry is <= tau; a_lo for the first
+                    // slot).  Later slots gallop from there (ancestors do not
+                    // decrease with the slot and are usually a few entries apart)
+                    // and finish with a binary search: the same index as a plain
+                    // binary search, with fewer dependent LDS loads.
+                    int lo = prev - a_lo + 1, hi = span;
                     if (p > 0 && lo < hi) {
                         if (stage[lo] > tau) {
                             hi = lo;
@@ -715,9 +874,10 @@ __global__ __launch_bounds__(kSmcThreads) void smc_persistent_kernel(SmcDev a) {
                         const int mid = (lo + hi) >> 1;
                         if (stage[mid] > tau) hi = mid; else lo = mid + 1;
                     }
-                    anc = a_lo + lo;
+                    anc = a_lo + lo - 1;
                 } else {
-                    anc = find_ancestor_global(tau, N, nb, kTile, tile_end, tile_pre, a.qloc, prev);
+                    anc = find_ancestor_global(tau, N, nb, kTile, tile_end, tile_pre, a.qtag, qtag, prev, abort_flag,
+                                               bad);
                 }
                 s_anc[threadIdx.x * P + p] = anc;
                 if (anc_row) anc_row[j] = anc;
@@ -725,15 +885,37 @@ __global__ __launch_bounds__(kSmcThreads) void smc_persistent_kernel(SmcDev a) {
             }
         }
         if constexpr (!MOVES) {
-            // gather the ancestors' state
+            // gather the ancestors' state: all loads first, then the tags; a word
+            // that is not yet current sends the thread through the polling reads
+            bool fresh = true;
 #pragma unroll
             for (int p = 0; p < P; ++p) {
                 if (!valid[p]) continue;
                 const int anc = s_anc[threadIdx.x * P + p];
+                if (kOwnX && (uint64_t)(anc - tile0) < (uint64_t)tlen) {
+                    st[p][0] = own_x[anc - tile0];      // an ancestor of this block's own tile
+                } else {
 #pragma unroll
-                for (int f = 0; f < M::NF; ++f) st[p][f] = a.xbuf[(size_t)f * N + anc];
+                    for (int f = 0; f < M::NF; ++f) {
+                        const uint64_t v = __hip_atomic_load(a.xtag + (size_t)f * N + anc, __ATOMIC_RELAXED,
+                                                             __HIP_MEMORY_SCOPE_AGENT);
+                        fresh = fresh && (uint32_t)(v >> 32) == xtag;
+                        st[p][f] = __uint_as_float((uint32_t)v);
+                    }
+                }
                 lw[p] = 0.0f;
                 lwc[p] = 0.0f;
+            }
+            if (!fresh) {
+#pragma unroll
+                for (int p = 0; p < P; ++p) {
+                    if (!valid[p]) continue;
+                    const int anc = s_anc[threadIdx.x * P + p];
+                    if (kOwnX && (uint64_t)(anc - tile0) < (uint64_t)tlen) continue;
+#pragma unroll
+                    for (int f = 0; f < M::NF; ++f)
+                        st[p][f] = read_x(a.xtag + (size_t)f * N + anc, xtag, abort_flag, bad);
+                }
             }
         } else {
             // resample-move: the gathered particles go through memory one at a
@@ -743,7 +925,8 @@ __global__ __launch_bounds__(kSmcThreads) void smc_persistent_kernel(SmcDev a) {
                 if (!valid[p]) continue;
                 const int anc = s_anc[threadIdx.x * P + p];
 #pragma unroll
-                for (int f = 0; f < M::NF; ++f) a.xbuf2[(size_t)f * N + jb + p] = a.xbuf[(size_t)f * N + anc];
+                for (int f = 0; f < M::NF; ++f)
+                    a.xbuf2[(size_t)f * N + jb + p] = read_x(a.xtag + (size_t)f * N + anc, xtag, abort_flag, bad);
                 lw[p] = 0.0f;
                 lwc[p] = 0.0f;
             }
@@ -761,6 +944,7 @@ __global__ __launch_bounds__(kSmcThreads) void smc_persistent_kernel(SmcDev a) {
                 for (int f = 0; f < M::NF; ++f) st[p][f] = valid[p] ? a.xbuf2[(size_t)f * N + jb + p] : 0.0f;
             }
         }
+        if (__syncthreads_or(bad ? 1 : 0)) { alive = false; break; }   // a tagged read gave up
     }
 
     // ---- stop: the run's state into the checkpoint
@@ -799,12 +983,12 @@ __global__ __launch_bounds__(kSmcThreads) void smc_persistent_kernel(SmcDev a) {
             }
         }
         block_sum2_f64(e1, e2, ldsd);
-        uint64_t rr[3];
-        if (!record_barrier(a.rec, a.bar, ++epoch, nb, dbits(e1), dbits(e2), 0, rr, false)) {
+        uint32_t rt[4];
+        if (!tagged_barrier<4>(a.rec, a.bar, ++epoch, nb, {hi32(e1), lo32(e1), hi32(e2), lo32(e2)}, rt)) {
             alive = false;
         } else {
-            double t1 = threadIdx.x < nb ? dval(rr[0]) : 0.0;
-            double t2 = threadIdx.x < nb ? dval(rr[1]) : 0.0;
+            double t1 = threadIdx.x < nb ? from32(rt[0], rt[1]) : 0.0;
+            double t2 = threadIdx.x < nb ? from32(rt[2], rt[3]) : 0.0;
             block_sum2_f64(t1, t2, ldsd);
             const double inc = (double)Mlast + log_f64(t1) - logN;
             logz += inc;
@@ -838,9 +1022,11 @@ __global__ __launch_bounds__(kSmcThreads) void smc_persistent_kernel(SmcDev a) {
 
 // Clears the abort flag and the record lines' epochs (a fill kernel, so the
 // launch sequence stays capturable).
-__global__ void smc_reset_kernel(unsigned *bar, uint64_t *rec, int n_lines) {
-    for (int i = threadIdx.x; i < kBarWords; i += blockDim.x) bar[i] = 0u;
-    for (int i = threadIdx.x; i < n_lines * kRecWords; i += blockDim.x) rec[i] = 0u;
+__global__ void smc_reset_kernel(unsigned *bar, uint64_t *rec, int n_lines, uint64_t *tagged, int64_t n_tagged) {
+    const int64_t i0 = (int64_t)blockIdx.x * blockDim.x + threadIdx.x, stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t i = i0; i < kBarWords; i += stride) bar[i] = 0u;
+    for (int64_t i = i0; i < (int64_t)n_lines * kRecWords; i += stride) rec[i] = 0u;
+    for (int64_t i = i0; i < n_tagged; i += stride) tagged[i] = 0u;
 }
 
 // ------------------------------------------------------------------ host --
@@ -857,8 +1043,8 @@ static int64_t smc_blocks(int64_t N, int P) { return (N + (int64_t)kSmcThreads *
 struct SmcLayout {
     double *scal;
     unsigned *bar;
-    uint64_t *rec, *qloc;
-    float *xbuf, *xbuf2;
+    uint64_t *rec, *qtag, *xtag;     // qtag and xtag adjacent: [N] then [NF][N]
+    float *xbuf2;
     size_t bytes;
 };
 
@@ -870,8 +1056,8 @@ static SmcLayout smc_layout(void *ws, int NF, int64_t N, int64_t nb) {
     L.scal = (double *)take(8 * sizeof(double));
     L.bar = (unsigned *)take(kBarWords * sizeof(unsigned));
     L.rec = (uint64_t *)take((size_t)2 * nb * kRecWords * sizeof(uint64_t));
-    L.qloc = (uint64_t *)take(N * sizeof(uint64_t));
-    L.xbuf = (float *)take((size_t)NF * N * sizeof(float));
+    L.qtag = (uint64_t *)take((size_t)(NF + 1) * N * sizeof(uint64_t));
+    L.xtag = L.qtag + N;
     L.xbuf2 = NF > 1 ? (float *)take((size_t)NF * N * sizeof(float)) : nullptr;   // mixture models only
     L.bytes = o;
     return L;
@@ -899,14 +1085,22 @@ static int launch(SmcDev &d, int64_t nb, hipStream_t st) {
     // stage as many prefix sums as the per-block LDS limit leaves room for (<= kStage)
     int max_lds = 0;
     PPL_HIP(hipDeviceGetAttribute(&max_lds, hipDeviceAttributeMaxSharedMemoryPerBlock, dev));
-    const int64_t fixed = (int64_t)2 * nb * sizeof(uint64_t) + (int64_t)kSmcThreads * P * sizeof(int32_t) +
+    const int64_t tile = (int64_t)kSmcThreads * P;
+    const int64_t own_x = M::NF == 1 ? tile * (int64_t)sizeof(float) : 0;
+    const int64_t fixed = (int64_t)(2 * nb + tile) * sizeof(uint64_t) + tile * (int64_t)sizeof(int32_t) + own_x +
                           (int64_t)kYChunk * sizeof(float) + 1024;      // + static LDS of the kernel
     d.stage_cap = (int)std::max<int64_t>(0, std::min<int64_t>(kStage, (max_lds - fixed) / 8));
-    const size_t lds = (size_t)(2 * nb + d.stage_cap) * sizeof(uint64_t) + (size_t)kSmcThreads * P * sizeof(int32_t);
+    const size_t lds = (size_t)(2 * nb + d.stage_cap + tile) * sizeof(uint64_t) + (size_t)tile * sizeof(int32_t) +
+                       (size_t)own_x;
     PPL_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, kern, kSmcThreads, lds));
     if ((int64_t)occ * ncu < nb)
         return fail(PPL_E_UNSUPPORTED, "SMC needs %lld co-resident blocks, device holds %d", (long long)nb, occ * ncu);
-    hipLaunchKernelGGL(smc_reset_kernel, dim3(1), dim3(256), 0, st, d.bar, d.rec, (int)(2 * nb));
+    // clears the barrier words, the record lines and the tagged resampling data
+    // (so no word of an earlier call carries a tag this call looks for)
+    const int64_t n_tagged = (int64_t)(d.xtag - d.qtag) + (int64_t)M::NF * d.N;
+    const int reset_blocks = (int)std::min<int64_t>(1024, std::max<int64_t>(1, (n_tagged + 255) / 256));
+    hipLaunchKernelGGL(smc_reset_kernel, dim3(reset_blocks), dim3(256), 0, st, d.bar, d.rec, (int)(2 * nb), d.qtag,
+                       n_tagged);
     PPL_LAUNCH_CHECK("smc_reset_kernel");
     void *args[] = {&d};
     KernelTimer timer("smc_persistent_kernel", st);
@@ -971,8 +1165,8 @@ int run_smc(const SmcArgs &a, hipStream_t st) {
     d.hyp64[1] = a.hyper[1];
     d.bar = L.bar;
     d.rec = L.rec;
-    d.qloc = L.qloc;
-    d.xbuf = L.xbuf;
+    d.qtag = L.qtag;
+    d.xtag = L.xtag;
     d.xbuf2 = L.xbuf2;
     if (a.model == PPL_MODEL_LGSSM) return launch_p<Lgssm>(d, P, nb, st);
     switch (a.K) {
