@@ -839,49 +839,84 @@ __global__ __launch_bounds__(kSmcThreads) void smc_persistent_kernel(SmcDev a) {
             __syncthreads();
 
             int32_t *anc_row = (a.anc_out && nres - 1 < a.max_events) ? a.anc_out + (size_t)(nres - 1) * N : nullptr;
-            int prev = a_lo;
-            SlotThreshold th = slot_threshold((uint32_t)jb, Sr, U, NN);
-#pragma unroll 1
-            for (int p = 0; p < P; ++p) {
-                const int j = jb + p;
-                if (j >= N) break;
-                if (p) slot_threshold_next(th, Sr, NN);
-                const uint64_t tau = (uint64_t)j * Sq + th.quo;
-                int anc;
+            if (jb < N) {
+                SlotThreshold th = slot_threshold((uint32_t)jb, Sr, U, NN);
                 if (staged) {
-                    // The ancestor is the last staged entry <= tau: one before the
-                    // first entry > tau (span if none), searched after the previous
-                    // slot's ancestor (whose entry is <= tau; a_lo for the first
-                    // slot).  Later slots gallop from there (ancestors do not
-                    // decrease with the slot and are usually a few entries apart)
-                    // and finish with a binary search: the same index as a plain
-                    // binary search, with fewer dependent LDS loads.
-                    int lo = prev - a_lo + 1, hi = span;
-                    if (p > 0 && lo < hi) {
-                        if (stage[lo] > tau) {
-                            hi = lo;
-                        } else {
-                            int step = 1;
-                            while (lo + step < hi && !(stage[lo + step] > tau)) {
-                                lo += step;
-                                step <<= 1;
-                            }
-                            hi = min(lo + step, hi);
-                            ++lo;
+                    // Each ancestor is the last staged entry <= its slot's tau:
+                    // one before the first entry > tau (span if none).  The
+                    // thread's first slot binary-searches the stage (entry 0, the
+                    // block's first ancestor, is <= tau); later slots count the
+                    // entries <= tau among the kWin after the first slot's
+                    // ancestor, held in registers (one round of LDS loads for all
+                    // slots), and past that window gallop from the previous slot's
+                    // ancestor (whose entry is <= tau) and finish with a binary
+                    // search.
+                    constexpr int kWin = 16;
+                    int lo = 1, hi = span;
+                    {
+                        const uint64_t tau0 = (uint64_t)jb * Sq + th.quo;
+                        while (lo < hi) {
+                            const int mid = (lo + hi) >> 1;
+                            if (stage[mid] > tau0) hi = mid; else lo = mid + 1;
                         }
                     }
-                    while (lo < hi) {
-                        const int mid = (lo + hi) >> 1;
-                        if (stage[mid] > tau) hi = mid; else lo = mid + 1;
+                    const int pos0 = lo - 1;
+                    uint64_t win[kWin];
+#pragma unroll
+                    for (int k = 0; k < kWin; ++k) win[k] = pos0 + 1 + k < span ? stage[pos0 + 1 + k] : ~0ull;
+                    int prev = pos0;
+#pragma unroll 1
+                    for (int p = 0; p < P; ++p) {
+                        const int j = jb + p;
+                        if (j >= N) break;
+                        if (p) slot_threshold_next(th, Sr, NN);
+                        const uint64_t tau = (uint64_t)j * Sq + th.quo;
+                        int c = 0;
+#pragma unroll
+                        for (int k = 0; k < kWin; ++k) c += win[k] <= tau ? 1 : 0;
+                        int idx;
+                        if (c < kWin) {
+                            idx = pos0 + c;
+                        } else {
+                            int l = prev + 1, h = span;
+                            if (l < h) {
+                                if (stage[l] > tau) {
+                                    h = l;
+                                } else {
+                                    int step = 1;
+                                    while (l + step < h && !(stage[l + step] > tau)) {
+                                        l += step;
+                                        step <<= 1;
+                                    }
+                                    h = min(l + step, h);
+                                    ++l;
+                                }
+                            }
+                            while (l < h) {
+                                const int mid = (l + h) >> 1;
+                                if (stage[mid] > tau) h = mid; else l = mid + 1;
+                            }
+                            idx = l - 1;
+                        }
+                        s_anc[threadIdx.x * P + p] = a_lo + idx;
+                        if (anc_row) anc_row[j] = a_lo + idx;
+                        prev = idx;
                     }
-                    anc = a_lo + lo - 1;
                 } else {
-                    anc = find_ancestor_global(tau, N, nb, kTile, tile_end, tile_pre, a.qtag, qtag, prev, abort_flag,
-                                               bad);
+                    int prev = a_lo;
+#pragma unroll 1
+                    for (int p = 0; p < P; ++p) {
+                        const int j = jb + p;
+                        if (j >= N) break;
+                        if (p) slot_threshold_next(th, Sr, NN);
+                        const uint64_t tau = (uint64_t)j * Sq + th.quo;
+                        const int anc = find_ancestor_global(tau, N, nb, kTile, tile_end, tile_pre, a.qtag, qtag, prev,
+                                                             abort_flag, bad);
+                        s_anc[threadIdx.x * P + p] = anc;
+                        if (anc_row) anc_row[j] = anc;
+                        prev = anc;
+                    }
                 }
-                s_anc[threadIdx.x * P + p] = anc;
-                if (anc_row) anc_row[j] = anc;
-                prev = anc;
             }
         }
         if constexpr (!MOVES) {
