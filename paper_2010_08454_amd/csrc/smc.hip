@@ -36,6 +36,7 @@
 // and every block leaves its loop at its next barrier, so the grid always
 // drains.
 #include <math.h>
+#include <stdlib.h>
 #include <string.h>
 
 #include <algorithm>
@@ -83,6 +84,7 @@ struct SmcDev {
     int move_steps;          // resample-move steps per particle after each resampling
     double move_lam;         // random-walk scale factor
     double hyp64[2];         // GMM {mu_sd, comp_sd} in FP64 (move scales)
+    int poll_all;            // 1: every tagged read takes the polling path (a checking aid)
     // workspace
     unsigned *bar;           // [1] abort flag
     uint64_t *rec;           // [2][nb][16] record lines: word 0 the epoch, words 1..3 the record
@@ -765,7 +767,7 @@ __global__ __launch_bounds__(kSmcThreads) void smc_persistent_kernel(SmcDev a) {
                 // is not yet current sends the thread through the polling reads
                 constexpr int kPer = kTile / kHalf;
                 int cnt = 0;
-                bool fresh = true;
+                bool fresh = !a.poll_all;
                 if (lo == (int)blockIdx.x) {       // this block's own tile: its prefix sums are in LDS
                     for (int i = hl; i < len; i += kHalf) cnt += (pre + own_q[i] <= tau) ? 1 : 0;
                 } else {
@@ -806,7 +808,7 @@ __global__ __launch_bounds__(kSmcThreads) void smc_persistent_kernel(SmcDev a) {
             const bool staged = span >= 1 && span <= a.stage_cap;
             if (staged) {
                 constexpr int kPer = kStage / kSmcThreads;
-                bool fresh = true;
+                bool fresh = !a.poll_all;
 #pragma unroll
                 for (int k0 = 0; k0 < kPer; k0 += kLoadBatch) {
                     uint64_t v[kLoadBatch];
@@ -922,7 +924,7 @@ __global__ __launch_bounds__(kSmcThreads) void smc_persistent_kernel(SmcDev a) {
         if constexpr (!MOVES) {
             // gather the ancestors' state: all loads first, then the tags; a word
             // that is not yet current sends the thread through the polling reads
-            bool fresh = true;
+            bool fresh = !a.poll_all;
 #pragma unroll
             for (int p = 0; p < P; ++p) {
                 if (!valid[p]) continue;
@@ -1195,6 +1197,12 @@ int run_smc(const SmcArgs &a, hipStream_t st) {
     d.t1 = a.t_end;
     d.ckpt = (char *)a.ckpt;
     d.move_steps = a.move_steps;
+    // PPL_SMC_POLL_ALL=1 sends every tagged read through the polling path
+    // (checking aid: the results must not change)
+    {
+        const char *e = getenv("PPL_SMC_POLL_ALL");
+        d.poll_all = (e && e[0] == '1') ? 1 : 0;
+    }
     d.move_lam = a.move_scale > 0.0 ? a.move_scale : 2.38 / sqrt(2.0 * a.K - 1.0);
     d.hyp64[0] = a.hyper[0];
     d.hyp64[1] = a.hyper[1];

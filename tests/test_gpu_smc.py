@@ -276,3 +276,28 @@ def test_gmm_resample_move_keeps_particles_distinct(ppl):
     d_plain = np.unique(plain["state"][4]).size
     d_moved = np.unique(moved["state"][4]).size
     assert d_moved > 100 * d_plain and d_moved > n // 4, (d_plain, d_moved)
+
+
+@pytest.mark.parametrize("model,K,n,T", [("lgssm", 0, (1 << 20) - 5, 60), ("lgssm", 0, 3000, 80),
+                                         ("gmm", 5, (1 << 17) + 3, 60)])
+def test_tagged_polling_path_gives_the_same_results(ppl, monkeypatch, model, K, n, T):
+    """Every word the blocks publish for each other carries its epoch or event
+    tag; a reader that finds an older tag polls the word again.  With
+    PPL_SMC_POLL_ALL=1 every tagged read takes that polling path: the run must
+    be bitwise the same (eight particles per lane at 2^20 - 5, one per lane at
+    3000, the mixture state at 2^17 + 3)."""
+    print(f"tagged polling path {model} n={n}", flush=True)
+    if model == "lgssm":
+        y, mid = synthetic.lgssm_data(T=T), ppl.PPL_MODEL_LGSSM
+    else:
+        inst = synthetic.gmm_instances(1, seed=7, d_lo=math.log10(T), d_hi=math.log10(T) + 1e-9, k_lo=K, k_hi=K)[0]
+        y, mid = inst["y"][:T], ppl.PPL_MODEL_GMM
+    monkeypatch.delenv("PPL_SMC_POLL_ALL", raising=False)
+    a = run_gpu(ppl, mid, y, n, 3, K=K, max_events=T)
+    monkeypatch.setenv("PPL_SMC_POLL_ALL", "1")
+    b = run_gpu(ppl, mid, y, n, 3, K=K, max_events=T)
+    monkeypatch.delenv("PPL_SMC_POLL_ALL")
+    assert a["n_resample"] > 0
+    assert a["log_z"] == b["log_z"] and a["n_resample"] == b["n_resample"]
+    assert np.array_equal(a["ancestors"], b["ancestors"])
+    assert np.array_equal(a["lw"], b["lw"]) and np.array_equal(a["state"], b["state"])
