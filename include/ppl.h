@@ -268,7 +268,11 @@ int ppl_philox(uint64_t seed, uint32_t c1, uint32_t c2, uint32_t c3, int64_t n,
  * (t < T - 1) the particles are resampled with ppl_resample's rule when
  * ESS < ess_frac * N, and the epoch's normaliser LSE(lw) - log N is added to
  * log Z-hat in FP64; the final epoch's normaliser is added after the last
- * factor.  model: PPL_MODEL_LGSSM or PPL_MODEL_GMM.  ess_frac in [0, 1]. */
+ * factor.  model: PPL_MODEL_LGSSM or PPL_MODEL_GMM.  ess_frac in [0, 1].
+ * One workgroup per CU holds up to 4096 particles, so N is limited by the
+ * device (2^20 on 256 CUs; PPL_E_UNSUPPORTED beyond).  Checking aid: with the
+ * environment variable PPL_SMC_POLL_ALL=1 every read of another workgroup's
+ * tagged resampling words takes the polling path; the results do not change. */
 int ppl_smc(int model, const ppl_data *data, int64_t n_particles, uint64_t seed,
             double ess_frac, void *d_ws, size_t ws_bytes, void *stream, ppl_result *out);
 
