@@ -203,19 +203,41 @@ __device__ __forceinline__ void bt_init(uint32_t j, uint32_t c3, Key key, float 
     }
 }
 
-// log sum_k pi_k N(y; mu_k, sd), shifted by the largest term, for a
-// compile-time component count KK (fully unrolled: no per-component branch
-// and no padding of the term array).  The exponentials and the logarithm are
-// the hardware's (v_exp_f32 / v_log_f32, about 1 ulp); their error is far
-// below the FP32 rounding of the log-weight sum over the data.
+// log sum_k pi_k N(y; mu_k, sd) for a compile-time component count KK (fully
+// unrolled: no per-component branch and no padding of the term array).  The
+// exponentials and the logarithm are the hardware's (v_exp_f32 / v_log_f32,
+// about 1 ulp); their error is far below the FP32 rounding of the log-weight
+// sum over the data.
+// Every term t_k = log pi_k - r_k^2 / 2 is <= 0, so the plain sum of exp(t_k)
+// cannot overflow; it is used when it exceeds kBtTiny (then no term has lost
+// more than a few bits to underflow).  A datum far from every mean gives a
+// smaller sum, and the factor is then the sum shifted by its largest term.
+// Which form a particle takes depends on its own terms only.
+constexpr float kBtTiny = 1e-30f;
+
 template <int KK>
-__device__ __forceinline__ float bt_factor(const float *st, float inv_sd, float lconst, float ys) {
-    float t[KK];
+__device__ __forceinline__ void bt_terms(const float *st, float inv_sd, float ys, float (&t)[KK]) {
 #pragma unroll
     for (int k = 0; k < KK; ++k) {
         const float r = (ys - st[KK + k]) * inv_sd;
         t[k] = fmaf(-0.5f * r, r, st[k]);
     }
+}
+
+template <int KK>
+__device__ __forceinline__ float bt_plain_sum(const float *st, float inv_sd, float ys) {
+    float t[KK];
+    bt_terms<KK>(st, inv_sd, ys, t);
+    float s = 0.0f;
+#pragma unroll
+    for (int k = 0; k < KK; ++k) s += __expf(t[k]);
+    return s;
+}
+
+template <int KK>
+__device__ __forceinline__ float bt_shifted(const float *st, float inv_sd, float lconst, float ys) {
+    float t[KK];
+    bt_terms<KK>(st, inv_sd, ys, t);
     float mx = t[0];
 #pragma unroll
     for (int k = 1; k < KK; ++k) mx = fmaxf(mx, t[k]);
@@ -223,6 +245,35 @@ __device__ __forceinline__ float bt_factor(const float *st, float inv_sd, float 
 #pragma unroll
     for (int k = 0; k < KK; ++k) s += __expf(t[k] - mx);
     return lconst + mx + __logf(s);
+}
+
+template <int KK>
+__device__ __forceinline__ float bt_factor(const float *st, float inv_sd, float lconst, float ys) {
+    const float s = bt_plain_sum<KK>(st, inv_sd, ys);
+    return s > kBtTiny ? lconst + __logf(s) : bt_shifted<KK>(st, inv_sd, lconst, ys);
+}
+
+// The factors of a thread's P particles for one datum: the plain sums first
+// (no branch between the particles, so their arithmetic interleaves), then,
+// only if some lane of the wave has a small sum, the shifted form for the
+// particles that need it.  Each particle's value is bt_factor's.
+template <int P, int KK>
+__device__ __forceinline__ void bt_factors(const float (&st)[P][2 * KK], float inv_sd, float lconst, float ys,
+                                           float (&f)[P]) {
+    float s[P];
+    bool small = false;
+#pragma unroll
+    for (int p = 0; p < P; ++p) {
+        s[p] = bt_plain_sum<KK>(st[p], inv_sd, ys);
+        small = small || !(s[p] > kBtTiny);
+    }
+#pragma unroll
+    for (int p = 0; p < P; ++p) f[p] = lconst + __logf(s[p]);
+    if (__ballot(small)) {
+#pragma unroll
+        for (int p = 0; p < P; ++p)
+            if (!(s[p] > kBtTiny)) f[p] = bt_shifted<KK>(st[p], inv_sd, lconst, ys);
+    }
 }
 
 // ------------------------------------------------------- resample-move --
@@ -333,10 +384,11 @@ __device__ __forceinline__ void bt_block_factors(const float (&st)[P][2 * KK], c
         const float ys = ybuf[t];
         float ml = -INFINITY;
         int nan_seen = 0;
+        float f[P];
+        bt_factors<P, KK>(st, inv_sd, lconst, ys, f);
 #pragma unroll
         for (int p = 0; p < P; ++p) {
-            const float f = bt_factor<KK>(st[p], inv_sd, lconst, ys);
-            if (valid[p]) kahan_add(lw[p], lwc[p], f);
+            if (valid[p]) kahan_add(lw[p], lwc[p], f[p]);
             ml = fmaxf(ml, lw[p]);
             nan_seen |= isnan(lw[p]) ? 1 : 0;
         }
@@ -368,11 +420,11 @@ __device__ __forceinline__ void bt_block_redo(const float (&st)[P][2 * KK], cons
                                               const float *ybuf, int nt, float inv_sd, float lconst) {
     for (int t = 0; t < nt; ++t) {
         const float ys = ybuf[t];
+        float f[P];
+        bt_factors<P, KK>(st, inv_sd, lconst, ys, f);
 #pragma unroll
-        for (int p = 0; p < P; ++p) {
-            const float f = bt_factor<KK>(st[p], inv_sd, lconst, ys);
-            if (valid[p]) kahan_add(lw[p], lwc[p], f);
-        }
+        for (int p = 0; p < P; ++p)
+            if (valid[p]) kahan_add(lw[p], lwc[p], f[p]);
     }
 }
 
