@@ -528,7 +528,9 @@ void ppl_smc_tune_cache_clear(void);
 
 /* Bytes of one parameter block (device, caller-owned, 256-byte aligned): FP32
  * master weights and biases, Adam first and second moments, BF16 copies of
- * the weights in [out][in] and [in][out] layouts, and the Adam step count. */
+ * the weights in [out][in] and [in][out] layouts, the Adam step count, then
+ * the two BF16 layouts again in the order the fused training pass loads them
+ * (all copies written by ppl_proposal_init and every Adam step). */
 size_t ppl_proposal_weights_bytes(void);
 
 /* Glorot-uniform initialisation: element e of W_l[out][in] (l = 0, 1, 2) is

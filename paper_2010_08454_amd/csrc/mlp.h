@@ -33,8 +33,21 @@ struct MlpParams {
     static constexpr size_t step_off() {                                  // int64 Adam step count
         return (3 * count() * sizeof(float) + 2 * bf16_count() * sizeof(uint16_t) + 255) / 256 * 256;
     }
-    static constexpr size_t bytes() { return step_off() + 256; }
+    // BF16 copies of both layouts in fragment order (frag_index), after the
+    // step count: what the fused training pass loads
+    static constexpr size_t frag_off() { return step_off() + 256; }
+    static constexpr size_t bytes() { return frag_off() + (2 * bf16_count() * sizeof(uint16_t) + 255) / 256 * 256; }
 };
+
+// Position of element (n, k) of a weight matrix with rows n < 256 and KD
+// columns (KD a multiple of 32) in fragment order: wave n / 64 of the fused
+// training pass loads, for k-step s = k / 32 and column tile j = (n % 64) / 16,
+// 64 lanes x 8 consecutive values (lane = 16 ((k % 32) / 8) + n % 16), so each
+// of its load instructions reads 1 KB of consecutive bytes.
+__host__ __device__ inline int64_t frag_index(int n, int k, int KD) {
+    const int wave = n >> 6, j = (n >> 4) & 3, s = k >> 5, lane = ((k & 31) >> 3) * 16 + (n & 15);
+    return ((((int64_t)wave * (KD >> 5) + s) * 4 + j) * 64 + lane) * 8 + (k & 7);
+}
 
 // FP32 -> BF16 bit pattern, round to nearest even (NaN stays NaN).
 __host__ __device__ inline uint16_t f32_to_bf16(float f) {
@@ -55,6 +68,7 @@ __host__ __device__ inline float bf16_to_f32(uint16_t b) {
 struct MlpView {
     float *master, *m, *v;
     uint16_t *wt, *w;        // BF16 bit patterns: [out][in] and [in][out]
+    uint16_t *wtf, *wf;      // the same two in fragment order (frag_index)
     int64_t *step;           // completed Adam steps (device)
 };
 
@@ -66,6 +80,8 @@ inline MlpView mlp_view(void *p) {
     v.wt = (uint16_t *)(v.v + MlpParams::count());
     v.w = v.wt + MlpParams::bf16_count();
     v.step = (int64_t *)((char *)p + MlpParams::step_off());
+    v.wtf = (uint16_t *)((char *)p + MlpParams::frag_off());
+    v.wf = v.wtf + MlpParams::bf16_count();
     return v;
 }
 

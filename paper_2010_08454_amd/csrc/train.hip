@@ -191,9 +191,12 @@ typedef __bf16 fbf16x8_t __attribute__((ext_vector_type(8)));
 typedef float ffloatx4_t __attribute__((ext_vector_type(4)));
 
 // A product's weight fragments for this wave: fb[s][j] holds B rows
-// 64 wave + 16 j + lane % 16, K entries 32 s + 8 (lane / 16) .. + 7.  They are
-// loaded one product ahead (while the previous product's epilogue and the
-// workgroup barrier run), so a product waits for global memory at most once.
+// 64 wave + 16 j + lane % 16, K entries 32 s + 8 (lane / 16) .. + 7, read from
+// the fragment-order copy of the weights (frag_index: each load instruction
+// reads 1 KB of consecutive bytes; from the [out][in] or [in][out] layout a
+// wave's load touched 16 rows, 64 bytes of each).  They are loaded one product
+// ahead (while the previous product's epilogue and the workgroup barrier run),
+// so a product waits for global memory at most once.
 typedef fbf16x8_t FuseFrags[8][4];
 
 template <int KD>
@@ -204,7 +207,7 @@ __device__ __forceinline__ void fuse_load_w(const uint16_t *Bw, FuseFrags &fb) {
     for (int s = 0; s < KD / 32; ++s)
 #pragma unroll
         for (int j = 0; j < 4; ++j)
-            fb[s][j] = *(const fbf16x8_t *)(Bw + (size_t)(64 * wave + 16 * j + fr) * KD + 32 * s + fk);
+            fb[s][j] = *(const fbf16x8_t *)(Bw + frag_index(64 * wave + 16 * j + fr, 32 * s + fk, KD));
     __builtin_amdgcn_sched_barrier(0);       // keep the scheduler from sinking the loads into the MFMA loop
 }
 
@@ -310,21 +313,21 @@ __global__ __launch_bounds__(256) void fused_pass_kernel(MlpView w, TrainBufs b,
     ffloatx4_t acc[2][4];
     FuseFrags fb;
     // layer 1: H1 = relu(X W1^T + b1)
-    fuse_load_w<kMlpIn>(w.wt + MlpParams::bf16_w_off(0), fb);
+    fuse_load_w<kMlpIn>(w.wtf + MlpParams::bf16_w_off(0), fb);
     for (int e = tid; e < kFuseRows * kThetaStride; e += 256) sTh[e] = b.theta[(size_t)b0 * kThetaStride + e];
     fuse_mma<kMlpIn>(b.x_row + (size_t)b0 * kMlpIn, kMlpIn, fb, acc);
-    fuse_load_w<kMlpHid>(w.wt + MlpParams::bf16_w_off(1), fb);
+    fuse_load_w<kMlpHid>(w.wtf + MlpParams::bf16_w_off(1), fb);
     fuse_store_hidden(acc, bias_r[0], sH1, b.h1_col, B, b0);
     for (int k = tid; k < kFuseRows * kFusePad / 2; k += 256) ((uint32_t *)sG)[k] = 0u;
     lds_barrier();
     // layer 2: H2 = relu(H1 W2^T + b2)
     fuse_mma<kMlpHid>(sH1, kFusePad, fb, acc);
-    fuse_load_w<kMlpHid>(w.wt + MlpParams::bf16_w_off(2), fb);
+    fuse_load_w<kMlpHid>(w.wtf + MlpParams::bf16_w_off(2), fb);
     fuse_store_hidden(acc, bias_r[1], sH2, b.h2_col, B, b0);
     lds_barrier();
     // layer 3: O = H2 W3^T + b3 (FP32)
     fuse_mma<kMlpHid>(sH2, kFusePad, fb, acc);
-    fuse_load_w<kMlpOut>(w.w + MlpParams::bf16_w_off(2), fb);
+    fuse_load_w<kMlpOut>(w.wf + MlpParams::bf16_w_off(2), fb);
     {
         const int fr = lane & 15, rq = (lane >> 4) * 4;
 #pragma unroll
@@ -359,7 +362,7 @@ __global__ __launch_bounds__(256) void fused_pass_kernel(MlpView w, TrainBufs b,
     }
     // layer 3 input gradient: dH2 = (dO W3) * [H2 > 0]
     fuse_mma<kMlpOut>(sG, kFusePad, fb, acc);
-    fuse_load_w<kMlpHid>(w.w + MlpParams::bf16_w_off(1), fb);
+    fuse_load_w<kMlpHid>(w.wf + MlpParams::bf16_w_off(1), fb);
     fuse_store_masked(acc, sH2, sD2, b.dh2_col, B, b0);
     lds_barrier();
     // layer 2 input gradient: dH1 = (dH2 W2) * [H1 > 0]
@@ -449,6 +452,8 @@ __global__ __launch_bounds__(256) void adam_kernel(MlpView w, SplitParts sp, con
         const uint16_t h = f32_to_bf16(p);
         w.wt[MlpParams::bf16_w_off(l) + local] = h;
         w.w[MlpParams::bf16_w_off(l) + (int64_t)i * out + o] = h;
+        w.wtf[MlpParams::bf16_w_off(l) + frag_index(o, i, in)] = h;
+        w.wf[MlpParams::bf16_w_off(l) + frag_index(i, o, out)] = h;
     }
 }
 
@@ -491,6 +496,8 @@ __global__ __launch_bounds__(256) void init_weights_kernel(MlpView w, Key key, f
         const uint16_t h = f32_to_bf16(p);
         w.wt[MlpParams::bf16_w_off(l) + local] = h;
         w.w[MlpParams::bf16_w_off(l) + (int64_t)i * out + o] = h;
+        w.wtf[MlpParams::bf16_w_off(l) + frag_index(o, i, in)] = h;
+        w.wf[MlpParams::bf16_w_off(l) + frag_index(i, o, out)] = h;
     }
     w.master[e] = p;
     w.m[e] = 0.0f;
