@@ -96,6 +96,75 @@ enum MlpEpi : int {
     kEpiOutF32Col = 64,  // FP32 column-major [N][M] output
 };
 
+// ------------------------------------------------------------ GEMM tile --
+typedef __bf16 bf16x8_t __attribute__((ext_vector_type(8)));
+typedef float floatx4_t __attribute__((ext_vector_type(4)));
+
+constexpr int kGemmTile = 64;
+
+__device__ __forceinline__ bf16x8_t load_frag(const uint16_t *p) { return *(const bf16x8_t *)p; }
+
+// One 64 x 64 output tile (bx, by) of C = A B^T over R-chunk bz, four waves of
+// 32 x 32 (the body of gemm_nt_kernel, also run by grouped launches).
+template <int EPI>
+__device__ __forceinline__ void gemm_nt_tile(const uint16_t *__restrict__ A, const uint16_t *__restrict__ B, int M,
+                                             int N, int R, int lda, int ldb, const float *__restrict__ bias,
+                                             const uint16_t *__restrict__ mask, uint16_t *__restrict__ out_row,
+                                             uint16_t *__restrict__ out_col, float *__restrict__ out_f32, int r_chunk,
+                                             int bx, int by, int bz) {
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int m0 = by * kGemmTile + (wave >> 1) * 32;
+    const int n0 = bx * kGemmTile + (wave & 1) * 32;
+    const int r_begin = bz * r_chunk;
+    const int r_end = min(R, r_begin + r_chunk);
+    const int fr = lane & 15, fk = (lane >> 4) * 8;
+    floatx4_t acc[2][2];
+#pragma unroll
+    for (int i = 0; i < 2; ++i)
+#pragma unroll
+        for (int j = 0; j < 2; ++j) acc[i][j] = floatx4_t{0.f, 0.f, 0.f, 0.f};
+    const uint16_t *a0 = A + (size_t)(m0 + fr) * lda + fk;
+    const uint16_t *a1 = A + (size_t)(m0 + 16 + fr) * lda + fk;
+    const uint16_t *b0 = B + (size_t)(n0 + fr) * ldb + fk;
+    const uint16_t *b1 = B + (size_t)(n0 + 16 + fr) * ldb + fk;
+    for (int r = r_begin; r < r_end; r += 32) {
+        const bf16x8_t fa0 = load_frag(a0 + r), fa1 = load_frag(a1 + r);
+        const bf16x8_t fb0 = load_frag(b0 + r), fb1 = load_frag(b1 + r);
+        acc[0][0] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(fa0, fb0, acc[0][0], 0, 0, 0);
+        acc[0][1] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(fa0, fb1, acc[0][1], 0, 0, 0);
+        acc[1][0] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(fa1, fb0, acc[1][0], 0, 0, 0);
+        acc[1][1] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(fa1, fb1, acc[1][1], 0, 0, 0);
+    }
+    // epilogue: acc[i][j][q] is C[m0 + 16 i + 4 (lane/16) + q][n0 + 16 j + lane%16]
+    float *part = (EPI & kEpiOutF32) ? out_f32 + (size_t)bz * M * N : nullptr;
+#pragma unroll
+    for (int i = 0; i < 2; ++i) {
+#pragma unroll
+        for (int j = 0; j < 2; ++j) {
+            const int n = n0 + 16 * j + fr;
+            const int mb = m0 + 16 * i + (lane >> 4) * 4;
+            const float bn = (EPI & kEpiBias) ? bias[n] : 0.0f;
+            float v[4];
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                const int m = mb + q;
+                float t = acc[i][j][q] + bn;
+                if (EPI & kEpiMaskRow) t = (mask[(size_t)m * N + n] & 0x7FFFu) ? t : 0.0f;
+                if (EPI & kEpiRelu) t = fmaxf(t, 0.0f);
+                v[q] = t;
+                if (EPI & kEpiOutF32) part[(size_t)m * N + n] = t;
+                if (EPI & kEpiOutRow) out_row[(size_t)m * N + n] = f32_to_bf16(t);
+            }
+            if (EPI & kEpiOutF32Col) *(float4 *)(out_f32 + (size_t)n * M + mb) = make_float4(v[0], v[1], v[2], v[3]);
+            if (EPI & kEpiOutCol) {
+                const uint32_t lo = (uint32_t)f32_to_bf16(v[0]) | ((uint32_t)f32_to_bf16(v[1]) << 16);
+                const uint32_t hi = (uint32_t)f32_to_bf16(v[2]) | ((uint32_t)f32_to_bf16(v[3]) << 16);
+                *(uint2 *)(out_col + (size_t)n * M + mb) = make_uint2(lo, hi);
+            }
+        }
+    }
+}
+
 // Launch C = A B^T for BF16 operands stored with the reduction dimension
 // contiguous (A: [M][R], B: [N][R]); M, N multiples of 64, R multiple of 32.
 int mlp_gemm(const uint16_t *A, const uint16_t *B, int M, int N, int R, int lda, int ldb, int epi, const float *bias,

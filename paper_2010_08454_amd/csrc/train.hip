@@ -373,11 +373,11 @@ __global__ __launch_bounds__(256) void fused_pass_kernel(MlpView w, TrainBufs b,
 // ------------------------------------------------------ bias gradients --
 // bgrad[l][o] = sum over the batch of the BF16 gradient column o of layer l
 // (FP32, a fixed order: 256 strided lane sums, then a tree).
-__global__ __launch_bounds__(256) void bias_grad_kernel(const uint16_t *__restrict__ g1, const uint16_t *__restrict__ g2,
-                                                        const uint16_t *__restrict__ g3, int B,
-                                                        float *__restrict__ bgrad) {
+__device__ __forceinline__ void bias_grad_unit(const uint16_t *__restrict__ g1, const uint16_t *__restrict__ g2,
+                                               const uint16_t *__restrict__ g3, int B, float *__restrict__ bgrad,
+                                               int unit) {
     __shared__ float red[4];
-    const int unit = blockIdx.x, l = unit >> 8, o = unit & 255;
+    const int l = unit >> 8, o = unit & 255;
     const uint16_t *g = (l == 0 ? g1 : (l == 1 ? g2 : g3)) + (size_t)o * B;
     float s = 0.0f;
     for (int b = threadIdx.x; b < B; b += 256) s += bf16_to_f32(g[b]);
@@ -386,6 +386,45 @@ __global__ __launch_bounds__(256) void bias_grad_kernel(const uint16_t *__restri
     if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = s;
     __syncthreads();
     if (threadIdx.x == 0) bgrad[unit] = (red[0] + red[1]) + (red[2] + red[3]);
+}
+
+__global__ __launch_bounds__(256) void bias_grad_kernel(const uint16_t *__restrict__ g1, const uint16_t *__restrict__ g2,
+                                                        const uint16_t *__restrict__ g3, int B,
+                                                        float *__restrict__ bgrad) {
+    bias_grad_unit(g1, g2, g3, B, bgrad, blockIdx.x);
+}
+
+// The three weight-gradient products (split over R-chunks) and the bias sums
+// in one launch: workgroups [first_k, first_k + tx ty nz) take product k's
+// tiles (x fastest, then y, then the chunk), the rest one bias each.  Every
+// tile and bias is computed as by the separate launches, so the bits match.
+struct WgradJob {
+    const uint16_t *A, *B;
+    float *partial;
+    int M, N, R, lda, ldb, chunk, tx, ty, first;
+};
+struct WgradGroup {
+    WgradJob job[3];
+    int gemm_blocks;
+    const uint16_t *g1, *g2, *g3;
+    int B;
+    float *bgrad;
+};
+
+__global__ __launch_bounds__(256) void wgrad_group_kernel(WgradGroup g) {
+    const int b = blockIdx.x;
+    if (b < g.gemm_blocks) {
+        const int k = b >= g.job[2].first ? 2 : (b >= g.job[1].first ? 1 : 0);
+        const WgradJob j = k == 0 ? g.job[0] : (k == 1 ? g.job[1] : g.job[2]);
+        int local = b - j.first;
+        const int bx = local % j.tx;
+        local /= j.tx;
+        const int by = local % j.ty, bz = local / j.ty;
+        gemm_nt_tile<kEpiOutF32>(j.A, j.B, j.M, j.N, j.R, j.lda, j.ldb, nullptr, nullptr, nullptr, nullptr, j.partial,
+                                 j.chunk, bx, by, bz);
+    } else {
+        bias_grad_unit(g.g1, g.g2, g.g3, g.B, g.bgrad, b - g.gemm_blocks);
+    }
 }
 
 // ------------------------------------------------------------ update --
@@ -658,11 +697,42 @@ int launch_fused_pass(int model, int K, const MlpView &w, const TrainBufs &b, hi
         timer.stop();
         PPL_LAUNCH_CHECK("fused_pass_kernel");
     }
-    if (int rc = mlp_gemm_splitr(b.do_col, b.h2_col, kMlpOut, kMlpHid, B, B, B, b.chunk[2], b.part[2], st)) return rc;
-    if (int rc = mlp_gemm_splitr(b.dh2_col, b.h1_col, kMlpHid, kMlpHid, B, B, B, b.chunk[1], b.part[1], st)) return rc;
-    if (int rc = mlp_gemm_splitr(b.dh1_col, b.x_col, kMlpHid, kMlpIn, B, B, B, b.chunk[0], b.part[0], st)) return rc;
-    hipLaunchKernelGGL(bias_grad_kernel, dim3(3 * 256), dim3(256), 0, st, b.dh1_col, b.dh2_col, b.do_col, B, b.bgrad);
-    PPL_LAUNCH_CHECK("bias_grad_kernel");
+    // the weight-gradient products and bias sums, grouped in one launch
+    WgradGroup g{};
+    const uint16_t *As[3] = {b.do_col, b.dh2_col, b.dh1_col}, *Bs[3] = {b.h2_col, b.h1_col, b.x_col};
+    const int Ms[3] = {kMlpOut, kMlpHid, kMlpHid}, Ns[3] = {kMlpHid, kMlpHid, kMlpIn}, layer[3] = {2, 1, 0};
+    int first = 0;
+    for (int k = 0; k < 3; ++k) {
+        const int l = layer[k], chunk = b.chunk[l];
+        if (Ms[k] % kGemmTile || Ns[k] % kGemmTile || B % 32 || chunk % 32 || chunk <= 0)
+            return fail(PPL_E_ARG, "split GEMM shape %d x %d x %d / %d not tile-aligned", Ms[k], Ns[k], B, chunk);
+        WgradJob &j = g.job[k];
+        j.A = As[k];
+        j.B = Bs[k];
+        j.partial = b.part[l];
+        j.M = Ms[k];
+        j.N = Ns[k];
+        j.R = B;
+        j.lda = B;
+        j.ldb = B;
+        j.chunk = chunk;
+        j.tx = Ns[k] / kGemmTile;
+        j.ty = Ms[k] / kGemmTile;
+        j.first = first;
+        first += j.tx * j.ty * ((B + chunk - 1) / chunk);
+    }
+    g.gemm_blocks = first;
+    g.g1 = b.dh1_col;
+    g.g2 = b.dh2_col;
+    g.g3 = b.do_col;
+    g.B = B;
+    g.bgrad = b.bgrad;
+    {
+        KernelTimer timer("wgrad_group_kernel", st);
+        hipLaunchKernelGGL(wgrad_group_kernel, dim3((unsigned)(first + 3 * 256)), dim3(256), 0, st, g);
+        timer.stop();
+        PPL_LAUNCH_CHECK("wgrad_group_kernel");
+    }
     return PPL_OK;
 }
 
