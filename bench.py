@@ -713,12 +713,18 @@ def bench_proposal_train(args, ppl, torch, dev, stream):
            "config": {"workload": "learned-proposal-training-poly", "pairs": pairs, "batch": B,
                       "graph": not args.no_graph, "loss_last": float(trace[-8:].mean())}}
     if args.no_graph:
-        g_ms, g_n = ppl.ppl_timing_query("gemm_nt_kernel")
+        # the kernels that run the network's products: the fused pass (forward,
+        # loss head, input gradients) and the grouped weight-gradient launch, or
+        # the per-product GEMMs when PPL_TRAIN_UNFUSED=1
+        names = ("fused_pass_kernel", "wgrad_group_kernel", "gemm_nt_kernel")
+        q = {k: ppl.ppl_timing_query(k) for k in names}
+        g_ms = sum(v[0] for v in q.values())
+        used = [k for k in names if q[k][1] > 0]
         achieved = GEMM_FLOP_PER_PAIR * pairs / (g_ms / 1e3) / 1e12
         out["roofline"] = {"bound": "mfma", "achieved": round(achieved, 3), "peak": BF16_MFMA_TFLOPS,
                            "unit": "TFLOP/s", "frac": round(achieved / BF16_MFMA_TFLOPS, 5), "traffic": None,
-                           "kernel": "gemm_nt_kernel", "kernel_ms": round(g_ms / max(g_n, 1), 5),
-                           "kernel_launches": g_n, "flop_per_pair": GEMM_FLOP_PER_PAIR}
+                           "kernel": "+".join(used), "kernel_ms_per_step": round(g_ms / steps, 5),
+                           "kernel_launches": {k: q[k][1] for k in used}, "flop_per_pair": GEMM_FLOP_PER_PAIR}
     ppl.ppl_timing_enable(False)
     print(json.dumps(out), flush=True)
 
