@@ -474,6 +474,10 @@ def cpu_baseline_resample(lw, state, seed, target_s=10.0):
 
 BF16_MFMA_TFLOPS = 2500.0
 GEMM_FLOP_PER_PAIR = 2 * 425984      # forward 3 layers + 2 input-gradient + 3 weight-gradient products
+# the kernels that run the network's products: the fused pass (forward, loss
+# head, input gradients) and the grouped weight-gradient launch, or the
+# per-product GEMMs when PPL_TRAIN_UNFUSED=1
+PRODUCT_KERNELS = ("fused_pass_kernel", "wgrad_group_kernel", "gemm_nt_kernel")
 SEEDS_PER_RUNG = 16
 RMSE_TARGET = 0.05
 
@@ -570,7 +574,7 @@ def bench_proposal(args, ppl, synthetic, torch, dev, stream):
     ppl.ppl_timing_enable(True)
     ppl.ppl_proposal_train(model, pcfg, 1, wcopy, ws=tws, stream=stream)
     torch.cuda.synchronize()
-    g_ms, g_n = ppl.ppl_timing_query("gemm_nt_kernel")
+    g_ms = sum(ppl.ppl_timing_query(k)[0] for k in PRODUCT_KERNELS)
     ppl.ppl_timing_enable(False)
     gemm_tflops = GEMM_FLOP_PER_PAIR * B * probe_steps / (g_ms / 1e3) / 1e12
     # adaptive tempering of the proposal for this dataset (pilot ESS, no reference)
@@ -713,10 +717,7 @@ def bench_proposal_train(args, ppl, torch, dev, stream):
            "config": {"workload": "learned-proposal-training-poly", "pairs": pairs, "batch": B,
                       "graph": not args.no_graph, "loss_last": float(trace[-8:].mean())}}
     if args.no_graph:
-        # the kernels that run the network's products: the fused pass (forward,
-        # loss head, input gradients) and the grouped weight-gradient launch, or
-        # the per-product GEMMs when PPL_TRAIN_UNFUSED=1
-        names = ("fused_pass_kernel", "wgrad_group_kernel", "gemm_nt_kernel")
+        names = PRODUCT_KERNELS
         q = {k: ppl.ppl_timing_query(k) for k in names}
         g_ms = sum(v[0] for v in q.values())
         used = [k for k in names if q[k][1] > 0]
