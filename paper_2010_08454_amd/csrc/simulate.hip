@@ -73,9 +73,11 @@ __device__ __forceinline__ void poly_acc_point(double (&a)[kPolyAcc], double x, 
 // Least-squares fit with n coefficients from the normalised moments
 // (normal equations G beta = m, G_ij = mean x^(i+j), m_i = mean x^i y) by a
 // Cholesky factorisation and two triangular solves.
+// The diagonal's reciprocals are formed once (one division per column, then
+// products): the solve's chain of dependent FP64 divisions is its latency.
 __device__ void poly_ls(int n, const double *gx, const double *mxy, double (&beta)[5]) {
 #pragma clang fp contract(off)
-    double L[5][5], z[5];
+    double L[5][5], z[5], rd[5];
 #pragma unroll
     for (int i = 0; i < 5; ++i) {
 #pragma unroll
@@ -84,7 +86,12 @@ __device__ void poly_ls(int n, const double *gx, const double *mxy, double (&bet
                 double s = gx[i + j];
 #pragma unroll
                 for (int k = 0; k < j; ++k) s -= L[i][k] * L[j][k];
-                L[i][j] = (i == j) ? sqrt(s > 1e-300 ? s : 1e-300) : s / L[j][j];
+                if (i == j) {
+                    L[i][i] = sqrt(s > 1e-300 ? s : 1e-300);
+                    rd[i] = 1.0 / L[i][i];
+                } else {
+                    L[i][j] = s * rd[j];
+                }
             }
         }
     }
@@ -94,7 +101,7 @@ __device__ void poly_ls(int n, const double *gx, const double *mxy, double (&bet
             double s = mxy[i];
 #pragma unroll
             for (int k = 0; k < i; ++k) s -= L[i][k] * z[k];
-            z[i] = s / L[i][i];
+            z[i] = s * rd[i];
         }
     }
 #pragma unroll
@@ -105,7 +112,7 @@ __device__ void poly_ls(int n, const double *gx, const double *mxy, double (&bet
 #pragma unroll
             for (int k = i + 1; k < 5; ++k)
                 if (k < n) s -= L[k][i] * beta[k];
-            beta[i] = s / L[i][i];
+            beta[i] = s * rd[i];
         }
     }
 }
@@ -131,7 +138,7 @@ __device__ void poly_finish(double (&a)[kPolyAcc], int64_t D, double (*wtot)[kPo
 #pragma clang fp contract(off)
     const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
 #pragma unroll
-    for (int k = 0; k < kPolyAcc; ++k) a[k] = wave_sum(a[k]);
+    for (int k = 0; k < kPolyAcc; ++k) a[k] = wave_sum_dpp(a[k]);
     if (lane == 0) {
 #pragma unroll
         for (int k = 0; k < kPolyAcc; ++k) wtot[wv][k] = a[k];
