@@ -480,3 +480,58 @@ def test_learned_proposal_beats_prior_gmm(ppl):
     wts = train_learned(ppl, "gmm", 100, K)
     learned, prior = gain_check(ppl, "gmm", data, ref, wts, (12, 22), (22, 30))
     assert learned[0] * 64 <= prior[0]
+
+
+def frag_order(mat):
+    """A [N][KD] BF16 matrix (N <= 256 rows, KD a multiple of 32) in the fused
+    training pass's fragment order, written out from the index definition:
+    wave n // 64, k-step k // 32, row tile (n % 64) // 16, lane
+    16 ((k % 32) // 8) + n % 16, element k % 8."""
+    N, KD = mat.shape
+    out = np.zeros(N * KD, dtype=mat.dtype)
+    n = np.arange(N)[:, None]
+    k = np.arange(KD)[None, :]
+    lane = ((k % 32) // 8) * 16 + n % 16
+    idx = ((((n // 64) * (KD // 32) + k // 32) * 4 + (n % 64) // 16) * 64 + lane) * 8 + k % 8
+    out[idx.ravel()] = mat.ravel()
+    return out
+
+
+def test_fragment_order_copies_follow_adam(ppl):
+    """The parameter block's fragment-order BF16 copies hold exactly the
+    [out][in] and [in][out] weights, after initialisation and after Adam
+    steps; the fused pass (which reads them) then still equals the per-product
+    launches (which read the plain layouts)."""
+    import os
+    torch = torch_()
+    frag_off = STEP_OFF + 256
+    wts = ppl.ppl_proposal_init(SEED)
+    assert ppl.ppl_proposal_weights_bytes() == frag_off + 2 * BF_COUNT * 2
+    cfg = ppl.train_config(3 * 256, 256, 1000)
+    for trained in (False, True):
+        if trained:
+            ppl.ppl_proposal_train(ppl.PPL_MODEL_POLY, cfg, SEED, wts)
+            torch.cuda.synchronize()
+        raw = wts.cpu().numpy()
+        parts = split_weights(wts)
+        frag = raw[frag_off:frag_off + 2 * BF_COUNT * 2].view(np.uint16)
+        for l, (on, inn) in enumerate(SHAPES):
+            o = BF_OFF[l]
+            wt = parts["wt"][o:o + on * inn].reshape(on, inn)        # [out][in]
+            w = parts["w"][o:o + on * inn].reshape(inn, on)          # [in][out]
+            np.testing.assert_array_equal(frag[o:o + on * inn], frag_order(wt))
+            np.testing.assert_array_equal(frag[BF_COUNT + o:BF_COUNT + o + on * inn], frag_order(w))
+    # fused and per-product passes agree at the trained weights
+    B = 256
+    gcfg = ppl.train_config(B, B, 1000)
+    res = []
+    for unfused in ("0", "1"):
+        os.environ["PPL_TRAIN_UNFUSED"] = unfused
+        try:
+            grad = torch.empty(COUNT, dtype=torch.float32, device="cuda")
+            ppl.ppl_proposal_gradient(ppl.PPL_MODEL_POLY, gcfg, SEED, 5, wts, grad=grad)
+            torch.cuda.synchronize()
+            res.append(grad.cpu().numpy())
+        finally:
+            del os.environ["PPL_TRAIN_UNFUSED"]
+    np.testing.assert_array_equal(res[0], res[1])
