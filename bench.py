@@ -332,8 +332,10 @@ def bench_enum(args, ppl, synthetic, torch, dev, stream):
     T = 20 steps, 2^40 paths (synthetic chain and observations, see
     synthetic.hmm_instance).  One step = one ppl_enumerate call (emission
     table, the maximum pass, the summing pass, merges).  Roofline: the summing
-    pass at two FP64 FMA (4 FLOP) per path against the FP64 vector peak; the
-    maximum pass (an add and a max per path) is reported beside it."""
+    pass at 2 + 1/K FLOP per path (an FMA of the path's weight into its last
+    site's sum, and one product per K sibling paths for their parent's
+    subtotal) against the FP64 vector peak; the maximum pass (an add and a max
+    per path) is reported beside it."""
     K, T = 4, 20
     pi0, A, mu, sigma, y, _ = synthetic.hmm_instance(K, T)
     dy = torch.from_numpy(y).to(dev)
@@ -365,7 +367,7 @@ def bench_enum(args, ppl, synthetic, torch, dev, stream):
     paths = float(K) ** T
     ms_per_step = total_ms / args.steps
     s_avg, m_avg = s_ms / max(s_n, 1), m_ms / max(m_n, 1)
-    flop_per_launch = 4 * paths
+    flop_per_launch = (2 + 1 / K) * paths
     achieved = flop_per_launch / (s_avg / 1e3) / 1e12
     out = {"metric": "paths/s", "value": paths / (ms_per_step / 1e3), "unit": "paths/s", "n_gpus": 1,
            "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(ms_per_step, 4),

@@ -65,6 +65,7 @@ struct EnLds {
     double cn[kEnMaxF];          // cn[L][j][k] = c[tail + L][j][k], nested level L (compile-time offsets)
     double F[kEnMaxF];           // F[L][j][k], nested level L (site tail + L)
     double V[(kEnMaxTS + 1) * 8];// V[L][j], V[TS][j] = 0
+    double G[kEnMaxTS * 8];      // G[L][j] = sum_k F[L][j][k] (k in order)
 };
 
 // Stages the tables: c for every site, and for the TS nested sites the
@@ -95,6 +96,12 @@ __device__ void en_stage(EnLds &s, const EnumDev &a, bool factors) {
         const int L = i / (K * K), j = (i / K) % K, k = i % K;
         const double vj = s.V[L * K + j];
         s.F[i] = vj > -INFINITY ? exp(s.c[((tail + L) * K + j) * K + k] + s.V[(L + 1) * K + k] - vj) : 0.0;
+    }
+    __syncthreads();
+    for (int i = threadIdx.x; i < TS * K; i += kEnThreads) {
+        double g = 0.0;
+        for (int k = 0; k < K; ++k) g += s.F[i * K + k];
+        s.G[i] = g;
     }
     __syncthreads();
 }
@@ -199,11 +206,12 @@ struct WalkSum {
                 tot += sub;
             }
         } else if constexpr (L == TS - 1) {
+            // each path's weight w F[k] goes into its site sum; the node's
+            // subtotal, their sum, is w times the row sum G (one product for
+            // the K paths)
 #pragma unroll
-            for (int k = 0; k < K; ++k) {
-                marg[L][k] = fma(w, F[k], marg[L][k]);
-                tot = fma(w, F[k], tot);
-            }
+            for (int k = 0; k < K; ++k) marg[L][k] = fma(w, F[k], marg[L][k]);
+            tot = w * s.G[L * K + prev];
         } else {
 #pragma unroll
             for (int k = 0; k < K; ++k) {
