@@ -66,6 +66,7 @@ struct EnLds {
     double F[kEnMaxF];           // F[L][j][k], nested level L (site tail + L)
     double V[(kEnMaxTS + 1) * 8];// V[L][j], V[TS][j] = 0
     double G[kEnMaxTS * 8];      // G[L][j] = sum_k F[L][j][k] (k in order)
+    double cm[8];                // cm[j] = max_k cn[TS - 1][j][k] (k in order)
 };
 
 // Stages the tables: c for every site, and for the TS nested sites the
@@ -80,6 +81,13 @@ __device__ void en_stage(EnLds &s, const EnumDev &a, bool factors) {
     if (threadIdx.x < K) s.c0[threadIdx.x] = a.lpi[threadIdx.x] + a.le[threadIdx.x];
     __syncthreads();
     for (int i = threadIdx.x; i < TS * K * K; i += kEnThreads) s.cn[i] = s.c[tail * K * K + i];
+    if constexpr (TS > 0)
+        if (threadIdx.x < K) {
+            const double *row = s.c + ((tail + TS - 1) * K + threadIdx.x) * K;
+            double v = row[0];
+            for (int k = 1; k < K; ++k) v = fmax(v, row[k]);
+            s.cm[threadIdx.x] = v;
+        }
     __syncthreads();
     if (!factors) return;
     if (threadIdx.x == 0) {
@@ -130,18 +138,20 @@ template <int K, int L, int TS, int UL>
 struct WalkMax {
     // largest log-weight below a node of an unrolled level
     __device__ static double leafmax(const EnLds &s, int prev, double lw) {
-        double v = 0.0;
+        // Round-to-nearest addition is monotone, so the largest of lw + c_k
+        // over the last site's K states is lw plus the largest c_k: the same
+        // double as taking the K sums and their maximum.
+        if constexpr (L == TS - 1) {
+            return lw + s.cm[prev];
+        } else {
+            double v = 0.0;
 #pragma unroll
-        for (int k = 0; k < K; ++k) {
-            const double lk = lw + s.cn[(L * K + prev) * K + k];
-            double x;
-            if constexpr (L == TS - 1)
-                x = lk;
-            else
-                x = WalkMax<K, L + 1, TS, UL>::leafmax(s, k, lk);
-            v = k == 0 ? x : fmax(v, x);
+            for (int k = 0; k < K; ++k) {
+                const double x = WalkMax<K, L + 1, TS, UL>::leafmax(s, k, lw + s.cn[(L * K + prev) * K + k]);
+                v = k == 0 ? x : fmax(v, x);
+            }
+            return v;
         }
-        return v;
     }
     // Raises best to the largest log-weight below the node and, when it does,
     // records the index of the node at level TS - UL that holds it.
