@@ -774,20 +774,23 @@ static int check_weights(const void *w) {
 // Forward, head and backward pass of one batch: fused per 32 pairs, or (with
 // the environment variable PPL_TRAIN_UNFUSED=1, a checking and timing aid)
 // one launch per product; both store the same bits.
-static int forward_backward(int model, int K, const MlpView &w, const TrainBufs &b, hipStream_t st) {
+static int forward_backward(int model, int K, const MlpView &w, const TrainBufs &b, const AdvanceJob &adv,
+                            hipStream_t st) {
     const char *e = getenv("PPL_TRAIN_UNFUSED");
-    if (!(e && e[0] == '1')) return launch_fused_pass(model, K, w, b, st);
+    if (!(e && e[0] == '1')) return launch_fused_pass(model, K, w, b, adv, st);
     if (int rc = launch_forward(w, b, true, st)) return rc;
-    return launch_head_backward(model, K, w, b, st);
+    if (int rc = launch_head_backward(model, K, w, b, st)) return rc;
+    return launch_advance(adv, st);
 }
 
-// One training step: simulate, forward, loss head, backward, Adam, bookkeeping.
+// One training step: simulate, forward, loss head, backward and the step's
+// bookkeeping, then Adam.
 static int train_step(const TrainPlan &p, uint64_t seed, const MlpView &w, const TrainBufs &b, double *loss_trace,
                       hipStream_t st) {
     if (int rc = launch_simulate(p.sim, p.B, seed, w.step, b.x_row, b.x_col, b.theta, nullptr, st)) return rc;
-    if (int rc = forward_backward(p.sim.model, p.sim.K, w, b, st)) return rc;
-    if (int rc = launch_update(w, b, p.adam, nullptr, st)) return rc;
-    return launch_advance(w.step, b, loss_trace, st);
+    if (int rc = forward_backward(p.sim.model, p.sim.K, w, b, advance_job(w.step, b, p.adam, loss_trace), st))
+        return rc;
+    return launch_update(w, b, p.adam, nullptr, st);
 }
 
 static int train_graph(const TrainPlan &p, uint64_t seed, const MlpView &w, const TrainBufs &b, double *loss_trace,
@@ -890,10 +893,9 @@ int ppl_proposal_gradient(int model, const ppl_train_config *cfg, uint64_t seed,
     if (int rc = launch_set_i64(b.local, 0, st)) return rc;
     if (int rc = launch_set_i64(b.local + 1, (int64_t)step, st)) return rc;
     if (int rc = launch_simulate(p.sim, p.B, seed, b.local + 1, b.x_row, b.x_col, b.theta, d_summaries, st)) return rc;
-    if (int rc = forward_backward(model, p.sim.K, w, b, st)) return rc;
+    if (int rc = forward_backward(model, p.sim.K, w, b, advance_job(nullptr, b, p.adam, d_loss), st)) return rc;
     if (d_grad)
         if (int rc = launch_update(w, b, p.adam, d_grad, st)) return rc;
-    if (int rc = launch_advance(nullptr, b, d_loss, st)) return rc;
     if (d_latents)
         PPL_HIP(hipMemcpyAsync(d_latents, b.theta, (size_t)p.B * kThetaStride * sizeof(double), hipMemcpyDeviceToDevice, st));
     if (d_outputs)

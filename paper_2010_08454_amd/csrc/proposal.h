@@ -52,6 +52,7 @@ struct TrainBufs {
     float *bgrad;                       // [3][256]
     double *lossp;                      // [B / 32] per-workgroup loss sums
     int64_t *local;                     // [0]: steps taken in this call, [1]: a fixed step index
+    float *coef;                        // [3] Adam constants of the step being taken: 1 - b1^t, 1 - b2^t, lr
 };
 
 size_t train_ws_bytes(int B);
@@ -63,19 +64,34 @@ struct AdamSpec {
     double final_frac;       // lr multiplier reached at the end of the decay
 };
 
+// Per-step bookkeeping, run once by one wave after the loss partials are
+// written and before the Adam update: loss_trace[local] = mean loss,
+// local += 1 and, if step is not null, the Adam constants of step
+// t = step + 1 into coef, then step += 1.
+struct AdvanceJob {
+    int64_t *step, *local;
+    const double *lossp;
+    int nparts;
+    double inv_b;
+    double *loss_trace;
+    AdamSpec ad;
+    float *coef;
+};
+AdvanceJob advance_job(int64_t *step, const TrainBufs &b, const AdamSpec &ad, double *loss_trace);
+
 // Forward pass of a batch whose summaries are already in bufs.x_row/x_col.
 int launch_forward(const MlpView &w, const TrainBufs &b, bool keep_cols, hipStream_t st);
 // Loss head and backward pass (gradients left in the split partials and bgrad).
 int launch_head_backward(int model, int K, const MlpView &w, const TrainBufs &b, hipStream_t st);
 // The same in fewer launches: forward, head and input gradients fused per 32
 // pairs (bitwise the values of launch_forward + launch_head_backward), then
-// the weight-gradient products and bias sums.
-int launch_fused_pass(int model, int K, const MlpView &w, const TrainBufs &b, hipStream_t st);
-// grad != null: write the summed gradient [count] and stop; else Adam update.
+// the weight-gradient products, bias sums and the step's bookkeeping (adv).
+int launch_fused_pass(int model, int K, const MlpView &w, const TrainBufs &b, const AdvanceJob &adv, hipStream_t st);
+// grad != null: write the summed gradient [count] and stop; else Adam update
+// with the constants the step's bookkeeping left in b.coef.
 int launch_update(const MlpView &w, const TrainBufs &b, const AdamSpec &ad, float *grad, hipStream_t st);
-// Per-step bookkeeping: loss_trace[local] = mean loss, local += 1 and, if
-// step is not null, step += 1.
-int launch_advance(int64_t *step, const TrainBufs &b, double *loss_trace, hipStream_t st);
+// The step's bookkeeping as a launch of its own (after launch_head_backward).
+int launch_advance(const AdvanceJob &adv, hipStream_t st);
 int launch_set_i64(int64_t *p, int64_t v, hipStream_t st);
 int launch_init_weights(void *weights, uint64_t seed, hipStream_t st);
 

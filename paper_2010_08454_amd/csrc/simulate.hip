@@ -266,17 +266,21 @@ __global__ __launch_bounds__(kSumThreads) void simulate_kernel(SimSpec sp, int B
     if constexpr (MODEL == PPL_MODEL_POLY) {
         const uint4 w0 = philox(pair, 0, step, kTagTrain, key);
         const int n = uniform_discrete(w0.x, (int)sp.hyper[1], (uint32_t)((int)sp.hyper[2] - (int)sp.hyper[1] + 1));
-        double z[8];
-        {
-            const uint4 w1 = philox(pair, 1, step, kTagTrain, key), w2 = philox(pair, 2, step, kTagTrain, key);
-            box_muller(u01(w1.x), u01(w1.y), z[0], z[1]);
-            box_muller(u01(w1.z), u01(w1.w), z[2], z[3]);
-            box_muller(u01(w2.x), u01(w2.y), z[4], z[5]);
-            box_muller(u01(w2.z), u01(w2.w), z[6], z[7]);
+        // coefficient normals z_0..z_4: Box-Muller pairs 0..2 of blocks 1 and
+        // 2 (pair q from words 2 (q % 2), 2 (q % 2) + 1 of block 1 + q / 2),
+        // one pair per thread of the first three, shared through LDS
+        __shared__ double s_z[6];
+        if (tid < 3) {
+            const uint4 w = philox(pair, 1 + (tid >> 1), step, kTagTrain, key);
+            double za, zb;
+            box_muller(u01((tid & 1) ? w.z : w.x), u01((tid & 1) ? w.w : w.y), za, zb);
+            s_z[2 * tid] = za;
+            s_z[2 * tid + 1] = zb;
         }
+        __syncthreads();
         double c[5];
 #pragma unroll
-        for (int j = 0; j < 5; ++j) c[j] = sp.hyper[0] * z[j];
+        for (int j = 0; j < 5; ++j) c[j] = sp.hyper[0] * s_z[j];
         double a[kPolyAcc];
 #pragma unroll
         for (int k = 0; k < kPolyAcc; ++k) a[k] = 0.0;

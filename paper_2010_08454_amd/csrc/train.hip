@@ -409,7 +409,38 @@ struct WgradGroup {
     const uint16_t *g1, *g2, *g3;
     int B;
     float *bgrad;
+    AdvanceJob adv;
 };
+
+// The step's bookkeeping (one wave): the mean loss from the per-workgroup
+// partials, the call's step counter and, when the weights' step count is
+// given, the Adam constants of step t = completed steps + 1 (bias
+// corrections, the learning rate optionally on a half-cosine schedule of the
+// completed steps) computed once for every parameter, then the count.
+__device__ void advance_unit(const AdvanceJob &a) {
+    double s = 0.0;
+    for (int k = threadIdx.x & 63; k < a.nparts; k += 64) s += a.lossp[k];
+    s = wave_sum(s);
+    if ((threadIdx.x & 63) == 0) {
+        const int64_t t = *a.local;
+        if (a.loss_trace) a.loss_trace[t] = s * a.inv_b;
+        *a.local = t + 1;
+        if (a.step) {
+            const int64_t n = *a.step;
+            const double done = (double)n;
+            const double tt = done + 1.0;
+            a.coef[0] = (float)(1.0 - pow((double)a.ad.b1, tt));
+            a.coef[1] = (float)(1.0 - pow((double)a.ad.b2, tt));
+            float lr = a.ad.lr;
+            if (a.ad.decay_steps > 0.0) {
+                const double x = fmin(done / a.ad.decay_steps, 1.0);
+                lr = (float)(a.ad.lr * (a.ad.final_frac + (1.0 - a.ad.final_frac) * 0.5 * (1.0 + cospi(x))));
+            }
+            a.coef[2] = lr;
+            *a.step = n + 1;
+        }
+    }
+}
 
 __global__ __launch_bounds__(256) void wgrad_group_kernel(WgradGroup g) {
     const int b = blockIdx.x;
@@ -422,8 +453,10 @@ __global__ __launch_bounds__(256) void wgrad_group_kernel(WgradGroup g) {
         const int by = local % j.ty, bz = local / j.ty;
         gemm_nt_tile<kEpiOutF32>(j.A, j.B, j.M, j.N, j.R, j.lda, j.ldb, nullptr, nullptr, nullptr, nullptr, j.partial,
                                  j.chunk, bx, by, bz);
-    } else {
+    } else if (b < g.gemm_blocks + 3 * 256) {
         bias_grad_unit(g.g1, g.g2, g.g3, g.B, g.bgrad, b - g.gemm_blocks);
+    } else if (threadIdx.x < 64) {
+        advance_unit(g.adv);
     }
 }
 
@@ -434,12 +467,11 @@ struct SplitParts {
 };
 
 // Gradient of parameter e: weights sum their split-R partials in chunk order,
-// biases come from bgrad.  grad != null: store it; else one Adam step
-// (bias-corrected moments, step t = completed steps + 1, the learning rate
-// optionally on a half-cosine schedule of the completed steps) and refresh
-// both BF16 weight layouts.
+// biases come from bgrad.  grad != null: store it; else one Adam step with
+// the bias corrections and learning rate of coef (left by the step's
+// bookkeeping) and refresh the BF16 weight layouts.
 __global__ __launch_bounds__(256) void adam_kernel(MlpView w, SplitParts sp, const float *__restrict__ bgrad, AdamSpec ad,
-                                                   float *__restrict__ grad) {
+                                                   const float *__restrict__ coef, float *__restrict__ grad) {
     const int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x;
     if (e >= MlpParams::count()) return;
     int l = 0;
@@ -471,15 +503,7 @@ __global__ __launch_bounds__(256) void adam_kernel(MlpView w, SplitParts sp, con
         grad[e] = gv;
         return;
     }
-    const double done = (double)*w.step;
-    const double t = done + 1.0;
-    const float bc1 = (float)(1.0 - pow((double)ad.b1, t));
-    const float bc2 = (float)(1.0 - pow((double)ad.b2, t));
-    float lr = ad.lr;
-    if (ad.decay_steps > 0.0) {
-        const double x = fmin(done / ad.decay_steps, 1.0);
-        lr = (float)(ad.lr * (ad.final_frac + (1.0 - ad.final_frac) * 0.5 * (1.0 + cospi(x))));
-    }
+    const float bc1 = coef[0], bc2 = coef[1], lr = coef[2];
     const float m = ad.b1 * w.m[e] + (1.0f - ad.b1) * gv;
     const float v = ad.b2 * w.v[e] + (1.0f - ad.b2) * gv * gv;
     const float p = w.master[e] - lr * (m / bc1) / (sqrtf(v / bc2) + ad.eps);
@@ -496,19 +520,7 @@ __global__ __launch_bounds__(256) void adam_kernel(MlpView w, SplitParts sp, con
     }
 }
 
-__global__ __launch_bounds__(64) void advance_kernel(int64_t *__restrict__ step, int64_t *__restrict__ local,
-                                                     const double *__restrict__ lossp, int nparts, double inv_b,
-                                                     double *__restrict__ loss_trace) {
-    double s = 0.0;
-    for (int k = threadIdx.x; k < nparts; k += 64) s += lossp[k];
-    s = wave_sum(s);
-    if (threadIdx.x == 0) {
-        const int64_t t = *local;
-        if (loss_trace) loss_trace[t] = s * inv_b;
-        *local = t + 1;
-        if (step) *step = *step + 1;
-    }
-}
+__global__ __launch_bounds__(64) void advance_kernel(AdvanceJob a) { advance_unit(a); }
 
 __global__ void set_i64_kernel(int64_t *p, int64_t v) { *p = v; }
 
@@ -635,7 +647,8 @@ TrainBufs train_bufs(void *ws, int B) {
     t.part[2] = (float *)take((size_t)t.nchunks[2] * kMlpOut * kMlpHid * 4);
     t.bgrad = (float *)take(3 * 256 * 4);
     t.lossp = (double *)take((bB / kHeadPairs + 1) * 8);
-    t.local = (int64_t *)take(16);
+    t.local = (int64_t *)take(64);
+    t.coef = (float *)(t.local + 4);
     return t;
 }
 
@@ -684,7 +697,7 @@ int launch_head_backward(int model, int K, const MlpView &w, const TrainBufs &b,
 
 // The fused pass (forward, head, input gradients) then the weight-gradient
 // products and bias sums of launch_head_backward.
-int launch_fused_pass(int model, int K, const MlpView &w, const TrainBufs &b, hipStream_t st) {
+int launch_fused_pass(int model, int K, const MlpView &w, const TrainBufs &b, const AdvanceJob &adv, hipStream_t st) {
     const int B = b.B;
     if (B % kFuseRows) return fail(PPL_E_ARG, "batch %d is not a multiple of %d", B, kFuseRows);
     const float inv_b = 1.0f / (float)B;
@@ -727,9 +740,10 @@ int launch_fused_pass(int model, int K, const MlpView &w, const TrainBufs &b, hi
     g.g3 = b.do_col;
     g.B = B;
     g.bgrad = b.bgrad;
+    g.adv = adv;
     {
         KernelTimer timer("wgrad_group_kernel", st);
-        hipLaunchKernelGGL(wgrad_group_kernel, dim3((unsigned)(first + 3 * 256)), dim3(256), 0, st, g);
+        hipLaunchKernelGGL(wgrad_group_kernel, dim3((unsigned)(first + 3 * 256 + 1)), dim3(256), 0, st, g);
         timer.stop();
         PPL_LAUNCH_CHECK("wgrad_group_kernel");
     }
@@ -743,15 +757,27 @@ int launch_update(const MlpView &w, const TrainBufs &b, const AdamSpec &ad, floa
         sp.nc[l] = b.nchunks[l];
     }
     const int blocks = (int)((MlpParams::count() + 255) / 256);
-    hipLaunchKernelGGL(adam_kernel, dim3(blocks), dim3(256), 0, st, w, sp, (const float *)b.bgrad, ad, grad);
+    hipLaunchKernelGGL(adam_kernel, dim3(blocks), dim3(256), 0, st, w, sp, (const float *)b.bgrad, ad,
+                       (const float *)b.coef, grad);
     PPL_LAUNCH_CHECK("adam_kernel");
     return PPL_OK;
 }
 
-int launch_advance(int64_t *step, const TrainBufs &b, double *loss_trace, hipStream_t st) {
-    hipLaunchKernelGGL(advance_kernel, dim3(1), dim3(64), 0, st, step, b.local, (const double *)b.lossp,
-                       b.B / kHeadPairs,
-                       1.0 / (double)b.B, loss_trace);
+AdvanceJob advance_job(int64_t *step, const TrainBufs &b, const AdamSpec &ad, double *loss_trace) {
+    AdvanceJob a{};
+    a.step = step;
+    a.local = b.local;
+    a.lossp = b.lossp;
+    a.nparts = b.B / kHeadPairs;
+    a.inv_b = 1.0 / (double)b.B;
+    a.loss_trace = loss_trace;
+    a.ad = ad;
+    a.coef = b.coef;
+    return a;
+}
+
+int launch_advance(const AdvanceJob &adv, hipStream_t st) {
+    hipLaunchKernelGGL(advance_kernel, dim3(1), dim3(64), 0, st, adv);
     PPL_LAUNCH_CHECK("advance_kernel");
     return PPL_OK;
 }
