@@ -783,14 +783,19 @@ static int forward_backward(int model, int K, const MlpView &w, const TrainBufs 
     return launch_advance(adv, st);
 }
 
-// One training step: simulate, forward, loss head, backward and the step's
-// bookkeeping, then Adam.
-static int train_step(const TrainPlan &p, uint64_t seed, const MlpView &w, const TrainBufs &b, double *loss_trace,
-                      hipStream_t st) {
-    if (int rc = launch_simulate(p.sim, p.B, seed, w.step, b.x_row, b.x_col, b.theta, nullptr, st)) return rc;
+// The network part of one training step, on a batch already simulated into
+// b: forward, loss head, backward and the step's bookkeeping, then Adam,
+// grouped with the simulation of the next step's batch when there is one.
+static int train_body(const TrainPlan &p, uint64_t seed, const MlpView &w, const TrainBufs &b, double *loss_trace,
+                      bool next, hipStream_t st) {
     if (int rc = forward_backward(p.sim.model, p.sim.K, w, b, advance_job(w.step, b, p.adam, loss_trace), st))
         return rc;
+    if (next) return launch_update_simulate(w, b, p.adam, p.sim, p.B, seed, w.step, st);
     return launch_update(w, b, p.adam, nullptr, st);
+}
+
+static int train_first_batch(const TrainPlan &p, uint64_t seed, const MlpView &w, const TrainBufs &b, hipStream_t st) {
+    return launch_simulate(p.sim, p.B, seed, w.step, b.x_row, b.x_col, b.theta, nullptr, st);
 }
 
 static int train_graph(const TrainPlan &p, uint64_t seed, const MlpView &w, const TrainBufs &b, double *loss_trace,
@@ -806,7 +811,7 @@ static int train_graph(const TrainPlan &p, uint64_t seed, const MlpView &w, cons
         if (e != hipSuccess) {
             rc = fail(PPL_E_HIP, "hipStreamBeginCapture: %s", hipGetErrorString(e));
         } else {
-            rc = train_step(p, seed, w, b, loss_trace, cap);
+            rc = train_body(p, seed, w, b, loss_trace, true, cap);
             e = hipStreamEndCapture(cap, &graph);
             if (!rc && e != hipSuccess) rc = fail(PPL_E_HIP, "hipStreamEndCapture: %s", hipGetErrorString(e));
         }
@@ -815,12 +820,16 @@ static int train_graph(const TrainPlan &p, uint64_t seed, const MlpView &w, cons
         hipError_t e = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
         if (e != hipSuccess) rc = fail(PPL_E_HIP, "hipGraphInstantiate: %s", hipGetErrorString(e));
     }
-    for (int64_t s = 0; !rc && s < p.steps; ++s) {
+    // the first batch, every step but the last as one graph launch (each also
+    // simulating the next batch), then the last step
+    if (!rc) rc = train_first_batch(p, seed, w, b, st);
+    for (int64_t s = 0; !rc && s + 1 < p.steps; ++s) {
         KernelTimer timer("proposal_train_step", st);
         hipError_t e = hipGraphLaunch(exec, st);
         timer.stop();
         if (e != hipSuccess) rc = fail(PPL_E_HIP, "hipGraphLaunch: %s", hipGetErrorString(e));
     }
+    if (!rc) rc = train_body(p, seed, w, b, loss_trace, false, st);
     // the executable graph is released only after its launches have finished
     if (exec) {
         hipError_t e = hipStreamSynchronize(st);
@@ -872,9 +881,10 @@ int ppl_proposal_train(int model, const ppl_train_config *cfg, uint64_t seed, vo
     const MlpView w = mlp_view(d_weights);
     const TrainBufs b = train_bufs(ws, p.B);
     if (int rc = launch_set_i64(b.local, 0, st)) return rc;
-    if (cfg->use_graph) return train_graph(p, seed, w, b, d_loss_trace, st);
+    if (cfg->use_graph && p.steps > 1) return train_graph(p, seed, w, b, d_loss_trace, st);
+    if (int rc = train_first_batch(p, seed, w, b, st)) return rc;
     for (int64_t s = 0; s < p.steps; ++s)
-        if (int rc = train_step(p, seed, w, b, d_loss_trace, st)) return rc;
+        if (int rc = train_body(p, seed, w, b, d_loss_trace, s + 1 < p.steps, st)) return rc;
     return PPL_OK;
 }
 

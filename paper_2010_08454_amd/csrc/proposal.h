@@ -92,6 +92,10 @@ int launch_fused_pass(int model, int K, const MlpView &w, const TrainBufs &b, co
 int launch_update(const MlpView &w, const TrainBufs &b, const AdamSpec &ad, float *grad, hipStream_t st);
 // The step's bookkeeping as a launch of its own (after launch_head_backward).
 int launch_advance(const AdvanceJob &adv, hipStream_t st);
+// launch_update (Adam, grad null) and launch_simulate of the next batch into
+// b.x_row, b.x_col, b.theta, in one launch; step must already be advanced.
+int launch_update_simulate(const MlpView &w, const TrainBufs &b, const AdamSpec &ad, const SimSpec &sp, int B,
+                           uint64_t seed, const int64_t *step, hipStream_t st);
 int launch_set_i64(int64_t *p, int64_t v, hipStream_t st);
 int launch_init_weights(void *weights, uint64_t seed, hipStream_t st);
 

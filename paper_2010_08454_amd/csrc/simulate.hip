@@ -17,6 +17,7 @@
 //         and their noise (words 2, 3); latents returned in the ordered
 //         unconstrained space (mu_(1), log gaps, log pi_(k) - log pi_(K)).
 // Every step is in FP64 on uniforms that are exact in both precisions.
+#include "adam.h"
 #include "device.h"
 #include "host.h"
 #include "proposal.h"
@@ -243,13 +244,11 @@ __device__ __forceinline__ void gmm_bin(int *hist, double y) {
 }
 
 // -------------------------------------------------- training simulation --
+// Dataset b of the batch (one workgroup).
 template <int MODEL>
-__global__ __launch_bounds__(kSumThreads) void simulate_kernel(SimSpec sp, int B, Key key,
-                                                               const int64_t *__restrict__ step_ptr,
-                                                               uint16_t *__restrict__ x_row,
-                                                               uint16_t *__restrict__ x_col,
-                                                               double *__restrict__ theta,
-                                                               double *__restrict__ s64) {
+__device__ __forceinline__ void simulate_block(const SimSpec &sp, int B, Key key, const int64_t *__restrict__ step_ptr,
+                                               uint16_t *__restrict__ x_row, uint16_t *__restrict__ x_col,
+                                               double *__restrict__ theta, double *__restrict__ s64, int b) {
 #pragma clang fp contract(off)
     extern __shared__ double ys[];
     __shared__ double wtot[kSumWaves][kPolyAcc];
@@ -258,7 +257,6 @@ __global__ __launch_bounds__(kSumThreads) void simulate_kernel(SimSpec sp, int B
     __shared__ double red[kSumWaves];
     __shared__ int hist[32];
     const int tid = threadIdx.x;
-    const int b = blockIdx.x;
     const uint32_t step = (uint32_t)*step_ptr;
     const uint32_t pair = (uint32_t)b;
     const int64_t D = sp.D;
@@ -369,6 +367,36 @@ __global__ __launch_bounds__(kSumThreads) void simulate_kernel(SimSpec sp, int B
     }
 }
 
+template <int MODEL>
+__global__ __launch_bounds__(kSumThreads) void simulate_kernel(SimSpec sp, int B, Key key,
+                                                               const int64_t *__restrict__ step_ptr,
+                                                               uint16_t *__restrict__ x_row,
+                                                               uint16_t *__restrict__ x_col,
+                                                               double *__restrict__ theta,
+                                                               double *__restrict__ s64) {
+    simulate_block<MODEL>(sp, B, key, step_ptr, x_row, x_col, theta, s64, (int)blockIdx.x);
+}
+
+// The Adam update of one step (workgroups 0 .. adam_blocks - 1) and the
+// simulation of the next step's batch (the rest) in one launch: the
+// simulation reads only the step count, which the step's bookkeeping has
+// already advanced, and its buffers were last read by the launches before.
+template <int MODEL>
+__global__ __launch_bounds__(kSumThreads) void adam_simulate_kernel(MlpView w, SplitParts spl,
+                                                                    const float *__restrict__ bgrad, AdamSpec ad,
+                                                                    const float *__restrict__ coef, int adam_blocks,
+                                                                    SimSpec sp, int B, Key key,
+                                                                    const int64_t *__restrict__ step_ptr,
+                                                                    uint16_t *__restrict__ x_row,
+                                                                    uint16_t *__restrict__ x_col,
+                                                                    double *__restrict__ theta) {
+    if ((int)blockIdx.x < adam_blocks) {
+        adam_unit(w, spl, bgrad, ad, coef, nullptr, (int64_t)blockIdx.x * kSumThreads + threadIdx.x);
+        return;
+    }
+    simulate_block<MODEL>(sp, B, key, step_ptr, x_row, x_col, theta, nullptr, (int)blockIdx.x - adam_blocks);
+}
+
 // ----------------------------------------------------- observed summary --
 template <int MODEL>
 __global__ __launch_bounds__(kSumThreads) void observed_summary_kernel(const void *__restrict__ xv,
@@ -426,6 +454,25 @@ int launch_simulate(const SimSpec &sp, int B, uint64_t seed, const int64_t *step
                            x_col, theta, s64);
         PPL_LAUNCH_CHECK("simulate_kernel<GMM>");
     }
+    return PPL_OK;
+}
+
+int launch_update_simulate(const MlpView &w, const TrainBufs &b, const AdamSpec &ad, const SimSpec &sp, int B,
+                           uint64_t seed, const int64_t *step, hipStream_t st) {
+    if (B <= 0) return fail(PPL_E_ARG, "simulation batch %d is not positive", B);
+    const int adam_blocks = (int)((MlpParams::count() + kSumThreads - 1) / kSumThreads);
+    const dim3 grid((unsigned)(adam_blocks + B)), block(kSumThreads);
+    const SplitParts spl = split_parts(b);
+    if (sp.model == PPL_MODEL_POLY) {
+        hipLaunchKernelGGL(adam_simulate_kernel<PPL_MODEL_POLY>, grid, block, 0, st, w, spl, (const float *)b.bgrad, ad,
+                           (const float *)b.coef, adam_blocks, sp, B, make_key(seed), step, b.x_row, b.x_col, b.theta);
+    } else {
+        if (sp.D > kGmmTrainMaxD) return fail(PPL_E_ARG, "mixture training datasets hold at most %d points", kGmmTrainMaxD);
+        const size_t lds = (size_t)(sp.D > 0 ? sp.D : 1) * sizeof(double);
+        hipLaunchKernelGGL(adam_simulate_kernel<PPL_MODEL_GMM>, grid, block, lds, st, w, spl, (const float *)b.bgrad, ad,
+                           (const float *)b.coef, adam_blocks, sp, B, make_key(seed), step, b.x_row, b.x_col, b.theta);
+    }
+    PPL_LAUNCH_CHECK("adam_simulate_kernel");
     return PPL_OK;
 }
 
