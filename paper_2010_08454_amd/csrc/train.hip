@@ -70,13 +70,23 @@ __device__ __forceinline__ float head_pair(const float *o, int os, const double 
     if constexpr (MODEL == PPL_MODEL_POLY) {
         const int n = min(max((int)th[0], 2), 5);
         const int off = poly_head_off(n);
+        // per coefficient: th5 = tanh(z / 5), iv = exp(-5 th5) (the inverse
+        // scale), dv = theta - mu; kept for the gradient below
+        float th5v[5], ivv[5], dvv[5];
 #pragma unroll
         for (int j = 0; j < 5; ++j) {
+            th5v[j] = ivv[j] = dvv[j] = 0.0f;
             if (j < n) {
                 const float mu = 10.0f * O(off + m * n + j);
-                const float lsd = 5.0f * tanhf(O(off + 8 * n + m * n + j) * 0.2f);
-                const float r = ((float)th[1 + j] - mu) * expf(-lsd);
+                const float th5 = tanhf(O(off + 8 * n + m * n + j) * 0.2f);
+                const float lsd = 5.0f * th5;
+                const float iv = expf(-lsd);
+                const float dv = (float)th[1 + j] - mu;
+                const float r = dv * iv;
                 t += -0.5f * r * r - lsd - kHalfLog2Pi;
+                th5v[j] = th5;
+                ivv[j] = iv;
+                dvv[j] = dv;
             }
         }
         const float tm = group8_max(t);
@@ -108,10 +118,7 @@ __device__ __forceinline__ float head_pair(const float *o, int os, const double 
         for (int j = 0; j < 5; ++j) {
             if (j < n) {
                 const int km = off + m * n + j, ks = off + 8 * n + m * n + j;
-                const float mu = 10.0f * O(km);
-                const float th5 = tanhf(O(ks) * 0.2f);
-                const float iv = expf(-5.0f * th5);
-                const float dv = (float)th[1 + j] - mu;
+                const float th5 = th5v[j], iv = ivv[j], dv = dvv[j];
                 const float r = dv * iv;
                 g[km] = f32_to_bf16(-resp * dv * iv * iv * 10.0f * inv_b);
                 g[ks] = f32_to_bf16(-resp * (r * r - 1.0f) * (1.0f - th5 * th5) * inv_b);
@@ -357,9 +364,15 @@ __global__ __launch_bounds__(256) void fused_pass_kernel(MlpView w, TrainBufs b,
     }
     lds_barrier();
     if (tid == 0) b.lossp[blockIdx.x] = (red[0] + red[1]) + (red[2] + red[3]);
-    for (int e = tid; e < kFuseRows * kMlpOut; e += 256) {
-        const int k = e / kFuseRows, q = e % kFuseRows;
-        b.do_col[(size_t)k * B + b0 + q] = sG[q * kFusePad + k];
+    // dO to the column-major copy: four consecutive pairs of one output per
+    // 8-byte store, all LDS reads of a thread issued together
+#pragma unroll
+    for (int it = 0; it < kFuseRows * kMlpOut / (4 * 256); ++it) {
+        const int e = tid + 256 * it;
+        const int k = e / (kFuseRows / 4), q = (e % (kFuseRows / 4)) * 4;
+        const uint32_t lo = (uint32_t)sG[q * kFusePad + k] | ((uint32_t)sG[(q + 1) * kFusePad + k] << 16);
+        const uint32_t hi = (uint32_t)sG[(q + 2) * kFusePad + k] | ((uint32_t)sG[(q + 3) * kFusePad + k] << 16);
+        *(uint2 *)(b.do_col + (size_t)k * B + b0 + q) = make_uint2(lo, hi);
     }
     // layer 3 input gradient: dH2 = (dO W3) * [H2 > 0]
     fuse_mma<kMlpOut>(sG, kFusePad, fb, acc);
