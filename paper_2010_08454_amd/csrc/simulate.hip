@@ -377,24 +377,24 @@ __global__ __launch_bounds__(kSumThreads) void simulate_kernel(SimSpec sp, int B
     simulate_block<MODEL>(sp, B, key, step_ptr, x_row, x_col, theta, s64, (int)blockIdx.x);
 }
 
-// The Adam update of one step (workgroups 0 .. adam_blocks - 1) and the
-// simulation of the next step's batch (the rest) in one launch: the
-// simulation reads only the step count, which the step's bookkeeping has
+// The simulation of the next step's batch (workgroups 0 .. B - 1, first, as
+// the longer ones) and the Adam update of this step (the rest) in one launch:
+// the simulation reads only the step count, which the step's bookkeeping has
 // already advanced, and its buffers were last read by the launches before.
 template <int MODEL>
 __global__ __launch_bounds__(kSumThreads) void adam_simulate_kernel(MlpView w, SplitParts spl,
                                                                     const float *__restrict__ bgrad, AdamSpec ad,
-                                                                    const float *__restrict__ coef, int adam_blocks,
-                                                                    SimSpec sp, int B, Key key,
+                                                                    const float *__restrict__ coef, SimSpec sp, int B,
+                                                                    Key key,
                                                                     const int64_t *__restrict__ step_ptr,
                                                                     uint16_t *__restrict__ x_row,
                                                                     uint16_t *__restrict__ x_col,
                                                                     double *__restrict__ theta) {
-    if ((int)blockIdx.x < adam_blocks) {
-        adam_unit(w, spl, bgrad, ad, coef, nullptr, (int64_t)blockIdx.x * kSumThreads + threadIdx.x);
+    if ((int)blockIdx.x >= B) {
+        adam_unit(w, spl, bgrad, ad, coef, nullptr, (int64_t)((int)blockIdx.x - B) * kSumThreads + threadIdx.x);
         return;
     }
-    simulate_block<MODEL>(sp, B, key, step_ptr, x_row, x_col, theta, nullptr, (int)blockIdx.x - adam_blocks);
+    simulate_block<MODEL>(sp, B, key, step_ptr, x_row, x_col, theta, nullptr, (int)blockIdx.x);
 }
 
 // ----------------------------------------------------- observed summary --
@@ -465,12 +465,12 @@ int launch_update_simulate(const MlpView &w, const TrainBufs &b, const AdamSpec 
     const SplitParts spl = split_parts(b);
     if (sp.model == PPL_MODEL_POLY) {
         hipLaunchKernelGGL(adam_simulate_kernel<PPL_MODEL_POLY>, grid, block, 0, st, w, spl, (const float *)b.bgrad, ad,
-                           (const float *)b.coef, adam_blocks, sp, B, make_key(seed), step, b.x_row, b.x_col, b.theta);
+                           (const float *)b.coef, sp, B, make_key(seed), step, b.x_row, b.x_col, b.theta);
     } else {
         if (sp.D > kGmmTrainMaxD) return fail(PPL_E_ARG, "mixture training datasets hold at most %d points", kGmmTrainMaxD);
         const size_t lds = (size_t)(sp.D > 0 ? sp.D : 1) * sizeof(double);
         hipLaunchKernelGGL(adam_simulate_kernel<PPL_MODEL_GMM>, grid, block, lds, st, w, spl, (const float *)b.bgrad, ad,
-                           (const float *)b.coef, adam_blocks, sp, B, make_key(seed), step, b.x_row, b.x_col, b.theta);
+                           (const float *)b.coef, sp, B, make_key(seed), step, b.x_row, b.x_col, b.theta);
     }
     PPL_LAUNCH_CHECK("adam_simulate_kernel");
     return PPL_OK;
