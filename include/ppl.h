@@ -553,7 +553,8 @@ typedef struct ppl_train_config {
     double lr, beta1, beta2, eps;
     const double *hyper;
     int32_t n_hyper;
-    int32_t use_graph;       /* nonzero: capture one step as a HIP graph and replay it */
+    int32_t use_graph;       /* nonzero: capture one step (it also simulates the next batch)
+                                as a HIP graph, replayed for every step but the last */
     int64_t lr_decay_steps;  /* 0: constant learning rate */
     double lr_final_frac;    /* in [0, 1] */
 } ppl_train_config;
