@@ -11,8 +11,8 @@ Printed as one JSON line, with
   roofline     -- the dominant kernel (blr_is_kernel) timed with HIP events on
                   its launch stream during the timed steps, against MI355X's
                   published FP32 vector peak (157.3 TFLOP/s, packed FP32), with
-                  the fraction of the unpacked FMA issue ceiling this build can
-                  reach (packed FP32 is disabled) beside it as frac_attainable:
+                  the fraction of the unpacked FMA issue ceiling the library can
+                  reach (it is compiled without packed FP32) beside it as frac_attainable:
                   algorithmic work 34 FLOP per evaluation (16 FMA residual +
                   1 FMA square-accumulate);
   cpu_baseline -- the CPU oracle on a bounded sample of the same workload.
@@ -54,7 +54,7 @@ sys.path.insert(0, ROOT)
 # Published MI355X figures used as denominators.
 CU, CLOCK_HZ, SIMD_PER_CU, LANES_PER_SIMD = 256, 2.4e9, 4, 16
 FP32_VALU_UNPACKED_TFLOPS = CU * SIMD_PER_CU * LANES_PER_SIMD * 2 * CLOCK_HZ / 1e12   # 78.6
-FP32_VALU_PUBLISHED_TFLOPS = 157.3        # needs packed FP32, which this build disables
+FP32_VALU_PUBLISHED_TFLOPS = 157.3        # needs packed FP32, which the library's compile flags disable
 FP64_VALU_TFLOPS = 78.6
 
 FLOP_PER_EVAL_BLR = 34                    # 17 FMA per (particle, row) at d = 16
@@ -160,7 +160,7 @@ def bench_peaks(torch, dev, stream):
         res[f"hbm_copy_{cb}wg"] = {"rate": round(2 * n4 * 16 / (ms / 1e3) / 1e9, 1), "unit": "GB/s", "published": 8000.0,
                                    "ms": round(ms, 4)}
     print(json.dumps({"metric": "measured peak rates", "n_gpus": 1, "data": "synthetic", "peaks": res,
-                      "note": "fp32 FMA issue without packed FP32 (disabled in this build) peaks at 78.64 TFLOP/s; "
+                      "note": "fp32 FMA issue without packed FP32 (disabled in the library's compile flags) peaks at 78.64 TFLOP/s; "
                               "the published 157.3 assumes packed FP32"}), flush=True)
 
 
@@ -779,7 +779,7 @@ def cpu_baseline_prior_ess(poly, x, y, D, target_s=15.0):
 def main():
     args = parse()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
-        print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1"}))
+        print(json.dumps({"error": "the library runs on one GPU only; --gpus must be 1"}))
         sys.exit(2)
     if args.copy_calibration:
         copy_calibration()
@@ -961,8 +961,8 @@ def main():
                 "kernel": kname, "kernel_ms": round(k_avg_ms, 4), "kernel_launches": k_n,
                 "flop_per_launch": flop_per_launch}
     if args.config == "blr":
-        roofline["peak_note"] = ("peak is MI355X's published FP32 vector rate, which counts packed FP32; this "
-                                 "build compiles without packed FP32, so its attainable ceiling is the unpacked "
+        roofline["peak_note"] = ("peak is MI355X's published FP32 vector rate, which counts packed FP32; the "
+                                 "library is compiled without packed FP32, so its attainable ceiling is the unpacked "
                                  "FMA issue rate 256 CU x 64 lanes x 2 FLOP x 2.4 GHz = 78.64 TFLOP/s")
         roofline["peak_attainable"] = round(FP32_VALU_UNPACKED_TFLOPS, 2)
         roofline["frac_attainable"] = round(achieved / FP32_VALU_UNPACKED_TFLOPS, 4)

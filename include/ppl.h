@@ -52,7 +52,7 @@ enum {
     PPL_E_WORKSPACE = -5,    /* workspace missing or smaller than ppl_workspace_size()        */
     PPL_E_NONFINITE = -6,    /* a log-weight was NaN (device-detected)                        */
     PPL_E_ZERO_WEIGHT = -7,  /* every weight was zero: log Z-hat = -inf (device-detected)      */
-    PPL_E_UNSUPPORTED = -8   /* valid request outside what this build implements              */
+    PPL_E_UNSUPPORTED = -8   /* valid request outside what the library implements            */
 };
 
 /* Short description of a status code (static storage). */
